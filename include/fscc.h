@@ -1,0 +1,160 @@
+/*
+ * fscc.h -- C ABI of the MI355X (gfx950) Fock-space relativistic CCSD hot path.
+ *
+ * What it computes (Oleynichenko, Zaitsevskii, Eliav, "Towards High
+ * Performance Relativistic Electronic Structure Modelling: The EXP-T Program
+ * Package", 2020):
+ *   - the second-quantised Hamiltonian of Eq. (1) with antisymmetrised
+ *     complex integrals <pq||rs> and a diagonal Fock operator (orbital
+ *     energies eps), partitioned into dense blocks by irreps (the
+ *     symmetry-handling section, Fig. 3);
+ *   - the CCSD amplitude equations of Eq. (3)-(4) for the (0h,0p) sector
+ *     (Eq. (5) sector partition), evaluated as transpose-transpose-GEMM-
+ *     transpose contractions over block lists (algorithm-design section,
+ *     Fig. 4), with the particle-particle ladder sum_{c<d} <ab||cd> t_ij^cd
+ *     on FP64 matrix cores;
+ *   - the Jacobi update t += R/D of Eq. (3) (D = negative H0-eigenvalue
+ *     differences) accelerated by DIIS, and the correlation energy.
+ *
+ * Conventions
+ *   Spinors: global index p in [0, nocc) occupied, [nocc, nocc+nvirt) virtual.
+ *   Irreps: Abelian Z_nirrep labels; <pq||rs> != 0 only if
+ *     irrep(p) + irrep(q) = irrep(r) + irrep(s) (mod nirrep).
+ *   Inside an irrep, spinors are ordered by ascending global index
+ *   ("irrep-sorted order" = irrep 0 first, then irrep 1, ...).
+ *   Complex numbers: fscc_c128 = two doubles (re, im) = C99 double _Complex
+ *   = torch.complex128.
+ *
+ * Packed amplitude / residual layouts (sector (0h,0p)):
+ *   T1, R1: for g = 0..nirrep-1: dense [o_g][v_g] row-major block of
+ *           t_i^a with irrep(i) = irrep(a) = g.
+ *   T2, R2: for G = 0..nirrep-1: dense [n_oo(G)][n_vv(G)] row-major block;
+ *           rows = occupied pairs i<j (irrep-sorted order) with
+ *           irrep(i)+irrep(j) = G, columns = virtual pairs a<b with
+ *           irrep(a)+irrep(b) = G.  Pairs are grouped by (g_p, g_q), g_p <= g_q,
+ *           g_p ascending; inside a group p-major (for g_p = g_q the strict
+ *           upper triangle, row-major).
+ *   fscc_layout() returns the lengths n1 (T1) and n2 (T2).
+ *
+ * Integral classes at the boundary (fscc_set_integrals): one contiguous
+ *   buffer per class, concatenating over (g1, g2, g3) in lexicographic order,
+ *   g4 = (g1 + g2 - g3) mod nirrep, the dense row-major blocks
+ *   [n_X1(g1)][n_X2(g2)][n_X3(g3)][n_X4(g4)] (full, not packed).  All
+ *   other integrals follow by antisymmetry and Hermiticity
+ *   (<pq||rs> = -<qp||rs> = -<pq||sr> = conj <rs||pq>).
+ *
+ * Ownership and errors
+ *   Every pointer argument is owned by the caller.  Amplitude, residual and
+ *   integral buffers are DEVICE memory on the context's device; scalar outputs
+ *   (max_step, energies, counts) are HOST memory.  The library owns its packed
+ *   integrals, intermediates and DIIS history (device memory allocated at
+ *   fscc_create / fscc_set_integrals and released by fscc_destroy).
+ *   All device work is ordered on the hip_stream given to fscc_create; a
+ *   call with host outputs synchronises that stream before returning.
+ *   No C++ exception crosses the ABI.  On error the outputs are untouched,
+ *   the call returns a negative status and fscc_last_error() describes it.
+ *   A context must not be used from two host threads at once.
+ */
+#ifndef FSCC_H
+#define FSCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fscc_ctx fscc_ctx;
+
+typedef struct {
+    double re, im;
+} fscc_c128;
+
+typedef enum {
+    FSCC_OK = 0,
+    FSCC_EINVAL = -1,  /* bad argument (sizes, pointers, sector, class)          */
+    FSCC_ESYMM = -2,   /* input violates antisymmetry / Hermiticity              */
+    FSCC_ENOMEM = -3,  /* device allocation failed                               */
+    FSCC_EHIP = -4,    /* a HIP runtime call failed                              */
+    FSCC_ESTATE = -5,  /* call out of order (e.g. integrals not all set)         */
+    FSCC_ENOCONV = -6  /* non-finite update (NaN / Inf in the step)              */
+} fscc_status;
+
+typedef enum { FSCC_FP64 = 0, FSCC_SPLIT_FP32 = 1, FSCC_SPLIT_BF16 = 2 } fscc_precision;
+
+typedef enum { FSCC_S00 = 0, FSCC_S01 = 1 } fscc_sector; /* (0h,0p), (0h,1p) */
+
+typedef enum { FSCC_OOOO = 0, FSCC_OOOV, FSCC_OOVV, FSCC_OVOV, FSCC_OVVV, FSCC_VVVV } fscc_iclass;
+
+typedef struct {
+    int32_t nocc, nvirt, nirrep;
+    const int32_t *irrep;  /* host [nocc+nvirt], labels in [0, nirrep)              */
+    const double *eps;     /* host [nocc+nvirt], orbital energies (Eh)             */
+    int32_t nact;          /* (0h,1p) active virtuals; 0 = (0h,0p) only            */
+    const int32_t *active; /* host [nact], global indices of the active virtuals   */
+} fscc_system;
+
+/* Build the plan for one system: irrep-sorted index spaces, block layouts,
+ * reorder maps and grouped-GEMM problem lists (the TTGT decomposition of
+ * every contraction of the CCSD residual).  hip_stream may be NULL (the null
+ * stream).  Only FSCC_FP64 is accepted by this build.  Device memory for
+ * intermediates is allocated here. */
+fscc_status fscc_create(const fscc_system *sys, fscc_precision prec, void *hip_stream, fscc_ctx **out);
+
+/* Import one integral class (boundary layout above, n complex elements) and
+ * pack it into the library's block layouts (integral sorting, step I of the
+ * flowchart).  dev_blocks may be freed on return.  All six classes must be
+ * set before fscc_build_residual / fscc_energy. */
+fscc_status fscc_set_integrals(fscc_ctx *ctx, fscc_iclass cls, const fscc_c128 *dev_blocks, size_t n);
+
+/* Packed lengths (complex elements) of T1/R1 and T2/R2 for a sector. */
+fscc_status fscc_layout(const fscc_ctx *ctx, fscc_sector sector, size_t *n1, size_t *n2);
+
+/* R = RHS - D*t for the CCSD equations (Eq. (3)), D_i^a = e_i - e_a,
+ * D_ij^ab = e_i + e_j - e_a - e_b.  t1, t2 inputs; r1, r2 outputs (device,
+ * packed layouts; must not alias the inputs).  Asynchronous on the stream. */
+fscc_status fscc_build_residual(fscc_ctx *ctx, fscc_sector sector, const fscc_c128 *t1, const fscc_c128 *t2,
+                                fscc_c128 *r1, fscc_c128 *r2);
+
+/* Jacobi step of Eq. (3): step = R/D, t' = t + step; then DIIS over the last
+ * ndiis (t', step) pairs (B_kl = Re <step_k, step_l> over the packed unique
+ * amplitudes, bordered Pulay system solved on the device in FP64) writes the
+ * extrapolated amplitudes into t1, t2.  *max_step (host) = max |step|.
+ * Returns FSCC_ENOCONV if the step is not finite. */
+fscc_status fscc_update_amplitudes(fscc_ctx *ctx, fscc_sector sector, fscc_c128 *t1, fscc_c128 *t2,
+                                   const fscc_c128 *r1, const fscc_c128 *r2, double *max_step);
+
+/* Correlation energy E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a)
+ * (f_ia = 0), complex in general; host outputs. */
+fscc_status fscc_energy(fscc_ctx *ctx, const fscc_c128 *t1, const fscc_c128 *t2, double *e_re, double *e_im);
+
+/* Clear the DIIS history of a sector and set its depth (0 or 1 = plain Jacobi, max 8). */
+fscc_status fscc_diis_reset(fscc_ctx *ctx, fscc_sector sector, int ndiis);
+
+/* The particle-particle ladder alone: out_ij^ab = sum_{c<d} <ab||cd> tau_ij^cd
+ * (T2 layouts, device; out overwritten).  The dominant contraction of the
+ * residual, exposed for parity checks and timing. */
+fscc_status fscc_ladder(fscc_ctx *ctx, const fscc_c128 *tau, fscc_c128 *out);
+
+/* Work counts of one residual evaluation: real flops of all grouped GEMMs,
+ * of the ladder alone, and its vvvv bytes (host outputs). */
+fscc_status fscc_work(const fscc_ctx *ctx, double *gemm_flops, double *ladder_flops, double *ladder_bytes);
+
+/* Per-operation timing.  fscc_profile(ctx, 1) makes every residual
+ * evaluation record HIP events around each operation on the stream;
+ * fscc_op_count returns the number of operations; fscc_op_info(k) returns
+ * the name (static until destroy), accumulated milliseconds, number of
+ * timed calls and real flops per call of operation k (host outputs). */
+fscc_status fscc_profile(fscc_ctx *ctx, int enable);
+fscc_status fscc_op_count(const fscc_ctx *ctx, int *count);
+fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, int *calls, double *flops);
+
+void fscc_destroy(fscc_ctx *ctx);
+const char *fscc_last_error(const fscc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSCC_H */

@@ -276,3 +276,18 @@ def mp2_energy_closed_form(be) -> complex:
     if isinstance(v, BlockTensor):
         return 0.25 * sum(np.sum(np.abs(x) ** 2 / be.D2.blocks[k]) for k, x in v.blocks.items())
     return 0.25 * np.sum(np.abs(v) ** 2 / be.D2)
+
+
+def pp_ladder(be, tau):
+    """Particle-particle ladder L_ij^ab = 1/2 sum_cd <ab||cd> tau_ij^cd (the bare-integral part of
+    the 1/2 sum_ef tau_ij^ef W_abef term)."""
+    return 0.5 * be.ein("ijcd,abcd->ijab", tau, be.V("vvvv"))
+
+
+def mp3_ladder_closed_form(be) -> complex:
+    """Textbook third-order pp-ladder energy 1/8 sum <ij||ab><ab||cd><cd||ij> / (D_ij^ab D_ij^cd),
+    summed directly over all (unpacked) indices with one einsum per (ij) pair set (dense only)."""
+    oovv, vvvv, D = be.V("oovv"), be.V("vvvv"), be.D2
+    y = oovv.conj() / D                      # y_ij^cd = <cd||ij> / D_ij^cd
+    x = oovv / D                             # <ij||ab> / D_ij^ab
+    return 0.125 * np.einsum("ijab,abcd,ijcd->", x, vvvv, y, optimize=True)

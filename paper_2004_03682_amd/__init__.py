@@ -1,0 +1,200 @@
+"""MI355X-native FS-RCCSD hot path: thin Python binding of libfscc.so.
+
+Every function here only marshals arguments to the C ABI declared in
+include/fscc.h; all computation runs in the library's HIP kernels.  Device
+buffers are torch tensors (complex128, on the GPU); torch is used for device
+memory and streams only.  There is no CPU fallback: importing the binding
+without the built library, or calling it on tensors that are not on a GPU,
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfscc.so")
+
+FSCC_S00, FSCC_S01 = 0, 1
+CLASSES = ("OOOO", "OOOV", "OOVV", "OVOV", "OVVV", "VVVV")
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ESYMM", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "ENOCONV"}
+
+_lib = None
+
+
+class FsccError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fscc {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int32), ("nvirt", ctypes.c_int32), ("nirrep", ctypes.c_int32),
+                ("irrep", ctypes.POINTER(ctypes.c_int32)), ("eps", ctypes.POINTER(ctypes.c_double)),
+                ("nact", ctypes.c_int32), ("active", ctypes.POINTER(ctypes.c_int32))]
+
+
+def lib():
+    """Load libfscc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, dp, ip = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        sigs = {
+            "fscc_create": ([ctypes.POINTER(_System), ip, vp, ctypes.POINTER(vp)], ip),
+            "fscc_set_integrals": ([vp, ip, vp, sz], ip),
+            "fscc_layout": ([vp, ip, ctypes.POINTER(sz), ctypes.POINTER(sz)], ip),
+            "fscc_build_residual": ([vp, ip, vp, vp, vp, vp], ip),
+            "fscc_update_amplitudes": ([vp, ip, vp, vp, vp, vp, dp], ip),
+            "fscc_energy": ([vp, vp, vp, dp, dp], ip),
+            "fscc_diis_reset": ([vp, ip, ip], ip),
+            "fscc_ladder": ([vp, vp, vp], ip),
+            "fscc_work": ([vp, dp, dp, dp], ip),
+            "fscc_profile": ([vp, ip], ip),
+            "fscc_op_count": ([vp, ctypes.POINTER(ip)], ip),
+            "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
+            "fscc_destroy": ([vp], None),
+            "fscc_last_error": ([vp], ctypes.c_char_p),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _dev_ptr(t, n=None):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("fscc expects GPU tensors")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError("fscc expects contiguous complex128 tensors")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One system (fscc_create ... fscc_destroy)."""
+
+    def __init__(self, nocc, nvirt, nirrep, irrep, eps, stream=None, active=()):
+        import numpy as np
+        import torch
+        L = lib()
+        self._irrep = np.ascontiguousarray(irrep, dtype=np.int32)
+        self._eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self._act = np.ascontiguousarray(active, dtype=np.int32)
+        s = _System(int(nocc), int(nvirt), int(nirrep),
+                    self._irrep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    self._eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    len(self._act), self._act.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = L.fscc_create(ctypes.byref(s), 0, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise FsccError(st, "fscc_create failed")
+        self._h = h
+        self.n1, self.n2 = self.layout(FSCC_S00)
+
+    @classmethod
+    def from_system(cls, sysm, stream=None):
+        return cls(sysm.nocc, sysm.nvirt, sysm.nirrep, sysm.irrep, sysm.eps, stream, getattr(sysm, "active", ()))
+
+    def _check(self, st):
+        if st != 0:
+            msg = lib().fscc_last_error(self._h)
+            raise FsccError(st, msg.decode() if msg else "")
+
+    def set_integrals(self, cls, dev_blocks):
+        k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)
+        self._check(lib().fscc_set_integrals(self._h, k, _dev_ptr(dev_blocks), dev_blocks.numel()))
+
+    def layout(self, sector=FSCC_S00):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(lib().fscc_layout(self._h, sector, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def build_residual(self, t1, t2, r1, r2, sector=FSCC_S00):
+        self._check(lib().fscc_build_residual(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+                                              _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2)))
+
+    def update_amplitudes(self, t1, t2, r1, r2, sector=FSCC_S00):
+        m = ctypes.c_double()
+        self._check(lib().fscc_update_amplitudes(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+                                                 _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2), ctypes.byref(m)))
+        return m.value
+
+    def energy(self, t1, t2):
+        er, ei = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().fscc_energy(self._h, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+                                      ctypes.byref(er), ctypes.byref(ei)))
+        return complex(er.value, ei.value)
+
+    def diis_reset(self, ndiis=6, sector=FSCC_S00):
+        self._check(lib().fscc_diis_reset(self._h, sector, int(ndiis)))
+
+    def ladder(self, tau, out):
+        self._check(lib().fscc_ladder(self._h, _dev_ptr(tau, self.n2), _dev_ptr(out, self.n2)))
+
+    def work(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().fscc_work(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(gemm_flops=a.value, ladder_flops=b.value, ladder_bytes=c.value)
+
+    def profile(self, enable=True):
+        self._check(lib().fscc_profile(self._h, 1 if enable else 0))
+
+    def op_times(self):
+        n = ctypes.c_int()
+        self._check(lib().fscc_op_count(self._h, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            nm, ms, calls, fl = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+            self._check(lib().fscc_op_info(self._h, k, ctypes.byref(nm), ctypes.byref(ms), ctypes.byref(calls),
+                                           ctypes.byref(fl)))
+            out.append(dict(name=nm.value.decode(), ms=ms.value, calls=calls.value, flops=fl.value))
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().fscc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
+    """Jacobi + DIIS iterations on the device until max|step| < tol.
+
+    Each iteration: fscc_build_residual -> fscc_update_amplitudes ->
+    fscc_energy.  Returns dict(E, iters, converged, history)."""
+    import torch
+    r1 = torch.empty_like(t1)
+    r2 = torch.empty_like(t2)
+    ctx.diis_reset(ndiis)
+    hist = []
+    E = 0j
+    converged = False
+    k = 0
+    for k in range(1, maxit + 1):
+        ctx.build_residual(t1, t2, r1, r2)
+        dmax = ctx.update_amplitudes(t1, t2, r1, r2)
+        E = ctx.energy(t1, t2)
+        hist.append(dict(iter=k, E=E, dmax=dmax))
+        if log:
+            log(f"iter {k:3d}  E = {E.real:+.14f} {E.imag:+.3e}i  max|step| = {dmax:.3e}")
+        if dmax < tol:
+            converged = True
+            break
+    return dict(E=E, iters=k, converged=converged, history=hist)

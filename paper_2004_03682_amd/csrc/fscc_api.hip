@@ -1,0 +1,514 @@
+// fscc_api.hip -- C ABI of the library (include/fscc.h): context, device
+// memory, execution of the residual plan on a HIP stream, Jacobi + DIIS
+// update and the correlation energy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fscc.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace fscc;
+
+namespace {
+
+struct GemmDev {
+    ZProb* probs = nullptr;
+    ZTile* tiles = nullptr;
+    int ntiles = 0;
+    int cfg = 0;
+};
+
+struct HipError : std::runtime_error {
+    explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kMaxDiis = 8;
+
+}  // namespace
+
+struct fscc_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    Plan plan;
+    std::vector<void*> dbuf;
+    std::vector<uint32_t*> dmap;
+    std::vector<GemmDev> gdev;
+    bool have_cls[IC_N] = {false, false, false, false, false, false};
+    // DIIS (sector 0h0p)
+    int ndiis = 6;
+    std::vector<int> order;    // occupied slots, oldest first
+    double2* hist_t = nullptr;
+    double2* hist_e = nullptr;
+    double* dB = nullptr;
+    double* part = nullptr;
+    double* part_max = nullptr;
+    double* coef = nullptr;
+    double* scal = nullptr;
+    int* dorder = nullptr;
+    double* hscal = nullptr;   // pinned host
+    double* epart = nullptr;
+    double* eout = nullptr;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> op_ms;
+    std::vector<int> op_calls;
+    std::string err;
+
+    int64_t n1() const { return plan.L_T1.total; }
+    int64_t n2() const { return plan.L_T2.total; }
+
+    void* dalloc(size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw std::bad_alloc();
+        return p;
+    }
+
+    ~fscc_ctx() {
+        for (size_t k = 0; k < dbuf.size(); ++k) {
+            BufKind kd = plan.bufs[k].kind;
+            if (kd != BUF_IN_T1 && kd != BUF_IN_T2 && kd != BUF_OUT_R1 && kd != BUF_OUT_R2 && dbuf[k]) (void)hipFree(dbuf[k]);
+        }
+        for (auto* m : dmap)
+            if (m) (void)hipFree(m);
+        for (auto& g : gdev) {
+            if (g.probs) (void)hipFree(g.probs);
+            if (g.tiles) (void)hipFree(g.tiles);
+        }
+        void* ps[] = {hist_t, hist_e, dB, part, part_max, coef, scal, dorder, epart, eout};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        if (hscal) (void)hipHostFree(hscal);
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+
+    double2* B(int id) const { return (double2*)dbuf[id]; }
+
+    void run_op(size_t k, const Op& o, int beta_override = -1, const double2* A_override = nullptr,
+                double2* C_override = nullptr) {
+        hipError_t e = hipSuccess;
+        switch (o.kind) {
+            case OP_AXPBY:
+                e = launch_axpby(B(o.dst), B(o.src), o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                break;
+            case OP_DIAG:
+                e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st);
+                break;
+            case OP_GATHER: {
+                GatherMaps gm;
+                for (int t = 0; t < 4; ++t) {
+                    gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
+                    gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
+                }
+                e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(), o.n,
+                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                break;
+            }
+            case OP_GEMM: {
+                const GemmDev& g = gdev[k];
+                int beta = beta_override >= 0 ? beta_override : o.beta;
+                e = launch_zgemm(g.cfg, o.tA, o.tB, A_override ? A_override : B(o.src), B(o.src2),
+                                 C_override ? C_override : B(o.dst), g.probs, g.tiles, g.ntiles, o.alpha.real(),
+                                 o.alpha.imag(), beta, o.cA, o.cB, st);
+                break;
+            }
+        }
+        hip_check(e, o.name.c_str());
+    }
+};
+
+namespace {
+
+fscc_status fail(fscc_ctx* c, fscc_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+template <class F>
+fscc_status guarded(fscc_ctx* c, F f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return fail(c, FSCC_EHIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(c, FSCC_ENOMEM, "device or host allocation failed");
+    } catch (const std::invalid_argument& e) {
+        return fail(c, FSCC_EINVAL, e.what());
+    } catch (const std::exception& e) {
+        return fail(c, FSCC_EINVAL, e.what());
+    } catch (...) {
+        return fail(c, FSCC_EINVAL, "unknown error");
+    }
+}
+
+void pick_gemm(const Op& o, GemmDev& g) {
+    int maxM = 0, maxN = 0;
+    for (auto& p : o.probs) {
+        maxM = std::max(maxM, p.M);
+        maxN = std::max(maxN, p.N);
+    }
+    if (maxN <= 16 && maxM > 64) g.cfg = ZCFG_128x16;
+    else if (maxM <= 16 && maxN > 64) g.cfg = ZCFG_16x128;
+    else g.cfg = ZCFG_64x64;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fscc_last_error(const fscc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_stream, fscc_ctx** out) {
+    if (!sys || !out) return FSCC_EINVAL;
+    *out = nullptr;
+    if (prec != FSCC_FP64) return FSCC_EINVAL;
+    if (sys->nocc < 0 || sys->nvirt < 0 || sys->nirrep < 1 || !sys->irrep || !sys->eps) return FSCC_EINVAL;
+    fscc_ctx* c = new (std::nothrow) fscc_ctx();
+    if (!c) return FSCC_ENOMEM;
+    fscc_status s = guarded(c, [&]() -> fscc_status {
+        hip_check(hipGetDevice(&c->device), "hipGetDevice");
+        c->st = (hipStream_t)hip_stream;
+        System S;
+        S.nocc = sys->nocc;
+        S.nvirt = sys->nvirt;
+        S.G = sys->nirrep;
+        int n = sys->nocc + sys->nvirt;
+        S.irrep.assign(sys->irrep, sys->irrep + n);
+        S.eps.assign(sys->eps, sys->eps + n);
+        for (int p = 0; p < n; ++p) {
+            if (S.irrep[p] < 0 || S.irrep[p] >= S.G) throw std::invalid_argument("irrep label out of range");
+            if (!std::isfinite(S.eps[p])) throw std::invalid_argument("non-finite orbital energy");
+        }
+        c->plan = build_plan_ccsd(S);
+        Plan& P = c->plan;
+        // buffers
+        c->dbuf.assign(P.bufs.size(), nullptr);
+        for (size_t k = 0; k < P.bufs.size(); ++k) {
+            const BufDesc& b = P.bufs[k];
+            if (b.kind == BUF_IN_T1 || b.kind == BUF_IN_T2 || b.kind == BUF_OUT_R1 || b.kind == BUF_OUT_R2) continue;
+            size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : sizeof(double2));
+            c->dbuf[k] = c->dalloc(bytes);
+        }
+        hip_check(hipMemcpy(c->dbuf[P.b_D1], P.D1.data(), P.D1.size() * sizeof(double), hipMemcpyHostToDevice), "D1");
+        hip_check(hipMemcpy(c->dbuf[P.b_D2], P.D2.data(), P.D2.size() * sizeof(double), hipMemcpyHostToDevice), "D2");
+        // maps of the per-iteration gathers (setup maps are uploaded at set_integrals)
+        c->dmap.assign(P.maps.size(), nullptr);
+        std::vector<char> is_setup(P.maps.size(), 0);
+        for (auto& sg : P.setup) is_setup[sg.map] = 1;
+        for (size_t k = 0; k < P.maps.size(); ++k) {
+            if (is_setup[k]) continue;
+            c->dmap[k] = (uint32_t*)c->dalloc(P.maps[k].size() * sizeof(uint32_t));
+            hip_check(hipMemcpy(c->dmap[k], P.maps[k].data(), P.maps[k].size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                      "map upload");
+            std::vector<uint32_t>().swap(P.maps[k]);
+        }
+        // grouped GEMM problem and tile lists
+        c->gdev.assign(P.ops.size(), GemmDev());
+        for (size_t k = 0; k < P.ops.size(); ++k) {
+            const Op& o = P.ops[k];
+            if (o.kind != OP_GEMM) continue;
+            GemmDev& g = c->gdev[k];
+            pick_gemm(o, g);
+            int bm, bn;
+            zcfg_tile(g.cfg, &bm, &bn);
+            std::vector<ZProb> pr;
+            std::vector<ZTile> tl;
+            for (size_t q = 0; q < o.probs.size(); ++q) {
+                const GemmProblem& p = o.probs[q];
+                pr.push_back(ZProb{p.a_off, p.b_off, p.c_off, p.M, p.N, p.K, p.lda, p.ldb, p.ldc});
+                for (int m0 = 0; m0 < p.M; m0 += bm)
+                    for (int n0 = 0; n0 < p.N; n0 += bn) tl.push_back(ZTile{(int)q, m0, n0, 0});
+            }
+            // longest-K tiles first (uneven symmetry blocks)
+            std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) {
+                return o.probs[a.prob].K > o.probs[b.prob].K;
+            });
+            g.ntiles = (int)tl.size();
+            g.probs = (ZProb*)c->dalloc(pr.size() * sizeof(ZProb));
+            g.tiles = (ZTile*)c->dalloc(tl.size() * sizeof(ZTile));
+            if (!pr.empty())
+                hip_check(hipMemcpy(g.probs, pr.data(), pr.size() * sizeof(ZProb), hipMemcpyHostToDevice), "probs");
+            if (!tl.empty())
+                hip_check(hipMemcpy(g.tiles, tl.data(), tl.size() * sizeof(ZTile), hipMemcpyHostToDevice), "tiles");
+        }
+        // DIIS and reduction scratch
+        int64_t nt = c->n1() + c->n2();
+        c->hist_t = (double2*)c->dalloc((size_t)kMaxDiis * nt * sizeof(double2));
+        c->hist_e = (double2*)c->dalloc((size_t)kMaxDiis * nt * sizeof(double2));
+        c->dB = (double*)c->dalloc(kMaxDiis * kMaxDiis * sizeof(double));
+        c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
+        c->part_max = (double*)c->dalloc(2048 * sizeof(double));
+        c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
+        c->scal = (double*)c->dalloc(4 * sizeof(double));
+        c->dorder = (int*)c->dalloc(kMaxDiis * sizeof(int));
+        c->epart = (double*)c->dalloc(2048 * sizeof(double));
+        c->eout = (double*)c->dalloc(4 * sizeof(double));
+        hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+        c->op_ms.assign(P.ops.size(), 0.0);
+        c->op_calls.assign(P.ops.size(), 0);
+        return FSCC_OK;
+    });
+    if (s != FSCC_OK) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return FSCC_OK;
+}
+
+void fscc_destroy(fscc_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+    else (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+fscc_status fscc_layout(const fscc_ctx* ctx, fscc_sector sector, size_t* n1, size_t* n2) {
+    if (!ctx || !n1 || !n2) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return FSCC_EINVAL;
+    *n1 = (size_t)ctx->n1();
+    *n2 = (size_t)ctx->n2();
+    return FSCC_OK;
+}
+
+fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* dev_blocks, size_t n) {
+    if (!ctx) return FSCC_EINVAL;
+    if ((int)cls < 0 || (int)cls >= IC_N) return fail(ctx, FSCC_EINVAL, "bad integral class");
+    Plan& P = ctx->plan;
+    if ((int64_t)n != P.full[cls].total)
+        return fail(ctx, FSCC_EINVAL, "integral class size " + std::to_string(n) + " != expected " +
+                                          std::to_string(P.full[cls].total));
+    if (n > 0 && !dev_blocks) return fail(ctx, FSCC_EINVAL, "null integral buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        for (auto& sg : P.setup) {
+            if (sg.cls != (int)cls) continue;
+            std::vector<uint32_t>& m = P.maps[sg.map];
+            uint32_t* dm = nullptr;
+            int64_t cnt = P.bufs[sg.dst].n;
+            if (cnt > 0) {
+                if ((int64_t)m.size() != cnt) throw std::logic_error("setup map already consumed: " + sg.name);
+                dm = (uint32_t*)ctx->dalloc(m.size() * sizeof(uint32_t));
+                hip_check(hipMemcpyAsync(dm, m.data(), m.size() * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->st),
+                          "pack map upload");
+                GatherMaps gm{};
+                gm.a[0] = dm;
+                hip_check(launch_gather(ctx->B(sg.dst), (const double2*)dev_blocks, nullptr, gm, 1, cnt, 1.0, 0.0, 0,
+                                        sg.conj ? 1 : 0, ctx->st),
+                          "integral pack");
+                hip_check(hipStreamSynchronize(ctx->st), "pack sync");
+                (void)hipFree(dm);
+            }
+        }
+        ctx->have_cls[cls] = true;
+        return FSCC_OK;
+    });
+}
+
+static bool all_integrals(const fscc_ctx* c) {
+    for (int k = 0; k < IC_N; ++k)
+        if (!c->have_cls[k]) return false;
+    return true;
+}
+
+static void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2) {
+    Plan& P = c->plan;
+    c->dbuf[P.b_t1] = (void*)t1;
+    c->dbuf[P.b_t2] = (void*)t2;
+    c->dbuf[P.b_r1] = (void*)r1;
+    c->dbuf[P.b_r2] = (void*)r2;
+}
+
+fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2,
+                                fscc_c128* r1, fscc_c128* r2) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
+    if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
+    if ((ctx->n1() && (!t1 || !r1)) || (ctx->n2() && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    if ((ctx->n1() && (const void*)r1 == (const void*)t1) || (ctx->n2() && (const void*)r2 == (const void*)t2))
+        return fail(ctx, FSCC_EINVAL, "residual aliases amplitudes");
+    return guarded(ctx, [&]() -> fscc_status {
+        bind_io(ctx, t1, t2, r1, r2);
+        Plan& P = ctx->plan;
+        if (ctx->prof && ctx->ev.size() != 2 * P.ops.size()) {
+            ctx->ev.assign(2 * P.ops.size(), nullptr);
+            for (auto& e : ctx->ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+        }
+        for (size_t k = 0; k < P.ops.size(); ++k) {
+            if (ctx->prof) hip_check(hipEventRecord(ctx->ev[2 * k], ctx->st), "event");
+            ctx->run_op(k, P.ops[k]);
+            if (ctx->prof) hip_check(hipEventRecord(ctx->ev[2 * k + 1], ctx->st), "event");
+        }
+        if (ctx->prof) {
+            hip_check(hipStreamSynchronize(ctx->st), "profile sync");
+            for (size_t k = 0; k < P.ops.size(); ++k) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, ctx->ev[2 * k], ctx->ev[2 * k + 1]), "elapsed");
+                ctx->op_ms[k] += ms;
+                ctx->op_calls[k] += 1;
+            }
+        }
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_ladder(fscc_ctx* ctx, const fscc_c128* tau, fscc_c128* out) {
+    if (!ctx || !tau || !out) return FSCC_EINVAL;
+    if (!ctx->have_cls[IC_VVVV]) return fail(ctx, FSCC_ESTATE, "VVVV integrals not set");
+    return guarded(ctx, [&]() -> fscc_status {
+        Plan& P = ctx->plan;
+        for (size_t k = 0; k < P.ops.size(); ++k)
+            if (P.ops[k].name == "pp-ladder") {
+                ctx->run_op(k, P.ops[k], 0, (const double2*)tau, (double2*)out);
+                return FSCC_OK;
+            }
+        throw std::logic_error("no ladder op");
+    });
+}
+
+fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
+    if (ndiis < 0 || ndiis > kMaxDiis) return fail(ctx, FSCC_EINVAL, "DIIS depth out of range");
+    ctx->ndiis = ndiis;
+    ctx->order.clear();
+    return FSCC_OK;
+}
+
+fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2,
+                                   const fscc_c128* r1, const fscc_c128* r2, double* max_step) {
+    if (!ctx || !max_step) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
+    if ((ctx->n1() && (!t1 || !r1)) || (ctx->n2() && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        Plan& P = ctx->plan;
+        const int64_t n1 = ctx->n1(), n2 = ctx->n2(), n = n1 + n2;
+        const int depth = std::max(1, ctx->ndiis);
+        std::vector<int>& ord = ctx->order;
+        int slot;
+        if ((int)ord.size() < depth) {
+            std::vector<char> used(kMaxDiis, 0);
+            for (int s : ord) used[s] = 1;
+            slot = 0;
+            while (used[slot]) ++slot;
+        } else {
+            slot = ord.front();
+            ord.erase(ord.begin());
+        }
+        // the new slot's B row must not see stale entries of dropped slots: they are
+        // only read through `order`, which lists live slots only.
+        ord.push_back(slot);
+        double2* ht = ctx->hist_t + (size_t)slot * n;
+        double2* he = ctx->hist_e + (size_t)slot * n;
+        int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
+        if (n1 > 0)
+            hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[P.b_D1], ht, he, n1,
+                                    ctx->part_max, nb1, ctx->st),
+                      "jacobi t1");
+        if (n2 > 0)
+            hip_check(launch_jacobi((const double2*)t2, (const double2*)r2, (const double*)ctx->dbuf[P.b_D2], ht + n1,
+                                    he + n1, n2, ctx->part_max + nb1, nb2, ctx->st),
+                      "jacobi t2");
+        int m = (int)ord.size();
+        std::vector<const double2*> ev(m);
+        for (int j = 0; j < m; ++j) ev[j] = ctx->hist_e + (size_t)ord[j] * n;
+        int nbd = reduce_blocks(n);
+        hip_check(launch_dots(ev.data(), m, he, n, ctx->part, nbd, ctx->st), "diis dots");
+        hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st), "order");
+        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, ctx->dB, kMaxDiis, slot, ctx->dorder,
+                                     ctx->coef, ctx->scal, ctx->st),
+                  "diis solve");
+        std::vector<const double2*> xs(kMaxDiis);
+        for (int s = 0; s < kMaxDiis; ++s) xs[s] = ctx->hist_t + (size_t)s * n;
+        if (n1 > 0) hip_check(launch_lincomb((double2*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb t1");
+        if (n2 > 0) {
+            for (int s = 0; s < kMaxDiis; ++s) xs[s] = ctx->hist_t + (size_t)s * n + n1;
+            hip_check(launch_lincomb((double2*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb t2");
+        }
+        hip_check(hipMemcpyAsync(ctx->hscal, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "scal");
+        hip_check(hipStreamSynchronize(ctx->st), "update sync");
+        int dropped = (int)ctx->hscal[1];
+        if (dropped > 0) ord.erase(ord.begin(), ord.begin() + std::min(dropped, (int)ord.size() - 1));
+        if (ctx->ndiis <= 1) ord.clear();
+        double mx = ctx->hscal[0];
+        if (!std::isfinite(mx)) return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step");
+        *max_step = mx;
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_energy(fscc_ctx* ctx, const fscc_c128* t1, const fscc_c128* t2, double* e_re, double* e_im) {
+    if (!ctx || !e_re || !e_im) return FSCC_EINVAL;
+    if (!ctx->have_cls[IC_OOVV]) return fail(ctx, FSCC_ESTATE, "OOVV integrals not set");
+    if ((ctx->n1() && !t1) || (ctx->n2() && !t2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        Plan& P = ctx->plan;
+        bind_io(ctx, t1, t2, nullptr, nullptr);
+        // tau = t2 + t1 t1 (the first two operations of the plan)
+        for (size_t k = 0; k < 2; ++k) ctx->run_op(k, P.ops[k]);
+        int nb = reduce_blocks(ctx->n2());
+        hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st), "energy");
+        hip_check(hipMemcpyAsync(ctx->hscal + 4, ctx->eout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "e d2h");
+        hip_check(hipStreamSynchronize(ctx->st), "energy sync");
+        *e_re = ctx->hscal[4];
+        *e_im = ctx->hscal[5];
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_work(const fscc_ctx* ctx, double* gemm_flops, double* ladder_flops, double* ladder_bytes) {
+    if (!ctx || !gemm_flops || !ladder_flops || !ladder_bytes) return FSCC_EINVAL;
+    const Plan& P = ctx->plan;
+    double f = 0, lf = 0, lb = 0;
+    for (auto& o : P.ops) {
+        if (o.kind != OP_GEMM) continue;
+        f += o.flops;
+        if (o.name == "pp-ladder") {
+            lf = o.flops;
+            lb = 16.0 * (double)P.bufs[o.src2].n;
+        }
+    }
+    *gemm_flops = f;
+    *ladder_flops = lf;
+    *ladder_bytes = lb;
+    return FSCC_OK;
+}
+
+fscc_status fscc_profile(fscc_ctx* ctx, int enable) {
+    if (!ctx) return FSCC_EINVAL;
+    ctx->prof = enable != 0;
+    std::fill(ctx->op_ms.begin(), ctx->op_ms.end(), 0.0);
+    std::fill(ctx->op_calls.begin(), ctx->op_calls.end(), 0);
+    return FSCC_OK;
+}
+
+fscc_status fscc_op_count(const fscc_ctx* ctx, int* count) {
+    if (!ctx || !count) return FSCC_EINVAL;
+    *count = (int)ctx->plan.ops.size();
+    return FSCC_OK;
+}
+
+fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, int* calls, double* flops) {
+    if (!ctx || !name || !ms || !calls || !flops) return FSCC_EINVAL;
+    if (k < 0 || k >= (int)ctx->plan.ops.size()) return fail(ctx, FSCC_EINVAL, "op index out of range");
+    *name = ctx->plan.ops[k].name.c_str();
+    *ms = ctx->op_ms[k];
+    *calls = ctx->op_calls[k];
+    *flops = ctx->plan.ops[k].flops;
+    return FSCC_OK;
+}
+
+}  // extern "C"

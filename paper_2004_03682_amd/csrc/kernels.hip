@@ -1,0 +1,661 @@
+// kernels.hip -- gfx950 kernels of the FS-RCCSD hot path.
+//
+//  * k_zgemm   grouped complex GEMM on FP64 matrix cores
+//              (v_mfma_f64_16x16x4_f64), LDS-staged tiles, one workgroup per
+//              output tile of a flat tile list covering every (problem = pair
+//              irrep block) of one contraction.  Complex products use four
+//              real MFMA chains: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+//  * k_gather  reorders / antisymmetrisers of the TTGT scheme: a gather through
+//              precomputed 32-bit maps (offset + sign bit), up to four terms,
+//              optionally multiplied by a second gathered operand (t1 x t1).
+//  * elementwise / reduction kernels of the Jacobi + DIIS update and the energy.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fscc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+static constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------
+// grouped complex GEMM
+
+template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
+                                               double2* __restrict__ C, const ZProb* __restrict__ probs,
+                                               const ZTile* __restrict__ tiles, double ar, double ai, int beta,
+                                               int cA, int cB) {
+    constexpr int BK = 16;
+    constexpr int PAD = 4;
+    constexpr int FM = BM / (16 * WM);
+    constexpr int FN = BN / (16 * WN);
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(FM >= 1 && FN >= 1, "tile too small");
+    __shared__ double As[2][BK][BM + PAD];
+    __shared__ double Bs[2][BK][BN + PAD];
+
+    const ZTile tl = tiles[blockIdx.x];
+    const ZProb pr = probs[tl.prob];
+    const int M = pr.M, N = pr.N, K = pr.K;
+    const double2* Ap = A + pr.a_off;
+    const double2* Bp = B + pr.b_off;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int m0 = tl.m0, n0 = tl.n0;
+    const double sA = cA ? -1.0 : 1.0;
+    const double sB = cB ? -1.0 : 1.0;
+
+    dbl4 accr[FM][FN], acci[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            accr[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+
+    // register staging of one BK slice: vectors of 4 consecutive complex along
+    // the contiguous dimension of each operand
+    constexpr int AV = BM * BK / 4;   // vec4 per A slice
+    constexpr int BV = BN * BK / 4;
+    constexpr int AVT = (AV + kThreads - 1) / kThreads;
+    constexpr int BVT = (BV + kThreads - 1) / kThreads;
+    double2 ra[AVT][4], rb[BVT][4];
+
+    auto load_slice = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < AVT; ++u) {
+            int v = tid + u * kThreads;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ra[u][e] = make_double2(0.0, 0.0);
+            if (v < AV) {
+                if (!TA) {   // A row-major [M][lda], k contiguous
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+                    int m = m0 + r;
+                    if (m < M) {
+                        const double2* p = Ap + (long long)m * pr.lda + k0 + kk;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (k0 + kk + e < K) ra[u][e] = p[e];
+                    }
+                } else {     // A stored [K][lda], m contiguous
+                    int kr = v / (BM / 4), mm = (v % (BM / 4)) * 4;
+                    int k = k0 + kr;
+                    if (k < K) {
+                        const double2* p = Ap + (long long)k * pr.lda + m0 + mm;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (m0 + mm + e < M) ra[u][e] = p[e];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BVT; ++u) {
+            int v = tid + u * kThreads;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rb[u][e] = make_double2(0.0, 0.0);
+            if (v < BV) {
+                if (!TB) {   // B row-major [K][ldb], n contiguous
+                    int kr = v / (BN / 4), nn = (v % (BN / 4)) * 4;
+                    int k = k0 + kr;
+                    if (k < K) {
+                        const double2* p = Bp + (long long)k * pr.ldb + n0 + nn;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (n0 + nn + e < N) rb[u][e] = p[e];
+                    }
+                } else {     // B stored [N][ldb], k contiguous
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+                    int n = n0 + r;
+                    if (n < N) {
+                        const double2* p = Bp + (long long)n * pr.ldb + k0 + kk;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (k0 + kk + e < K) rb[u][e] = p[e];
+                    }
+                }
+            }
+        }
+    };
+
+    auto store_slice = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < AVT; ++u) {
+            int v = tid + u * kThreads;
+            if (v < AV) {
+                if (!TA) {
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        As[buf][kk + e][r] = ra[u][e].x;
+                    }
+                } else {
+                    int kr = v / (BM / 4), mm = (v % (BM / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) As[buf][kr][mm + e] = ra[u][e].x;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BVT; ++u) {
+            int v = tid + u * kThreads;
+            if (v < BV) {
+                if (!TB) {
+                    int kr = v / (BN / 4), nn = (v % (BN / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[buf][kr][nn + e] = rb[u][e].x;
+                } else {
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[buf][kk + e][r] = rb[u][e].x;
+                }
+            }
+        }
+    };
+    // imaginary planes share the same LDS arrays in a second pass (see below)
+    auto store_slice_im = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < AVT; ++u) {
+            int v = tid + u * kThreads;
+            if (v < AV) {
+                if (!TA) {
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) As[buf][kk + e][r] = sA * ra[u][e].y;
+                } else {
+                    int kr = v / (BM / 4), mm = (v % (BM / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) As[buf][kr][mm + e] = sA * ra[u][e].y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BVT; ++u) {
+            int v = tid + u * kThreads;
+            if (v < BV) {
+                if (!TB) {
+                    int kr = v / (BN / 4), nn = (v % (BN / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[buf][kr][nn + e] = sB * rb[u][e].y;
+                } else {
+                    int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[buf][kk + e][r] = sB * rb[u][e].y;
+                }
+            }
+        }
+    };
+
+    const int lr = lane & 15;        // row (A) / column (B) inside a 16-wide fragment
+    const int lk = lane >> 4;        // k inside a 4-deep step
+    const int wm0 = wm * FM * 16, wn0 = wn * FN * 16;
+
+    // LDS buffer 0 holds the real planes, buffer 1 the imaginary planes; the
+    // global loads of slice k+1 are in flight while slice k is multiplied
+    if (K > 0) load_slice(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store_slice(0);
+        store_slice_im(1);
+        __syncthreads();
+        if (k0 + BK < K) load_slice(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            double a_r[FM], a_i[FM], a_n[FM], b_r[FN], b_i[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                a_r[i] = As[0][ks * 4 + lk][wm0 + i * 16 + lr];
+                a_i[i] = As[1][ks * 4 + lk][wm0 + i * 16 + lr];
+                a_n[i] = -a_i[i];
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                b_r[j] = Bs[0][ks * 4 + lk][wn0 + j * 16 + lr];
+                b_i[j] = Bs[1][ks * 4 + lk][wn0 + j * 16 + lr];
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], acci[i][j], 0, 0, 0);
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], acci[i][j], 0, 0, 0);
+                }
+        }
+    }
+
+    // epilogue: for the FP64 16x16x4 MFMA, accumulator element q of a lane is
+    // row 4*q + lane/16, column lane%16 of the fragment
+    double2* Cp = C + pr.c_off;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            int col = n0 + wn0 + j * 16 + lr;
+            if (col >= N) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int row = m0 + wm0 + i * 16 + q * 4 + lk;
+                if (row >= M) continue;
+                double xr = accr[i][j][q], xi = acci[i][j][q];
+                double2 out = make_double2(ar * xr - ai * xi, ar * xi + ai * xr);
+                double2* c = Cp + (long long)row * pr.ldc + col;
+                if (beta) {
+                    double2 old = *c;
+                    out.x += old.x;
+                    out.y += old.y;
+                }
+                *c = out;
+            }
+        }
+}
+
+void zcfg_tile(int cfg, int* bm, int* bn) {
+    switch (cfg) {
+        case ZCFG_128x16: *bm = 128; *bn = 16; break;
+        case ZCFG_16x128: *bm = 16; *bn = 128; break;
+        default: *bm = 64; *bn = 64; break;
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
+                             const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
+                             hipStream_t st) {
+    dim3 grid(ntiles), block(kThreads);
+    if (!tA && !tB) k_zgemm<BM, BN, WM, WN, false, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    else if (!tA && tB) k_zgemm<BM, BN, WM, WN, false, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    else if (tA && !tB) k_zgemm<BM, BN, WM, WN, true, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    else k_zgemm<BM, BN, WM, WN, true, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    return hipGetLastError();
+}
+
+hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
+                        const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
+                        hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (cfg) {
+        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        default: return launch_cfg<64, 64, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gather / reorder
+
+__device__ __forceinline__ double2 map_load(const double2* __restrict__ s, uint32_t m) {
+    if (m == 0xFFFFFFFFu) return make_double2(0.0, 0.0);
+    double2 x = s[m & 0x7FFFFFFFu];
+    if (m & 0x80000000u) {
+        x.x = -x.x;
+        x.y = -x.y;
+    }
+    return x;
+}
+
+template <int NT, bool BIL>
+__global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                const double2* __restrict__ src2, GatherMaps maps, long long n,
+                                                double ar, double ai, int beta, int conj) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double2 x = map_load(src, maps.a[t][k]);
+        if (conj) x.y = -x.y;
+        if (BIL) {
+            double2 y = map_load(src2, maps.b[t][k]);
+            double xr = x.x * y.x - x.y * y.y, xi = x.x * y.y + x.y * y.x;
+            x.x = xr;
+            x.y = xi;
+        }
+        sr += x.x;
+        si += x.y;
+    }
+    double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+    if (beta) {
+        double2 o = dst[k];
+        out.x += o.x;
+        out.y += o.y;
+    }
+    dst[k] = out;
+}
+
+hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
+                         long long n, double ar, double ai, int beta, int conj, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads)), block(kThreads);
+    bool bil = src2 != nullptr;
+#define FSCC_G(NT)                                                                                               \
+    if (bil) k_gather<NT, true><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj);          \
+    else k_gather<NT, false><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj);
+    switch (nt) {
+        case 1: FSCC_G(1); break;
+        case 2: FSCC_G(2); break;
+        case 3: FSCC_G(3); break;
+        case 4: FSCC_G(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FSCC_G
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+
+__global__ __launch_bounds__(256) void k_axpby(double2* __restrict__ dst, const double2* __restrict__ src, long long n,
+                                               double ar, double ai, int beta, int conj) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double2 x = src[k];
+    if (conj) x.y = -x.y;
+    double2 out = make_double2(ar * x.x - ai * x.y, ar * x.y + ai * x.x);
+    if (beta) {
+        double2 o = dst[k];
+        out.x += o.x;
+        out.y += o.y;
+    }
+    dst[k] = out;
+}
+
+hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
+                        hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_axpby<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, src, n, ar, ai, beta, conj);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_diag(double2* __restrict__ dst, const double* __restrict__ d,
+                                              const double2* __restrict__ src, long long n) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double2 o = dst[k], x = src[k];
+    double dd = d[k];
+    o.x -= dd * x.x;
+    o.y -= dd * x.y;
+    dst[k] = o;
+}
+
+hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_diag<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, d, src, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero(double2* __restrict__ dst, long long n) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_zero(double2* dst, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_zero<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic: fixed grid, per-block partials, one final block)
+
+int reduce_blocks(long long n) {
+    long long b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
+            sh[threadIdx.x] = (a > b || a != a) ? a : b;   // NaN propagates
+        }
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi(const double2* __restrict__ t, const double2* __restrict__ r,
+                                                const double* __restrict__ D, double2* __restrict__ ht,
+                                                double2* __restrict__ he, long long n, double* part_max) {
+    __shared__ double sh[kThreads];
+    double mx = 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double2 rr = r[k], tt = t[k];
+        double d = D[k];
+        double2 s = make_double2(rr.x / d, rr.y / d);
+        he[k] = s;
+        ht[k] = make_double2(tt.x + s.x, tt.y + s.y);
+        double a = sqrt(s.x * s.x + s.y * s.y);
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    double b = block_max(mx, sh);
+    if (threadIdx.x == 0) part_max[blockIdx.x] = b;
+}
+
+hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
+                         long long n, double* part_max, int nblk, hipStream_t st) {
+    k_jacobi<<<nblk, kThreads, 0, st>>>(t, r, D, hist_t, hist_e, n, part_max);
+    return hipGetLastError();
+}
+
+// part[b*8 + j] = Re sum conj(e_j) enew over block b's share
+struct PtrList {
+    const double2* p[8];
+};
+
+__global__ __launch_bounds__(256) void k_dots(PtrList e, int m, const double2* __restrict__ enew, long long n,
+                                              double* part) {
+    __shared__ double sh[kThreads];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double2 y = enew[k];
+        for (int j = 0; j < m; ++j) {
+            double2 x = e.p[j][k];
+            acc[j] += x.x * y.x + x.y * y.y;
+        }
+    }
+    for (int j = 0; j < m; ++j) {
+        double b = block_sum(acc[j], sh);
+        if (threadIdx.x == 0) part[blockIdx.x * 8 + j] = b;
+    }
+}
+
+hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
+                       hipStream_t st) {
+    PtrList pl;
+    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? e[j] : nullptr;
+    k_dots<<<nblk, kThreads, 0, st>>>(pl, m, enew, n, part);
+    return hipGetLastError();
+}
+
+// One workgroup: reduce the dot partials into row/column `newslot` of B,
+// then solve the bordered Pulay system over the slots listed in `order`
+// (oldest first) by Gaussian elimination with partial pivoting in FP64;
+// if a pivot is below 1e-14 * max|A| the oldest slot is dropped and the solve
+// repeated.  coef[slot] receives the coefficient (0 for unused slots);
+// scal[0] = max |step|, scal[1] = number of dropped slots.
+__global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ part, int nblk, int m,
+                                                     const double* __restrict__ part_max, int nblk_max,
+                                                     double* __restrict__ B, int ldb, int newslot,
+                                                     const int* __restrict__ order, double* __restrict__ coef,
+                                                     double* __restrict__ scal) {
+    __shared__ double sh[kThreads];
+    __shared__ double row[8];
+    for (int j = 0; j < m; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * 8 + j];
+        double s = block_sum(v, sh);
+        if (threadIdx.x == 0) row[j] = s;
+    }
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk_max; b += kThreads) {
+        double a = part_max[b];
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    mx = block_max(mx, sh);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    scal[0] = mx;
+    // row[j] pairs the new vector with the slot order[j]
+    for (int j = 0; j < m; ++j) {
+        B[newslot * ldb + order[j]] = row[j];
+        B[order[j] * ldb + newslot] = row[j];
+    }
+    for (int j = 0; j < ldb; ++j) coef[j] = 0.0;
+    int first = 0, dropped = 0;
+    while (true) {
+        int k = m - first;
+        if (k <= 1) {
+            coef[order[m - 1]] = 1.0;
+            break;
+        }
+        double a[9][10];
+        double scale = 0.0;
+        for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(B[order[first + i] * ldb + order[first + i]]));
+        if (!(scale > 0.0)) scale = 1.0;
+        for (int i = 0; i < k; ++i) {
+            for (int j = 0; j < k; ++j) a[i][j] = B[order[first + i] * ldb + order[first + j]] / scale;
+            a[i][k] = -1.0;
+            a[i][k + 1] = 0.0;
+        }
+        for (int j = 0; j < k; ++j) a[k][j] = -1.0;
+        a[k][k] = 0.0;
+        a[k][k + 1] = -1.0;
+        int nn = k + 1;
+        double amax = 0.0;
+        for (int i = 0; i < nn; ++i)
+            for (int j = 0; j < nn; ++j) amax = fmax(amax, fabs(a[i][j]));
+        bool singular = false;
+        for (int c = 0; c < nn && !singular; ++c) {
+            int p = c;
+            for (int i = c + 1; i < nn; ++i)
+                if (fabs(a[i][c]) > fabs(a[p][c])) p = i;
+            if (!(fabs(a[p][c]) >= 1e-14 * amax)) {
+                singular = true;
+                break;
+            }
+            if (p != c)
+                for (int j = 0; j <= nn; ++j) {
+                    double t = a[c][j];
+                    a[c][j] = a[p][j];
+                    a[p][j] = t;
+                }
+            for (int i = c + 1; i < nn; ++i) {
+                double f = a[i][c] / a[c][c];
+                for (int j = c; j <= nn; ++j) a[i][j] -= f * a[c][j];
+            }
+        }
+        if (singular) {
+            ++first;
+            ++dropped;
+            continue;
+        }
+        double x[9];
+        for (int i = nn - 1; i >= 0; --i) {
+            double s = a[i][nn];
+            for (int j = i + 1; j < nn; ++j) s -= a[i][j] * x[j];
+            x[i] = s / a[i][i];
+        }
+        for (int i = 0; i < k; ++i) coef[order[first + i]] = x[i];
+        break;
+    }
+    scal[1] = (double)dropped;
+}
+
+hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
+                              int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st) {
+    k_finish_diis<<<1, kThreads, 0, st>>>(part, nblk, m, part_max, nblk_max, B, ldb, newslot, order, coef, scal);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_lincomb(double2* __restrict__ out, PtrList xs, const double* __restrict__ coef,
+                                                 int m, long long n) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double c = coef[j];
+        if (c != 0.0) {
+            double2 x = xs.p[j][k];
+            sr += c * x.x;
+            si += c * x.y;
+        }
+    }
+    out[k] = make_double2(sr, si);
+}
+
+hipError_t launch_lincomb(double2* out, const double2* const* xs, const double* coef, int m, long long n,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    PtrList pl;
+    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? xs[j] : nullptr;
+    k_lincomb<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(out, pl, coef, m, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zdotu_part(const double2* __restrict__ x, const double2* __restrict__ y,
+                                                    long long n, double* part) {
+    __shared__ double sh[kThreads];
+    double sr = 0.0, si = 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double2 a = x[k], b = y[k];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+    }
+    double r = block_sum(sr, sh);
+    double i = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r;
+        part[2 * blockIdx.x + 1] = i;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ part, int nblk, double* out) {
+    __shared__ double sh[kThreads];
+    double r = 0.0, i = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        r += part[2 * b];
+        i += part[2 * b + 1];
+    }
+    r = block_sum(r, sh);
+    i = block_sum(i, sh);
+    if (threadIdx.x == 0) {
+        out[0] = r;
+        out[1] = i;
+    }
+}
+
+hipError_t launch_zdotu(const double2* x, const double2* y, long long n, double* part, int nblk, double* out,
+                        hipStream_t st) {
+    k_zdotu_part<<<nblk, kThreads, 0, st>>>(x, y, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sum2<<<1, kThreads, 0, st>>>(part, nblk, out);
+    return hipGetLastError();
+}
+
+}  // namespace fscc

@@ -1,0 +1,62 @@
+// kernels.hpp -- launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fscc {
+
+// one GEMM problem (offsets in complex elements)
+struct ZProb {
+    long long a_off, b_off, c_off;
+    int M, N, K, lda, ldb, ldc;
+};
+// one output tile of one problem
+struct ZTile {
+    int prob, m0, n0, pad;
+};
+
+// tile shapes of the grouped complex GEMM
+enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16 = 1, ZCFG_16x128 = 2, ZCFG_N };
+void zcfg_tile(int cfg, int* bm, int* bn);
+
+// C(m,n) = alpha * sum_k opA(m,k) opB(k,n) + beta*C(m,n)  for every tile in `tiles`
+//   !tA: A(m,k) = A[a_off + m*lda + k]      tA: A(m,k) = A[a_off + k*lda + m]
+//   !tB: B(k,n) = B[b_off + k*ldb + n]      tB: B(k,n) = B[b_off + n*ldb + k]
+//   cA/cB conjugate the operand; beta is 0 (overwrite) or 1 (accumulate).
+hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
+                        const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
+                        hipStream_t st);
+
+// dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
+struct GatherMaps {
+    const uint32_t* a[4];
+    const uint32_t* b[4];
+};
+hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
+                         long long n, double ar, double ai, int beta, int conj, hipStream_t st);
+
+hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
+                        hipStream_t st);
+hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st);
+
+// Jacobi: step = r/D; tn = t + step (written to hist_t), e = step (hist_e);
+// per-block max |step| into part_max[block]
+hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
+                         long long n, double* part_max, int nblk, hipStream_t st);
+// sum_b part[b*stride + j] -> out[j]  (j < cols), and max over part_max
+hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
+                       hipStream_t st);
+hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
+                              int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st);
+hipError_t launch_lincomb(double2* out, const double2* const* xs, const double* coef, int m, long long n,
+                          hipStream_t st);
+// complex dot sum_k x[k]*y[k] (no conjugation): per-block partials then final
+hipError_t launch_zdotu(const double2* x, const double2* y, long long n, double* part, int nblk, double* out,
+                        hipStream_t st);
+hipError_t launch_zero(double2* dst, long long n, hipStream_t st);
+
+int reduce_blocks(long long n);
+
+}  // namespace fscc

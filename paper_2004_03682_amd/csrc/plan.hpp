@@ -1,0 +1,113 @@
+// plan.hpp -- the residual as a list of elementary operations.
+//
+// Every Goldstone-diagram contraction is evaluated by the TTGT scheme of the
+// algorithm-design section: reorder the operands into supermatrix layouts
+// (gather ops), one grouped complex GEMM over the symmetry blocks (one
+// problem per pair irrep, the block loop of Fig. 4), then reorder and
+// antisymmetrise the result into the residual (gather-accumulate ops).
+// The plan is pure host data: buffers, gather maps and GEMM problem lists.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.hpp"
+
+namespace fscc {
+
+using cplx = std::complex<double>;
+
+enum BufKind { BUF_IN_T1, BUF_IN_T2, BUF_OUT_R1, BUF_OUT_R2, BUF_CONST, BUF_SCRATCH, BUF_REAL };
+
+struct BufDesc {
+    std::string name;
+    int64_t n;        // complex elements (doubles for BUF_REAL)
+    BufKind kind;
+};
+
+struct GemmProblem {
+    int64_t a_off, b_off, c_off;
+    int M, N, K;
+    int lda, ldb, ldc;
+};
+
+enum OpKind {
+    OP_GATHER,   // dst[k] = beta*dst[k] + alpha * sum_t s_t * cj(src[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
+    OP_GEMM,     // grouped: C = alpha*op(A)op(B) + beta*C
+    OP_AXPBY,    // dst[k] = alpha*cj(src[k]) + beta*dst[k]
+    OP_DIAG,     // dst[k] -= d[k] * src[k]   (d real)
+};
+
+struct Op {
+    OpKind kind;
+    std::string name;
+    int dst = -1, src = -1, src2 = -1;
+    std::vector<int> mapsA, mapsB;   // gather maps (map ids)
+    cplx alpha = 1.0;
+    int beta = 0;
+    bool conj = false;
+    int64_t n = 0;
+    // GEMM
+    bool tA = false, tB = false, cA = false, cB = false;
+    std::vector<GemmProblem> probs;
+    double flops = 0;                // real flops (8 per complex MAC)
+};
+
+// integral classes
+enum IClass { IC_OOOO = 0, IC_OOOV, IC_OOVV, IC_OVOV, IC_OVVV, IC_VVVV, IC_N };
+
+// a derived constant built at set_integrals time from one class
+struct SetupGather {
+    int cls;
+    int dst;          // buffer id
+    int map;          // map id (from the class's FullBlocks buffer)
+    bool conj;
+    std::string name;
+};
+
+struct System {
+    int nocc = 0, nvirt = 0, G = 1;
+    std::vector<int> irrep;     // global order
+    std::vector<double> eps;    // global order
+    std::vector<int> active;    // global indices of active virtuals (0h1p)
+};
+
+struct Plan {
+    int G = 1;
+    Space O, V;
+    std::vector<BufDesc> bufs;
+    std::vector<std::vector<uint32_t>> maps;
+    std::vector<std::string> map_names;
+    std::vector<Op> ops;
+    std::vector<SetupGather> setup;
+    FullBlocks full[IC_N];
+    // stored layouts of the caller's amplitudes
+    Layout L_T1, L_T2;
+    int b_t1 = -1, b_t2 = -1, b_r1 = -1, b_r2 = -1;
+    int b_D1 = -1, b_D2 = -1;         // real denominators in T1/T2 layouts
+    int b_oovv = -1;                  // <ij||ab> in the T2 layout (energy)
+    int b_tau = -1;                   // tau in the T2 layout (energy scratch)
+    std::vector<double> D1, D2;       // host copies (uploaded once)
+    std::vector<uint32_t> tau_mapsA[2], tau_mapsB[2];
+
+    int buf(const std::string& name, int64_t n, BufKind k) {
+        bufs.push_back({name, n, k});
+        return (int)bufs.size() - 1;
+    }
+    int map(const std::string& name, std::vector<uint32_t>&& m) {
+        maps.push_back(std::move(m));
+        map_names.push_back(name);
+        return (int)maps.size() - 1;
+    }
+    double total_flops() const {
+        double f = 0;
+        for (auto& o : ops) f += o.flops;
+        return f;
+    }
+};
+
+Plan build_plan_ccsd(const System& S);
+
+}  // namespace fscc

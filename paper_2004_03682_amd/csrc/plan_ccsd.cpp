@@ -1,0 +1,436 @@
+// plan_ccsd.cpp -- the (0h,0p) CCSD residual as TTGT operations.
+//
+// Equations: spin-orbital CCSD (Stanton-Gauss intermediates) for a diagonal
+// Fock matrix and complex antisymmetrised integrals, with the W_abef term
+// never materialised: its bare-integral part is the particle-particle ladder
+//   L_ij^ab = sum_{c<d} <ab||cd> tau_ij^cd               (one GEMM per pair irrep)
+// its T1 part is -P(ab) sum_m t_m^b Z_ij^am with Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef,
+// and its tau*tau part is folded into the hole-hole ladder through
+//   W'_mnij = <mn||ij> + P(ij) sum_e t_j^e <mn||ie> + 1/2 sum_ef tau_ij^ef <mn||ef>.
+// Residual R = RHS - D*t with D_i^a = e_i - e_a, D_ij^ab = e_i + e_j - e_a - e_b
+// (Eq. (3)-(4): D is the negative of the H0 eigenvalue differences).
+//
+// Integral views used below (<pq||rs> antisymmetric in (pq), (rs); Hermitian):
+//   <mb||ej> = -<mb||je>            (OVOV)
+//   <mn||ej> = -<mn||je>            (OOOV)
+//   <ab||ej> = -conj <je||ab>       (OVVV)
+//   <mb||ij> =  conj <ij||mb>       (OOOV)
+//   <ab||ij> =  conj <ij||ab>       (OOVV)   -- the T2 driver
+#include <cmath>
+#include <stdexcept>
+
+#include "plan.hpp"
+
+namespace fscc {
+namespace {
+
+bool same_group(const Group& a, const Group& b) {
+    if (a.ns != b.ns || a.packed != b.packed) return false;
+    for (int k = 0; k < a.ns; ++k)
+        if (a.s[k].sp != b.s[k].sp || a.s[k].sg != b.s[k].sg) return false;
+    return true;
+}
+
+struct Builder {
+    Plan& P;
+    int G;
+    const Space* o;
+    const Space* v;
+
+    Builder(Plan& p) : P(p), G(p.G), o(&p.O), v(&p.V) {}
+
+    Slot s(int l, const Space* sp, int sg) const { return Slot{l, sp, sg}; }
+
+    // dst (+)= alpha * sum_t sign_t * cj(src[map_t]) [* src2[map2_t]]
+    struct Term {
+        std::vector<int> perm;
+        int sign;
+        std::vector<int> perm2;   // for the second operand (bilinear); empty if none
+    };
+
+    void gather(const std::string& name, int dst, const Layout& Ld, int src, const Layout& Ls,
+                const std::vector<Term>& terms, cplx alpha, int beta, bool conj = false, int src2 = -1,
+                const Layout* Ls2 = nullptr) {
+        Op op;
+        op.kind = OP_GATHER;
+        op.name = name;
+        op.dst = dst;
+        op.src = src;
+        op.src2 = src2;
+        op.alpha = alpha;
+        op.beta = beta;
+        op.conj = conj;
+        op.n = Ld.total;
+        if (P.bufs[dst].n != Ld.total) throw std::logic_error("gather dst size mismatch: " + name);
+        if (P.bufs[src].n != Ls.total) throw std::logic_error("gather src size mismatch: " + name);
+        for (size_t t = 0; t < terms.size(); ++t) {
+            op.mapsA.push_back(P.map(name + "/A" + std::to_string(t), build_map(Ld, Ls, terms[t].perm, terms[t].sign)));
+            if (src2 >= 0)
+                op.mapsB.push_back(P.map(name + "/B" + std::to_string(t), build_map(Ld, *Ls2, terms[t].perm2, 1)));
+        }
+        P.ops.push_back(std::move(op));
+    }
+
+    void gemm(const std::string& name, int bA, const Layout& A, bool tA, bool cA, int bB, const Layout& B, bool tB,
+              bool cB, int bC, const Layout& C, cplx alpha, int beta) {
+        const Group& AM = tA ? A.C : A.R;
+        const Group& AK = tA ? A.R : A.C;
+        const Group& BK = tB ? B.C : B.R;
+        const Group& BN = tB ? B.R : B.C;
+        if (!same_group(AM, C.R)) throw std::logic_error("gemm " + name + ": A/M group != C rows");
+        if (!same_group(AK, BK)) throw std::logic_error("gemm " + name + ": K groups differ");
+        if (!same_group(BN, C.C)) throw std::logic_error("gemm " + name + ": B/N group != C cols");
+        if (P.bufs[bA].n != A.total || P.bufs[bB].n != B.total || P.bufs[bC].n != C.total)
+            throw std::logic_error("gemm " + name + ": buffer size mismatch");
+        Op op;
+        op.kind = OP_GEMM;
+        op.name = name;
+        op.src = bA;
+        op.src2 = bB;
+        op.dst = bC;
+        op.tA = tA;
+        op.tB = tB;
+        op.cA = cA;
+        op.cB = cB;
+        op.alpha = alpha;
+        op.beta = beta;
+        for (int r = 0; r < G; ++r) {
+            if (!C.kmask[r] || C.nrow[r] == 0 || C.ncol[r] == 0) continue;
+            int a = tA ? modG(A.colsign * r, G) : r;
+            int kK = tA ? a : A.col_kappa(a);
+            int b = tB ? modG(B.colsign * kK, G) : kK;
+            int nK = tB ? b : B.col_kappa(b);
+            if (nK != C.col_kappa(r)) throw std::logic_error("gemm " + name + ": kappa mismatch");
+            int64_t M = C.nrow[r], N = C.ncol[r], K = AK.size[kK];
+            if (K == 0 && beta) continue;
+            GemmProblem pr{0, 0, C.boff[r], (int)M, (int)N, (int)K, 1, 1, (int)C.ncol[r]};
+            if (K > 0) {
+                if (!A.kmask[a] || !B.kmask[b]) throw std::logic_error("gemm " + name + ": operand block not stored");
+                int64_t ar = tA ? K : M, ac = tA ? M : K, br = tB ? N : K, bc = tB ? K : N;
+                if (A.nrow[a] != ar || A.ncol[a] != ac) throw std::logic_error("gemm " + name + ": A block shape");
+                if (B.nrow[b] != br || B.ncol[b] != bc) throw std::logic_error("gemm " + name + ": B block shape");
+                pr.a_off = A.boff[a];
+                pr.lda = (int)A.ncol[a];
+                pr.b_off = B.boff[b];
+                pr.ldb = (int)B.ncol[b];
+            }
+            op.flops += 8.0 * (double)M * (double)N * (double)K;
+            op.probs.push_back(pr);
+        }
+        P.ops.push_back(std::move(op));
+    }
+
+    void axpby(const std::string& name, int dst, int src, int64_t n, cplx alpha, int beta, bool conj) {
+        Op op;
+        op.kind = OP_AXPBY;
+        op.name = name;
+        op.dst = dst;
+        op.src = src;
+        op.n = n;
+        op.alpha = alpha;
+        op.beta = beta;
+        op.conj = conj;
+        P.ops.push_back(std::move(op));
+    }
+
+    void diag(const std::string& name, int dst, int d, int src, int64_t n) {
+        Op op;
+        op.kind = OP_DIAG;
+        op.name = name;
+        op.dst = dst;
+        op.src2 = d;
+        op.src = src;
+        op.n = n;
+        P.ops.push_back(std::move(op));
+    }
+
+    // constant derived from integral class `cls` (boundary full blocks)
+    int derived(const std::string& name, int cls, const Layout& L, const std::vector<int>& perm, int sign, bool conj) {
+        int b = P.buf(name, L.total, BUF_CONST);
+        int m = P.map(name + "/pack", build_map(L, P.full[cls], perm, sign));
+        P.setup.push_back({cls, b, m, conj, name});
+        return b;
+    }
+};
+
+}  // namespace
+
+Plan build_plan_ccsd(const System& S) {
+    Plan P;
+    const int G = S.G;
+    P.G = G;
+    if (G < 1 || S.nocc < 0 || S.nvirt < 0) throw std::invalid_argument("bad system sizes");
+    {
+        std::vector<int> gi, li, ga, la;
+        for (int p = 0; p < S.nocc; ++p) {
+            gi.push_back(p);
+            li.push_back(S.irrep[p]);
+        }
+        for (int p = S.nocc; p < S.nocc + S.nvirt; ++p) {
+            ga.push_back(p);
+            la.push_back(S.irrep[p]);
+        }
+        P.O = Space::make(G, gi, li);
+        P.V = Space::make(G, ga, la);
+    }
+    Builder B(P);
+    const Space* o = &P.O;
+    const Space* v = &P.V;
+    auto s = [&](int l, const Space* sp, int sg) { return Slot{l, sp, sg}; };
+    using T = Builder::Term;
+
+    P.full[IC_OOOO] = FullBlocks::make(G, o, o, o, o);
+    P.full[IC_OOOV] = FullBlocks::make(G, o, o, o, v);
+    P.full[IC_OOVV] = FullBlocks::make(G, o, o, v, v);
+    P.full[IC_OVOV] = FullBlocks::make(G, o, v, o, v);
+    P.full[IC_OVVV] = FullBlocks::make(G, o, v, v, v);
+    P.full[IC_VVVV] = FullBlocks::make(G, v, v, v, v);
+
+    // ---------------------------------------------------------------- layouts
+    // amplitudes: T1 (i,a) = [g][o_g][v_g];  T2 (i,j,a,b) = [G][ij<][ab<]
+    P.L_T1 = make_layout("T1", G, {s(0, o, 1)}, -1, {s(1, v, 1)}, -1, 1);
+    P.L_T2 = make_layout("T2", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+    const Layout& L_T1 = P.L_T1;
+    const Layout& L_T2 = P.L_T2;
+    // rank-2 quantities seen as vectors over (p,q) pairs of pair irrep 0 (same memory as [g][n_g][m_g])
+    Layout L_T1v = make_layout("T1v", G, {s(0, o, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
+    Layout L_T1w = make_layout("T1w", G, {s(0, o, 1), s(1, v, -1)}, -1, {}, -1, 1, 0);
+
+    P.b_t1 = P.buf("t1", L_T1.total, BUF_IN_T1);
+    P.b_t2 = P.buf("t2", L_T2.total, BUF_IN_T2);
+    P.b_r1 = P.buf("r1", L_T1.total, BUF_OUT_R1);
+    P.b_r2 = P.buf("r2", L_T2.total, BUF_OUT_R2);
+
+    // denominators
+    {
+        P.D1.assign(L_T1.total, 0.0);
+        L_T1.for_each([&](int64_t k, const int* x) { P.D1[k] = S.eps[o->glob[x[0]]] - S.eps[v->glob[x[1]]]; });
+        P.D2.assign(L_T2.total, 0.0);
+        L_T2.for_each([&](int64_t k, const int* x) {
+            P.D2[k] = S.eps[o->glob[x[0]]] + S.eps[o->glob[x[1]]] - S.eps[v->glob[x[2]]] - S.eps[v->glob[x[3]]];
+        });
+        P.b_D1 = P.buf("D1", L_T1.total, BUF_REAL);
+        P.b_D2 = P.buf("D2", L_T2.total, BUF_REAL);
+    }
+
+    // ------------------------------------------------------- stored integrals
+    // OOOO <ij||kl> [ij<|kl<]
+    Layout L_OOOO = make_layout("OOOO", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, o, 1), s(3, o, 1)}, 0, 1);
+    int b_oooo = B.derived("V_oooo", IC_OOOO, L_OOOO, {0, 1, 2, 3}, 1, false);
+    // OOVV <ij||ab> [ij<|ab<]
+    Layout L_OOVV = make_layout("OOVV", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+    int b_oovv = B.derived("V_oovv", IC_OOVV, L_OOVV, {0, 1, 2, 3}, 1, false);
+    P.b_oovv = b_oovv;
+    // VVVV <ab||cd> [ab<|cd<]
+    Layout L_VVVV = make_layout("VVVV", G, {s(0, v, 1), s(1, v, 1)}, 0, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+    int b_vvvv = B.derived("V_vvvv", IC_VVVV, L_VVVV, {0, 1, 2, 3}, 1, false);
+    // OVVV <ma||ef> [(m,a)|ef<]
+    Layout L_OVVV = make_layout("OVVV", G, {s(0, o, 1), s(1, v, 1)}, -1, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+    int b_ovvv = B.derived("V_ovvv", IC_OVVV, L_OVVV, {0, 1, 2, 3}, 1, false);
+
+    // <mn||ef> as [(m,e)|(n,f)] (ph supermatrix): logical (m,n,e,f)
+    Layout L_oovv_ph = make_layout("oovv_ph", G, {s(0, o, -1), s(2, v, 1)}, -1, {s(1, o, 1), s(3, v, -1)}, -1, 1);
+    int b_oovv_ph = B.derived("V_oovv_ph", IC_OOVV, L_oovv_ph, {0, 1, 2, 3}, 1, false);
+    // <mn||ef> as [(m,n<,f)|(e)]
+    Layout L_oovv_2b = make_layout("oovv_2b", G, {s(0, o, 1), s(1, o, 1), s(3, v, -1)}, 0, {s(2, v, 1)}, -1, 1);
+    int b_oovv_2b = B.derived("V_oovv_2b", IC_OOVV, L_oovv_2b, {0, 1, 2, 3}, 1, false);
+    // <mn||ef> as [(m)|(n,ef<)]
+    Layout L_oovv_3b = make_layout("oovv_3b", G, {s(0, o, 1)}, -1, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, -1);
+    int b_oovv_3b = B.derived("V_oovv_3b", IC_OOVV, L_oovv_3b, {0, 1, 2, 3}, 1, false);
+    // <mn||ie> as [(m,i)|(n,e)], pair irrep 0 only: logical (m,n,i,e)
+    Layout L_ooov_3a = make_layout("ooov_3a", G, {s(0, o, -1), s(2, o, 1)}, -1, {s(1, o, -1), s(3, v, 1)}, -1, -1, 0);
+    int b_ooov_3a = B.derived("V_ooov_3a", IC_OOOV, L_ooov_3a, {0, 1, 2, 3}, 1, false);
+    // <mn||ie> as [(m,n<,i)|(e)]
+    Layout L_ooov_5b = make_layout("ooov_5b", G, {s(0, o, 1), s(1, o, 1), s(2, o, -1)}, 0, {s(3, v, 1)}, -1, 1);
+    int b_ooov_5b = B.derived("V_ooov_5b", IC_OOOV, L_ooov_5b, {0, 1, 2, 3}, 1, false);
+    // <mn||ej> = -<mn||je> as [(m,e,j)|(n)]: logical (m,n,e,j)
+    Layout L_oovo_9c = make_layout("oovo_9c", G, {s(0, o, -1), s(2, v, 1), s(3, o, 1)}, -1, {s(1, o, 1)}, -1, 1);
+    int b_oovo_9c = B.derived("V_oovo_9c", IC_OOOV, L_oovo_9c, {0, 1, 3, 2}, -1, false);
+    // <mb||ij> = conj <ij||mb> as [(i,j<,b)|(m)]: logical (m,b,i,j)
+    Layout L_ovoo_12 = make_layout("ovoo_12", G, {s(2, o, 1), s(3, o, 1), s(1, v, -1)}, 0, {s(0, o, 1)}, -1, 1);
+    int b_ovoo_12 = B.derived("V_ovoo_12", IC_OOOV, L_ovoo_12, {2, 3, 0, 1}, 1, true);
+    // <mn||ie> as [(i)|(m,n<,e)]: logical (m,n,i,e)
+    Layout L_ooov_14f = make_layout("ooov_14f", G, {s(2, o, 1)}, -1, {s(0, o, 1), s(1, o, 1), s(3, v, -1)}, 0, 1);
+    int b_ooov_14f = B.derived("V_ooov_14f", IC_OOOV, L_ooov_14f, {0, 1, 2, 3}, 1, false);
+    // <mb||ej> = -<mb||je> as [(m,e)|(j,b)] (the ring W layout): logical (m,b,e,j)
+    Layout L_W = make_layout("W", G, {s(0, o, -1), s(2, v, 1)}, -1, {s(3, o, -1), s(1, v, 1)}, -1, 1);
+    int b_ring0 = B.derived("V_ovvo_ring", IC_OVOV, L_W, {0, 1, 3, 2}, -1, false);
+    // <mb||ej> as [(m,b,j)|(e)]
+    Layout L_ovvo_9f = make_layout("ovvo_9f", G, {s(0, o, 1), s(1, v, 1), s(3, o, -1)}, -1, {s(2, v, 1)}, -1, 1);
+    int b_ovvo_9f = B.derived("V_ovvo_9f", IC_OVOV, L_ovvo_9f, {0, 1, 3, 2}, -1, false);
+    // <na||if> as [(i,a)|(n,f)], pair irrep 0: logical (n,a,i,f)
+    Layout L_ovov_14d = make_layout("ovov_14d", G, {s(2, o, -1), s(1, v, 1)}, -1, {s(0, o, -1), s(3, v, 1)}, -1, 1, 0);
+    int b_ovov_14d = B.derived("V_ovov_14d", IC_OVOV, L_ovov_14d, {0, 1, 2, 3}, 1, false);
+    // <ma||fe> as [(a,e)|(m,f)], pair irrep 0: logical (m,a,f,e)
+    Layout L_ovvv_2a = make_layout("ovvv_2a", G, {s(1, v, -1), s(3, v, 1)}, -1, {s(0, o, -1), s(2, v, 1)}, -1, -1, 0);
+    int b_ovvv_2a = B.derived("V_ovvv_2a", IC_OVVV, L_ovvv_2a, {0, 1, 2, 3}, 1, false);
+    // <mb||ef> as [(m,e,b)|(f)]: logical (m,b,e,f)
+    Layout L_ovvv_9b = make_layout("ovvv_9b", G, {s(0, o, 1), s(2, v, -1), s(1, v, 1)}, -1, {s(3, v, 1)}, -1, 1);
+    int b_ovvv_9b = B.derived("V_ovvv_9b", IC_OVVV, L_ovvv_9b, {0, 1, 2, 3}, 1, false);
+    // <ab||ej> = -conj <je||ab> as [(a,b<,j)|(e)]: logical (a,b,e,j)
+    Layout L_vvvo_11 = make_layout("vvvo_11", G, {s(0, v, 1), s(1, v, 1), s(3, o, -1)}, 0, {s(2, v, 1)}, -1, 1);
+    int b_vvvo_11 = B.derived("V_vvvo_11", IC_OVVV, L_vvvo_11, {3, 2, 0, 1}, -1, true);
+    // <ma||ef> as [(m,ef<)|(a)]: logical (m,a,e,f)
+    Layout L_ovvv_14e = make_layout("ovvv_14e", G, {s(0, o, 1), s(2, v, -1), s(3, v, -1)}, 1, {s(1, v, 1)}, -1, -1);
+    int b_ovvv_14e = B.derived("V_ovvv_14e", IC_OVVV, L_ovvv_14e, {0, 1, 2, 3}, 1, false);
+
+    // ------------------------------------------------------------------ tau
+    int b_tau = P.buf("tau", L_T2.total, BUF_SCRATCH);
+    int b_taut = P.buf("tau~", L_T2.total, BUF_SCRATCH);
+    P.b_tau = b_tau;
+    // tau = t2 + t_i^a t_j^b - t_i^b t_j^a   (T1 logical (i,a); T2 logical (i,j,a,b))
+    std::vector<T> tt = {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}};
+    B.axpby("tau=t2", b_tau, P.b_t2, L_T2.total, 1.0, 0, false);
+    B.gather("tau+=t1t1", b_tau, L_T2, P.b_t1, L_T1, tt, 1.0, 1, false, P.b_t1, &L_T1);
+    B.axpby("tau~=t2", b_taut, P.b_t2, L_T2.total, 1.0, 0, false);
+    B.gather("tau~+=t1t1/2", b_taut, L_T2, P.b_t1, L_T1, tt, 0.5, 1, false, P.b_t1, &L_T1);
+
+    // ------------------------------------------------------- F intermediates
+    // F_me = sum_nf <mn||ef> t_n^f
+    Layout L_Fme_v = make_layout("Fme_v", G, {s(0, o, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
+    Layout L_Fme_m = make_layout("Fme_m", G, {s(0, o, 1)}, -1, {s(1, v, 1)}, -1, 1);
+    int b_Fme = P.buf("Fme", L_T1.total, BUF_SCRATCH);
+    B.gemm("Fme", b_oovv_ph, L_oovv_ph, false, false, P.b_t1, L_T1w, false, false, b_Fme, L_Fme_v, 1.0, 0);
+    // F_ae = sum_mf t_m^f <ma||fe> - sum_{m<n,f} tau~_mn^af <mn||ef>
+    Layout L_Fae_v = make_layout("Fae_v", G, {s(0, v, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
+    Layout L_Fae_m = make_layout("Fae_m", G, {s(0, v, 1)}, -1, {s(1, v, 1)}, -1, 1);
+    int nvv0 = (int)L_Fae_m.total;
+    int b_Fae = P.buf("Fae", nvv0, BUF_SCRATCH);
+    B.gemm("Fae.1", b_ovvv_2a, L_ovvv_2a, false, false, P.b_t1, L_T1v, false, false, b_Fae, L_Fae_v, 1.0, 0);
+    Layout L_tt_2b = make_layout("tau~_2b", G, {s(2, v, 1)}, -1, {s(0, o, 1), s(1, o, 1), s(3, v, -1)}, 0, 1);
+    int b_tt2b = P.buf("tau~_2b", L_tt_2b.total, BUF_SCRATCH);
+    B.gather("tau~->2b", b_tt2b, L_tt_2b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    B.gemm("Fae.2", b_tt2b, L_tt_2b, false, false, b_oovv_2b, L_oovv_2b, false, false, b_Fae, L_Fae_m, -1.0, 1);
+    // F_mi = sum_ne t_n^e <mn||ie> + sum_{n,e<f} tau~_in^ef <mn||ef>
+    Layout L_Fmi_v = make_layout("Fmi_v", G, {s(0, o, -1), s(1, o, 1)}, -1, {}, -1, 1, 0);
+    Layout L_Fmi_m = make_layout("Fmi_m", G, {s(0, o, 1)}, -1, {s(1, o, 1)}, -1, 1);
+    int b_Fmi = P.buf("Fmi", L_Fmi_m.total, BUF_SCRATCH);
+    B.gemm("Fmi.1", b_ooov_3a, L_ooov_3a, false, false, P.b_t1, L_T1v, false, false, b_Fmi, L_Fmi_v, 1.0, 0);
+    Layout L_tt_3b = make_layout("tau~_3b", G, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, {s(0, o, 1)}, -1, -1);
+    int b_tt3b = P.buf("tau~_3b", L_tt_3b.total, BUF_SCRATCH);
+    B.gather("tau~->3b", b_tt3b, L_tt_3b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    B.gemm("Fmi.2", b_oovv_3b, L_oovv_3b, false, false, b_tt3b, L_tt_3b, false, false, b_Fmi, L_Fmi_m, 1.0, 1);
+
+    // ------------------------------------------------------------ W'_mnij
+    Layout L_Wp = make_layout("W'", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, o, 1), s(3, o, 1)}, 0, 1);
+    int b_Wp = P.buf("W'", L_Wp.total, BUF_SCRATCH);
+    B.axpby("W'=<mn||ij>", b_Wp, b_oooo, L_Wp.total, 1.0, 0, false);
+    Layout L_X5 = make_layout("X5", G, {s(0, o, 1), s(1, o, 1), s(2, o, -1)}, 0, {s(3, o, 1)}, -1, 1);
+    int b_X5 = P.buf("X5", L_X5.total, BUF_SCRATCH);
+    B.gemm("W'.t1", b_ooov_5b, L_ooov_5b, false, false, P.b_t1, L_T1, true, false, b_X5, L_X5, 1.0, 0);
+    B.gather("W'+=P(ij)X5", b_Wp, L_Wp, b_X5, L_X5, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}}, 1.0, 1);
+    B.gemm("W'.tau", b_oovv, L_OOVV, false, false, b_tau, L_T2, true, false, b_Wp, L_Wp, 1.0, 1);
+
+    // --------------------------------------------------------- T2 residual
+    B.axpby("r2=<ab||ij>", P.b_r2, b_oovv, L_T2.total, 1.0, 0, true);
+    B.gemm("hh-ladder", b_Wp, L_Wp, true, false, b_tau, L_T2, false, false, P.b_r2, L_T2, 1.0, 1);
+    B.gemm("pp-ladder", b_tau, L_T2, false, false, b_vvvv, L_VVVV, true, false, P.b_r2, L_T2, 1.0, 1);
+    // Z_ij^am = -sum_{e<f} <ma||ef> tau_ij^ef ;  r2 += -P(ab) sum_m t_m^b Z_ij^am
+    Layout L_Z1 = make_layout("Z1", G, {s(0, o, 1), s(1, v, 1)}, -1, {s(2, o, 1), s(3, o, 1)}, 0, 1);
+    int b_Z1 = P.buf("Z1", L_Z1.total, BUF_SCRATCH);
+    B.gemm("Z", b_ovvv, L_OVVV, false, false, b_tau, L_T2, true, false, b_Z1, L_Z1, -1.0, 0);
+    Layout L_Z2 = make_layout("Z2", G, {s(2, o, 1), s(3, o, 1), s(1, v, -1)}, 0, {s(0, o, 1)}, -1, 1);
+    int b_Z2 = P.buf("Z2", L_Z2.total, BUF_SCRATCH);
+    B.gather("Z1->Z2", b_Z2, L_Z2, b_Z1, L_Z1, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    Layout L_Y8 = make_layout("Y8", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+    int b_Y8 = P.buf("Y8", L_Y8.total, BUF_SCRATCH);
+    B.gemm("Z.t1", b_Z2, L_Z2, false, false, P.b_t1, L_T1, false, false, b_Y8, L_Y8, 1.0, 0);
+    B.gather("r2+=-P(ab)Y8", P.b_r2, L_T2, b_Y8, L_Y8, {T{{0, 1, 2, 3}, -1, {}}, T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
+
+    // ---------------------------------------------------------------- ring
+    int b_W = P.buf("W", L_W.total, BUF_SCRATCH);
+    B.axpby("W=<mb||ej>", b_W, b_ring0, L_W.total, 1.0, 0, false);
+    Layout L_X9b = make_layout("X9b", G, {s(0, o, 1), s(1, v, -1), s(2, v, 1)}, -1, {s(3, o, 1)}, -1, 1);
+    int b_X9b = P.buf("X9b", L_X9b.total, BUF_SCRATCH);
+    B.gemm("W.t1.ovvv", b_ovvv_9b, L_ovvv_9b, false, false, P.b_t1, L_T1, true, false, b_X9b, L_X9b, 1.0, 0);
+    B.gather("W+=X9b", b_W, L_W, b_X9b, L_X9b, {T{{0, 2, 1, 3}, 1, {}}}, 1.0, 1);
+    Layout L_X9c = make_layout("X9c", G, {s(0, o, -1), s(1, v, 1), s(2, o, 1)}, -1, {s(3, v, 1)}, -1, 1);
+    int b_X9c = P.buf("X9c", L_X9c.total, BUF_SCRATCH);
+    B.gemm("W.t1.ooov", b_oovo_9c, L_oovo_9c, false, false, P.b_t1, L_T1, false, false, b_X9c, L_X9c, -1.0, 0);
+    B.gather("W+=X9c", b_W, L_W, b_X9c, L_X9c, {T{{0, 2, 3, 1}, 1, {}}}, 1.0, 1);
+    // U_(n,f),(j,b) = 1/2 t_jn^fb + t_j^f t_n^b  : logical (n,f,j,b)
+    Layout L_U = make_layout("U", G, {s(0, o, 1), s(1, v, -1)}, -1, {s(2, o, -1), s(3, v, 1)}, -1, 1);
+    int b_U = P.buf("U", L_U.total, BUF_SCRATCH);
+    B.gather("U=t2/2", b_U, L_U, P.b_t2, L_T2, {T{{2, 0, 1, 3}, 1, {}}}, 0.5, 0);
+    B.gather("U+=t1t1", b_U, L_U, P.b_t1, L_T1, {T{{2, 1}, 1, {0, 3}}}, 1.0, 1, false, P.b_t1, &L_T1);
+    B.gemm("W.U", b_oovv_ph, L_oovv_ph, false, false, b_U, L_U, false, false, b_W, L_W, -1.0, 1);
+    // ring: X_(i,a),(j,b) = sum_(m,e) t_im^ae W_mbej
+    Layout L_Tr = make_layout("Tring", G, {s(0, o, -1), s(2, v, 1)}, -1, {s(1, o, -1), s(3, v, 1)}, -1, -1);
+    int b_Tr = P.buf("Tring", L_Tr.total, BUF_SCRATCH);
+    B.gather("t2->ring", b_Tr, L_Tr, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    Layout L_X = make_layout("Xring", G, {s(0, o, -1), s(1, v, 1)}, -1, {s(2, o, -1), s(3, v, 1)}, -1, -1);
+    int b_X = P.buf("Xring", L_X.total, BUF_SCRATCH);
+    B.gemm("ring", b_Tr, L_Tr, false, false, b_W, L_W, false, false, b_X, L_X, 1.0, 0);
+    // Y9_ijab = sum_me t_i^e t_m^a <mb||ej>
+    Layout L_Q = make_layout("Q", G, {s(0, o, 1), s(1, v, 1), s(2, o, -1)}, -1, {s(3, o, 1)}, -1, 1);
+    int b_Q = P.buf("Q", L_Q.total, BUF_SCRATCH);
+    B.gemm("Q", b_ovvo_9f, L_ovvo_9f, false, false, P.b_t1, L_T1, true, false, b_Q, L_Q, 1.0, 0);
+    Layout L_Q2 = make_layout("Q2", G, {s(3, o, 1), s(2, o, 1), s(1, v, -1)}, -1, {s(0, o, 1)}, -1, 1);
+    int b_Q2 = P.buf("Q2", L_Q2.total, BUF_SCRATCH);
+    B.gather("Q->Q2", b_Q2, L_Q2, b_Q, L_Q, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    Layout L_Y9 = make_layout("Y9", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, -1, {s(3, v, 1)}, -1, 1);
+    int b_Y9 = P.buf("Y9", L_Y9.total, BUF_SCRATCH);
+    B.gemm("Y9", b_Q2, L_Q2, false, false, P.b_t1, L_T1, false, false, b_Y9, L_Y9, 1.0, 0);
+    B.gather("r2+=PP X", P.b_r2, L_T2, b_X, L_X,
+             {T{{0, 2, 1, 3}, 1, {}}, T{{1, 2, 0, 3}, -1, {}}, T{{0, 3, 1, 2}, -1, {}}, T{{1, 3, 0, 2}, 1, {}}}, 1.0, 1);
+    B.gather("r2+=-PP Y9", P.b_r2, L_T2, b_Y9, L_Y9,
+             {T{{0, 1, 3, 2}, -1, {}}, T{{1, 0, 3, 2}, 1, {}}, T{{0, 1, 2, 3}, 1, {}}, T{{1, 0, 2, 3}, -1, {}}}, 1.0, 1);
+
+    // ------------------------------------------------------------ F terms
+    // F'_be = F_be - 1/2 sum_m t_m^b F_me
+    Layout L_Fbe = make_layout("Fbe", G, {s(0, v, 1)}, -1, {s(1, v, 1)}, -1, 1);
+    int b_Fbe = P.buf("Fbe", L_Fbe.total, BUF_SCRATCH);
+    B.axpby("Fbe=Fae", b_Fbe, b_Fae, L_Fbe.total, 1.0, 0, false);
+    B.gemm("Fbe.t1", P.b_t1, L_T1, true, false, b_Fme, L_Fme_m, false, false, b_Fbe, L_Fbe, -0.5, 1);
+    Layout L_T10a = make_layout("T10a", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+    int b_T10a = P.buf("T10a", L_T10a.total, BUF_SCRATCH);
+    B.gather("t2->10a", b_T10a, L_T10a, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    Layout L_Y10a = make_layout("Y10a", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+    int b_Y10a = P.buf("Y10a", L_Y10a.total, BUF_SCRATCH);
+    B.gemm("t2.Fbe", b_T10a, L_T10a, false, false, b_Fbe, L_Fbe, true, false, b_Y10a, L_Y10a, 1.0, 0);
+    B.gather("r2+=P(ab)Y10a", P.b_r2, L_T2, b_Y10a, L_Y10a, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}}, 1.0, 1);
+    // F'_mj = F_mj + 1/2 sum_e t_j^e F_me
+    Layout L_Fmj = make_layout("Fmj", G, {s(0, o, 1)}, -1, {s(1, o, 1)}, -1, 1);
+    int b_Fmj = P.buf("Fmj", L_Fmj.total, BUF_SCRATCH);
+    B.axpby("Fmj=Fmi", b_Fmj, b_Fmi, L_Fmj.total, 1.0, 0, false);
+    B.gemm("Fmj.t1", b_Fme, L_Fme_m, false, false, P.b_t1, L_T1, true, false, b_Fmj, L_Fmj, 0.5, 1);
+    Layout L_T10b = make_layout("T10b", G, {s(2, v, 1), s(3, v, 1), s(0, o, -1)}, 0, {s(1, o, 1)}, -1, 1);
+    int b_T10b = P.buf("T10b", L_T10b.total, BUF_SCRATCH);
+    B.gather("t2->10b", b_T10b, L_T10b, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    Layout L_Y10b = make_layout("Y10b", G, {s(0, v, 1), s(1, v, 1), s(2, o, -1)}, 0, {s(3, o, 1)}, -1, 1);
+    int b_Y10b = P.buf("Y10b", L_Y10b.total, BUF_SCRATCH);
+    B.gemm("t2.Fmj", b_T10b, L_T10b, false, false, b_Fmj, L_Fmj, false, false, b_Y10b, L_Y10b, 1.0, 0);
+    B.gather("r2+=-P(ij)Y10b", P.b_r2, L_T2, b_Y10b, L_Y10b, {T{{2, 3, 0, 1}, -1, {}}, T{{2, 3, 1, 0}, 1, {}}}, 1.0, 1);
+    // P(ij) sum_e t_i^e <ab||ej>
+    Layout L_Y11 = make_layout("Y11", G, {s(0, v, 1), s(1, v, 1), s(2, o, -1)}, 0, {s(3, o, 1)}, -1, 1);
+    int b_Y11 = P.buf("Y11", L_Y11.total, BUF_SCRATCH);
+    B.gemm("t1.vvvo", b_vvvo_11, L_vvvo_11, false, false, P.b_t1, L_T1, true, false, b_Y11, L_Y11, 1.0, 0);
+    B.gather("r2+=P(ij)Y11", P.b_r2, L_T2, b_Y11, L_Y11, {T{{2, 3, 1, 0}, 1, {}}, T{{2, 3, 0, 1}, -1, {}}}, 1.0, 1);
+    // -P(ab) sum_m t_m^a <mb||ij>
+    Layout L_Y12 = make_layout("Y12", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+    int b_Y12 = P.buf("Y12", L_Y12.total, BUF_SCRATCH);
+    B.gemm("t1.ovoo", b_ovoo_12, L_ovoo_12, false, false, P.b_t1, L_T1, false, false, b_Y12, L_Y12, 1.0, 0);
+    B.gather("r2+=-P(ab)Y12", P.b_r2, L_T2, b_Y12, L_Y12, {T{{0, 1, 3, 2}, -1, {}}, T{{0, 1, 2, 3}, 1, {}}}, 1.0, 1);
+    B.diag("r2-=D2*t2", P.b_r2, P.b_D2, P.b_t2, L_T2.total);
+
+    // --------------------------------------------------------- T1 residual
+    Layout L_R1v = make_layout("R1v", G, {s(0, o, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
+    B.gemm("t1.Fae", P.b_t1, L_T1, false, false, b_Fae, L_Fae_m, true, false, P.b_r1, L_T1, 1.0, 0);
+    B.gemm("Fmi.t1", b_Fmi, L_Fmi_m, true, false, P.b_t1, L_T1, false, false, P.b_r1, L_T1, -1.0, 1);
+    B.gemm("t2.Fme", b_Tr, L_Tr, false, false, b_Fme, L_Fme_v, false, false, P.b_r1, L_R1v, 1.0, 1);
+    B.gemm("t1.ovov", b_ovov_14d, L_ovov_14d, false, false, P.b_t1, L_T1v, false, false, P.b_r1, L_R1v, -1.0, 1);
+    Layout L_T14e = make_layout("T14e", G, {s(0, o, 1)}, -1, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, -1);
+    int b_T14e = P.buf("T14e", L_T14e.total, BUF_SCRATCH);
+    B.gather("t2->14e", b_T14e, L_T14e, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    B.gemm("t2.ovvv", b_T14e, L_T14e, false, false, b_ovvv_14e, L_ovvv_14e, false, false, P.b_r1, L_T1, -1.0, 1);
+    Layout L_T14f = make_layout("T14f", G, {s(0, o, 1), s(1, o, 1), s(3, v, -1)}, 0, {s(2, v, 1)}, -1, 1);
+    int b_T14f = P.buf("T14f", L_T14f.total, BUF_SCRATCH);
+    B.gather("t2->14f", b_T14f, L_T14f, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+    B.gemm("ooov.t2", b_ooov_14f, L_ooov_14f, false, false, b_T14f, L_T14f, false, false, P.b_r1, L_T1, -1.0, 1);
+    B.diag("r1-=D1*t1", P.b_r1, P.b_D1, P.b_t1, L_T1.total);
+
+    (void)b_oovo_9c;
+    return P;
+}
+
+}  // namespace fscc

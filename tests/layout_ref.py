@@ -1,0 +1,95 @@
+"""Independent numpy implementation of the documented packed amplitude layouts.
+
+Used only by tests to move between the oracle's dense tensors and the
+library's packed buffers (include/fscc.h documents the layouts):
+
+  T1: [g][o_g][v_g]                 -- t_i^a with irrep(i) = irrep(a) = g
+  T2: [G][ij<][ab<]                 -- G = irrep(i)+irrep(j) = irrep(a)+irrep(b) (mod n)
+      pairs (p,q) of one space with p<q in the irrep-sorted order, grouped by
+      (g_p, g_q) with g_p <= g_q, g_p ascending; inside a group p-major.
+Spinors inside an irrep are in ascending global index.
+"""
+import numpy as np
+
+
+def members(sysm, X, g):
+    """Positions within space X (0-based in that space) of irrep g, ascending."""
+    base = 0 if X == "O" else sysm.nocc
+    return sysm.members(X, g) - base
+
+
+def pair_list(sysm, X, G):
+    """Pairs (p<q) of space X with g_p + g_q = G, in layout order."""
+    n = sysm.nirrep
+    P, Q = [], []
+    for gp in range(n):
+        gq = (G - gp) % n
+        if gp > gq:
+            continue
+        mp, mq = members(sysm, X, gp), members(sysm, X, gq)
+        if gp < gq:
+            for p in mp:
+                for q in mq:
+                    P.append(p)
+                    Q.append(q)
+        else:
+            for a in range(len(mp)):
+                for b in range(a + 1, len(mp)):
+                    P.append(mp[a])
+                    Q.append(mp[b])
+    return np.array(P, dtype=np.int64), np.array(Q, dtype=np.int64)
+
+
+def pack_t1(sysm, t1):
+    out = []
+    for g in range(sysm.nirrep):
+        mo, mv = members(sysm, "O", g), members(sysm, "V", g)
+        out.append(t1[np.ix_(mo, mv)].ravel())
+    return np.concatenate(out) if out else np.zeros(0, np.complex128)
+
+
+def unpack_t1(sysm, buf):
+    t1 = np.zeros((sysm.nocc, sysm.nvirt), np.complex128)
+    off = 0
+    for g in range(sysm.nirrep):
+        mo, mv = members(sysm, "O", g), members(sysm, "V", g)
+        sz = len(mo) * len(mv)
+        t1[np.ix_(mo, mv)] = buf[off:off + sz].reshape(len(mo), len(mv))
+        off += sz
+    assert off == buf.size
+    return t1
+
+
+def pack_t2(sysm, t2):
+    out = []
+    for G in range(sysm.nirrep):
+        I, J = pair_list(sysm, "O", G)
+        A, B = pair_list(sysm, "V", G)
+        out.append(t2[I[:, None], J[:, None], A[None, :], B[None, :]].ravel())
+    return np.concatenate(out)
+
+
+def unpack_t2(sysm, buf):
+    no, nv = sysm.nocc, sysm.nvirt
+    t2 = np.zeros((no, no, nv, nv), np.complex128)
+    off = 0
+    for G in range(sysm.nirrep):
+        I, J = pair_list(sysm, "O", G)
+        A, B = pair_list(sysm, "V", G)
+        sz = len(I) * len(A)
+        x = buf[off:off + sz].reshape(len(I), len(A))
+        off += sz
+        t2[I[:, None], J[:, None], A[None, :], B[None, :]] = x
+        t2[J[:, None], I[:, None], A[None, :], B[None, :]] = -x
+        t2[I[:, None], J[:, None], B[None, :], A[None, :]] = -x
+        t2[J[:, None], I[:, None], B[None, :], A[None, :]] = x
+    assert off == buf.size
+    return t2
+
+
+def t2_size(sysm):
+    return sum(len(pair_list(sysm, "O", G)[0]) * len(pair_list(sysm, "V", G)[0]) for G in range(sysm.nirrep))
+
+
+def t1_size(sysm):
+    return int(sum(len(members(sysm, "O", g)) * len(members(sysm, "V", g)) for g in range(sysm.nirrep)))

@@ -1,0 +1,201 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: per call max|R_gpu - R_oracle| <= 1e-12 * max|R| (FP64 with a
+different summation order); converged correlation energy within 1e-10 Eh
+(real and imaginary parts) and amplitudes within 1e-9 max-abs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import fsgen
+import layout_ref as LR
+from oracle import ccsd, solver
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def gpu_ctx(s):
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    ctx = F.Context.from_system(s)
+    for C in fsgen.CLASSES:
+        buf, _ = fsgen.class_buffer(s, C)
+        d = torch.from_numpy(buf).to("cuda")
+        ctx.set_integrals(C, d)
+        del d
+    return ctx
+
+
+def dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def allowed_random_t(s, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    no, nv, ni = s.nocc, s.nvirt, s.nirrep
+    t1 = scale * (rng.normal(size=(no, nv)) + 1j * rng.normal(size=(no, nv)))
+    t2 = scale * (rng.normal(size=(no, no, nv, nv)) + 1j * rng.normal(size=(no, no, nv, nv)))
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    g = s.irrep
+    go, gv = g[:no], g[no:]
+    t1[(go[:, None] - gv[None, :]) % ni != 0] = 0
+    t2[(go[:, None, None, None] + go[None, :, None, None] - gv[None, None, :, None] - gv[None, None, None, :]) % ni != 0] = 0
+    return t1, t2
+
+
+SYSTEMS = [
+    ("cfg0", None),
+    ("z4-empty-irreps", (6, 14, 4, 0.1, 21)),
+    ("z6-empty-irreps", (5, 12, 6, 0.1, 4)),
+    ("one-occupied", (1, 5, 1, 0.1, 3)),
+    ("two-occupied-z3", (2, 7, 3, 0.1, 5)),
+    ("ragged-z5", (9, 37, 5, 0.05, 17)),
+]
+
+
+def _system(spec):
+    name, p = spec
+    if name == "cfg0":
+        return fsgen.config_system(0)
+    return fsgen.make_system(p[0], p[1], p[2], p[3], p[4])
+
+
+@pytest.mark.parametrize("spec", SYSTEMS, ids=[s[0] for s in SYSTEMS])
+def test_residual_matches_oracle(spec):
+    torch = _torch()
+    s = _system(spec)
+    print("case", spec, flush=True)
+    ctx = gpu_ctx(s)
+    t1, t2 = allowed_random_t(s, 7)
+    p1, p2 = LR.pack_t1(s, t1), LR.pack_t2(s, t2)
+    assert (ctx.n1, ctx.n2) == (p1.size, p2.size)
+    d1, d2 = dev(p1), dev(p2)
+    r1, r2 = torch.empty_like(d1), torch.empty_like(d2)
+    ctx.build_residual(d1, d2, r1, r2)
+    torch.cuda.synchronize()
+    R1, R2 = ccsd.residual(ccsd.Dense(s), t1, t2)
+    scale = max(np.abs(R2).max() if R2.size else 0.0, np.abs(R1).max(), 1e-300)
+    assert np.abs(LR.unpack_t1(s, host(r1)) - R1).max() <= 1e-12 * scale
+    if p2.size:
+        assert np.abs(LR.unpack_t2(s, host(r2)) - R2).max() <= 1e-12 * scale
+    ctx.destroy()
+
+
+def test_residual_matches_blocked_oracle_cfg1():
+    torch = _torch()
+    s = fsgen.config_system(1)
+    ctx = gpu_ctx(s)
+    t1, t2 = allowed_random_t(s, 11, 0.02)
+    d1, d2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
+    r1, r2 = torch.empty_like(d1), torch.empty_like(d2)
+    ctx.build_residual(d1, d2, r1, r2)
+    be = ccsd.Blocked(s)
+    from oracle.blocks import BlockTensor
+    bt1 = BlockTensor.from_dense(t1, [be.mem["O"], be.mem["V"]], list(be.D1.blocks.keys()))
+    bt2 = BlockTensor.from_dense(t2, [be.mem[X] for X in "OOVV"], list(be.D2.blocks.keys()))
+    R1, R2 = ccsd.residual(be, bt1, bt2)
+    R1, R2 = be.dense(R1), be.dense(R2)
+    scale = np.abs(R2).max()
+    assert np.abs(LR.unpack_t1(s, host(r1)) - R1).max() <= 1e-12 * scale
+    assert np.abs(LR.unpack_t2(s, host(r2)) - R2).max() <= 1e-12 * scale
+    ctx.destroy()
+
+
+def test_first_update_gives_mp2_energy():
+    torch = _torch()
+    s = fsgen.make_system(7, 30, 4, 0.05, 8)
+    ctx = gpu_ctx(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+    ctx.diis_reset(6)
+    ctx.build_residual(t1, t2, r1, r2)
+    ctx.update_amplitudes(t1, t2, r1, r2)
+    E = ctx.energy(t1, t2)
+    E2 = ccsd.mp2_energy_closed_form(ccsd.Dense(s))
+    assert abs(E - E2) <= 1e-13 * abs(E2)
+    assert float(torch.abs(t1).max()) == 0.0
+    ctx.destroy()
+
+
+def test_ladder_mp3_closed_form():
+    torch = _torch()
+    s = fsgen.make_system(6, 22, 3, 0.05, 12)
+    be = ccsd.Dense(s)
+    ctx = gpu_ctx(s)
+    y = be.V("oovv").conj() / be.D2
+    tau = dev(LR.pack_t2(s, y))
+    out = torch.empty_like(tau)
+    ctx.ladder(tau, out)
+    L = LR.unpack_t2(s, host(out))
+    e = 0.25 * np.sum(be.V("oovv") * L / be.D2)
+    ref = ccsd.mp3_ladder_closed_form(be)
+    assert abs(e - ref) <= 1e-12 * abs(ref)
+    Lo = ccsd.pp_ladder(be, y)
+    assert np.abs(L - Lo).max() <= 1e-12 * np.abs(Lo).max()
+    ctx.destroy()
+
+
+def test_converged_cfg0_matches_oracle():
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    s = fsgen.config_system(0)
+    ctx = gpu_ctx(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    g = F.solve(ctx, t1, t2, tol=1e-10)
+    o = solver.solve_ccsd(ccsd.Dense(s), tol=1e-10)
+    assert g["converged"] and o["converged"]
+    assert abs(g["E"].real - o["E"].real) <= 1e-10 and abs(g["E"].imag - o["E"].imag) <= 1e-10
+    assert np.abs(LR.unpack_t2(s, host(t2)) - o["t2"]).max() <= 1e-9
+    assert np.abs(LR.unpack_t1(s, host(t1)) - o["t1"]).max() <= 1e-9
+    ctx.destroy()
+
+
+def test_converged_cfg1_matches_golden():
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    gold = json.load(open(os.path.join(HERE, "golden", "cfg1_ccsd.json")))
+    s = fsgen.config_system(1)
+    ctx = gpu_ctx(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    g = F.solve(ctx, t1, t2, tol=1e-10)
+    print("cfg1 gpu", g["E"], g["iters"], "oracle", gold["E_re"], gold["E_im"], gold["iters"], flush=True)
+    assert g["converged"]
+    assert abs(g["E"].real - gold["E_re"]) <= 1e-10
+    assert abs(g["E"].imag - gold["E_im"]) <= 1e-10
+    ctx.destroy()
+
+
+def test_errors_are_reported():
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(3, 6, 2, 0.05, 1)
+    ctx = F.Context.from_system(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    with pytest.raises(F.FsccError) as e:
+        ctx.build_residual(t1, t2, torch.empty_like(t1), torch.empty_like(t2))
+    assert e.value.status == -5
+    with pytest.raises(F.FsccError) as e:
+        ctx.set_integrals("OOVV", torch.zeros(3, dtype=torch.complex128, device="cuda"))
+    assert e.value.status == -1
+    ctx.destroy()

@@ -219,3 +219,18 @@ def test_fixed_point_independent_of_diis():
     assert a["converged"] and b["converged"]
     assert abs(a["E"] - b["E"]) < 1e-11
     assert np.abs(a["t2"] - b["t2"]).max() < 1e-10
+
+
+# --------------------------------------------------------------------------- P11
+
+@pytest.mark.parametrize("no,nv,ni,seed", [(4, 10, 1, 5), (6, 14, 3, 2)])
+def test_ladder_mp3_closed_form(no, nv, ni, seed):
+    # the ladder applied to first-order amplitudes gives the textbook MP3 pp-ladder energy, which is real
+    s = fsgen.make_system(no, nv, ni, 0.1, seed)
+    be = ccsd.Dense(s)
+    y = be.V("oovv").conj() / be.D2
+    L = ccsd.pp_ladder(be, y)
+    e = 0.25 * np.sum(be.V("oovv") * L / be.D2)
+    ref = ccsd.mp3_ladder_closed_form(be)
+    assert abs(e - ref) < 1e-13 * abs(ref)
+    assert abs(ref.imag) < 1e-13 * abs(ref)
