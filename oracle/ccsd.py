@@ -131,14 +131,26 @@ class Dense:
         return x
 
 
+def _views(sysm, C, buf):
+    """Block views of an already generated class buffer (boundary layout)."""
+    views, off = {}, 0
+    for key, shp in fsgen.class_tuples(sysm, C):
+        sz = int(np.prod(shp))
+        views[key] = buf[off:off + sz].reshape(shp)
+        off += sz
+    assert off == buf.size
+    return buf, views
+
+
 class Blocked:
     """Block lists keyed by irreps (Fig. 3 partition, Fig. 4 contraction)."""
 
-    def __init__(self, sysm: fsgen.System):
+    def __init__(self, sysm: fsgen.System, buffers: dict | None = None):
         self.sys = sysm
         self.cls = {}
         for C in CLASSES:
-            _, views = fsgen.class_buffer(sysm, C)
+            out = None if buffers is None else buffers[C]
+            _, views = fsgen.class_buffer(sysm, C, out=out) if out is None else _views(sysm, C, out)
             self.cls[C] = BlockTensor(4, {k: v for k, v in views.items() if v.size})
         n = sysm.nirrep
         no = sysm.nocc
@@ -171,6 +183,9 @@ class Blocked:
         if pattern not in self._cache:
             C, axes, s, c = integral_image(pattern)
             x = self.cls[C]
+            if axes == (0, 1, 2, 3) and s == 1 and not c:
+                self._cache[pattern] = x        # the stored class itself (no copy)
+                return x
             x = x.conj() if c else x
             x = x.transpose(axes)
             self._cache[pattern] = BlockTensor(4, {k: np.ascontiguousarray(s * v) for k, v in x.blocks.items()})
@@ -218,34 +233,39 @@ def _P(x, a, b):
     return x - x.transpose(ax)
 
 
-def intermediates(be, t1, t2):
+def intermediates(be, t1, t2, progress=None):
     ein, V = be.ein, be.V
+    say = progress or (lambda msg: None)
     t1t1 = ein("ia,jb->ijab", t1, t1)
     tau_t = t2 + 0.5 * (t1t1 - t1t1.transpose(0, 1, 3, 2))
     tau = t2 + (t1t1 - t1t1.transpose(0, 1, 3, 2))
     Fae = ein("mf,mafe->ae", t1, V("ovvv")) - 0.5 * ein("mnaf,mnef->ae", tau_t, V("oovv"))
     Fmi = ein("ne,mnie->mi", t1, V("ooov")) + 0.5 * ein("inef,mnef->mi", tau_t, V("oovv"))
     Fme = ein("nf,mnef->me", t1, V("oovv"))
+    say("F intermediates")
     Wmnij = (V("oooo") + _P(ein("je,mnie->mnij", t1, V("ooov")), 2, 3)
              + 0.25 * ein("ijef,mnef->mnij", tau, V("oovv")))
     Wabef = (V("vvvv") - _P(ein("mb,amef->abef", t1, V("vovv")), 0, 1)
              + 0.25 * ein("mnab,mnef->abef", tau, V("oovv")))
+    say("W_abef")
     u = 0.5 * t2 + ein("jf,nb->jnfb", t1, t1)
     Wmbej = (V("ovvo") + ein("jf,mbef->mbej", t1, V("ovvv")) - ein("nb,mnej->mbej", t1, V("oovo"))
              - ein("jnfb,mnef->mbej", u, V("oovv")))
     return dict(tau=tau, tau_t=tau_t, Fae=Fae, Fmi=Fmi, Fme=Fme, Wmnij=Wmnij, Wabef=Wabef, Wmbej=Wmbej)
 
 
-def residual(be, t1, t2):
+def residual(be, t1, t2, progress=None):
     """(R1, R2) = RHS - D*t for the spin-orbital CCSD equations."""
     ein, V = be.ein, be.V
-    I = intermediates(be, t1, t2)
+    say = progress or (lambda msg: None)
+    I = intermediates(be, t1, t2, progress)
     tau, Fae, Fmi, Fme, Wmnij, Wabef, Wmbej = (I[k] for k in ("tau", "Fae", "Fmi", "Fme", "Wmnij", "Wabef", "Wmbej"))
     # T1 equation
     R1 = (ein("ie,ae->ia", t1, Fae) - ein("ma,mi->ia", t1, Fmi) + ein("imae,me->ia", t2, Fme)
           - ein("nf,naif->ia", t1, V("ovov")) - 0.5 * ein("imef,maef->ia", t2, V("ovvv"))
           - 0.5 * ein("mnae,nmei->ia", t2, V("oovo")))
     R1 = R1 - be.D1 * t1
+    say("T1 residual")
     # T2 equation
     Fbe = Fae - 0.5 * ein("mb,me->be", t1, Fme)
     Fmj = Fmi + 0.5 * ein("je,me->mj", t1, Fme)
@@ -261,6 +281,7 @@ def residual(be, t1, t2):
           + _P(ein("ie,abej->ijab", t1, V("vvvo")), 0, 1)
           - _P(ein("ma,mbij->ijab", t1, V("ovoo")), 2, 3))
     R2 = R2 - be.D2 * t2
+    say("T2 residual")
     return R1, R2
 
 

@@ -24,6 +24,12 @@ struct GemmDev {
     ZTile* tiles = nullptr;
     int ntiles = 0;
     int cfg = 0;
+    // split-K: the tiles write partial products into `work`, a second pass reduces
+    bool split = false;
+    ZRed* reds = nullptr;
+    int nred = 0;
+    int maxMN = 0;
+    double2* work = nullptr;
 };
 
 struct HipError : std::runtime_error {
@@ -88,6 +94,8 @@ struct fscc_ctx {
         for (auto& g : gdev) {
             if (g.probs) (void)hipFree(g.probs);
             if (g.tiles) (void)hipFree(g.tiles);
+            if (g.reds) (void)hipFree(g.reds);
+            if (g.work) (void)hipFree(g.work);
         }
         void* ps[] = {hist_t, hist_e, dB, part, part_max, coef, scal, dorder, epart, eout};
         for (void* p : ps)
@@ -121,9 +129,18 @@ struct fscc_ctx {
             case OP_GEMM: {
                 const GemmDev& g = gdev[k];
                 int beta = beta_override >= 0 ? beta_override : o.beta;
-                e = launch_zgemm(g.cfg, o.tA, o.tB, A_override ? A_override : B(o.src), B(o.src2),
-                                 C_override ? C_override : B(o.dst), g.probs, g.tiles, g.ntiles, o.alpha.real(),
-                                 o.alpha.imag(), beta, o.cA, o.cB, st);
+                const double2* Ap = A_override ? A_override : B(o.src);
+                double2* Cp = C_override ? C_override : B(o.dst);
+                if (!g.split) {
+                    e = launch_zgemm(g.cfg, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
+                                     o.alpha.imag(), beta, o.cA, o.cB, st);
+                } else {
+                    e = launch_zgemm(g.cfg, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
+                                     o.cA, o.cB, st);
+                    if (e == hipSuccess)
+                        e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
+                                                 beta, st);
+                }
                 break;
             }
         }
@@ -155,15 +172,91 @@ fscc_status guarded(fscc_ctx* c, F f) {
     }
 }
 
-void pick_gemm(const Op& o, GemmDev& g) {
-    int maxM = 0, maxN = 0;
-    for (auto& p : o.probs) {
-        maxM = std::max(maxM, p.M);
-        maxN = std::max(maxN, p.N);
+// Tile shape with the least padded MFMA work (ties: the larger tile).
+int pick_cfg(const Op& o) {
+    int best = ZCFG_64x64;
+    double best_work = -1.0, best_area = 0.0;
+    for (int c = 0; c < ZCFG_N; ++c) {
+        int bm, bn;
+        zcfg_tile(c, &bm, &bn);
+        double w = 0.0;
+        for (auto& p : o.probs)
+            w += (double)((p.M + bm - 1) / bm * bm) * (double)((p.N + bn - 1) / bn * bn) * (double)std::max(p.K, 1);
+        double area = (double)bm * bn;
+        if (best_work < 0 || w < best_work * 0.999 || (w <= best_work * 1.001 && area > best_area)) {
+            best = c;
+            best_work = w;
+            best_area = area;
+        }
     }
-    if (maxN <= 16 && maxM > 64) g.cfg = ZCFG_128x16;
-    else if (maxM <= 16 && maxN > 64) g.cfg = ZCFG_16x128;
-    else g.cfg = ZCFG_64x64;
+    return best;
+}
+
+// Problem / tile lists for one GEMM op.  Contractions whose output tiles are
+// too few to fill the GPU are split along K into chunks of >= 256 (partial
+// products to a workspace, then a deterministic reduction).
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g) {
+    g.cfg = pick_cfg(o);
+    int bm, bn;
+    zcfg_tile(g.cfg, &bm, &bn);
+    long long tiles0 = 0;
+    int maxK = 0;
+    for (auto& p : o.probs) {
+        tiles0 += (long long)((p.M + bm - 1) / bm) * ((p.N + bn - 1) / bn);
+        maxK = std::max(maxK, p.K);
+    }
+    const long long target = 2048;
+    int S = tiles0 > 0 ? (int)std::min<long long>(512, (target + tiles0 - 1) / tiles0) : 1;
+    std::vector<int> Sq(o.probs.size(), 1);
+    bool split = false;
+    if (S > 1 && maxK >= 512)
+        for (size_t q = 0; q < o.probs.size(); ++q) {
+            Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
+            split |= Sq[q] > 1;
+        }
+    std::vector<ZProb> pr;
+    std::vector<ZTile> tl;
+    std::vector<ZRed> rd;
+    long long woff = 0;
+    int maxMN = 0;
+    for (size_t q = 0; q < o.probs.size(); ++q) {
+        const GemmProblem& p = o.probs[q];
+        if (!split) {
+            pr.push_back(ZProb{p.a_off, p.b_off, p.c_off, p.M, p.N, p.K, p.lda, p.ldb, p.ldc});
+        } else {
+            int chunk = (p.K + Sq[q] - 1) / std::max(Sq[q], 1);
+            int ns = 0;
+            for (int k0 = 0; k0 < std::max(p.K, 1); k0 += std::max(chunk, 1)) {
+                int len = std::max(0, std::min(chunk, p.K - k0));
+                long long ao = p.a_off + (o.tA ? (long long)k0 * p.lda : k0);
+                long long bo = p.b_off + (o.tB ? k0 : (long long)k0 * p.ldb);
+                pr.push_back(ZProb{ao, bo, woff + (long long)ns * p.M * p.N, p.M, p.N, len, p.lda, p.ldb, p.N});
+                ++ns;
+                if (p.K == 0) break;
+            }
+            rd.push_back(ZRed{p.c_off, woff, p.M, p.N, p.ldc, ns});
+            woff += (long long)ns * p.M * p.N;
+            maxMN = std::max(maxMN, p.M * p.N);
+        }
+    }
+    for (size_t q = 0; q < pr.size(); ++q)
+        for (int m0 = 0; m0 < pr[q].M; m0 += bm)
+            for (int n0 = 0; n0 < pr[q].N; n0 += bn) tl.push_back(ZTile{(int)q, m0, n0, 0});
+    // longest-K tiles first (uneven symmetry blocks)
+    std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) { return pr[a.prob].K > pr[b.prob].K; });
+    g.ntiles = (int)tl.size();
+    g.probs = (ZProb*)c->dalloc(std::max<size_t>(1, pr.size()) * sizeof(ZProb));
+    g.tiles = (ZTile*)c->dalloc(std::max<size_t>(1, tl.size()) * sizeof(ZTile));
+    if (!pr.empty()) hip_check(hipMemcpy(g.probs, pr.data(), pr.size() * sizeof(ZProb), hipMemcpyHostToDevice), "probs");
+    if (!tl.empty()) hip_check(hipMemcpy(g.tiles, tl.data(), tl.size() * sizeof(ZTile), hipMemcpyHostToDevice), "tiles");
+    g.split = split;
+    if (split) {
+        g.nred = (int)rd.size();
+        g.maxMN = maxMN;
+        g.reds = (ZRed*)c->dalloc(rd.size() * sizeof(ZRed));
+        hip_check(hipMemcpy(g.reds, rd.data(), rd.size() * sizeof(ZRed), hipMemcpyHostToDevice), "reds");
+        g.work = (double2*)c->dalloc((size_t)std::max<long long>(1, woff) * sizeof(double2));
+    }
 }
 
 }  // namespace
@@ -221,29 +314,7 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         for (size_t k = 0; k < P.ops.size(); ++k) {
             const Op& o = P.ops[k];
             if (o.kind != OP_GEMM) continue;
-            GemmDev& g = c->gdev[k];
-            pick_gemm(o, g);
-            int bm, bn;
-            zcfg_tile(g.cfg, &bm, &bn);
-            std::vector<ZProb> pr;
-            std::vector<ZTile> tl;
-            for (size_t q = 0; q < o.probs.size(); ++q) {
-                const GemmProblem& p = o.probs[q];
-                pr.push_back(ZProb{p.a_off, p.b_off, p.c_off, p.M, p.N, p.K, p.lda, p.ldb, p.ldc});
-                for (int m0 = 0; m0 < p.M; m0 += bm)
-                    for (int n0 = 0; n0 < p.N; n0 += bn) tl.push_back(ZTile{(int)q, m0, n0, 0});
-            }
-            // longest-K tiles first (uneven symmetry blocks)
-            std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) {
-                return o.probs[a.prob].K > o.probs[b.prob].K;
-            });
-            g.ntiles = (int)tl.size();
-            g.probs = (ZProb*)c->dalloc(pr.size() * sizeof(ZProb));
-            g.tiles = (ZTile*)c->dalloc(tl.size() * sizeof(ZTile));
-            if (!pr.empty())
-                hip_check(hipMemcpy(g.probs, pr.data(), pr.size() * sizeof(ZProb), hipMemcpyHostToDevice), "probs");
-            if (!tl.empty())
-                hip_check(hipMemcpy(g.tiles, tl.data(), tl.size() * sizeof(ZTile), hipMemcpyHostToDevice), "tiles");
+            plan_gemm(c, o, c->gdev[k]);
         }
         // DIIS and reduction scratch
         int64_t nt = c->n1() + c->n2();

@@ -260,6 +260,9 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
     switch (cfg) {
         case ZCFG_128x16: *bm = 128; *bn = 16; break;
         case ZCFG_16x128: *bm = 16; *bn = 128; break;
+        case ZCFG_32x32: *bm = 32; *bn = 32; break;
+        case ZCFG_64x16: *bm = 64; *bn = 16; break;
+        case ZCFG_16x64: *bm = 16; *bn = 64; break;
         default: *bm = 64; *bn = 64; break;
     }
 }
@@ -283,8 +286,42 @@ hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const doubl
     switch (cfg) {
         case ZCFG_128x16: return launch_cfg<128, 16, 4, 1>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
         case ZCFG_16x128: return launch_cfg<16, 128, 1, 4>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
         default: return launch_cfg<64, 64, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
     }
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, const double2* __restrict__ W,
+                                                       const ZRed* __restrict__ reds, double ar, double ai, int beta) {
+    const ZRed r = reds[blockIdx.y];
+    const long long mn = (long long)r.M * r.N;
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mn) return;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < r.S; ++s) {
+        double2 x = W[r.w_off + s * mn + e];
+        sr += x.x;
+        si += x.y;
+    }
+    int m = (int)(e / r.N), n = (int)(e % r.N);
+    double2* c = C + r.c_off + (long long)m * r.ldc + n;
+    double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+    if (beta) {
+        double2 o = *c;
+        out.x += o.x;
+        out.y += o.y;
+    }
+    *c = out;
+}
+
+hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
+                                double ai, int beta, hipStream_t st) {
+    if (nred <= 0 || maxMN <= 0) return hipSuccess;
+    dim3 grid((unsigned)((maxMN + kThreads - 1) / kThreads), (unsigned)nred);
+    k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

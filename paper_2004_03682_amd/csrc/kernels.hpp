@@ -18,7 +18,7 @@ struct ZTile {
 };
 
 // tile shapes of the grouped complex GEMM
-enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16 = 1, ZCFG_16x128 = 2, ZCFG_N };
+enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_N };
 void zcfg_tile(int cfg, int* bm, int* bn);
 
 // C(m,n) = alpha * sum_k opA(m,k) opB(k,n) + beta*C(m,n)  for every tile in `tiles`
@@ -28,6 +28,14 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
                         const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
                         hipStream_t st);
+
+// split-K second pass: C = alpha * sum_s W[w_off + s*M*N + m*N + n] + beta*C
+struct ZRed {
+    long long c_off, w_off;
+    int M, N, ldc, S;
+};
+hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
+                                double ai, int beta, hipStream_t st);
 
 // dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
 struct GatherMaps {
