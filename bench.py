@@ -124,6 +124,13 @@ def main():
     torch.cuda.empty_cache()
     log(f"integral import + pack in {time.perf_counter() - t0:.1f}s")
 
+    t0 = time.perf_counter()
+    ctx.autotune(1)
+    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64"}
+    tuned = {n: f"{names[c]}/bk{b}{'/splitK' if sp else ''}" for n, c, b, sp in ctx.gemm_configs()}
+    log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
+        ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
+
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device=dev)
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device=dev)
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
@@ -177,6 +184,7 @@ def main():
                    "parallelism": "single GPU"},
         "mfma_tflops_residual": round(work["gemm_flops"] / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms > 0 else None,
         "gemm_flops_per_iteration": work["gemm_flops"],
+        "gemm_tiles": tuned,
         "residual_ms_per_iteration": round(resid_ms, 4),
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,

@@ -150,6 +150,29 @@ fscc_status fscc_profile(fscc_ctx *ctx, int enable);
 fscc_status fscc_op_count(const fscc_ctx *ctx, int *count);
 fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, int *calls, double *flops);
 
+/* Tile-shape autotuner for the grouped complex GEMMs (the block contractions
+ * of Fig. 4 have very uneven shapes).  level 1: every candidate tile shape,
+ * K depth (16/32) and split-K choice of each GEMM operation is timed on the
+ * device (HIP events on the context's stream) and the fastest is kept;
+ * level 0: restore the cost-model defaults chosen at fscc_create.  Results
+ * are numerically equivalent (FP64, summation order may change). */
+fscc_status fscc_autotune(fscc_ctx *ctx, int level);
+
+/* Chosen configuration of operation k (cfg = tile shape id or -1 if k is not
+ * a GEMM; bk = K depth; split = 1 if split along K); host outputs. */
+fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int *split);
+
+/* One complex GEMM through the grouped MFMA kernel, for kernel-level tests:
+ * C = alpha * op(A) op(B) + beta*C with op = transpose (tA/tB) and/or
+ * conjugate (cA/cB); A is M x K (lda) or, if tA, K x M; B is K x N (ldb) or,
+ * if tB, N x K; all row-major, device pointers.  cfg = tile shape id
+ * (0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64; -1 = cost
+ * model), bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.
+ * Synchronises hip_stream. */
+fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128 *A, int lda,
+                       const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,
+                       int allow_split, void *hip_stream);
+
 void fscc_destroy(fscc_ctx *ctx);
 const char *fscc_last_error(const fscc_ctx *ctx);
 

@@ -55,6 +55,9 @@ def lib():
             "fscc_profile": ([vp, ip], ip),
             "fscc_op_count": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
+            "fscc_autotune": ([vp, ip], ip),
+            "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
+            "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
             "fscc_destroy": ([vp], None),
             "fscc_last_error": ([vp], ctypes.c_char_p),
         }
@@ -162,6 +165,19 @@ class Context:
             out.append(dict(name=nm.value.decode(), ms=ms.value, calls=calls.value, flops=fl.value))
         return out
 
+    def autotune(self, level=1):
+        self._check(lib().fscc_autotune(self._h, int(level)))
+
+    def gemm_configs(self):
+        """[(op name, tile cfg id, bk, split)] for every GEMM operation."""
+        out = []
+        for k, o in enumerate(self.op_times()):
+            c, b, sp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            self._check(lib().fscc_gemm_config(self._h, k, ctypes.byref(c), ctypes.byref(b), ctypes.byref(sp)))
+            if c.value >= 0:
+                out.append((o["name"], c.value, b.value, sp.value))
+        return out
+
     def destroy(self):
         if getattr(self, "_h", None):
             lib().fscc_destroy(self._h)
@@ -198,3 +214,16 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
             converged = True
             break
     return dict(E=E, iters=k, converged=converged, history=hist)
+
+
+def zgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=False, alpha=1.0, beta=0,
+          cfg=-1, bk=16, allow_split=True, stream=None):
+    """One complex GEMM through the library's grouped MFMA kernel (fscc_zgemm)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    alpha = complex(alpha)
+    r = lib().fscc_zgemm(int(cfg), int(bk), int(tA), int(tB), int(cA), int(cB), int(M), int(N), int(K),
+                         _dev_ptr(A), int(lda), _dev_ptr(B), int(ldb), _dev_ptr(C), int(ldc), alpha.real, alpha.imag,
+                         int(beta), int(allow_split), ctypes.c_void_p(st.cuda_stream))
+    if r != 0:
+        raise FsccError(r, "fscc_zgemm failed")

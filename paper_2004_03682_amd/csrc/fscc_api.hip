@@ -24,8 +24,10 @@ struct GemmDev {
     ZTile* tiles = nullptr;
     int ntiles = 0;
     int cfg = 0;
+    int bk = 16;
     // split-K: the tiles write partial products into `work`, a second pass reduces
     bool split = false;
+    int role = 0;   // 1: pp-ladder, 2: ring GEMMs (distinct kernel symbols in profiles)
     ZRed* reds = nullptr;
     int nred = 0;
     int maxMN = 0;
@@ -132,11 +134,11 @@ struct fscc_ctx {
                 const double2* Ap = A_override ? A_override : B(o.src);
                 double2* Cp = C_override ? C_override : B(o.dst);
                 if (!g.split) {
-                    e = launch_zgemm(g.cfg, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
-                                     o.alpha.imag(), beta, o.cA, o.cB, st);
+                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role);
                 } else {
-                    e = launch_zgemm(g.cfg, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
-                                     o.cA, o.cB, st);
+                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
+                                     0.0, 0, o.cA, o.cB, st, g.role);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
                                                  beta, st);
@@ -172,31 +174,47 @@ fscc_status guarded(fscc_ctx* c, F f) {
     }
 }
 
-// Tile shape with the least padded MFMA work (ties: the larger tile).
+// Default tile shape from a cost model: padded MFMA work at a per-shape
+// efficiency, against operand re-reads (A once per column tile, B once per
+// row tile) at HBM speed.  fscc_autotune() replaces it by measurement.
+double cfg_cost(const Op& o, int cfg) {
+    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8};
+    int bm, bn;
+    zcfg_tile(cfg, &bm, &bn);
+    double fl = 0.0, by = 0.0;
+    for (auto& p : o.probs) {
+        double tm = (p.M + bm - 1) / bm, tn = (p.N + bn - 1) / bn;
+        fl += 8.0 * tm * bm * tn * bn * (double)std::max(p.K, 1);
+        by += 16.0 * ((double)p.M * p.K * tn + (double)p.K * p.N * tm) + 16.0 * (double)p.M * p.N;
+    }
+    return std::max(fl * eff[cfg] / 60e12, by / 5e12);
+}
+
 int pick_cfg(const Op& o) {
     int best = ZCFG_64x64;
-    double best_work = -1.0, best_area = 0.0;
+    double bc = cfg_cost(o, best);
     for (int c = 0; c < ZCFG_N; ++c) {
-        int bm, bn;
-        zcfg_tile(c, &bm, &bn);
-        double w = 0.0;
-        for (auto& p : o.probs)
-            w += (double)((p.M + bm - 1) / bm * bm) * (double)((p.N + bn - 1) / bn * bn) * (double)std::max(p.K, 1);
-        double area = (double)bm * bn;
-        if (best_work < 0 || w < best_work * 0.999 || (w <= best_work * 1.001 && area > best_area)) {
+        double x = cfg_cost(o, c);
+        if (x < bc * 0.95) {
             best = c;
-            best_work = w;
-            best_area = area;
+            bc = x;
         }
     }
     return best;
 }
 
-// Problem / tile lists for one GEMM op.  Contractions whose output tiles are
-// too few to fill the GPU are split along K into chunks of >= 256 (partial
-// products to a workspace, then a deterministic reduction).
-void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g) {
-    g.cfg = pick_cfg(o);
+void free_gemm(GemmDev& g) {
+    if (g.probs) (void)hipFree(g.probs);
+    if (g.tiles) (void)hipFree(g.tiles);
+    if (g.reds) (void)hipFree(g.reds);
+    if (g.work) (void)hipFree(g.work);
+    g = GemmDev();
+}
+
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split) {
+    g.cfg = cfg;
+    g.bk = bk;
+    g.role = o.name == "pp-ladder" ? 1 : (o.name == "ring" || o.name == "W.U") ? 2 : 0;
     int bm, bn;
     zcfg_tile(g.cfg, &bm, &bn);
     long long tiles0 = 0;
@@ -209,7 +227,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g) {
     int S = tiles0 > 0 ? (int)std::min<long long>(512, (target + tiles0 - 1) / tiles0) : 1;
     std::vector<int> Sq(o.probs.size(), 1);
     bool split = false;
-    if (S > 1 && maxK >= 512)
+    if (allow_split && S > 1 && maxK >= 512)
         for (size_t q = 0; q < o.probs.size(); ++q) {
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
             split |= Sq[q] > 1;
@@ -314,7 +332,7 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         for (size_t k = 0; k < P.ops.size(); ++k) {
             const Op& o = P.ops[k];
             if (o.kind != OP_GEMM) continue;
-            plan_gemm(c, o, c->gdev[k]);
+            plan_gemm(c, o, c->gdev[k], pick_cfg(o), 16, true);
         }
         // DIIS and reduction scratch
         int64_t nt = c->n1() + c->n2();
@@ -580,6 +598,138 @@ fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, in
     *calls = ctx->op_calls[k];
     *flops = ctx->plan.ops[k].flops;
     return FSCC_OK;
+}
+
+// Measure every candidate (tile shape x K depth x split) of each GEMM op on
+// the device and keep the fastest.  Timing is data independent, so the
+// context's own buffers and zeroed temporary amplitude buffers are used.
+fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
+    if (!ctx) return FSCC_EINVAL;
+    if (level < 0 || level > 1) return fail(ctx, FSCC_EINVAL, "autotune level must be 0 or 1");
+    return guarded(ctx, [&]() -> fscc_status {
+        Plan& P = ctx->plan;
+        if (level == 0) {
+            for (size_t k = 0; k < P.ops.size(); ++k) {
+                if (P.ops[k].kind != OP_GEMM) continue;
+                free_gemm(ctx->gdev[k]);
+                plan_gemm(ctx, P.ops[k], ctx->gdev[k], pick_cfg(P.ops[k]), 16, true);
+            }
+            return FSCC_OK;
+        }
+        const int64_t n1 = std::max<int64_t>(1, ctx->n1()), n2 = std::max<int64_t>(1, ctx->n2());
+        double2* tmp = (double2*)ctx->dalloc((size_t)(2 * n1 + 2 * n2) * sizeof(double2));
+        hip_check(hipMemsetAsync(tmp, 0, (size_t)(2 * n1 + 2 * n2) * sizeof(double2), ctx->st), "memset");
+        bind_io(ctx, (fscc_c128*)tmp, (fscc_c128*)(tmp + n1), (fscc_c128*)(tmp + n1 + n2), (fscc_c128*)(tmp + 2 * n1 + n2));
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        auto time_op = [&](size_t k) -> float {
+            ctx->run_op(k, P.ops[k]);
+            float best = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                hip_check(hipEventRecord(e0, ctx->st), "event");
+                ctx->run_op(k, P.ops[k]);
+                hip_check(hipEventRecord(e1, ctx->st), "event");
+                hip_check(hipEventSynchronize(e1), "event sync");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        for (size_t k = 0; k < P.ops.size(); ++k) {
+            const Op& o = P.ops[k];
+            if (o.kind != OP_GEMM || o.flops < 1e7) continue;
+            float best_ms = time_op(k);
+            GemmDev best = ctx->gdev[k];
+            ctx->gdev[k] = GemmDev();
+            for (int cfg = 0; cfg < ZCFG_N; ++cfg)
+                for (int bk : {16, 32})
+                    for (int sp = 1; sp >= 0; --sp) {
+                        GemmDev cand;
+                        plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
+                        if (sp == 0 && !cand.split) {
+                            // identical to the split-enabled candidate when no split applies
+                            GemmDev probe;
+                            plan_gemm(ctx, o, probe, cfg, bk, true);
+                            bool same = !probe.split;
+                            free_gemm(probe);
+                            if (same) {
+                                free_gemm(cand);
+                                continue;
+                            }
+                        }
+                        ctx->gdev[k] = cand;
+                        float ms = time_op(k);
+                        ctx->gdev[k] = GemmDev();
+                        if (ms < best_ms) {
+                            free_gemm(best);
+                            best = cand;
+                            best_ms = ms;
+                        } else {
+                            free_gemm(cand);
+                        }
+                    }
+            ctx->gdev[k] = best;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hip_check(hipStreamSynchronize(ctx->st), "autotune sync");
+        (void)hipFree(tmp);
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int* split) {
+    if (!ctx || !cfg || !bk || !split) return FSCC_EINVAL;
+    if (k < 0 || k >= (int)ctx->plan.ops.size()) return FSCC_EINVAL;
+    const GemmDev& g = ctx->gdev[k];
+    *cfg = ctx->plan.ops[k].kind == OP_GEMM ? g.cfg : -1;
+    *bk = g.bk;
+    *split = g.split ? 1 : 0;
+    return FSCC_OK;
+}
+
+// One complex GEMM through the grouped kernel (one problem), for kernel-level tests.
+fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128* A, int lda,
+                       const fscc_c128* B, int ldb, fscc_c128* C, int ldc, double alpha_re, double alpha_im, int beta,
+                       int allow_split, void* hip_stream) {
+    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
+    if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
+    if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
+    fscc_ctx* c = new (std::nothrow) fscc_ctx();
+    if (!c) return FSCC_ENOMEM;
+    c->st = (hipStream_t)hip_stream;
+    fscc_status s = guarded(c, [&]() -> fscc_status {
+        Op o;
+        o.kind = OP_GEMM;
+        o.name = "zgemm";
+        o.tA = tA != 0;
+        o.tB = tB != 0;
+        o.cA = cA != 0;
+        o.cB = cB != 0;
+        o.alpha = cplx(alpha_re, alpha_im);
+        o.beta = beta ? 1 : 0;
+        if (M > 0 && N > 0) o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
+        GemmDev g;
+        plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0);
+        c->gdev.push_back(g);
+        hipError_t e;
+        if (!g.split) {
+            e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
+                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0);
+        } else {
+            e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
+                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0);
+            if (e == hipSuccess)
+                e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, alpha_re, alpha_im, o.beta, c->st);
+        }
+        hip_check(e, "zgemm");
+        hip_check(hipStreamSynchronize(c->st), "zgemm sync");
+        return FSCC_OK;
+    });
+    delete c;
+    return s;
 }
 
 }  // extern "C"

@@ -22,12 +22,12 @@ static constexpr int kThreads = 256;
 // ---------------------------------------------------------------------------
 // grouped complex GEMM
 
-template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+// ROLE only distinguishes kernel symbols in profiles (0 generic, 1 pp-ladder, 2 ring).
+template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE>
 __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
                                                int cA, int cB) {
-    constexpr int BK = 16;
     constexpr int PAD = 4;
     constexpr int FM = BM / (16 * WM);
     constexpr int FN = BN / (16 * WN);
@@ -218,15 +218,28 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
                 b_r[j] = Bs[0][ks * 4 + lk][wn0 + j * 16 + lr];
                 b_i[j] = Bs[1][ks * 4 + lk][wn0 + j * 16 + lr];
             }
+            // four passes over the fragment grid so that consecutive MFMAs
+            // update different accumulators
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
+                for (int j = 0; j < FN; ++j)
                     accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], accr[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
                     acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], acci[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
                     accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], accr[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
                     acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], acci[i][j], 0, 0, 0);
-                }
         }
     }
 
@@ -267,30 +280,47 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
     }
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int BK>
 static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
                              const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
-                             hipStream_t st) {
+                             hipStream_t st, int role) {
     dim3 grid(ntiles), block(kThreads);
-    if (!tA && !tB) k_zgemm<BM, BN, WM, WN, false, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
-    else if (!tA && tB) k_zgemm<BM, BN, WM, WN, false, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
-    else if (tA && !tB) k_zgemm<BM, BN, WM, WN, true, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
-    else k_zgemm<BM, BN, WM, WN, true, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    if (!tA && !tB) {
+        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    } else if (!tA && tB) {
+        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    } else if (tA && !tB) {
+        k_zgemm<BM, BN, WM, WN, BK, true, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    } else {
+        k_zgemm<BM, BN, WM, WN, BK, true, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
-                        const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
-                        hipStream_t st) {
-    if (ntiles <= 0) return hipSuccess;
+template <int BK>
+static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C,
+                            const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
+                            int cB, hipStream_t st, int role) {
     switch (cfg) {
-        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
-        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
-        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
-        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
-        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
-        default: return launch_cfg<64, 64, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st);
+        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
+                        const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
+                        int cB, hipStream_t st, int role) {
+    if (ntiles <= 0) return hipSuccess;
+    if (bk == 32) return launch_bk<32>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+    if (bk == 16) return launch_bk<16>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+    return hipErrorInvalidValue;
 }
 
 __global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, const double2* __restrict__ W,

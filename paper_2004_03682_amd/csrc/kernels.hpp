@@ -25,9 +25,10 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 //   !tA: A(m,k) = A[a_off + m*lda + k]      tA: A(m,k) = A[a_off + k*lda + m]
 //   !tB: B(k,n) = B[b_off + k*ldb + n]      tB: B(k,n) = B[b_off + n*ldb + k]
 //   cA/cB conjugate the operand; beta is 0 (overwrite) or 1 (accumulate).
-hipError_t launch_zgemm(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
-                        const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
-                        hipStream_t st);
+//   bk = 16 or 32 (K depth of one LDS stage); role only selects a distinct kernel symbol.
+hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
+                        const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
+                        int cB, hipStream_t st, int role = 0);
 
 // split-K second pass: C = alpha * sum_s W[w_off + s*M*N + m*N + n] + beta*C
 struct ZRed {
