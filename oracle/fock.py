@@ -168,3 +168,36 @@ def projected_residual(fs: FockSpace, t1: np.ndarray, t2: np.ndarray):
 def fci_energies(fs: FockSpace, N: int) -> tuple[np.ndarray, np.ndarray]:
     """Eigenvalues/vectors of H in sector N."""
     return np.linalg.eigh(fs.hamiltonian(N))
+
+
+def ea_basis(fs: FockSpace):
+    """(0h,1p)-sector basis of the N+1 electron space: |a> = a+_a|Phi>, |ab_j> = a+_a a+_b a_j|Phi> (a<b)."""
+    no, nv = fs.nocc, fs.n - fs.nocc
+    N1 = fs.nocc + 1
+    vecs, labels = [], []
+    for a in range(nv):
+        vecs.append(fs.det(N1, [no + a], []))
+        labels.append(("p", a))
+    for j in range(no):
+        for a in range(nv):
+            for b in range(a + 1, nv):
+                vecs.append(fs.det(N1, [no + a, no + b], [j]))
+                labels.append(("pph", j, a, b))
+    return np.array(vecs).T, labels
+
+
+def ea_matrix(fs: FockSpace, t1: np.ndarray, t2: np.ndarray, E_tot: float | complex):
+    """M_mu,nu = <mu| exp(-T) H exp(T) - E_tot |nu> on the (0h,1p) basis (T from the (0h,0p) sector)."""
+    N1 = fs.nocc + 1
+    H = fs.hamiltonian(N1)
+    T = fs.t_operator(N1, t1, t2)
+    B, labels = ea_basis(fs)
+    # exp(-T) H exp(T) applied to each basis vector
+    cols = []
+    for k in range(B.shape[1]):
+        v = expm_nilpotent(T, B[:, k], 1.0)
+        v = expm_nilpotent(T, H @ v, -1.0)
+        cols.append(v)
+    HB = np.array(cols).T
+    M = B.conj().T @ HB - E_tot * np.eye(B.shape[1])
+    return M, labels
