@@ -36,6 +36,18 @@
  *           upper triangle, row-major).
  *   fscc_layout() returns the lengths n1 (T1) and n2 (T2).
  *
+ * Packed layouts of the (0h,1p) sector (Eq. (5) sector partition; one valence
+ * particle in the active virtual spinors A given at fscc_create):
+ *   S1, R1: for g = 0..nirrep-1: dense [x_g][v_g] row-major block of s_x^a,
+ *           x = active spinors of irrep g (ascending global index), a = ALL
+ *           virtual spinors of irrep g.  Entries with a in A are model-space
+ *           components, not amplitudes: they are ignored on input and are 0 in R1.
+ *   S2, R2: for G = 0..nirrep-1: dense [n_xj(G)][n_vv(G)] row-major block of
+ *           s_xj^ab (antisymmetric in ab, stored a<b); rows = pairs (x, j),
+ *           x active, j occupied, irrep(x)+irrep(j) = G, grouped by
+ *           (irrep(x), irrep(j)) with irrep(x) ascending, x-major inside;
+ *           columns exactly as for T2.
+ *
  * Integral classes at the boundary (fscc_set_integrals): one contiguous
  *   buffer per class, concatenating over (g1, g2, g3) in lexicographic order,
  *   g4 = (g1 + g2 - g3) mod nirrep, the dense row-major blocks
@@ -124,6 +136,35 @@ fscc_status fscc_build_residual(fscc_ctx *ctx, fscc_sector sector, const fscc_c1
  * Returns FSCC_ENOCONV if the step is not finite. */
 fscc_status fscc_update_amplitudes(fscc_ctx *ctx, fscc_sector sector, fscc_c128 *t1, fscc_c128 *t2,
                                    const fscc_c128 *r1, const fscc_c128 *r2, double *max_step);
+
+/* Prepare the (0h,1p) sector from converged (0h,0p) amplitudes t1, t2 (device):
+ * builds the one- and two-body elements of Hbar = exp(-T) H exp(T) used by
+ * the sector's equations (kept by the library) and clears the sector's DIIS
+ * history.  Must be called before fscc_build_residual / fscc_heff with
+ * sector FSCC_S01, and again if T changes. */
+fscc_status fscc_prepare_sector(fscc_ctx *ctx, fscc_sector sector, const fscc_c128 *t1, const fscc_c128 *t2);
+
+/* (0h,1p) sector, with sector = FSCC_S01 in fscc_build_residual: for every
+ * active x, r(x) = e_x + s_x and sigma(x) = Hbar_N r(x) on the {1p, 2p1h}
+ * space; H_eff[y][x] = sigma(x)^y (y in A) is the closed part of Eq. (3)'s
+ * Omega (V Omega)_Cl, and the residual is the Bloch equation
+ *   R1_x^a = sigma(x)^a - sum_y s_y^a H_eff[y][x]   (a not in A),
+ *   R2_xj^ab = sigma(x)_j^ab - sum_y s_yj^ab H_eff[y][x],
+ * with Jacobi denominators D_x^a = e_x - e_a, D_xj^ab = e_x + e_j - e_a - e_b
+ * in fscc_update_amplitudes(FSCC_S01, ...).
+ * fscc_heff returns H_eff = (H Omega)_Cl for amplitudes s1, s2 as a dense
+ * row-major nact x nact complex matrix heff_host[y][x] (host memory), rows
+ * and columns in the order of sys->active; its eigenvalues are the (0h,1p)
+ * state energies relative to the (0h,0p) reference state.  Synchronises. */
+fscc_status fscc_heff(fscc_ctx *ctx, const fscc_c128 *s1, const fscc_c128 *s2, fscc_c128 *heff_host);
+
+/* Jacobi denominators of the (0h,1p) sector (sector = FSCC_S01).  mode 0:
+ * D from the orbital energies (Eq. (3)-(4), the default).  mode 1 (after
+ * fscc_prepare_sector): D from the diagonal of Hbar, D_x^a = Re(Fbar_xx -
+ * Fbar_aa), D_xj^ab = Re(Fbar_xx + Fbar_jj - Fbar_aa - Fbar_bb), clamped to
+ * <= -floor (floor > 0, Eh).  Only the step changes, not the solution of the
+ * Bloch equation; clears the sector's DIIS history. */
+fscc_status fscc_precondition(fscc_ctx *ctx, fscc_sector sector, int mode, double floor);
 
 /* Correlation energy E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a)
  * (f_ia = 0), complex in general; host outputs. */

@@ -79,7 +79,10 @@ def sigma(be, hb, r1, r2):
 class FS01:
     """(0h,1p) sector at fixed converged T: residual, update, H_eff."""
 
-    def __init__(self, be, t1, t2, active):
+    def __init__(self, be, t1, t2, active, precond="bare", floor=0.1):
+        """precond: 'bare' -> D from orbital energies (Eq. (3)); 'dressed' -> D from the
+        diagonal of Hbar (Fbar_xx + Fbar_jj - Fbar_aa - Fbar_bb, real part), clamped to
+        <= -floor.  Only the step changes; the fixed point R = 0 does not."""
         self.be = be
         self.hb = hbar(be, t1, t2)
         sys_ = be.sys
@@ -91,6 +94,15 @@ class FS01:
         ex = ev[self.act]
         self.D1 = ex[:, None] - ev[None, :]
         self.D2 = ex[:, None, None, None] + eo[None, :, None, None] - ev[None, None, :, None] - ev[None, None, None, :]
+        if precond == "dressed":
+            fv = np.real(np.diag(self.hb["Fae"]))
+            fo = np.real(np.diag(self.hb["Fmi"]))
+            fx = fv[self.act]
+            self.D1 = np.minimum(fx[:, None] - fv[None, :], -floor)
+            self.D2 = np.minimum(fx[:, None, None, None] + fo[None, :, None, None] - fv[None, None, :, None]
+                                 - fv[None, None, None, :], -floor)
+        elif precond != "bare":
+            raise ValueError(precond)
         g = sys_.irrep
         go, gv = g[: self.no], g[self.no:]
         gx = gv[self.act]

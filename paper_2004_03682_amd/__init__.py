@@ -55,6 +55,9 @@ def lib():
             "fscc_profile": ([vp, ip], ip),
             "fscc_op_count": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
+            "fscc_prepare_sector": ([vp, ip, vp, vp], ip),
+            "fscc_heff": ([vp, vp, vp, vp], ip),
+            "fscc_precondition": ([vp, ip, ip, ctypes.c_double], ip),
             "fscc_autotune": ([vp, ip], ip),
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
@@ -105,6 +108,11 @@ class Context:
             raise FsccError(st, "fscc_create failed")
         self._h = h
         self.n1, self.n2 = self.layout(FSCC_S00)
+        self.nact = len(self._act)
+        self.m1, self.m2 = self.layout(FSCC_S01) if self.nact else (0, 0)
+
+    def _sizes(self, sector):
+        return (self.n1, self.n2) if sector == FSCC_S00 else (self.m1, self.m2)
 
     @classmethod
     def from_system(cls, sysm, stream=None):
@@ -125,14 +133,30 @@ class Context:
         return a.value, b.value
 
     def build_residual(self, t1, t2, r1, r2, sector=FSCC_S00):
-        self._check(lib().fscc_build_residual(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
-                                              _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2)))
+        a, b = self._sizes(sector)
+        self._check(lib().fscc_build_residual(self._h, sector, _dev_ptr(t1, a), _dev_ptr(t2, b),
+                                              _dev_ptr(r1, a), _dev_ptr(r2, b)))
 
     def update_amplitudes(self, t1, t2, r1, r2, sector=FSCC_S00):
+        a, b = self._sizes(sector)
         m = ctypes.c_double()
-        self._check(lib().fscc_update_amplitudes(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
-                                                 _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2), ctypes.byref(m)))
+        self._check(lib().fscc_update_amplitudes(self._h, sector, _dev_ptr(t1, a), _dev_ptr(t2, b),
+                                                 _dev_ptr(r1, a), _dev_ptr(r2, b), ctypes.byref(m)))
         return m.value
+
+    def prepare_sector(self, t1, t2, sector=FSCC_S01):
+        self._check(lib().fscc_prepare_sector(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2)))
+
+    def precondition(self, mode=1, floor=0.1, sector=FSCC_S01):
+        self._check(lib().fscc_precondition(self._h, sector, int(mode), float(floor)))
+
+    def heff(self, s1, s2):
+        """H_eff[y][x] (numpy complex, nact x nact, rows/columns in the order of the active list)."""
+        import numpy as np
+        out = np.zeros((self.nact, self.nact), np.complex128)
+        self._check(lib().fscc_heff(self._h, _dev_ptr(s1, self.m1), _dev_ptr(s2, self.m2),
+                                    out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def energy(self, t1, t2):
         er, ei = ctypes.c_double(), ctypes.c_double()
@@ -188,6 +212,30 @@ class Context:
             self.destroy()
         except Exception:
             pass
+
+
+def solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=6, log=None):
+    """(0h,1p) Jacobi + DIIS iterations (after ctx.prepare_sector(t1, t2)).
+    Returns dict(heff, eig (sorted by real part), iters, converged)."""
+    import numpy as np
+    import torch
+    r1 = torch.empty_like(s1)
+    r2 = torch.empty_like(s2)
+    ctx.diis_reset(ndiis, FSCC_S01)
+    converged = False
+    k = 0
+    for k in range(1, maxit + 1):
+        ctx.build_residual(s1, s2, r1, r2, FSCC_S01)
+        dmax = ctx.update_amplitudes(s1, s2, r1, r2, FSCC_S01)
+        if log:
+            log(f"(0h,1p) iter {k:3d}  max|step| = {dmax:.3e}")
+        if dmax < tol:
+            converged = True
+            break
+    h = ctx.heff(s1, s2)
+    w = np.linalg.eigvals(h)
+    w = w[np.lexsort((w.imag, w.real))]
+    return dict(heff=h, eig=w, iters=k, converged=converged)
 
 
 def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):

@@ -1,6 +1,6 @@
 // fscc_api.hip -- C ABI of the library (include/fscc.h): context, device
-// memory, execution of the residual plan on a HIP stream, Jacobi + DIIS
-// update and the correlation energy.
+// memory, execution of the (0h,0p) and (0h,1p) residual plans on a HIP
+// stream, Jacobi + DIIS update, correlation energy and H_eff.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +44,26 @@ void hip_check(hipError_t e, const char* what) {
 
 constexpr int kMaxDiis = 8;
 
+// one executable op list with its device GEMM lists and timing slots
+struct OpList {
+    std::vector<Op>* ops = nullptr;
+    std::vector<GemmDev> g;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> ms;
+    std::vector<int> calls;
+};
+
+// DIIS state of one sector
+struct Diis {
+    int ndiis = 6;
+    std::vector<int> order;   // live slots, oldest first
+    double2* ht = nullptr;
+    double2* he = nullptr;
+    double* dB = nullptr;
+    int64_t n1 = 0, n2 = 0;
+    int b_D1 = -1, b_D2 = -1;
+};
+
 }  // namespace
 
 struct fscc_ctx {
@@ -52,14 +72,10 @@ struct fscc_ctx {
     Plan plan;
     std::vector<void*> dbuf;
     std::vector<uint32_t*> dmap;
-    std::vector<GemmDev> gdev;
+    OpList L00, L01p, L01;
     bool have_cls[IC_N] = {false, false, false, false, false, false};
-    // DIIS (sector 0h0p)
-    int ndiis = 6;
-    std::vector<int> order;    // occupied slots, oldest first
-    double2* hist_t = nullptr;
-    double2* hist_e = nullptr;
-    double* dB = nullptr;
+    bool ready01 = false;
+    Diis diis[2];
     double* part = nullptr;
     double* part_max = nullptr;
     double* coef = nullptr;
@@ -68,11 +84,8 @@ struct fscc_ctx {
     double* hscal = nullptr;   // pinned host
     double* epart = nullptr;
     double* eout = nullptr;
-    // profiling
+    double2* rs_tmp = nullptr; // residual scratch for fscc_heff
     bool prof = false;
-    std::vector<hipEvent_t> ev;
-    std::vector<double> op_ms;
-    std::vector<int> op_calls;
     std::string err;
 
     int64_t n1() const { return plan.L_T1.total; }
@@ -86,29 +99,39 @@ struct fscc_ctx {
         return p;
     }
 
-    ~fscc_ctx() {
-        for (size_t k = 0; k < dbuf.size(); ++k) {
-            BufKind kd = plan.bufs[k].kind;
-            if (kd != BUF_IN_T1 && kd != BUF_IN_T2 && kd != BUF_OUT_R1 && kd != BUF_OUT_R2 && dbuf[k]) (void)hipFree(dbuf[k]);
-        }
-        for (auto* m : dmap)
-            if (m) (void)hipFree(m);
-        for (auto& g : gdev) {
+    static void free_list(OpList& L) {
+        for (auto& g : L.g) {
             if (g.probs) (void)hipFree(g.probs);
             if (g.tiles) (void)hipFree(g.tiles);
             if (g.reds) (void)hipFree(g.reds);
             if (g.work) (void)hipFree(g.work);
         }
-        void* ps[] = {hist_t, hist_e, dB, part, part_max, coef, scal, dorder, epart, eout};
+        for (auto& e : L.ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    ~fscc_ctx() {
+        for (size_t k = 0; k < dbuf.size(); ++k)
+            if (!caller_buffer(plan.bufs[k].kind) && dbuf[k]) (void)hipFree(dbuf[k]);
+        for (auto* m : dmap)
+            if (m) (void)hipFree(m);
+        free_list(L00);
+        free_list(L01p);
+        free_list(L01);
+        for (auto& d : diis) {
+            if (d.ht) (void)hipFree(d.ht);
+            if (d.he) (void)hipFree(d.he);
+            if (d.dB) (void)hipFree(d.dB);
+        }
+        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hscal) (void)hipHostFree(hscal);
-        for (auto& e : ev) (void)hipEventDestroy(e);
     }
 
     double2* B(int id) const { return (double2*)dbuf[id]; }
 
-    void run_op(size_t k, const Op& o, int beta_override = -1, const double2* A_override = nullptr,
+    void run_op(const Op& o, const GemmDev* gd, int beta_override = -1, const double2* A_override = nullptr,
                 double2* C_override = nullptr) {
         hipError_t e = hipSuccess;
         switch (o.kind) {
@@ -117,6 +140,9 @@ struct fscc_ctx {
                 break;
             case OP_DIAG:
                 e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st);
+                break;
+            case OP_MUL:
+                e = launch_mul(B(o.dst), (const double*)dbuf[o.src2], o.n, st);
                 break;
             case OP_GATHER: {
                 GatherMaps gm;
@@ -129,7 +155,7 @@ struct fscc_ctx {
                 break;
             }
             case OP_GEMM: {
-                const GemmDev& g = gdev[k];
+                const GemmDev& g = *gd;
                 int beta = beta_override >= 0 ? beta_override : o.beta;
                 const double2* Ap = A_override ? A_override : B(o.src);
                 double2* Cp = C_override ? C_override : B(o.dst);
@@ -147,6 +173,28 @@ struct fscc_ctx {
             }
         }
         hip_check(e, o.name.c_str());
+    }
+
+    void run_list(OpList& L, bool timed) {
+        std::vector<Op>& ops = *L.ops;
+        if (timed && L.ev.size() != 2 * ops.size()) {
+            L.ev.assign(2 * ops.size(), nullptr);
+            for (auto& e : L.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+        }
+        for (size_t k = 0; k < ops.size(); ++k) {
+            if (timed) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
+            run_op(ops[k], &L.g[k]);
+            if (timed) hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
+        }
+        if (timed) {
+            hip_check(hipStreamSynchronize(st), "profile sync");
+            for (size_t k = 0; k < ops.size(); ++k) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, L.ev[2 * k], L.ev[2 * k + 1]), "elapsed");
+                L.ms[k] += ms;
+                L.calls[k] += 1;
+            }
+        }
     }
 };
 
@@ -277,6 +325,49 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
     }
 }
 
+
+void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
+    L.ops = &ops;
+    L.g.assign(ops.size(), GemmDev());
+    L.ms.assign(ops.size(), 0.0);
+    L.calls.assign(ops.size(), 0);
+    for (size_t k = 0; k < ops.size(); ++k)
+        if (ops[k].kind == OP_GEMM) plan_gemm(c, ops[k], L.g[k], pick_cfg(ops[k]), 16, true);
+}
+
+void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2) {
+    d.n1 = n1;
+    d.n2 = n2;
+    d.b_D1 = bD1;
+    d.b_D2 = bD2;
+    int64_t n = std::max<int64_t>(1, n1 + n2);
+    d.ht = (double2*)c->dalloc((size_t)kMaxDiis * n * sizeof(double2));
+    d.he = (double2*)c->dalloc((size_t)kMaxDiis * n * sizeof(double2));
+    d.dB = (double*)c->dalloc(kMaxDiis * kMaxDiis * sizeof(double));
+}
+
+void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2) {
+    Plan& P = c->plan;
+    c->dbuf[P.b_t1] = (void*)t1;
+    c->dbuf[P.b_t2] = (void*)t2;
+    c->dbuf[P.b_r1] = (void*)r1;
+    c->dbuf[P.b_r2] = (void*)r2;
+}
+
+void bind_io01(fscc_ctx* c, const fscc_c128* s1, const fscc_c128* s2, fscc_c128* r1, fscc_c128* r2) {
+    Plan& P = c->plan;
+    c->dbuf[P.b_s1] = (void*)s1;
+    c->dbuf[P.b_s2] = (void*)s2;
+    c->dbuf[P.b_rs1] = (void*)r1;
+    c->dbuf[P.b_rs2] = (void*)r2;
+}
+
+bool all_integrals(const fscc_ctx* c) {
+    for (int k = 0; k < IC_N; ++k)
+        if (!c->have_cls[k]) return false;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -288,6 +379,7 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
     *out = nullptr;
     if (prec != FSCC_FP64) return FSCC_EINVAL;
     if (sys->nocc < 0 || sys->nvirt < 0 || sys->nirrep < 1 || !sys->irrep || !sys->eps) return FSCC_EINVAL;
+    if (sys->nact < 0 || (sys->nact > 0 && !sys->active)) return FSCC_EINVAL;
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
     if (!c) return FSCC_ENOMEM;
     fscc_status s = guarded(c, [&]() -> fscc_status {
@@ -300,22 +392,34 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         int n = sys->nocc + sys->nvirt;
         S.irrep.assign(sys->irrep, sys->irrep + n);
         S.eps.assign(sys->eps, sys->eps + n);
+        if (sys->nact > 0) S.active.assign(sys->active, sys->active + sys->nact);
         for (int p = 0; p < n; ++p) {
             if (S.irrep[p] < 0 || S.irrep[p] >= S.G) throw std::invalid_argument("irrep label out of range");
             if (!std::isfinite(S.eps[p])) throw std::invalid_argument("non-finite orbital energy");
         }
-        c->plan = build_plan_ccsd(S);
+        build_plan_ccsd(S, c->plan);
         Plan& P = c->plan;
         // buffers
         c->dbuf.assign(P.bufs.size(), nullptr);
         for (size_t k = 0; k < P.bufs.size(); ++k) {
             const BufDesc& b = P.bufs[k];
-            if (b.kind == BUF_IN_T1 || b.kind == BUF_IN_T2 || b.kind == BUF_OUT_R1 || b.kind == BUF_OUT_R2) continue;
+            if (caller_buffer(b.kind)) continue;
             size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : sizeof(double2));
             c->dbuf[k] = c->dalloc(bytes);
         }
-        hip_check(hipMemcpy(c->dbuf[P.b_D1], P.D1.data(), P.D1.size() * sizeof(double), hipMemcpyHostToDevice), "D1");
-        hip_check(hipMemcpy(c->dbuf[P.b_D2], P.D2.data(), P.D2.size() * sizeof(double), hipMemcpyHostToDevice), "D2");
+        auto up_real = [&](int b, const std::vector<double>& v) {
+            if (b >= 0 && !v.empty())
+                hip_check(hipMemcpy(c->dbuf[b], v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+        };
+        up_real(P.b_D1, P.D1);
+        up_real(P.b_D2, P.D2);
+        up_real(P.b_D1x, P.D1x);
+        up_real(P.b_D2x, P.D2x);
+        up_real(P.b_mask1, P.mask1);
+        for (auto& hc : P.const_host)
+            if (!hc.data.empty())
+                hip_check(hipMemcpy(c->dbuf[hc.buf], hc.data.data(), hc.data.size() * sizeof(double2),
+                                    hipMemcpyHostToDevice), "const upload");
         // maps of the per-iteration gathers (setup maps are uploaded at set_integrals)
         c->dmap.assign(P.maps.size(), nullptr);
         std::vector<char> is_setup(P.maps.size(), 0);
@@ -327,18 +431,14 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
                       "map upload");
             std::vector<uint32_t>().swap(P.maps[k]);
         }
-        // grouped GEMM problem and tile lists
-        c->gdev.assign(P.ops.size(), GemmDev());
-        for (size_t k = 0; k < P.ops.size(); ++k) {
-            const Op& o = P.ops[k];
-            if (o.kind != OP_GEMM) continue;
-            plan_gemm(c, o, c->gdev[k], pick_cfg(o), 16, true);
+        setup_list(c, c->L00, P.ops);
+        setup_list(c, c->L01p, P.ops01_prep);
+        setup_list(c, c->L01, P.ops01);
+        setup_diis(c, c->diis[0], c->n1(), c->n2(), P.b_D1, P.b_D2);
+        if (P.has01) {
+            setup_diis(c, c->diis[1], P.L_S1.total, P.L_S2.total, P.b_D1x, P.b_D2x);
+            c->rs_tmp = (double2*)c->dalloc((size_t)(P.L_S1.total + P.L_S2.total) * sizeof(double2));
         }
-        // DIIS and reduction scratch
-        int64_t nt = c->n1() + c->n2();
-        c->hist_t = (double2*)c->dalloc((size_t)kMaxDiis * nt * sizeof(double2));
-        c->hist_e = (double2*)c->dalloc((size_t)kMaxDiis * nt * sizeof(double2));
-        c->dB = (double*)c->dalloc(kMaxDiis * kMaxDiis * sizeof(double));
         c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
         c->part_max = (double*)c->dalloc(2048 * sizeof(double));
         c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
@@ -347,8 +447,6 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         c->epart = (double*)c->dalloc(2048 * sizeof(double));
         c->eout = (double*)c->dalloc(4 * sizeof(double));
         hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
-        c->op_ms.assign(P.ops.size(), 0.0);
-        c->op_calls.assign(P.ops.size(), 0);
         return FSCC_OK;
     });
     if (s != FSCC_OK) {
@@ -368,10 +466,17 @@ void fscc_destroy(fscc_ctx* ctx) {
 
 fscc_status fscc_layout(const fscc_ctx* ctx, fscc_sector sector, size_t* n1, size_t* n2) {
     if (!ctx || !n1 || !n2) return FSCC_EINVAL;
-    if (sector != FSCC_S00) return FSCC_EINVAL;
-    *n1 = (size_t)ctx->n1();
-    *n2 = (size_t)ctx->n2();
-    return FSCC_OK;
+    if (sector == FSCC_S00) {
+        *n1 = (size_t)ctx->n1();
+        *n2 = (size_t)ctx->n2();
+        return FSCC_OK;
+    }
+    if (sector == FSCC_S01 && ctx->plan.has01) {
+        *n1 = (size_t)ctx->plan.L_S1.total;
+        *n2 = (size_t)ctx->plan.L_S2.total;
+        return FSCC_OK;
+    }
+    return FSCC_EINVAL;
 }
 
 fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* dev_blocks, size_t n) {
@@ -382,15 +487,15 @@ fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* 
         return fail(ctx, FSCC_EINVAL, "integral class size " + std::to_string(n) + " != expected " +
                                           std::to_string(P.full[cls].total));
     if (n > 0 && !dev_blocks) return fail(ctx, FSCC_EINVAL, "null integral buffer");
+    if (ctx->have_cls[cls]) return fail(ctx, FSCC_ESTATE, "integral class already set");
     return guarded(ctx, [&]() -> fscc_status {
         for (auto& sg : P.setup) {
             if (sg.cls != (int)cls) continue;
             std::vector<uint32_t>& m = P.maps[sg.map];
-            uint32_t* dm = nullptr;
             int64_t cnt = P.bufs[sg.dst].n;
             if (cnt > 0) {
                 if ((int64_t)m.size() != cnt) throw std::logic_error("setup map already consumed: " + sg.name);
-                dm = (uint32_t*)ctx->dalloc(m.size() * sizeof(uint32_t));
+                uint32_t* dm = (uint32_t*)ctx->dalloc(m.size() * sizeof(uint32_t));
                 hip_check(hipMemcpyAsync(dm, m.data(), m.size() * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->st),
                           "pack map upload");
                 GatherMaps gm{};
@@ -401,55 +506,120 @@ fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* 
                 hip_check(hipStreamSynchronize(ctx->st), "pack sync");
                 (void)hipFree(dm);
             }
+            std::vector<uint32_t>().swap(m);
         }
         ctx->have_cls[cls] = true;
         return FSCC_OK;
     });
 }
 
-static bool all_integrals(const fscc_ctx* c) {
-    for (int k = 0; k < IC_N; ++k)
-        if (!c->have_cls[k]) return false;
-    return true;
-}
-
-static void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2) {
-    Plan& P = c->plan;
-    c->dbuf[P.b_t1] = (void*)t1;
-    c->dbuf[P.b_t2] = (void*)t2;
-    c->dbuf[P.b_r1] = (void*)r1;
-    c->dbuf[P.b_r2] = (void*)r2;
-}
-
 fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2,
                                 fscc_c128* r1, fscc_c128* r2) {
     if (!ctx) return FSCC_EINVAL;
-    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
     if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
-    if ((ctx->n1() && (!t1 || !r1)) || (ctx->n2() && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
-    if ((ctx->n1() && (const void*)r1 == (const void*)t1) || (ctx->n2() && (const void*)r2 == (const void*)t2))
+    int64_t n1, n2;
+    if (sector == FSCC_S00) {
+        n1 = ctx->n1();
+        n2 = ctx->n2();
+    } else if (sector == FSCC_S01 && ctx->plan.has01) {
+        if (!ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
+        n1 = ctx->plan.L_S1.total;
+        n2 = ctx->plan.L_S2.total;
+    } else {
+        return fail(ctx, FSCC_EINVAL, "sector not available for this system");
+    }
+    if ((n1 && (!t1 || !r1)) || (n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    if ((n1 && (const void*)r1 == (const void*)t1) || (n2 && (const void*)r2 == (const void*)t2))
         return fail(ctx, FSCC_EINVAL, "residual aliases amplitudes");
     return guarded(ctx, [&]() -> fscc_status {
-        bind_io(ctx, t1, t2, r1, r2);
-        Plan& P = ctx->plan;
-        if (ctx->prof && ctx->ev.size() != 2 * P.ops.size()) {
-            ctx->ev.assign(2 * P.ops.size(), nullptr);
-            for (auto& e : ctx->ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+        if (sector == FSCC_S00) {
+            bind_io(ctx, t1, t2, r1, r2);
+            ctx->run_list(ctx->L00, ctx->prof);
+        } else {
+            bind_io01(ctx, t1, t2, r1, r2);
+            ctx->run_list(ctx->L01, ctx->prof);
         }
-        for (size_t k = 0; k < P.ops.size(); ++k) {
-            if (ctx->prof) hip_check(hipEventRecord(ctx->ev[2 * k], ctx->st), "event");
-            ctx->run_op(k, P.ops[k]);
-            if (ctx->prof) hip_check(hipEventRecord(ctx->ev[2 * k + 1], ctx->st), "event");
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S01 || !ctx->plan.has01) return fail(ctx, FSCC_EINVAL, "no (0h,1p) sector for this system");
+    if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
+    if ((ctx->n1() && !t1) || (ctx->n2() && !t2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        bind_io(ctx, t1, t2, nullptr, nullptr);
+        ctx->run_list(ctx->L01p, false);
+        hip_check(hipStreamSynchronize(ctx->st), "prepare sync");
+        ctx->ready01 = true;
+        ctx->diis[1].order.clear();
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_heff(fscc_ctx* ctx, const fscc_c128* s1, const fscc_c128* s2, fscc_c128* heff_host) {
+    if (!ctx || !heff_host) return FSCC_EINVAL;
+    Plan& P = ctx->plan;
+    if (!P.has01) return fail(ctx, FSCC_EINVAL, "no (0h,1p) sector for this system");
+    if (!ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
+    if ((P.L_S1.total && !s1) || (P.L_S2.total && !s2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        bind_io01(ctx, s1, s2, (fscc_c128*)ctx->rs_tmp, (fscc_c128*)(ctx->rs_tmp + P.L_S1.total));
+        ctx->run_list(ctx->L01, false);
+        std::vector<double2> h(P.L_Heff.total);
+        if (!h.empty())
+            hip_check(hipMemcpyAsync(h.data(), ctx->B(P.b_heff), h.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                                     ctx->st), "heff d2h");
+        hip_check(hipStreamSynchronize(ctx->st), "heff sync");
+        const int nact = P.X.n;
+        for (int k = 0; k < nact * nact; ++k) heff_host[k] = fscc_c128{0.0, 0.0};
+        // block-diagonal [g][y_g][x_g] in irrep-sorted active order -> dense [y][x] in the caller's order
+        int64_t off = 0;
+        for (int g = 0; g < P.G; ++g) {
+            int ng = P.X.cnt[g], o0 = P.X.off[g];
+            for (int a = 0; a < ng; ++a)
+                for (int b = 0; b < ng; ++b) {
+                    double2 v = h[(size_t)(off + (int64_t)a * ng + b)];
+                    heff_host[P.x_order[o0 + a] * nact + P.x_order[o0 + b]] = fscc_c128{v.x, v.y};
+                }
+            off += (int64_t)ng * ng;
         }
-        if (ctx->prof) {
-            hip_check(hipStreamSynchronize(ctx->st), "profile sync");
-            for (size_t k = 0; k < P.ops.size(); ++k) {
-                float ms = 0.f;
-                hip_check(hipEventElapsedTime(&ms, ctx->ev[2 * k], ctx->ev[2 * k + 1]), "elapsed");
-                ctx->op_ms[k] += ms;
-                ctx->op_calls[k] += 1;
-            }
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_precondition(fscc_ctx* ctx, fscc_sector sector, int mode, double floor) {
+    if (!ctx) return FSCC_EINVAL;
+    Plan& P = ctx->plan;
+    if (sector != FSCC_S01 || !P.has01) return fail(ctx, FSCC_EINVAL, "only the (0h,1p) sector has preconditioner modes");
+    if (mode < 0 || mode > 1 || !(floor > 0.0)) return fail(ctx, FSCC_EINVAL, "bad preconditioner mode or floor");
+    if (mode == 1 && !ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
+    return guarded(ctx, [&]() -> fscc_status {
+        std::vector<double> d1 = P.D1x, d2 = P.D2x;
+        if (mode == 1) {
+            std::vector<double2> fv(P.bufs[P.b_Fvv01].n), fo(P.bufs[P.b_Foo01].n);
+            if (!fv.empty())
+                hip_check(hipMemcpyAsync(fv.data(), ctx->B(P.b_Fvv01), fv.size() * sizeof(double2),
+                                         hipMemcpyDeviceToHost, ctx->st), "Fbar d2h");
+            if (!fo.empty())
+                hip_check(hipMemcpyAsync(fo.data(), ctx->B(P.b_Foo01), fo.size() * sizeof(double2),
+                                         hipMemcpyDeviceToHost, ctx->st), "Fbar d2h");
+            hip_check(hipStreamSynchronize(ctx->st), "precondition sync");
+            auto fvd = [&](int p) { return fv[(size_t)P.fvv_diag[p]].x; };
+            auto fod = [&](int i) { return fo[(size_t)P.foo_diag[i]].x; };
+            P.L_S1.for_each([&](int64_t k, const int* p) {
+                if (P.mask1[k] != 0.0) d1[k] = std::min(fvd(P.x_vpos[p[0]]) - fvd(p[1]), -floor);
+            });
+            P.L_S2.for_each([&](int64_t k, const int* p) {
+                d2[k] = std::min(fvd(P.x_vpos[p[0]]) + fod(p[1]) - fvd(p[2]) - fvd(p[3]), -floor);
+            });
         }
+        if (!d1.empty())
+            hip_check(hipMemcpy(ctx->dbuf[P.b_D1x], d1.data(), d1.size() * sizeof(double), hipMemcpyHostToDevice), "D1x");
+        if (!d2.empty())
+            hip_check(hipMemcpy(ctx->dbuf[P.b_D2x], d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice), "D2x");
+        ctx->diis[1].order.clear();
         return FSCC_OK;
     });
 }
@@ -461,7 +631,7 @@ fscc_status fscc_ladder(fscc_ctx* ctx, const fscc_c128* tau, fscc_c128* out) {
         Plan& P = ctx->plan;
         for (size_t k = 0; k < P.ops.size(); ++k)
             if (P.ops[k].name == "pp-ladder") {
-                ctx->run_op(k, P.ops[k], 0, (const double2*)tau, (double2*)out);
+                ctx->run_op(P.ops[k], &ctx->L00.g[k], 0, (const double2*)tau, (double2*)out);
                 return FSCC_OK;
             }
         throw std::logic_error("no ladder op");
@@ -470,23 +640,25 @@ fscc_status fscc_ladder(fscc_ctx* ctx, const fscc_c128* tau, fscc_c128* out) {
 
 fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
     if (!ctx) return FSCC_EINVAL;
-    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
+    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01)))
+        return fail(ctx, FSCC_EINVAL, "sector not available for this system");
     if (ndiis < 0 || ndiis > kMaxDiis) return fail(ctx, FSCC_EINVAL, "DIIS depth out of range");
-    ctx->ndiis = ndiis;
-    ctx->order.clear();
+    ctx->diis[sector].ndiis = ndiis;
+    ctx->diis[sector].order.clear();
     return FSCC_OK;
 }
 
 fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2,
                                    const fscc_c128* r1, const fscc_c128* r2, double* max_step) {
     if (!ctx || !max_step) return FSCC_EINVAL;
-    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "sector not available in this build");
-    if ((ctx->n1() && (!t1 || !r1)) || (ctx->n2() && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01)))
+        return fail(ctx, FSCC_EINVAL, "sector not available for this system");
+    Diis& D = ctx->diis[sector];
+    if ((D.n1 && (!t1 || !r1)) || (D.n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
     return guarded(ctx, [&]() -> fscc_status {
-        Plan& P = ctx->plan;
-        const int64_t n1 = ctx->n1(), n2 = ctx->n2(), n = n1 + n2;
-        const int depth = std::max(1, ctx->ndiis);
-        std::vector<int>& ord = ctx->order;
+        const int64_t n1 = D.n1, n2 = D.n2, n = n1 + n2;
+        const int depth = std::max(1, D.ndiis);
+        std::vector<int>& ord = D.order;
         int slot;
         if ((int)ord.size() < depth) {
             std::vector<char> used(kMaxDiis, 0);
@@ -497,41 +669,39 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
             slot = ord.front();
             ord.erase(ord.begin());
         }
-        // the new slot's B row must not see stale entries of dropped slots: they are
-        // only read through `order`, which lists live slots only.
         ord.push_back(slot);
-        double2* ht = ctx->hist_t + (size_t)slot * n;
-        double2* he = ctx->hist_e + (size_t)slot * n;
+        double2* ht = D.ht + (size_t)slot * n;
+        double2* he = D.he + (size_t)slot * n;
         int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
         if (n1 > 0)
-            hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[P.b_D1], ht, he, n1,
+            hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[D.b_D1], ht, he, n1,
                                     ctx->part_max, nb1, ctx->st),
-                      "jacobi t1");
+                      "jacobi 1");
         if (n2 > 0)
-            hip_check(launch_jacobi((const double2*)t2, (const double2*)r2, (const double*)ctx->dbuf[P.b_D2], ht + n1,
+            hip_check(launch_jacobi((const double2*)t2, (const double2*)r2, (const double*)ctx->dbuf[D.b_D2], ht + n1,
                                     he + n1, n2, ctx->part_max + nb1, nb2, ctx->st),
-                      "jacobi t2");
+                      "jacobi 2");
         int m = (int)ord.size();
         std::vector<const double2*> ev(m);
-        for (int j = 0; j < m; ++j) ev[j] = ctx->hist_e + (size_t)ord[j] * n;
+        for (int j = 0; j < m; ++j) ev[j] = D.he + (size_t)ord[j] * n;
         int nbd = reduce_blocks(n);
         hip_check(launch_dots(ev.data(), m, he, n, ctx->part, nbd, ctx->st), "diis dots");
         hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st), "order");
-        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, ctx->dB, kMaxDiis, slot, ctx->dorder,
+        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, ctx->dorder,
                                      ctx->coef, ctx->scal, ctx->st),
                   "diis solve");
         std::vector<const double2*> xs(kMaxDiis);
-        for (int s = 0; s < kMaxDiis; ++s) xs[s] = ctx->hist_t + (size_t)s * n;
-        if (n1 > 0) hip_check(launch_lincomb((double2*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb t1");
+        for (int s = 0; s < kMaxDiis; ++s) xs[s] = D.ht + (size_t)s * n;
+        if (n1 > 0) hip_check(launch_lincomb((double2*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb 1");
         if (n2 > 0) {
-            for (int s = 0; s < kMaxDiis; ++s) xs[s] = ctx->hist_t + (size_t)s * n + n1;
-            hip_check(launch_lincomb((double2*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb t2");
+            for (int s = 0; s < kMaxDiis; ++s) xs[s] = D.ht + (size_t)s * n + n1;
+            hip_check(launch_lincomb((double2*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
         }
         hip_check(hipMemcpyAsync(ctx->hscal, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "scal");
         hip_check(hipStreamSynchronize(ctx->st), "update sync");
         int dropped = (int)ctx->hscal[1];
         if (dropped > 0) ord.erase(ord.begin(), ord.begin() + std::min(dropped, (int)ord.size() - 1));
-        if (ctx->ndiis <= 1) ord.clear();
+        if (D.ndiis <= 1) ord.clear();
         double mx = ctx->hscal[0];
         if (!std::isfinite(mx)) return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step");
         *max_step = mx;
@@ -547,7 +717,7 @@ fscc_status fscc_energy(fscc_ctx* ctx, const fscc_c128* t1, const fscc_c128* t2,
         Plan& P = ctx->plan;
         bind_io(ctx, t1, t2, nullptr, nullptr);
         // tau = t2 + t1 t1 (the first two operations of the plan)
-        for (size_t k = 0; k < 2; ++k) ctx->run_op(k, P.ops[k]);
+        for (size_t k = 0; k < 2; ++k) ctx->run_op(P.ops[k], &ctx->L00.g[k]);
         int nb = reduce_blocks(ctx->n2());
         hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st), "energy");
         hip_check(hipMemcpyAsync(ctx->hscal + 4, ctx->eout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "e d2h");
@@ -579,24 +749,43 @@ fscc_status fscc_work(const fscc_ctx* ctx, double* gemm_flops, double* ladder_fl
 fscc_status fscc_profile(fscc_ctx* ctx, int enable) {
     if (!ctx) return FSCC_EINVAL;
     ctx->prof = enable != 0;
-    std::fill(ctx->op_ms.begin(), ctx->op_ms.end(), 0.0);
-    std::fill(ctx->op_calls.begin(), ctx->op_calls.end(), 0);
+    for (OpList* L : {&ctx->L00, &ctx->L01}) {
+        std::fill(L->ms.begin(), L->ms.end(), 0.0);
+        std::fill(L->calls.begin(), L->calls.end(), 0);
+    }
     return FSCC_OK;
+}
+
+// operations are numbered: (0h,0p) residual first, then the (0h,1p) residual
+static bool op_ref(fscc_ctx* ctx, int k, OpList** L, int* j) {
+    int n0 = (int)ctx->plan.ops.size(), n1 = (int)ctx->plan.ops01.size();
+    if (k < 0 || k >= n0 + n1) return false;
+    if (k < n0) {
+        *L = &ctx->L00;
+        *j = k;
+    } else {
+        *L = &ctx->L01;
+        *j = k - n0;
+    }
+    return true;
 }
 
 fscc_status fscc_op_count(const fscc_ctx* ctx, int* count) {
     if (!ctx || !count) return FSCC_EINVAL;
-    *count = (int)ctx->plan.ops.size();
+    *count = (int)(ctx->plan.ops.size() + ctx->plan.ops01.size());
     return FSCC_OK;
 }
 
 fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, int* calls, double* flops) {
     if (!ctx || !name || !ms || !calls || !flops) return FSCC_EINVAL;
-    if (k < 0 || k >= (int)ctx->plan.ops.size()) return fail(ctx, FSCC_EINVAL, "op index out of range");
-    *name = ctx->plan.ops[k].name.c_str();
-    *ms = ctx->op_ms[k];
-    *calls = ctx->op_calls[k];
-    *flops = ctx->plan.ops[k].flops;
+    OpList* L;
+    int j;
+    if (!op_ref(ctx, k, &L, &j)) return fail(ctx, FSCC_EINVAL, "op index out of range");
+    const Op& o = (*L->ops)[j];
+    *name = o.name.c_str();
+    *ms = L->ms[j];
+    *calls = L->calls[j];
+    *flops = o.flops;
     return FSCC_OK;
 }
 
@@ -608,27 +797,50 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
     if (level < 0 || level > 1) return fail(ctx, FSCC_EINVAL, "autotune level must be 0 or 1");
     return guarded(ctx, [&]() -> fscc_status {
         Plan& P = ctx->plan;
+        std::vector<OpList*> lists = {&ctx->L00, &ctx->L01};
         if (level == 0) {
-            for (size_t k = 0; k < P.ops.size(); ++k) {
-                if (P.ops[k].kind != OP_GEMM) continue;
-                free_gemm(ctx->gdev[k]);
-                plan_gemm(ctx, P.ops[k], ctx->gdev[k], pick_cfg(P.ops[k]), 16, true);
-            }
+            for (OpList* L : lists)
+                for (size_t k = 0; k < L->ops->size(); ++k) {
+                    const Op& o = (*L->ops)[k];
+                    if (o.kind != OP_GEMM) continue;
+                    free_gemm(L->g[k]);
+                    plan_gemm(ctx, o, L->g[k], pick_cfg(o), 16, true);
+                }
             return FSCC_OK;
         }
-        const int64_t n1 = std::max<int64_t>(1, ctx->n1()), n2 = std::max<int64_t>(1, ctx->n2());
-        double2* tmp = (double2*)ctx->dalloc((size_t)(2 * n1 + 2 * n2) * sizeof(double2));
-        hip_check(hipMemsetAsync(tmp, 0, (size_t)(2 * n1 + 2 * n2) * sizeof(double2), ctx->st), "memset");
-        bind_io(ctx, (fscc_c128*)tmp, (fscc_c128*)(tmp + n1), (fscc_c128*)(tmp + n1 + n2), (fscc_c128*)(tmp + 2 * n1 + n2));
+        int64_t nio = 2 * std::max<int64_t>(1, ctx->n1()) + 2 * std::max<int64_t>(1, ctx->n2());
+        if (P.has01) nio += 2 * std::max<int64_t>(1, P.L_S1.total) + 2 * std::max<int64_t>(1, P.L_S2.total);
+        double2* tmp = (double2*)ctx->dalloc((size_t)nio * sizeof(double2));
+        hip_check(hipMemsetAsync(tmp, 0, (size_t)nio * sizeof(double2), ctx->st), "memset");
+        {
+            double2* q = tmp;
+            auto take = [&](int64_t cnt) {
+                double2* r = q;
+                q += std::max<int64_t>(1, cnt);
+                return (fscc_c128*)r;
+            };
+            fscc_c128* a = take(ctx->n1());
+            fscc_c128* b = take(ctx->n2());
+            fscc_c128* c = take(ctx->n1());
+            fscc_c128* d = take(ctx->n2());
+            bind_io(ctx, a, b, c, d);
+            if (P.has01) {
+                fscc_c128* e = take(P.L_S1.total);
+                fscc_c128* f = take(P.L_S2.total);
+                fscc_c128* g = take(P.L_S1.total);
+                fscc_c128* h = take(P.L_S2.total);
+                bind_io01(ctx, e, f, g, h);
+            }
+        }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
-        auto time_op = [&](size_t k) -> float {
-            ctx->run_op(k, P.ops[k]);
+        auto time_op = [&](const Op& o, const GemmDev* g) -> float {
+            ctx->run_op(o, g);
             float best = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
                 hip_check(hipEventRecord(e0, ctx->st), "event");
-                ctx->run_op(k, P.ops[k]);
+                ctx->run_op(o, g);
                 hip_check(hipEventRecord(e1, ctx->st), "event");
                 hip_check(hipEventSynchronize(e1), "event sync");
                 float ms = 0.f;
@@ -637,41 +849,38 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             }
             return best;
         };
-        for (size_t k = 0; k < P.ops.size(); ++k) {
-            const Op& o = P.ops[k];
-            if (o.kind != OP_GEMM || o.flops < 1e7) continue;
-            float best_ms = time_op(k);
-            GemmDev best = ctx->gdev[k];
-            ctx->gdev[k] = GemmDev();
-            for (int cfg = 0; cfg < ZCFG_N; ++cfg)
-                for (int bk : {16, 32})
-                    for (int sp = 1; sp >= 0; --sp) {
-                        GemmDev cand;
-                        plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
-                        if (sp == 0 && !cand.split) {
-                            // identical to the split-enabled candidate when no split applies
-                            GemmDev probe;
-                            plan_gemm(ctx, o, probe, cfg, bk, true);
-                            bool same = !probe.split;
-                            free_gemm(probe);
-                            if (same) {
+        for (OpList* L : lists)
+            for (size_t k = 0; k < L->ops->size(); ++k) {
+                const Op& o = (*L->ops)[k];
+                if (o.kind != OP_GEMM || o.flops < 1e7) continue;
+                GemmDev best = L->g[k];
+                float best_ms = time_op(o, &best);
+                for (int cfg = 0; cfg < ZCFG_N; ++cfg)
+                    for (int bk : {16, 32})
+                        for (int sp = 1; sp >= 0; --sp) {
+                            GemmDev cand;
+                            plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
+                            if (sp == 0 && !cand.split) {
+                                GemmDev probe;
+                                plan_gemm(ctx, o, probe, cfg, bk, true);
+                                bool same = !probe.split;
+                                free_gemm(probe);
+                                if (same) {
+                                    free_gemm(cand);
+                                    continue;
+                                }
+                            }
+                            float ms = time_op(o, &cand);
+                            if (ms < best_ms) {
+                                free_gemm(best);
+                                best = cand;
+                                best_ms = ms;
+                            } else {
                                 free_gemm(cand);
-                                continue;
                             }
                         }
-                        ctx->gdev[k] = cand;
-                        float ms = time_op(k);
-                        ctx->gdev[k] = GemmDev();
-                        if (ms < best_ms) {
-                            free_gemm(best);
-                            best = cand;
-                            best_ms = ms;
-                        } else {
-                            free_gemm(cand);
-                        }
-                    }
-            ctx->gdev[k] = best;
-        }
+                L->g[k] = best;
+            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         hip_check(hipStreamSynchronize(ctx->st), "autotune sync");
@@ -682,15 +891,16 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
 
 fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int* split) {
     if (!ctx || !cfg || !bk || !split) return FSCC_EINVAL;
-    if (k < 0 || k >= (int)ctx->plan.ops.size()) return FSCC_EINVAL;
-    const GemmDev& g = ctx->gdev[k];
-    *cfg = ctx->plan.ops[k].kind == OP_GEMM ? g.cfg : -1;
+    OpList* L;
+    int j;
+    if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
+    const GemmDev& g = L->g[j];
+    *cfg = (*L->ops)[j].kind == OP_GEMM ? g.cfg : -1;
     *bk = g.bk;
     *split = g.split ? 1 : 0;
     return FSCC_OK;
 }
 
-// One complex GEMM through the grouped kernel (one problem), for kernel-level tests.
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128* A, int lda,
                        const fscc_c128* B, int ldb, fscc_c128* C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void* hip_stream) {
@@ -713,7 +923,6 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         if (M > 0 && N > 0) o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
         GemmDev g;
         plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0);
-        c->gdev.push_back(g);
         hipError_t e;
         if (!g.split) {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
@@ -726,6 +935,7 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         }
         hip_check(e, "zgemm");
         hip_check(hipStreamSynchronize(c->st), "zgemm sync");
+        free_gemm(g);
         return FSCC_OK;
     });
     delete c;

@@ -457,6 +457,20 @@ hipError_t launch_diag(double2* dst, const double* d, const double2* src, long l
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_mul(double2* __restrict__ dst, const double* __restrict__ d, long long n) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double2 o = dst[k];
+    double dd = d[k];
+    dst[k] = make_double2(dd * o.x, dd * o.y);
+}
+
+hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_mul<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, d, n);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_zero(double2* __restrict__ dst, long long n) {
     long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) dst[k] = make_double2(0.0, 0.0);

@@ -49,6 +49,7 @@ hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, 
 hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
                         hipStream_t st);
 hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st);
+hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st);   // dst *= d (real)
 
 // Jacobi: step = r/D; tn = t + step (written to hist_t), e = step (hist_e);
 // per-block max |step| into part_max[block]

@@ -19,7 +19,13 @@ namespace fscc {
 
 using cplx = std::complex<double>;
 
-enum BufKind { BUF_IN_T1, BUF_IN_T2, BUF_OUT_R1, BUF_OUT_R2, BUF_CONST, BUF_SCRATCH, BUF_REAL };
+enum BufKind { BUF_IN_T1, BUF_IN_T2, BUF_OUT_R1, BUF_OUT_R2, BUF_CONST, BUF_SCRATCH, BUF_REAL,
+               BUF_IN_S1, BUF_IN_S2, BUF_OUT_RS1, BUF_OUT_RS2 };
+
+inline bool caller_buffer(BufKind k) {
+    return k == BUF_IN_T1 || k == BUF_IN_T2 || k == BUF_OUT_R1 || k == BUF_OUT_R2 || k == BUF_IN_S1 ||
+           k == BUF_IN_S2 || k == BUF_OUT_RS1 || k == BUF_OUT_RS2;
+}
 
 struct BufDesc {
     std::string name;
@@ -38,6 +44,7 @@ enum OpKind {
     OP_GEMM,     // grouped: C = alpha*op(A)op(B) + beta*C
     OP_AXPBY,    // dst[k] = alpha*cj(src[k]) + beta*dst[k]
     OP_DIAG,     // dst[k] -= d[k] * src[k]   (d real)
+    OP_MUL,      // dst[k] *= d[k]            (d real)
 };
 
 struct Op {
@@ -90,7 +97,25 @@ struct Plan {
     int b_oovv = -1;                  // <ij||ab> in the T2 layout (energy)
     int b_tau = -1;                   // tau in the T2 layout (energy scratch)
     std::vector<double> D1, D2;       // host copies (uploaded once)
-    std::vector<uint32_t> tau_mapsA[2], tau_mapsB[2];
+
+    // ---- (0h,1p) sector (present when the system has active virtuals)
+    bool has01 = false;
+    Space X;                          // active virtuals, irrep-sorted
+    std::vector<int> x_vpos;          // X position -> V position
+    std::vector<int> x_order;         // X position -> index in the caller's active list
+    Layout L_S1, L_S2, L_Heff;
+    int b_s1 = -1, b_s2 = -1, b_rs1 = -1, b_rs2 = -1;
+    int b_D1x = -1, b_D2x = -1, b_mask1 = -1, b_heff = -1;
+    std::vector<double> D1x, D2x, mask1;
+    int b_Fvv01 = -1, b_Foo01 = -1;   // Fbar_vv, Fbar_oo ([g][n_g][n_g] blocks)
+    std::vector<int64_t> fvv_diag, foo_diag;   // offset of the diagonal element per V / O position
+    std::vector<Op> ops01_prep;       // Hbar elements from the converged (0h,0p) amplitudes
+    std::vector<Op> ops01;            // sigma + Bloch residual
+    struct HostConst {
+        int buf;
+        std::vector<cplx> data;
+    };
+    std::vector<HostConst> const_host;   // small complex constants uploaded at create
 
     int buf(const std::string& name, int64_t n, BufKind k) {
         bufs.push_back({name, n, k});
@@ -108,6 +133,6 @@ struct Plan {
     }
 };
 
-Plan build_plan_ccsd(const System& S);
+void build_plan_ccsd(const System& S, Plan& P);
 
 }  // namespace fscc

@@ -16,6 +16,7 @@
 //   <ab||ej> = -conj <je||ab>       (OVVV)
 //   <mb||ij> =  conj <ij||mb>       (OOOV)
 //   <ab||ij> =  conj <ij||ab>       (OOVV)   -- the T2 driver
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -36,8 +37,9 @@ struct Builder {
     int G;
     const Space* o;
     const Space* v;
+    std::vector<Op>* out;   // op list being built
 
-    Builder(Plan& p) : P(p), G(p.G), o(&p.O), v(&p.V) {}
+    Builder(Plan& p) : P(p), G(p.G), o(&p.O), v(&p.V), out(&p.ops) {}
 
     Slot s(int l, const Space* sp, int sg) const { return Slot{l, sp, sg}; }
 
@@ -68,7 +70,7 @@ struct Builder {
             if (src2 >= 0)
                 op.mapsB.push_back(P.map(name + "/B" + std::to_string(t), build_map(Ld, *Ls2, terms[t].perm2, 1)));
         }
-        P.ops.push_back(std::move(op));
+        out->push_back(std::move(op));
     }
 
     void gemm(const std::string& name, int bA, const Layout& A, bool tA, bool cA, int bB, const Layout& B, bool tB,
@@ -117,7 +119,7 @@ struct Builder {
             op.flops += 8.0 * (double)M * (double)N * (double)K;
             op.probs.push_back(pr);
         }
-        P.ops.push_back(std::move(op));
+        out->push_back(std::move(op));
     }
 
     void axpby(const std::string& name, int dst, int src, int64_t n, cplx alpha, int beta, bool conj) {
@@ -130,7 +132,17 @@ struct Builder {
         op.alpha = alpha;
         op.beta = beta;
         op.conj = conj;
-        P.ops.push_back(std::move(op));
+        out->push_back(std::move(op));
+    }
+
+    void mul(const std::string& name, int dst, int d, int64_t n) {
+        Op op;
+        op.kind = OP_MUL;
+        op.name = name;
+        op.dst = dst;
+        op.src2 = d;
+        op.n = n;
+        out->push_back(std::move(op));
     }
 
     void diag(const std::string& name, int dst, int d, int src, int64_t n) {
@@ -141,7 +153,7 @@ struct Builder {
         op.src2 = d;
         op.src = src;
         op.n = n;
-        P.ops.push_back(std::move(op));
+        out->push_back(std::move(op));
     }
 
     // constant derived from integral class `cls` (boundary full blocks)
@@ -155,8 +167,7 @@ struct Builder {
 
 }  // namespace
 
-Plan build_plan_ccsd(const System& S) {
-    Plan P;
+void build_plan_ccsd(const System& S, Plan& P) {
     const int G = S.G;
     P.G = G;
     if (G < 1 || S.nocc < 0 || S.nvirt < 0) throw std::invalid_argument("bad system sizes");
@@ -278,38 +289,39 @@ Plan build_plan_ccsd(const System& S) {
     int b_tau = P.buf("tau", L_T2.total, BUF_SCRATCH);
     int b_taut = P.buf("tau~", L_T2.total, BUF_SCRATCH);
     P.b_tau = b_tau;
-    // tau = t2 + t_i^a t_j^b - t_i^b t_j^a   (T1 logical (i,a); T2 logical (i,j,a,b))
-    std::vector<T> tt = {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}};
-    B.axpby("tau=t2", b_tau, P.b_t2, L_T2.total, 1.0, 0, false);
-    B.gather("tau+=t1t1", b_tau, L_T2, P.b_t1, L_T1, tt, 1.0, 1, false, P.b_t1, &L_T1);
-    B.axpby("tau~=t2", b_taut, P.b_t2, L_T2.total, 1.0, 0, false);
-    B.gather("tau~+=t1t1/2", b_taut, L_T2, P.b_t1, L_T1, tt, 0.5, 1, false, P.b_t1, &L_T1);
-
-    // ------------------------------------------------------- F intermediates
-    // F_me = sum_nf <mn||ef> t_n^f
     Layout L_Fme_v = make_layout("Fme_v", G, {s(0, o, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
     Layout L_Fme_m = make_layout("Fme_m", G, {s(0, o, 1)}, -1, {s(1, v, 1)}, -1, 1);
     int b_Fme = P.buf("Fme", L_T1.total, BUF_SCRATCH);
-    B.gemm("Fme", b_oovv_ph, L_oovv_ph, false, false, P.b_t1, L_T1w, false, false, b_Fme, L_Fme_v, 1.0, 0);
-    // F_ae = sum_mf t_m^f <ma||fe> - sum_{m<n,f} tau~_mn^af <mn||ef>
     Layout L_Fae_v = make_layout("Fae_v", G, {s(0, v, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
     Layout L_Fae_m = make_layout("Fae_m", G, {s(0, v, 1)}, -1, {s(1, v, 1)}, -1, 1);
     int nvv0 = (int)L_Fae_m.total;
     int b_Fae = P.buf("Fae", nvv0, BUF_SCRATCH);
-    B.gemm("Fae.1", b_ovvv_2a, L_ovvv_2a, false, false, P.b_t1, L_T1v, false, false, b_Fae, L_Fae_v, 1.0, 0);
     Layout L_tt_2b = make_layout("tau~_2b", G, {s(2, v, 1)}, -1, {s(0, o, 1), s(1, o, 1), s(3, v, -1)}, 0, 1);
     int b_tt2b = P.buf("tau~_2b", L_tt_2b.total, BUF_SCRATCH);
-    B.gather("tau~->2b", b_tt2b, L_tt_2b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
-    B.gemm("Fae.2", b_tt2b, L_tt_2b, false, false, b_oovv_2b, L_oovv_2b, false, false, b_Fae, L_Fae_m, -1.0, 1);
-    // F_mi = sum_ne t_n^e <mn||ie> + sum_{n,e<f} tau~_in^ef <mn||ef>
     Layout L_Fmi_v = make_layout("Fmi_v", G, {s(0, o, -1), s(1, o, 1)}, -1, {}, -1, 1, 0);
     Layout L_Fmi_m = make_layout("Fmi_m", G, {s(0, o, 1)}, -1, {s(1, o, 1)}, -1, 1);
     int b_Fmi = P.buf("Fmi", L_Fmi_m.total, BUF_SCRATCH);
-    B.gemm("Fmi.1", b_ooov_3a, L_ooov_3a, false, false, P.b_t1, L_T1v, false, false, b_Fmi, L_Fmi_v, 1.0, 0);
     Layout L_tt_3b = make_layout("tau~_3b", G, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, {s(0, o, 1)}, -1, -1);
     int b_tt3b = P.buf("tau~_3b", L_tt_3b.total, BUF_SCRATCH);
-    B.gather("tau~->3b", b_tt3b, L_tt_3b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
-    B.gemm("Fmi.2", b_oovv_3b, L_oovv_3b, false, false, b_tt3b, L_tt_3b, false, false, b_Fmi, L_Fmi_m, 1.0, 1);
+    // tau = t2 + t_i^a t_j^b - t_i^b t_j^a   (T1 logical (i,a); T2 logical (i,j,a,b))
+    std::vector<T> tt = {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}};
+    auto emit_tau_F = [&]() {
+        B.axpby("tau=t2", b_tau, P.b_t2, L_T2.total, 1.0, 0, false);
+        B.gather("tau+=t1t1", b_tau, L_T2, P.b_t1, L_T1, tt, 1.0, 1, false, P.b_t1, &L_T1);
+        B.axpby("tau~=t2", b_taut, P.b_t2, L_T2.total, 1.0, 0, false);
+        B.gather("tau~+=t1t1/2", b_taut, L_T2, P.b_t1, L_T1, tt, 0.5, 1, false, P.b_t1, &L_T1);
+        // F_me = sum_nf <mn||ef> t_n^f
+        B.gemm("Fme", b_oovv_ph, L_oovv_ph, false, false, P.b_t1, L_T1w, false, false, b_Fme, L_Fme_v, 1.0, 0);
+        // F_ae = sum_mf t_m^f <ma||fe> - sum_{m<n,f} tau~_mn^af <mn||ef>
+        B.gemm("Fae.1", b_ovvv_2a, L_ovvv_2a, false, false, P.b_t1, L_T1v, false, false, b_Fae, L_Fae_v, 1.0, 0);
+        B.gather("tau~->2b", b_tt2b, L_tt_2b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        B.gemm("Fae.2", b_tt2b, L_tt_2b, false, false, b_oovv_2b, L_oovv_2b, false, false, b_Fae, L_Fae_m, -1.0, 1);
+        // F_mi = sum_ne t_n^e <mn||ie> + sum_{n,e<f} tau~_in^ef <mn||ef>
+        B.gemm("Fmi.1", b_ooov_3a, L_ooov_3a, false, false, P.b_t1, L_T1v, false, false, b_Fmi, L_Fmi_v, 1.0, 0);
+        B.gather("tau~->3b", b_tt3b, L_tt_3b, b_taut, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        B.gemm("Fmi.2", b_oovv_3b, L_oovv_3b, false, false, b_tt3b, L_tt_3b, false, false, b_Fmi, L_Fmi_m, 1.0, 1);
+    };
+    emit_tau_F();
 
     // ------------------------------------------------------------ W'_mnij
     Layout L_Wp = make_layout("W'", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, o, 1), s(3, o, 1)}, 0, 1);
@@ -429,8 +441,259 @@ Plan build_plan_ccsd(const System& S) {
     B.gemm("ooov.t2", b_ooov_14f, L_ooov_14f, false, false, b_T14f, L_T14f, false, false, P.b_r1, L_T1, -1.0, 1);
     B.diag("r1-=D1*t1", P.b_r1, P.b_D1, P.b_t1, L_T1.total);
 
-    (void)b_oovo_9c;
-    return P;
+
+    // =====================================================================
+    // (0h,1p) sector: Bloch equation Q Hbar_N (P + S) = S H_eff on the
+    // {1p, 2p1h} space, sigma(x) = Hbar_N r(x), r(x) = e_x + s_x.
+    if (!S.active.empty()) {
+        P.has01 = true;
+        std::vector<int> act(S.active);
+        std::sort(act.begin(), act.end());
+        for (size_t k = 1; k < act.size(); ++k)
+            if (act[k] == act[k - 1]) throw std::invalid_argument("duplicate active spinor");
+        std::vector<int> xl;
+        for (int gidx : act) {
+            if (gidx < S.nocc || gidx >= S.nocc + S.nvirt) throw std::invalid_argument("active spinor is not virtual");
+            xl.push_back(S.irrep[gidx]);
+        }
+        P.X = Space::make(G, act, xl);
+        const Space* x = &P.X;
+        P.x_vpos.assign(x->n, 0);
+        P.x_order.assign(x->n, 0);
+        for (int q = 0; q < x->n; ++q) {
+            int gidx = x->glob[q];
+            for (int a = 0; a < v->n; ++a)
+                if (v->glob[a] == gidx) P.x_vpos[q] = a;
+            for (size_t k = 0; k < S.active.size(); ++k)
+                if (S.active[k] == gidx) P.x_order[q] = (int)k;
+        }
+        // amplitudes: S1 (x,a) = [g][x_g][v_g] (all virtuals a; active a are model-space entries),
+        //             S2 (x,j,a,b) = [G][(x,j)][ab<]
+        P.L_S1 = make_layout("S1", G, {s(0, x, 1)}, -1, {s(1, v, 1)}, -1, 1);
+        P.L_S2 = make_layout("S2", G, {s(0, x, 1), s(1, o, 1)}, -1, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+        P.L_Heff = make_layout("Heff", G, {s(0, x, 1)}, -1, {s(1, x, 1)}, -1, 1);
+        const Layout& L_S1 = P.L_S1;
+        const Layout& L_S2 = P.L_S2;
+        const Layout& L_Heff = P.L_Heff;
+        Layout L_S1v = make_layout("S1v", G, {s(0, x, -1), s(1, v, 1)}, -1, {}, -1, 1, 0);
+        P.b_s1 = P.buf("s1", L_S1.total, BUF_IN_S1);
+        P.b_s2 = P.buf("s2", L_S2.total, BUF_IN_S2);
+        P.b_rs1 = P.buf("rs1", L_S1.total, BUF_OUT_RS1);
+        P.b_rs2 = P.buf("rs2", L_S2.total, BUF_OUT_RS2);
+        // denominators D_x^a = e_x - e_a, D_xj^ab = e_x + e_j - e_a - e_b; model-space entries masked
+        P.D1x.assign(L_S1.total, 1.0);
+        P.mask1.assign(L_S1.total, 0.0);
+        std::vector<cplx> eid(L_S1.total, 0.0);
+        L_S1.for_each([&](int64_t k, const int* p) {
+            bool model = false;
+            for (int q = 0; q < x->n; ++q)
+                if (P.x_vpos[q] == p[1]) model = true;
+            if (!model) {
+                P.D1x[k] = S.eps[x->glob[p[0]]] - S.eps[v->glob[p[1]]];
+                P.mask1[k] = 1.0;
+            }
+            if (P.x_vpos[p[0]] == p[1]) eid[k] = 1.0;
+        });
+        P.D2x.assign(L_S2.total, 0.0);
+        L_S2.for_each([&](int64_t k, const int* p) {
+            P.D2x[k] = S.eps[x->glob[p[0]]] + S.eps[o->glob[p[1]]] - S.eps[v->glob[p[2]]] - S.eps[v->glob[p[3]]];
+        });
+        P.b_D1x = P.buf("D1x", L_S1.total, BUF_REAL);
+        P.b_D2x = P.buf("D2x", L_S2.total, BUF_REAL);
+        P.b_mask1 = P.buf("mask1", L_S1.total, BUF_REAL);
+        int b_eid = P.buf("Eid", L_S1.total, BUF_CONST);
+        P.const_host.push_back({b_eid, std::move(eid)});
+
+        // ---------------------------------------------------- Hbar (prepare)
+        B.out = &P.ops01_prep;
+        emit_tau_F();
+        int b_t1c = P.buf("t1(01)", L_T1.total, BUF_SCRATCH);
+        B.axpby("t1 copy", b_t1c, P.b_t1, L_T1.total, 1.0, 0, false);
+        int b_tauc = P.buf("tau(01)", L_T2.total, BUF_SCRATCH);
+        B.axpby("tau copy", b_tauc, b_tau, L_T2.total, 1.0, 0, false);
+        int b_Fov = P.buf("Fbar_ov", L_T1.total, BUF_SCRATCH);
+        B.axpby("Fbar_ov=Fme", b_Fov, b_Fme, L_T1.total, 1.0, 0, false);
+        // Fbar_vv = F_ae + diag(e_v) - 1/2 sum_m t_m^a F_me
+        std::vector<cplx> dv(L_Fae_m.total, 0.0), dov(L_Fmi_m.total, 0.0);
+        L_Fae_m.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) dv[k] = S.eps[v->glob[p[0]]]; });
+        L_Fmi_m.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) dov[k] = S.eps[o->glob[p[0]]]; });
+        int b_dv = P.buf("diag e_v", L_Fae_m.total, BUF_CONST);
+        int b_do = P.buf("diag e_o", L_Fmi_m.total, BUF_CONST);
+        P.const_host.push_back({b_dv, std::move(dv)});
+        P.const_host.push_back({b_do, std::move(dov)});
+        int b_Fvv = P.buf("Fbar_vv", L_Fae_m.total, BUF_SCRATCH);
+        B.axpby("Fbar_vv=Fae", b_Fvv, b_Fae, L_Fae_m.total, 1.0, 0, false);
+        B.axpby("Fbar_vv+=e", b_Fvv, b_dv, L_Fae_m.total, 1.0, 1, false);
+        B.gemm("Fbar_vv.t1", P.b_t1, L_T1, true, false, b_Fme, L_Fme_m, false, false, b_Fvv, L_Fae_m, -0.5, 1);
+        // Fbar_oo = F_mi + diag(e_o) + 1/2 sum_e F_me t_i^e
+        int b_Foo = P.buf("Fbar_oo", L_Fmi_m.total, BUF_SCRATCH);
+        P.b_Fvv01 = b_Fvv;
+        P.b_Foo01 = b_Foo;
+        P.fvv_diag.assign(v->n, 0);
+        P.foo_diag.assign(o->n, 0);
+        L_Fae_m.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) P.fvv_diag[p[0]] = k; });
+        L_Fmi_m.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) P.foo_diag[p[0]] = k; });
+        B.axpby("Fbar_oo=Fmi", b_Foo, b_Fmi, L_Fmi_m.total, 1.0, 0, false);
+        B.axpby("Fbar_oo+=e", b_Foo, b_do, L_Fmi_m.total, 1.0, 1, false);
+        B.gemm("Fbar_oo.t1", b_Fme, L_Fme_m, false, false, P.b_t1, L_T1, true, false, b_Foo, L_Fmi_m, 0.5, 1);
+        // Wbar_amef = <am||ef> - sum_n t_n^a <nm||ef>, layout [(m,ef<)|(a)]
+        int b_Wam = P.buf("Wbar_amef", L_ovvv_14e.total, BUF_SCRATCH);
+        B.axpby("Wbar_amef=-<ma||ef>", b_Wam, b_ovvv_14e, L_ovvv_14e.total, -1.0, 0, false);
+        B.gemm("Wbar_amef.t1", b_oovv_3b, L_oovv_3b, true, false, P.b_t1, L_T1, false, false, b_Wam, L_ovvv_14e, -1.0, 1);
+        // Wbar_mbej (ring layout) = <mb||ej> + sum_f t_j^f <mb||ef> - sum_n t_n^b <mn||ej>
+        //                           - sum_nf (t_jn^fb + t_j^f t_n^b) <mn||ef>
+        int b_Wb = P.buf("Wbar_mbej", L_W.total, BUF_SCRATCH);
+        int b_X9b01 = P.buf("X9b(01)", L_X9b.total, BUF_SCRATCH);
+        int b_X9c01 = P.buf("X9c(01)", L_X9c.total, BUF_SCRATCH);
+        int b_U01 = P.buf("U(01)", L_U.total, BUF_SCRATCH);
+        B.axpby("Wbar=<mb||ej>", b_Wb, b_ring0, L_W.total, 1.0, 0, false);
+        B.gemm("Wbar.t1.ovvv", b_ovvv_9b, L_ovvv_9b, false, false, P.b_t1, L_T1, true, false, b_X9b01, L_X9b, 1.0, 0);
+        B.gather("Wbar+=X9b", b_Wb, L_W, b_X9b01, L_X9b, {T{{0, 2, 1, 3}, 1, {}}}, 1.0, 1);
+        B.gemm("Wbar.t1.ooov", b_oovo_9c, L_oovo_9c, false, false, P.b_t1, L_T1, false, false, b_X9c01, L_X9c, -1.0, 0);
+        B.gather("Wbar+=X9c", b_Wb, L_W, b_X9c01, L_X9c, {T{{0, 2, 3, 1}, 1, {}}}, 1.0, 1);
+        B.gather("U'=t2", b_U01, L_U, P.b_t2, L_T2, {T{{2, 0, 1, 3}, 1, {}}}, 1.0, 0);
+        B.gather("U'+=t1t1", b_U01, L_U, P.b_t1, L_T1, {T{{2, 1}, 1, {0, 3}}}, 1.0, 1, false, P.b_t1, &L_T1);
+        B.gemm("Wbar.U'", b_oovv_ph, L_oovv_ph, false, false, b_U01, L_U, false, false, b_Wb, L_W, -1.0, 1);
+        // Xc_mbej = <mb||ej> - sum_nf t_nj^bf <mn||ef>  (ring layout, then [(m,b,j)|(e)])
+        int b_Xc = P.buf("Xc ring", L_W.total, BUF_SCRATCH);
+        int b_Tnf = P.buf("t_nj^bf", L_U.total, BUF_SCRATCH);
+        B.axpby("Xc=<mb||ej>", b_Xc, b_ring0, L_W.total, 1.0, 0, false);
+        B.gather("t2->(n,f|j,b)", b_Tnf, L_U, P.b_t2, L_T2, {T{{0, 2, 3, 1}, 1, {}}}, 1.0, 0);
+        B.gemm("Xc.t2", b_oovv_ph, L_oovv_ph, false, false, b_Tnf, L_U, false, false, b_Xc, L_W, -1.0, 1);
+        int b_Xc9f = P.buf("Xc", L_ovvo_9f.total, BUF_SCRATCH);
+        B.gather("Xc->(m,b,j|e)", b_Xc9f, L_ovvo_9f, b_Xc, L_W, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        // t2 as [(m)|(j,ab<)] and in the ring layout
+        Layout L_Tm = make_layout("T2(m|j,ab<)", G, {s(0, o, 1)}, -1, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, -1);
+        int b_Tm = P.buf("T2(m|j,ab<)", L_Tm.total, BUF_SCRATCH);
+        B.gather("t2->(m|j,ab<)", b_Tm, L_Tm, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        int b_Tr01 = P.buf("Tring(01)", L_Tr.total, BUF_SCRATCH);
+        B.gather("t2->ring(01)", b_Tr01, L_Tr, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+
+        // ------------------------------------------------ sigma + residual
+        B.out = &P.ops01;
+        int b_r1x = P.buf("r1(x)", L_S1.total, BUF_SCRATCH);
+        B.axpby("r1=s1", b_r1x, P.b_s1, L_S1.total, 1.0, 0, false);
+        B.mul("r1*=mask", b_r1x, P.b_mask1, L_S1.total);
+        B.axpby("r1+=e_x", b_r1x, b_eid, L_S1.total, 1.0, 1, false);
+        // rho_xj^ef = s_xj^ef + r(x)^e t_j^f - r(x)^f t_j^e
+        int b_rho = P.buf("rho", L_S2.total, BUF_SCRATCH);
+        B.axpby("rho=s2", b_rho, P.b_s2, L_S2.total, 1.0, 0, false);
+        B.gather("rho+=r1t1", b_rho, L_S2, b_r1x, L_S1, {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}}, 1.0, 1, false,
+                 b_t1c, &L_T1);
+        // S2 ladder: sigma2 = sum_{e<f} <ab||ef> rho_xj^ef
+        B.gemm("S2-ladder", b_rho, L_S2, false, false, b_vvvv, L_VVVV, true, false, P.b_rs2, L_S2, 1.0, 0);
+        // -P(ab) sum_m t_m^b Z_xj^am,  Z_xj^am = -sum_{e<f} <ma||ef> rho_xj^ef
+        Layout L_Z1x = make_layout("Z1x", G, {s(0, o, 1), s(1, v, 1)}, -1, {s(2, x, 1), s(3, o, 1)}, -1, 1);
+        int b_Z1x = P.buf("Z1x", L_Z1x.total, BUF_SCRATCH);
+        B.gemm("S2.Z", b_ovvv, L_OVVV, false, false, b_rho, L_S2, true, false, b_Z1x, L_Z1x, -1.0, 0);
+        Layout L_Z2x = make_layout("Z2x", G, {s(2, x, 1), s(3, o, 1), s(1, v, -1)}, -1, {s(0, o, 1)}, -1, 1);
+        int b_Z2x = P.buf("Z2x", L_Z2x.total, BUF_SCRATCH);
+        B.gather("Z1x->Z2x", b_Z2x, L_Z2x, b_Z1x, L_Z1x, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        Layout L_Y4 = make_layout("Y4x", G, {s(0, x, 1), s(1, o, 1), s(2, v, -1)}, -1, {s(3, v, 1)}, -1, 1);
+        int b_Y4 = P.buf("Y4x", L_Y4.total, BUF_SCRATCH);
+        B.gemm("S2.Z.t1", b_Z2x, L_Z2x, false, false, b_t1c, L_T1, false, false, b_Y4, L_Y4, 1.0, 0);
+        B.gather("rs2+=-P(ab)Y4", P.b_rs2, L_S2, b_Y4, L_Y4, {T{{0, 1, 2, 3}, -1, {}}, T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
+        // hole-hole part: sum_{m<n} tau_mn^ab (X_mn,xj + w_mn,xj)
+        Layout L_Xpp = make_layout("X''", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, x, 1), s(3, o, 1)}, -1, 1);
+        int b_Xpp = P.buf("X''", L_Xpp.total, BUF_SCRATCH);
+        B.gemm("S2.X", b_oovv, L_OOVV, false, false, b_rho, L_S2, true, false, b_Xpp, L_Xpp, 1.0, 0);
+        Layout L_w = make_layout("w", G, {s(0, o, 1), s(1, o, 1), s(2, o, -1)}, 0, {s(3, x, 1)}, -1, 1);
+        int b_w = P.buf("w", L_w.total, BUF_SCRATCH);
+        B.gemm("S2.w", b_ooov_5b, L_ooov_5b, false, false, b_r1x, L_S1, true, false, b_w, L_w, -1.0, 0);
+        B.gather("X''+=w", b_Xpp, L_Xpp, b_w, L_w, {T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
+        B.gemm("S2.hh", b_Xpp, L_Xpp, true, false, b_tauc, L_T2, false, false, P.b_rs2, L_S2, 1.0, 1);
+        // sum_e <ab||ej> r(x)^e
+        Layout L_Y6 = make_layout("Y6x", G, {s(0, v, 1), s(1, v, 1), s(2, o, -1)}, 0, {s(3, x, 1)}, -1, 1);
+        int b_Y6 = P.buf("Y6x", L_Y6.total, BUF_SCRATCH);
+        B.gemm("S2.vvvo", b_vvvo_11, L_vvvo_11, false, false, b_r1x, L_S1, true, false, b_Y6, L_Y6, 1.0, 0);
+        B.gather("rs2+=Y6", P.b_rs2, L_S2, b_Y6, L_Y6, {T{{2, 3, 1, 0}, 1, {}}}, 1.0, 1);
+        // P(ab) sum_e Fbar_be s_xj^ae
+        Layout L_S7 = make_layout("S2(x,j,a|e)", G, {s(0, x, 1), s(1, o, 1), s(2, v, -1)}, -1, {s(3, v, 1)}, -1, 1);
+        int b_S7 = P.buf("S2(x,j,a|e)", L_S7.total, BUF_SCRATCH);
+        B.gather("s2->(x,j,a|e)", b_S7, L_S7, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        int b_Y7 = P.buf("Y7x", L_S7.total, BUF_SCRATCH);
+        B.gemm("S2.Fvv", b_S7, L_S7, false, false, b_Fvv, L_Fae_m, true, false, b_Y7, L_S7, 1.0, 0);
+        B.gather("rs2+=P(ab)Y7", P.b_rs2, L_S2, b_Y7, L_S7, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}}, 1.0, 1);
+        // -sum_m Fbar_mj s_xm^ab
+        Layout L_S8 = make_layout("S2(x,ab<|m)", G, {s(0, x, 1), s(2, v, -1), s(3, v, -1)}, 1, {s(1, o, 1)}, -1, -1);
+        int b_S8 = P.buf("S2(x,ab<|m)", L_S8.total, BUF_SCRATCH);
+        B.gather("s2->(x,ab<|m)", b_S8, L_S8, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        int b_Y8 = P.buf("Y8x", L_S8.total, BUF_SCRATCH);
+        B.gemm("S2.Foo", b_S8, L_S8, false, false, b_Foo, L_Fmi_m, false, false, b_Y8, L_S8, 1.0, 0);
+        B.gather("rs2+=-Y8", P.b_rs2, L_S2, b_Y8, L_S8, {T{{0, 1, 2, 3}, -1, {}}}, 1.0, 1);
+        // P(ab) sum_me Wbar_mbej s_xm^ae  (ring)
+        Layout L_S9 = make_layout("S2 ring", G, {s(0, x, -1), s(2, v, 1)}, -1, {s(1, o, -1), s(3, v, 1)}, -1, -1);
+        int b_S9 = P.buf("S2 ring", L_S9.total, BUF_SCRATCH);
+        B.gather("s2->ring", b_S9, L_S9, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        Layout L_Y9x = make_layout("Y9x", G, {s(0, x, -1), s(1, v, 1)}, -1, {s(2, o, -1), s(3, v, 1)}, -1, -1);
+        int b_Y9x = P.buf("Y9x", L_Y9x.total, BUF_SCRATCH);
+        B.gemm("S2.ring", b_S9, L_S9, false, false, b_Wb, L_W, false, false, b_Y9x, L_Y9x, 1.0, 0);
+        B.gather("rs2+=P(ab)Y9", P.b_rs2, L_S2, b_Y9x, L_Y9x, {T{{0, 2, 1, 3}, 1, {}}, T{{0, 3, 1, 2}, -1, {}}}, 1.0, 1);
+        // -P(ab) sum_mf t_mj^af v_mbf^x,  v_mbf^x = sum_e <mb||ef> r(x)^e
+        Layout L_Yv = make_layout("Yv", G, {s(0, o, 1), s(1, v, -1), s(2, v, 1)}, -1, {s(3, x, 1)}, -1, 1);
+        int b_Yv = P.buf("Yv", L_Yv.total, BUF_SCRATCH);
+        B.gemm("S2.v", b_ovvv_9b, L_ovvv_9b, false, false, b_r1x, L_S1, true, false, b_Yv, L_Yv, 1.0, 0);
+        Layout L_vp = make_layout("v'", G, {s(0, o, -1), s(1, v, 1)}, -1, {s(2, x, -1), s(3, v, 1)}, -1, 1);
+        int b_vp = P.buf("v'", L_vp.total, BUF_SCRATCH);
+        // v'(m,f,x,b) = -Yv(m,f,b,x)
+        B.gather("Yv->v'", b_vp, L_vp, b_Yv, L_Yv, {T{{0, 1, 3, 2}, -1, {}}}, 1.0, 0);
+        Layout L_Cv = make_layout("Cv", G, {s(0, o, -1), s(1, v, 1)}, -1, {s(2, x, -1), s(3, v, 1)}, -1, -1);
+        int b_Cv = P.buf("Cv", L_Cv.total, BUF_SCRATCH);
+        B.gemm("S2.t2.v", b_Tr01, L_Tr, false, false, b_vp, L_vp, false, false, b_Cv, L_Cv, 1.0, 0);
+        B.gather("rs2+=P(ab)Cv", P.b_rs2, L_S2, b_Cv, L_Cv, {T{{1, 2, 0, 3}, 1, {}}, T{{1, 3, 0, 2}, -1, {}}}, 1.0, 1);
+        // -P(ab) sum_m t_m^a y_mbj^x,  y_mbj^x = sum_e Xc_mbej r(x)^e
+        Layout L_Yy = make_layout("Yy", G, {s(0, o, 1), s(1, v, 1), s(2, o, -1)}, -1, {s(3, x, 1)}, -1, 1);
+        int b_Yy = P.buf("Yy", L_Yy.total, BUF_SCRATCH);
+        B.gemm("S2.y", b_Xc9f, L_ovvo_9f, false, false, b_r1x, L_S1, true, false, b_Yy, L_Yy, 1.0, 0);
+        Layout L_Yy2 = make_layout("Yy2", G, {s(3, x, 1), s(2, o, 1), s(1, v, -1)}, -1, {s(0, o, 1)}, -1, 1);
+        int b_Yy2 = P.buf("Yy2", L_Yy2.total, BUF_SCRATCH);
+        B.gather("Yy->Yy2", b_Yy2, L_Yy2, b_Yy, L_Yy, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        Layout L_Yy3 = make_layout("Yy3", G, {s(0, x, 1), s(1, o, 1), s(2, v, -1)}, -1, {s(3, v, 1)}, -1, 1);
+        int b_Yy3 = P.buf("Yy3", L_Yy3.total, BUF_SCRATCH);
+        B.gemm("S2.y.t1", b_Yy2, L_Yy2, false, false, b_t1c, L_T1, false, false, b_Yy3, L_Yy3, 1.0, 0);
+        B.gather("rs2+=-P(ab)Yy3", P.b_rs2, L_S2, b_Yy3, L_Yy3, {T{{0, 1, 3, 2}, -1, {}}, T{{0, 1, 2, 3}, 1, {}}}, 1.0, 1);
+        // sigma1 = sum_e Fbar_ae r^e + sum_me Fbar_me s_xm^ae + sum_{m,e<f} Wbar_amef s_xm^ef
+        B.gemm("S1.Fvv", b_r1x, L_S1, false, false, b_Fvv, L_Fae_m, true, false, P.b_rs1, L_S1, 1.0, 0);
+        B.gemm("S1.Fov", b_S9, L_S9, false, false, b_Fov, L_Fme_v, false, false, P.b_rs1, L_S1v, 1.0, 1);
+        Layout L_S12 = make_layout("S2(x|m,ef<)", G, {s(0, x, 1)}, -1, {s(1, o, 1), s(2, v, -1), s(3, v, -1)}, 1, -1);
+        int b_S12 = P.buf("S2(x|m,ef<)", L_S12.total, BUF_SCRATCH);
+        B.gather("s2->(x|m,ef<)", b_S12, L_S12, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+        B.gemm("S1.Wamef", b_S12, L_S12, false, false, b_Wam, L_ovvv_14e, false, false, P.b_rs1, L_S1, 1.0, 1);
+        // -sum_m (q_xm + u_xm) t_mj^ab,  q_xm = sum_{n,e<f} <mn||ef> s_xn^ef,  u_xm = sum_e Fbar_me r(x)^e
+        Layout L_q = make_layout("q", G, {s(0, x, 1)}, -1, {s(1, o, 1)}, -1, 1);
+        int b_q = P.buf("q", L_q.total, BUF_SCRATCH);
+        B.gemm("S2.q", b_S12, L_S12, false, false, b_oovv_3b, L_oovv_3b, true, false, b_q, L_q, 1.0, 0);
+        B.gemm("S2.u", b_r1x, L_S1, false, false, b_Fov, L_Fme_m, true, false, b_q, L_q, 1.0, 1);
+        int b_C9 = P.buf("C9", L_S12.total, BUF_SCRATCH);
+        B.gemm("S2.q.t2", b_q, L_q, false, false, b_Tm, L_Tm, false, false, b_C9, L_S12, -1.0, 0);
+        // H_eff[y][x] = sigma(x)^y  (block diagonal)
+        P.b_heff = P.buf("Heff", L_Heff.total, BUF_SCRATCH);
+        {
+            Op op;
+            op.kind = OP_GATHER;
+            op.name = "Heff=sigma1";
+            op.dst = P.b_heff;
+            op.src = P.b_rs1;
+            op.alpha = 1.0;
+            op.beta = 0;
+            op.n = L_Heff.total;
+            std::vector<uint32_t> m((size_t)L_Heff.total, MAP_ZERO);
+            L_Heff.for_each([&](int64_t k, const int* p) {
+                int pos[2] = {p[1], P.x_vpos[p[0]]};    // sigma(x)^y: S1 logical (x, a = y)
+                int sg = 1;
+                int64_t so = L_S1.find(pos, &sg);
+                if (so >= 0) m[(size_t)k] = (uint32_t)so;
+            });
+            op.mapsA.push_back(P.map("Heff/A0", std::move(m)));
+            B.out->push_back(std::move(op));
+        }
+        // Bloch residual: R1 = sigma1 - sum_y s_y^a Heff_yx (masked);  R2 = sigma2 + C9 - sum_y s_yj^ab Heff_yx
+        B.gemm("R1.Heff", P.b_heff, L_Heff, true, false, P.b_s1, L_S1, false, false, P.b_rs1, L_S1, -1.0, 1);
+        B.mul("R1*=mask", P.b_rs1, P.b_mask1, L_S1.total);
+        B.gemm("R2.Heff", P.b_heff, L_Heff, true, false, b_S12, L_S12, false, false, b_C9, L_S12, -1.0, 1);
+        B.gather("rs2+=C9", P.b_rs2, L_S2, b_C9, L_S12, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 1);
+        B.out = &P.ops;
+    }
 }
 
 }  // namespace fscc

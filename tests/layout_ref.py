@@ -93,3 +93,69 @@ def t2_size(sysm):
 
 def t1_size(sysm):
     return int(sum(len(members(sysm, "O", g)) * len(members(sysm, "V", g)) for g in range(sysm.nirrep)))
+
+
+# ---------------------------------------------------------------- (0h,1p) sector
+#   S1: [g][x_g][v_g]   (x = active spinors of irrep g, ascending global index; all virtuals)
+#   S2: [G][(x,j)][ab<] (rows grouped by (g_x, g_j), g_x ascending, x-major)
+
+def active_members(sysm, g):
+    """Indices into sysm.active (sorted ascending) of the active spinors of irrep g."""
+    act = np.sort(np.asarray(sysm.active))
+    return np.array([k for k, p in enumerate(act) if sysm.irrep[p] == g], dtype=np.int64)
+
+
+def xj_list(sysm, G):
+    X, J = [], []
+    n = sysm.nirrep
+    for gx in range(n):
+        gj = (G - gx) % n
+        for x in active_members(sysm, gx):
+            for j in members(sysm, "O", gj):
+                X.append(x)
+                J.append(j)
+    return np.array(X, dtype=np.int64), np.array(J, dtype=np.int64)
+
+
+def pack_s1(sysm, s1):
+    out = []
+    for g in range(sysm.nirrep):
+        mx, mv = active_members(sysm, g), members(sysm, "V", g)
+        out.append(s1[np.ix_(mx, mv)].ravel())
+    return np.concatenate(out)
+
+
+def unpack_s1(sysm, buf):
+    s1 = np.zeros((len(sysm.active), sysm.nvirt), np.complex128)
+    off = 0
+    for g in range(sysm.nirrep):
+        mx, mv = active_members(sysm, g), members(sysm, "V", g)
+        sz = len(mx) * len(mv)
+        s1[np.ix_(mx, mv)] = buf[off:off + sz].reshape(len(mx), len(mv))
+        off += sz
+    assert off == buf.size
+    return s1
+
+
+def pack_s2(sysm, s2):
+    out = []
+    for G in range(sysm.nirrep):
+        X, J = xj_list(sysm, G)
+        A, B = pair_list(sysm, "V", G)
+        out.append(s2[X[:, None], J[:, None], A[None, :], B[None, :]].ravel())
+    return np.concatenate(out)
+
+
+def unpack_s2(sysm, buf):
+    s2 = np.zeros((len(sysm.active), sysm.nocc, sysm.nvirt, sysm.nvirt), np.complex128)
+    off = 0
+    for G in range(sysm.nirrep):
+        X, J = xj_list(sysm, G)
+        A, B = pair_list(sysm, "V", G)
+        sz = len(X) * len(A)
+        x = buf[off:off + sz].reshape(len(X), len(A))
+        off += sz
+        s2[X[:, None], J[:, None], A[None, :], B[None, :]] = x
+        s2[X[:, None], J[:, None], B[None, :], A[None, :]] = -x
+    assert off == buf.size
+    return s2
