@@ -86,3 +86,28 @@ def test_fs01_converged_eigenvalues(spec):
         for e in go["eig"]:
             assert np.min(np.abs(wM - e)) <= 1e-9
     ctx.destroy()
+
+
+def test_fs01_dressed_preconditioner_same_fixed_point():
+    import torch
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(6, 18, 3, 0.05, 9, nact=4)
+    be = ccsd.Dense(s)
+    ctx = _ctx(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    assert F.solve(ctx, t1, t2, tol=1e-11)["converged"]
+    ctx.prepare_sector(t1, t2)
+    out = []
+    for mode in (0, 1):
+        ctx.precondition(mode, 0.1)
+        s1 = torch.zeros(ctx.m1, dtype=torch.complex128, device="cuda")
+        s2 = torch.zeros(ctx.m2, dtype=torch.complex128, device="cuda")
+        g = F.solve01(ctx, s1, s2, tol=1e-11)
+        assert g["converged"]
+        out.append(g["eig"])
+    r = solver.solve_ccsd(be, tol=1e-11)
+    o = fs01.solve_fs01(fs01.FS01(be, r["t1"], r["t2"], s.active, precond="dressed"), tol=1e-11)
+    assert np.abs(out[0] - out[1]).max() <= 1e-10
+    assert np.abs(out[1] - o["eig"]).max() <= 1e-10
+    ctx.destroy()
