@@ -92,7 +92,20 @@ def main():
     ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) sector")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 3 device copies of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 1 << 30, "copy_bytes_written_per_launch": 1 << 30}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)

@@ -110,8 +110,8 @@ typedef struct {
 /* Build the plan for one system: irrep-sorted index spaces, block layouts,
  * reorder maps and grouped-GEMM problem lists (the TTGT decomposition of
  * every contraction of the CCSD residual).  hip_stream may be NULL (the null
- * stream).  Only FSCC_FP64 is accepted by this build.  Device memory for
- * intermediates is allocated here. */
+ * stream).  prec selects the arithmetic of the dominant contractions (see
+ * fscc_set_precision).  Device memory for intermediates is allocated here. */
 fscc_status fscc_create(const fscc_system *sys, fscc_precision prec, void *hip_stream, fscc_ctx **out);
 
 /* Import one integral class (boundary layout above, n complex elements) and
@@ -213,6 +213,46 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128 *A, int lda,
                        const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void *hip_stream);
+
+/* Arithmetic of the three dominant (0h,0p) contractions: the particle-
+ * particle ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets
+ * (the T2 part of W_mbej and sum_me t_im^ae W_mbej), which together carry
+ * most of the flops of an iteration.  Every other step -- the remaining contractions, the reorders,
+ * the denominator (Jacobi) update, the DIIS subspace solve and the energy --
+ * stays FP64 in every mode.
+ *   FSCC_FP64        complex FP64 on the FP64 matrix cores.
+ *   FSCC_SPLIT_BF16  each FP64 operand value is written as three bf16 pieces
+ *                    (x ~ h0 + h1 + h2, each piece the rounded remainder of
+ *                    the previous ones); a product keeps the six piece
+ *                    products of order <= 2 (exact in fp32) on the bf16
+ *                    matrix cores with fp32 accumulation; every 32-deep
+ *                    k block of fp32 sums is added into FP64, and the
+ *                    alpha/beta epilogue is FP64.  Relative error of one
+ *                    output element ~1e-7 of sum_k |a_k||b_k|.
+ *   FSCC_SPLIT_FP32  two fp32 pieces (hi + lo), three products (hi hi,
+ *                    hi lo, lo hi) on the fp32 matrix cores, same
+ *                    accumulation; same order of accuracy.
+ * Constant operands (integrals) are split once and kept (12 B per complex
+ * element for bf16, 16 B for fp32, beside their FP64 copy); amplitude
+ * operands are split on every call.  Switching is allowed between residual
+ * calls; DIIS history is kept.  The first switch to a split mode allocates
+ * the piece buffers. */
+fscc_status fscc_set_precision(fscc_ctx *ctx, fscc_precision prec);
+fscc_status fscc_get_precision(const fscc_ctx *ctx, int *prec);
+
+/* Split-kernel tile shape of operation k in the current precision (host
+ * output; -1 if k does not run in split precision now).  Shapes: 0: 64x64,
+ * 1: 64x32, 2: 32x64, 3: 32x32.  fscc_autotune(ctx, 1) in a split mode also
+ * measures these shapes. */
+fscc_status fscc_mixed_config(const fscc_ctx *ctx, int k, int *cfg);
+
+/* One complex GEMM through the split-precision kernel (kernel-level tests):
+ * same operand conventions as fscc_zgemm; prec = FSCC_SPLIT_BF16 or
+ * FSCC_SPLIT_FP32; cfg = split tile shape (0..3).  Allocates and frees its
+ * piece buffers; synchronises hip_stream. */
+fscc_status fscc_zgemm_split(int prec, int cfg, int tA, int tB, int cA, int cB, int M, int N, int K,
+                             const fscc_c128 *A, int lda, const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc,
+                             double alpha_re, double alpha_im, int beta, void *hip_stream);
 
 void fscc_destroy(fscc_ctx *ctx);
 const char *fscc_last_error(const fscc_ctx *ctx);

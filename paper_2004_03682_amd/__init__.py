@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfscc.so")
 
 FSCC_S00, FSCC_S01 = 0, 1
+FSCC_FP64, FSCC_SPLIT_FP32, FSCC_SPLIT_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FSCC_FP64, "split_fp32": FSCC_SPLIT_FP32, "split_bf16": FSCC_SPLIT_BF16}
 CLASSES = ("OOOO", "OOOV", "OOVV", "OVOV", "OVVV", "VVVV")
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESYMM", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "ENOCONV"}
 
@@ -61,6 +63,10 @@ def lib():
             "fscc_autotune": ([vp, ip], ip),
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
+            "fscc_set_precision": ([vp, ip], ip),
+            "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
+            "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
+            "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
             "fscc_destroy": ([vp], None),
             "fscc_last_error": ([vp], ctypes.c_char_p),
         }
@@ -70,6 +76,14 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+def _prec(p):
+    if isinstance(p, str):
+        if p not in PRECISIONS:
+            raise ValueError(f"unknown precision {p!r}")
+        return PRECISIONS[p]
+    return int(p)
 
 
 def _dev_ptr(t, n=None):
@@ -88,7 +102,7 @@ def _dev_ptr(t, n=None):
 class Context:
     """One system (fscc_create ... fscc_destroy)."""
 
-    def __init__(self, nocc, nvirt, nirrep, irrep, eps, stream=None, active=()):
+    def __init__(self, nocc, nvirt, nirrep, irrep, eps, stream=None, active=(), precision="fp64"):
         import numpy as np
         import torch
         L = lib()
@@ -103,7 +117,7 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ctypes.c_void_p()
-        st = L.fscc_create(ctypes.byref(s), 0, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        st = L.fscc_create(ctypes.byref(s), _prec(precision), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise FsccError(st, "fscc_create failed")
         self._h = h
@@ -115,8 +129,28 @@ class Context:
         return (self.n1, self.n2) if sector == FSCC_S00 else (self.m1, self.m2)
 
     @classmethod
-    def from_system(cls, sysm, stream=None):
-        return cls(sysm.nocc, sysm.nvirt, sysm.nirrep, sysm.irrep, sysm.eps, stream, getattr(sysm, "active", ()))
+    def from_system(cls, sysm, stream=None, precision="fp64"):
+        return cls(sysm.nocc, sysm.nvirt, sysm.nirrep, sysm.irrep, sysm.eps, stream, getattr(sysm, "active", ()),
+                   precision)
+
+    def set_precision(self, precision):
+        """'fp64', 'split_bf16' or 'split_fp32' for the ladder and ring contractions."""
+        self._check(lib().fscc_set_precision(self._h, _prec(precision)))
+
+    def precision(self):
+        p = ctypes.c_int()
+        self._check(lib().fscc_get_precision(self._h, ctypes.byref(p)))
+        return {v: k for k, v in PRECISIONS.items()}[p.value]
+
+    def mixed_configs(self):
+        """[(op name, split tile cfg id)] for the operations running in split precision now."""
+        out = []
+        for k, o in enumerate(self.op_times()):
+            c = ctypes.c_int()
+            self._check(lib().fscc_mixed_config(self._h, k, ctypes.byref(c)))
+            if c.value >= 0:
+                out.append((o["name"], c.value))
+        return out
 
     def _check(self, st):
         if st != 0:
@@ -264,6 +298,22 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
     return dict(E=E, iters=k, converged=converged, history=hist)
 
 
+def solve_mixed(ctx, t1, t2, switch_tol=1e-6, tol=1e-10, maxit=200, ndiis=6, log=None):
+    """Two-stage solve: iterate with the context's split precision until
+    max|step| < switch_tol, then continue in FP64 (fresh DIIS subspace) to tol.
+    The context's precision is restored on return.  Returns dict(E, iters,
+    split_iters, fp64_iters, converged, history)."""
+    prec = ctx.precision()
+    try:
+        a = solve(ctx, t1, t2, tol=switch_tol, maxit=maxit, ndiis=ndiis, log=log)
+        ctx.set_precision("fp64")
+        b = solve(ctx, t1, t2, tol=tol, maxit=maxit, ndiis=ndiis, log=log)
+    finally:
+        ctx.set_precision(prec)
+    return dict(E=b["E"], iters=a["iters"] + b["iters"], split_iters=a["iters"], fp64_iters=b["iters"],
+                converged=b["converged"], history=a["history"] + b["history"])
+
+
 def zgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=False, alpha=1.0, beta=0,
           cfg=-1, bk=16, allow_split=True, stream=None):
     """One complex GEMM through the library's grouped MFMA kernel (fscc_zgemm)."""
@@ -275,3 +325,16 @@ def zgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=Fals
                          int(beta), int(allow_split), ctypes.c_void_p(st.cuda_stream))
     if r != 0:
         raise FsccError(r, "fscc_zgemm failed")
+
+
+def zgemm_split(A, B, C, M, N, K, lda, ldb, ldc, precision="split_bf16", cfg=0, tA=False, tB=False, cA=False,
+                cB=False, alpha=1.0, beta=0, stream=None):
+    """One complex GEMM through the split-precision kernel (fscc_zgemm_split)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    alpha = complex(alpha)
+    r = lib().fscc_zgemm_split(_prec(precision), int(cfg), int(tA), int(tB), int(cA), int(cB), int(M), int(N), int(K),
+                               _dev_ptr(A), int(lda), _dev_ptr(B), int(ldb), _dev_ptr(C), int(ldc), alpha.real,
+                               alpha.imag, int(beta), ctypes.c_void_p(st.cuda_stream))
+    if r != 0:
+        raise FsccError(r, "fscc_zgemm_split failed")

@@ -19,6 +19,28 @@ using namespace fscc;
 
 namespace {
 
+// one operand of a split-precision GEMM: its piece planes and how to fill them
+struct SplitDev {
+    SplitProb* sp = nullptr;
+    int nsp = 0;
+    long long max_chunks = 0;
+    void* planes = nullptr;
+    long long plane = 0;      // elements per plane
+    bool conj = false;
+    bool constant = false;    // integral-derived: split once, then reused
+    bool valid = false;
+};
+
+// split-precision form of one GEMM op (FSCC_SPLIT_BF16 / FSCC_SPLIT_FP32)
+struct MixedDev {
+    int prec = 0;
+    int cfg = 0;
+    MProb* probs = nullptr;
+    ZTile* tiles = nullptr;
+    int ntiles = 0;
+    SplitDev a, b;
+};
+
 struct GemmDev {
     ZProb* probs = nullptr;
     ZTile* tiles = nullptr;
@@ -32,6 +54,7 @@ struct GemmDev {
     int nred = 0;
     int maxMN = 0;
     double2* work = nullptr;
+    MixedDev* mx = nullptr;   // present for the ops that may run in split precision
 };
 
 struct HipError : std::runtime_error {
@@ -86,6 +109,7 @@ struct fscc_ctx {
     double* eout = nullptr;
     double2* rs_tmp = nullptr; // residual scratch for fscc_heff
     bool prof = false;
+    int prec = FSCC_FP64;
     std::string err;
 
     int64_t n1() const { return plan.L_T1.total; }
@@ -99,12 +123,22 @@ struct fscc_ctx {
         return p;
     }
 
+    static void free_mixed(MixedDev*& m) {
+        if (!m) return;
+        void* ps[] = {m->probs, m->tiles, m->a.sp, m->a.planes, m->b.sp, m->b.planes};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        delete m;
+        m = nullptr;
+    }
+
     static void free_list(OpList& L) {
         for (auto& g : L.g) {
             if (g.probs) (void)hipFree(g.probs);
             if (g.tiles) (void)hipFree(g.tiles);
             if (g.reds) (void)hipFree(g.reds);
             if (g.work) (void)hipFree(g.work);
+            free_mixed(g.mx);
         }
         for (auto& e : L.ev)
             if (e) (void)hipEventDestroy(e);
@@ -159,7 +193,9 @@ struct fscc_ctx {
                 int beta = beta_override >= 0 ? beta_override : o.beta;
                 const double2* Ap = A_override ? A_override : B(o.src);
                 double2* Cp = C_override ? C_override : B(o.dst);
-                if (!g.split) {
+                if (prec != FSCC_FP64 && g.mx && g.mx->prec == prec && !(A_override && g.mx->a.constant)) {
+                    e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
+                } else if (!g.split) {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
                                      o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role);
                 } else {
@@ -173,6 +209,24 @@ struct fscc_ctx {
             }
         }
         hip_check(e, o.name.c_str());
+    }
+
+    hipError_t split_operand(SplitDev& d, const double2* src, bool bf16) {
+        if (d.constant && d.valid) return hipSuccess;
+        hipError_t e = launch_split(bf16, src, d.planes, d.plane, d.sp, d.nsp, d.max_chunks, d.conj ? 1 : 0, st);
+        if (e == hipSuccess && d.constant) d.valid = true;
+        return e;
+    }
+
+    hipError_t run_mixed(const Op& o, MixedDev& m, const double2* A, const double2* Bm, double2* C, int beta) {
+        const bool bf = m.prec == FSCC_SPLIT_BF16;
+        hipError_t e = split_operand(m.a, A, bf);
+        if (e == hipSuccess) e = split_operand(m.b, Bm, bf);
+        if (e == hipSuccess)
+            e = launch_zgemm_split(bf, m.cfg, m.a.planes, m.a.plane, m.b.planes, m.b.plane, C, m.probs, m.tiles,
+                                   m.ntiles, o.alpha.real(), o.alpha.imag(), beta, st,
+                                   o.name == "pp-ladder" ? 1 : 2);
+        return e;
     }
 
     void run_list(OpList& L, bool timed) {
@@ -251,12 +305,128 @@ int pick_cfg(const Op& o) {
     return best;
 }
 
+// Workgroups of one launch are handed to the 8 XCDs round-robin (block b runs on
+// XCD b % 8) and each XCD has its own L2.  Permute the logical tile sequence so
+// that 8 consecutive logical tiles (which share operand panels) land on one XCD
+// in consecutive dispatch slots: block 64u + 8v + x takes logical tile
+// 64u + 8x + v.  A trailing partial round keeps the identity order.
+std::vector<ZTile> xcd_order(const std::vector<ZTile>& logical) {
+    const size_t n = logical.size(), full = n / 64 * 64;
+    std::vector<ZTile> out(logical);
+    for (size_t b = 0; b < full; ++b) {
+        const size_t u = b / 64, v = (b / 8) % 8, x = b % 8;
+        out[b] = logical[64 * u + 8 * x + v];
+    }
+    return out;
+}
+
 void free_gemm(GemmDev& g) {
     if (g.probs) (void)hipFree(g.probs);
     if (g.tiles) (void)hipFree(g.tiles);
     if (g.reds) (void)hipFree(g.reds);
     if (g.work) (void)hipFree(g.work);
+    fscc_ctx::free_mixed(g.mx);
     g = GemmDev();
+}
+
+// The contractions that may run in split precision: the particle-particle
+// ladder and the two ring GEMM sets (W_mbej's T2 part and the ring itself).
+bool mixed_eligible(const Op& o) {
+    return o.kind == OP_GEMM && (o.name == "pp-ladder" || o.name == "W.U" || o.name == "ring");
+}
+
+long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+// Split-precision plan of one GEMM op: piece-plane descriptors of both
+// operands (A rows = M; B rows = N, both with the contraction index as the
+// panel depth) and the tile list of the split kernel.
+MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg) {
+    MixedDev* m = new MixedDev();
+    try {
+        m->prec = prec;
+        m->cfg = cfg;
+        const int es = prec == FSCC_SPLIT_BF16 ? 2 : 4, npl = prec == FSCC_SPLIT_BF16 ? 6 : 4;
+        std::vector<SplitProb> sa, sb;
+        std::vector<MProb> pr;
+        long long oa = 0, ob = 0, cha = 0, chb = 0;
+        for (auto& p : o.probs) {
+            const int kp = (int)round_up(p.K, 32);
+            const int ra = (int)round_up(std::max(p.M, 1), 64), rb = (int)round_up(std::max(p.N, 1), 64);
+            sa.push_back(SplitProb{p.a_off, oa, p.M, p.K, p.lda, o.tA ? 1 : 0, ra, kp});
+            sb.push_back(SplitProb{p.b_off, ob, p.N, p.K, p.ldb, o.tB ? 0 : 1, rb, kp});
+            pr.push_back(MProb{oa, ob, p.c_off, p.M, p.N, kp, p.ldc, ra, rb});
+            cha = std::max(cha, (long long)ra * kp / 8);
+            chb = std::max(chb, (long long)rb * kp / 8);
+            oa += (long long)ra * kp;
+            ob += (long long)rb * kp;
+        }
+        int bm, bn;
+        mcfg_tile(cfg, &bm, &bn);
+        std::vector<ZTile> tl;
+        for (size_t q = 0; q < pr.size(); ++q) {
+            const int mt = (pr[q].M + bm - 1) / bm, nt = (pr[q].N + bn - 1) / bn;
+            for (int mg = 0; mg < mt; mg += 8)
+                for (int n = 0; n < nt; ++n)
+                    for (int mm = mg; mm < std::min(mt, mg + 8); ++mm) tl.push_back(ZTile{(int)q, mm * bm, n * bn, 0});
+        }
+        std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& x, const ZTile& y) { return pr[x.prob].Kp > pr[y.prob].Kp; });
+        tl = xcd_order(tl);
+        m->ntiles = (int)tl.size();
+        auto up = [&](const void* h, size_t bytes) {
+            void* d = c->dalloc(std::max<size_t>(bytes, 16));
+            if (bytes) hip_check(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice), "mixed plan upload");
+            return d;
+        };
+        m->probs = (MProb*)up(pr.data(), pr.size() * sizeof(MProb));
+        m->tiles = (ZTile*)up(tl.data(), tl.size() * sizeof(ZTile));
+        m->a.sp = (SplitProb*)up(sa.data(), sa.size() * sizeof(SplitProb));
+        m->b.sp = (SplitProb*)up(sb.data(), sb.size() * sizeof(SplitProb));
+        m->a.nsp = (int)sa.size();
+        m->b.nsp = (int)sb.size();
+        m->a.max_chunks = cha;
+        m->b.max_chunks = chb;
+        m->a.plane = round_up(std::max(oa, 1LL), 64);
+        m->b.plane = round_up(std::max(ob, 1LL), 64);
+        m->a.planes = c->dalloc((size_t)m->a.plane * npl * es);
+        m->b.planes = c->dalloc((size_t)m->b.plane * npl * es);
+        m->a.conj = o.cA;
+        m->b.conj = o.cB;
+        m->a.constant = c->plan.bufs[o.src].kind == BUF_CONST;
+        m->b.constant = c->plan.bufs[o.src2].kind == BUF_CONST;
+    } catch (...) {
+        fscc_ctx::free_mixed(m);
+        throw;
+    }
+    return m;
+}
+
+// Default split-kernel tile: the largest one that still gives the launch
+// enough workgroups to cover the chip.
+int pick_mcfg(const Op& o) {
+    for (int cfg : {MCFG_64x64, MCFG_64x32, MCFG_32x64, MCFG_32x32}) {
+        int bm, bn;
+        mcfg_tile(cfg, &bm, &bn);
+        long long t = 0;
+        for (auto& p : o.probs) t += (long long)((p.M + bm - 1) / bm) * ((p.N + bn - 1) / bn);
+        if (t >= 512) return cfg;
+    }
+    return MCFG_32x32;
+}
+
+// Switch the eligible GEMM ops of the (0h,0p) residual to precision `prec`
+// (planning their split form on first use); FP64 keeps the plans.
+void apply_precision(fscc_ctx* c, int prec) {
+    if (prec != FSCC_FP64) {
+        std::vector<Op>& ops = *c->L00.ops;
+        for (size_t k = 0; k < ops.size(); ++k) {
+            if (!mixed_eligible(ops[k])) continue;
+            GemmDev& g = c->L00.g[k];
+            if (g.mx && g.mx->prec == prec) continue;
+            fscc_ctx::free_mixed(g.mx);
+            g.mx = plan_mixed(c, ops[k], prec, pick_mcfg(ops[k]));
+        }
+    }
+    c->prec = prec;
 }
 
 void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split) {
@@ -305,11 +475,17 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
             maxMN = std::max(maxMN, p.M * p.N);
         }
     }
-    for (size_t q = 0; q < pr.size(); ++q)
-        for (int m0 = 0; m0 < pr[q].M; m0 += bm)
-            for (int n0 = 0; n0 < pr[q].N; n0 += bn) tl.push_back(ZTile{(int)q, m0, n0, 0});
+    // Logical tile order inside a problem: bands of up to 8 row tiles, the band's
+    // row tiles innermost, so neighbouring tiles share one column panel of B.
+    for (size_t q = 0; q < pr.size(); ++q) {
+        const int mt = (pr[q].M + bm - 1) / bm, nt = (pr[q].N + bn - 1) / bn;
+        for (int mg = 0; mg < mt; mg += 8)
+            for (int n = 0; n < nt; ++n)
+                for (int m = mg; m < std::min(mt, mg + 8); ++m) tl.push_back(ZTile{(int)q, m * bm, n * bn, 0});
+    }
     // longest-K tiles first (uneven symmetry blocks)
     std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) { return pr[a.prob].K > pr[b.prob].K; });
+    tl = xcd_order(tl);
     g.ntiles = (int)tl.size();
     g.probs = (ZProb*)c->dalloc(std::max<size_t>(1, pr.size()) * sizeof(ZProb));
     g.tiles = (ZTile*)c->dalloc(std::max<size_t>(1, tl.size()) * sizeof(ZTile));
@@ -377,7 +553,7 @@ const char* fscc_last_error(const fscc_ctx* ctx) { return ctx ? ctx->err.c_str()
 fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_stream, fscc_ctx** out) {
     if (!sys || !out) return FSCC_EINVAL;
     *out = nullptr;
-    if (prec != FSCC_FP64) return FSCC_EINVAL;
+    if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16) return FSCC_EINVAL;
     if (sys->nocc < 0 || sys->nvirt < 0 || sys->nirrep < 1 || !sys->irrep || !sys->eps) return FSCC_EINVAL;
     if (sys->nact < 0 || (sys->nact > 0 && !sys->active)) return FSCC_EINVAL;
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
@@ -447,6 +623,7 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         c->epart = (double*)c->dalloc(2048 * sizeof(double));
         c->eout = (double*)c->dalloc(4 * sizeof(double));
         hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+        apply_precision(c, prec);
         return FSCC_OK;
     });
     if (s != FSCC_OK) {
@@ -803,8 +980,11 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (size_t k = 0; k < L->ops->size(); ++k) {
                     const Op& o = (*L->ops)[k];
                     if (o.kind != OP_GEMM) continue;
+                    MixedDev* keep = L->g[k].mx;
+                    L->g[k].mx = nullptr;
                     free_gemm(L->g[k]);
                     plan_gemm(ctx, o, L->g[k], pick_cfg(o), 16, true);
+                    L->g[k].mx = keep;
                 }
             return FSCC_OK;
         }
@@ -853,6 +1033,8 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             for (size_t k = 0; k < L->ops->size(); ++k) {
                 const Op& o = (*L->ops)[k];
                 if (o.kind != OP_GEMM || o.flops < 1e7) continue;
+                MixedDev* keep = L->g[k].mx;   // the FP64 candidates are timed without it
+                L->g[k].mx = nullptr;
                 GemmDev best = L->g[k];
                 float best_ms = time_op(o, &best);
                 for (int cfg = 0; cfg < ZCFG_N; ++cfg)
@@ -880,6 +1062,27 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                             }
                         }
                 L->g[k] = best;
+                L->g[k].mx = keep;
+            }
+        if (ctx->prec != FSCC_FP64)
+            for (size_t k = 0; k < ctx->L00.ops->size(); ++k) {
+                const Op& o = (*ctx->L00.ops)[k];
+                GemmDev& g = ctx->L00.g[k];
+                if (!mixed_eligible(o) || !g.mx) continue;
+                float best_ms = time_op(o, &g);
+                for (int cfg = 0; cfg < MCFG_N; ++cfg) {
+                    if (cfg == g.mx->cfg) continue;
+                    MixedDev* old = g.mx;
+                    g.mx = plan_mixed(ctx, o, ctx->prec, cfg);
+                    float ms = time_op(o, &g);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        fscc_ctx::free_mixed(old);
+                    } else {
+                        fscc_ctx::free_mixed(g.mx);
+                        g.mx = old;
+                    }
+                }
             }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -887,6 +1090,71 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         (void)hipFree(tmp);
         return FSCC_OK;
     });
+}
+
+fscc_status fscc_set_precision(fscc_ctx* ctx, fscc_precision prec) {
+    if (!ctx) return FSCC_EINVAL;
+    if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16)
+        return fail(ctx, FSCC_EINVAL, "unknown precision");
+    return guarded(ctx, [&]() -> fscc_status {
+        apply_precision(ctx, prec);
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_get_precision(const fscc_ctx* ctx, int* prec) {
+    if (!ctx || !prec) return FSCC_EINVAL;
+    *prec = ctx->prec;
+    return FSCC_OK;
+}
+
+fscc_status fscc_mixed_config(const fscc_ctx* ctx, int k, int* cfg) {
+    if (!ctx || !cfg) return FSCC_EINVAL;
+    OpList* L;
+    int j;
+    if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
+    const GemmDev& g = L->g[j];
+    *cfg = (g.mx && g.mx->prec == ctx->prec && ctx->prec != FSCC_FP64) ? g.mx->cfg : -1;
+    return FSCC_OK;
+}
+
+fscc_status fscc_zgemm_split(int prec, int cfg, int tA, int tB, int cA, int cB, int M, int N, int K,
+                             const fscc_c128* A, int lda, const fscc_c128* B, int ldb, fscc_c128* C, int ldc,
+                             double alpha_re, double alpha_im, int beta, void* hip_stream) {
+    if (prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16) return FSCC_EINVAL;
+    if (M < 0 || N < 0 || K < 0 || cfg < 0 || cfg >= MCFG_N) return FSCC_EINVAL;
+    if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
+    if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
+    if (M == 0 || N == 0) return FSCC_OK;
+    fscc_ctx* c = new (std::nothrow) fscc_ctx();
+    if (!c) return FSCC_ENOMEM;
+    c->st = (hipStream_t)hip_stream;
+    fscc_status s = guarded(c, [&]() -> fscc_status {
+        // a one-op plan with two caller buffers (ids 0 and 1), neither constant
+        c->plan.bufs.push_back(BufDesc{"A", 0, BUF_SCRATCH});
+        c->plan.bufs.push_back(BufDesc{"B", 0, BUF_SCRATCH});
+        Op o;
+        o.kind = OP_GEMM;
+        o.name = "zgemm";
+        o.src = 0;
+        o.src2 = 1;
+        o.tA = tA != 0;
+        o.tB = tB != 0;
+        o.cA = cA != 0;
+        o.cB = cB != 0;
+        o.alpha = cplx(alpha_re, alpha_im);
+        o.beta = beta ? 1 : 0;
+        o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
+        MixedDev* m = plan_mixed(c, o, prec, cfg);
+        c->prec = prec;
+        hipError_t e = c->run_mixed(o, *m, (const double2*)A, (const double2*)B, (double2*)C, o.beta);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        fscc_ctx::free_mixed(m);
+        hip_check(e, "zgemm_split");
+        return FSCC_OK;
+    });
+    delete c;
+    return s;
 }
 
 fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int* split) {

@@ -30,6 +30,33 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                         int cB, hipStream_t st, int role = 0);
 
+// ---- compensated mixed-precision GEMM (kernels_split.hip)
+// element (r, k) of a rows x cols operand: src[src_off + r*ld + k] (trans = 0)
+// or src[src_off + k*ld + r] (trans = 1); written as piece planes in the
+// panel layout [kpad/32][rows_pad][32] at dst_off (rows_pad % 64 == 0,
+// kpad % 32 == 0, zero fill outside rows x cols).
+struct SplitProb {
+    long long src_off, dst_off;
+    int rows, cols, ld, trans, rows_pad, kpad;
+};
+// bf16: 6 planes (piece-major, re/im), fp32: 4 planes; `plane` = elements per
+// plane (multiple of 64); conj negates the imaginary pieces.  max_chunks =
+// max over problems of rows_pad*kpad/8.
+hipError_t launch_split(bool bf16, const double2* src, void* dst, long long plane, const SplitProb* sp, int nprob,
+                        long long max_chunks, int conj, hipStream_t st);
+// C(m,n) = alpha * sum_k A(m,k) B(n,k) + beta*C(m,n), A/B in split planes
+// (a_off/b_off: element offsets of the problem inside a plane, rows_a/rows_b
+// the panel row counts, Kp the padded depth).
+struct MProb {
+    long long a_off, b_off, c_off;
+    int M, N, Kp, ldc, rows_a, rows_b;
+};
+enum MCfg { MCFG_64x64 = 0, MCFG_64x32, MCFG_32x64, MCFG_32x32, MCFG_N };
+void mcfg_tile(int cfg, int* bm, int* bn);
+hipError_t launch_zgemm_split(bool bf16, int cfg, const void* A, long long sA, const void* B, long long sB, double2* C,
+                              const MProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta,
+                              hipStream_t st, int role = 0);
+
 // split-K second pass: C = alpha * sum_s W[w_off + s*M*N + m*N + n] + beta*C
 struct ZRed {
     long long c_off, w_off;
