@@ -33,9 +33,13 @@ def log(*a):
 
 
 def kernel_source_sha():
+    """Hash of the library sources that decide a kernel's memory traffic
+    (kernels, tile lists, plans)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2004_03682_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    d = os.path.join(ROOT, "paper_2004_03682_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -83,6 +87,118 @@ def cpu_baseline(sysm, buffers):
                 energy_re=float(E.real))
 
 
+def time_to(hist, E_ref, t_start, thr=1e-8):
+    """(iterations, seconds) until |E_k - E_ref| < thr holds for every later iterate."""
+    k = next((k for k in range(len(hist)) if all(abs(h["E"] - E_ref) < thr for h in hist[k:])), None)
+    if k is None:
+        return None, None
+    return k + 1, round(hist[k]["time"] - t_start, 5)
+
+
+def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
+    """FP64 against split-BF16 / split-FP32 ladder + ring contractions:
+    per-iteration time, per-result error and time to |E - E_inf| < 1e-8 Eh
+    (E_inf = the FP64 converged energy), all from the same zero start."""
+    u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device=dev)
+    u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device=dev)
+    q1, q2 = torch.empty_like(u1), torch.empty_like(u2)
+    out = {}
+    ctx.set_precision("fp64")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    a = F.solve(ctx, u1, u2, tol=1e-10, maxit=300)
+    k8, s8 = time_to(a["history"], E_inf, ts)
+    out["fp64"] = {"iterations": a["iters"], "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
+                   "seconds_to_converged": round(a["history"][-1]["time"] - ts, 5)}
+    log(f"fp64 from zero: {a['iters']} iterations, |dE|<1e-8 after {k8} ({s8}s)")
+    # reference residual at the MP2 amplitudes (first Jacobi step from zero)
+    u1.zero_()
+    u2.zero_()
+    ctx.diis_reset(1)
+    ctx.build_residual(u1, u2, q1, q2)
+    ctx.update_amplitudes(u1, u2, q1, q2)
+    ctx.build_residual(u1, u2, q1, q2)
+    R1, R2 = q1.clone(), q2.clone()
+    Rmax = max(float(R1.abs().max()), float(R2.abs().max()))
+    mp2 = (u1.clone(), u2.clone())
+    for prec in ("split_bf16", "split_fp32"):
+        ctx.set_precision(prec)
+        t0 = time.perf_counter()
+        ctx.autotune(2)
+        cfgs = {n: {0: "64x64", 1: "64x32", 2: "32x64", 3: "32x32"}[c] for n, c in ctx.mixed_configs()}
+        log(f"{prec}: split tiles {cfgs} (tuned in {time.perf_counter() - t0:.1f}s)")
+        u1.copy_(mp2[0])
+        u2.copy_(mp2[1])
+        ctx.build_residual(u1, u2, q1, q2)
+        err = max(float((q1 - R1).abs().max()), float((q2 - R2).abs().max())) / Rmax
+        # per-iteration time (profiled like the FP64 line)
+        u1.zero_()
+        u2.zero_()
+        ctx.diis_reset(6)
+        for _ in range(args.warmup):
+            ctx.build_residual(u1, u2, q1, q2)
+            ctx.update_amplitudes(u1, u2, q1, q2)
+            ctx.energy(u1, u2)
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        st = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.build_residual(u1, u2, q1, q2)
+            ctx.update_amplitudes(u1, u2, q1, q2)
+            ctx.energy(u1, u2)
+        torch.cuda.synchronize()
+        per_it = (time.perf_counter() - st) / args.steps
+        ops = {o["name"]: o for o in ctx.op_times()}
+        ctx.profile(False)
+        mfac = 6.0 if prec == "split_bf16" else 3.0
+        peak = 2500.0 if prec == "split_bf16" else 157.3
+        lad = ops["pp-ladder"]
+        lad_ms = lad["ms"] / max(1, lad["calls"])
+        split_ops = {}
+        for n in ("pp-ladder", "W.U", "ring"):
+            o = ops[n]
+            ms = o["ms"] / max(1, o["calls"])
+            split_ops[n] = {"ms_per_call": round(ms, 4),
+                            "fp64_equivalent_tflops": round(o["flops"] / (ms * 1e-3) / 1e12, 2),
+                            "issued_mfma_tflops": round(mfac * o["flops"] / (ms * 1e-3) / 1e12, 2)}
+        rec = {"s_per_iteration": round(per_it, 6), "residual_rel_error_at_mp2": err, "split_tiles": cfgs,
+               "split_ops": split_ops,
+               "ladder_issued_mfma_frac": round(mfac * lad["flops"] / (lad_ms * 1e-3) / 1e12 / peak, 4),
+               "mfma_peak_tflops": peak, "issued_products_per_complex_product": mfac * 4}
+        # two-stage convergence from zero: split until max|step| < 1e-7, then FP64
+        for sw in (1e-6, 1e-7):
+            u1.zero_()
+            u2.zero_()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            b = F.solve_mixed(ctx, u1, u2, switch_tol=sw, tol=1e-10, maxit=300)
+            k8, s8 = time_to(b["history"], E_inf, ts)
+            rec[f"two_stage_switch_{sw:g}"] = {
+                "split_iterations": b["split_iters"], "fp64_iterations": b["fp64_iters"],
+                "iterations_to_1e-8": k8, "seconds_to_1e-8": s8, "converged": b["converged"],
+                "seconds_to_converged": round(b["history"][-1]["time"] - ts, 5),
+                "final_dE": abs(b["E"] - E_inf)}
+            log(f"{prec}: two-stage (switch {sw:g}): {b['split_iters']}+{b['fp64_iters']} iterations, "
+                f"|dE|<1e-8 after {k8} ({s8}s), final |dE| = {abs(b['E'] - E_inf):.2e}")
+        # split precision alone: where the iteration settles
+        u1.zero_()
+        u2.zero_()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        c = F.solve(ctx, u1, u2, tol=1e-12, maxit=120)
+        k8, s8 = time_to(c["history"], E_inf, ts)
+        rec["split_only"] = {"iterations": c["iters"], "last_max_step": c["history"][-1]["dmax"],
+                             "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
+                             "dE_vs_fp64": abs(c["E"] - E_inf),
+                             "max_abs_dt1_vs_fp64": float((u1 - tconv[0]).abs().max()),
+                             "max_abs_dt2_vs_fp64": float((u2 - tconv[1]).abs().max())}
+        log(f"{prec}: split-only after {c['iters']} iterations: max|step| {c['history'][-1]['dmax']:.2e}, "
+            f"|dE| = {abs(c['E'] - E_inf):.2e}; {per_it * 1e3:.3f} ms/iteration, residual rel. error {err:.2e}")
+        out[prec] = rec
+    ctx.set_precision("fp64")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +206,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) sector")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -203,7 +320,7 @@ def main():
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,
     }
-    if args.converge or not args.no_fs01:
+    if args.converge or not args.no_fs01 or not args.no_mixed:
         # continue to convergence, record |E_k - E_inf| < 1e-8 Eh
         it = args.warmup + args.steps
         es = [h[1] for h in hist]
@@ -216,6 +333,8 @@ def main():
         result["converged_iterations"] = it
         result["iterations_to_1e-8"] = k8
         result["converged_energy"] = [E.real, E.imag]
+    if not args.no_mixed:
+        result["precision"] = precision_study(ctx, F, torch, dev, E, (t1, t2), args, log)
     if not args.no_fs01:
         # (0h,1p) sector with the 6 lowest virtual spinors active, on the converged T
         ctx.prepare_sector(t1, t2)

@@ -195,8 +195,11 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * of Fig. 4 have very uneven shapes).  level 1: every candidate tile shape,
  * K depth (16/32) and split-K choice of each GEMM operation is timed on the
  * device (HIP events on the context's stream) and the fastest is kept;
- * level 0: restore the cost-model defaults chosen at fscc_create.  Results
- * are numerically equivalent (FP64, summation order may change). */
+ * in a split precision (fscc_set_precision) level 1 also times the split
+ * kernel's tile shapes of the split operations; level 2 times only those;
+ * level 0: restore the cost-model defaults chosen at fscc_create (FP64
+ * shapes).  Results are numerically equivalent (summation order may
+ * change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
 
 /* Chosen configuration of operation k (cfg = tile shape id or -1 if k is not

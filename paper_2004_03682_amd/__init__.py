@@ -272,15 +272,19 @@ def solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=6, log=None):
     return dict(heff=h, eig=w, iters=k, converged=converged)
 
 
-def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
+def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True):
     """Jacobi + DIIS iterations on the device until max|step| < tol.
 
     Each iteration: fscc_build_residual -> fscc_update_amplitudes ->
-    fscc_energy.  Returns dict(E, iters, converged, history)."""
+    fscc_energy.  Returns dict(E, iters, converged, history); history entries
+    carry the host time after the iteration's energy (which synchronises).
+    reset_diis=False continues with the context's current DIIS subspace."""
+    import time
     import torch
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
-    ctx.diis_reset(ndiis)
+    if reset_diis:
+        ctx.diis_reset(ndiis)
     hist = []
     E = 0j
     converged = False
@@ -289,7 +293,7 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
         ctx.build_residual(t1, t2, r1, r2)
         dmax = ctx.update_amplitudes(t1, t2, r1, r2)
         E = ctx.energy(t1, t2)
-        hist.append(dict(iter=k, E=E, dmax=dmax))
+        hist.append(dict(iter=k, E=E, dmax=dmax, time=time.perf_counter()))
         if log:
             log(f"iter {k:3d}  E = {E.real:+.14f} {E.imag:+.3e}i  max|step| = {dmax:.3e}")
         if dmax < tol:
@@ -298,16 +302,16 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, etol=None):
     return dict(E=E, iters=k, converged=converged, history=hist)
 
 
-def solve_mixed(ctx, t1, t2, switch_tol=1e-6, tol=1e-10, maxit=200, ndiis=6, log=None):
+def solve_mixed(ctx, t1, t2, switch_tol=1e-6, tol=1e-10, maxit=200, ndiis=6, log=None, keep_diis=True):
     """Two-stage solve: iterate with the context's split precision until
-    max|step| < switch_tol, then continue in FP64 (fresh DIIS subspace) to tol.
-    The context's precision is restored on return.  Returns dict(E, iters,
-    split_iters, fp64_iters, converged, history)."""
+    max|step| < switch_tol, then continue in FP64 to tol (keeping the DIIS
+    subspace unless keep_diis=False).  The context's precision is restored on
+    return.  Returns dict(E, iters, split_iters, fp64_iters, converged, history)."""
     prec = ctx.precision()
     try:
         a = solve(ctx, t1, t2, tol=switch_tol, maxit=maxit, ndiis=ndiis, log=log)
         ctx.set_precision("fp64")
-        b = solve(ctx, t1, t2, tol=tol, maxit=maxit, ndiis=ndiis, log=log)
+        b = solve(ctx, t1, t2, tol=tol, maxit=maxit, ndiis=ndiis, log=log, reset_diis=not keep_diis)
     finally:
         ctx.set_precision(prec)
     return dict(E=b["E"], iters=a["iters"] + b["iters"], split_iters=a["iters"], fp64_iters=b["iters"],

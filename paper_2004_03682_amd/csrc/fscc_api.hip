@@ -971,7 +971,7 @@ fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, in
 // context's own buffers and zeroed temporary amplitude buffers are used.
 fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
     if (!ctx) return FSCC_EINVAL;
-    if (level < 0 || level > 1) return fail(ctx, FSCC_EINVAL, "autotune level must be 0 or 1");
+    if (level < 0 || level > 2) return fail(ctx, FSCC_EINVAL, "autotune level must be 0, 1 or 2");
     return guarded(ctx, [&]() -> fscc_status {
         Plan& P = ctx->plan;
         std::vector<OpList*> lists = {&ctx->L00, &ctx->L01};
@@ -1030,7 +1030,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             return best;
         };
         for (OpList* L : lists)
-            for (size_t k = 0; k < L->ops->size(); ++k) {
+            for (size_t k = 0; k < L->ops->size() && level == 1; ++k) {
                 const Op& o = (*L->ops)[k];
                 if (o.kind != OP_GEMM || o.flops < 1e7) continue;
                 MixedDev* keep = L->g[k].mx;   // the FP64 candidates are timed without it
