@@ -237,3 +237,74 @@ def class_buffer(sysm: System, cls: str, out: np.ndarray | None = None):
         views[key] = v
         off += sz
     return out, views
+
+
+# --------------------------------------------------------------------------
+# device-side generation (same definition, evaluated on the GPU)
+
+_SRC_GPU = os.path.join(_HERE, "fsgen_gpu.hip")
+_LIB_GPU = os.path.join(_HERE, "libfsgen_gpu.so")
+_lib_gpu = None
+_GEN_BLOCK = np.dtype([("off", "<i8"), ("n", "<i4", (4,)), ("mem", "<i4", (4,))], align=True)
+
+
+def build_gpu(force: bool = False) -> str:
+    """Compile libfsgen_gpu.so (hipcc, gfx950)."""
+    if force or not os.path.exists(_LIB_GPU) or os.path.getmtime(_LIB_GPU) < os.path.getmtime(_SRC_GPU):
+        tmp = _LIB_GPU + ".tmp%d" % os.getpid()
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-Wno-unused-command-line-argument", "-o", tmp, _SRC_GPU],
+                              stderr=subprocess.DEVNULL)
+        os.replace(tmp, _LIB_GPU)
+    return _LIB_GPU
+
+
+def _get_lib_gpu():
+    global _lib_gpu
+    if _lib_gpu is None:
+        if not os.path.exists(_LIB_GPU):
+            raise ImportError(f"{_LIB_GPU} is missing: build it with fsgen.build_gpu()")
+        lib = ctypes.CDLL(_LIB_GPU)
+        vp = ctypes.c_void_p
+        lib.fsgen_gpu_class.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_int, vp, ctypes.c_int, vp,
+                                        ctypes.c_int, vp, ctypes.c_int, vp, vp]
+        lib.fsgen_gpu_class.restype = ctypes.c_int
+        _lib_gpu = lib
+    return _lib_gpu
+
+
+def class_buffer_gpu(sysm: System, cls: str, out=None, stream=None):
+    """class_buffer() generated in device memory: returns a torch complex128
+    CUDA tensor (or fills `out`).  Values agree with the host generator to a
+    few ulps (device transcendental functions)."""
+    import torch
+    tuples = class_tuples(sysm, cls)
+    total = int(sum(int(np.prod(s)) for _, s in tuples))
+    if out is None:
+        out = torch.empty(max(total, 1), dtype=torch.complex128, device="cuda")[:total]
+    assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous() and out.numel() == total
+    mem, moff = [], {}
+    for X in "OV":
+        for g in range(sysm.nirrep):
+            moff[(X, g)] = len(mem)
+            mem.extend(int(v) for v in sysm.members(X, g))
+    blocks = np.zeros(len(tuples), _GEN_BLOCK)
+    off = 0
+    for k, (key, shp) in enumerate(tuples):
+        blocks[k]["off"] = off
+        blocks[k]["n"] = shp
+        blocks[k]["mem"] = [moff[(cls[i], key[i])] for i in range(4)]
+        off += int(np.prod(shp))
+    keep = np.array([int(np.prod(s)) > 0 for _, s in tuples], bool)
+    blocks = np.ascontiguousarray(blocks[keep])
+    mem = np.ascontiguousarray(np.array(mem if mem else [0], np.int32))
+    irr = np.ascontiguousarray(sysm.irrep, dtype=np.int32)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    if total:
+        rc = _get_lib_gpu().fsgen_gpu_class(sysm.seed, sysm.sigma, sysm.n, irr.ctypes.data, sysm.nirrep,
+                                            blocks.ctypes.data, len(blocks), mem.ctypes.data, len(mem),
+                                            out.data_ptr(), st.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"fsgen_gpu_class failed (HIP error {rc})")
+    return out

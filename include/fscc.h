@@ -260,6 +260,60 @@ fscc_status fscc_zgemm_split(int prec, int cfg, int tA, int tB, int cA, int cB, 
 void fscc_destroy(fscc_ctx *ctx);
 const char *fscc_last_error(const fscc_ctx *ctx);
 
+/* ---- batches of independent systems (the block-loop structure of Fig. 4
+ * extended over systems) -------------------------------------------------
+ * A batch holds nsys (0h,0p) systems (nact must be 0).  Their residual plans
+ * are concatenated buffer by buffer, so every contraction runs as ONE grouped
+ * GEMM launch over the symmetry blocks of all systems, and every reorder and
+ * elementwise step as one launch over the concatenation.  Amplitude and
+ * residual vectors of a batch are the concatenations of the systems' packed
+ * vectors (fscc_layout order): T1 of system 0, T1 of system 1, ... and
+ * likewise T2; fscc_batch_segment gives each system's offsets.  Each system
+ * keeps its own Jacobi + DIIS subspace on the device; once its max|step|
+ * falls below tol it is frozen (amplitudes no longer updated, its GEMM tiles
+ * skipped) while the others continue.  A batch owns its device memory and is
+ * not thread-safe; calls are asynchronous on hip_stream unless stated. */
+typedef struct fscc_batch fscc_batch;
+
+/* sys[nsys] as for fscc_create.  Plans are built in parallel host threads. */
+fscc_status fscc_batch_create(const fscc_system *sys, int nsys, fscc_precision prec, void *hip_stream,
+                              fscc_batch **out);
+void fscc_batch_destroy(fscc_batch *b);
+const char *fscc_batch_last_error(const fscc_batch *b);
+
+/* Totals of the concatenated T1 / T2 vectors, and system s's segments. */
+fscc_status fscc_batch_sizes(const fscc_batch *b, size_t *n1, size_t *n2);
+fscc_status fscc_batch_segment(const fscc_batch *b, int s, size_t *off1, size_t *n1, size_t *off2, size_t *n2);
+
+/* Integral class of system s, boundary layout as fscc_set_integrals
+ * (synchronous; dev_blocks may be freed on return). */
+fscc_status fscc_batch_set_integrals(fscc_batch *b, int s, fscc_iclass cls, const fscc_c128 *dev_blocks, size_t n);
+
+/* Fresh DIIS subspaces (depth ndiis in 1..8) for every system, all systems
+ * active, convergence threshold tol on max|step| (default after create: 6,
+ * 1e-10).  Drops a captured graph. */
+fscc_status fscc_batch_reset(fscc_batch *b, int ndiis, double tol);
+
+/* Residuals of all systems, R = RHS - D*t (Eq. (3)) (rows of frozen systems
+ * are not meaningful). */
+fscc_status fscc_batch_build_residual(fscc_batch *b, const fscc_c128 *t1, const fscc_c128 *t2, fscc_c128 *r1,
+                                      fscc_c128 *r2);
+
+/* One iteration for every active system: residual, Jacobi step, DIIS
+ * extrapolation, energy of the new amplitudes.  use_graph = 1 replays a HIP
+ * graph of the whole iteration (captured on first use for these four
+ * pointers, re-captured when they change).  Synchronous: report[nsys*6]
+ * (host) receives per system E_re, E_im, max|step| of this iteration (last
+ * value for frozen systems), active (1 = not yet converged), iterations
+ * taken, failed (1 = non-finite step; the system is frozen). */
+fscc_status fscc_batch_step(fscc_batch *b, fscc_c128 *t1, fscc_c128 *t2, fscc_c128 *r1, fscc_c128 *r2,
+                            int use_graph, double *report);
+
+/* The batch's executor, for the introspection calls only (fscc_profile,
+ * fscc_op_count, fscc_op_info, fscc_autotune, fscc_gemm_config): its
+ * operations are the merged grouped launches.  Owned by the batch. */
+fscc_ctx *fscc_batch_context(fscc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,16 @@ def lib():
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
             "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
+            "fscc_batch_create": ([ctypes.POINTER(_System), ip, ip, vp, ctypes.POINTER(vp)], ip),
+            "fscc_batch_destroy": ([vp], None),
+            "fscc_batch_last_error": ([vp], ctypes.c_char_p),
+            "fscc_batch_sizes": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz)], ip),
+            "fscc_batch_segment": ([vp, ip] + [ctypes.POINTER(sz)] * 4, ip),
+            "fscc_batch_set_integrals": ([vp, ip, ip, vp, sz], ip),
+            "fscc_batch_reset": ([vp, ip, ctypes.c_double], ip),
+            "fscc_batch_build_residual": ([vp, vp, vp, vp, vp], ip),
+            "fscc_batch_step": ([vp, vp, vp, vp, vp, ip, dp], ip),
+            "fscc_batch_context": ([vp], vp),
             "fscc_destroy": ([vp], None),
             "fscc_last_error": ([vp], ctypes.c_char_p),
         }
@@ -342,3 +352,124 @@ def zgemm_split(A, B, C, M, N, K, lda, ldb, ldc, precision="split_bf16", cfg=0, 
                                alpha.imag, int(beta), ctypes.c_void_p(st.cuda_stream))
     if r != 0:
         raise FsccError(r, "fscc_zgemm_split failed")
+
+
+def _system_struct(sysm, keep):
+    import numpy as np
+    irr = np.ascontiguousarray(sysm.irrep, dtype=np.int32)
+    eps = np.ascontiguousarray(sysm.eps, dtype=np.float64)
+    act = np.ascontiguousarray(getattr(sysm, "active", ()), dtype=np.int32)
+    keep += [irr, eps, act]
+    return _System(int(sysm.nocc), int(sysm.nvirt), int(sysm.nirrep),
+                   irr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                   eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(act),
+                   act.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+class _ContextView(Context):
+    """Introspection view (profile, op times, autotune, GEMM configs) of a batch's executor."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def destroy(self):
+        self._h = None
+
+
+class Batch:
+    """Many independent (0h,0p) systems in grouped launches (fscc_batch_*)."""
+
+    REPORT = ("E_re", "E_im", "max_step", "active", "iters", "failed")
+
+    def __init__(self, systems, stream=None, precision="fp64"):
+        import torch
+        L = lib()
+        keep = []
+        arr = (_System * len(systems))(*[_system_struct(s, keep) for s in systems])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.nsys = len(systems)
+        h = ctypes.c_void_p()
+        st = L.fscc_batch_create(arr, len(systems), _prec(precision), ctypes.c_void_p(stream.cuda_stream),
+                                 ctypes.byref(h))
+        if st != 0:
+            raise FsccError(st, "fscc_batch_create failed")
+        self._h = h
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(L.fscc_batch_sizes(self._h, ctypes.byref(a), ctypes.byref(b)))
+        self.n1, self.n2 = a.value, b.value
+        self.segments = []
+        for k in range(self.nsys):
+            v = [ctypes.c_size_t() for _ in range(4)]
+            self._check(L.fscc_batch_segment(self._h, k, *[ctypes.byref(x) for x in v]))
+            self.segments.append(tuple(x.value for x in v))   # off1, n1, off2, n2
+
+    def _check(self, st):
+        if st != 0:
+            msg = lib().fscc_batch_last_error(self._h)
+            raise FsccError(st, msg.decode() if msg else "")
+
+    def set_integrals(self, s, cls, dev_blocks):
+        k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)
+        self._check(lib().fscc_batch_set_integrals(self._h, int(s), k, _dev_ptr(dev_blocks), dev_blocks.numel()))
+
+    def reset(self, ndiis=6, tol=1e-10):
+        self._check(lib().fscc_batch_reset(self._h, int(ndiis), float(tol)))
+
+    def build_residual(self, t1, t2, r1, r2):
+        self._check(lib().fscc_batch_build_residual(self._h, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+                                                    _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2)))
+
+    def step(self, t1, t2, r1, r2, use_graph=False):
+        """One iteration of every active system; returns a numpy [nsys, 6] report
+        (E_re, E_im, max_step, active, iters, failed)."""
+        import numpy as np
+        rep = np.zeros((self.nsys, 6))
+        self._check(lib().fscc_batch_step(self._h, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+                                          _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2), 1 if use_graph else 0,
+                                          rep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return rep
+
+    def context(self):
+        return _ContextView(ctypes.c_void_p(lib().fscc_batch_context(self._h)))
+
+    def split(self, t, part):
+        """Per-system views of a concatenated vector (part 1: T1, 2: T2)."""
+        return [t[(g[0] if part == 1 else g[2]):(g[0] + g[1] if part == 1 else g[2] + g[3])] for g in self.segments]
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().fscc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None):
+    """Iterate every system of a batch until each one's max|step| < tol.
+    Returns dict(E [complex per system], iters, converged, failed, history
+    (list of reports), times (host time after each iteration))."""
+    import time
+    import numpy as np
+    import torch
+    r1 = torch.empty_like(t1)
+    r2 = torch.empty_like(t2)
+    batch.reset(ndiis, tol)
+    hist, times = [], []
+    rep = None
+    for k in range(1, maxit + 1):
+        rep = batch.step(t1, t2, r1, r2, use_graph)
+        hist.append(rep)
+        times.append(time.perf_counter())
+        if log:
+            log(f"batch iter {k:3d}: active {int(rep[:, 3].sum())}/{batch.nsys}, max|step| {rep[:, 2].max():.3e}")
+        if not rep[:, 3].any():
+            break
+    E = rep[:, 0] + 1j * rep[:, 1]
+    return dict(E=E, iters=rep[:, 4].astype(int), converged=(rep[:, 3] == 0) & (rep[:, 5] == 0),
+                failed=rep[:, 5] != 0, history=hist, times=times)

@@ -11,270 +11,10 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fscc.h"
-#include "kernels.hpp"
-#include "plan.hpp"
+#include "runtime.hpp"
 
-using namespace fscc;
-
-namespace {
-
-// one operand of a split-precision GEMM: its piece planes and how to fill them
-struct SplitDev {
-    SplitProb* sp = nullptr;
-    int nsp = 0;
-    long long max_chunks = 0;
-    void* planes = nullptr;
-    long long plane = 0;      // elements per plane
-    bool conj = false;
-    bool constant = false;    // integral-derived: split once, then reused
-    bool valid = false;
-};
-
-// split-precision form of one GEMM op (FSCC_SPLIT_BF16 / FSCC_SPLIT_FP32)
-struct MixedDev {
-    int prec = 0;
-    int cfg = 0;
-    MProb* probs = nullptr;
-    ZTile* tiles = nullptr;
-    int ntiles = 0;
-    SplitDev a, b;
-};
-
-struct GemmDev {
-    ZProb* probs = nullptr;
-    ZTile* tiles = nullptr;
-    int ntiles = 0;
-    int cfg = 0;
-    int bk = 16;
-    // split-K: the tiles write partial products into `work`, a second pass reduces
-    bool split = false;
-    int role = 0;   // 1: pp-ladder, 2: ring GEMMs (distinct kernel symbols in profiles)
-    ZRed* reds = nullptr;
-    int nred = 0;
-    int maxMN = 0;
-    double2* work = nullptr;
-    MixedDev* mx = nullptr;   // present for the ops that may run in split precision
-};
-
-struct HipError : std::runtime_error {
-    explicit HipError(const std::string& s) : std::runtime_error(s) {}
-};
-
-void hip_check(hipError_t e, const char* what) {
-    if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
-}
-
-constexpr int kMaxDiis = 8;
-
-// one executable op list with its device GEMM lists and timing slots
-struct OpList {
-    std::vector<Op>* ops = nullptr;
-    std::vector<GemmDev> g;
-    std::vector<hipEvent_t> ev;
-    std::vector<double> ms;
-    std::vector<int> calls;
-};
-
-// DIIS state of one sector
-struct Diis {
-    int ndiis = 6;
-    std::vector<int> order;   // live slots, oldest first
-    double2* ht = nullptr;
-    double2* he = nullptr;
-    double* dB = nullptr;
-    int64_t n1 = 0, n2 = 0;
-    int b_D1 = -1, b_D2 = -1;
-};
-
-}  // namespace
-
-struct fscc_ctx {
-    int device = 0;
-    hipStream_t st = nullptr;
-    Plan plan;
-    std::vector<void*> dbuf;
-    std::vector<uint32_t*> dmap;
-    OpList L00, L01p, L01;
-    bool have_cls[IC_N] = {false, false, false, false, false, false};
-    bool ready01 = false;
-    Diis diis[2];
-    double* part = nullptr;
-    double* part_max = nullptr;
-    double* coef = nullptr;
-    double* scal = nullptr;
-    int* dorder = nullptr;
-    double* hscal = nullptr;   // pinned host
-    double* epart = nullptr;
-    double* eout = nullptr;
-    double2* rs_tmp = nullptr; // residual scratch for fscc_heff
-    bool prof = false;
-    int prec = FSCC_FP64;
-    std::string err;
-
-    int64_t n1() const { return plan.L_T1.total; }
-    int64_t n2() const { return plan.L_T2.total; }
-
-    void* dalloc(size_t bytes) {
-        void* p = nullptr;
-        if (bytes == 0) bytes = 16;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) throw std::bad_alloc();
-        return p;
-    }
-
-    static void free_mixed(MixedDev*& m) {
-        if (!m) return;
-        void* ps[] = {m->probs, m->tiles, m->a.sp, m->a.planes, m->b.sp, m->b.planes};
-        for (void* p : ps)
-            if (p) (void)hipFree(p);
-        delete m;
-        m = nullptr;
-    }
-
-    static void free_list(OpList& L) {
-        for (auto& g : L.g) {
-            if (g.probs) (void)hipFree(g.probs);
-            if (g.tiles) (void)hipFree(g.tiles);
-            if (g.reds) (void)hipFree(g.reds);
-            if (g.work) (void)hipFree(g.work);
-            free_mixed(g.mx);
-        }
-        for (auto& e : L.ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-
-    ~fscc_ctx() {
-        for (size_t k = 0; k < dbuf.size(); ++k)
-            if (!caller_buffer(plan.bufs[k].kind) && dbuf[k]) (void)hipFree(dbuf[k]);
-        for (auto* m : dmap)
-            if (m) (void)hipFree(m);
-        free_list(L00);
-        free_list(L01p);
-        free_list(L01);
-        for (auto& d : diis) {
-            if (d.ht) (void)hipFree(d.ht);
-            if (d.he) (void)hipFree(d.he);
-            if (d.dB) (void)hipFree(d.dB);
-        }
-        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp};
-        for (void* p : ps)
-            if (p) (void)hipFree(p);
-        if (hscal) (void)hipHostFree(hscal);
-    }
-
-    double2* B(int id) const { return (double2*)dbuf[id]; }
-
-    void run_op(const Op& o, const GemmDev* gd, int beta_override = -1, const double2* A_override = nullptr,
-                double2* C_override = nullptr) {
-        hipError_t e = hipSuccess;
-        switch (o.kind) {
-            case OP_AXPBY:
-                e = launch_axpby(B(o.dst), B(o.src), o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
-                break;
-            case OP_DIAG:
-                e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st);
-                break;
-            case OP_MUL:
-                e = launch_mul(B(o.dst), (const double*)dbuf[o.src2], o.n, st);
-                break;
-            case OP_GATHER: {
-                GatherMaps gm;
-                for (int t = 0; t < 4; ++t) {
-                    gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
-                    gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
-                }
-                e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(), o.n,
-                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
-                break;
-            }
-            case OP_GEMM: {
-                const GemmDev& g = *gd;
-                int beta = beta_override >= 0 ? beta_override : o.beta;
-                const double2* Ap = A_override ? A_override : B(o.src);
-                double2* Cp = C_override ? C_override : B(o.dst);
-                if (prec != FSCC_FP64 && g.mx && g.mx->prec == prec && !(A_override && g.mx->a.constant)) {
-                    e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
-                } else if (!g.split) {
-                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role);
-                } else {
-                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                     0.0, 0, o.cA, o.cB, st, g.role);
-                    if (e == hipSuccess)
-                        e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
-                                                 beta, st);
-                }
-                break;
-            }
-        }
-        hip_check(e, o.name.c_str());
-    }
-
-    hipError_t split_operand(SplitDev& d, const double2* src, bool bf16) {
-        if (d.constant && d.valid) return hipSuccess;
-        hipError_t e = launch_split(bf16, src, d.planes, d.plane, d.sp, d.nsp, d.max_chunks, d.conj ? 1 : 0, st);
-        if (e == hipSuccess && d.constant) d.valid = true;
-        return e;
-    }
-
-    hipError_t run_mixed(const Op& o, MixedDev& m, const double2* A, const double2* Bm, double2* C, int beta) {
-        const bool bf = m.prec == FSCC_SPLIT_BF16;
-        hipError_t e = split_operand(m.a, A, bf);
-        if (e == hipSuccess) e = split_operand(m.b, Bm, bf);
-        if (e == hipSuccess)
-            e = launch_zgemm_split(bf, m.cfg, m.a.planes, m.a.plane, m.b.planes, m.b.plane, C, m.probs, m.tiles,
-                                   m.ntiles, o.alpha.real(), o.alpha.imag(), beta, st,
-                                   o.name == "pp-ladder" ? 1 : 2);
-        return e;
-    }
-
-    void run_list(OpList& L, bool timed) {
-        std::vector<Op>& ops = *L.ops;
-        if (timed && L.ev.size() != 2 * ops.size()) {
-            L.ev.assign(2 * ops.size(), nullptr);
-            for (auto& e : L.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
-        }
-        for (size_t k = 0; k < ops.size(); ++k) {
-            if (timed) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
-            run_op(ops[k], &L.g[k]);
-            if (timed) hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
-        }
-        if (timed) {
-            hip_check(hipStreamSynchronize(st), "profile sync");
-            for (size_t k = 0; k < ops.size(); ++k) {
-                float ms = 0.f;
-                hip_check(hipEventElapsedTime(&ms, L.ev[2 * k], L.ev[2 * k + 1]), "elapsed");
-                L.ms[k] += ms;
-                L.calls[k] += 1;
-            }
-        }
-    }
-};
-
-namespace {
-
-fscc_status fail(fscc_ctx* c, fscc_status s, const std::string& msg) {
-    if (c) c->err = msg;
-    return s;
-}
-
-template <class F>
-fscc_status guarded(fscc_ctx* c, F f) {
-    try {
-        return f();
-    } catch (const HipError& e) {
-        return fail(c, FSCC_EHIP, e.what());
-    } catch (const std::bad_alloc&) {
-        return fail(c, FSCC_ENOMEM, "device or host allocation failed");
-    } catch (const std::invalid_argument& e) {
-        return fail(c, FSCC_EINVAL, e.what());
-    } catch (const std::exception& e) {
-        return fail(c, FSCC_EINVAL, e.what());
-    } catch (...) {
-        return fail(c, FSCC_EINVAL, "unknown error");
-    }
-}
+namespace fscc {
+namespace rt {
 
 // Default tile shape from a cost model: padded MFMA work at a per-shape
 // efficiency, against operand re-reads (A once per column tile, B once per
@@ -367,7 +107,8 @@ MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg) {
             const int mt = (pr[q].M + bm - 1) / bm, nt = (pr[q].N + bn - 1) / bn;
             for (int mg = 0; mg < mt; mg += 8)
                 for (int n = 0; n < nt; ++n)
-                    for (int mm = mg; mm < std::min(mt, mg + 8); ++mm) tl.push_back(ZTile{(int)q, mm * bm, n * bn, 0});
+                    for (int mm = mg; mm < std::min(mt, mg + 8); ++mm)
+                        tl.push_back(ZTile{(int)q, mm * bm, n * bn, o.probs[q].sys});
         }
         std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& x, const ZTile& y) { return pr[x.prob].Kp > pr[y.prob].Kp; });
         tl = xcd_order(tl);
@@ -451,6 +192,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
             split |= Sq[q] > 1;
         }
     std::vector<ZProb> pr;
+    std::vector<int> psys;
     std::vector<ZTile> tl;
     std::vector<ZRed> rd;
     long long woff = 0;
@@ -459,6 +201,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
         const GemmProblem& p = o.probs[q];
         if (!split) {
             pr.push_back(ZProb{p.a_off, p.b_off, p.c_off, p.M, p.N, p.K, p.lda, p.ldb, p.ldc});
+            psys.push_back(p.sys);
         } else {
             int chunk = (p.K + Sq[q] - 1) / std::max(Sq[q], 1);
             int ns = 0;
@@ -467,6 +210,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
                 long long ao = p.a_off + (o.tA ? (long long)k0 * p.lda : k0);
                 long long bo = p.b_off + (o.tB ? k0 : (long long)k0 * p.ldb);
                 pr.push_back(ZProb{ao, bo, woff + (long long)ns * p.M * p.N, p.M, p.N, len, p.lda, p.ldb, p.N});
+                psys.push_back(p.sys);
                 ++ns;
                 if (p.K == 0) break;
             }
@@ -481,7 +225,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
         const int mt = (pr[q].M + bm - 1) / bm, nt = (pr[q].N + bn - 1) / bn;
         for (int mg = 0; mg < mt; mg += 8)
             for (int n = 0; n < nt; ++n)
-                for (int m = mg; m < std::min(mt, mg + 8); ++m) tl.push_back(ZTile{(int)q, m * bm, n * bn, 0});
+                for (int m = mg; m < std::min(mt, mg + 8); ++m) tl.push_back(ZTile{(int)q, m * bm, n * bn, psys[q]});
     }
     // longest-K tiles first (uneven symmetry blocks)
     std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) { return pr[a.prob].K > pr[b.prob].K; });
@@ -544,7 +288,64 @@ bool all_integrals(const fscc_ctx* c) {
     return true;
 }
 
-}  // namespace
+// Device buffers, uploads of the host constants and per-iteration maps, GEMM
+// plans of the op lists, DIIS state and reduction scratch of a context whose
+// plan is built (setup maps stay on the host until their class is imported).
+void ctx_allocate(fscc_ctx* c, bool diis) {
+    Plan& P = c->plan;
+    // buffers
+    c->dbuf.assign(P.bufs.size(), nullptr);
+    for (size_t k = 0; k < P.bufs.size(); ++k) {
+        const BufDesc& b = P.bufs[k];
+        if (caller_buffer(b.kind)) continue;
+        size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : sizeof(double2));
+        c->dbuf[k] = c->dalloc(bytes);
+    }
+    auto up_real = [&](int b, const std::vector<double>& v) {
+        if (b >= 0 && !v.empty())
+            hip_check(hipMemcpy(c->dbuf[b], v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+    };
+    up_real(P.b_D1, P.D1);
+    up_real(P.b_D2, P.D2);
+    up_real(P.b_D1x, P.D1x);
+    up_real(P.b_D2x, P.D2x);
+    up_real(P.b_mask1, P.mask1);
+    for (auto& hc : P.const_host)
+        if (!hc.data.empty())
+            hip_check(hipMemcpy(c->dbuf[hc.buf], hc.data.data(), hc.data.size() * sizeof(double2),
+                                hipMemcpyHostToDevice), "const upload");
+    // maps of the per-iteration gathers (setup maps are uploaded at set_integrals)
+    c->dmap.assign(P.maps.size(), nullptr);
+    std::vector<char> is_setup(P.maps.size(), 0);
+    for (auto& sg : P.setup) is_setup[sg.map] = 1;
+    for (size_t k = 0; k < P.maps.size(); ++k) {
+        if (is_setup[k]) continue;
+        c->dmap[k] = (uint32_t*)c->dalloc(P.maps[k].size() * sizeof(uint32_t));
+        hip_check(hipMemcpy(c->dmap[k], P.maps[k].data(), P.maps[k].size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                  "map upload");
+        std::vector<uint32_t>().swap(P.maps[k]);
+    }
+    setup_list(c, c->L00, P.ops);
+    setup_list(c, c->L01p, P.ops01_prep);
+    setup_list(c, c->L01, P.ops01);
+    if (diis) setup_diis(c, c->diis[0], c->n1(), c->n2(), P.b_D1, P.b_D2);
+    if (P.has01) {
+        setup_diis(c, c->diis[1], P.L_S1.total, P.L_S2.total, P.b_D1x, P.b_D2x);
+        c->rs_tmp = (double2*)c->dalloc((size_t)(P.L_S1.total + P.L_S2.total) * sizeof(double2));
+    }
+    c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
+    c->part_max = (double*)c->dalloc(2048 * sizeof(double));
+    c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
+    c->scal = (double*)c->dalloc(4 * sizeof(double));
+    c->dorder = (int*)c->dalloc(kMaxDiis * sizeof(int));
+    c->epart = (double*)c->dalloc(2048 * sizeof(double));
+    c->eout = (double*)c->dalloc(4 * sizeof(double));
+    hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+}
+
+}  // namespace rt
+}  // namespace fscc
+
 
 extern "C" {
 
@@ -574,55 +375,7 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
             if (!std::isfinite(S.eps[p])) throw std::invalid_argument("non-finite orbital energy");
         }
         build_plan_ccsd(S, c->plan);
-        Plan& P = c->plan;
-        // buffers
-        c->dbuf.assign(P.bufs.size(), nullptr);
-        for (size_t k = 0; k < P.bufs.size(); ++k) {
-            const BufDesc& b = P.bufs[k];
-            if (caller_buffer(b.kind)) continue;
-            size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : sizeof(double2));
-            c->dbuf[k] = c->dalloc(bytes);
-        }
-        auto up_real = [&](int b, const std::vector<double>& v) {
-            if (b >= 0 && !v.empty())
-                hip_check(hipMemcpy(c->dbuf[b], v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
-        };
-        up_real(P.b_D1, P.D1);
-        up_real(P.b_D2, P.D2);
-        up_real(P.b_D1x, P.D1x);
-        up_real(P.b_D2x, P.D2x);
-        up_real(P.b_mask1, P.mask1);
-        for (auto& hc : P.const_host)
-            if (!hc.data.empty())
-                hip_check(hipMemcpy(c->dbuf[hc.buf], hc.data.data(), hc.data.size() * sizeof(double2),
-                                    hipMemcpyHostToDevice), "const upload");
-        // maps of the per-iteration gathers (setup maps are uploaded at set_integrals)
-        c->dmap.assign(P.maps.size(), nullptr);
-        std::vector<char> is_setup(P.maps.size(), 0);
-        for (auto& sg : P.setup) is_setup[sg.map] = 1;
-        for (size_t k = 0; k < P.maps.size(); ++k) {
-            if (is_setup[k]) continue;
-            c->dmap[k] = (uint32_t*)c->dalloc(P.maps[k].size() * sizeof(uint32_t));
-            hip_check(hipMemcpy(c->dmap[k], P.maps[k].data(), P.maps[k].size() * sizeof(uint32_t), hipMemcpyHostToDevice),
-                      "map upload");
-            std::vector<uint32_t>().swap(P.maps[k]);
-        }
-        setup_list(c, c->L00, P.ops);
-        setup_list(c, c->L01p, P.ops01_prep);
-        setup_list(c, c->L01, P.ops01);
-        setup_diis(c, c->diis[0], c->n1(), c->n2(), P.b_D1, P.b_D2);
-        if (P.has01) {
-            setup_diis(c, c->diis[1], P.L_S1.total, P.L_S2.total, P.b_D1x, P.b_D2x);
-            c->rs_tmp = (double2*)c->dalloc((size_t)(P.L_S1.total + P.L_S2.total) * sizeof(double2));
-        }
-        c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
-        c->part_max = (double*)c->dalloc(2048 * sizeof(double));
-        c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
-        c->scal = (double*)c->dalloc(4 * sizeof(double));
-        c->dorder = (int*)c->dalloc(kMaxDiis * sizeof(int));
-        c->epart = (double*)c->dalloc(2048 * sizeof(double));
-        c->eout = (double*)c->dalloc(4 * sizeof(double));
-        hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+        ctx_allocate(c, true);
         apply_precision(c, prec);
         return FSCC_OK;
     });

@@ -27,7 +27,7 @@ template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE>
 __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
-                                               int cA, int cB) {
+                                               int cA, int cB, const int* __restrict__ active) {
     constexpr int PAD = 4;
     constexpr int FM = BM / (16 * WM);
     constexpr int FN = BN / (16 * WN);
@@ -37,6 +37,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
     __shared__ double Bs[2][BK][BN + PAD];
 
     const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;   // whole workgroup: a converged system of a batch
     const ZProb pr = probs[tl.prob];
     const int M = pr.M, N = pr.N, K = pr.K;
     const double2* Ap = A + pr.a_off;
@@ -283,18 +284,18 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
 template <int BM, int BN, int WM, int WN, int BK>
 static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
                              const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
-                             hipStream_t st, int role) {
+                             hipStream_t st, int role, const int* active) {
     dim3 grid(ntiles), block(kThreads);
     if (!tA && !tB) {
-        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
-        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (!tA && tB) {
-        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
-        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (tA && !tB) {
-        k_zgemm<BM, BN, WM, WN, BK, true, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        k_zgemm<BM, BN, WM, WN, BK, true, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else {
-        k_zgemm<BM, BN, WM, WN, BK, true, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB);
+        k_zgemm<BM, BN, WM, WN, BK, true, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     }
     return hipGetLastError();
 }
@@ -302,24 +303,24 @@ static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* 
 template <int BK>
 static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                             const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                            int cB, hipStream_t st, int role) {
+                            int cB, hipStream_t st, int role, const int* active) {
     switch (cfg) {
-        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role) {
+                        int cB, hipStream_t st, int role, const int* active) {
     if (ntiles <= 0) return hipSuccess;
-    if (bk == 32) return launch_bk<32>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
-    if (bk == 16) return launch_bk<16>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role);
+    if (bk == 32) return launch_bk<32>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+    if (bk == 16) return launch_bk<16>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
     return hipErrorInvalidValue;
 }
 
@@ -573,39 +574,12 @@ hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long
     return hipGetLastError();
 }
 
-// One workgroup: reduce the dot partials into row/column `newslot` of B,
-// then solve the bordered Pulay system over the slots listed in `order`
-// (oldest first) by Gaussian elimination with partial pivoting in FP64;
-// if a pivot is below 1e-14 * max|A| the oldest slot is dropped and the solve
-// repeated.  coef[slot] receives the coefficient (0 for unused slots);
-// scal[0] = max |step|, scal[1] = number of dropped slots.
-__global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ part, int nblk, int m,
-                                                     const double* __restrict__ part_max, int nblk_max,
-                                                     double* __restrict__ B, int ldb, int newslot,
-                                                     const int* __restrict__ order, double* __restrict__ coef,
-                                                     double* __restrict__ scal) {
-    __shared__ double sh[kThreads];
-    __shared__ double row[8];
-    for (int j = 0; j < m; ++j) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * 8 + j];
-        double s = block_sum(v, sh);
-        if (threadIdx.x == 0) row[j] = s;
-    }
-    double mx = 0.0;
-    for (int b = threadIdx.x; b < nblk_max; b += kThreads) {
-        double a = part_max[b];
-        mx = (a > mx || a != a) ? a : mx;
-    }
-    mx = block_max(mx, sh);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    scal[0] = mx;
-    // row[j] pairs the new vector with the slot order[j]
-    for (int j = 0; j < m; ++j) {
-        B[newslot * ldb + order[j]] = row[j];
-        B[order[j] * ldb + newslot] = row[j];
-    }
+// Bordered Pulay system over the slots order[0..m) (oldest first) of the
+// symmetric matrix B (leading dimension ldb): Gaussian elimination with
+// partial pivoting in FP64; a pivot below 1e-14 * max|A| drops the oldest
+// slot and the solve is repeated.  coef[slot] receives the coefficients (0 for
+// slots not used).  Single-thread code.  Returns the number of dropped slots.
+__device__ int diis_solve(const double* B, int ldb, const int* order, int m, double* coef) {
     for (int j = 0; j < ldb; ++j) coef[j] = 0.0;
     int first = 0, dropped = 0;
     while (true) {
@@ -664,6 +638,43 @@ __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ 
         for (int i = 0; i < k; ++i) coef[order[first + i]] = x[i];
         break;
     }
+    return dropped;
+}
+
+// One workgroup: reduce the dot partials into row/column `newslot` of B,
+// then solve the bordered Pulay system over the slots listed in `order`
+// (oldest first) by Gaussian elimination with partial pivoting in FP64;
+// if a pivot is below 1e-14 * max|A| the oldest slot is dropped and the solve
+// repeated.  coef[slot] receives the coefficient (0 for unused slots);
+// scal[0] = max |step|, scal[1] = number of dropped slots.
+__global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ part, int nblk, int m,
+                                                     const double* __restrict__ part_max, int nblk_max,
+                                                     double* __restrict__ B, int ldb, int newslot,
+                                                     const int* __restrict__ order, double* __restrict__ coef,
+                                                     double* __restrict__ scal) {
+    __shared__ double sh[kThreads];
+    __shared__ double row[8];
+    for (int j = 0; j < m; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * 8 + j];
+        double s = block_sum(v, sh);
+        if (threadIdx.x == 0) row[j] = s;
+    }
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk_max; b += kThreads) {
+        double a = part_max[b];
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    mx = block_max(mx, sh);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    scal[0] = mx;
+    // row[j] pairs the new vector with the slot order[j]
+    for (int j = 0; j < m; ++j) {
+        B[newslot * ldb + order[j]] = row[j];
+        B[order[j] * ldb + newslot] = row[j];
+    }
+    int dropped = diis_solve(B, ldb, order, m, coef);
     scal[1] = (double)dropped;
 }
 
@@ -736,6 +747,232 @@ hipError_t launch_zdotu(const double2* x, const double2* y, long long n, double*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_sum2<<<1, kThreads, 0, st>>>(part, nblk, out);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// batched Jacobi + DIIS update and energy: blockIdx.y (or x) = system; each
+// system keeps its own circular DIIS history on the device, so an iteration
+// needs no host decision and can be replayed as a graph.
+
+__global__ __launch_bounds__(256) void k_bjacobi(const double2* __restrict__ t1, const double2* __restrict__ t2,
+                                                 const double2* __restrict__ r1, const double2* __restrict__ r2,
+                                                 const double* __restrict__ D1, const double* __restrict__ D2,
+                                                 const BSeg* __restrict__ segs, const BState* __restrict__ state,
+                                                 double2* __restrict__ ht, double2* __restrict__ he,
+                                                 double* __restrict__ part_max) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.y;
+    const BState stt = state[s];
+    if (!stt.active) {
+        if (threadIdx.x == 0) part_max[(long long)s * gridDim.x + blockIdx.x] = 0.0;
+        return;
+    }
+    const BSeg g = segs[s];
+    const long long n = g.n1 + g.n2;
+    const int slot = (stt.newest + 1) % stt.nd;
+    double2* hts = ht + g.hoff + (long long)slot * n;
+    double2* hes = he + g.hoff + (long long)slot * n;
+    double mx = 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double2 rr, tt;
+        double d;
+        if (k < g.n1) {
+            rr = r1[g.off1 + k];
+            tt = t1[g.off1 + k];
+            d = D1[g.off1 + k];
+        } else {
+            rr = r2[g.off2 + k - g.n1];
+            tt = t2[g.off2 + k - g.n1];
+            d = D2[g.off2 + k - g.n1];
+        }
+        const double2 st = make_double2(rr.x / d, rr.y / d);
+        hes[k] = st;
+        hts[k] = make_double2(tt.x + st.x, tt.y + st.y);
+        const double a = sqrt(st.x * st.x + st.y * st.y);
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    const double b = block_max(mx, sh);
+    if (threadIdx.x == 0) part_max[(long long)s * gridDim.x + blockIdx.x] = b;
+}
+
+// live slots of system state `st` after adding the new vector: oldest first
+__device__ inline int bslots(const BState& st, int* order) {
+    const int nw = (st.newest + 1) % st.nd;
+    const int m = min(st.count + 1, st.nd);
+    for (int j = 0; j < m; ++j) order[j] = ((nw - (m - 1) + j) % st.nd + st.nd) % st.nd;
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_bdots(const BSeg* __restrict__ segs, const BState* __restrict__ state,
+                                               const double2* __restrict__ he, double* __restrict__ part) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.y;
+    const BState stt = state[s];
+    if (!stt.active) return;
+    const BSeg g = segs[s];
+    const long long n = g.n1 + g.n2;
+    int order[8];
+    const int m = bslots(stt, order);
+    const double2* enew = he + g.hoff + (long long)order[m - 1] * n;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        const double2 y = enew[k];
+        for (int j = 0; j < m; ++j) {
+            const double2 x = he[g.hoff + (long long)order[j] * n + k];
+            acc[j] += x.x * y.x + x.y * y.y;
+        }
+    }
+    for (int j = 0; j < m; ++j) {
+        const double b = block_sum(acc[j], sh);
+        if (threadIdx.x == 0) part[((long long)s * gridDim.x + blockIdx.x) * 8 + j] = b;
+    }
+}
+
+// one workgroup per system: finish the dots, update B, solve, advance the
+// circular history, apply the convergence test (max|step| < tol freezes the
+// system after this update; a non-finite step freezes it as failed)
+__global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, const double* __restrict__ part, int nblk,
+                                                 const double* __restrict__ part_max, double* __restrict__ Bm,
+                                                 double* __restrict__ coef, double* __restrict__ maxstep, double tol,
+                                                 int* __restrict__ active) {
+    __shared__ double sh[kThreads];
+    __shared__ double row[8];
+    const int s = blockIdx.x;
+    BState stt = state[s];
+    if (!stt.active) {
+        if (threadIdx.x == 0) {
+            state[s].upd = 0;
+            active[s] = 0;
+        }
+        return;
+    }
+    int order[8];
+    const int m = bslots(stt, order);
+    for (int j = 0; j < m; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[((long long)s * nblk + b) * 8 + j];
+        const double r = block_sum(v, sh);
+        if (threadIdx.x == 0) row[j] = r;
+    }
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        const double a = part_max[(long long)s * nblk + b];
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    mx = block_max(mx, sh);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* B = Bm + (long long)s * 64;
+    const int nw = order[m - 1];
+    for (int j = 0; j < m; ++j) {
+        B[nw * 8 + order[j]] = row[j];
+        B[order[j] * 8 + nw] = row[j];
+    }
+    const int dropped = diis_solve(B, 8, order, m, coef + (long long)s * 8);
+    stt.newest = nw;
+    stt.count = max(1, m - dropped);
+    stt.iters += 1;
+    stt.upd = 1;
+    if (!(mx == mx) || mx > 1.7976931348623157e308) {
+        stt.failed = 1;
+        stt.active = 0;
+        stt.upd = 0;
+    } else if (mx < tol) {
+        stt.active = 0;
+    }
+    state[s] = stt;
+    active[s] = stt.active;
+    maxstep[s] = mx;
+}
+
+__global__ __launch_bounds__(256) void k_blincomb(double2* __restrict__ t1, double2* __restrict__ t2,
+                                                  const BSeg* __restrict__ segs, const BState* __restrict__ state,
+                                                  const double2* __restrict__ ht, const double* __restrict__ coef) {
+    const int s = blockIdx.y;
+    const BState stt = state[s];
+    if (!stt.upd) return;
+    const BSeg g = segs[s];
+    const long long n = g.n1 + g.n2;
+    double c[8];
+    for (int j = 0; j < 8; ++j) c[j] = j < stt.nd ? coef[s * 8 + j] : 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < stt.nd; ++j)
+            if (c[j] != 0.0) {
+                const double2 x = ht[g.hoff + (long long)j * n + k];
+                sr += c[j] * x.x;
+                si += c[j] * x.y;
+            }
+        if (k < g.n1) t1[g.off1 + k] = make_double2(sr, si);
+        else t2[g.off2 + k - g.n1] = make_double2(sr, si);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_benergy(const double2* __restrict__ x, const double2* __restrict__ y,
+                                                 const BSeg* __restrict__ segs, double* __restrict__ part) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.y;
+    const BSeg g = segs[s];
+    double sr = 0.0, si = 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < g.n2; k += (long long)gridDim.x * kThreads) {
+        const double2 a = x[g.off2 + k], b = y[g.off2 + k];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+    }
+    const double r = block_sum(sr, sh);
+    const double i = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        part[((long long)s * gridDim.x + blockIdx.x) * 2] = r;
+        part[((long long)s * gridDim.x + blockIdx.x) * 2 + 1] = i;
+    }
+}
+
+// per-system report row: E_re, E_im, max|step|, active, iterations, failed
+__global__ __launch_bounds__(256) void k_breport(const double* __restrict__ part, int nblk,
+                                                 const BState* __restrict__ state, const double* __restrict__ maxstep,
+                                                 double* __restrict__ out) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.x;
+    double r = 0.0, i = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        r += part[((long long)s * nblk + b) * 2];
+        i += part[((long long)s * nblk + b) * 2 + 1];
+    }
+    r = block_sum(r, sh);
+    i = block_sum(i, sh);
+    if (threadIdx.x == 0) {
+        const BState st = state[s];
+        double* o = out + (long long)s * 6;
+        o[0] = r;
+        o[1] = i;
+        o[2] = maxstep[s];
+        o[3] = st.active;
+        o[4] = st.iters;
+        o[5] = st.failed;
+    }
+}
+
+hipError_t launch_batch_update(const double2* t1, const double2* t2, const double2* r1, const double2* r2,
+                               double2* t1o, double2* t2o, const double* D1, const double* D2, const BSeg* segs,
+                               BState* state, double2* ht, double2* he, double* part_max, double* part, double* Bm,
+                               double* coef, double* maxstep, double tol, int* active, int nsys, int nblk,
+                               hipStream_t st) {
+    if (nsys <= 0) return hipSuccess;
+    dim3 grid(nblk, nsys);
+    k_bjacobi<<<grid, kThreads, 0, st>>>(t1, t2, r1, r2, D1, D2, segs, state, ht, he, part_max);
+    k_bdots<<<grid, kThreads, 0, st>>>(segs, state, he, part);
+    k_bfinish<<<nsys, kThreads, 0, st>>>(state, part, nblk, part_max, Bm, coef, maxstep, tol, active);
+    k_blincomb<<<grid, kThreads, 0, st>>>(t1o, t2o, segs, state, ht, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_energy(const double2* oovv, const double2* tau, const BSeg* segs, const BState* state,
+                               const double* maxstep, double* part, double* out, int nsys, int nblk, hipStream_t st) {
+    if (nsys <= 0) return hipSuccess;
+    k_benergy<<<dim3(nblk, nsys), kThreads, 0, st>>>(oovv, tau, segs, part);
+    k_breport<<<nsys, kThreads, 0, st>>>(part, nblk, state, maxstep, out);
     return hipGetLastError();
 }
 

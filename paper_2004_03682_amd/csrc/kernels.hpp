@@ -12,9 +12,9 @@ struct ZProb {
     long long a_off, b_off, c_off;
     int M, N, K, lda, ldb, ldc;
 };
-// one output tile of one problem
+// one output tile of one problem; sys = system index of a batched launch
 struct ZTile {
-    int prob, m0, n0, pad;
+    int prob, m0, n0, sys;
 };
 
 // tile shapes of the grouped complex GEMM
@@ -26,9 +26,10 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 //   !tB: B(k,n) = B[b_off + k*ldb + n]      tB: B(k,n) = B[b_off + n*ldb + k]
 //   cA/cB conjugate the operand; beta is 0 (overwrite) or 1 (accumulate).
 //   bk = 16 or 32 (K depth of one LDS stage); role only selects a distinct kernel symbol.
+//   active (may be null): tiles whose active[tile.sys] == 0 are skipped.
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role = 0);
+                        int cB, hipStream_t st, int role = 0, const int* active = nullptr);
 
 // ---- compensated mixed-precision GEMM (kernels_split.hip)
 // element (r, k) of a rows x cols operand: src[src_off + r*ld + k] (trans = 0)
@@ -95,5 +96,28 @@ hipError_t launch_zdotu(const double2* x, const double2* y, long long n, double*
 hipError_t launch_zero(double2* dst, long long n, hipStream_t st);
 
 int reduce_blocks(long long n);
+
+// ---- batched update (many independent systems in concatenated vectors)
+// segment of system s: T1 part [off1, off1+n1), T2 part [off2, off2+n2);
+// history: nd slots of n1+n2 elements at hoff
+struct BSeg {
+    long long off1, n1, off2, n2, hoff;
+};
+// per-system DIIS state: count live slots, newest slot, active (not yet
+// converged), upd (updated in the current iteration), iterations, failed
+// (non-finite step), nd = history depth (<= 8)
+struct BState {
+    int count, newest, active, upd, iters, failed, nd, pad;
+};
+// Jacobi step + per-system DIIS (t?o may alias t?); one launch sequence
+hipError_t launch_batch_update(const double2* t1, const double2* t2, const double2* r1, const double2* r2,
+                               double2* t1o, double2* t2o, const double* D1, const double* D2, const BSeg* segs,
+                               BState* state, double2* ht, double2* he, double* part_max, double* part, double* Bm,
+                               double* coef, double* maxstep, double tol, int* active, int nsys, int nblk,
+                               hipStream_t st);
+// per-system E = sum oovv*tau over the T2 segment, then the report rows
+// out[s*6 + {0..5}] = E_re, E_im, max|step|, active, iterations, failed
+hipError_t launch_batch_energy(const double2* oovv, const double2* tau, const BSeg* segs, const BState* state,
+                               const double* maxstep, double* part, double* out, int nsys, int nblk, hipStream_t st);
 
 }  // namespace fscc

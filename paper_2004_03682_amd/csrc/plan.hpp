@@ -37,6 +37,7 @@ struct GemmProblem {
     int64_t a_off, b_off, c_off;
     int M, N, K;
     int lda, ldb, ldc;
+    int sys = 0;   // system of a batched plan (tiles of inactive systems are skipped)
 };
 
 enum OpKind {

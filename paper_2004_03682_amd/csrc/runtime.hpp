@@ -1,0 +1,306 @@
+// runtime.hpp -- host runtime shared by the single-system and batched C ABI:
+// device GEMM plans, op lists, DIIS state and the context that executes a
+// residual plan on a HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fscc.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace fscc {
+namespace rt {
+
+
+// one operand of a split-precision GEMM: its piece planes and how to fill them
+struct SplitDev {
+    SplitProb* sp = nullptr;
+    int nsp = 0;
+    long long max_chunks = 0;
+    void* planes = nullptr;
+    long long plane = 0;      // elements per plane
+    bool conj = false;
+    bool constant = false;    // integral-derived: split once, then reused
+    bool valid = false;
+};
+
+// split-precision form of one GEMM op (FSCC_SPLIT_BF16 / FSCC_SPLIT_FP32)
+struct MixedDev {
+    int prec = 0;
+    int cfg = 0;
+    MProb* probs = nullptr;
+    ZTile* tiles = nullptr;
+    int ntiles = 0;
+    SplitDev a, b;
+};
+
+struct GemmDev {
+    ZProb* probs = nullptr;
+    ZTile* tiles = nullptr;
+    int ntiles = 0;
+    int cfg = 0;
+    int bk = 16;
+    // split-K: the tiles write partial products into `work`, a second pass reduces
+    bool split = false;
+    int role = 0;   // 1: pp-ladder, 2: ring GEMMs (distinct kernel symbols in profiles)
+    ZRed* reds = nullptr;
+    int nred = 0;
+    int maxMN = 0;
+    double2* work = nullptr;
+    MixedDev* mx = nullptr;   // present for the ops that may run in split precision
+};
+
+struct HipError : std::runtime_error {
+    explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kMaxDiis = 8;
+
+// one executable op list with its device GEMM lists and timing slots
+struct OpList {
+    std::vector<Op>* ops = nullptr;
+    std::vector<GemmDev> g;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> ms;
+    std::vector<int> calls;
+};
+
+// DIIS state of one sector
+struct Diis {
+    int ndiis = 6;
+    std::vector<int> order;   // live slots, oldest first
+    double2* ht = nullptr;
+    double2* he = nullptr;
+    double* dB = nullptr;
+    int64_t n1 = 0, n2 = 0;
+    int b_D1 = -1, b_D2 = -1;
+};
+
+
+}  // namespace rt
+}  // namespace fscc
+
+using namespace fscc;
+using namespace fscc::rt;
+
+struct fscc_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    Plan plan;
+    std::vector<void*> dbuf;
+    std::vector<uint32_t*> dmap;
+    OpList L00, L01p, L01;
+    bool have_cls[IC_N] = {false, false, false, false, false, false};
+    bool ready01 = false;
+    Diis diis[2];
+    double* part = nullptr;
+    double* part_max = nullptr;
+    double* coef = nullptr;
+    double* scal = nullptr;
+    int* dorder = nullptr;
+    double* hscal = nullptr;   // pinned host
+    double* epart = nullptr;
+    double* eout = nullptr;
+    double2* rs_tmp = nullptr; // residual scratch for fscc_heff
+    bool prof = false;
+    int prec = FSCC_FP64;
+    const int* d_active = nullptr;   // batched plans: per-system flags, GEMM tiles of 0-systems are skipped
+    std::string err;
+
+    int64_t n1() const { return plan.L_T1.total; }
+    int64_t n2() const { return plan.L_T2.total; }
+
+    void* dalloc(size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw std::bad_alloc();
+        return p;
+    }
+
+    static void free_mixed(MixedDev*& m) {
+        if (!m) return;
+        void* ps[] = {m->probs, m->tiles, m->a.sp, m->a.planes, m->b.sp, m->b.planes};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        delete m;
+        m = nullptr;
+    }
+
+    static void free_list(OpList& L) {
+        for (auto& g : L.g) {
+            if (g.probs) (void)hipFree(g.probs);
+            if (g.tiles) (void)hipFree(g.tiles);
+            if (g.reds) (void)hipFree(g.reds);
+            if (g.work) (void)hipFree(g.work);
+            free_mixed(g.mx);
+        }
+        for (auto& e : L.ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    ~fscc_ctx() {
+        for (size_t k = 0; k < dbuf.size(); ++k)
+            if (!caller_buffer(plan.bufs[k].kind) && dbuf[k]) (void)hipFree(dbuf[k]);
+        for (auto* m : dmap)
+            if (m) (void)hipFree(m);
+        free_list(L00);
+        free_list(L01p);
+        free_list(L01);
+        for (auto& d : diis) {
+            if (d.ht) (void)hipFree(d.ht);
+            if (d.he) (void)hipFree(d.he);
+            if (d.dB) (void)hipFree(d.dB);
+        }
+        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        if (hscal) (void)hipHostFree(hscal);
+    }
+
+    double2* B(int id) const { return (double2*)dbuf[id]; }
+
+    void run_op(const Op& o, const GemmDev* gd, int beta_override = -1, const double2* A_override = nullptr,
+                double2* C_override = nullptr) {
+        hipError_t e = hipSuccess;
+        switch (o.kind) {
+            case OP_AXPBY:
+                e = launch_axpby(B(o.dst), B(o.src), o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                break;
+            case OP_DIAG:
+                e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st);
+                break;
+            case OP_MUL:
+                e = launch_mul(B(o.dst), (const double*)dbuf[o.src2], o.n, st);
+                break;
+            case OP_GATHER: {
+                GatherMaps gm;
+                for (int t = 0; t < 4; ++t) {
+                    gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
+                    gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
+                }
+                e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(), o.n,
+                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                break;
+            }
+            case OP_GEMM: {
+                const GemmDev& g = *gd;
+                int beta = beta_override >= 0 ? beta_override : o.beta;
+                const double2* Ap = A_override ? A_override : B(o.src);
+                double2* Cp = C_override ? C_override : B(o.dst);
+                if (prec != FSCC_FP64 && g.mx && g.mx->prec == prec && !(A_override && g.mx->a.constant)) {
+                    e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
+                } else if (!g.split) {
+                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active);
+                } else {
+                    e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
+                                     0.0, 0, o.cA, o.cB, st, g.role, d_active);
+                    if (e == hipSuccess)
+                        e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
+                                                 beta, st);
+                }
+                break;
+            }
+        }
+        hip_check(e, o.name.c_str());
+    }
+
+    hipError_t split_operand(SplitDev& d, const double2* src, bool bf16) {
+        if (d.constant && d.valid) return hipSuccess;
+        hipError_t e = launch_split(bf16, src, d.planes, d.plane, d.sp, d.nsp, d.max_chunks, d.conj ? 1 : 0, st);
+        if (e == hipSuccess && d.constant) d.valid = true;
+        return e;
+    }
+
+    hipError_t run_mixed(const Op& o, MixedDev& m, const double2* A, const double2* Bm, double2* C, int beta) {
+        const bool bf = m.prec == FSCC_SPLIT_BF16;
+        hipError_t e = split_operand(m.a, A, bf);
+        if (e == hipSuccess) e = split_operand(m.b, Bm, bf);
+        if (e == hipSuccess)
+            e = launch_zgemm_split(bf, m.cfg, m.a.planes, m.a.plane, m.b.planes, m.b.plane, C, m.probs, m.tiles,
+                                   m.ntiles, o.alpha.real(), o.alpha.imag(), beta, st,
+                                   o.name == "pp-ladder" ? 1 : 2);
+        return e;
+    }
+
+    void run_list(OpList& L, bool timed) {
+        std::vector<Op>& ops = *L.ops;
+        if (timed && L.ev.size() != 2 * ops.size()) {
+            L.ev.assign(2 * ops.size(), nullptr);
+            for (auto& e : L.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+        }
+        for (size_t k = 0; k < ops.size(); ++k) {
+            if (timed) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
+            run_op(ops[k], &L.g[k]);
+            if (timed) hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
+        }
+        if (timed) {
+            hip_check(hipStreamSynchronize(st), "profile sync");
+            for (size_t k = 0; k < ops.size(); ++k) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, L.ev[2 * k], L.ev[2 * k + 1]), "elapsed");
+                L.ms[k] += ms;
+                L.calls[k] += 1;
+            }
+        }
+    }
+};
+
+
+namespace fscc {
+namespace rt {
+
+inline fscc_status fail(fscc_ctx* c, fscc_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+template <class F>
+fscc_status guarded(fscc_ctx* c, F f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return fail(c, FSCC_EHIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(c, FSCC_ENOMEM, "device or host allocation failed");
+    } catch (const std::invalid_argument& e) {
+        return fail(c, FSCC_EINVAL, e.what());
+    } catch (const std::exception& e) {
+        return fail(c, FSCC_EINVAL, e.what());
+    } catch (...) {
+        return fail(c, FSCC_EINVAL, "unknown error");
+    }
+}
+
+double cfg_cost(const Op& o, int cfg);
+int pick_cfg(const Op& o);
+std::vector<ZTile> xcd_order(const std::vector<ZTile>& logical);
+void free_gemm(GemmDev& g);
+bool mixed_eligible(const Op& o);
+MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg);
+int pick_mcfg(const Op& o);
+void apply_precision(fscc_ctx* c, int prec);
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split);
+void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops);
+void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2);
+void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2);
+void bind_io01(fscc_ctx* c, const fscc_c128* s1, const fscc_c128* s2, fscc_c128* r1, fscc_c128* r2);
+bool all_integrals(const fscc_ctx* c);
+void ctx_allocate(fscc_ctx* c, bool diis);
+
+}  // namespace rt
+}  // namespace fscc
