@@ -199,6 +199,109 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
     return out
 
 
+BATCH_SOLVER = dict(ndiis=8, shift=1.0)   # DIIS(8) + 1 Eh level shift for the batched workload (same fixed point)
+
+
+def batch_study(F, torch, fsgen, args, log):
+    """64 independent systems (nocc U{10..30}, nvirt U{60..200}, 4-8 irreps,
+    sigma 0.05, seeds 40000..40063): one batched solve (grouped launches, graph
+    per iteration) against the same systems solved one after another."""
+    import numpy as np
+    ss = fsgen.batch_systems(64, 40000)
+    t0 = time.perf_counter()
+    b = F.Batch(ss)
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k, s in enumerate(ss):
+        for C in fsgen.CLASSES:
+            d = fsgen.class_buffer_gpu(s, C)
+            b.set_integrals(k, C, d)
+            del d
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    t_int = time.perf_counter() - t0
+    log(f"batch: 64 systems, n1={b.n1} n2={b.n2}; plans {t_plan:.1f}s, integrals (device generator) {t_int:.1f}s")
+    t0 = time.perf_counter()
+    b.context().autotune(1)
+    t_tune = time.perf_counter() - t0
+    t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
+    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+    # per-iteration time with every system active (graph replay)
+    b.reset(BATCH_SOLVER["ndiis"], 1e-10, BATCH_SOLVER["shift"])
+    for _ in range(2):
+        b.step(t1, t2, r1, r2, True)
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    for _ in range(5):
+        b.step(t1, t2, r1, r2, True)
+    it_ms = (time.perf_counter() - st) / 5 * 1e3
+    ctxv = b.context()
+    gemm = sum(o["flops"] for o in ctxv.op_times() if o["flops"] > 0)
+    # full solve from zero
+    t1.zero_()
+    t2.zero_()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=300, use_graph=True, **BATCH_SOLVER)
+    el = time.perf_counter() - ts
+    conv = res["converged"]
+    E = res["E"]
+    # time until every converged system is within 1e-8 Eh of its final energy
+    hist = res["history"]
+    k8 = []
+    for s in range(len(ss)):
+        if not conv[s]:
+            continue
+        e = hist[-1][s, 0] + 1j * hist[-1][s, 1]
+        k8.append(next(k for k in range(len(hist)) if all(abs(h[s, 0] + 1j * h[s, 1] - e) < 1e-8 for h in hist[k:])))
+    t8 = res["times"][max(k8)] - ts if k8 else None
+    log(f"batch: {it_ms:.2f} ms/iteration (all active), solve {el:.2f}s, converged {int(conv.sum())}/64, "
+        f"iterations mean {res['iters'].mean():.1f} max {res['iters'].max()}")
+    out = {"systems": 64, "n1_total": b.n1, "n2_total": b.n2, "ms_per_iteration_all_active": round(it_ms, 3),
+           "gemm_tflops_all_active": round(gemm / (it_ms * 1e-3) / 1e12, 2) if gemm else None,
+           "solve_seconds": round(el, 4), "seconds_to_1e-8_all_converged": round(t8, 4) if t8 else None,
+           "converged": int(conv.sum()), "iterations_mean": float(res["iters"].mean()),
+           "iterations_max": int(res["iters"].max()), "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True),
+           "plan_seconds": round(t_plan, 2), "integral_seconds": round(t_int, 2), "autotune_seconds": round(t_tune, 2)}
+    b.destroy()
+    del t1, t2, r1, r2
+    torch.cuda.empty_cache()
+    if args.no_sequential:
+        return out
+    # the same systems one after another (plans and integrals outside the clock)
+    seq, iters, agree = 0.0, 0, 0.0
+    for k, s in enumerate(ss):
+        ctx = F.Context.from_system(s)
+        for C in fsgen.CLASSES:
+            d = fsgen.class_buffer_gpu(s, C)
+            ctx.set_integrals(C, d)
+            del d
+        ctx.level_shift(BATCH_SOLVER["shift"])
+        u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+        u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        try:
+            g = F.solve(ctx, u1, u2, tol=1e-10, maxit=300, ndiis=BATCH_SOLVER["ndiis"])
+            iters += g["iters"]
+            if conv[k]:
+                agree = max(agree, abs(g["E"] - E[k]))
+        except F.FsccError:
+            iters += 300
+        seq += time.perf_counter() - ts
+        ctx.destroy()
+        del u1, u2
+        if k % 16 == 15:
+            log(f"  sequential: {k + 1} systems, {seq:.2f}s")
+    out["sequential_solve_seconds"] = round(seq, 4)
+    out["sequential_iterations_total"] = int(iters)
+    out["batched_speedup"] = round(seq / el, 2)
+    out["max_abs_dE_batched_vs_sequential"] = agree
+    log(f"batch: sequential {seq:.2f}s vs batched {el:.2f}s (x{seq / el:.2f}); max |dE| {agree:.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) sector")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
+    ap.add_argument("--no-sequential", action="store_true", help="skip the one-by-one baseline of the batch")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -373,6 +478,8 @@ def main():
     ctx.destroy()
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batch"] = batch_study(F, torch, fsgen, args, log)
     if not args.no_cpu:
         log("timing the CPU oracle on one iteration of the same system ...")
         result["cpu_baseline"] = cpu_baseline(s, buffers)

@@ -217,6 +217,12 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
                        const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void *hip_stream);
 
+/* Level shift (Eh, >= 0) of the (0h,0p) Jacobi step: step = R / (D - shift)
+ * with D < 0 for every T1/T2 denominator, so the update is damped; the fixed
+ * point R = 0 is unchanged.  Default 0.  sector must be FSCC_S00.  Applies
+ * from the next fscc_update_amplitudes. */
+fscc_status fscc_level_shift(fscc_ctx *ctx, fscc_sector sector, double shift);
+
 /* Arithmetic of the three dominant (0h,0p) contractions: the particle-
  * particle ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets
  * (the T2 part of W_mbej and sum_me t_im^ae W_mbej), which together carry
@@ -290,9 +296,11 @@ fscc_status fscc_batch_segment(const fscc_batch *b, int s, size_t *off1, size_t 
 fscc_status fscc_batch_set_integrals(fscc_batch *b, int s, fscc_iclass cls, const fscc_c128 *dev_blocks, size_t n);
 
 /* Fresh DIIS subspaces (depth ndiis in 1..8) for every system, all systems
- * active, convergence threshold tol on max|step| (default after create: 6,
- * 1e-10).  Drops a captured graph. */
-fscc_status fscc_batch_reset(fscc_batch *b, int ndiis, double tol);
+ * active, convergence threshold tol on max|step|, level shift >= 0 (Eh): the
+ * Jacobi step is R / (D - shift) (D < 0), which damps the update and leaves
+ * the fixed point R = 0 unchanged (default after create: 6, 1e-10, 0).
+ * Drops a captured graph. */
+fscc_status fscc_batch_reset(fscc_batch *b, int ndiis, double tol, double shift);
 
 /* Residuals of all systems, R = RHS - D*t (Eq. (3)) (rows of frozen systems
  * are not meaningful). */

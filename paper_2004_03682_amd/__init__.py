@@ -64,6 +64,7 @@ def lib():
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
             "fscc_set_precision": ([vp, ip], ip),
+            "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
             "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
@@ -73,7 +74,7 @@ def lib():
             "fscc_batch_sizes": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz)], ip),
             "fscc_batch_segment": ([vp, ip] + [ctypes.POINTER(sz)] * 4, ip),
             "fscc_batch_set_integrals": ([vp, ip, ip, vp, sz], ip),
-            "fscc_batch_reset": ([vp, ip, ctypes.c_double], ip),
+            "fscc_batch_reset": ([vp, ip, ctypes.c_double, ctypes.c_double], ip),
             "fscc_batch_build_residual": ([vp, vp, vp, vp, vp], ip),
             "fscc_batch_step": ([vp, vp, vp, vp, vp, ip, dp], ip),
             "fscc_batch_context": ([vp], vp),
@@ -142,6 +143,10 @@ class Context:
     def from_system(cls, sysm, stream=None, precision="fp64"):
         return cls(sysm.nocc, sysm.nvirt, sysm.nirrep, sysm.irrep, sysm.eps, stream, getattr(sysm, "active", ()),
                    precision)
+
+    def level_shift(self, shift, sector=FSCC_S00):
+        """Jacobi step R / (D - shift) for the sector (damping; same fixed point)."""
+        self._check(lib().fscc_level_shift(self._h, sector, float(shift)))
 
     def set_precision(self, precision):
         """'fp64', 'split_bf16' or 'split_fp32' for the ladder and ring contractions."""
@@ -414,8 +419,8 @@ class Batch:
         k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)
         self._check(lib().fscc_batch_set_integrals(self._h, int(s), k, _dev_ptr(dev_blocks), dev_blocks.numel()))
 
-    def reset(self, ndiis=6, tol=1e-10):
-        self._check(lib().fscc_batch_reset(self._h, int(ndiis), float(tol)))
+    def reset(self, ndiis=6, tol=1e-10, shift=0.0):
+        self._check(lib().fscc_batch_reset(self._h, int(ndiis), float(tol), float(shift)))
 
     def build_residual(self, t1, t2, r1, r2):
         self._check(lib().fscc_batch_build_residual(self._h, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
@@ -450,7 +455,7 @@ class Batch:
             pass
 
 
-def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None):
+def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None, shift=0.0):
     """Iterate every system of a batch until each one's max|step| < tol.
     Returns dict(E [complex per system], iters, converged, failed, history
     (list of reports), times (host time after each iteration))."""
@@ -459,7 +464,7 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
     import torch
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
-    batch.reset(ndiis, tol)
+    batch.reset(ndiis, tol, shift)
     hist, times = [], []
     rep = None
     for k in range(1, maxit + 1):

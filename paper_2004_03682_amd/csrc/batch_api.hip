@@ -145,9 +145,11 @@ struct fscc_batch {
     int nblk = 32;
     int ndiis = 6;
     double tol = 1e-10;
+    double shift = 0.0;
     BSeg* dseg = nullptr;
     BState* dstate = nullptr;
     int* dactive = nullptr;
+    int* dupd = nullptr;   // systems updated in the current iteration
     double2 *ht = nullptr, *he = nullptr;
     double *Bm = nullptr, *coef = nullptr, *maxstep = nullptr, *part = nullptr, *part_max = nullptr, *epart = nullptr,
            *report = nullptr;
@@ -168,7 +170,7 @@ struct fscc_batch {
         else (void)hipDeviceSynchronize();
         drop_graph();
         if (gst) (void)hipStreamDestroy(gst);
-        void* ps[] = {dseg, dstate, dactive, ht, he, Bm, coef, maxstep, part, part_max, epart, report};
+        void* ps[] = {dseg, dstate, dactive, dupd, ht, he, Bm, coef, maxstep, part, part_max, epart, report};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hreport) (void)hipHostFree(hreport);
@@ -199,9 +201,10 @@ void enqueue_iteration(fscc_batch* b, hipStream_t st, const fscc_c128* t1, const
         hip_check(launch_batch_update((const double2*)t1, (const double2*)t2, (const double2*)r1, (const double2*)r2,
                                       (double2*)t1, (double2*)t2, (const double*)c.dbuf[P.b_D1],
                                       (const double*)c.dbuf[P.b_D2], b->dseg, b->dstate, b->ht, b->he, b->part_max,
-                                      b->part, b->Bm, b->coef, b->maxstep, b->tol, b->dactive, b->nsys, b->nblk, st),
+                                      b->part, b->Bm, b->coef, b->maxstep, b->tol, b->shift, b->dactive, b->dupd, b->nsys, b->nblk, st),
                   "batch update");
-        for (size_t k = 0; k < 2; ++k) c.run_op(P.ops[k], &c.L00.g[k]);   // tau of the updated amplitudes
+        // tau of the updated amplitudes (the systems updated in this iteration)
+        for (size_t k = 0; k < 2; ++k) c.run_op(P.ops[k], &c.L00.g[k], -1, nullptr, nullptr, b->dupd);
         hip_check(launch_batch_energy(c.B(P.b_oovv), c.B(P.b_tau), b->dseg, b->dstate, b->maxstep, b->epart, b->report,
                                       b->nsys, b->nblk, st),
                   "batch energy");
@@ -303,6 +306,39 @@ fscc_status fscc_batch_create(const fscc_system* sys, int nsys, fscc_precision p
         hip_check(hipHostMalloc((void**)&b->hreport, sizeof(double) * 6 * nsys, hipHostMallocDefault), "hipHostMalloc");
         hip_check(hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking), "capture stream");
         c.d_active = b->dactive;
+        b->dupd = (int*)c.dalloc(sizeof(int) * nsys);
+        // block tables of the segmented elementwise launches: one per destination buffer
+        c.segb.assign(c.plan.bufs.size(), SegBlocks());
+        for (const Op& o : c.plan.ops) {
+            if (o.kind == OP_GEMM || o.dst < 0 || c.segb[o.dst].sys) continue;
+            std::vector<int> bs;
+            std::vector<long long> b0, b1;
+            for (int s = 0; s < nsys; ++s) {
+                const long long base = b->base[s][o.dst], n = b->sub[s]->bufs[o.dst].n;
+                for (long long k = 0; k < n; k += 256) {
+                    bs.push_back(s);
+                    b0.push_back(base + k);
+                    b1.push_back(base + n);
+                }
+            }
+            SegBlocks sb;
+            sb.nblk = (int)bs.size();
+            int* ds = (int*)c.dalloc(sizeof(int) * std::max<size_t>(1, bs.size()));
+            long long* d0 = (long long*)c.dalloc(sizeof(long long) * std::max<size_t>(1, bs.size()));
+            long long* d1 = (long long*)c.dalloc(sizeof(long long) * std::max<size_t>(1, bs.size()));
+            c.seg_mem.push_back(ds);
+            c.seg_mem.push_back(d0);
+            c.seg_mem.push_back(d1);
+            if (!bs.empty()) {
+                hip_check(hipMemcpy(ds, bs.data(), sizeof(int) * bs.size(), hipMemcpyHostToDevice), "seg tables");
+                hip_check(hipMemcpy(d0, b0.data(), sizeof(long long) * bs.size(), hipMemcpyHostToDevice), "seg tables");
+                hip_check(hipMemcpy(d1, b1.data(), sizeof(long long) * bs.size(), hipMemcpyHostToDevice), "seg tables");
+            }
+            sb.sys = ds;
+            sb.start = d0;
+            sb.end = d1;
+            c.segb[o.dst] = sb;
+        }
         apply_precision(&c, prec);
         return FSCC_OK;
     });
@@ -310,7 +346,7 @@ fscc_status fscc_batch_create(const fscc_system* sys, int nsys, fscc_precision p
         delete b;
         return st;
     }
-    fscc_status r = fscc_batch_reset(b, 6, 1e-10);
+    fscc_status r = fscc_batch_reset(b, 6, 1e-10, 0.0);
     if (r != FSCC_OK) {
         delete b;
         return r;
@@ -378,16 +414,19 @@ fscc_status fscc_batch_set_integrals(fscc_batch* b, int s, fscc_iclass cls, cons
     });
 }
 
-fscc_status fscc_batch_reset(fscc_batch* b, int ndiis, double tol) {
+fscc_status fscc_batch_reset(fscc_batch* b, int ndiis, double tol, double shift) {
     if (!b) return FSCC_EINVAL;
-    if (ndiis < 1 || ndiis > 8 || !(tol > 0.0)) return bfail(b, FSCC_EINVAL, "ndiis must be 1..8 and tol > 0");
+    if (ndiis < 1 || ndiis > 8 || !(tol > 0.0) || !(shift >= 0.0 && shift < 1e6))
+        return bfail(b, FSCC_EINVAL, "ndiis must be 1..8, tol > 0 and 0 <= shift < 1e6");
     return guarded(&b->c, [&]() -> fscc_status {
         b->ndiis = ndiis;
         b->tol = tol;
+        b->shift = shift;
         std::vector<BState> h(b->nsys, BState{0, ndiis - 1, 1, 0, 0, 0, ndiis, 0});
         std::vector<int> a(b->nsys, 1);
         hip_check(hipMemcpy(b->dstate, h.data(), sizeof(BState) * b->nsys, hipMemcpyHostToDevice), "state");
         hip_check(hipMemcpy(b->dactive, a.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice), "active");
+        if (b->dupd) hip_check(hipMemcpy(b->dupd, a.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice), "upd");
         b->drop_graph();   // the tolerance is a kernel argument of the captured update
         return FSCC_OK;
     });
@@ -426,9 +465,9 @@ fscc_status fscc_batch_step(fscc_batch* b, fscc_c128* t1, fscc_c128* t2, fscc_c1
                                               (const double2*)r2, (double2*)t1, (double2*)t2,
                                               (const double*)c.dbuf[c.plan.b_D1], (const double*)c.dbuf[c.plan.b_D2],
                                               b->dseg, b->dstate, b->ht, b->he, b->part_max, b->part, b->Bm, b->coef,
-                                              b->maxstep, b->tol, b->dactive, b->nsys, b->nblk, c.st),
+                                              b->maxstep, b->tol, b->shift, b->dactive, b->dupd, b->nsys, b->nblk, c.st),
                           "batch update");
-                for (size_t k = 0; k < 2; ++k) c.run_op(c.plan.ops[k], &c.L00.g[k]);
+                for (size_t k = 0; k < 2; ++k) c.run_op(c.plan.ops[k], &c.L00.g[k], -1, nullptr, nullptr, b->dupd);
                 hip_check(launch_batch_energy(c.B(c.plan.b_oovv), c.B(c.plan.b_tau), b->dseg, b->dstate, b->maxstep,
                                               b->epart, b->report, b->nsys, b->nblk, c.st),
                           "batch energy");

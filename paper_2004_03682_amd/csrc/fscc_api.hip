@@ -214,7 +214,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
                 ++ns;
                 if (p.K == 0) break;
             }
-            rd.push_back(ZRed{p.c_off, woff, p.M, p.N, p.ldc, ns});
+            rd.push_back(ZRed{p.c_off, woff, p.M, p.N, p.ldc, ns, p.sys, 0});
             woff += (long long)ns * p.M * p.N;
             maxMN = std::max(maxMN, p.M * p.N);
         }
@@ -605,11 +605,11 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
         int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
         if (n1 > 0)
             hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[D.b_D1], ht, he, n1,
-                                    ctx->part_max, nb1, ctx->st),
+                                    ctx->part_max, nb1, ctx->st, D.shift),
                       "jacobi 1");
         if (n2 > 0)
             hip_check(launch_jacobi((const double2*)t2, (const double2*)r2, (const double*)ctx->dbuf[D.b_D2], ht + n1,
-                                    he + n1, n2, ctx->part_max + nb1, nb2, ctx->st),
+                                    he + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift),
                       "jacobi 2");
         int m = (int)ord.size();
         std::vector<const double2*> ev(m);
@@ -843,6 +843,14 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         (void)hipFree(tmp);
         return FSCC_OK;
     });
+}
+
+fscc_status fscc_level_shift(fscc_ctx* ctx, fscc_sector sector, double shift) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "level shift applies to the (0h,0p) sector");
+    if (!(shift >= 0.0 && shift < 1e6)) return fail(ctx, FSCC_EINVAL, "level shift must be in [0, 1e6)");
+    ctx->diis[sector].shift = shift;
+    return FSCC_OK;
 }
 
 fscc_status fscc_set_precision(fscc_ctx* ctx, fscc_precision prec) {

@@ -325,8 +325,10 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
 }
 
 __global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, const double2* __restrict__ W,
-                                                       const ZRed* __restrict__ reds, double ar, double ai, int beta) {
+                                                       const ZRed* __restrict__ reds, double ar, double ai, int beta,
+                                                       const int* __restrict__ active) {
     const ZRed r = reds[blockIdx.y];
+    if (active && !active[r.sys]) return;
     const long long mn = (long long)r.M * r.N;
     long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mn) return;
@@ -348,10 +350,10 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, 
 }
 
 hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
-                                double ai, int beta, hipStream_t st) {
+                                double ai, int beta, hipStream_t st, const int* active) {
     if (nred <= 0 || maxMN <= 0) return hipSuccess;
     dim3 grid((unsigned)((maxMN + kThreads - 1) / kThreads), (unsigned)nred);
-    k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta);
+    k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta, active);
     return hipGetLastError();
 }
 
@@ -368,12 +370,28 @@ __device__ __forceinline__ double2 map_load(const double2* __restrict__ s, uint3
     return x;
 }
 
+// element of this thread in a plain or segmented launch; false if none
+__device__ __forceinline__ bool elem_index(const SegBlocks& sb, long long n, long long* k) {
+    if (sb.sys) {
+        const int b = blockIdx.x;
+        if (!sb.active[sb.sys[b]]) return false;
+        *k = sb.start[b] + threadIdx.x;
+        return *k < sb.end[b];
+    }
+    *k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    return *k < n;
+}
+
+__host__ inline unsigned elem_grid(const SegBlocks& sb, long long n) {
+    return sb.sys ? (unsigned)sb.nblk : (unsigned)((n + kThreads - 1) / kThreads);
+}
+
 template <int NT, bool BIL>
 __global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const double2* __restrict__ src,
                                                 const double2* __restrict__ src2, GatherMaps maps, long long n,
-                                                double ar, double ai, int beta, int conj) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+                                                double ar, double ai, int beta, int conj, SegBlocks sb) {
+    long long k;
+    if (!elem_index(sb, n, &k)) return;
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -398,13 +416,13 @@ __global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const
 }
 
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
-                         long long n, double ar, double ai, int beta, int conj, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + kThreads - 1) / kThreads)), block(kThreads);
+                         long long n, double ar, double ai, int beta, int conj, hipStream_t st, SegBlocks sb) {
+    if (n <= 0 || (sb.sys && sb.nblk <= 0)) return hipSuccess;
+    dim3 grid(elem_grid(sb, n)), block(kThreads);
     bool bil = src2 != nullptr;
 #define FSCC_G(NT)                                                                                               \
-    if (bil) k_gather<NT, true><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj);          \
-    else k_gather<NT, false><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj);
+    if (bil) k_gather<NT, true><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj, sb);      \
+    else k_gather<NT, false><<<grid, block, 0, st>>>(dst, src, src2, maps, n, ar, ai, beta, conj, sb);
     switch (nt) {
         case 1: FSCC_G(1); break;
         case 2: FSCC_G(2); break;
@@ -420,9 +438,9 @@ hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, 
 // elementwise
 
 __global__ __launch_bounds__(256) void k_axpby(double2* __restrict__ dst, const double2* __restrict__ src, long long n,
-                                               double ar, double ai, int beta, int conj) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+                                               double ar, double ai, int beta, int conj, SegBlocks sb) {
+    long long k;
+    if (!elem_index(sb, n, &k)) return;
     double2 x = src[k];
     if (conj) x.y = -x.y;
     double2 out = make_double2(ar * x.x - ai * x.y, ar * x.y + ai * x.x);
@@ -435,16 +453,16 @@ __global__ __launch_bounds__(256) void k_axpby(double2* __restrict__ dst, const 
 }
 
 hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
-                        hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    k_axpby<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, src, n, ar, ai, beta, conj);
+                        hipStream_t st, SegBlocks sb) {
+    if (n <= 0 || (sb.sys && sb.nblk <= 0)) return hipSuccess;
+    k_axpby<<<elem_grid(sb, n), kThreads, 0, st>>>(dst, src, n, ar, ai, beta, conj, sb);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_diag(double2* __restrict__ dst, const double* __restrict__ d,
-                                              const double2* __restrict__ src, long long n) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+                                              const double2* __restrict__ src, long long n, SegBlocks sb) {
+    long long k;
+    if (!elem_index(sb, n, &k)) return;
     double2 o = dst[k], x = src[k];
     double dd = d[k];
     o.x -= dd * x.x;
@@ -452,23 +470,24 @@ __global__ __launch_bounds__(256) void k_diag(double2* __restrict__ dst, const d
     dst[k] = o;
 }
 
-hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    k_diag<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, d, src, n);
+hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st, SegBlocks sb) {
+    if (n <= 0 || (sb.sys && sb.nblk <= 0)) return hipSuccess;
+    k_diag<<<elem_grid(sb, n), kThreads, 0, st>>>(dst, d, src, n, sb);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_mul(double2* __restrict__ dst, const double* __restrict__ d, long long n) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__global__ __launch_bounds__(256) void k_mul(double2* __restrict__ dst, const double* __restrict__ d, long long n,
+                                             SegBlocks sb) {
+    long long k;
+    if (!elem_index(sb, n, &k)) return;
     double2 o = dst[k];
     double dd = d[k];
     dst[k] = make_double2(dd * o.x, dd * o.y);
 }
 
-hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    k_mul<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(dst, d, n);
+hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st, SegBlocks sb) {
+    if (n <= 0 || (sb.sys && sb.nblk <= 0)) return hipSuccess;
+    k_mul<<<elem_grid(sb, n), kThreads, 0, st>>>(dst, d, n, sb);
     return hipGetLastError();
 }
 
@@ -522,12 +541,13 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 
 __global__ __launch_bounds__(256) void k_jacobi(const double2* __restrict__ t, const double2* __restrict__ r,
                                                 const double* __restrict__ D, double2* __restrict__ ht,
-                                                double2* __restrict__ he, long long n, double* part_max) {
+                                                double2* __restrict__ he, long long n, double* part_max,
+                                                double shift) {
     __shared__ double sh[kThreads];
     double mx = 0.0;
     for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
         double2 rr = r[k], tt = t[k];
-        double d = D[k];
+        double d = D[k] - shift;
         double2 s = make_double2(rr.x / d, rr.y / d);
         he[k] = s;
         ht[k] = make_double2(tt.x + s.x, tt.y + s.y);
@@ -539,8 +559,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const double2* __restrict__ t, c
 }
 
 hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
-                         long long n, double* part_max, int nblk, hipStream_t st) {
-    k_jacobi<<<nblk, kThreads, 0, st>>>(t, r, D, hist_t, hist_e, n, part_max);
+                         long long n, double* part_max, int nblk, hipStream_t st, double shift) {
+    k_jacobi<<<nblk, kThreads, 0, st>>>(t, r, D, hist_t, hist_e, n, part_max, shift);
     return hipGetLastError();
 }
 
@@ -761,7 +781,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(const double2* __restrict__ t1,
                                                  const double* __restrict__ D1, const double* __restrict__ D2,
                                                  const BSeg* __restrict__ segs, const BState* __restrict__ state,
                                                  double2* __restrict__ ht, double2* __restrict__ he,
-                                                 double* __restrict__ part_max) {
+                                                 double* __restrict__ part_max, double shift) {
     __shared__ double sh[kThreads];
     const int s = blockIdx.y;
     const BState stt = state[s];
@@ -787,6 +807,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(const double2* __restrict__ t1,
             tt = t2[g.off2 + k - g.n1];
             d = D2[g.off2 + k - g.n1];
         }
+        d -= shift;   // level shift: D < 0 for every amplitude, so |D| grows and the step is damped
         const double2 st = make_double2(rr.x / d, rr.y / d);
         hes[k] = st;
         hts[k] = make_double2(tt.x + st.x, tt.y + st.y);
@@ -836,7 +857,7 @@ __global__ __launch_bounds__(256) void k_bdots(const BSeg* __restrict__ segs, co
 __global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, const double* __restrict__ part, int nblk,
                                                  const double* __restrict__ part_max, double* __restrict__ Bm,
                                                  double* __restrict__ coef, double* __restrict__ maxstep, double tol,
-                                                 int* __restrict__ active) {
+                                                 int* __restrict__ active, int* __restrict__ upd) {
     __shared__ double sh[kThreads];
     __shared__ double row[8];
     const int s = blockIdx.x;
@@ -845,6 +866,7 @@ __global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, con
         if (threadIdx.x == 0) {
             state[s].upd = 0;
             active[s] = 0;
+            upd[s] = 0;
         }
         return;
     }
@@ -884,6 +906,7 @@ __global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, con
     }
     state[s] = stt;
     active[s] = stt.active;
+    upd[s] = stt.upd;
     maxstep[s] = mx;
 }
 
@@ -957,13 +980,13 @@ __global__ __launch_bounds__(256) void k_breport(const double* __restrict__ part
 hipError_t launch_batch_update(const double2* t1, const double2* t2, const double2* r1, const double2* r2,
                                double2* t1o, double2* t2o, const double* D1, const double* D2, const BSeg* segs,
                                BState* state, double2* ht, double2* he, double* part_max, double* part, double* Bm,
-                               double* coef, double* maxstep, double tol, int* active, int nsys, int nblk,
-                               hipStream_t st) {
+                               double* coef, double* maxstep, double tol, double shift, int* active, int* upd,
+                               int nsys, int nblk, hipStream_t st) {
     if (nsys <= 0) return hipSuccess;
     dim3 grid(nblk, nsys);
-    k_bjacobi<<<grid, kThreads, 0, st>>>(t1, t2, r1, r2, D1, D2, segs, state, ht, he, part_max);
+    k_bjacobi<<<grid, kThreads, 0, st>>>(t1, t2, r1, r2, D1, D2, segs, state, ht, he, part_max, shift);
     k_bdots<<<grid, kThreads, 0, st>>>(segs, state, he, part);
-    k_bfinish<<<nsys, kThreads, 0, st>>>(state, part, nblk, part_max, Bm, coef, maxstep, tol, active);
+    k_bfinish<<<nsys, kThreads, 0, st>>>(state, part, nblk, part_max, Bm, coef, maxstep, tol, active, upd);
     k_blincomb<<<grid, kThreads, 0, st>>>(t1o, t2o, segs, state, ht, coef);
     return hipGetLastError();
 }

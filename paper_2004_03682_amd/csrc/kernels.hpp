@@ -59,12 +59,25 @@ hipError_t launch_zgemm_split(bool bf16, int cfg, const void* A, long long sA, c
                               hipStream_t st, int role = 0);
 
 // split-K second pass: C = alpha * sum_s W[w_off + s*M*N + m*N + n] + beta*C
+// (sys: system of a batched launch; skipped when active[sys] == 0)
 struct ZRed {
     long long c_off, w_off;
-    int M, N, ldc, S;
+    int M, N, ldc, S, sys, pad;
 };
 hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
-                                double ai, int beta, hipStream_t st);
+                                double ai, int beta, hipStream_t st, const int* active = nullptr);
+
+// Block table of a segmented elementwise launch over a batched buffer: block b
+// handles elements [start[b], min(start[b] + 256, end[b])) of system sys[b]
+// and does nothing if active[sys[b]] == 0.  sys == nullptr: plain launch over
+// [0, n).
+struct SegBlocks {
+    const int* sys = nullptr;
+    const long long* start = nullptr;
+    const long long* end = nullptr;
+    const int* active = nullptr;
+    int nblk = 0;
+};
 
 // dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
 struct GatherMaps {
@@ -72,17 +85,20 @@ struct GatherMaps {
     const uint32_t* b[4];
 };
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
-                         long long n, double ar, double ai, int beta, int conj, hipStream_t st);
+                         long long n, double ar, double ai, int beta, int conj, hipStream_t st,
+                         SegBlocks sb = SegBlocks());
 
 hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
-                        hipStream_t st);
-hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st);
-hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st);   // dst *= d (real)
+                        hipStream_t st, SegBlocks sb = SegBlocks());
+hipError_t launch_diag(double2* dst, const double* d, const double2* src, long long n, hipStream_t st,
+                       SegBlocks sb = SegBlocks());
+hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st,
+                      SegBlocks sb = SegBlocks());   // dst *= d (real)
 
-// Jacobi: step = r/D; tn = t + step (written to hist_t), e = step (hist_e);
+// Jacobi: step = r/(D - shift); tn = t + step (written to hist_t), e = step (hist_e);
 // per-block max |step| into part_max[block]
 hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
-                         long long n, double* part_max, int nblk, hipStream_t st);
+                         long long n, double* part_max, int nblk, hipStream_t st, double shift = 0.0);
 // sum_b part[b*stride + j] -> out[j]  (j < cols), and max over part_max
 hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
                        hipStream_t st);
@@ -109,12 +125,13 @@ struct BSeg {
 struct BState {
     int count, newest, active, upd, iters, failed, nd, pad;
 };
-// Jacobi step + per-system DIIS (t?o may alias t?); one launch sequence
+// Jacobi step r/(D - shift) + per-system DIIS (t?o may alias t?); one launch sequence.
+// active[s] / upd[s] receive the system's flags after / during this update
 hipError_t launch_batch_update(const double2* t1, const double2* t2, const double2* r1, const double2* r2,
                                double2* t1o, double2* t2o, const double* D1, const double* D2, const BSeg* segs,
                                BState* state, double2* ht, double2* he, double* part_max, double* part, double* Bm,
-                               double* coef, double* maxstep, double tol, int* active, int nsys, int nblk,
-                               hipStream_t st);
+                               double* coef, double* maxstep, double tol, double shift, int* active, int* upd,
+                               int nsys, int nblk, hipStream_t st);
 // per-system E = sum oovv*tau over the T2 segment, then the report rows
 // out[s*6 + {0..5}] = E_re, E_im, max|step|, active, iterations, failed
 hipError_t launch_batch_energy(const double2* oovv, const double2* tau, const BSeg* segs, const BState* state,

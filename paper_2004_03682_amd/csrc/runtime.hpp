@@ -87,6 +87,7 @@ struct Diis {
     double* dB = nullptr;
     int64_t n1 = 0, n2 = 0;
     int b_D1 = -1, b_D2 = -1;
+    double shift = 0.0;   // level shift of the Jacobi denominators
 };
 
 
@@ -165,6 +166,8 @@ struct fscc_ctx {
             if (d.he) (void)hipFree(d.he);
             if (d.dB) (void)hipFree(d.dB);
         }
+        for (void* p : seg_mem)
+            if (p) (void)hipFree(p);
         void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp};
         for (void* p : ps)
             if (p) (void)hipFree(p);
@@ -173,18 +176,32 @@ struct fscc_ctx {
 
     double2* B(int id) const { return (double2*)dbuf[id]; }
 
+    // batched plans: block tables of the segmented elementwise launches, per buffer
+    std::vector<SegBlocks> segb;
+    std::vector<void*> seg_mem;
+
+    SegBlocks seg_of(int buf, const int* flags) const {
+        if (!d_active || buf < 0 || buf >= (int)segb.size() || !segb[buf].sys) return SegBlocks();
+        SegBlocks sb = segb[buf];
+        sb.active = flags ? flags : d_active;
+        return sb;
+    }
+
+    // seg_flags (batched plans only): per-system flags used instead of d_active
+    // for the elementwise and gather launches of this call
     void run_op(const Op& o, const GemmDev* gd, int beta_override = -1, const double2* A_override = nullptr,
-                double2* C_override = nullptr) {
+                double2* C_override = nullptr, const int* seg_flags = nullptr) {
         hipError_t e = hipSuccess;
+        const SegBlocks sb = seg_of(o.dst, seg_flags);
         switch (o.kind) {
             case OP_AXPBY:
-                e = launch_axpby(B(o.dst), B(o.src), o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                e = launch_axpby(B(o.dst), B(o.src), o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st, sb);
                 break;
             case OP_DIAG:
-                e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st);
+                e = launch_diag(B(o.dst), (const double*)dbuf[o.src2], B(o.src), o.n, st, sb);
                 break;
             case OP_MUL:
-                e = launch_mul(B(o.dst), (const double*)dbuf[o.src2], o.n, st);
+                e = launch_mul(B(o.dst), (const double*)dbuf[o.src2], o.n, st, sb);
                 break;
             case OP_GATHER: {
                 GatherMaps gm;
@@ -193,7 +210,7 @@ struct fscc_ctx {
                     gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
                 }
                 e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(), o.n,
-                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st, sb);
                 break;
             }
             case OP_GEMM: {
@@ -211,7 +228,7 @@ struct fscc_ctx {
                                      0.0, 0, o.cA, o.cB, st, g.role, d_active);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
-                                                 beta, st);
+                                                 beta, st, d_active);
                 }
                 break;
             }

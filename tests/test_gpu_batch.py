@@ -87,22 +87,23 @@ def test_batch_layout_and_residual_match_single_systems():
     b.destroy()
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_converges_like_single_systems(use_graph):
+@pytest.mark.parametrize("use_graph,shift,ndiis", [(False, 0.0, 6), (True, 0.0, 6), (True, 0.7, 8)])
+def test_batch_converges_like_single_systems(use_graph, shift, ndiis):
     torch = _torch()
     import paper_2004_03682_amd as F
     systems = [fsgen.make_system(*p) for p in SPECS[:4]] + [fsgen.make_system(7, 30, 4, 0.05, 8)]
     b = make_batch(systems)
     t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
-    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=use_graph)
+    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=use_graph, shift=shift, ndiis=ndiis)
     assert res["converged"].all(), res["iters"]
     T1, T2 = t1.cpu().numpy(), t2.cpu().numpy()
     for k, s in enumerate(systems):
         ctx = single_ctx(s)
         u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
         u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
-        g = F.solve(ctx, u1, u2, tol=1e-10, maxit=150)
+        ctx.level_shift(shift)
+        g = F.solve(ctx, u1, u2, tol=1e-10, maxit=150, ndiis=ndiis)
         print("system", k, "batch", res["E"][k], res["iters"][k], "single", g["E"], g["iters"], flush=True)
         assert g["converged"]
         assert abs(res["E"][k] - g["E"]) <= 1e-10
