@@ -317,10 +317,73 @@ fscc_status fscc_batch_build_residual(fscc_batch *b, const fscc_c128 *t1, const 
 fscc_status fscc_batch_step(fscc_batch *b, fscc_c128 *t1, fscc_c128 *t2, fscc_c128 *r1, fscc_c128 *r2,
                             int use_graph, double *report);
 
+/* Device copies of the batch's Jacobi denominators D (concatenated T1 / T2
+ * layouts, e_i - e_a and e_i + e_j - e_a - e_b, without level shift). */
+fscc_status fscc_batch_denominators(fscc_batch *b, double *D1, double *D2);
+
+/* Per system s: out[s] = max |r / D| over its T1 and T2 segments (host
+ * output, synchronous) -- the size of the Jacobi step a residual r implies. */
+fscc_status fscc_batch_maxnorm(fscc_batch *b, const fscc_c128 *r1, const fscc_c128 *r2, double *out);
+
 /* The batch's executor, for the introspection calls only (fscc_profile,
  * fscc_op_count, fscc_op_info, fscc_autotune, fscc_gemm_config): its
  * operations are the merged grouped launches.  Owned by the batch. */
 fscc_ctx *fscc_batch_context(fscc_batch *b);
+
+/* ---- learned warm start ----------------------------------------------
+ * A small network predicts the converged T2 amplitudes from quantities of
+ * the first two Jacobi iterates, to start the iteration of Eq. (3) closer to
+ * its fixed point.  Per packed T2 element: u = MP2 amplitude (the Jacobi
+ * iterate from t = 0), r = the residual at u, D = the denominator,
+ * v = r / D, s = |u| + |v| + 1e-30.
+ *   features x[8] = (Re u/s, Im u/s, Re v/s, Im v/s,
+ *                    clip(ln((|v|+1e-30)/(|u|+1e-30)), -10, 10)/10, D/10,
+ *                    ln(s)/10, |v|/s)                              (fp32)
+ *   network  h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
+ *            8 -> 256 -> 256 -> 4, fp32, W stored [in][out]; the flat
+ *            parameter vector is W1, b1, W2, b2, W3, b3 (69124 floats)
+ *   head     t = u + v + a v + b u with a = y0 + i y1, b = y2 + i y3
+ *            (y = 0: the ordinary second Jacobi iterate u + v)
+ *   loss     mean over rows of |t - t_converged|^2 / s^2
+ *   update   Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * All arrays are device memory; n = rows.  The network's calls run on its
+ * stream; the fscc_ws_* calls on the stream given. */
+typedef struct fscc_mlp fscc_mlp;
+
+fscc_status fscc_mlp_num_params(size_t *n);
+/* He-normal W1, W2 from a SplitMix64 + Box-Muller stream keyed by seed; zero
+ * W3 and biases (the untrained network returns the second Jacobi iterate). */
+fscc_status fscc_mlp_create(uint64_t seed, void *hip_stream, fscc_mlp **out);
+void fscc_mlp_destroy(fscc_mlp *net);
+const char *fscc_mlp_last_error(const fscc_mlp *net);
+/* Host parameter vectors (count = fscc_mlp_num_params); set resets Adam. */
+fscc_status fscc_mlp_set_params(fscc_mlp *net, const float *host, size_t count);
+fscc_status fscc_mlp_get_params(fscc_mlp *net, float *host, size_t count);
+/* Gradient of the last fscc_mlp_loss_grad call (host copy). */
+fscc_status fscc_mlp_get_grad(fscc_mlp *net, float *host, size_t count);
+
+/* X[n][8] from u, r, D. */
+fscc_status fscc_ws_features(const fscc_c128 *u, const fscc_c128 *r, const double *D, size_t n, float *X,
+                             void *hip_stream);
+/* Y[n][4] = network(X[n][8]) (row chunks of 2^20; allocates its scratch on
+ * first use). */
+fscc_status fscc_mlp_forward(fscc_mlp *net, const float *X, size_t n, float *Y);
+/* out = u + v + a v + b u from Y (Y may be NULL: out = u + v). */
+fscc_status fscc_ws_apply(const float *Y, const fscc_c128 *u, const fscc_c128 *r, const double *D, size_t n,
+                          fscc_c128 *out, void *hip_stream);
+/* out = t + r / D (t may be NULL: out = r / D, e.g. the MP2 amplitudes from
+ * the residual at t = 0). */
+fscc_status fscc_ws_step(const fscc_c128 *t, const fscc_c128 *r, const double *D, size_t n, fscc_c128 *out,
+                         void *hip_stream);
+/* dst[k] = src[idx[k]] for elements of 8 or 16 bytes. */
+fscc_status fscc_ws_gather(const void *src, size_t elem_bytes, const int64_t *idx, size_t n, void *dst,
+                           void *hip_stream);
+/* Loss and gradient (kept in the network) on rows idx[0..n) of the arrays
+ * (idx NULL: rows 0..n-1), n <= 2^24.  Synchronous; *loss on the host. */
+fscc_status fscc_mlp_loss_grad(fscc_mlp *net, const fscc_c128 *u, const fscc_c128 *r, const double *D,
+                               const fscc_c128 *t, const int64_t *idx, size_t n, double *loss);
+/* One Adam step with the current gradient (asynchronous). */
+fscc_status fscc_mlp_adam(fscc_mlp *net, float lr);
 
 #ifdef __cplusplus
 }

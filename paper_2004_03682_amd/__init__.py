@@ -78,6 +78,22 @@ def lib():
             "fscc_batch_build_residual": ([vp, vp, vp, vp, vp], ip),
             "fscc_batch_step": ([vp, vp, vp, vp, vp, ip, dp], ip),
             "fscc_batch_context": ([vp], vp),
+            "fscc_batch_denominators": ([vp, vp, vp], ip),
+            "fscc_batch_maxnorm": ([vp, vp, vp, dp], ip),
+            "fscc_mlp_num_params": ([ctypes.POINTER(sz)], ip),
+            "fscc_mlp_create": ([ctypes.c_uint64, vp, ctypes.POINTER(vp)], ip),
+            "fscc_mlp_destroy": ([vp], None),
+            "fscc_mlp_last_error": ([vp], ctypes.c_char_p),
+            "fscc_mlp_set_params": ([vp, vp, sz], ip),
+            "fscc_mlp_get_params": ([vp, vp, sz], ip),
+            "fscc_mlp_get_grad": ([vp, vp, sz], ip),
+            "fscc_ws_features": ([vp, vp, vp, sz, vp, vp], ip),
+            "fscc_mlp_forward": ([vp, vp, sz, vp], ip),
+            "fscc_ws_apply": ([vp, vp, vp, vp, sz, vp, vp], ip),
+            "fscc_ws_step": ([vp, vp, vp, sz, vp, vp], ip),
+            "fscc_ws_gather": ([vp, sz, vp, sz, vp, vp], ip),
+            "fscc_mlp_loss_grad": ([vp, vp, vp, vp, vp, vp, sz, dp], ip),
+            "fscc_mlp_adam": ([vp, ctypes.c_float], ip),
             "fscc_destroy": ([vp], None),
             "fscc_last_error": ([vp], ctypes.c_char_p),
         }
@@ -95,6 +111,18 @@ def _prec(p):
             raise ValueError(f"unknown precision {p!r}")
         return PRECISIONS[p]
     return int(p)
+
+
+def _ptr(t, dtype=None):
+    """Device pointer of a contiguous GPU tensor of any dtype (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise TypeError("fscc expects contiguous GPU tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _dev_ptr(t, n=None):
@@ -439,6 +467,22 @@ class Batch:
     def context(self):
         return _ContextView(ctypes.c_void_p(lib().fscc_batch_context(self._h)))
 
+    def denominators(self):
+        """(D1, D2) float64 device tensors of the concatenated layouts."""
+        import torch
+        D1 = torch.empty(max(self.n1, 1), dtype=torch.float64, device="cuda")[:self.n1]
+        D2 = torch.empty(max(self.n2, 1), dtype=torch.float64, device="cuda")[:self.n2]
+        self._check(lib().fscc_batch_denominators(self._h, _ptr(D1), _ptr(D2)))
+        return D1, D2
+
+    def maxnorm(self, r1, r2):
+        """Per-system max |r / D| (numpy [nsys])."""
+        import numpy as np
+        out = np.zeros(self.nsys)
+        self._check(lib().fscc_batch_maxnorm(self._h, _dev_ptr(r1, self.n1), _dev_ptr(r2, self.n2),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
     def split(self, t, part):
         """Per-system views of a concatenated vector (part 1: T1, 2: T2)."""
         return [t[(g[0] if part == 1 else g[2]):(g[0] + g[1] if part == 1 else g[2] + g[3])] for g in self.segments]
@@ -478,3 +522,108 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
     E = rep[:, 0] + 1j * rep[:, 1]
     return dict(E=E, iters=rep[:, 4].astype(int), converged=(rep[:, 3] == 0) & (rep[:, 5] == 0),
                 failed=rep[:, 5] != 0, history=hist, times=times)
+
+
+# ---------------------------------------------------------------- learned warm start
+
+def _stream_ptr(stream):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def _ws(st, what):
+    if st != 0:
+        raise FsccError(st, what + " failed")
+
+
+def mlp_num_params():
+    n = ctypes.c_size_t()
+    _ws(lib().fscc_mlp_num_params(ctypes.byref(n)), "fscc_mlp_num_params")
+    return n.value
+
+
+class MLP:
+    """The warm-start network (fscc_mlp_*): parameters and Adam state on the device."""
+
+    def __init__(self, seed=0, stream=None):
+        h = ctypes.c_void_p()
+        _ws(lib().fscc_mlp_create(ctypes.c_uint64(int(seed)), _stream_ptr(stream), ctypes.byref(h)), "fscc_mlp_create")
+        self._h = h
+        self.n_params = mlp_num_params()
+
+    def _check(self, st):
+        if st != 0:
+            msg = lib().fscc_mlp_last_error(self._h)
+            raise FsccError(st, msg.decode() if msg else "")
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(lib().fscc_mlp_set_params(self._h, p.ctypes.data, p.size))
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(self.n_params, np.float32)
+        self._check(lib().fscc_mlp_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def get_grad(self):
+        import numpy as np
+        g = np.zeros(self.n_params, np.float32)
+        self._check(lib().fscc_mlp_get_grad(self._h, g.ctypes.data, g.size))
+        return g
+
+    def forward(self, X, Y):
+        import torch
+        n = X.shape[0]
+        self._check(lib().fscc_mlp_forward(self._h, _ptr(X, torch.float32), n, _ptr(Y, torch.float32)))
+
+    def loss_grad(self, u, r, D, t, idx=None, n=None):
+        import torch
+        n = int(idx.numel()) if idx is not None else int(n if n is not None else u.numel())
+        loss = ctypes.c_double()
+        self._check(lib().fscc_mlp_loss_grad(self._h, _ptr(u, torch.complex128), _ptr(r, torch.complex128),
+                                             _ptr(D, torch.float64), _ptr(t, torch.complex128),
+                                             _ptr(idx, torch.int64), n, ctypes.byref(loss)))
+        return loss.value
+
+    def adam(self, lr):
+        self._check(lib().fscc_mlp_adam(self._h, ctypes.c_float(lr)))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().fscc_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ws_features(u, r, D, X, stream=None):
+    import torch
+    _ws(lib().fscc_ws_features(_ptr(u, torch.complex128), _ptr(r, torch.complex128), _ptr(D, torch.float64),
+                               u.numel(), _ptr(X, torch.float32), _stream_ptr(stream)), "fscc_ws_features")
+
+
+def ws_apply(Y, u, r, D, out, stream=None):
+    import torch
+    _ws(lib().fscc_ws_apply(_ptr(Y, torch.float32), _ptr(u, torch.complex128), _ptr(r, torch.complex128),
+                            _ptr(D, torch.float64), u.numel(), _ptr(out, torch.complex128), _stream_ptr(stream)),
+        "fscc_ws_apply")
+
+
+def ws_step(t, r, D, out, stream=None):
+    import torch
+    _ws(lib().fscc_ws_step(_ptr(t, torch.complex128), _ptr(r, torch.complex128), _ptr(D, torch.float64),
+                           r.numel(), _ptr(out, torch.complex128), _stream_ptr(stream)), "fscc_ws_step")
+
+
+def ws_gather(src, idx, dst, stream=None):
+    import torch
+    eb = src.element_size()
+    _ws(lib().fscc_ws_gather(_ptr(src), eb, _ptr(idx, torch.int64), idx.numel(), _ptr(dst), _stream_ptr(stream)),
+        "fscc_ws_gather")

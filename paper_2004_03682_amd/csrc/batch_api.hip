@@ -159,6 +159,8 @@ struct fscc_batch {
     hipGraphExec_t gexec = nullptr;
     const void* gkey[4] = {nullptr, nullptr, nullptr, nullptr};
 
+    double* maxstep_tmp() { return epart; }   // nsys doubles of scratch outside an iteration
+
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -499,6 +501,36 @@ fscc_status fscc_batch_step(fscc_batch* b, fscc_c128* t1, fscc_c128* t2, fscc_c1
         }
         hip_check(hipStreamSynchronize(c.st), "step sync");
         std::memcpy(report, b->hreport, sizeof(double) * 6 * b->nsys);
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_batch_denominators(fscc_batch* b, double* D1, double* D2) {
+    if (!b || (b->c.n1() && !D1) || (b->c.n2() && !D2)) return FSCC_EINVAL;
+    return guarded(&b->c, [&]() -> fscc_status {
+        fscc_ctx& c = b->c;
+        if (c.n1())
+            hip_check(hipMemcpyAsync(D1, c.dbuf[c.plan.b_D1], sizeof(double) * c.n1(), hipMemcpyDeviceToDevice, c.st),
+                      "D1 copy");
+        if (c.n2())
+            hip_check(hipMemcpyAsync(D2, c.dbuf[c.plan.b_D2], sizeof(double) * c.n2(), hipMemcpyDeviceToDevice, c.st),
+                      "D2 copy");
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_batch_maxnorm(fscc_batch* b, const fscc_c128* r1, const fscc_c128* r2, double* out) {
+    if (!b || !out || (b->c.n1() && !r1) || (b->c.n2() && !r2)) return FSCC_EINVAL;
+    return guarded(&b->c, [&]() -> fscc_status {
+        fscc_ctx& c = b->c;
+        hip_check(launch_batch_maxnorm((const double2*)r1, (const double2*)r2, (const double*)c.dbuf[c.plan.b_D1],
+                                       (const double*)c.dbuf[c.plan.b_D2], b->dseg, b->part_max, b->maxstep_tmp(),
+                                       b->nsys, b->nblk, c.st),
+                  "batch maxnorm");
+        hip_check(hipMemcpyAsync(b->hreport, b->maxstep_tmp(), sizeof(double) * b->nsys, hipMemcpyDeviceToHost, c.st),
+                  "maxnorm d2h");
+        hip_check(hipStreamSynchronize(c.st), "maxnorm sync");
+        std::memcpy(out, b->hreport, sizeof(double) * b->nsys);
         return FSCC_OK;
     });
 }

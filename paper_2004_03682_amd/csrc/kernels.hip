@@ -999,4 +999,52 @@ hipError_t launch_batch_energy(const double2* oovv, const double2* tau, const BS
     return hipGetLastError();
 }
 
+
+// per-system max |r / D| over the T1 and T2 segments
+__global__ __launch_bounds__(256) void k_bmaxnorm(const double2* __restrict__ r1, const double2* __restrict__ r2,
+                                                  const double* __restrict__ D1, const double* __restrict__ D2,
+                                                  const BSeg* __restrict__ segs, double* __restrict__ part) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.y;
+    const BSeg g = segs[s];
+    const long long n = g.n1 + g.n2;
+    double mx = 0.0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
+        double2 rr;
+        double d;
+        if (k < g.n1) {
+            rr = r1[g.off1 + k];
+            d = D1[g.off1 + k];
+        } else {
+            rr = r2[g.off2 + k - g.n1];
+            d = D2[g.off2 + k - g.n1];
+        }
+        const double a = sqrt(rr.x * rr.x + rr.y * rr.y) / fabs(d);
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    const double b = block_max(mx, sh);
+    if (threadIdx.x == 0) part[(long long)s * gridDim.x + blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(256) void k_bmaxnorm_final(const double* __restrict__ part, int nblk,
+                                                        double* __restrict__ out) {
+    __shared__ double sh[kThreads];
+    const int s = blockIdx.x;
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        const double a = part[(long long)s * nblk + b];
+        mx = (a > mx || a != a) ? a : mx;
+    }
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) out[s] = mx;
+}
+
+hipError_t launch_batch_maxnorm(const double2* r1, const double2* r2, const double* D1, const double* D2,
+                                const BSeg* segs, double* part, double* out, int nsys, int nblk, hipStream_t st) {
+    if (nsys <= 0) return hipSuccess;
+    k_bmaxnorm<<<dim3(nblk, nsys), kThreads, 0, st>>>(r1, r2, D1, D2, segs, part);
+    k_bmaxnorm_final<<<nsys, kThreads, 0, st>>>(part, nblk, out);
+    return hipGetLastError();
+}
+
 }  // namespace fscc

@@ -134,6 +134,9 @@ hipError_t launch_batch_update(const double2* t1, const double2* t2, const doubl
                                int nsys, int nblk, hipStream_t st);
 // per-system E = sum oovv*tau over the T2 segment, then the report rows
 // out[s*6 + {0..5}] = E_re, E_im, max|step|, active, iterations, failed
+// out[s] = max |r / D| over system s's T1 and T2 segments
+hipError_t launch_batch_maxnorm(const double2* r1, const double2* r2, const double* D1, const double* D2,
+                                const BSeg* segs, double* part, double* out, int nsys, int nblk, hipStream_t st);
 hipError_t launch_batch_energy(const double2* oovv, const double2* tau, const BSeg* segs, const BState* state,
                                const double* maxstep, double* part, double* out, int nsys, int nblk, hipStream_t st);
 

@@ -1,0 +1,254 @@
+"""Learned warm start of the amplitude iteration (host orchestration).
+
+Every arithmetic step runs in the library's kernels (fscc_ws_*, fscc_mlp_*,
+fscc_batch_*); this module only sequences the calls:
+
+  * first_iterates   u = MP2 amplitudes (the Jacobi iterate from t = 0) and
+                     r = the CCSD residual at u, for every system of a batch.
+  * warm_start       t2 = network prediction from (u, r, D); t1 = the ordinary
+                     Jacobi iterate; per system, if the residual at the
+                     prediction implies a larger Jacobi step than the one at u
+                     (max |R/D|), the system falls back to the plain second
+                     iterate u + v.  Costs three residual evaluations.
+  * collect / train  training rows (u, r, D, t_converged) sampled from batched
+                     solves of synthetic systems; Adam on minibatches.
+  * evaluate         iterations and time to convergence from the MP2 start
+                     against the learned start, same solver settings.
+
+Command line (GPU): python -m paper_2004_03682_amd.warmstart train
+  [--systems 512 --seed0 50000 --out paper_2004_03682_amd/warmstart_mlp.npz]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import (MLP, Batch, FsccError, mlp_num_params, solve_batch, ws_apply, ws_features, ws_gather,  # noqa: F401
+               ws_step)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "warmstart_mlp.npz")
+SOLVER = dict(ndiis=8, shift=1.0)      # DIIS(8) + 1 Eh level shift (same fixed point)
+TRAIN_SEED0, EVAL_SEED0 = 50000, 40000
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _zeros(n, dtype):
+    import torch
+    return torch.zeros(max(n, 1), dtype=dtype, device="cuda")[:n]
+
+
+def make_batch(systems, log=None):
+    """Batch with integrals from the device generator."""
+    import fsgen
+    import torch
+    b = Batch(systems)
+    for k, s in enumerate(systems):
+        for C in fsgen.CLASSES:
+            d = fsgen.class_buffer_gpu(s, C)
+            b.set_integrals(k, C, d)
+            del d
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return b
+
+
+def first_iterates(b, D1, D2):
+    """(u1, u2, r1, r2): the Jacobi iterate from zero and the residual there."""
+    import torch
+    z1, z2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
+    r1, r2 = torch.empty_like(z1), torch.empty_like(z2)
+    b.build_residual(z1, z2, r1, r2)
+    u1, u2 = torch.empty_like(z1), torch.empty_like(z2)
+    ws_step(None, r1, D1, u1)
+    ws_step(None, r2, D2, u2)
+    b.build_residual(u1, u2, r1, r2)
+    return u1, u2, r1, r2
+
+
+def predict(net, u2, r2, D2, out, chunk=1 << 22):
+    """out = network prediction for every row (row chunks bound the scratch)."""
+    import torch
+    n = u2.numel()
+    m = min(chunk, max(n, 1))
+    X = torch.empty((m, 8), dtype=torch.float32, device="cuda")
+    Y = torch.empty((m, 4), dtype=torch.float32, device="cuda")
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        k = c1 - c0
+        ws_features(u2[c0:c1], r2[c0:c1], D2[c0:c1], X[:k])
+        net.forward(X[:k], Y[:k])
+        ws_apply(Y[:k], u2[c0:c1], r2[c0:c1], D2[c0:c1], out[c0:c1])
+
+
+def warm_start(b, net, D1, D2):
+    """Learned starting amplitudes (t1, t2) for a batch, with the MP2 fallback."""
+    import torch
+    u1, u2, r1, r2 = first_iterates(b, D1, D2)
+    base = b.maxnorm(r1, r2)
+    t1, t2 = torch.empty_like(u1), torch.empty_like(u2)
+    ws_step(u1, r1, D1, t1)
+    predict(net, u2, r2, D2, t2)
+    q1, q2 = torch.empty_like(t1), torch.empty_like(t2)
+    b.build_residual(t1, t2, q1, q2)
+    new = b.maxnorm(q1, q2)
+    fallback = ~(new < base)
+    if fallback.any():
+        alt = torch.empty_like(u2)
+        ws_apply(None, u2, r2, D2, alt)
+        for s in np.nonzero(fallback)[0]:
+            off2, n2 = b.segments[s][2], b.segments[s][3]
+            t2[off2:off2 + n2].copy_(alt[off2:off2 + n2])
+    return t1, t2, dict(residual_evaluations=3, fallback=fallback, step_at_u=base, step_at_prediction=new)
+
+
+def collect(systems, per_system=4096, seed=0, tol=1e-9, maxit=150, log=None):
+    """Training rows (u, r, D, t_converged) of the converged systems of one batch."""
+    import torch
+    b = make_batch(systems)
+    D1, D2 = b.denominators()
+    u1, u2, r1, r2 = first_iterates(b, D1, D2)
+    del u1, r1
+    t1, t2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
+    res = solve_batch(b, t1, t2, tol=tol, maxit=maxit, use_graph=True, **SOLVER)
+    rng = np.random.default_rng(seed)
+    idx = []
+    for s in range(len(systems)):
+        if not res["converged"][s]:
+            continue
+        off2, n2 = b.segments[s][2], b.segments[s][3]
+        k = min(per_system, n2)
+        idx.append(off2 + rng.choice(n2, k, replace=False))
+    idx = torch.from_numpy(np.concatenate(idx).astype(np.int64)).cuda()
+    out = {}
+    for name, src in (("u", u2), ("r", r2), ("D", D2), ("t", t2)):
+        dst = torch.empty(idx.numel(), dtype=src.dtype, device="cuda")
+        ws_gather(src, idx, dst)
+        out[name] = dst
+    torch.cuda.synchronize()
+    info = dict(converged=int(res["converged"].sum()), systems=len(systems), rows=int(idx.numel()))
+    b.destroy()
+    del u2, r2, D1, D2, t1, t2
+    torch.cuda.empty_cache()
+    return out, info
+
+
+def train(net, data, steps=4000, batch=8192, lr=1e-3, seed=0, log=None):
+    """Adam on random minibatches of the training rows; returns the loss history."""
+    import torch
+    n = data["u"].numel()
+    rng = np.random.default_rng(seed)
+    hist = []
+    for k in range(steps):
+        idx = torch.from_numpy(rng.integers(0, n, batch).astype(np.int64)).cuda()
+        L = net.loss_grad(data["u"], data["r"], data["D"], data["t"], idx=idx)
+        step_lr = lr * (0.1 ** (k / max(1, steps)))      # exponential decay to lr/10
+        net.adam(step_lr)
+        hist.append(L)
+        if log and (k % 500 == 0 or k == steps - 1):
+            log(f"  train step {k:5d}: loss {L:.4e}")
+    return hist
+
+
+def solve_from(b, t1, t2, tol=1e-10, maxit=300):
+    import torch
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    res = solve_batch(b, t1, t2, tol=tol, maxit=maxit, use_graph=True, **SOLVER)
+    return res, time.perf_counter() - ts
+
+
+def evaluate(net, b, tol=1e-10, maxit=300, log=None):
+    """MP2 start against the learned start on every system of a batch."""
+    import torch
+    D1, D2 = b.denominators()
+    t1, t2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
+    mp2, t_mp2 = solve_from(b, t1, t2, tol, maxit)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    w1, w2, info = warm_start(b, net, D1, D2)
+    torch.cuda.synchronize()
+    t_ws = time.perf_counter() - ts
+    lrn, t_lrn = solve_from(b, w1, w2, tol, maxit)
+    both = mp2["converged"] & lrn["converged"]
+    it_mp2 = mp2["iters"][both]
+    it_lrn = lrn["iters"][both] + info["residual_evaluations"]
+    dE = float(np.abs(mp2["E"][both] - lrn["E"][both]).max()) if both.any() else None
+    out = dict(systems=b.nsys, both_converged=int(both.sum()), mp2_converged=int(mp2["converged"].sum()),
+               learned_converged=int(lrn["converged"].sum()),
+               iterations_mp2_mean=float(it_mp2.mean()) if both.any() else None,
+               iterations_learned_mean=float(it_lrn.mean()) if both.any() else None,
+               iterations_saved_mean=float((it_mp2 - it_lrn).mean()) if both.any() else None,
+               systems_faster=int((it_lrn < it_mp2).sum()), systems_slower=int((it_lrn > it_mp2).sum()),
+               fallback_systems=int(info["fallback"].sum()),
+               seconds_mp2=round(t_mp2, 4), seconds_learned=round(t_ws + t_lrn, 4),
+               seconds_warm_start=round(t_ws, 4), max_abs_dE_mp2_vs_learned=dE,
+               overhead_residual_evaluations=info["residual_evaluations"])
+    if log:
+        log(f"warm start: iterations {out['iterations_mp2_mean']} (MP2) -> {out['iterations_learned_mean']} "
+            f"(learned, incl. {info['residual_evaluations']} start evaluations); time {t_mp2:.2f}s -> "
+            f"{t_ws + t_lrn:.2f}s; fallback {out['fallback_systems']}; max |dE| {dE}")
+    return out
+
+
+def save(net, path, meta):
+    p = net.get_params()
+    np.savez(path, params=p, **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load(net, path=WEIGHTS):
+    with np.load(path, allow_pickle=False) as z:
+        net.set_params(z["params"])
+        return {k: z[k] for k in z.files if k != "params"}
+
+
+def main(argv=None):
+    import fsgen
+    import torch
+    ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
+    ap.add_argument("mode", choices=["train"])
+    ap.add_argument("--systems", type=int, default=512)
+    ap.add_argument("--seed0", type=int, default=TRAIN_SEED0)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--per-system", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--eval", type=int, default=0, help="evaluate on this many systems from seed 40000")
+    a = ap.parse_args(argv)
+    assert torch.cuda.is_available()
+    t0 = time.perf_counter()
+    parts, infos = [], []
+    for c0 in range(0, a.systems, a.chunk):
+        ss = fsgen.batch_systems(min(a.chunk, a.systems - c0), a.seed0 + c0)
+        d, info = collect(ss, a.per_system, seed=a.seed0 + c0)
+        parts.append(d)
+        infos.append(info)
+        _log(f"collected systems {c0}..{c0 + len(ss) - 1}: {info} ({time.perf_counter() - t0:.1f}s)")
+    data = {k: torch.cat([p[k] for p in parts]) for k in ("u", "r", "D", "t")}
+    del parts
+    net = MLP(seed=a.seed)
+    t1 = time.perf_counter()
+    hist = train(net, data, a.steps, a.batch, a.lr, a.seed, log=_log)
+    t_train = time.perf_counter() - t1
+    meta = dict(systems=a.systems, seed0=a.seed0, rows=int(data["u"].numel()), steps=a.steps, batch=a.batch,
+                lr=a.lr, seed=a.seed, loss_first=hist[0], loss_last=float(np.mean(hist[-100:])),
+                train_seconds=t_train, converged=sum(i["converged"] for i in infos))
+    save(net, a.out, meta)
+    _log(f"saved {a.out}: {meta}")
+    if a.eval:
+        b = make_batch(fsgen.batch_systems(a.eval, EVAL_SEED0))
+        evaluate(net, b, log=_log)
+
+
+if __name__ == "__main__":
+    main()
