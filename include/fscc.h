@@ -317,6 +317,12 @@ fscc_status fscc_batch_build_residual(fscc_batch *b, const fscc_c128 *t1, const 
 fscc_status fscc_batch_step(fscc_batch *b, fscc_c128 *t1, fscc_c128 *t2, fscc_c128 *r1, fscc_c128 *r2,
                             int use_graph, double *report);
 
+/* Fresh DIIS subspace for the systems with mask[s] != 0 (host array [nsys]):
+ * they become active again and their next step starts from whatever
+ * amplitudes their segments then hold; iteration counts keep running.
+ * Synchronous. */
+fscc_status fscc_batch_restart(fscc_batch *b, const int *mask);
+
 /* Device copies of the batch's Jacobi denominators D (concatenated T1 / T2
  * layouts, e_i - e_a and e_i + e_j - e_a - e_b, without level shift). */
 fscc_status fscc_batch_denominators(fscc_batch *b, double *D1, double *D2);
@@ -344,7 +350,8 @@ fscc_ctx *fscc_batch_context(fscc_batch *b);
  *            parameter vector is W1, b1, W2, b2, W3, b3 (69124 floats)
  *   head     t = u + v + a v + b u with a = y0 + i y1, b = y2 + i y3
  *            (y = 0: the ordinary second Jacobi iterate u + v)
- *   loss     mean over rows of |t - t_converged|^2 / s^2
+ *   loss     mode 0: mean over rows of |t - t_converged|^2 / s^2 (relative)
+ *            mode 1: sum |t - t_converged|^2 / sum s^2 (absolute)
  *   update   Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
  * All arrays are device memory; n = rows.  The network's calls run on its
  * stream; the fscc_ws_* calls on the stream given. */
@@ -381,7 +388,7 @@ fscc_status fscc_ws_gather(const void *src, size_t elem_bytes, const int64_t *id
 /* Loss and gradient (kept in the network) on rows idx[0..n) of the arrays
  * (idx NULL: rows 0..n-1), n <= 2^24.  Synchronous; *loss on the host. */
 fscc_status fscc_mlp_loss_grad(fscc_mlp *net, const fscc_c128 *u, const fscc_c128 *r, const double *D,
-                               const fscc_c128 *t, const int64_t *idx, size_t n, double *loss);
+                               const fscc_c128 *t, const int64_t *idx, size_t n, int mode, double *loss);
 /* One Adam step with the current gradient (asynchronous). */
 fscc_status fscc_mlp_adam(fscc_mlp *net, float lr);
 

@@ -16,7 +16,9 @@ Definition (one packed T2 element k of a system):
            y = h2 W3 + b3 (256 -> 4); W stored [in][out]
   head     a = y0 + i y1, b = y2 + i y3;  t_pred = u + v + a v + b u
            (y = 0 gives the ordinary second Jacobi iterate u + v)
-  loss     L = (1/N) sum_k |t_pred_k - t_k|^2 / s_k^2   (t = converged T2)
+  loss     mode 0 (relative):  L = (1/N) sum_k |t_pred_k - t_k|^2 / s_k^2
+           mode 1 (absolute):  L = sum_k |t_pred_k - t_k|^2 / sum_k s_k^2
+           (t = converged T2; mode 1 weights elements by their size)
   Adam     (Kingma & Ba, ICLR 2015) with bias correction:
            m = b1 m + (1-b1) g,  w = b2 w + (1-b2) g^2,
            p -= lr * (m / (1-b1^n)) / (sqrt(w / (1-b2^n)) + eps)
@@ -77,18 +79,21 @@ def predict(y, u, v):
     return u + v + a * v + b * u
 
 
-def loss_and_dy(y, u, v, t, s):
-    """Loss and dL/dy for the head above."""
+def loss_and_dy(y, u, v, t, s, mode=0):
+    """Loss and dL/dy for the head above (mode 0 relative, 1 absolute)."""
     n = y.shape[0]
     e = predict(y, u, v) - t
-    w = 1.0 / (s * s)
-    L = float(np.sum(np.abs(e) ** 2 * w) / n)
+    if mode == 0:
+        w = 1.0 / (s * s) / n
+    else:
+        w = np.full(n, 1.0 / np.sum(s * s))
+    L = float(np.sum(np.abs(e) ** 2 * w))
     ce = np.conj(e)
     dy = np.empty_like(y)
-    dy[:, 0] = 2.0 * np.real(ce * v) * w / n
-    dy[:, 1] = -2.0 * np.imag(ce * v) * w / n
-    dy[:, 2] = 2.0 * np.real(ce * u) * w / n
-    dy[:, 3] = -2.0 * np.imag(ce * u) * w / n
+    dy[:, 0] = 2.0 * np.real(ce * v) * w
+    dy[:, 1] = -2.0 * np.imag(ce * v) * w
+    dy[:, 2] = 2.0 * np.real(ce * u) * w
+    dy[:, 3] = -2.0 * np.imag(ce * u) * w
     return L, dy
 
 
@@ -107,9 +112,9 @@ def backward(p, cache, dy):
     return np.concatenate([g.ravel() for g in (gW1, gb1, gW2, gb2, gW3, gb3)])
 
 
-def loss_and_grad(p, x, u, v, t, s):
+def loss_and_grad(p, x, u, v, t, s, mode=0):
     y, cache = forward(p, x)
-    L, dy = loss_and_dy(y, u, v, t, s)
+    L, dy = loss_and_dy(y, u, v, t, s, mode)
     return L, backward(p, cache, dy)
 
 

@@ -79,6 +79,7 @@ def lib():
             "fscc_batch_step": ([vp, vp, vp, vp, vp, ip, dp], ip),
             "fscc_batch_context": ([vp], vp),
             "fscc_batch_denominators": ([vp, vp, vp], ip),
+            "fscc_batch_restart": ([vp, vp], ip),
             "fscc_batch_maxnorm": ([vp, vp, vp, dp], ip),
             "fscc_mlp_num_params": ([ctypes.POINTER(sz)], ip),
             "fscc_mlp_create": ([ctypes.c_uint64, vp, ctypes.POINTER(vp)], ip),
@@ -92,7 +93,7 @@ def lib():
             "fscc_ws_apply": ([vp, vp, vp, vp, sz, vp, vp], ip),
             "fscc_ws_step": ([vp, vp, vp, sz, vp, vp], ip),
             "fscc_ws_gather": ([vp, sz, vp, sz, vp, vp], ip),
-            "fscc_mlp_loss_grad": ([vp, vp, vp, vp, vp, vp, sz, dp], ip),
+            "fscc_mlp_loss_grad": ([vp, vp, vp, vp, vp, vp, sz, ip, dp], ip),
             "fscc_mlp_adam": ([vp, ctypes.c_float], ip),
             "fscc_destroy": ([vp], None),
             "fscc_last_error": ([vp], ctypes.c_char_p),
@@ -467,6 +468,13 @@ class Batch:
     def context(self):
         return _ContextView(ctypes.c_void_p(lib().fscc_batch_context(self._h)))
 
+    def restart(self, mask):
+        """Fresh DIIS subspace for the systems where mask is true."""
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.int32))
+        assert m.size == self.nsys
+        self._check(lib().fscc_batch_restart(self._h, m.ctypes.data))
+
     def denominators(self):
         """(D1, D2) float64 device tensors of the concatenated layouts."""
         import torch
@@ -499,7 +507,8 @@ class Batch:
             pass
 
 
-def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None, shift=0.0):
+def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None, shift=0.0, reset=True,
+                first=None):
     """Iterate every system of a batch until each one's max|step| < tol.
     Returns dict(E [complex per system], iters, converged, failed, history
     (list of reports), times (host time after each iteration))."""
@@ -508,10 +517,17 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
     import torch
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
-    batch.reset(ndiis, tol, shift)
+    if reset:
+        batch.reset(ndiis, tol, shift)
     hist, times = [], []
     rep = None
-    for k in range(1, maxit + 1):
+    if first is not None:            # reports of iterations already taken
+        hist.extend(first)
+        times.extend([time.perf_counter()] * len(first))
+        rep = first[-1]
+    for k in range(len(hist) + 1, maxit + 1):
+        if rep is not None and not rep[:, 3].any():
+            break
         rep = batch.step(t1, t2, r1, r2, use_graph)
         hist.append(rep)
         times.append(time.perf_counter())
@@ -579,13 +595,14 @@ class MLP:
         n = X.shape[0]
         self._check(lib().fscc_mlp_forward(self._h, _ptr(X, torch.float32), n, _ptr(Y, torch.float32)))
 
-    def loss_grad(self, u, r, D, t, idx=None, n=None):
+    def loss_grad(self, u, r, D, t, idx=None, n=None, mode=0):
+        """mode 0: relative loss, 1: absolute (size-weighted) loss."""
         import torch
         n = int(idx.numel()) if idx is not None else int(n if n is not None else u.numel())
         loss = ctypes.c_double()
         self._check(lib().fscc_mlp_loss_grad(self._h, _ptr(u, torch.complex128), _ptr(r, torch.complex128),
                                              _ptr(D, torch.float64), _ptr(t, torch.complex128),
-                                             _ptr(idx, torch.int64), n, ctypes.byref(loss)))
+                                             _ptr(idx, torch.int64), n, int(mode), ctypes.byref(loss)))
         return loss.value
 
     def adam(self, lr):

@@ -535,4 +535,28 @@ fscc_status fscc_batch_maxnorm(fscc_batch* b, const fscc_c128* r1, const fscc_c1
     });
 }
 
+fscc_status fscc_batch_restart(fscc_batch* b, const int* mask) {
+    if (!b || !mask) return FSCC_EINVAL;
+    return guarded(&b->c, [&]() -> fscc_status {
+        fscc_ctx& c = b->c;
+        std::vector<BState> h(b->nsys);
+        std::vector<int> a(b->nsys);
+        hip_check(hipStreamSynchronize(c.st), "restart sync");
+        hip_check(hipMemcpy(h.data(), b->dstate, sizeof(BState) * b->nsys, hipMemcpyDeviceToHost), "state d2h");
+        hip_check(hipMemcpy(a.data(), b->dactive, sizeof(int) * b->nsys, hipMemcpyDeviceToHost), "active d2h");
+        for (int s = 0; s < b->nsys; ++s) {
+            if (!mask[s]) continue;
+            h[s].count = 0;
+            h[s].newest = h[s].nd - 1;
+            h[s].active = 1;
+            h[s].upd = 0;
+            h[s].failed = 0;
+            a[s] = 1;
+        }
+        hip_check(hipMemcpy(b->dstate, h.data(), sizeof(BState) * b->nsys, hipMemcpyHostToDevice), "state h2d");
+        hip_check(hipMemcpy(b->dactive, a.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice), "active h2d");
+        return FSCC_OK;
+    });
+}
+
 }  // extern "C"

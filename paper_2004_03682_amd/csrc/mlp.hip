@@ -7,7 +7,8 @@
 // features x = (Re u/s, Im u/s, Re v/s, Im v/s, clip(ln((|v|+1e-30)/(|u|+1e-30)),
 // -10, 10)/10, D/10, ln(s)/10, |v|/s); the network output y gives
 // a = y0 + i y1, b = y2 + i y3 and the prediction t = u + v + a v + b u; the
-// training loss is mean |t - t_converged|^2 / s^2.
+// training loss is mean |t - t_converged|^2 / s^2 (relative) or
+// sum |t - t_converged|^2 / sum s^2 (absolute).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -174,10 +175,33 @@ __global__ __launch_bounds__(256) void k_ws_apply(const float* __restrict__ Y, c
                           uu.y + v.y + (ar * v.y + ai * v.x) + (br * uu.y + bi * uu.x));
 }
 
-// loss rows and dL/dy (scaled by 1/n); per-block loss partials
+// per-block partial sums of s^2 (the absolute loss normaliser)
+__global__ __launch_bounds__(256) void k_ws_s2(const double2* __restrict__ u, const double2* __restrict__ r,
+                                               const double* __restrict__ D, long long n, double* __restrict__ part) {
+    __shared__ double sh[kT];
+    const long long k = (long long)blockIdx.x * kT + threadIdx.x;
+    double q = 0.0;
+    if (k < n) {
+        double2 v;
+        double s;
+        ws_v_s(u[k], r[k], D[k], &v, &s);
+        q = s * s;
+    }
+    sh[threadIdx.x] = q;
+    __syncthreads();
+    for (int s2 = kT / 2; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// loss rows and dL/dy; weight w_k = 1/(n s_k^2) (mode 0) or 1/sum s^2 (mode 1,
+// *norm holds sum s^2); per-block loss partials (already weighted)
 __global__ __launch_bounds__(256) void k_ws_head(const float* __restrict__ Y, const double2* __restrict__ u,
                                                  const double2* __restrict__ r, const double* __restrict__ D,
-                                                 const double2* __restrict__ t, long long n, float* __restrict__ dY,
+                                                 const double2* __restrict__ t, long long n, int mode,
+                                                 const double* __restrict__ norm, float* __restrict__ dY,
                                                  double* __restrict__ part) {
     __shared__ double sh[kT];
     const long long k = (long long)blockIdx.x * kT + threadIdx.x;
@@ -191,9 +215,9 @@ __global__ __launch_bounds__(256) void k_ws_head(const float* __restrict__ Y, co
         const double2 tt = t[k];
         const double er = uu.x + v.x + (ar * v.x - ai * v.y) + (br * uu.x - bi * uu.y) - tt.x;
         const double ei = uu.y + v.y + (ar * v.y + ai * v.x) + (br * uu.y + bi * uu.x) - tt.y;
-        const double w = 1.0 / (s * s);
+        const double w = mode == 0 ? 1.0 / (s * s) / (double)n : 1.0 / *norm;
         l = (er * er + ei * ei) * w;
-        const double f = 2.0 * w / (double)n;
+        const double f = 2.0 * w;
         // conj(e) * v = (er v.x + ei v.y) + i (er v.y - ei v.x)
         dY[k * F_OUT] = (float)(f * (er * v.x + ei * v.y));
         dY[k * F_OUT + 1] = (float)(-f * (er * v.y - ei * v.x));
@@ -348,7 +372,7 @@ hipError_t ensure_train(fscc_mlp* n, size_t rows) {
     if (ok(e)) e = dalloc(&n->dY, b * F_OUT);
     if (ok(e)) e = dalloc(&n->cpart, ((b + 255) / 256) * HID);
     if (ok(e)) e = dalloc(&n->part, (b + 255) / 256);
-    if (ok(e)) e = dalloc(&n->loss, 1);
+    if (ok(e)) e = dalloc(&n->loss, 2);
     if (ok(e)) e = dalloc(&n->bD, b);
     if (ok(e)) e = dalloc(&n->bu, b);
     if (ok(e)) e = dalloc(&n->br, b);
@@ -379,7 +403,7 @@ hipError_t colsum(fscc_mlp* n, const float* H, int M, int N, float* out) {
 }
 
 // forward + loss + backward on the staged rows (bu, br, bD, bt) -> n->g, n->loss
-hipError_t loss_grad_staged(fscc_mlp* n, size_t rows) {
+hipError_t loss_grad_staged(fscc_mlp* n, size_t rows, int mode) {
     const int M = (int)rows;
     const float* P = n->p;
     float* G = n->g;
@@ -388,8 +412,12 @@ hipError_t loss_grad_staged(fscc_mlp* n, size_t rows) {
     hipError_t e = hipGetLastError();
     if (ok(e)) e = forward_rows(n, n->X, rows, n->h1, n->h2, n->Y);
     if (!ok(e)) return e;
-    k_ws_head<<<grid1(M), kT, 0, st>>>(n->Y, n->bu, n->br, n->bD, n->bt, M, n->dY, n->part);
-    k_sum_parts<<<1, kT, 0, st>>>(n->part, (int)grid1(M), 1.0 / (double)M, n->loss);
+    if (mode == 1) {
+        k_ws_s2<<<grid1(M), kT, 0, st>>>(n->bu, n->br, n->bD, M, n->part);
+        k_sum_parts<<<1, kT, 0, st>>>(n->part, (int)grid1(M), 1.0, n->loss + 1);
+    }
+    k_ws_head<<<grid1(M), kT, 0, st>>>(n->Y, n->bu, n->br, n->bD, n->bt, M, mode, n->loss + 1, n->dY, n->part);
+    k_sum_parts<<<1, kT, 0, st>>>(n->part, (int)grid1(M), 1.0, n->loss);
     e = hipGetLastError();
     // W3, b3
     if (ok(e)) e = sgemm<true, false, SG_PLAIN>(n->h2, n->dY, G + OFF_W3, HID, F_OUT, M, HID, F_OUT, F_OUT, nullptr,
@@ -558,8 +586,9 @@ fscc_status fscc_mlp_forward(fscc_mlp* n, const float* X, size_t rows, float* Y)
 }
 
 fscc_status fscc_mlp_loss_grad(fscc_mlp* n, const fscc_c128* u, const fscc_c128* r, const double* D,
-                               const fscc_c128* t, const int64_t* idx, size_t rows, double* loss) {
-    if (!n || !loss || rows == 0 || !u || !r || !D || !t || rows > (size_t)1 << 24) return FSCC_EINVAL;
+                               const fscc_c128* t, const int64_t* idx, size_t rows, int mode, double* loss) {
+    if (!n || !loss || rows == 0 || !u || !r || !D || !t || rows > (size_t)1 << 24 || mode < 0 || mode > 1)
+        return FSCC_EINVAL;
     hipError_t e = ensure_train(n, rows);
     if (!ok(e)) return herr(n, e, "training scratch");
     hipStream_t st = n->st;
@@ -579,7 +608,7 @@ fscc_status fscc_mlp_loss_grad(fscc_mlp* n, const fscc_c128* u, const fscc_c128*
         if (ok(e)) e = hipMemcpyAsync(n->bD, D, 8 * rows, hipMemcpyDeviceToDevice, st);
     }
     if (ok(e)) e = hipGetLastError();
-    if (ok(e)) e = loss_grad_staged(n, rows);
+    if (ok(e)) e = loss_grad_staged(n, rows, mode);
     if (ok(e)) e = hipMemcpyAsync(n->hloss, n->loss, sizeof(double), hipMemcpyDeviceToHost, st);
     if (ok(e)) e = hipStreamSynchronize(st);
     if (!ok(e)) return herr(n, e, "loss/grad");

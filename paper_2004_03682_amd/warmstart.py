@@ -5,11 +5,12 @@ fscc_batch_*); this module only sequences the calls:
 
   * first_iterates   u = MP2 amplitudes (the Jacobi iterate from t = 0) and
                      r = the CCSD residual at u, for every system of a batch.
-  * warm_start       t2 = network prediction from (u, r, D); t1 = the ordinary
-                     Jacobi iterate; per system, if the residual at the
-                     prediction implies a larger Jacobi step than the one at u
-                     (max |R/D|), the system falls back to the plain second
-                     iterate u + v.  Costs three residual evaluations.
+  * solve_learned    t2 = network prediction from (u, r, D), t1 = the Jacobi
+                     step of T1; per system, if the T2 residual at the
+                     prediction (computed by the first iteration) implies a
+                     larger Jacobi step than the one at u (max |R/D|), the
+                     system falls back to the MP2 start.  Two residual
+                     evaluations before the first iteration.
   * collect / train  training rows (u, r, D, t_converged) sampled from batched
                      solves of synthetic systems; Adam on minibatches.
   * evaluate         iterations and time to convergence from the MP2 start
@@ -61,8 +62,11 @@ def make_batch(systems, log=None):
 
 
 def first_iterates(b, D1, D2):
-    """(u1, u2, r1, r2): the Jacobi iterate from zero and the residual there."""
+    """(u1, u2, r1, r2): the Jacobi iterate from zero and the residual there.
+    Resets the batch's convergence mask (residuals of frozen systems are not
+    computed)."""
     import torch
+    b.reset(SOLVER["ndiis"], 1e-10, SOLVER["shift"])
     z1, z2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
     r1, r2 = torch.empty_like(z1), torch.empty_like(z2)
     b.build_residual(z1, z2, r1, r2)
@@ -88,25 +92,36 @@ def predict(net, u2, r2, D2, out, chunk=1 << 22):
         ws_apply(Y[:k], u2[c0:c1], r2[c0:c1], D2[c0:c1], out[c0:c1])
 
 
-def warm_start(b, net, D1, D2):
-    """Learned starting amplitudes (t1, t2) for a batch, with the MP2 fallback."""
+def solve_learned(b, net, D1, D2, tol=1e-10, maxit=300):
+    """Learned start and the solve that follows it, for every system of a batch.
+
+    Start: t2 = network prediction from (u, r, D), t1 = the Jacobi step of T1
+    at (0, u) -- two residual evaluations (at 0 and at u).  The first
+    iteration from there computes the residual at the prediction; a system
+    whose T2 part implies a larger Jacobi step (max |R/D|) than at the MP2
+    amplitudes falls back to the MP2 start (t1 = 0, t2 = u) with a fresh DIIS
+    subspace (its wasted iteration is counted).  Returns (result, info)."""
     import torch
     u1, u2, r1, r2 = first_iterates(b, D1, D2)
-    base = b.maxnorm(r1, r2)
-    t1, t2 = torch.empty_like(u1), torch.empty_like(u2)
-    ws_step(u1, r1, D1, t1)
+    z1 = torch.zeros_like(u1)
+    base = b.maxnorm(z1, r2)
+    t2 = torch.empty_like(u2)
     predict(net, u2, r2, D2, t2)
-    q1, q2 = torch.empty_like(t1), torch.empty_like(t2)
-    b.build_residual(t1, t2, q1, q2)
-    new = b.maxnorm(q1, q2)
+    t1 = torch.empty_like(u1)
+    ws_step(u1, r1, D1, t1)
+    b.reset(SOLVER["ndiis"], tol, SOLVER["shift"])
+    q1, q2 = torch.empty_like(u1), torch.empty_like(u2)
+    first = b.step(t1, t2, q1, q2, use_graph=False)
+    new = b.maxnorm(z1, q2)
     fallback = ~(new < base)
     if fallback.any():
-        alt = torch.empty_like(u2)
-        ws_apply(None, u2, r2, D2, alt)
         for s in np.nonzero(fallback)[0]:
-            off2, n2 = b.segments[s][2], b.segments[s][3]
-            t2[off2:off2 + n2].copy_(alt[off2:off2 + n2])
-    return t1, t2, dict(residual_evaluations=3, fallback=fallback, step_at_u=base, step_at_prediction=new)
+            off1, n1, off2, n2 = b.segments[s]
+            t1[off1:off1 + n1].zero_()
+            t2[off2:off2 + n2].copy_(u2[off2:off2 + n2])
+        b.restart(fallback)
+    res = solve_batch(b, t1, t2, tol=tol, maxit=maxit, use_graph=True, reset=False, first=[first], **SOLVER)
+    return res, dict(start_evaluations=2, fallback=fallback, step_at_u=base, step_at_prediction=new)
 
 
 def collect(systems, per_system=4096, seed=0, tol=1e-9, maxit=150, log=None):
@@ -140,7 +155,7 @@ def collect(systems, per_system=4096, seed=0, tol=1e-9, maxit=150, log=None):
     return out, info
 
 
-def train(net, data, steps=4000, batch=8192, lr=1e-3, seed=0, log=None):
+def train(net, data, steps=4000, batch=8192, lr=1e-3, seed=0, log=None, mode=1):
     """Adam on random minibatches of the training rows; returns the loss history."""
     import torch
     n = data["u"].numel()
@@ -148,7 +163,7 @@ def train(net, data, steps=4000, batch=8192, lr=1e-3, seed=0, log=None):
     hist = []
     for k in range(steps):
         idx = torch.from_numpy(rng.integers(0, n, batch).astype(np.int64)).cuda()
-        L = net.loss_grad(data["u"], data["r"], data["D"], data["t"], idx=idx)
+        L = net.loss_grad(data["u"], data["r"], data["D"], data["t"], idx=idx, mode=mode)
         step_lr = lr * (0.1 ** (k / max(1, steps)))      # exponential decay to lr/10
         net.adam(step_lr)
         hist.append(L)
@@ -165,36 +180,50 @@ def solve_from(b, t1, t2, tol=1e-10, maxit=300):
     return res, time.perf_counter() - ts
 
 
+def iterations_to(res, thr=1e-8):
+    """Per system: first iteration after which |E_k - E_final| < thr holds (0 if never)."""
+    h = res["history"]
+    E = np.array([[r[s, 0] + 1j * r[s, 1] for s in range(r.shape[0])] for r in h])   # [iters, nsys]
+    out = np.zeros(E.shape[1], int)
+    for s in range(E.shape[1]):
+        bad = np.nonzero(np.abs(E[:, s] - E[-1, s]) >= thr)[0]
+        out[s] = (bad[-1] + 2) if bad.size else 1
+    return out
+
+
 def evaluate(net, b, tol=1e-10, maxit=300, log=None):
-    """MP2 start against the learned start on every system of a batch."""
+    """MP2 start against the learned start on every system of a batch
+    (iterations counted from t = 0 on both sides; the learned side adds its two
+    start-up residual evaluations)."""
     import torch
     D1, D2 = b.denominators()
     t1, t2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
     mp2, t_mp2 = solve_from(b, t1, t2, tol, maxit)
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    w1, w2, info = warm_start(b, net, D1, D2)
-    torch.cuda.synchronize()
-    t_ws = time.perf_counter() - ts
-    lrn, t_lrn = solve_from(b, w1, w2, tol, maxit)
+    lrn, info = solve_learned(b, net, D1, D2, tol, maxit)
+    t_lrn = time.perf_counter() - ts
     both = mp2["converged"] & lrn["converged"]
-    it_mp2 = mp2["iters"][both]
-    it_lrn = lrn["iters"][both] + info["residual_evaluations"]
-    dE = float(np.abs(mp2["E"][both] - lrn["E"][both]).max()) if both.any() else None
-    out = dict(systems=b.nsys, both_converged=int(both.sum()), mp2_converged=int(mp2["converged"].sum()),
-               learned_converged=int(lrn["converged"].sum()),
-               iterations_mp2_mean=float(it_mp2.mean()) if both.any() else None,
-               iterations_learned_mean=float(it_lrn.mean()) if both.any() else None,
-               iterations_saved_mean=float((it_mp2 - it_lrn).mean()) if both.any() else None,
-               systems_faster=int((it_lrn < it_mp2).sum()), systems_slower=int((it_lrn > it_mp2).sum()),
-               fallback_systems=int(info["fallback"].sum()),
-               seconds_mp2=round(t_mp2, 4), seconds_learned=round(t_ws + t_lrn, 4),
-               seconds_warm_start=round(t_ws, 4), max_abs_dE_mp2_vs_learned=dE,
-               overhead_residual_evaluations=info["residual_evaluations"])
+    extra = info["start_evaluations"]
+    it_mp2, it_lrn = mp2["iters"][both], lrn["iters"][both] + extra
+    e8_mp2, e8_lrn = iterations_to(mp2)[both], iterations_to(lrn)[both] + extra
+    ok = bool(both.any())
+    dE = float(np.abs(mp2["E"][both] - lrn["E"][both]).max()) if ok else None
+    out = {"systems": b.nsys, "both_converged": int(both.sum()), "mp2_converged": int(mp2["converged"].sum()),
+           "learned_converged": int(lrn["converged"].sum()),
+           "iterations_to_1e-8_mp2_mean": float(e8_mp2.mean()) if ok else None,
+           "iterations_to_1e-8_learned_mean": float(e8_lrn.mean()) if ok else None,
+           "iterations_mp2_mean": float(it_mp2.mean()) if ok else None,
+           "iterations_learned_mean": float(it_lrn.mean()) if ok else None,
+           "systems_faster_to_1e-8": int((e8_lrn < e8_mp2).sum()), "systems_slower_to_1e-8": int((e8_lrn > e8_mp2).sum()),
+           "fallback_systems": int(info["fallback"].sum()),
+           "seconds_mp2": round(t_mp2, 4), "seconds_learned": round(t_lrn, 4),
+           "max_abs_dE_mp2_vs_learned": dE, "start_residual_evaluations": extra}
     if log:
-        log(f"warm start: iterations {out['iterations_mp2_mean']} (MP2) -> {out['iterations_learned_mean']} "
-            f"(learned, incl. {info['residual_evaluations']} start evaluations); time {t_mp2:.2f}s -> "
-            f"{t_ws + t_lrn:.2f}s; fallback {out['fallback_systems']}; max |dE| {dE}")
+        log(f"warm start: iterations to 1e-8 Eh {out['iterations_to_1e-8_mp2_mean']} (MP2) -> "
+            f"{out['iterations_to_1e-8_learned_mean']} (learned, incl. {extra} start evaluations); to convergence "
+            f"{out['iterations_mp2_mean']} -> {out['iterations_learned_mean']}; time {t_mp2:.2f}s -> {t_lrn:.2f}s; "
+            f"fallback {out['fallback_systems']}; max |dE| {dE}")
     return out
 
 
@@ -222,6 +251,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--loss", type=int, default=1, help="0 relative, 1 absolute (size-weighted)")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--eval", type=int, default=0, help="evaluate on this many systems from seed 40000")
     a = ap.parse_args(argv)
@@ -238,10 +268,10 @@ def main(argv=None):
     del parts
     net = MLP(seed=a.seed)
     t1 = time.perf_counter()
-    hist = train(net, data, a.steps, a.batch, a.lr, a.seed, log=_log)
+    hist = train(net, data, a.steps, a.batch, a.lr, a.seed, log=_log, mode=a.loss)
     t_train = time.perf_counter() - t1
     meta = dict(systems=a.systems, seed0=a.seed0, rows=int(data["u"].numel()), steps=a.steps, batch=a.batch,
-                lr=a.lr, seed=a.seed, loss_first=hist[0], loss_last=float(np.mean(hist[-100:])),
+                lr=a.lr, seed=a.seed, loss_mode=a.loss, loss_first=hist[0], loss_last=float(np.mean(hist[-100:])),
                 train_seconds=t_train, converged=sum(i["converged"] for i in infos))
     save(net, a.out, meta)
     _log(f"saved {a.out}: {meta}")

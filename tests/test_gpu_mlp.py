@@ -73,8 +73,8 @@ def test_forward_matches_oracle():
     net.destroy()
 
 
-@pytest.mark.parametrize("gather", [False, True])
-def test_loss_and_gradient_match_oracle(gather):
+@pytest.mark.parametrize("gather,mode", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_loss_and_gradient_match_oracle(gather, mode):
     torch = _torch()
     import paper_2004_03682_amd as F
     u, r, D, t = _rows(4, 5000)
@@ -83,14 +83,14 @@ def test_loss_and_gradient_match_oracle(gather):
     net.set_params(p)
     if gather:
         idx = np.random.default_rng(6).choice(u.size, 1777, replace=False)
-        L = net.loss_grad(dev(u), dev(r), dev(D), dev(t), idx=dev(idx.astype(np.int64)))
+        L = net.loss_grad(dev(u), dev(r), dev(D), dev(t), idx=dev(idx.astype(np.int64)), mode=mode)
         u, r, D, t = u[idx], r[idx], D[idx], t[idx]
     else:
-        L = net.loss_grad(dev(u), dev(r), dev(D), dev(t))
+        L = net.loss_grad(dev(u), dev(r), dev(D), dev(t), mode=mode)
     g = net.get_grad()
     x, v, s = O.features(u, r, D)
     x = x.astype(np.float32).astype(np.float64)        # the network sees fp32 features
-    Lo, go = O.loss_and_grad(p.astype(np.float64), x, u, v, t, s)
+    Lo, go = O.loss_and_grad(p.astype(np.float64), x, u, v, t, s, mode)
     assert abs(L - Lo) <= 1e-4 * Lo
     offs = np.cumsum([0] + [int(np.prod(q)) for q in O.SHAPES])
     for k in range(len(O.SHAPES)):

@@ -3,6 +3,7 @@ do not come from the oracle itself: hand-evaluated features and head, the
 closed form of the zero network's loss, a central-difference gradient, and
 the first Adam step (which moves each parameter by lr * sign(g))."""
 import numpy as np
+import pytest
 
 from oracle import mlp
 
@@ -50,12 +51,22 @@ def test_zero_network_loss_closed_form():
     assert abs(L - ref) <= 1e-14 * ref
 
 
-def test_gradient_central_differences():
+def test_absolute_loss_closed_form():
+    u, r, D, t = _data(4)
+    x, v, s = mlp.features(u, r, D)
+    y = np.zeros((u.size, 4))
+    L, _ = mlp.loss_and_dy(y, u, v, t, s, mode=1)
+    ref = np.sum(np.abs(u + r / D - t) ** 2) / np.sum((np.abs(u) + np.abs(r / D) + 1e-30) ** 2)
+    assert abs(L - ref) <= 1e-14 * ref
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gradient_central_differences(mode):
     u, r, D, t = _data(2, n=11)
     x, v, s = mlp.features(u, r, D)
     rng = np.random.default_rng(3)
     p = 0.2 * rng.normal(size=mlp.n_params())
-    L, g = mlp.loss_and_grad(p, x, u, v, t, s)
+    L, g = mlp.loss_and_grad(p, x, u, v, t, s, mode)
     idx = rng.choice(p.size, 60, replace=False)
     # include coordinates of every parameter block
     offs = np.cumsum([0] + [int(np.prod(q)) for q in mlp.SHAPES])
@@ -64,8 +75,8 @@ def test_gradient_central_differences():
     for k in idx:
         e = np.zeros_like(p)
         e[k] = h
-        Lp, _ = mlp.loss_and_grad(p + e, x, u, v, t, s)
-        Lm, _ = mlp.loss_and_grad(p - e, x, u, v, t, s)
+        Lp, _ = mlp.loss_and_grad(p + e, x, u, v, t, s, mode)
+        Lm, _ = mlp.loss_and_grad(p - e, x, u, v, t, s, mode)
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g).max()), (k, fd, g[k])
 
