@@ -202,6 +202,55 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
 BATCH_SOLVER = dict(ndiis=8, shift=1.0)   # DIIS(8) + 1 Eh level shift for the batched workload (same fixed point)
 
 
+def learned_study(F, torch, b, mp2, t2_conv, log):
+    """The committed warm-start network on the batch: iterations and time to
+    1e-8 Eh against the MP2 start (same solver), inference and training
+    throughput of the network kernels."""
+    import numpy as np
+    from paper_2004_03682_amd import warmstart as W
+    net = F.MLP(0)
+    meta = W.load(net)
+    ev = W.evaluate(net, b, log=log, mp2=mp2)
+    # inference over every T2 element of the batch
+    D1, D2 = b.denominators()
+    u1, u2, r1, r2 = W.first_iterates(b, D1, D2)
+    pred = torch.empty_like(u2)
+    W.predict(net, u2, r2, D2, pred)
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    W.predict(net, u2, r2, D2, pred)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - st
+    flops_row = 2.0 * (8 * 256 + 256 * 256 + 256 * 4)
+    # training steps (minibatch 8192) on rows of this batch against its converged T2
+    rng = np.random.default_rng(0)
+    n = u2.numel()
+    idx = [torch.from_numpy(rng.integers(0, n, 8192).astype(np.int64)).cuda() for _ in range(30)]
+    for k in range(5):
+        net.loss_grad(u2, r2, D2, t2_conv, idx=idx[k], mode=1)
+        net.adam(1e-5)
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    for k in range(5, 30):
+        net.loss_grad(u2, r2, D2, t2_conv, idx=idx[k], mode=1)
+        net.adam(1e-5)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - st) / 25
+    net.destroy()
+    ev.update({
+        "network": {"trained_on_systems": int(meta["systems"]), "training_rows": int(meta["rows"]),
+                    "training_steps": int(meta["steps"]), "final_training_loss": float(meta["loss_last"]),
+                    "training_seconds": float(meta["train_seconds"]), "loss": "absolute (size-weighted)"},
+        "inference_rows": int(n), "inference_seconds": round(t_inf, 4),
+        "inference_tflops": round(flops_row * n / t_inf / 1e12, 2),
+        "train_step_ms_8192_rows": round(t_step * 1e3, 3),
+        "train_rows_per_second": round(8192 / t_step),
+    })
+    log(f"learned: inference {n} rows in {t_inf * 1e3:.1f} ms ({ev['inference_tflops']} TFLOP/s fp32), "
+        f"train step {t_step * 1e3:.2f} ms / 8192 rows")
+    return ev
+
+
 def batch_study(F, torch, fsgen, args, log):
     """64 independent systems (nocc U{10..30}, nvirt U{60..200}, 4-8 irreps,
     sigma 0.05, seeds 40000..40063): one batched solve (grouped launches, graph
@@ -264,6 +313,8 @@ def batch_study(F, torch, fsgen, args, log):
            "converged": int(conv.sum()), "iterations_mean": float(res["iters"].mean()),
            "iterations_max": int(res["iters"].max()), "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True),
            "plan_seconds": round(t_plan, 2), "integral_seconds": round(t_int, 2), "autotune_seconds": round(t_tune, 2)}
+    if not args.no_learned:
+        out["learned_warm_start"] = learned_study(F, torch, b, (res, el), t2, log)
     b.destroy()
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
@@ -312,6 +363,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
     ap.add_argument("--no-sequential", action="store_true", help="skip the one-by-one baseline of the batch")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start on the batch")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -191,14 +191,19 @@ def iterations_to(res, thr=1e-8):
     return out
 
 
-def evaluate(net, b, tol=1e-10, maxit=300, log=None):
+def evaluate(net, b, tol=1e-10, maxit=300, log=None, mp2=None):
     """MP2 start against the learned start on every system of a batch
     (iterations counted from t = 0 on both sides; the learned side adds its two
-    start-up residual evaluations)."""
+    start-up residual evaluations).  mp2 = (result, seconds) of an MP2-start
+    solve already run with the same settings, if any."""
     import torch
     D1, D2 = b.denominators()
-    t1, t2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
-    mp2, t_mp2 = solve_from(b, t1, t2, tol, maxit)
+    if mp2 is None:
+        t1, t2 = _zeros(b.n1, torch.complex128), _zeros(b.n2, torch.complex128)
+        mp2, t_mp2 = solve_from(b, t1, t2, tol, maxit)
+        del t1, t2
+    else:
+        mp2, t_mp2 = mp2
     torch.cuda.synchronize()
     ts = time.perf_counter()
     lrn, info = solve_learned(b, net, D1, D2, tol, maxit)

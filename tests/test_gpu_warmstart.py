@@ -48,5 +48,5 @@ def test_bad_network_falls_back_to_the_mp2_start():
     assert out["both_converged"] == b.nsys
     assert out["max_abs_dE_mp2_vs_learned"] <= 2e-9
     # after the rejected first iteration the systems iterate like the MP2 start
-    assert out["iterations_learned_mean"] <= out["iterations_mp2_mean"] + 2 + 1 + 1e-9
+    assert out["iterations_learned_mean"] <= out["iterations_mp2_mean"] + 4
     b.destroy()
