@@ -20,7 +20,17 @@ namespace rt {
 // efficiency, against operand re-reads (A once per column tile, B once per
 // row tile) at HBM speed.  fscc_autotune() replaces it by measurement.
 double cfg_cost(const Op& o, int cfg) {
-    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8};
+    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0};
+    if (cfg == ZCFG_SKINNY) {
+        // exact work on the vector ALUs (~20 TFLOP/s from LDS), operands read once
+        double fl = 0.0, by = 0.0;
+        for (auto& p : o.probs) {
+            if ((long long)p.M * p.N > ZSKINNY_MAX_MN) return 1e30;
+            fl += 8.0 * p.M * p.N * (double)std::max(p.K, 1);
+            by += 16.0 * ((double)p.M + p.N) * p.K;
+        }
+        return std::max(fl / 20e12, by / 4e12) + 4e-6;
+    }
     int bm, bn;
     zcfg_tile(cfg, &bm, &bn);
     double fl = 0.0, by = 0.0;
@@ -186,7 +196,14 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
     int S = tiles0 > 0 ? (int)std::min<long long>(512, (target + tiles0 - 1) / tiles0) : 1;
     std::vector<int> Sq(o.probs.size(), 1);
     bool split = false;
-    if (allow_split && S > 1 && maxK >= 512)
+    if (cfg == ZCFG_SKINNY) {
+        // the skinny kernel always writes partial blocks: K chunks of >= 256
+        for (auto& p : o.probs)
+            if ((long long)p.M * p.N > ZSKINNY_MAX_MN) throw std::invalid_argument("skinny tile: M*N too large");
+        split = true;
+        for (size_t q = 0; q < o.probs.size(); ++q)
+            Sq[q] = allow_split ? std::max(1, std::min(S, (o.probs[q].K + 255) / 256)) : 1;
+    } else if (allow_split && S > 1 && maxK >= 512)
         for (size_t q = 0; q < o.probs.size(); ++q) {
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
             split |= Sq[q] > 1;
@@ -793,6 +810,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (int cfg = 0; cfg < ZCFG_N; ++cfg)
                     for (int bk : {16, 32})
                         for (int sp = 1; sp >= 0; --sp) {
+                            if (cfg == ZCFG_SKINNY && (bk != 16 || cfg_cost(o, cfg) >= 1e29)) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
                             if (sp == 0 && !cand.split) {

@@ -270,8 +270,135 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
         }
 }
 
+// Skinny products (M*N small, K long): the A rows and B columns of a K slice
+// are staged in LDS and every thread accumulates up to 8 outputs on the
+// vector ALUs, so no MFMA work is wasted on padding.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                 double2* __restrict__ C, const ZProb* __restrict__ probs,
+                                                 const ZTile* __restrict__ tiles, double ar, double ai, int beta,
+                                                 int cA, int cB, const int* __restrict__ active) {
+    constexpr int LDS = 4096;                       // staged complex elements (64 KB)
+    constexpr int MAXO = ZSKINNY_MAX_MN / kThreads;  // outputs per thread
+    __shared__ double2 sm[LDS];
+    const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;
+    const ZProb pr = probs[tl.prob];
+    const int M = pr.M, N = pr.N, K = pr.K, MN = M * N;
+    const int tid = threadIdx.x;
+    int KS = LDS / max(1, M + N);
+    if (KS > 256) KS = 256;
+    // G threads per output when the block is small: thread (o, g) sums k = g, g+G, ...
+    const int G = (MN > 0 && MN <= kThreads / 2) ? kThreads / MN : 1;
+    double2* As = sm;            // [M][KS]
+    double2* Bs = sm + M * KS;   // [KS][N]
+    const double sA = cA ? -1.0 : 1.0, sB = cB ? -1.0 : 1.0;
+    const double2* Ap = A + pr.a_off;
+    const double2* Bp = B + pr.b_off;
+    double accr[MAXO], acci[MAXO];
+#pragma unroll
+    for (int j = 0; j < MAXO; ++j) accr[j] = acci[j] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += KS) {
+        const int kl = min(KS, K - k0);
+        __syncthreads();
+        for (int e = tid; e < M * KS; e += kThreads) {
+            int m, k;
+            if (!TA) {
+                m = e / KS;
+                k = e % KS;
+            } else {
+                k = e / M;
+                m = e % M;
+            }
+            double2 v = make_double2(0.0, 0.0);
+            if (k < kl) v = TA ? Ap[(long long)(k0 + k) * pr.lda + m] : Ap[(long long)m * pr.lda + k0 + k];
+            v.y *= sA;
+            As[m * KS + k] = v;
+        }
+        for (int e = tid; e < N * KS; e += kThreads) {
+            int n, k;
+            if (!TB) {
+                k = e / N;
+                n = e % N;
+            } else {
+                n = e / KS;
+                k = e % KS;
+            }
+            double2 v = make_double2(0.0, 0.0);
+            if (k < kl) v = TB ? Bp[(long long)n * pr.ldb + k0 + k] : Bp[(long long)(k0 + k) * pr.ldb + n];
+            v.y *= sB;
+            Bs[k * N + n] = v;
+        }
+        __syncthreads();
+        if (G > 1) {
+            const int o = tid % MN, g = tid / MN;
+            if (g < G) {
+                const int m = o / N, n = o % N;
+                double sr = accr[0], si = acci[0];
+                const double2* a = As + m * KS;
+                for (int k = g; k < kl; k += G) {
+                    const double2 x = a[k], y = Bs[k * N + n];
+                    sr += x.x * y.x - x.y * y.y;
+                    si += x.x * y.y + x.y * y.x;
+                }
+                accr[0] = sr;
+                acci[0] = si;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < MAXO; ++j) {
+                const int o = tid + j * kThreads;
+                if (o < MN) {
+                    const int m = o / N, n = o % N;
+                    double sr = accr[j], si = acci[j];
+                    const double2* a = As + m * KS;
+                    for (int k = 0; k < kl; ++k) {
+                        const double2 x = a[k], y = Bs[k * N + n];
+                        sr += x.x * y.x - x.y * y.y;
+                        si += x.x * y.y + x.y * y.x;
+                    }
+                    accr[j] = sr;
+                    acci[j] = si;
+                }
+            }
+        }
+    }
+    if (G > 1) {   // combine the G partial sums of each output (fixed order)
+        __syncthreads();
+        const int o = tid % MN, g = tid / MN;
+        if (g < G) sm[g * MN + o] = make_double2(accr[0], acci[0]);
+        __syncthreads();
+        if (tid < MN) {
+            double sr = 0.0, si = 0.0;
+            for (int q = 0; q < G; ++q) {
+                sr += sm[q * MN + tid].x;
+                si += sm[q * MN + tid].y;
+            }
+            accr[0] = sr;
+            acci[0] = si;
+        }
+    }
+    double2* Cp = C + pr.c_off;
+#pragma unroll
+    for (int j = 0; j < MAXO; ++j) {
+        const int o = tid + j * kThreads;
+        if (o < MN && (G == 1 || j == 0)) {
+            const int m = o / N, n = o % N;
+            double2 out = make_double2(ar * accr[j] - ai * acci[j], ar * acci[j] + ai * accr[j]);
+            double2* c = Cp + (long long)m * pr.ldc + n;
+            if (beta) {
+                const double2 old = *c;
+                out.x += old.x;
+                out.y += old.y;
+            }
+            *c = out;
+        }
+    }
+}
+
 void zcfg_tile(int cfg, int* bm, int* bn) {
     switch (cfg) {
+        case ZCFG_SKINNY: *bm = 1 << 16; *bn = 1 << 16; break;
         case ZCFG_128x16: *bm = 128; *bn = 16; break;
         case ZCFG_16x128: *bm = 16; *bn = 128; break;
         case ZCFG_32x32: *bm = 32; *bn = 32; break;
@@ -319,6 +446,14 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                         int cB, hipStream_t st, int role, const int* active) {
     if (ntiles <= 0) return hipSuccess;
+    if (cfg == ZCFG_SKINNY) {
+        dim3 grid(ntiles), block(kThreads);
+        if (!tA && !tB) k_zskinny<false, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else if (!tA && tB) k_zskinny<false, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else if (tA && !tB) k_zskinny<true, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zskinny<true, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        return hipGetLastError();
+    }
     if (bk == 32) return launch_bk<32>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
     if (bk == 16) return launch_bk<16>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
     return hipErrorInvalidValue;

@@ -18,7 +18,11 @@ struct ZTile {
 };
 
 // tile shapes of the grouped complex GEMM
-enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_N };
+// ZCFG_SKINNY: one workgroup per (problem, K chunk) computing the whole M x N
+// block on the vector ALUs (for M*N <= ZSKINNY_MAX_MN); always used with the
+// split-K reduction.
+enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_SKINNY, ZCFG_N };
+constexpr int ZSKINNY_MAX_MN = 2048;
 void zcfg_tile(int cfg, int* bm, int* bn);
 
 // C(m,n) = alpha * sum_k opA(m,k) opB(k,n) + beta*C(m,n)  for every tile in `tiles`
