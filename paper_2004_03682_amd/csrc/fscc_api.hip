@@ -22,12 +22,13 @@ namespace rt {
 double cfg_cost(const Op& o, int cfg) {
     static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0};
     if (cfg == ZCFG_SKINNY) {
-        // exact work on the vector ALUs (~20 TFLOP/s from LDS), operands read once
+        // exact work on the vector ALUs (~20 TFLOP/s from LDS); A re-read once
+        // per 32-column block, B once per 64-row block
         double fl = 0.0, by = 0.0;
         for (auto& p : o.probs) {
-            if ((long long)p.M * p.N > ZSKINNY_MAX_MN) return 1e30;
+            const double tm = (p.M + ZSKINNY_BM - 1) / ZSKINNY_BM, tn = (p.N + ZSKINNY_BN - 1) / ZSKINNY_BN;
             fl += 8.0 * p.M * p.N * (double)std::max(p.K, 1);
-            by += 16.0 * ((double)p.M + p.N) * p.K;
+            by += 16.0 * ((double)p.M * p.K * tn + (double)p.N * p.K * tm + 2.0 * p.M * p.N);
         }
         return std::max(fl / 20e12, by / 4e12) + 4e-6;
     }
@@ -197,12 +198,10 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
     std::vector<int> Sq(o.probs.size(), 1);
     bool split = false;
     if (cfg == ZCFG_SKINNY) {
-        // the skinny kernel always writes partial blocks: K chunks of >= 256
-        for (auto& p : o.probs)
-            if ((long long)p.M * p.N > ZSKINNY_MAX_MN) throw std::invalid_argument("skinny tile: M*N too large");
+        // the skinny kernel always writes partial blocks: K chunks of >= 64
         split = true;
         for (size_t q = 0; q < o.probs.size(); ++q)
-            Sq[q] = allow_split ? std::max(1, std::min(S, (o.probs[q].K + 255) / 256)) : 1;
+            Sq[q] = allow_split ? std::max(1, std::min(S, (o.probs[q].K + 63) / 64)) : 1;
     } else if (allow_split && S > 1 && maxK >= 512)
         for (size_t q = 0; q < o.probs.size(); ++q) {
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
@@ -802,7 +801,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         for (OpList* L : lists)
             for (size_t k = 0; k < L->ops->size() && level == 1; ++k) {
                 const Op& o = (*L->ops)[k];
-                if (o.kind != OP_GEMM || o.flops < 1e7) continue;
+                if (o.kind != OP_GEMM || o.flops < 1e5) continue;
                 MixedDev* keep = L->g[k].mx;   // the FP64 candidates are timed without it
                 L->g[k].mx = nullptr;
                 GemmDev best = L->g[k];
@@ -810,7 +809,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (int cfg = 0; cfg < ZCFG_N; ++cfg)
                     for (int bk : {16, 32})
                         for (int sp = 1; sp >= 0; --sp) {
-                            if (cfg == ZCFG_SKINNY && (bk != 16 || cfg_cost(o, cfg) >= 1e29)) continue;
+                            if (cfg == ZCFG_SKINNY && bk != 16) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
                             if (sp == 0 && !cand.split) {

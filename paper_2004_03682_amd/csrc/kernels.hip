@@ -270,9 +270,11 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
         }
 }
 
-// Skinny products (M*N small, K long): the A rows and B columns of a K slice
-// are staged in LDS and every thread accumulates up to 8 outputs on the
-// vector ALUs, so no MFMA work is wasted on padding.
+// Skinny products (a small M or N, or a short K): each workgroup takes a
+// block of at most 64 x 32 outputs of one K chunk, stages the A rows and B
+// columns of a K slice in LDS, and every thread accumulates up to 8 outputs on
+// the vector ALUs (small blocks: several threads per output, summed in a
+// fixed order), so no MFMA work is wasted on padding.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, const double2* __restrict__ B,
                                                  double2* __restrict__ C, const ZProb* __restrict__ probs,
@@ -284,50 +286,66 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
     const ZTile tl = tiles[blockIdx.x];
     if (active && !active[tl.sys]) return;
     const ZProb pr = probs[tl.prob];
-    const int M = pr.M, N = pr.N, K = pr.K, MN = M * N;
+    // this workgroup's block: rows m0.., columns n0.. of at most ZSKINNY_BM x ZSKINNY_BN
+    const int M = min(ZSKINNY_BM, pr.M - tl.m0), N = min(ZSKINNY_BN, pr.N - tl.n0), K = pr.K, MN = M * N;
     const int tid = threadIdx.x;
-    int KS = LDS / max(1, M + N);
-    if (KS > 256) KS = 256;
+    // K slice: the largest power of two <= min(256, LDS / (M + N))
+    int kss = 0;
+    while ((2 << kss) <= LDS / max(1, M + N) && (2 << kss) <= 256) ++kss;
+    const int KS = 1 << kss;
     // G threads per output when the block is small: thread (o, g) sums k = g, g+G, ...
     const int G = (MN > 0 && MN <= kThreads / 2) ? kThreads / MN : 1;
     double2* As = sm;            // [M][KS]
     double2* Bs = sm + M * KS;   // [KS][N]
     const double sA = cA ? -1.0 : 1.0, sB = cB ? -1.0 : 1.0;
-    const double2* Ap = A + pr.a_off;
-    const double2* Bp = B + pr.b_off;
+    const double2* Ap = A + pr.a_off + (TA ? (long long)tl.m0 : (long long)tl.m0 * pr.lda);
+    const double2* Bp = B + pr.b_off + (TB ? (long long)tl.n0 * pr.ldb : (long long)tl.n0);
     double accr[MAXO], acci[MAXO];
 #pragma unroll
     for (int j = 0; j < MAXO; ++j) accr[j] = acci[j] = 0.0;
+    const int nA = M * KS, nAB = (M + N) * KS;   // staged elements (<= LDS)
     for (int k0 = 0; k0 < K; k0 += KS) {
         const int kl = min(KS, K - k0);
         __syncthreads();
-        for (int e = tid; e < M * KS; e += kThreads) {
-            int m, k;
-            if (!TA) {
-                m = e / KS;
-                k = e % KS;
-            } else {
-                k = e / M;
-                m = e % M;
+        // batches of 4 elements per thread: the 4 global loads are in flight together
+        for (int base = 0; base < nAB; base += 4 * kThreads) {
+            double2 v[4];
+            int dst[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = base + tid + j * kThreads;
+                v[j] = make_double2(0.0, 0.0);
+                dst[j] = -1;
+                if (e < nA) {
+                    int m, k;
+                    if (!TA) {
+                        m = e >> kss;
+                        k = e & (KS - 1);
+                    } else {
+                        k = e / M;
+                        m = e - k * M;
+                    }
+                    if (k < kl) v[j] = TA ? Ap[(long long)(k0 + k) * pr.lda + m] : Ap[(long long)m * pr.lda + k0 + k];
+                    v[j].y *= sA;
+                    dst[j] = m * KS + k;
+                } else if (e < nAB) {
+                    const int f = e - nA;
+                    int n, k;
+                    if (!TB) {
+                        k = f / N;
+                        n = f - k * N;
+                    } else {
+                        n = f >> kss;
+                        k = f & (KS - 1);
+                    }
+                    if (k < kl) v[j] = TB ? Bp[(long long)n * pr.ldb + k0 + k] : Bp[(long long)(k0 + k) * pr.ldb + n];
+                    v[j].y *= sB;
+                    dst[j] = nA + k * N + n;
+                }
             }
-            double2 v = make_double2(0.0, 0.0);
-            if (k < kl) v = TA ? Ap[(long long)(k0 + k) * pr.lda + m] : Ap[(long long)m * pr.lda + k0 + k];
-            v.y *= sA;
-            As[m * KS + k] = v;
-        }
-        for (int e = tid; e < N * KS; e += kThreads) {
-            int n, k;
-            if (!TB) {
-                k = e / N;
-                n = e % N;
-            } else {
-                n = e / KS;
-                k = e % KS;
-            }
-            double2 v = make_double2(0.0, 0.0);
-            if (k < kl) v = TB ? Bp[(long long)n * pr.ldb + k0 + k] : Bp[(long long)(k0 + k) * pr.ldb + n];
-            v.y *= sB;
-            Bs[k * N + n] = v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (dst[j] >= 0) sm[dst[j]] = v[j];
         }
         __syncthreads();
         if (G > 1) {
@@ -336,6 +354,7 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
                 const int m = o / N, n = o % N;
                 double sr = accr[0], si = acci[0];
                 const double2* a = As + m * KS;
+#pragma unroll 2
                 for (int k = g; k < kl; k += G) {
                     const double2 x = a[k], y = Bs[k * N + n];
                     sr += x.x * y.x - x.y * y.y;
@@ -352,6 +371,7 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
                     const int m = o / N, n = o % N;
                     double sr = accr[j], si = acci[j];
                     const double2* a = As + m * KS;
+#pragma unroll 2
                     for (int k = 0; k < kl; ++k) {
                         const double2 x = a[k], y = Bs[k * N + n];
                         sr += x.x * y.x - x.y * y.y;
@@ -378,7 +398,7 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
             acci[0] = si;
         }
     }
-    double2* Cp = C + pr.c_off;
+    double2* Cp = C + pr.c_off + (long long)tl.m0 * pr.ldc + tl.n0;
 #pragma unroll
     for (int j = 0; j < MAXO; ++j) {
         const int o = tid + j * kThreads;
@@ -398,7 +418,7 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
 
 void zcfg_tile(int cfg, int* bm, int* bn) {
     switch (cfg) {
-        case ZCFG_SKINNY: *bm = 1 << 16; *bn = 1 << 16; break;
+        case ZCFG_SKINNY: *bm = ZSKINNY_BM; *bn = ZSKINNY_BN; break;
         case ZCFG_128x16: *bm = 128; *bn = 16; break;
         case ZCFG_16x128: *bm = 16; *bn = 128; break;
         case ZCFG_32x32: *bm = 32; *bn = 32; break;

@@ -18,11 +18,10 @@ struct ZTile {
 };
 
 // tile shapes of the grouped complex GEMM
-// ZCFG_SKINNY: one workgroup per (problem, K chunk) computing the whole M x N
-// block on the vector ALUs (for M*N <= ZSKINNY_MAX_MN); always used with the
-// split-K reduction.
+// ZCFG_SKINNY: one workgroup per (64 x 32 output block, K chunk) on the
+// vector ALUs; always used with the split-K reduction.
 enum ZCfg { ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_SKINNY, ZCFG_N };
-constexpr int ZSKINNY_MAX_MN = 2048;
+constexpr int ZSKINNY_BM = 64, ZSKINNY_BN = 32, ZSKINNY_MAX_MN = ZSKINNY_BM * ZSKINNY_BN;
 void zcfg_tile(int cfg, int* bm, int* bn);
 
 // C(m,n) = alpha * sum_k opA(m,k) opB(k,n) + beta*C(m,n)  for every tile in `tiles`
