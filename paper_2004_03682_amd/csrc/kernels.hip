@@ -79,18 +79,28 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
                     int m = m0 + r;
                     if (m < M) {
                         const double2* p = Ap + (long long)m * pr.lda + k0 + kk;
+                        if (k0 + kk + 3 < K) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (k0 + kk + e < K) ra[u][e] = p[e];
+                            for (int e = 0; e < 4; ++e) ra[u][e] = p[e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (k0 + kk + e < K) ra[u][e] = p[e];
+                        }
                     }
                 } else {     // A stored [K][lda], m contiguous
                     int kr = v / (BM / 4), mm = (v % (BM / 4)) * 4;
                     int k = k0 + kr;
                     if (k < K) {
                         const double2* p = Ap + (long long)k * pr.lda + m0 + mm;
+                        if (m0 + mm + 3 < M) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (m0 + mm + e < M) ra[u][e] = p[e];
+                            for (int e = 0; e < 4; ++e) ra[u][e] = p[e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (m0 + mm + e < M) ra[u][e] = p[e];
+                        }
                     }
                 }
             }
@@ -106,18 +116,28 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
                     int k = k0 + kr;
                     if (k < K) {
                         const double2* p = Bp + (long long)k * pr.ldb + n0 + nn;
+                        if (n0 + nn + 3 < N) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (n0 + nn + e < N) rb[u][e] = p[e];
+                            for (int e = 0; e < 4; ++e) rb[u][e] = p[e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (n0 + nn + e < N) rb[u][e] = p[e];
+                        }
                     }
                 } else {     // B stored [N][ldb], k contiguous
                     int r = v / (BK / 4), kk = (v % (BK / 4)) * 4;
                     int n = n0 + r;
                     if (n < N) {
                         const double2* p = Bp + (long long)n * pr.ldb + k0 + kk;
+                        if (k0 + kk + 3 < K) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (k0 + kk + e < K) rb[u][e] = p[e];
+                            for (int e = 0; e < 4; ++e) rb[u][e] = p[e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (k0 + kk + e < K) rb[u][e] = p[e];
+                        }
                     }
                 }
             }
