@@ -43,9 +43,9 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_name):
+def measured_traffic(kernel_name, tile=None):
     """HBM bytes per launch from committed rocprofv3 --pmc counters, if they were
-    taken on the current kernel source; else None."""
+    taken on the current library sources and the same tile shape; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -55,6 +55,8 @@ def measured_traffic(kernel_name):
         return None
     ent = d.get(kernel_name)
     if not ent or ent.get("kernels_sha256") != kernel_source_sha():
+        return None
+    if tile is not None and ent.get("tile") != tile:
         return None
     return ent.get("bytes_per_launch")
 
@@ -414,7 +416,7 @@ def main():
 
     t0 = time.perf_counter()
     ctx.autotune(1)
-    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64"}
+    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32"}
     tuned = {n: f"{names[c]}/bk{b}{'/splitK' if sp else ''}" for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
@@ -455,7 +457,7 @@ def main():
     dom = max(gemms, key=lambda o: o["ms"])
     per_launch_s = dom["ms"] / dom["calls"] * 1e-3
     achieved = dom["flops"] / per_launch_s / 1e12
-    traffic = measured_traffic(dom["name"])
+    traffic = measured_traffic(dom["name"], tuned.get(dom["name"]))
     gemm_ms = sum(o["ms"] for o in gemms) / max(1, args.steps)
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64, 4), "traffic": traffic,
