@@ -209,9 +209,12 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
 /* One complex GEMM through the grouped MFMA kernel, for kernel-level tests:
  * C = alpha * op(A) op(B) + beta*C with op = transpose (tA/tB) and/or
  * conjugate (cA/cB); A is M x K (lda) or, if tA, K x M; B is K x N (ldb) or,
- * if tB, N x K; all row-major, device pointers.  cfg = tile shape id
- * (0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64; -1 = cost
- * model), bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.
+ * if tB, N x K; all row-major, device pointers.  cfg = kernel form: MFMA tile
+ * shapes 0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64;
+ * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
+ * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256);
+ * -1 = cost model.  FSCC_EINVAL if the shape does not fit the form.
+ * bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.
  * Synchronises hip_stream. */
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128 *A, int lda,
                        const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,

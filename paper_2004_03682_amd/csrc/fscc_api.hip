@@ -19,8 +19,35 @@ namespace rt {
 // Default tile shape from a cost model: padded MFMA work at a per-shape
 // efficiency, against operand re-reads (A once per column tile, B once per
 // row tile) at HBM speed.  fscc_autotune() replaces it by measurement.
+// Shape limits of the vector-ALU forms (the MFMA tiles and the skinny form
+// take any shape).
+bool cfg_ok(const Op& o, int cfg) {
+    if (cfg < 0 || cfg >= ZCFG_N) return false;
+    if (cfg == ZCFG_TALL) {
+        if (o.tA) return false;
+        for (auto& p : o.probs)
+            if (p.K > ZTALL_MAX_K || p.N > ZTALL_MAX_KN || (long long)p.K * p.N > ZTALL_MAX_KN) return false;
+    }
+    if (cfg == ZCFG_RED) {
+        if (o.tB) return false;
+        for (auto& p : o.probs)
+            if (p.M > ZRED_MAX_M || p.N > ZRED_MAX_N) return false;
+    }
+    return true;
+}
+
 double cfg_cost(const Op& o, int cfg) {
-    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0};
+    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0, 1.0, 1.0};
+    if (cfg == ZCFG_TALL || cfg == ZCFG_RED) {
+        // streaming forms: every operand element read once, exact work on the
+        // vector ALUs
+        double fl = 0.0, by = 0.0;
+        for (auto& p : o.probs) {
+            fl += 8.0 * p.M * p.N * (double)std::max(p.K, 1);
+            by += 16.0 * ((double)p.M * p.K + (double)p.K * p.N + (1.0 + o.beta) * p.M * p.N);
+        }
+        return std::max(fl / 20e12, by / 6e12) + (cfg == ZCFG_RED ? 4e-6 : 0.0);
+    }
     if (cfg == ZCFG_SKINNY) {
         // exact work on the vector ALUs (~20 TFLOP/s from LDS); A re-read once
         // per 32-column block, B once per 64-row block
@@ -47,6 +74,7 @@ int pick_cfg(const Op& o) {
     int best = ZCFG_64x64;
     double bc = cfg_cost(o, best);
     for (int c = 0; c < ZCFG_N; ++c) {
+        if (!cfg_ok(o, c)) continue;
         double x = cfg_cost(o, c);
         if (x < bc * 0.95) {
             best = c;
@@ -189,9 +217,11 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
     zcfg_tile(g.cfg, &bm, &bn);
     long long tiles0 = 0;
     int maxK = 0;
+    g.maxM = 0;
     for (auto& p : o.probs) {
         tiles0 += (long long)((p.M + bm - 1) / bm) * ((p.N + bn - 1) / bn);
         maxK = std::max(maxK, p.K);
+        g.maxM = std::max(g.maxM, p.M);
     }
     const long long target = 2048;
     int S = tiles0 > 0 ? (int)std::min<long long>(512, (target + tiles0 - 1) / tiles0) : 1;
@@ -202,7 +232,18 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
         split = true;
         for (size_t q = 0; q < o.probs.size(); ++q)
             Sq[q] = allow_split ? std::max(1, std::min(S, (o.probs[q].K + 63) / 64)) : 1;
-    } else if (allow_split && S > 1 && maxK >= 512)
+    } else if (cfg == ZCFG_RED) {
+        // the reduction form always writes partial blocks: K chunks of at most
+        // ZRED_LDS / M (the chunk of A is staged in LDS) and, when splitting
+        // for parallelism is allowed, of >= 128
+        split = true;
+        for (size_t q = 0; q < o.probs.size(); ++q) {
+            const GemmProblem& p = o.probs[q];
+            const int cap = ZRED_LDS / std::max(1, p.M);
+            const int need = (p.K + cap - 1) / cap;
+            Sq[q] = std::max(1, std::max(need, allow_split ? std::min(S, (p.K + 127) / 128) : 1));
+        }
+    } else if (cfg != ZCFG_TALL && allow_split && S > 1 && maxK >= 512)
         for (size_t q = 0; q < o.probs.size(); ++q) {
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
             split |= Sq[q] > 1;
@@ -809,7 +850,9 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (int cfg = 0; cfg < ZCFG_N; ++cfg)
                     for (int bk : {16, 32})
                         for (int sp = 1; sp >= 0; --sp) {
-                            if (cfg == ZCFG_SKINNY && bk != 16) continue;
+                            if ((cfg == ZCFG_SKINNY || cfg == ZCFG_TALL || cfg == ZCFG_RED) && bk != 16) continue;
+                            if ((cfg == ZCFG_TALL && sp == 1) || (cfg == ZCFG_RED && sp == 0)) continue;
+                            if (!cfg_ok(o, cfg)) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
                             if (sp == 0 && !cand.split) {
@@ -967,15 +1010,16 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         o.alpha = cplx(alpha_re, alpha_im);
         o.beta = beta ? 1 : 0;
         if (M > 0 && N > 0) o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
+        if (cfg >= 0 && !cfg_ok(o, cfg)) return FSCC_EINVAL;
         GemmDev g;
         plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0);
         hipError_t e;
         if (!g.split) {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
-                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0);
+                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM);
         } else {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0);
+                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM);
             if (e == hipSuccess)
                 e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, alpha_re, alpha_im, o.beta, c->st);
         }

@@ -436,9 +436,175 @@ __global__ __launch_bounds__(256) void k_zskinny(const double2* __restrict__ A, 
     }
 }
 
+// Tall products (many rows, K <= ZTALL_MAX_K, K*N <= ZTALL_MAX_KN, A stored
+// with k contiguous): B is staged in LDS once per workgroup and every thread
+// streams one row of A with eight independent loads in flight, so the large
+// operand is read once at full width and nothing is padded to a 16-wide
+// matrix-core fragment.
+template <bool TB>
+__global__ __launch_bounds__(256) void k_ztall(const double2* __restrict__ A, const double2* __restrict__ B,
+                                               double2* __restrict__ C, const ZProb* __restrict__ probs,
+                                               const ZTile* __restrict__ tiles, double ar, double ai, int beta,
+                                               int cA, int cB, const int* __restrict__ active) {
+    __shared__ double2 Bs[ZTALL_MAX_KN];   // [k][n]
+    const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;
+    const ZProb pr = probs[tl.prob];
+    const int N = pr.N, K = pr.K;
+    const double sA = cA ? -1.0 : 1.0, sB = cB ? -1.0 : 1.0;
+    const double2* Bp = B + pr.b_off;
+    for (int e = threadIdx.x; e < K * N; e += kThreads) {
+        const int k = e / N, n = e - k * N;
+        double2 v = TB ? Bp[(long long)n * pr.ldb + k] : Bp[(long long)k * pr.ldb + n];
+        v.y *= sB;
+        Bs[e] = v;
+    }
+    __syncthreads();
+    const int m = tl.m0 + (int)threadIdx.x;
+    if (m >= pr.M) return;
+    const double2* a = A + pr.a_off + (long long)m * pr.lda;
+    double2* c = C + pr.c_off + (long long)m * pr.ldc;
+    for (int n0 = 0; n0 < N; n0 += 8) {
+        double xr[8], xi[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xr[q] = xi[q] = 0.0;
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            double2 av[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) av[j] = k0 + j < K ? a[k0 + j] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (k0 + j < K) {
+                    const double pr_ = av[j].x, pi_ = sA * av[j].y;
+                    const double2* b = Bs + (k0 + j) * N + n0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (n0 + q < N) {
+                            const double2 y = b[q];
+                            xr[q] += pr_ * y.x - pi_ * y.y;
+                            xi[q] += pr_ * y.y + pi_ * y.x;
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (n0 + q < N) {
+                double2 out = make_double2(ar * xr[q] - ai * xi[q], ar * xi[q] + ai * xr[q]);
+                if (beta) {
+                    const double2 old = c[n0 + q];
+                    out.x += old.x;
+                    out.y += old.y;
+                }
+                c[n0 + q] = out;
+            }
+    }
+}
+
+// Reduction-shaped products (M <= MAXM, N <= 256, long K, B stored with n
+// contiguous): one workgroup per K chunk (M * chunk <= ZRED_LDS).  The chunk
+// of A is staged in LDS; thread t then takes column n = t % N and every P-th
+// k from t / N (P = 256 / N), so each step of the workgroup reads P
+// consecutive rows of B as one contiguous span, and the B rows of the next U
+// steps are in flight while the current ones are used (only B loads occupy
+// the memory queue).  The P partial sums of an output are combined in LDS in
+// a fixed order.
+template <bool TA, int MAXM, int U>
+__global__ __launch_bounds__(256) void k_zred(const double2* __restrict__ A, const double2* __restrict__ B,
+                                              double2* __restrict__ C, const ZProb* __restrict__ probs,
+                                              const ZTile* __restrict__ tiles, double ar, double ai, int beta,
+                                              int cA, int cB, const int* __restrict__ active) {
+    __shared__ double2 As[ZRED_LDS];   // [m][k] of the chunk
+    __shared__ double2 red[kThreads];
+    const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;
+    const ZProb pr = probs[tl.prob];
+    const int M = pr.M, N = pr.N, K = pr.K;
+    if (M <= 0 || N <= 0) return;
+    const int P = kThreads / N;
+    const int tid = threadIdx.x, n = tid % N, kl = tid / N;
+    const bool live = kl < P;
+    const double sA = cA ? -1.0 : 1.0, sB = cB ? -1.0 : 1.0;
+    const double2* Ap = A + pr.a_off;
+    const double2* Bp = B + pr.b_off + n;
+    for (int e = tid; e < M * K; e += kThreads) {
+        int i, k;
+        if (TA) {   // A(i, k) at Ap[k * lda + i]: i fastest for coalescing
+            k = e / M;
+            i = e - k * M;
+        } else {
+            i = e / K;
+            k = e - i * K;
+        }
+        double2 v = TA ? Ap[(long long)k * pr.lda + i] : Ap[(long long)i * pr.lda + k];
+        v.y *= sA;
+        As[i * K + k] = v;
+    }
+    __syncthreads();
+    double xr[MAXM], xi[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) xr[i] = xi[i] = 0.0;
+    auto fma_k = [&](const double2 b, int k) {
+        const double br = b.x, bi = sB * b.y;
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+            if (i < M) {
+                const double2 x = As[i * K + k];
+                xr[i] += x.x * br - x.y * bi;
+                xi[i] += x.x * bi + x.y * br;
+            }
+    };
+    if (live) {
+        const int step = U * P;
+        int k = kl;
+        double2 nb[U];
+        if (k + (U - 1) * P < K) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) nb[u] = Bp[(long long)(k + u * P) * pr.ldb];
+        }
+        for (; k + (U - 1) * P < K; k += step) {
+            double2 cb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cb[u] = nb[u];
+            if (k + step + (U - 1) * P < K) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) nb[u] = Bp[(long long)(k + step + u * P) * pr.ldb];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) fma_k(cb[u], k + u * P);
+        }
+        for (; k < K; k += P) fma_k(Bp[(long long)k * pr.ldb], k);
+    }
+    double2* Cp = C + pr.c_off;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        if (i >= M) break;
+        __syncthreads();
+        if (live) red[kl * N + n] = make_double2(xr[i], xi[i]);
+        __syncthreads();
+        if (tid < N) {
+            double sr = 0.0, si = 0.0;
+            for (int q = 0; q < P; ++q) {
+                sr += red[q * N + tid].x;
+                si += red[q * N + tid].y;
+            }
+            double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+            double2* c = Cp + (long long)i * pr.ldc + tid;
+            if (beta) {
+                const double2 old = *c;
+                out.x += old.x;
+                out.y += old.y;
+            }
+            *c = out;
+        }
+    }
+}
+
 void zcfg_tile(int cfg, int* bm, int* bn) {
     switch (cfg) {
         case ZCFG_SKINNY: *bm = ZSKINNY_BM; *bn = ZSKINNY_BN; break;
+        case ZCFG_TALL: *bm = ZTALL_ROWS; *bn = ZTALL_MAX_KN; break;
+        case ZCFG_RED: *bm = ZRED_MAX_M; *bn = ZRED_MAX_N; break;
         case ZCFG_128x16: *bm = 128; *bn = 16; break;
         case ZCFG_16x128: *bm = 16; *bn = 128; break;
         case ZCFG_32x32: *bm = 32; *bn = 32; break;
@@ -484,8 +650,30 @@ static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const d
 
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role, const int* active) {
+                        int cB, hipStream_t st, int role, const int* active, int max_m) {
     if (ntiles <= 0) return hipSuccess;
+    if (cfg == ZCFG_TALL) {
+        if (tA) return hipErrorInvalidValue;
+        dim3 grid(ntiles), block(kThreads);
+        if (tB) k_ztall<true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_ztall<false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        return hipGetLastError();
+    }
+    if (cfg == ZCFG_RED) {
+        if (tB || max_m < 1 || max_m > ZRED_MAX_M) return hipErrorInvalidValue;
+        dim3 grid(ntiles), block(kThreads);
+        if (max_m <= 2) {
+            if (tA) k_zred<true, 2, 8><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+            else k_zred<false, 2, 8><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        } else if (max_m <= 4) {
+            if (tA) k_zred<true, 4, 8><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+            else k_zred<false, 4, 8><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        } else {
+            if (tA) k_zred<true, 8, 4><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+            else k_zred<false, 8, 4><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        }
+        return hipGetLastError();
+    }
     if (cfg == ZCFG_SKINNY) {
         dim3 grid(ntiles), block(kThreads);
         if (!tA && !tB) k_zskinny<false, false><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
@@ -499,35 +687,65 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
     return hipErrorInvalidValue;
 }
 
+// Split-K second pass: each workgroup takes 16 consecutive outputs of one
+// problem; 16 threads per output sum every 16th partial block (four loads in
+// flight), and the 16 partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, const double2* __restrict__ W,
                                                        const ZRed* __restrict__ reds, double ar, double ai, int beta,
                                                        const int* __restrict__ active) {
+    __shared__ double2 part[kThreads];
     const ZRed r = reds[blockIdx.y];
     if (active && !active[r.sys]) return;
     const long long mn = (long long)r.M * r.N;
-    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mn) return;
+    const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const long long e = (long long)blockIdx.x * 16 + o;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < r.S; ++s) {
-        double2 x = W[r.w_off + s * mn + e];
-        sr += x.x;
-        si += x.y;
+    if (e < mn) {
+        const double2* w = W + r.w_off + e;
+        int s = g;
+        for (; s + 48 < r.S; s += 64) {
+            const double2 x0 = w[(long long)s * mn], x1 = w[(long long)(s + 16) * mn];
+            const double2 x2 = w[(long long)(s + 32) * mn], x3 = w[(long long)(s + 48) * mn];
+            sr += x0.x;
+            si += x0.y;
+            sr += x1.x;
+            si += x1.y;
+            sr += x2.x;
+            si += x2.y;
+            sr += x3.x;
+            si += x3.y;
+        }
+        for (; s < r.S; s += 16) {
+            const double2 x = w[(long long)s * mn];
+            sr += x.x;
+            si += x.y;
+        }
     }
-    int m = (int)(e / r.N), n = (int)(e % r.N);
-    double2* c = C + r.c_off + (long long)m * r.ldc + n;
-    double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
-    if (beta) {
-        double2 o = *c;
-        out.x += o.x;
-        out.y += o.y;
+    part[threadIdx.x] = make_double2(sr, si);
+    __syncthreads();
+    if (g == 0 && e < mn) {
+        sr = 0.0;
+        si = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            sr += part[q * 16 + o].x;
+            si += part[q * 16 + o].y;
+        }
+        const int m = (int)(e / r.N), n = (int)(e % r.N);
+        double2* c = C + r.c_off + (long long)m * r.ldc + n;
+        double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+        if (beta) {
+            const double2 old = *c;
+            out.x += old.x;
+            out.y += old.y;
+        }
+        *c = out;
     }
-    *c = out;
 }
 
 hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
                                 double ai, int beta, hipStream_t st, const int* active) {
     if (nred <= 0 || maxMN <= 0) return hipSuccess;
-    dim3 grid((unsigned)((maxMN + kThreads - 1) / kThreads), (unsigned)nred);
+    dim3 grid((unsigned)((maxMN + 15) / 16), (unsigned)nred);
     k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta, active);
     return hipGetLastError();
 }

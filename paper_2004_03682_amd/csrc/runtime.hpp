@@ -55,6 +55,7 @@ struct GemmDev {
     ZRed* reds = nullptr;
     int nred = 0;
     int maxMN = 0;
+    int maxM = 0;   // largest M over the problems (ZCFG_RED picks its register tile by it)
     double2* work = nullptr;
     MixedDev* mx = nullptr;   // present for the ops that may run in split precision
 };
@@ -222,10 +223,10 @@ struct fscc_ctx {
                     e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
                 } else if (!g.split) {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active);
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM);
                 } else {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                     0.0, 0, o.cA, o.cB, st, g.role, d_active);
+                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
                                                  beta, st, d_active);
@@ -303,6 +304,7 @@ fscc_status guarded(fscc_ctx* c, F f) {
     }
 }
 
+bool cfg_ok(const Op& o, int cfg);
 double cfg_cost(const Op& o, int cfg);
 int pick_cfg(const Op& o);
 std::vector<ZTile> xcd_order(const std::vector<ZTile>& logical);

@@ -1,7 +1,7 @@
-"""Kernel-level parity of the grouped complex FP64-MFMA GEMM (through the C ABI)
-against numpy, over every tile shape, K depth, transpose/conjugate flag and
-split-K choice, with ragged sizes (not multiples of any tile), K = 0 and
-accumulation (beta = 1)."""
+"""Kernel-level parity of the grouped complex FP64 GEMM forms (through the C
+ABI) against numpy: every MFMA tile shape, K depth, transpose/conjugate flag
+and split-K choice, the vector-ALU skinny, tall and reduction forms, with
+ragged sizes (not multiples of any tile), K = 0 and accumulation (beta = 1)."""
 import itertools
 
 import numpy as np
@@ -33,8 +33,8 @@ def _run(M, N, K, tA, tB, cA, cB, cfg, bk, split, beta, seed=0, alpha=0.7 - 0.3j
     dA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
     dB = torch.from_numpy(np.ascontiguousarray(B)).cuda()
     dC = torch.from_numpy(np.ascontiguousarray(C0)).cuda()
-    lda = A.shape[1] if A.size else 1
-    ldb = B.shape[1] if B.size else 1
+    lda = max(A.shape[1], 1)
+    ldb = max(B.shape[1], 1)
     F.zgemm(dA, dB, dC, M, N, K, max(lda, 1), max(ldb, 1), max(N, 1), tA, tB, cA, cB, alpha, beta, cfg, bk, split)
     out = dC.cpu().numpy()
     scale = max(1.0, np.abs(ref).max())
@@ -55,3 +55,35 @@ def test_zgemm_split_k_and_edges(cfg):
     for (M, N, K, beta) in [(7, 34, 3000, 0), (7, 7, 5000, 1), (20, 3, 700, 1), (9, 11, 0, 0), (9, 11, 0, 1)]:
         err = _run(M, N, K, 0, 1, 0, 0, cfg, 16, True, beta)
         assert err < 1e-13, (cfg, M, N, K, beta, err)
+
+
+TALL, RED = 7, 8
+
+
+@pytest.mark.parametrize("tB,cA,cB", [(0, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1)])
+def test_zgemm_tall_form(tB, cA, cB):
+    # many rows, short K, few columns (the t1 x integral products); K*N <= 1024
+    for (M, N, K) in [(1, 1, 1), (255, 7, 21), (257, 3, 48), (1000, 48, 7), (5000, 1, 64), (300, 16, 64),
+                      (77, 1024, 1), (513, 9, 0)]:
+        for beta in (0, 1):
+            err = _run(M, N, K, 0, tB, cA, cB, TALL, 16, False, beta, seed=M + N + K)
+            assert err < 1e-13, (tB, cA, cB, M, N, K, beta, err)
+
+
+@pytest.mark.parametrize("tA,cA,cB", [(0, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1)])
+def test_zgemm_reduction_form(tA, cA, cB):
+    # few outputs, long K (the amplitude x integral contractions over three
+    # indices); M <= 8, N <= 256; every register-tile size (M <= 2, 4, 8)
+    for (M, N, K) in [(1, 1, 1), (2, 21, 5000), (3, 21, 20011), (4, 7, 12345), (7, 48, 3001), (8, 256, 700),
+                      (5, 100, 1), (6, 13, 0)]:
+        for split in (True, False):
+            for beta in (0, 1):
+                err = _run(M, N, K, tA, 0, cA, cB, RED, 16, split, beta, seed=M * N + K)
+                assert err < 1e-13, (tA, cA, cB, M, N, K, split, beta, err)
+
+
+def test_vector_forms_reject_shapes_they_do_not_fit():
+    for (cfg, tA, tB, M, N, K) in [(TALL, 1, 0, 10, 3, 5), (TALL, 0, 0, 10, 3, 65), (TALL, 0, 1, 10, 40, 30),
+                                   (RED, 0, 1, 3, 3, 100), (RED, 0, 0, 9, 3, 100), (RED, 1, 0, 3, 257, 100)]:
+        with pytest.raises(Exception):
+            _run(M, N, K, tA, tB, 0, 0, cfg, 16, True, 0)
