@@ -226,6 +226,30 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
  * from the next fscc_update_amplitudes. */
 fscc_status fscc_level_shift(fscc_ctx *ctx, fscc_sector sector, double shift);
 
+/* Dynamic denominator shifts against intruder states (the FS-RCC method's
+ * shifting of ill-defined, nearly zero or positive, energy denominators,
+ * followed by extrapolation to zero shift).  With S < 0 (Eh) and integer
+ * exponent n (1..16) every amplitude K of the sector gets
+ *   Delta_K = S * (S / (min(D_K, 0) + S))^n
+ * (D_K: the sector's Jacobi denominator in use), and the solved equations
+ * become R_K = Delta_K s_K: fscc_update_amplitudes takes the step
+ * (R - Delta s) / (D + Delta).  Delta = S where D = 0 and decays as
+ * S (S/D)^n for |D| >> |S|.  S = 0 switches the shift off (n ignored).
+ * Clears the sector's DIIS history.  FSCC_EINVAL for S > 0, S <= -1e6, n out
+ * of range, or FSCC_S01 on a context without the sector.  Contexts of the
+ * batch API do not take shifts. */
+fscc_status fscc_dynamic_shift(fscc_ctx *ctx, fscc_sector sector, double S, int n);
+
+/* Value at x0 of the [L/M] Pade approximant
+ *   E(x) = (a_0 + a_1 x + ... + a_L x^L) / (1 + b_1 x + ... + b_M x^M)
+ * fitted to npts points (x[i], y[i]) by linearised least squares
+ * (sum_j a_j x^j - y sum_{j>=1} b_j x^j = y), e.g. state energies at shifts
+ * x_i * S extrapolated to x0 = 0.  Host arrays; host code only (no device
+ * work).  npts >= L + M + 1, L + M + 1 <= 17, npts <= 4096.  FSCC_EINVAL on
+ * bad sizes, non-finite input, a rank-deficient system or a non-finite
+ * result. */
+fscc_status fscc_pade(int npts, const double *x, const fscc_c128 *y, int L, int M, double x0, fscc_c128 *out);
+
 /* Arithmetic of the three dominant (0h,0p) contractions: the particle-
  * particle ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets
  * (the T2 part of W_mbej and sum_me t_im^ae W_mbej), which together carry

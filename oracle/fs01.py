@@ -20,7 +20,8 @@ electron-attachment EOM-CCSD sigma equations, complex-correct placement of
 every integral as <creators||annihilators>); signs and conjugates are pinned
 by comparing sigma with a brute-force <mu| exp(-T) H exp(T) - E |nu> matrix
 (oracle.fock.ea_matrix).  Update: s += R / D with D_x^a = e_x - e_a,
-D_xj^ab = e_x + e_j - e_a - e_b (Eq. (3)-(4) denominators of the sector).
+D_xj^ab = e_x + e_j - e_a - e_b (Eq. (3)-(4) denominators of the sector);
+with dynamic shifts (oracle.shift) s += (R - Delta s) / (D + Delta).
 Dense backend only (x is a leading index over the active set).
 """
 from __future__ import annotations
@@ -79,10 +80,12 @@ def sigma(be, hb, r1, r2):
 class FS01:
     """(0h,1p) sector at fixed converged T: residual, update, H_eff."""
 
-    def __init__(self, be, t1, t2, active, precond="bare", floor=0.1):
+    def __init__(self, be, t1, t2, active, precond="bare", floor=0.1, shift=None):
         """precond: 'bare' -> D from orbital energies (Eq. (3)); 'dressed' -> D from the
         diagonal of Hbar (Fbar_xx + Fbar_jj - Fbar_aa - Fbar_bb, real part), clamped to
-        <= -floor.  Only the step changes; the fixed point R = 0 does not."""
+        <= -floor.  Only the step changes; the fixed point R = 0 does not.
+        shift = (S, n): dynamic denominator shifts (oracle.shift) evaluated on
+        the denominators in use; the solved equations become R = Delta s."""
         self.be = be
         self.hb = hbar(be, t1, t2)
         sys_ = be.sys
@@ -103,6 +106,12 @@ class FS01:
                                  - fv[None, None, None, :], -floor)
         elif precond != "bare":
             raise ValueError(precond)
+        self.Delta1 = np.zeros_like(self.D1)
+        self.Delta2 = np.zeros_like(self.D2)
+        if shift is not None:
+            from .shift import delta
+            self.Delta1 = delta(self.D1, shift[0], shift[1])
+            self.Delta2 = delta(self.D2, shift[0], shift[1])
         g = sys_.irrep
         go, gv = g[: self.no], g[self.no:]
         gx = gv[self.act]
@@ -134,18 +143,22 @@ class FS01:
         return R1, R2, heff
 
 
-def solve_fs01(fs, tol=1e-10, maxit=200, ndiis=6, log=None):
-    """Jacobi + DIIS on (S1, S2).  Returns dict(s1, s2, heff, eig, iters, converged)."""
+def solve_fs01(fs, tol=1e-10, maxit=200, ndiis=6, log=None, start=None):
+    """Jacobi + DIIS on (S1, S2) (shifted equations if fs has shifts); start =
+    (s1, s2) or zeros.  Returns dict(s1, s2, heff, eig, iters, converged)."""
     from .solver import diis_coefficients
-    s1, s2 = fs.zeros()
+    s1, s2 = fs.zeros() if start is None else (start[0].copy(), start[1].copy())
     hist_t, hist_e = [], []
     converged = False
     heff = None
     k = 0
     for k in range(1, maxit + 1):
         R1, R2, heff = fs.residual(s1, s2)
-        e1 = np.where(fs.mask1, R1 / np.where(fs.mask1, fs.D1, 1.0), 0.0)
-        e2 = np.where(fs.mask2, R2 / fs.D2, 0.0)
+        # shifted equations: R - Delta s = 0, step (R - Delta s) / (D + Delta)
+        R1 = R1 - fs.Delta1 * s1
+        R2 = R2 - fs.Delta2 * s2
+        e1 = np.where(fs.mask1, R1 / np.where(fs.mask1, fs.D1 + fs.Delta1, 1.0), 0.0)
+        e2 = np.where(fs.mask2, R2 / (fs.D2 + fs.Delta2), 0.0)
         n1, n2 = s1 + e1, s2 + e2
         dmax = max(float(np.abs(e1).max()), float(np.abs(e2).max()) if e2.size else 0.0)
         if ndiis > 1:

@@ -65,6 +65,8 @@ def lib():
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
             "fscc_set_precision": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
+            "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
+            "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
             "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
@@ -176,6 +178,11 @@ class Context:
     def level_shift(self, shift, sector=FSCC_S00):
         """Jacobi step R / (D - shift) for the sector (damping; same fixed point)."""
         self._check(lib().fscc_level_shift(self._h, sector, float(shift)))
+
+    def dynamic_shift(self, S, n=3, sector=FSCC_S01):
+        """Dynamic denominator shifts Delta = S (S/(min(D,0)+S))^n of the sector
+        (S < 0; S = 0 switches them off): the solved equations become R = Delta s."""
+        self._check(lib().fscc_dynamic_shift(self._h, sector, float(S), int(n)))
 
     def set_precision(self, precision):
         """'fp64', 'split_bf16' or 'split_fp32' for the ladder and ring contractions."""
@@ -314,6 +321,46 @@ def solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=6, log=None):
     w = np.linalg.eigvals(h)
     w = w[np.lexsort((w.imag, w.real))]
     return dict(heff=h, eig=w, iters=k, converged=converged)
+
+
+def pade(x, y, L, M, x0=0.0):
+    """Value at x0 of the [L/M] Pade approximant fitted to (x[i], y[i]) (fscc_pade)."""
+    import numpy as np
+    xs = np.ascontiguousarray(x, dtype=np.float64)
+    ys = np.ascontiguousarray(y, dtype=np.complex128)
+    if xs.shape != ys.shape or xs.ndim != 1:
+        raise ValueError("x and y must be 1-D of equal length")
+    out = np.zeros(1, dtype=np.complex128)
+    r = lib().fscc_pade(int(xs.size), xs.ctypes.data_as(ctypes.c_void_p), ys.ctypes.data_as(ctypes.c_void_p),
+                        int(L), int(M), float(x0), out.ctypes.data_as(ctypes.c_void_p))
+    if r != 0:
+        raise FsccError(r, "fscc_pade failed")
+    return complex(out[0])
+
+
+def solve01_extrapolated(ctx, s1, s2, S, n=3, scales=(1.0, 0.8, 0.6, 0.4), L=1, M=1, tol=1e-10, maxit=200,
+                         ndiis=6, log=None):
+    """(0h,1p) sector solved with dynamic shifts lambda*S for each lambda in
+    `scales` (each solve starts from the previous amplitudes), then every
+    state energy (sorted by real part) extrapolated to lambda = 0 by an [L/M]
+    Pade approximant.  Returns dict(scales, eig (per scale), iters,
+    converged, extrapolated).  The shift is switched off afterwards."""
+    import numpy as np
+    eigs, iters, conv = [], [], []
+    try:
+        for lam in scales:
+            ctx.dynamic_shift(lam * S, n, FSCC_S01)
+            r = solve01(ctx, s1, s2, tol=tol, maxit=maxit, ndiis=ndiis, log=log)
+            eigs.append(r["eig"])
+            iters.append(r["iters"])
+            conv.append(r["converged"])
+    finally:
+        ctx.dynamic_shift(0.0, n, FSCC_S01)
+    ext = None
+    if all(conv) and len(scales) >= L + M + 1:
+        E = np.array(eigs)
+        ext = np.array([pade(scales, E[:, k], L, M, 0.0) for k in range(E.shape[1])])
+    return dict(scales=list(scales), eig=eigs, iters=iters, converged=conv, extrapolated=ext)
 
 
 def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True):

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -662,11 +663,11 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
         int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
         if (n1 > 0)
             hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[D.b_D1], ht, he, n1,
-                                    ctx->part_max, nb1, ctx->st, D.shift),
+                                    ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
                       "jacobi 1");
         if (n2 > 0)
             hip_check(launch_jacobi((const double2*)t2, (const double2*)r2, (const double*)ctx->dbuf[D.b_D2], ht + n1,
-                                    he + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift),
+                                    he + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift, D.dyn_S, D.dyn_n),
                       "jacobi 2");
         int m = (int)ord.size();
         std::vector<const double2*> ev(m);
@@ -903,6 +904,76 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         (void)hipFree(tmp);
         return FSCC_OK;
     });
+}
+
+fscc_status fscc_dynamic_shift(fscc_ctx* ctx, fscc_sector sector, double S, int n) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S00 && sector != FSCC_S01) return fail(ctx, FSCC_EINVAL, "unknown sector");
+    if (sector == FSCC_S01 && !ctx->plan.has01) return fail(ctx, FSCC_EINVAL, "context has no (0h,1p) sector");
+    if (!(S <= 0.0 && S > -1e6) || (S < 0.0 && (n < 1 || n > 16)))
+        return fail(ctx, FSCC_EINVAL, "dynamic shift needs -1e6 < S <= 0 and 1 <= n <= 16");
+    Diis& D = ctx->diis[sector];
+    D.dyn_S = S;
+    D.dyn_n = S < 0.0 ? n : 0;
+    D.order.clear();   // iterates of other equations are no DIIS history
+    return FSCC_OK;
+}
+
+// Linearised least-squares Pade fit: modified Gram-Schmidt QR of the
+// augmented complex system [A | y] (Bjorck's least-squares form), then back
+// substitution; at most 17 unknowns.
+fscc_status fscc_pade(int npts, const double* x, const fscc_c128* y, int L, int M, double x0, fscc_c128* out) {
+    if (!x || !y || !out || L < 0 || M < 0 || L + M + 1 > 17 || npts < L + M + 1 || npts > 4096) return FSCC_EINVAL;
+    typedef std::complex<double> cd;
+    const int nu = L + M + 1, nc = nu + 1;
+    // column j of the augmented matrix: Q[j * npts + i]
+    //   rows: sum_j a_j x^j - y sum_{j>=1} b_j x^j = y
+    std::vector<cd> Q((size_t)nc * npts);
+    for (int i = 0; i < npts; ++i) {
+        const cd yi(y[i].re, y[i].im);
+        if (!std::isfinite(x[i]) || !std::isfinite(yi.real()) || !std::isfinite(yi.imag())) return FSCC_EINVAL;
+        double p = 1.0;
+        for (int j = 0; j <= L; ++j, p *= x[i]) Q[(size_t)j * npts + i] = p;
+        p = x[i];
+        for (int j = 1; j <= M; ++j, p *= x[i]) Q[(size_t)(L + j) * npts + i] = -yi * p;
+        Q[(size_t)nu * npts + i] = yi;
+    }
+    std::vector<cd> R((size_t)nu * nc, cd(0.0));
+    std::vector<double> n0(nu, 0.0);
+    for (int j = 0; j < nu; ++j) {
+        for (int i = 0; i < npts; ++i) n0[j] += std::norm(Q[(size_t)j * npts + i]);
+        n0[j] = std::sqrt(n0[j]);
+    }
+    for (int j = 0; j < nu; ++j) {
+        double nrm = 0.0;
+        for (int i = 0; i < npts; ++i) nrm += std::norm(Q[(size_t)j * npts + i]);
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 1e-12 * n0[j])) return FSCC_EINVAL;   // numerically rank deficient
+        R[(size_t)j * nc + j] = nrm;
+        for (int i = 0; i < npts; ++i) Q[(size_t)j * npts + i] /= nrm;
+        for (int k = j + 1; k < nc; ++k) {
+            cd d = 0.0;
+            for (int i = 0; i < npts; ++i) d += std::conj(Q[(size_t)j * npts + i]) * Q[(size_t)k * npts + i];
+            R[(size_t)j * nc + k] = d;
+            for (int i = 0; i < npts; ++i) Q[(size_t)k * npts + i] -= d * Q[(size_t)j * npts + i];
+        }
+    }
+    std::vector<cd> coef(nu);
+    for (int r = nu - 1; r >= 0; --r) {
+        cd acc = R[(size_t)r * nc + nu];
+        for (int k = r + 1; k < nu; ++k) acc -= R[(size_t)r * nc + k] * coef[k];
+        coef[r] = acc / R[(size_t)r * nc + r];
+    }
+    cd num = 0.0, den = 1.0;
+    double p = 1.0;
+    for (int j = 0; j <= L; ++j, p *= x0) num += coef[j] * p;
+    p = x0;
+    for (int j = 1; j <= M; ++j, p *= x0) den += coef[L + j] * p;
+    const cd v = num / den;
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return FSCC_EINVAL;
+    out->re = v.real();
+    out->im = v.imag();
+    return FSCC_OK;
 }
 
 fscc_status fscc_level_shift(fscc_ctx* ctx, fscc_sector sector, double shift) {

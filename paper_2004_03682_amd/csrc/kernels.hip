@@ -24,7 +24,7 @@ static constexpr int kThreads = 256;
 
 // ROLE only distinguishes kernel symbols in profiles (0 generic, 1 pp-ladder, 2 ring).
 template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE>
-__global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
+__global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
                                                int cA, int cB, const int* __restrict__ active) {
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
     const double2* Bp = B + pr.b_off;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WN, wn = wave % WN;
     const int m0 = tl.m0, n0 = tl.n0;
     const double sA = cA ? -1.0 : 1.0;
@@ -215,6 +215,9 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
     const int lr = lane & 15;        // row (A) / column (B) inside a 16-wide fragment
     const int lk = lane >> 4;        // k inside a 4-deep step
     const int wm0 = wm * FM * 16, wn0 = wn * FN * 16;
+    // a wave whose whole fragment block lies outside the problem (edge tiles)
+    // issues no MFMA
+    const bool wave_live = m0 + wm0 < M && n0 + wn0 < N;
 
     // LDS buffer 0 holds the real planes, buffer 1 the imaginary planes; the
     // global loads of slice k+1 are in flight while slice k is multiplied
@@ -225,8 +228,11 @@ __global__ __launch_bounds__(256) void k_zgemm(const double2* __restrict__ A, co
         store_slice_im(1);
         __syncthreads();
         if (k0 + BK < K) load_slice(k0 + BK);
-#pragma unroll
+        // large fragment grids: one 4-deep step at a time keeps the register
+        // count (and so the occupancy) of the 64x64 tile in check
+#pragma unroll(FM * FN >= 4 ? 1 : BK / 4)
         for (int ks = 0; ks < BK / 4; ++ks) {
+            if (!wave_live) break;
             double a_r[FM], a_i[FM], a_n[FM], b_r[FN], b_i[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
@@ -932,15 +938,32 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     return r;
 }
 
+// Dynamic denominator shift of one amplitude (sector shift S < 0, exponent
+// n >= 1): Delta = S (S / (min(D, 0) + S))^n; the shifted equations are
+// R = Delta t, solved by the step (R - Delta t) / (D + Delta).
+__device__ __forceinline__ double dyn_delta(double d, double S, int n) {
+    const double q = S / (fmin(d, 0.0) + S);
+    double p = q;
+    for (int i = 1; i < n; ++i) p *= q;
+    return S * p;
+}
+
 __global__ __launch_bounds__(256) void k_jacobi(const double2* __restrict__ t, const double2* __restrict__ r,
                                                 const double* __restrict__ D, double2* __restrict__ ht,
                                                 double2* __restrict__ he, long long n, double* part_max,
-                                                double shift) {
+                                                double shift, double dS, int dn) {
     __shared__ double sh[kThreads];
     double mx = 0.0;
     for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
         double2 rr = r[k], tt = t[k];
-        double d = D[k] - shift;
+        double d = D[k];
+        if (dS != 0.0) {
+            const double dl = dyn_delta(d, dS, dn);
+            rr.x -= dl * tt.x;
+            rr.y -= dl * tt.y;
+            d += dl;
+        }
+        d -= shift;
         double2 s = make_double2(rr.x / d, rr.y / d);
         he[k] = s;
         ht[k] = make_double2(tt.x + s.x, tt.y + s.y);
@@ -952,8 +975,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double2* __restrict__ t, c
 }
 
 hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
-                         long long n, double* part_max, int nblk, hipStream_t st, double shift) {
-    k_jacobi<<<nblk, kThreads, 0, st>>>(t, r, D, hist_t, hist_e, n, part_max, shift);
+                         long long n, double* part_max, int nblk, hipStream_t st, double shift, double dyn_S,
+                         int dyn_n) {
+    if (dyn_S != 0.0 && !(dyn_S < 0.0 && dyn_n >= 1)) return hipErrorInvalidValue;
+    k_jacobi<<<nblk, kThreads, 0, st>>>(t, r, D, hist_t, hist_e, n, part_max, shift, dyn_S, dyn_n);
     return hipGetLastError();
 }
 

@@ -111,9 +111,11 @@ hipError_t launch_mul(double2* dst, const double* d, long long n, hipStream_t st
                       SegBlocks sb = SegBlocks());   // dst *= d (real)
 
 // Jacobi: step = r/(D - shift); tn = t + step (written to hist_t), e = step (hist_e);
-// per-block max |step| into part_max[block]
+// per-block max |step| into part_max[block].  dyn_S < 0: dynamic shifts
+// Delta = dyn_S (dyn_S / (min(D,0) + dyn_S))^dyn_n, step = (r - Delta t) / (D + Delta - shift).
 hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, double2* hist_t, double2* hist_e,
-                         long long n, double* part_max, int nblk, hipStream_t st, double shift = 0.0);
+                         long long n, double* part_max, int nblk, hipStream_t st, double shift = 0.0,
+                         double dyn_S = 0.0, int dyn_n = 0);
 // sum_b part[b*stride + j] -> out[j]  (j < cols), and max over part_max
 hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
                        hipStream_t st);

@@ -89,6 +89,8 @@ struct Diis {
     int64_t n1 = 0, n2 = 0;
     int b_D1 = -1, b_D2 = -1;
     double shift = 0.0;   // level shift of the Jacobi denominators
+    double dyn_S = 0.0;   // dynamic denominator shift (changes the solved equations)
+    int dyn_n = 0;
 };
 
 

@@ -111,3 +111,71 @@ def test_fs01_dressed_preconditioner_same_fixed_point():
     assert np.abs(out[0] - out[1]).max() <= 1e-10
     assert np.abs(out[1] - o["eig"]).max() <= 1e-10
     ctx.destroy()
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_fs01_dynamic_shift_and_extrapolation_match_oracle(n):
+    # shifted equations R = Delta s at several shift scales, then the [2/1]
+    # Pade extrapolation to zero shift: GPU path against the oracle chain
+    import torch
+    import paper_2004_03682_amd as F
+    from oracle import shift
+    s = fsgen.make_system(7, 19, 3, 0.05, 8, nact=6)
+    print("case shift n", n, flush=True)
+    be = ccsd.Dense(s)
+    ctx = _ctx(s)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    assert F.solve(ctx, t1, t2, tol=1e-11)["converged"]
+    ctx.prepare_sector(t1, t2)
+    s1 = torch.zeros(ctx.m1, dtype=torch.complex128, device="cuda")
+    s2 = torch.zeros(ctx.m2, dtype=torch.complex128, device="cuda")
+    lams = (1.0, 0.8, 0.6, 0.4, 0.2)
+    g = F.solve01_extrapolated(ctx, s1, s2, -0.5, n, scales=lams, L=2, M=1, tol=1e-11)
+    assert all(g["converged"])
+    r = solver.solve_ccsd(be, tol=1e-11)
+    E, st = [], None
+    for lam in lams:
+        o = fs01.solve_fs01(fs01.FS01(be, r["t1"], r["t2"], s.active, shift=(-0.5 * lam, n)), tol=1e-11, start=st)
+        assert o["converged"]
+        st = (o["s1"], o["s2"])
+        E.append(o["eig"])
+    E = np.array(E)
+    assert np.abs(np.array(g["eig"]) - E).max() <= 1e-10
+    ext = np.array([shift.pade(lams, E[:, k], 2, 1) for k in range(E.shape[1])])
+    assert np.abs(g["extrapolated"] - ext).max() <= 1e-9
+    # the shift is off again: an unshifted solve reproduces the oracle's unshifted energies
+    s1.zero_()
+    s2.zero_()
+    u = F.solve01(ctx, s1, s2, tol=1e-11)
+    o = fs01.solve_fs01(fs01.FS01(be, r["t1"], r["t2"], s.active), tol=1e-11)
+    assert np.abs(u["eig"] - o["eig"]).max() <= 1e-10
+    ctx.destroy()
+
+
+def test_pade_matches_oracle_and_rejects_bad_input():
+    import paper_2004_03682_amd as F
+    from oracle import shift
+    rng = np.random.default_rng(7)
+    for (npts, L, M) in [(3, 1, 1), (5, 2, 1), (6, 2, 2), (9, 3, 2), (4, 3, 0)]:
+        x = np.sort(rng.uniform(0.1, 1.0, npts))
+        y = (1.0 + rng.normal(size=npts) * 0.1) * np.exp(1j * rng.normal(size=npts) * 0.1) / (1 + 0.3 * x)
+        a = F.pade(x, y, L, M)
+        b = shift.pade(x, y, L, M)
+        assert abs(a - b) <= 1e-9 * max(1.0, abs(b)), (npts, L, M, a, b)
+    with pytest.raises(F.FsccError):
+        F.pade([0.5, 1.0], [1.0, 2.0], 1, 1)
+    with pytest.raises(F.FsccError):
+        F.pade([0.5, 0.5, 0.5], [1.0, 1.0, 1.0], 1, 1)
+
+
+def test_dynamic_shift_rejects_bad_parameters():
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(3, 6, 1, 0.1, 5, nact=2)
+    ctx = _ctx(s)
+    for S, n in [(0.5, 3), (-0.5, 0), (-0.5, 17), (-2e6, 3)]:
+        with pytest.raises(F.FsccError):
+            ctx.dynamic_shift(S, n)
+    ctx.dynamic_shift(-0.5, 3)
+    ctx.dynamic_shift(0.0, 0)
+    ctx.destroy()
