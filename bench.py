@@ -416,7 +416,7 @@ def main():
 
     t0 = time.perf_counter()
     ctx.autotune(1)
-    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32"}
+    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction"}
     tuned = {n: f"{names[c]}/bk{b}{'/splitK' if sp else ''}" for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
@@ -506,7 +506,7 @@ def main():
         torch.cuda.synchronize()
         st = time.perf_counter()
         try:
-            while n01 < 200:
+            while n01 < 100:
                 ctx.build_residual(s1, s2, q1, q2, F.FSCC_S01)
                 d01 = ctx.update_amplitudes(s1, s2, q1, q2, F.FSCC_S01)
                 n01 += 1
@@ -515,7 +515,7 @@ def main():
                 if d01 < 1e-10:
                     break
             else:
-                status = "not converged in 200 iterations"
+                status = "not converged in 100 iterations"
         except F.FsccError as e:
             status = f"diverged at iteration {n01 + 1} ({e})"
         torch.cuda.synchronize()
@@ -527,8 +527,38 @@ def main():
             w = np.linalg.eigvals(h)
             w = w[np.lexsort((w.imag, w.real))]
             fs["heff_eigenvalues_re"] = [float(x.real) for x in w]
-        result["fs01"] = fs
         log(f"(0h,1p): {status}; {n01} iterations, {fs['ms_per_iteration']:.3f} ms/iteration")
+        # the intruder-state remedy: dynamic denominator shifts at decreasing
+        # scale, then Pade extrapolation of every state energy to zero shift
+        ctx.precondition(0, 0.1)
+        S_dyn, n_dyn, scales = -3.0, 3, (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4)
+        s1.zero_()
+        s2.zero_()
+        torch.cuda.synchronize()
+        st = time.perf_counter()
+        try:
+            xr = F.solve01_extrapolated(ctx, s1, s2, S_dyn, n_dyn, scales=scales, L=2, M=1, tol=1e-10, maxit=200,
+                                        ndiis=8)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - st
+            sh = {"S": S_dyn, "n": n_dyn, "scales": list(scales), "pade": [2, 1], "ndiis": 8,
+                  "iterations": xr["iters"], "converged": xr["converged"], "seconds": round(el, 4),
+                  "ms_per_iteration": round(el / max(1, sum(xr["iters"])) * 1e3, 4),
+                  "eigenvalues_re_by_scale": [[float(x.real) for x in e] for e in xr["eig"]]}
+            if xr["extrapolated"] is not None:
+                sh["extrapolated_re"] = [float(x.real) for x in xr["extrapolated"]]
+                sh["extrapolated_im"] = [float(x.imag) for x in xr["extrapolated"]]
+                # spread between two approximant orders: a measure of the extrapolation error
+                E = np.array(xr["eig"])
+                alt = np.array([F.pade(list(scales), E[:, k], 3, 0) for k in range(E.shape[1])])
+                sh["max_abs_diff_pade_2_1_vs_3_0"] = float(np.abs(alt - xr["extrapolated"]).max())
+            fs["dynamic_shift"] = sh
+            log(f"(0h,1p) with dynamic shifts S={S_dyn} n={n_dyn}: iterations {xr['iters']}, "
+                f"extrapolated {sh.get('extrapolated_re')}")
+        except F.FsccError as e:
+            fs["dynamic_shift"] = {"S": S_dyn, "n": n_dyn, "status": f"failed ({e})"}
+            log(f"(0h,1p) with dynamic shifts failed: {e}")
+        result["fs01"] = fs
     ctx.destroy()
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
