@@ -133,15 +133,18 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
         u2.copy_(mp2[1])
         ctx.build_residual(u1, u2, q1, q2)
         err = max(float((q1 - R1).abs().max()), float((q2 - R2).abs().max())) / Rmax
-        # per-iteration time (profiled like the FP64 line)
+        # per-operation times from profiled warm-up iterations, then the
+        # per-iteration time of unprofiled steps
         u1.zero_()
         u2.zero_()
         ctx.diis_reset(6)
-        for _ in range(args.warmup):
+        ctx.profile(True)
+        for _ in range(max(1, args.warmup)):
             ctx.build_residual(u1, u2, q1, q2)
             ctx.update_amplitudes(u1, u2, q1, q2)
             ctx.energy(u1, u2)
-        ctx.profile(True)
+        ops = {o["name"]: o for o in ctx.op_times()}
+        ctx.profile(False)
         torch.cuda.synchronize()
         st = time.perf_counter()
         for _ in range(args.steps):
@@ -150,8 +153,6 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
             ctx.energy(u1, u2)
         torch.cuda.synchronize()
         per_it = (time.perf_counter() - st) / args.steps
-        ops = {o["name"]: o for o in ctx.op_times()}
-        ctx.profile(False)
         mfac = 6.0 if prec == "split_bf16" else 3.0
         peak = 2500.0 if prec == "split_bf16" else 157.3
         lad = ops["pp-ladder"]
@@ -432,9 +433,24 @@ def main():
         d = ctx.update_amplitudes(t1, t2, r1, r2)
         return d, ctx.energy(t1, t2)
 
-    for _ in range(args.warmup):
-        dmax, E = step()
+    # warm-up iterations time every operation (HIP events around each one):
+    # the per-operation table and the choice of the dominant GEMM
     ctx.profile(True)
+    for _ in range(max(1, args.warmup)):
+        dmax, E = step()
+    ops = ctx.op_times()
+    ctx.profile(False)
+    nwarm = max(1, args.warmup)
+    gemms = [o for o in ops if o["flops"] > 0 and o["calls"] > 0]
+    resid_ms = sum(o["ms"] for o in ops) / nwarm
+    for o in sorted(ops, key=lambda o: -o["ms"])[:12]:
+        per = o["ms"] / max(1, o["calls"])
+        tf = o["flops"] / (per * 1e-3) / 1e12 if o["flops"] and per > 0 else 0.0
+        log(f"  {o['name']:18s} {per:8.3f} ms/call  {tf:7.2f} TFLOP/s")
+    dom_name = max(gemms, key=lambda o: o["ms"])["name"]
+    gemm_ms = sum(o["ms"] for o in gemms) / nwarm
+    # timed region: events only around the dominant GEMM, on the library's stream
+    ctx.profile(True, only=dom_name)
     torch.cuda.synchronize()
     st = time.perf_counter()
     hist = []
@@ -443,22 +459,14 @@ def main():
         hist.append((dmax, E))
     torch.cuda.synchronize()
     el = time.perf_counter() - st
-    ops = ctx.op_times()
+    dom = next(o for o in ctx.op_times() if o["name"] == dom_name)
     ctx.profile(False)
     work = ctx.work()
     s_per_iter = el / args.steps
     log(f"{args.steps} iterations in {el:.4f}s -> {s_per_iter * 1e3:.3f} ms/iteration; E = {E}")
-    gemms = [o for o in ops if o["flops"] > 0 and o["calls"] > 0]
-    resid_ms = sum(o["ms"] for o in ops) / max(1, args.steps)
-    for o in sorted(ops, key=lambda o: -o["ms"])[:12]:
-        per = o["ms"] / max(1, o["calls"])
-        tf = o["flops"] / (per * 1e-3) / 1e12 if o["flops"] and per > 0 else 0.0
-        log(f"  {o['name']:18s} {per:8.3f} ms/call  {tf:7.2f} TFLOP/s")
-    dom = max(gemms, key=lambda o: o["ms"])
     per_launch_s = dom["ms"] / dom["calls"] * 1e-3
     achieved = dom["flops"] / per_launch_s / 1e12
     traffic = measured_traffic(dom["name"], tuned.get(dom["name"]))
-    gemm_ms = sum(o["ms"] for o in gemms) / max(1, args.steps)
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64, 4), "traffic": traffic,
             "kernel": "k_zgemm (grouped complex FP64 MFMA GEMM), op '%s'" % dom["name"],

@@ -188,6 +188,13 @@ fscc_status fscc_work(const fscc_ctx *ctx, double *gemm_flops, double *ladder_fl
  * the name (static until destroy), accumulated milliseconds, number of
  * timed calls and real flops per call of operation k (host outputs). */
 fscc_status fscc_profile(fscc_ctx *ctx, int enable);
+
+/* While profiling is enabled, record events only around operation k
+ * (k = -1: every operation, the default).  Events are read back when the
+ * next residual evaluation starts or by fscc_op_info / fscc_profile, so
+ * profiling adds no stream synchronisation; timing one operation leaves the
+ * others' launch sequence untouched.  FSCC_EINVAL if k is not an operation. */
+fscc_status fscc_profile_select(fscc_ctx *ctx, int k);
 fscc_status fscc_op_count(const fscc_ctx *ctx, int *count);
 fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, int *calls, double *flops);
 

@@ -64,6 +64,7 @@ def lib():
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
             "fscc_set_precision": ([vp, ip], ip),
+            "fscc_profile_select": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
             "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
@@ -260,8 +261,25 @@ class Context:
         self._check(lib().fscc_work(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return dict(gemm_flops=a.value, ladder_flops=b.value, ladder_bytes=c.value)
 
-    def profile(self, enable=True):
+    def profile(self, enable=True, only=None):
+        """Per-operation HIP-event timing; only = an operation name (or index)
+        times that operation alone."""
+        k = -1
+        if only is not None:
+            k = only if isinstance(only, int) else self.op_index(only)
+        self._check(lib().fscc_profile_select(self._h, int(k)))
         self._check(lib().fscc_profile(self._h, 1 if enable else 0))
+
+    def op_index(self, name):
+        n = ctypes.c_int()
+        self._check(lib().fscc_op_count(self._h, ctypes.byref(n)))
+        for k in range(n.value):
+            nm, ms, calls, fl = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+            self._check(lib().fscc_op_info(self._h, k, ctypes.byref(nm), ctypes.byref(ms), ctypes.byref(calls),
+                                           ctypes.byref(fl)))
+            if nm.value.decode() == name:
+                return k
+        raise KeyError(name)
 
     def op_times(self):
         n = ctypes.c_int()

@@ -386,6 +386,7 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     setup_list(c, c->L00, P.ops);
     setup_list(c, c->L01p, P.ops01_prep);
     setup_list(c, c->L01, P.ops01);
+    c->L01.base = (int)P.ops.size();
     if (diis) setup_diis(c, c->diis[0], c->n1(), c->n2(), P.b_D1, P.b_D2);
     if (P.has01) {
         setup_diis(c, c->diis[1], P.L_S1.total, P.L_S2.total, P.b_D1x, P.b_D2x);
@@ -736,11 +737,22 @@ fscc_status fscc_work(const fscc_ctx* ctx, double* gemm_flops, double* ladder_fl
 
 fscc_status fscc_profile(fscc_ctx* ctx, int enable) {
     if (!ctx) return FSCC_EINVAL;
-    ctx->prof = enable != 0;
-    for (OpList* L : {&ctx->L00, &ctx->L01}) {
-        std::fill(L->ms.begin(), L->ms.end(), 0.0);
-        std::fill(L->calls.begin(), L->calls.end(), 0);
-    }
+    return guarded(ctx, [&]() -> fscc_status {
+        ctx->prof = enable != 0;
+        for (OpList* L : {&ctx->L00, &ctx->L01}) {
+            ctx->collect(*L);   // finish outstanding timings before clearing
+            std::fill(L->ms.begin(), L->ms.end(), 0.0);
+            std::fill(L->calls.begin(), L->calls.end(), 0);
+        }
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_profile_select(fscc_ctx* ctx, int k) {
+    if (!ctx) return FSCC_EINVAL;
+    int n = 0;
+    if (fscc_op_count(ctx, &n) != FSCC_OK || k < -1 || k >= n) return fail(ctx, FSCC_EINVAL, "no such operation");
+    ctx->prof_sel = k;
     return FSCC_OK;
 }
 
@@ -769,12 +781,15 @@ fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, in
     OpList* L;
     int j;
     if (!op_ref(ctx, k, &L, &j)) return fail(ctx, FSCC_EINVAL, "op index out of range");
-    const Op& o = (*L->ops)[j];
-    *name = o.name.c_str();
-    *ms = L->ms[j];
-    *calls = L->calls[j];
-    *flops = o.flops;
-    return FSCC_OK;
+    return guarded(ctx, [&]() -> fscc_status {
+        ctx->collect(*L);
+        const Op& o = (*L->ops)[j];
+        *name = o.name.c_str();
+        *ms = L->ms[j];
+        *calls = L->calls[j];
+        *flops = o.flops;
+        return FSCC_OK;
+    });
 }
 
 // Measure every candidate (tile shape x K depth x split) of each GEMM op on

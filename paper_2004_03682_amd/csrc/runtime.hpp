@@ -75,8 +75,10 @@ struct OpList {
     std::vector<Op>* ops = nullptr;
     std::vector<GemmDev> g;
     std::vector<hipEvent_t> ev;
+    std::vector<char> pend;   // events recorded, elapsed time not yet added
     std::vector<double> ms;
     std::vector<int> calls;
+    int base = 0;             // number of the first operation (fscc_op_info numbering)
 };
 
 // DIIS state of one sector
@@ -120,6 +122,7 @@ struct fscc_ctx {
     double* eout = nullptr;
     double2* rs_tmp = nullptr; // residual scratch for fscc_heff
     bool prof = false;
+    int prof_sel = -1;   // with prof: time only this operation (-1: all)
     int prec = FSCC_FP64;
     const int* d_active = nullptr;   // batched plans: per-system flags, GEMM tiles of 0-systems are skipped
     std::string err;
@@ -257,24 +260,36 @@ struct fscc_ctx {
         return e;
     }
 
+    // add the elapsed times of operations timed earlier (waits for their end events)
+    void collect(OpList& L) {
+        for (size_t k = 0; k < L.pend.size(); ++k) {
+            if (!L.pend[k]) continue;
+            hip_check(hipEventSynchronize(L.ev[2 * k + 1]), "event sync");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, L.ev[2 * k], L.ev[2 * k + 1]), "elapsed");
+            L.ms[k] += ms;
+            L.calls[k] += 1;
+            L.pend[k] = 0;
+        }
+    }
+
+    // timed: HIP events around every operation (or only operation prof_sel),
+    // read back lazily, so timing adds no synchronisation to the stream
     void run_list(OpList& L, bool timed) {
         std::vector<Op>& ops = *L.ops;
         if (timed && L.ev.size() != 2 * ops.size()) {
             L.ev.assign(2 * ops.size(), nullptr);
             for (auto& e : L.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+            L.pend.assign(ops.size(), 0);
         }
+        if (timed) collect(L);
         for (size_t k = 0; k < ops.size(); ++k) {
-            if (timed) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
+            const bool tk = timed && (prof_sel < 0 || prof_sel == L.base + (int)k);
+            if (tk) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
             run_op(ops[k], &L.g[k]);
-            if (timed) hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
-        }
-        if (timed) {
-            hip_check(hipStreamSynchronize(st), "profile sync");
-            for (size_t k = 0; k < ops.size(); ++k) {
-                float ms = 0.f;
-                hip_check(hipEventElapsedTime(&ms, L.ev[2 * k], L.ev[2 * k + 1]), "elapsed");
-                L.ms[k] += ms;
-                L.calls[k] += 1;
+            if (tk) {
+                hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
+                L.pend[k] = 1;
             }
         }
     }
