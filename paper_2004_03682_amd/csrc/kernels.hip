@@ -28,7 +28,10 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
                                                int cA, int cB, const int* __restrict__ active) {
-    constexpr int PAD = 4;
+    // odd row padding: the transposed slice stores (4 k rows x 16 columns per
+    // wave) and the fragment reads (4 k rows x 16 columns) spread over the
+    // LDS banks
+    constexpr int PAD = 1;
     constexpr int FM = BM / (16 * WM);
     constexpr int FN = BN / (16 * WN);
     static_assert(WM * WN == 4, "four waves");
