@@ -83,6 +83,7 @@ class System:
     eps: np.ndarray            # float64 [nocc+nvirt]
     nact: int = 0
     active: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))  # global indices
+    real: bool = False         # real-double-group stand-in: V = sqrt(2) Re V_complex
 
     @property
     def n(self) -> int:
@@ -112,7 +113,13 @@ def _largest_remainder(total: int, p: np.ndarray) -> np.ndarray:
     return c
 
 
-def make_system(nocc: int, nvirt: int, nirrep: int, sigma: float, seed: int, nact: int = 0) -> System:
+def make_system(nocc: int, nvirt: int, nirrep: int, sigma: float, seed: int, nact: int = 0,
+                real: bool = False) -> System:
+    """real=True: the integrals are sqrt(2) Re of the complex ones -- still
+    antisymmetric and now real symmetric (<pq||rs> = <rs||pq>), the case of
+    double groups with real irreducible representations; the same element
+    variance (sigma^2 / 8) as the complex draw.  Buffers stay complex128 with
+    zero imaginary parts (real_buffer() gives the float64 copy)."""
     rng = np.random.default_rng(seed)
     eo = np.sort(rng.uniform(-2.0, -0.5, nocc))
     ev = np.sort(rng.uniform(0.2, 3.0, nvirt))
@@ -128,7 +135,7 @@ def make_system(nocc: int, nvirt: int, nirrep: int, sigma: float, seed: int, nac
     eps = np.concatenate([eo, ev]).astype(np.float64)
     # active (0h,1p) set: the nact lowest-energy virtual spinors, whatever their irreps
     active = (nocc + np.arange(min(nact, nvirt))).astype(np.int32)
-    return System(nocc, nvirt, nirrep, float(sigma), int(seed), irrep, eps, nact, active)
+    return System(nocc, nvirt, nirrep, float(sigma), int(seed), irrep, eps, nact, active, bool(real))
 
 
 # Workload configurations (sizes of the paper-shaped synthetic systems).
@@ -175,7 +182,21 @@ def block(sysm: System, P, Q, R, S, out: np.ndarray | None = None) -> np.ndarray
         lib.fsgen_block(sysm.seed, sysm.sigma, sysm.n, _iptr(irr), sysm.nirrep,
                         _iptr(P), len(P), _iptr(Q), len(Q), _iptr(R), len(R), _iptr(S), len(S),
                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if sysm.real:
+            _make_real(out)
     return out.reshape(shape)
+
+
+def _make_real(a: np.ndarray) -> None:
+    """In place: a <- sqrt(2) Re a (imaginary parts zero)."""
+    a.real *= np.sqrt(2.0)
+    a.imag = 0.0
+
+
+def real_buffer(buf: np.ndarray) -> np.ndarray:
+    """float64 copy of a class buffer of a real system (for real-arithmetic contexts)."""
+    assert not np.any(buf.imag), "not a real system's buffer"
+    return np.ascontiguousarray(buf.real)
 
 
 def xraw(sysm: System, p, q, r, s) -> complex:
@@ -226,6 +247,8 @@ def class_buffer(sysm: System, cls: str, out: np.ndarray | None = None):
         sirr = np.ascontiguousarray(sysm.irrep[sysm.space(X)], dtype=np.int32)
         _get_lib().fsgen_class_sym(sysm.seed, sysm.sigma, sysm.n, base, len(sirr), _iptr(sirr), sysm.nirrep,
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if sysm.real:
+            _make_real(out)
     views = {}
     off = 0
     for key, shp in tuples:
@@ -279,6 +302,8 @@ def class_buffer_gpu(sysm: System, cls: str, out=None, stream=None):
     CUDA tensor (or fills `out`).  Values agree with the host generator to a
     few ulps (device transcendental functions)."""
     import torch
+    if sysm.real:
+        raise ValueError("the device generator draws complex integrals only")
     tuples = class_tuples(sysm, cls)
     total = int(sum(int(np.prod(s)) for _, s in tuples))
     if out is None:

@@ -93,7 +93,13 @@ typedef enum {
     FSCC_ENOCONV = -6  /* non-finite update (NaN / Inf in the step)              */
 } fscc_status;
 
-typedef enum { FSCC_FP64 = 0, FSCC_SPLIT_FP32 = 1, FSCC_SPLIT_BF16 = 2 } fscc_precision;
+/* Arithmetic of a context.  FSCC_REAL_FP64 (fscc_create only): real double
+ * groups -- integrals, amplitudes and residuals are real, every buffer the
+ * caller passes holds DOUBLES (8 bytes per element, the same layouts and
+ * element counts as the complex form), the fscc_c128 pointer types of the
+ * calls are reinterpreted accordingly and fscc_energy returns e_im = 0; the
+ * (0h,0p) sector only (nact must be 0), no split precision. */
+typedef enum { FSCC_FP64 = 0, FSCC_SPLIT_FP32 = 1, FSCC_SPLIT_BF16 = 2, FSCC_REAL_FP64 = 3 } fscc_precision;
 
 typedef enum { FSCC_S00 = 0, FSCC_S01 = 1 } fscc_sector; /* (0h,0p), (0h,1p) */
 
@@ -226,6 +232,13 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128 *A, int lda,
                        const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void *hip_stream);
+
+/* Real form of fscc_zgemm (kernel-level tests of the real-arithmetic path):
+ * C = alpha * op(A) op(B) + beta*C on doubles, same layout conventions and
+ * kernel forms except 6 (skinny), which has no real form (FSCC_EINVAL).
+ * Synchronises hip_stream. */
+fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, const double *A, int lda, const double *B,
+                       int ldb, double *C, int ldc, double alpha, int beta, int allow_split, void *hip_stream);
 
 /* Level shift (Eh, >= 0) of the (0h,0p) Jacobi step: step = R / (D - shift)
  * with D < 0 for every T1/T2 denominator, so the update is damped; the fixed

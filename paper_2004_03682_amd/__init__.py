@@ -2,7 +2,8 @@
 
 Every function here only marshals arguments to the C ABI declared in
 include/fscc.h; all computation runs in the library's HIP kernels.  Device
-buffers are torch tensors (complex128, on the GPU); torch is used for device
+buffers are torch tensors (complex128 -- float64 in a real-arithmetic
+context -- on the GPU); torch is used for device
 memory and streams only.  There is no CPU fallback: importing the binding
 without the built library, or calling it on tensors that are not on a GPU,
 raises.
@@ -16,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfscc.so")
 
 FSCC_S00, FSCC_S01 = 0, 1
-FSCC_FP64, FSCC_SPLIT_FP32, FSCC_SPLIT_BF16 = 0, 1, 2
-PRECISIONS = {"fp64": FSCC_FP64, "split_fp32": FSCC_SPLIT_FP32, "split_bf16": FSCC_SPLIT_BF16}
+FSCC_FP64, FSCC_SPLIT_FP32, FSCC_SPLIT_BF16, FSCC_REAL_FP64 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FSCC_FP64, "split_fp32": FSCC_SPLIT_FP32, "split_bf16": FSCC_SPLIT_BF16,
+              "real_fp64": FSCC_REAL_FP64}
 CLASSES = ("OOOO", "OOOV", "OOVV", "OVOV", "OVVV", "VVVV")
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESYMM", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "ENOCONV"}
 
@@ -66,6 +68,7 @@ def lib():
             "fscc_set_precision": ([vp, ip], ip),
             "fscc_profile_select": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
+            "fscc_dgemm": ([ip, ip, ip, ip, ip, ip, ip, vp, ip, vp, ip, vp, ip, ctypes.c_double, ip, ip, vp], ip),
             "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
@@ -129,14 +132,15 @@ def _ptr(t, dtype=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _dev_ptr(t, n=None):
+def _dev_ptr(t, n=None, dtype=None):
     if t is None:
         return None
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda):
         raise TypeError("fscc expects GPU tensors")
-    if t.dtype != torch.complex128 or not t.is_contiguous():
-        raise TypeError("fscc expects contiguous complex128 tensors")
+    want = torch.complex128 if dtype is None else dtype
+    if t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"fscc expects contiguous {want} tensors")
     if n is not None and t.numel() != n:
         raise ValueError(f"expected {n} elements, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
@@ -164,9 +168,16 @@ class Context:
         if st != 0:
             raise FsccError(st, "fscc_create failed")
         self._h = h
+        self.real = _prec(precision) == FSCC_REAL_FP64
+        self.dtype = torch.float64 if self.real else torch.complex128
         self.n1, self.n2 = self.layout(FSCC_S00)
         self.nact = len(self._act)
         self.m1, self.m2 = self.layout(FSCC_S01) if self.nact else (0, 0)
+
+    def _d(self, t, n=None):
+        """Device pointer of an amplitude / residual / integral tensor of this
+        context (complex128, or float64 in a real context)."""
+        return _dev_ptr(t, n, self.dtype)
 
     def _sizes(self, sector):
         return (self.n1, self.n2) if sector == FSCC_S00 else (self.m1, self.m2)
@@ -211,7 +222,7 @@ class Context:
 
     def set_integrals(self, cls, dev_blocks):
         k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)
-        self._check(lib().fscc_set_integrals(self._h, k, _dev_ptr(dev_blocks), dev_blocks.numel()))
+        self._check(lib().fscc_set_integrals(self._h, k, self._d(dev_blocks), dev_blocks.numel()))
 
     def layout(self, sector=FSCC_S00):
         a, b = ctypes.c_size_t(), ctypes.c_size_t()
@@ -220,18 +231,18 @@ class Context:
 
     def build_residual(self, t1, t2, r1, r2, sector=FSCC_S00):
         a, b = self._sizes(sector)
-        self._check(lib().fscc_build_residual(self._h, sector, _dev_ptr(t1, a), _dev_ptr(t2, b),
-                                              _dev_ptr(r1, a), _dev_ptr(r2, b)))
+        self._check(lib().fscc_build_residual(self._h, sector, self._d(t1, a), self._d(t2, b),
+                                              self._d(r1, a), self._d(r2, b)))
 
     def update_amplitudes(self, t1, t2, r1, r2, sector=FSCC_S00):
         a, b = self._sizes(sector)
         m = ctypes.c_double()
-        self._check(lib().fscc_update_amplitudes(self._h, sector, _dev_ptr(t1, a), _dev_ptr(t2, b),
-                                                 _dev_ptr(r1, a), _dev_ptr(r2, b), ctypes.byref(m)))
+        self._check(lib().fscc_update_amplitudes(self._h, sector, self._d(t1, a), self._d(t2, b),
+                                                 self._d(r1, a), self._d(r2, b), ctypes.byref(m)))
         return m.value
 
     def prepare_sector(self, t1, t2, sector=FSCC_S01):
-        self._check(lib().fscc_prepare_sector(self._h, sector, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2)))
+        self._check(lib().fscc_prepare_sector(self._h, sector, self._d(t1, self.n1), self._d(t2, self.n2)))
 
     def precondition(self, mode=1, floor=0.1, sector=FSCC_S01):
         self._check(lib().fscc_precondition(self._h, sector, int(mode), float(floor)))
@@ -240,13 +251,13 @@ class Context:
         """H_eff[y][x] (numpy complex, nact x nact, rows/columns in the order of the active list)."""
         import numpy as np
         out = np.zeros((self.nact, self.nact), np.complex128)
-        self._check(lib().fscc_heff(self._h, _dev_ptr(s1, self.m1), _dev_ptr(s2, self.m2),
+        self._check(lib().fscc_heff(self._h, self._d(s1, self.m1), self._d(s2, self.m2),
                                     out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def energy(self, t1, t2):
         er, ei = ctypes.c_double(), ctypes.c_double()
-        self._check(lib().fscc_energy(self._h, _dev_ptr(t1, self.n1), _dev_ptr(t2, self.n2),
+        self._check(lib().fscc_energy(self._h, self._d(t1, self.n1), self._d(t2, self.n2),
                                       ctypes.byref(er), ctypes.byref(ei)))
         return complex(er.value, ei.value)
 
@@ -254,7 +265,7 @@ class Context:
         self._check(lib().fscc_diis_reset(self._h, sector, int(ndiis)))
 
     def ladder(self, tau, out):
-        self._check(lib().fscc_ladder(self._h, _dev_ptr(tau, self.n2), _dev_ptr(out, self.n2)))
+        self._check(lib().fscc_ladder(self._h, self._d(tau, self.n2), self._d(out, self.n2)))
 
     def work(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -440,6 +451,19 @@ def zgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=Fals
         raise FsccError(r, "fscc_zgemm failed")
 
 
+def dgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, alpha=1.0, beta=0, cfg=-1, bk=16, allow_split=True,
+          stream=None):
+    """One real GEMM through the library's real-arithmetic kernels (fscc_dgemm)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    r = lib().fscc_dgemm(int(cfg), int(bk), int(tA), int(tB), int(M), int(N), int(K),
+                         _dev_ptr(A, dtype=torch.float64), int(lda), _dev_ptr(B, dtype=torch.float64), int(ldb),
+                         _dev_ptr(C, dtype=torch.float64), int(ldc), float(alpha), int(beta), int(allow_split),
+                         ctypes.c_void_p(st.cuda_stream))
+    if r != 0:
+        raise FsccError(r, "fscc_dgemm failed")
+
+
 def zgemm_split(A, B, C, M, N, K, lda, ldb, ldc, precision="split_bf16", cfg=0, tA=False, tB=False, cA=False,
                 cB=False, alpha=1.0, beta=0, stream=None):
     """One complex GEMM through the split-precision kernel (fscc_zgemm_split)."""
@@ -469,7 +493,10 @@ class _ContextView(Context):
     """Introspection view (profile, op times, autotune, GEMM configs) of a batch's executor."""
 
     def __init__(self, handle):
+        import torch
         self._h = handle
+        self.real = False
+        self.dtype = torch.complex128
 
     def destroy(self):
         self._h = None

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfscc.so")
-SOURCES = ["fscc_api.hip", "batch_api.hip", "kernels.hip", "kernels_split.hip", "mlp.hip", "plan_ccsd.cpp"]
+SOURCES = ["fscc_api.hip", "batch_api.hip", "kernels.hip", "kernels_real.hip", "kernels_split.hip", "mlp.hip",
+           "plan_ccsd.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

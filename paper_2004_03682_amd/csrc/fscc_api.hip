@@ -22,8 +22,9 @@ namespace rt {
 // row tile) at HBM speed.  fscc_autotune() replaces it by measurement.
 // Shape limits of the vector-ALU forms (the MFMA tiles and the skinny form
 // take any shape).
-bool cfg_ok(const Op& o, int cfg) {
+bool cfg_ok(const Op& o, int cfg, bool real) {
     if (cfg < 0 || cfg >= ZCFG_N) return false;
+    if (real && cfg == ZCFG_SKINNY) return false;   // no real form of the skinny kernel
     if (cfg == ZCFG_TALL) {
         if (o.tA) return false;
         for (auto& p : o.probs)
@@ -71,11 +72,11 @@ double cfg_cost(const Op& o, int cfg) {
     return std::max(fl * eff[cfg] / 60e12, by / 5e12);
 }
 
-int pick_cfg(const Op& o) {
+int pick_cfg(const Op& o, bool real) {
     int best = ZCFG_64x64;
     double bc = cfg_cost(o, best);
     for (int c = 0; c < ZCFG_N; ++c) {
-        if (!cfg_ok(o, c)) continue;
+        if (!cfg_ok(o, c, real)) continue;
         double x = cfg_cost(o, c);
         if (x < bc * 0.95) {
             best = c;
@@ -299,7 +300,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
         g.maxMN = maxMN;
         g.reds = (ZRed*)c->dalloc(rd.size() * sizeof(ZRed));
         hip_check(hipMemcpy(g.reds, rd.data(), rd.size() * sizeof(ZRed), hipMemcpyHostToDevice), "reds");
-        g.work = (double2*)c->dalloc((size_t)std::max<long long>(1, woff) * sizeof(double2));
+        g.work = (double2*)c->dalloc((size_t)std::max<long long>(1, woff) * c->esz());
     }
 }
 
@@ -310,7 +311,7 @@ void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
     L.ms.assign(ops.size(), 0.0);
     L.calls.assign(ops.size(), 0);
     for (size_t k = 0; k < ops.size(); ++k)
-        if (ops[k].kind == OP_GEMM) plan_gemm(c, ops[k], L.g[k], pick_cfg(ops[k]), 16, true);
+        if (ops[k].kind == OP_GEMM) plan_gemm(c, ops[k], L.g[k], pick_cfg(ops[k], c->real), 16, true);
 }
 
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2) {
@@ -319,8 +320,8 @@ void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2) 
     d.b_D1 = bD1;
     d.b_D2 = bD2;
     int64_t n = std::max<int64_t>(1, n1 + n2);
-    d.ht = (double2*)c->dalloc((size_t)kMaxDiis * n * sizeof(double2));
-    d.he = (double2*)c->dalloc((size_t)kMaxDiis * n * sizeof(double2));
+    d.ht = (double2*)c->dalloc((size_t)kMaxDiis * n * c->esz());   // doubles in a real context
+    d.he = (double2*)c->dalloc((size_t)kMaxDiis * n * c->esz());
     d.dB = (double*)c->dalloc(kMaxDiis * kMaxDiis * sizeof(double));
 }
 
@@ -356,7 +357,7 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     for (size_t k = 0; k < P.bufs.size(); ++k) {
         const BufDesc& b = P.bufs[k];
         if (caller_buffer(b.kind)) continue;
-        size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : sizeof(double2));
+        size_t bytes = (size_t)b.n * (b.kind == BUF_REAL ? sizeof(double) : c->esz());
         c->dbuf[k] = c->dalloc(bytes);
     }
     auto up_real = [&](int b, const std::vector<double>& v) {
@@ -413,9 +414,11 @@ const char* fscc_last_error(const fscc_ctx* ctx) { return ctx ? ctx->err.c_str()
 fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_stream, fscc_ctx** out) {
     if (!sys || !out) return FSCC_EINVAL;
     *out = nullptr;
-    if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16) return FSCC_EINVAL;
+    if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16 && prec != FSCC_REAL_FP64)
+        return FSCC_EINVAL;
     if (sys->nocc < 0 || sys->nvirt < 0 || sys->nirrep < 1 || !sys->irrep || !sys->eps) return FSCC_EINVAL;
     if (sys->nact < 0 || (sys->nact > 0 && !sys->active)) return FSCC_EINVAL;
+    if (prec == FSCC_REAL_FP64 && sys->nact > 0) return FSCC_EINVAL;   // (0h,0p) only in real arithmetic
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
     if (!c) return FSCC_ENOMEM;
     fscc_status s = guarded(c, [&]() -> fscc_status {
@@ -434,8 +437,9 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
             if (!std::isfinite(S.eps[p])) throw std::invalid_argument("non-finite orbital energy");
         }
         build_plan_ccsd(S, c->plan);
+        c->real = prec == FSCC_REAL_FP64;
         ctx_allocate(c, true);
-        apply_precision(c, prec);
+        apply_precision(c, c->real ? FSCC_FP64 : prec);
         return FSCC_OK;
     });
     if (s != FSCC_OK) {
@@ -489,9 +493,14 @@ fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* 
                           "pack map upload");
                 GatherMaps gm{};
                 gm.a[0] = dm;
-                hip_check(launch_gather(ctx->B(sg.dst), (const double2*)dev_blocks, nullptr, gm, 1, cnt, 1.0, 0.0, 0,
-                                        sg.conj ? 1 : 0, ctx->st),
-                          "integral pack");
+                if (ctx->real)
+                    hip_check(launch_dgather(ctx->D(sg.dst), (const double*)dev_blocks, nullptr, gm, 1, cnt, 1.0, 0,
+                                             ctx->st),
+                              "integral pack");
+                else
+                    hip_check(launch_gather(ctx->B(sg.dst), (const double2*)dev_blocks, nullptr, gm, 1, cnt, 1.0, 0.0,
+                                            0, sg.conj ? 1 : 0, ctx->st),
+                              "integral pack");
                 hip_check(hipStreamSynchronize(ctx->st), "pack sync");
                 (void)hipFree(dm);
             }
@@ -662,6 +671,37 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
         double2* ht = D.ht + (size_t)slot * n;
         double2* he = D.he + (size_t)slot * n;
         int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
+        if (ctx->real) {
+            // the same sequence on doubles (history slots hold n doubles)
+            double* dht = (double*)D.ht + (size_t)slot * n;
+            double* dhe = (double*)D.he + (size_t)slot * n;
+            if (n1 > 0)
+                hip_check(launch_djacobi((const double*)t1, (const double*)r1, (const double*)ctx->dbuf[D.b_D1], dht,
+                                         dhe, n1, ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
+                          "jacobi 1");
+            if (n2 > 0)
+                hip_check(launch_djacobi((const double*)t2, (const double*)r2, (const double*)ctx->dbuf[D.b_D2],
+                                         dht + n1, dhe + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift, D.dyn_S,
+                                         D.dyn_n),
+                          "jacobi 2");
+            int m = (int)ord.size();
+            std::vector<const double*> ev(m);
+            for (int j = 0; j < m; ++j) ev[j] = (const double*)D.he + (size_t)ord[j] * n;
+            int nbd = reduce_blocks(n);
+            hip_check(launch_ddots(ev.data(), m, dhe, n, ctx->part, nbd, ctx->st), "diis dots");
+            hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st),
+                      "order");
+            hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot,
+                                         ctx->dorder, ctx->coef, ctx->scal, ctx->st),
+                      "diis solve");
+            std::vector<const double*> xs(kMaxDiis);
+            for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n;
+            if (n1 > 0) hip_check(launch_dlincomb((double*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb 1");
+            if (n2 > 0) {
+                for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n + n1;
+                hip_check(launch_dlincomb((double*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
+            }
+        } else {
         if (n1 > 0)
             hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[D.b_D1], ht, he, n1,
                                     ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
@@ -686,6 +726,7 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
             for (int s = 0; s < kMaxDiis; ++s) xs[s] = D.ht + (size_t)s * n + n1;
             hip_check(launch_lincomb((double2*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
         }
+        }
         hip_check(hipMemcpyAsync(ctx->hscal, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "scal");
         hip_check(hipStreamSynchronize(ctx->st), "update sync");
         int dropped = (int)ctx->hscal[1];
@@ -708,7 +749,12 @@ fscc_status fscc_energy(fscc_ctx* ctx, const fscc_c128* t1, const fscc_c128* t2,
         // tau = t2 + t1 t1 (the first two operations of the plan)
         for (size_t k = 0; k < 2; ++k) ctx->run_op(P.ops[k], &ctx->L00.g[k]);
         int nb = reduce_blocks(ctx->n2());
-        hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st), "energy");
+        if (ctx->real)
+            hip_check(launch_ddot(ctx->D(P.b_oovv), ctx->D(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st),
+                      "energy");
+        else
+            hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st),
+                      "energy");
         hip_check(hipMemcpyAsync(ctx->hscal + 4, ctx->eout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "e d2h");
         hip_check(hipStreamSynchronize(ctx->st), "energy sync");
         *e_re = ctx->hscal[4];
@@ -809,14 +855,14 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                     MixedDev* keep = L->g[k].mx;
                     L->g[k].mx = nullptr;
                     free_gemm(L->g[k]);
-                    plan_gemm(ctx, o, L->g[k], pick_cfg(o), 16, true);
+                    plan_gemm(ctx, o, L->g[k], pick_cfg(o, ctx->real), 16, true);
                     L->g[k].mx = keep;
                 }
             return FSCC_OK;
         }
         int64_t nio = 2 * std::max<int64_t>(1, ctx->n1()) + 2 * std::max<int64_t>(1, ctx->n2());
         if (P.has01) nio += 2 * std::max<int64_t>(1, P.L_S1.total) + 2 * std::max<int64_t>(1, P.L_S2.total);
-        double2* tmp = (double2*)ctx->dalloc((size_t)nio * sizeof(double2));
+        double2* tmp = (double2*)ctx->dalloc((size_t)nio * sizeof(double2));   // large enough for either element type
         hip_check(hipMemsetAsync(tmp, 0, (size_t)nio * sizeof(double2), ctx->st), "memset");
         {
             double2* q = tmp;
@@ -868,7 +914,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                         for (int sp = 1; sp >= 0; --sp) {
                             if ((cfg == ZCFG_SKINNY || cfg == ZCFG_TALL || cfg == ZCFG_RED) && bk != 16) continue;
                             if ((cfg == ZCFG_TALL && sp == 1) || (cfg == ZCFG_RED && sp == 0)) continue;
-                            if (!cfg_ok(o, cfg)) continue;
+                            if (!cfg_ok(o, cfg, ctx->real)) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
                             if (sp == 0 && !cand.split) {
@@ -1003,6 +1049,7 @@ fscc_status fscc_set_precision(fscc_ctx* ctx, fscc_precision prec) {
     if (!ctx) return FSCC_EINVAL;
     if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16)
         return fail(ctx, FSCC_EINVAL, "unknown precision");
+    if (ctx->real && prec != FSCC_FP64) return fail(ctx, FSCC_EINVAL, "a real context computes in FP64 only");
     return guarded(ctx, [&]() -> fscc_status {
         apply_precision(ctx, prec);
         return FSCC_OK;
@@ -1011,7 +1058,7 @@ fscc_status fscc_set_precision(fscc_ctx* ctx, fscc_precision prec) {
 
 fscc_status fscc_get_precision(const fscc_ctx* ctx, int* prec) {
     if (!ctx || !prec) return FSCC_EINVAL;
-    *prec = ctx->prec;
+    *prec = ctx->real ? FSCC_REAL_FP64 : ctx->prec;
     return FSCC_OK;
 }
 
@@ -1118,4 +1165,44 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
     return s;
 }
 
+
+fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, const double* A, int lda, const double* B,
+                       int ldb, double* C, int ldc, double alpha, int beta, int allow_split, void* hip_stream) {
+    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
+    if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
+    if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
+    fscc_ctx* c = new (std::nothrow) fscc_ctx();
+    if (!c) return FSCC_ENOMEM;
+    c->st = (hipStream_t)hip_stream;
+    c->real = true;
+    fscc_status s = guarded(c, [&]() -> fscc_status {
+        Op o;
+        o.kind = OP_GEMM;
+        o.name = "dgemm";
+        o.tA = tA != 0;
+        o.tB = tB != 0;
+        o.alpha = cplx(alpha, 0.0);
+        o.beta = beta ? 1 : 0;
+        if (M > 0 && N > 0) o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
+        if (cfg >= 0 && !cfg_ok(o, cfg, true)) return FSCC_EINVAL;
+        GemmDev g;
+        plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o, true) : cfg, bk, allow_split != 0);
+        hipError_t e;
+        if (!g.split) {
+            e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, A, B, C, g.probs, g.tiles, g.ntiles, alpha, o.beta, c->st, 0,
+                             nullptr, g.maxM);
+        } else {
+            e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, A, B, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0, 0, c->st,
+                             0, nullptr, g.maxM);
+            if (e == hipSuccess)
+                e = launch_dsplitk_reduce(C, (const double*)g.work, g.reds, g.nred, g.maxMN, alpha, o.beta, c->st);
+        }
+        hip_check(e, "dgemm");
+        hip_check(hipStreamSynchronize(c->st), "dgemm sync");
+        free_gemm(g);
+        return FSCC_OK;
+    });
+    delete c;
+    return s;
+}
 }  // extern "C"

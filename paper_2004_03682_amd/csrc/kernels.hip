@@ -34,6 +34,7 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
     constexpr int PAD = 1;
     constexpr int FM = BM / (16 * WM);
     constexpr int FN = BN / (16 * WN);
+    constexpr int KS_UNROLL = FM * FN >= 4 ? 1 : BK / 4;   // 4-deep steps unrolled per slice
     static_assert(WM * WN == 4, "four waves");
     static_assert(FM >= 1 && FN >= 1, "tile too small");
     __shared__ double As[2][BK][BM + PAD];
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
         if (k0 + BK < K) load_slice(k0 + BK);
         // large fragment grids: one 4-deep step at a time keeps the register
         // count (and so the occupancy) of the 64x64 tile in check
-#pragma unroll(FM * FN >= 4 ? 1 : BK / 4)
+#pragma unroll KS_UNROLL
         for (int ks = 0; ks < BK / 4; ++ks) {
             if (!wave_live) break;
             double a_r[FM], a_i[FM], a_n[FM], b_r[FN], b_i[FN];

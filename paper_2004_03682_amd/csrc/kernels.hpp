@@ -130,6 +130,31 @@ hipError_t launch_zero(double2* dst, long long n, hipStream_t st);
 
 int reduce_blocks(long long n);
 
+// ---- real arithmetic (kernels_real.hip): the same operations on doubles for
+// double groups with real integrals and amplitudes; alpha is real, no
+// conjugation, plain (unsegmented) launches.  launch_dgemm takes the MFMA
+// tile shapes and ZCFG_TALL / ZCFG_RED (not ZCFG_SKINNY).
+hipError_t launch_dgemm(int cfg, int bk, bool tA, bool tB, const double* A, const double* B, double* C,
+                        const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
+                        int role = 0, const int* active = nullptr, int max_m = 0);
+hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, double alpha,
+                                 int beta, hipStream_t st);
+hipError_t launch_dgather(double* dst, const double* src, const double* src2, GatherMaps maps, int nt, long long n,
+                          double alpha, int beta, hipStream_t st);
+hipError_t launch_daxpby(double* dst, const double* src, long long n, double alpha, int beta, hipStream_t st);
+hipError_t launch_ddiag(double* dst, const double* d, const double* src, long long n, hipStream_t st);
+hipError_t launch_dmul(double* dst, const double* d, long long n, hipStream_t st);
+hipError_t launch_djacobi(const double* t, const double* r, const double* D, double* hist_t, double* hist_e,
+                          long long n, double* part_max, int nblk, hipStream_t st, double shift = 0.0,
+                          double dyn_S = 0.0, int dyn_n = 0);
+hipError_t launch_ddots(const double* const* e, int m, const double* enew, long long n, double* part, int nblk,
+                        hipStream_t st);
+hipError_t launch_dlincomb(double* out, const double* const* xs, const double* coef, int m, long long n,
+                           hipStream_t st);
+// out[0] = sum x*y, out[1] = 0
+hipError_t launch_ddot(const double* x, const double* y, long long n, double* part, int nblk, double* out,
+                       hipStream_t st);
+
 // ---- batched update (many independent systems in concatenated vectors)
 // segment of system s: T1 part [off1, off1+n1), T2 part [off2, off2+n2);
 // history: nd slots of n1+n2 elements at hoff

@@ -123,6 +123,11 @@ struct fscc_ctx {
     double2* rs_tmp = nullptr; // residual scratch for fscc_heff
     bool prof = false;
     int prof_sel = -1;   // with prof: time only this operation (-1: all)
+    // real arithmetic (real double groups): every amplitude, integral and
+    // intermediate buffer holds doubles instead of complex doubles
+    bool real = false;
+    size_t esz() const { return real ? sizeof(double) : sizeof(double2); }
+    double* D(int id) const { return (double*)dbuf[id]; }
     int prec = FSCC_FP64;
     const int* d_active = nullptr;   // batched plans: per-system flags, GEMM tiles of 0-systems are skipped
     std::string err;
@@ -193,11 +198,53 @@ struct fscc_ctx {
         return sb;
     }
 
+    // the real-arithmetic form of run_op (real alpha, no conjugation)
+    hipError_t run_op_real(const Op& o, const GemmDev* gd, int beta_override, const double* A_override,
+                           double* C_override) {
+        switch (o.kind) {
+            case OP_AXPBY:
+                return launch_daxpby(D(o.dst), D(o.src), o.n, o.alpha.real(), o.beta, st);
+            case OP_DIAG:
+                return launch_ddiag(D(o.dst), (const double*)dbuf[o.src2], D(o.src), o.n, st);
+            case OP_MUL:
+                return launch_dmul(D(o.dst), (const double*)dbuf[o.src2], o.n, st);
+            case OP_GATHER: {
+                GatherMaps gm;
+                for (int t = 0; t < 4; ++t) {
+                    gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
+                    gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
+                }
+                return launch_dgather(D(o.dst), D(o.src), o.src2 >= 0 ? D(o.src2) : nullptr, gm, (int)o.mapsA.size(),
+                                      o.n, o.alpha.real(), o.beta, st);
+            }
+            case OP_GEMM: {
+                const GemmDev& g = *gd;
+                const int beta = beta_override >= 0 ? beta_override : o.beta;
+                const double* Ap = A_override ? A_override : D(o.src);
+                double* Cp = C_override ? C_override : D(o.dst);
+                if (!g.split)
+                    return launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, D(o.src2), Cp, g.probs, g.tiles, g.ntiles,
+                                        o.alpha.real(), beta, st, g.role, nullptr, g.maxM);
+                hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, D(o.src2), (double*)g.work, g.probs, g.tiles,
+                                            g.ntiles, 1.0, 0, st, g.role, nullptr, g.maxM);
+                if (e == hipSuccess)
+                    e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), beta,
+                                              st);
+                return e;
+            }
+        }
+        return hipSuccess;
+    }
+
     // seg_flags (batched plans only): per-system flags used instead of d_active
     // for the elementwise and gather launches of this call
     void run_op(const Op& o, const GemmDev* gd, int beta_override = -1, const double2* A_override = nullptr,
                 double2* C_override = nullptr, const int* seg_flags = nullptr) {
         hipError_t e = hipSuccess;
+        if (real) {
+            hip_check(run_op_real(o, gd, beta_override, (const double*)A_override, (double*)C_override), o.name.c_str());
+            return;
+        }
         const SegBlocks sb = seg_of(o.dst, seg_flags);
         switch (o.kind) {
             case OP_AXPBY:
@@ -321,9 +368,9 @@ fscc_status guarded(fscc_ctx* c, F f) {
     }
 }
 
-bool cfg_ok(const Op& o, int cfg);
+bool cfg_ok(const Op& o, int cfg, bool real = false);
 double cfg_cost(const Op& o, int cfg);
-int pick_cfg(const Op& o);
+int pick_cfg(const Op& o, bool real = false);
 std::vector<ZTile> xcd_order(const std::vector<ZTile>& logical);
 void free_gemm(GemmDev& g);
 bool mixed_eligible(const Op& o);
