@@ -202,6 +202,68 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
     return out
 
 
+def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log):
+    """The cfg2 shape as a real double group (the same seed's integrals made
+    real): the real-arithmetic context's s/iteration, its GEMM rate and
+    iterations to convergence, against the complex iteration."""
+    s = fsgen.make_system(cfg["nocc"], cfg["nvirt"], cfg["nirrep"], cfg["sigma"], cfg["seed"], real=True)
+    ctx = F.Context.from_system(s, precision="real_fp64")
+    for C in fsgen.CLASSES:
+        buf, _ = fsgen.class_buffer(s, C)
+        d = torch.from_numpy(fsgen.real_buffer(buf)).cuda()
+        ctx.set_integrals(C, d)
+        del d, buf
+    ctx.autotune(1)
+    t1 = torch.zeros(ctx.n1, dtype=torch.float64, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.float64, device="cuda")
+    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+    ctx.diis_reset(6)
+    ctx.profile(True)
+    for _ in range(max(1, args.warmup)):
+        ctx.build_residual(t1, t2, r1, r2)
+        ctx.update_amplitudes(t1, t2, r1, r2)
+        ctx.energy(t1, t2)
+    ops = ctx.op_times()
+    ctx.profile(False)
+    nw = max(1, args.warmup)
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.build_residual(t1, t2, r1, r2)
+        ctx.update_amplitudes(t1, t2, r1, r2)
+        ctx.energy(t1, t2)
+    torch.cuda.synchronize()
+    per_it = (time.perf_counter() - st) / args.steps
+    work = ctx.work()
+    gemm_ms = sum(o["ms"] for o in ops if o["flops"] > 0) / nw
+    real_flops = work["gemm_flops"] / 4.0          # the plan counts complex flops (8 per complex MAC)
+    lad = next(o for o in ops if o["name"] == "pp-ladder")
+    lad_ms = lad["ms"] / max(1, lad["calls"])
+    t1.zero_()
+    t2.zero_()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    g = F.solve(ctx, t1, t2, tol=1e-10, maxit=200)
+    solve_s = time.perf_counter() - ts
+    E = g["E"]
+    k8 = next((h["iter"] for k, h in enumerate(g["history"]) if all(abs(x["E"] - E) < 1e-8 for x in g["history"][k:])),
+              None)
+    rec = {"s_per_iteration": round(per_it, 6), "complex_s_per_iteration": round(complex_s_per_iter, 6),
+           "speedup_vs_complex": round(complex_s_per_iter / per_it, 3),
+           "gemm_tflops": round(real_flops / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms > 0 else None,
+           "real_gemm_flops_per_iteration": real_flops,
+           "pp_ladder_ms": round(lad_ms, 4),
+           "pp_ladder_tflops": round(lad["flops"] / 4.0 / (lad_ms * 1e-3) / 1e12, 3),
+           "converged": g["converged"], "iterations": g["iters"], "iterations_to_1e-8": k8,
+           "seconds_to_converged": round(solve_s, 4), "energy": E.real,
+           "workload": "cfg2 shape, real integrals (sqrt(2) Re of seed 1002's), real-arithmetic context"}
+    log(f"real: {per_it * 1e3:.3f} ms/iteration ({complex_s_per_iter / per_it:.2f}x the complex iteration), "
+        f"ladder {lad_ms:.3f} ms, converged {g['converged']} in {g['iters']} iterations ({solve_s:.3f}s)")
+    ctx.destroy()
+    torch.cuda.empty_cache()
+    return rec
+
+
 BATCH_SOLVER = dict(ndiis=8, shift=1.0)   # DIIS(8) + 1 Eh level shift for the batched workload (same fixed point)
 
 
@@ -365,6 +427,7 @@ def main():
     ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) sector")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
+    ap.add_argument("--no-real", action="store_true", help="skip the real-arithmetic (real double group) study")
     ap.add_argument("--no-sequential", action="store_true", help="skip the one-by-one baseline of the batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start on the batch")
     ap.add_argument("--converge", action="store_true",
@@ -570,6 +633,8 @@ def main():
     ctx.destroy()
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
+    if not args.no_real:
+        result["real_arithmetic"] = real_study(F, torch, fsgen, cfg, s_per_iter, args, log)
     if not args.no_batch:
         result["batch"] = batch_study(F, torch, fsgen, args, log)
     if not args.no_cpu:
