@@ -246,6 +246,22 @@ fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, con
  * from the next fscc_update_amplitudes. */
 fscc_status fscc_level_shift(fscc_ctx *ctx, fscc_sector sector, double shift);
 
+/* Out-of-core <ab||cd> (the paper's block-contraction loop that loads each
+ * integral block from disk while the contraction runs, Fig. 4; for systems
+ * whose packed VVVV does not fit the GPU): with staging_bytes > 0 the packed
+ * VVVV integrals move to pinned host memory (their device copy is freed) and
+ * every GEMM that reads them (the particle-particle ladders of both sectors)
+ * streams them through two device staging buffers of staging_bytes / 2 each:
+ * a copy stream brings one chunk of integral rows while the matrix cores
+ * work on the previous one.  Problems are cut along the ladder's ab index to
+ * fit a staging buffer; results equal the in-memory ones up to summation
+ * order.  staging_bytes = 0 moves VVVV back to device memory.  Needs all
+ * integrals set and FP64 precision; afterwards fscc_autotune and split
+ * precision are refused (FSCC_ESTATE) until VVVV is back.  FSCC_EINVAL if a
+ * staging buffer cannot hold one integral row (nvv pairs of the largest
+ * block). */
+fscc_status fscc_vvvv_out_of_core(fscc_ctx *ctx, size_t staging_bytes);
+
 /* Dynamic denominator shifts against intruder states (the FS-RCC method's
  * shifting of ill-defined, nearly zero or positive, energy denominators,
  * followed by extrapolation to zero shift).  With S < 0 (Eh) and integer

@@ -68,6 +68,7 @@ def lib():
             "fscc_set_precision": ([vp, ip], ip),
             "fscc_profile_select": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
+            "fscc_vvvv_out_of_core": ([vp, sz], ip),
             "fscc_dgemm": ([ip, ip, ip, ip, ip, ip, ip, vp, ip, vp, ip, vp, ip, ctypes.c_double, ip, ip, vp], ip),
             "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
@@ -190,6 +191,12 @@ class Context:
     def level_shift(self, shift, sector=FSCC_S00):
         """Jacobi step R / (D - shift) for the sector (damping; same fixed point)."""
         self._check(lib().fscc_level_shift(self._h, sector, float(shift)))
+
+    def vvvv_out_of_core(self, staging_bytes):
+        """Move the packed VVVV integrals to pinned host memory and stream them
+        through two device staging buffers (staging_bytes in total); 0 moves
+        them back to device memory."""
+        self._check(lib().fscc_vvvv_out_of_core(self._h, int(staging_bytes)))
 
     def dynamic_shift(self, S, n=3, sector=FSCC_S01):
         """Dynamic denominator shifts Delta = S (S/(min(D,0)+S))^n of the sector

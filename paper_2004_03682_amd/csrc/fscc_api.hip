@@ -407,6 +407,61 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
 }  // namespace fscc
 
 
+// Chunk lists of the GEMMs that read buffer b as a transposed B operand (rows
+// of K contiguous elements): problems are cut along N so that every piece's
+// rows span at most `half` elements, and consecutive pieces are packed into
+// chunks whose rows lie in one window of `half` elements.
+static std::vector<std::vector<StreamChunk>> stream_plan(fscc_ctx* c, OpList& L, int b, long long half) {
+    std::vector<std::vector<StreamChunk>> out(L.ops->size());
+    for (size_t k = 0; k < L.ops->size(); ++k) {
+        const Op& o = (*L.ops)[k];
+        if (o.kind != OP_GEMM || o.src2 != b) continue;
+        std::vector<GemmProblem> pieces;
+        for (const GemmProblem& p : o.probs) {
+            if (p.M <= 0 || p.N <= 0) continue;
+            if (p.K <= 0) {
+                GemmProblem q = p;
+                pieces.push_back(q);
+                continue;
+            }
+            if ((long long)p.ldb > half) throw std::invalid_argument("staging buffer smaller than one operand row");
+            const int rows = (int)std::max<long long>(1, half / p.ldb);
+            for (int n0 = 0; n0 < p.N; n0 += rows) {
+                GemmProblem q = p;
+                q.N = std::min(rows, p.N - n0);
+                q.b_off = p.b_off + (int64_t)n0 * p.ldb;
+                q.c_off = p.c_off + n0;
+                pieces.push_back(q);
+            }
+        }
+        std::stable_sort(pieces.begin(), pieces.end(),
+                         [](const GemmProblem& a, const GemmProblem& b2) { return a.b_off < b2.b_off; });
+        const GemmDev& g0 = L.g[k];
+        std::vector<std::vector<GemmProblem>> groups;
+        std::vector<std::pair<long long, long long>> span;
+        for (const GemmProblem& q : pieces) {
+            const long long lo = q.b_off, hi = q.K > 0 ? q.b_off + (long long)(q.N - 1) * q.ldb + q.K : q.b_off;
+            if (groups.empty() || hi - span.back().first > half) {
+                groups.push_back({});
+                span.push_back({lo, hi});
+            }
+            groups.back().push_back(q);
+            span.back().second = std::max(span.back().second, hi);
+        }
+        for (size_t j = 0; j < groups.size(); ++j) {
+            Op sub = o;
+            sub.probs = groups[j];
+            StreamChunk ch;
+            ch.lo = span[j].first;
+            ch.hi = span[j].second;
+            plan_gemm(c, sub, ch.g, g0.cfg, g0.bk, true);
+            hip_check(hipEventCreateWithFlags(&ch.copied, hipEventDisableTiming), "event");
+            out[k].push_back(ch);
+        }
+    }
+    return out;
+}
+
 extern "C" {
 
 const char* fscc_last_error(const fscc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -629,7 +684,10 @@ fscc_status fscc_ladder(fscc_ctx* ctx, const fscc_c128* tau, fscc_c128* out) {
         Plan& P = ctx->plan;
         for (size_t k = 0; k < P.ops.size(); ++k)
             if (P.ops[k].name == "pp-ladder") {
-                ctx->run_op(P.ops[k], &ctx->L00.g[k], 0, (const double2*)tau, (double2*)out);
+                if (ctx->sp.buf >= 0 && !ctx->sp.ch00[k].empty())
+                    ctx->run_streamed(P.ops[k], ctx->sp.ch00[k], 0, tau, out);
+                else
+                    ctx->run_op(P.ops[k], &ctx->L00.g[k], 0, (const double2*)tau, (double2*)out);
                 return FSCC_OK;
             }
         throw std::logic_error("no ladder op");
@@ -843,6 +901,7 @@ fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, in
 // context's own buffers and zeroed temporary amplitude buffers are used.
 fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
     if (!ctx) return FSCC_EINVAL;
+    if (ctx->sp.buf >= 0) return fail(ctx, FSCC_ESTATE, "autotune before moving VVVV out of device memory");
     if (level < 0 || level > 2) return fail(ctx, FSCC_EINVAL, "autotune level must be 0, 1 or 2");
     return guarded(ctx, [&]() -> fscc_status {
         Plan& P = ctx->plan;
@@ -1037,6 +1096,63 @@ fscc_status fscc_pade(int npts, const double* x, const fscc_c128* y, int L, int 
     return FSCC_OK;
 }
 
+fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
+    if (!ctx) return FSCC_EINVAL;
+    if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
+    return guarded(ctx, [&]() -> fscc_status {
+        Plan& P = ctx->plan;
+        int b = -1;
+        for (auto& o : P.ops)
+            if (o.name == "pp-ladder") b = o.src2;
+        if (b < 0) throw std::logic_error("no ladder op");
+        const size_t es = ctx->esz();
+        const size_t bytes = (size_t)P.bufs[b].n * es;
+        if (staging_bytes == 0) {   // back to device memory
+            if (ctx->sp.buf < 0) return FSCC_OK;
+            hip_check(hipStreamSynchronize(ctx->st), "sync");
+            hip_check(hipStreamSynchronize(ctx->sp.cs), "sync");
+            void* d = ctx->dalloc(bytes);
+            hip_check(hipMemcpy(d, ctx->sp.host, bytes, hipMemcpyHostToDevice), "operand to device");
+            ctx->dbuf[b] = d;
+            ctx->free_stream();
+            return FSCC_OK;
+        }
+        if (ctx->sp.buf >= 0) return fail(ctx, FSCC_ESTATE, "VVVV is already out of device memory");
+        if (ctx->prec != FSCC_FP64) return fail(ctx, FSCC_ESTATE, "out-of-core VVVV needs FP64 precision");
+        // every reader of the buffer must be a GEMM taking it as a transposed B
+        for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01})
+            for (auto& o : *L->ops) {
+                const bool reads = o.src == b || o.dst == b || o.src2 == b;
+                if (reads && !(o.kind == OP_GEMM && o.src2 == b && o.tB && L != &ctx->L01p))
+                    return fail(ctx, FSCC_EINVAL, "operation " + o.name + " cannot stream VVVV");
+            }
+        StreamPlan& sp = ctx->sp;
+        try {
+            sp.half = (long long)(staging_bytes / 2 / es);
+            if (sp.half < 1) throw std::invalid_argument("staging buffer too small");
+            hip_check(hipHostMalloc(&sp.host, std::max<size_t>(bytes, 16), hipHostMallocDefault), "hipHostMalloc");
+            hip_check(hipStreamSynchronize(ctx->st), "sync");
+            if (bytes) hip_check(hipMemcpy(sp.host, ctx->dbuf[b], bytes, hipMemcpyDeviceToHost), "operand to host");
+            sp.bytes = bytes;
+            for (int s = 0; s < 2; ++s) {
+                sp.stage[s] = ctx->dalloc((size_t)sp.half * es);
+                hip_check(hipEventCreateWithFlags(&sp.free_ev[s], hipEventDisableTiming), "event");
+                hip_check(hipEventRecord(sp.free_ev[s], ctx->st), "event");
+            }
+            hip_check(hipStreamCreateWithFlags(&sp.cs, hipStreamNonBlocking), "copy stream");
+            sp.ch00 = stream_plan(ctx, ctx->L00, b, sp.half);
+            sp.ch01 = stream_plan(ctx, ctx->L01, b, sp.half);
+            sp.buf = b;
+        } catch (...) {
+            ctx->free_stream();
+            throw;
+        }
+        (void)hipFree(ctx->dbuf[b]);
+        ctx->dbuf[b] = nullptr;
+        return FSCC_OK;
+    });
+}
+
 fscc_status fscc_level_shift(fscc_ctx* ctx, fscc_sector sector, double shift) {
     if (!ctx) return FSCC_EINVAL;
     if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "level shift applies to the (0h,0p) sector");
@@ -1050,6 +1166,8 @@ fscc_status fscc_set_precision(fscc_ctx* ctx, fscc_precision prec) {
     if (prec != FSCC_FP64 && prec != FSCC_SPLIT_FP32 && prec != FSCC_SPLIT_BF16)
         return fail(ctx, FSCC_EINVAL, "unknown precision");
     if (ctx->real && prec != FSCC_FP64) return fail(ctx, FSCC_EINVAL, "a real context computes in FP64 only");
+    if (ctx->sp.buf >= 0 && prec != FSCC_FP64)
+        return fail(ctx, FSCC_ESTATE, "split precision needs VVVV in device memory");
     return guarded(ctx, [&]() -> fscc_status {
         apply_precision(ctx, prec);
         return FSCC_OK;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -71,6 +72,29 @@ inline void hip_check(hipError_t e, const char* what) {
 constexpr int kMaxDiis = 8;
 
 // one executable op list with its device GEMM lists and timing slots
+// One chunk of a GEMM whose B operand streams from pinned host memory: the
+// problem pieces whose B rows lie in [lo, hi) (elements of the host copy)
+struct StreamChunk {
+    long long lo = 0, hi = 0;
+    GemmDev g;
+    hipEvent_t copied = nullptr;
+};
+
+// Out-of-core operand (the packed <ab||cd> integrals): host copy, two device
+// staging buffers used alternately, a copy stream, and the chunk lists of the
+// GEMMs that read it (indexed like the op list; empty = not streamed).
+struct StreamPlan {
+    int buf = -1;
+    void* host = nullptr;
+    size_t bytes = 0;
+    void* stage[2] = {nullptr, nullptr};
+    long long half = 0;   // elements per staging buffer
+    hipStream_t cs = nullptr;
+    hipEvent_t free_ev[2] = {nullptr, nullptr};
+    int next = 0;         // staging buffer of the next chunk
+    std::vector<std::vector<StreamChunk>> ch00, ch01;
+};
+
 struct OpList {
     std::vector<Op>* ops = nullptr;
     std::vector<GemmDev> g;
@@ -109,6 +133,7 @@ struct fscc_ctx {
     std::vector<void*> dbuf;
     std::vector<uint32_t*> dmap;
     OpList L00, L01p, L01;
+    StreamPlan sp;   // out-of-core VVVV (fscc_vvvv_out_of_core)
     bool have_cls[IC_N] = {false, false, false, false, false, false};
     bool ready01 = false;
     Diis diis[2];
@@ -152,6 +177,33 @@ struct fscc_ctx {
         m = nullptr;
     }
 
+    static void free_gemm_dev(GemmDev& g) {
+        if (g.probs) (void)hipFree(g.probs);
+        if (g.tiles) (void)hipFree(g.tiles);
+        if (g.reds) (void)hipFree(g.reds);
+        if (g.work) (void)hipFree(g.work);
+        g.probs = nullptr;
+        g.tiles = nullptr;
+        g.reds = nullptr;
+        g.work = nullptr;
+    }
+
+    void free_stream() {
+        for (auto* L : {&sp.ch00, &sp.ch01})
+            for (auto& v : *L)
+                for (auto& c : v) {
+                    free_gemm_dev(c.g);
+                    if (c.copied) (void)hipEventDestroy(c.copied);
+                }
+        for (int s = 0; s < 2; ++s) {
+            if (sp.stage[s]) (void)hipFree(sp.stage[s]);
+            if (sp.free_ev[s]) (void)hipEventDestroy(sp.free_ev[s]);
+        }
+        if (sp.cs) (void)hipStreamDestroy(sp.cs);
+        if (sp.host) (void)hipHostFree(sp.host);
+        sp = StreamPlan();
+    }
+
     static void free_list(OpList& L) {
         for (auto& g : L.g) {
             if (g.probs) (void)hipFree(g.probs);
@@ -165,6 +217,8 @@ struct fscc_ctx {
     }
 
     ~fscc_ctx() {
+        if (sp.cs) (void)hipStreamSynchronize(sp.cs);
+        free_stream();
         for (size_t k = 0; k < dbuf.size(); ++k)
             if (!caller_buffer(plan.bufs[k].kind) && dbuf[k]) (void)hipFree(dbuf[k]);
         for (auto* m : dmap)
@@ -307,6 +361,76 @@ struct fscc_ctx {
         return e;
     }
 
+    std::vector<std::vector<StreamChunk>>* stream_chunks(OpList& L) {
+        if (sp.buf < 0) return nullptr;
+        if (&L == &L00) return &sp.ch00;
+        if (&L == &L01) return &sp.ch01;
+        return nullptr;
+    }
+
+    // A GEMM whose B operand is streamed: per chunk, the copy stream brings its
+    // rows into the staging buffer not in use (after the GEMM that last read
+    // it), and the GEMM of the chunk runs on the context's stream once the copy
+    // has landed, so copies and matrix-core work overlap.  B is addressed as
+    // stage - lo, so the problems keep their offsets into the full operand.
+    void run_streamed(const Op& o, std::vector<StreamChunk>& chunks, int beta_override = -1,
+                      const void* A_override = nullptr, void* C_override = nullptr) {
+        const size_t es = esz();
+        int s = sp.next;
+        for (auto& c : chunks) {
+            hip_check(hipStreamWaitEvent(sp.cs, sp.free_ev[s], 0), "stream wait");
+            if (c.hi > c.lo)
+                hip_check(hipMemcpyAsync(sp.stage[s], (const char*)sp.host + (size_t)c.lo * es,
+                                         (size_t)(c.hi - c.lo) * es, hipMemcpyHostToDevice, sp.cs),
+                          "operand stream copy");
+            hip_check(hipEventRecord(c.copied, sp.cs), "event");
+            hip_check(hipStreamWaitEvent(st, c.copied, 0), "stream wait");
+            const void* Bp = (const char*)sp.stage[s] - (ptrdiff_t)((size_t)c.lo * es);
+            if (real) {
+                hip_check(gemm_real(o, c.g, beta_override, (const double*)A_override, (double*)C_override,
+                                    (const double*)Bp),
+                          o.name.c_str());
+            } else {
+                hip_check(gemm_complex(o, c.g, beta_override, (const double2*)A_override, (double2*)C_override,
+                                       (const double2*)Bp),
+                          o.name.c_str());
+            }
+            hip_check(hipEventRecord(sp.free_ev[s], st), "event");
+            s ^= 1;
+        }
+        sp.next = s;
+    }
+
+    hipError_t gemm_complex(const Op& o, const GemmDev& g, int beta_override, const double2* A_override,
+                            double2* C_override, const double2* Bp) {
+        const int beta = beta_override >= 0 ? beta_override : o.beta;
+        const double2* Ap = A_override ? A_override : B(o.src);
+        double2* Cp = C_override ? C_override : B(o.dst);
+        if (!g.split)
+            return launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
+                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM);
+        hipError_t e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
+                                    o.cA, o.cB, st, g.role, nullptr, g.maxM);
+        if (e == hipSuccess)
+            e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(), beta, st);
+        return e;
+    }
+
+    hipError_t gemm_real(const Op& o, const GemmDev& g, int beta_override, const double* A_override,
+                         double* C_override, const double* Bp) {
+        const int beta = beta_override >= 0 ? beta_override : o.beta;
+        const double* Ap = A_override ? A_override : D(o.src);
+        double* Cp = C_override ? C_override : D(o.dst);
+        if (!g.split)
+            return launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(), beta,
+                                st, g.role, nullptr, g.maxM);
+        hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0,
+                                    0, st, g.role, nullptr, g.maxM);
+        if (e == hipSuccess)
+            e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), beta, st);
+        return e;
+    }
+
     // add the elapsed times of operations timed earlier (waits for their end events)
     void collect(OpList& L) {
         for (size_t k = 0; k < L.pend.size(); ++k) {
@@ -330,10 +454,12 @@ struct fscc_ctx {
             L.pend.assign(ops.size(), 0);
         }
         if (timed) collect(L);
+        std::vector<std::vector<StreamChunk>>* sc = stream_chunks(L);
         for (size_t k = 0; k < ops.size(); ++k) {
             const bool tk = timed && (prof_sel < 0 || prof_sel == L.base + (int)k);
             if (tk) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
-            run_op(ops[k], &L.g[k]);
+            if (sc && k < sc->size() && !(*sc)[k].empty()) run_streamed(ops[k], (*sc)[k]);
+            else run_op(ops[k], &L.g[k]);
             if (tk) {
                 hip_check(hipEventRecord(L.ev[2 * k + 1], st), "event");
                 L.pend[k] = 1;
