@@ -202,6 +202,60 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
     return out
 
 
+def out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log, staging=512 << 20):
+    """The cfg2 iteration with the packed VVVV integrals in pinned host memory,
+    streamed through 2 x 256 MB staging buffers: ladder time and whole
+    iteration against the in-memory ones, and the host-to-device copy rate
+    the ladder sustains against a plain pinned copy."""
+    work = ctx.work()
+    vbytes = work["ladder_bytes"]
+    # plain pinned host -> device copy of the same size (reference rate)
+    n = int(vbytes // 16)
+    h = torch.empty(n, dtype=torch.complex128).pin_memory()
+    d = torch.empty(n, dtype=torch.complex128, device="cuda")
+    d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    for _ in range(3):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    copy_gbs = 3 * vbytes / (time.perf_counter() - st) / 1e9
+    del h, d
+    torch.cuda.empty_cache()
+    ctx.vvvv_out_of_core(staging)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+    ctx.diis_reset(6)
+    for _ in range(max(1, args.warmup)):
+        ctx.build_residual(t1, t2, r1, r2)
+        ctx.update_amplitudes(t1, t2, r1, r2)
+        ctx.energy(t1, t2)
+    ctx.profile(True, only="pp-ladder")
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.build_residual(t1, t2, r1, r2)
+        ctx.update_amplitudes(t1, t2, r1, r2)
+        ctx.energy(t1, t2)
+    torch.cuda.synchronize()
+    per_it = (time.perf_counter() - st) / args.steps
+    lad = next(o for o in ctx.op_times() if o["name"] == "pp-ladder")
+    ctx.profile(False)
+    lad_ms = lad["ms"] / max(1, lad["calls"])
+    ctx.vvvv_out_of_core(0)
+    rec = {"staging_bytes": staging, "vvvv_bytes": vbytes, "s_per_iteration": round(per_it, 6),
+           "in_memory_s_per_iteration": round(s_per_iter, 6),
+           "ladder_ms": round(lad_ms, 4), "in_memory_ladder_ms": round(dom["ms"] / dom["calls"], 4),
+           "ladder_stream_gbs": round(vbytes / (lad_ms * 1e-3) / 1e9, 2),
+           "pinned_copy_gbs": round(copy_gbs, 2),
+           "device_bytes_saved": vbytes - staging}
+    log(f"out-of-core VVVV: ladder {lad_ms:.3f} ms ({rec['ladder_stream_gbs']} GB/s streamed; plain pinned copy "
+        f"{copy_gbs:.1f} GB/s), iteration {per_it * 1e3:.3f} ms vs {s_per_iter * 1e3:.3f} ms in memory")
+    del t1, t2, r1, r2
+    return rec
+
+
 def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log):
     """The cfg2 shape as a real double group (the same seed's integrals made
     real): the real-arithmetic context's s/iteration, its GEMM rate and
@@ -428,6 +482,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
     ap.add_argument("--no-real", action="store_true", help="skip the real-arithmetic (real double group) study")
+    ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core VVVV study")
     ap.add_argument("--no-sequential", action="store_true", help="skip the one-by-one baseline of the batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start on the batch")
     ap.add_argument("--converge", action="store_true",
@@ -630,6 +685,8 @@ def main():
             fs["dynamic_shift"] = {"S": S_dyn, "n": n_dyn, "status": f"failed ({e})"}
             log(f"(0h,1p) with dynamic shifts failed: {e}")
         result["fs01"] = fs
+    if not args.no_ooc:
+        result["out_of_core"] = out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log)
     ctx.destroy()
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
