@@ -223,7 +223,8 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
  * C = alpha * op(A) op(B) + beta*C with op = transpose (tA/tB) and/or
  * conjugate (cA/cB); A is M x K (lda) or, if tA, K x M; B is K x N (ldb) or,
  * if tB, N x K; all row-major, device pointers.  cfg = kernel form: MFMA tile
- * shapes 0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64;
+ * shapes 0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64,
+ * 9: 32x64, 10: 64x32;
  * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
  * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256);
  * -1 = cost model.  FSCC_EINVAL if the shape does not fit the form.

@@ -28,7 +28,7 @@ struct ZTile {
 // chunks of at most ZRED_LDS / M.
 enum ZCfg {
     ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_SKINNY, ZCFG_TALL, ZCFG_RED,
-    ZCFG_N
+    ZCFG_32x64, ZCFG_64x32, ZCFG_N
 };
 constexpr int ZSKINNY_BM = 64, ZSKINNY_BN = 32, ZSKINNY_MAX_MN = ZSKINNY_BM * ZSKINNY_BN;
 constexpr int ZTALL_ROWS = 256, ZTALL_MAX_K = 64, ZTALL_MAX_KN = 1024;

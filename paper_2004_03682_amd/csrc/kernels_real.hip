@@ -356,6 +356,8 @@ hipError_t dlaunch_bk(int cfg, bool tA, bool tB, const double* A, const double* 
         case ZCFG_64x16: return dlaunch_cfg<64, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         case ZCFG_16x64: return dlaunch_cfg<16, 64, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         case ZCFG_64x64: return dlaunch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_32x64: return dlaunch_cfg<32, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x32: return dlaunch_cfg<64, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }

@@ -9,7 +9,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-CFGS = range(7)   # 6 = skinny (vector-ALU) form
+CFGS = (0, 1, 2, 3, 4, 5, 6, 9, 10)   # MFMA tiles 0-5, 9 (32x64), 10 (64x32); 6 = skinny (vector ALUs)
 
 
 def _rand(rng, *shape):

@@ -20,7 +20,7 @@ from oracle import ccsd, solver
 
 pytestmark = pytest.mark.gpu
 
-MFMA = (0, 1, 2, 3, 4, 5)
+MFMA = (0, 1, 2, 3, 4, 5, 9, 10)
 TALL, RED, SKINNY = 7, 8, 6
 
 
