@@ -201,3 +201,54 @@ def ea_matrix(fs: FockSpace, t1: np.ndarray, t2: np.ndarray, E_tot: float | comp
     HB = np.array(cols).T
     M = B.conj().T @ HB - E_tot * np.eye(B.shape[1])
     return M, labels
+
+
+# -- (0h,2p) sector ----------------------------------------------------------
+def apply_attach(fs: FockSpace, M: int, r1: np.ndarray, r2: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """R v for R = sum_e r1^e a+_e + 1/2 sum_mef r2_m^ef a+_e a+_f a_m (virtual e, f; occupied m),
+    v in sector M, result in sector M+1."""
+    no, nv = fs.nocc, fs.n - fs.nocc
+    out = np.zeros(comb(fs.n, M + 1), np.complex128)
+    for e in range(nv):
+        if r1[e] != 0:
+            out += r1[e] * (fs.a(M + 1, no + e).T @ v)
+    for m in range(no):
+        w0 = fs.a(M, m) @ v                                   # sector M-1
+        for f in range(nv):
+            w1 = fs.a(M, no + f).T @ w0                       # sector M
+            for e in range(nv):
+                if r2[m, e, f] != 0:
+                    out += 0.5 * r2[m, e, f] * (fs.a(M + 1, no + e).T @ w1)
+    return out
+
+
+def hbar_apply(fs: FockSpace, N: int, t1: np.ndarray, t2: np.ndarray, E_tot, v: np.ndarray) -> np.ndarray:
+    """(exp(-T) H exp(T) - E_tot) v on sector N."""
+    H = fs.hamiltonian(N)
+    T = fs.t_operator(N, t1, t2)
+    u = expm_nilpotent(T, v, 1.0)
+    u = H @ u - E_tot * u
+    return expm_nilpotent(T, u, -1.0)
+
+
+def pp_projection(fs: FockSpace, v: np.ndarray) -> np.ndarray:
+    """c[a, b] = <Phi| a_b a_a |v> (coefficient of a+_a a+_b |Phi>), antisymmetric, v in sector nocc+2."""
+    no, nv = fs.nocc, fs.n - fs.nocc
+    c = np.zeros((nv, nv), np.complex128)
+    for a in range(nv):
+        for b in range(a + 1, nv):
+            x = np.vdot(fs.det(no + 2, [no + a, no + b], []), v)
+            c[a, b], c[b, a] = x, -x
+    return c
+
+
+def dea_state(fs: FockSpace, r1x, r2x, r1y, r2y, s_pp) -> np.ndarray:
+    """R_x R_y |Phi> + sum_{a<b} s^ab a+_a a+_b |Phi> on sector nocc+2."""
+    no, nv = fs.nocc, fs.n - fs.nocc
+    phi = fs.reference(no)
+    v = apply_attach(fs, no + 1, r1x, r2x, apply_attach(fs, no, r1y, r2y, phi))
+    for a in range(nv):
+        for b in range(a + 1, nv):
+            if s_pp[a, b] != 0:
+                v = v + s_pp[a, b] * fs.det(no + 2, [no + a, no + b], [])
+    return v
