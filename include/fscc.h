@@ -101,7 +101,7 @@ typedef enum {
  * (0h,0p) sector only (nact must be 0), no split precision. */
 typedef enum { FSCC_FP64 = 0, FSCC_SPLIT_FP32 = 1, FSCC_SPLIT_BF16 = 2, FSCC_REAL_FP64 = 3 } fscc_precision;
 
-typedef enum { FSCC_S00 = 0, FSCC_S01 = 1 } fscc_sector; /* (0h,0p), (0h,1p) */
+typedef enum { FSCC_S00 = 0, FSCC_S01 = 1, FSCC_S02 = 2 } fscc_sector; /* (0h,0p), (0h,1p), (0h,2p) */
 
 typedef enum { FSCC_OOOO = 0, FSCC_OOOV, FSCC_OOVV, FSCC_OVOV, FSCC_OVVV, FSCC_VVVV } fscc_iclass;
 
@@ -126,7 +126,8 @@ fscc_status fscc_create(const fscc_system *sys, fscc_precision prec, void *hip_s
  * set before fscc_build_residual / fscc_energy. */
 fscc_status fscc_set_integrals(fscc_ctx *ctx, fscc_iclass cls, const fscc_c128 *dev_blocks, size_t n);
 
-/* Packed lengths (complex elements) of T1/R1 and T2/R2 for a sector. */
+/* Packed lengths (complex elements) of T1/R1 and T2/R2 for a sector (for
+ * FSCC_S02: n1 = 0 and n2 = the length of S_xy^ab, see fscc_heff2). */
 fscc_status fscc_layout(const fscc_ctx *ctx, fscc_sector sector, size_t *n1, size_t *n2);
 
 /* R = RHS - D*t for the CCSD equations (Eq. (3)), D_i^a = e_i - e_a,
@@ -163,6 +164,30 @@ fscc_status fscc_prepare_sector(fscc_ctx *ctx, fscc_sector sector, const fscc_c1
  * and columns in the order of sys->active; its eigenvalues are the (0h,1p)
  * state energies relative to the (0h,0p) reference state.  Synchronises. */
 fscc_status fscc_heff(fscc_ctx *ctx, const fscc_c128 *s1, const fscc_c128 *s2, fscc_c128 *heff_host);
+
+/* (0h,2p) sector (the next step of the sector hierarchy of Eq. (5), two valence
+ * particles; present when nact >= 2).  Prepared with fscc_prepare_sector(ctx,
+ * FSCC_S02, s1, s2) from CONVERGED (0h,1p) amplitudes s1, s2 (device, the
+ * FSCC_S01 layouts) after the (0h,1p) preparation; repeat if s1, s2 or T
+ * change (a new (0h,1p) preparation invalidates it).  Amplitudes s_xy^ab for
+ * active pairs x < y and virtual pairs a < b that are not both active,
+ * layout [G][xy<][ab<] (G = irrep(x)+irrep(y) = irrep(a)+irrep(b), pairs as in
+ * the T2 layout over the irrep-sorted active spinors; n1 = 0, pass t1 = r1 =
+ * NULL).  With the normal-ordered wave operator, Omega|xy> = R_x R_y|Phi> +
+ * S_xy|Phi> where R_x attaches the dressed particle r(x) = e_x + s_x of the
+ * (0h,1p) sector; sigma2(xy) = [Hbar_N Omega|xy>] on the 2p space,
+ * H_eff[zw][xy] = sigma2(xy)^zw, and fscc_build_residual(FSCC_S02, NULL, s,
+ * NULL, r) writes the Bloch residual
+ *   R_xy^ab = sigma2(xy)^ab - sum_{z<w} omega(zw)^ab H_eff[zw][xy],
+ *   omega(zw)^ab = r(z)^a r(w)^b - r(z)^b r(w)^a + s_zw^ab,
+ * zero on the model pairs; Jacobi denominators D_xy^ab = e_x + e_y - e_a - e_b
+ * in fscc_update_amplitudes(FSCC_S02, NULL, s, NULL, r, ...); dynamic shifts
+ * as for FSCC_S01.  fscc_heff2 returns H_eff for amplitudes s as a dense
+ * row-major P x P complex matrix heff_host[pair(zw)][pair(xy)] (host memory,
+ * P = nact(nact-1)/2), pairs i < j of positions in sys->active ordered
+ * row-major over the upper triangle; its eigenvalues are the (0h,2p) state
+ * energies relative to the (0h,0p) reference state.  Synchronises. */
+fscc_status fscc_heff2(fscc_ctx *ctx, const fscc_c128 *s, fscc_c128 *heff_host);
 
 /* Jacobi denominators of the (0h,1p) sector (sector = FSCC_S01).  mode 0:
  * D from the orbital energies (Eq. (3)-(4), the default).  mode 1 (after
@@ -273,7 +298,7 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx *ctx, size_t staging_bytes);
  * (R - Delta s) / (D + Delta).  Delta = S where D = 0 and decays as
  * S (S/D)^n for |D| >> |S|.  S = 0 switches the shift off (n ignored).
  * Clears the sector's DIIS history.  FSCC_EINVAL for S > 0, S <= -1e6, n out
- * of range, or FSCC_S01 on a context without the sector.  Contexts of the
+ * of range, or FSCC_S01 / FSCC_S02 on a context without the sector.  Contexts of the
  * batch API do not take shifts. */
 fscc_status fscc_dynamic_shift(fscc_ctx *ctx, fscc_sector sector, double S, int n);
 

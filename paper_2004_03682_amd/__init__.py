@@ -16,7 +16,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfscc.so")
 
-FSCC_S00, FSCC_S01 = 0, 1
+FSCC_S00, FSCC_S01, FSCC_S02 = 0, 1, 2
 FSCC_FP64, FSCC_SPLIT_FP32, FSCC_SPLIT_BF16, FSCC_REAL_FP64 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FSCC_FP64, "split_fp32": FSCC_SPLIT_FP32, "split_bf16": FSCC_SPLIT_BF16,
               "real_fp64": FSCC_REAL_FP64}
@@ -61,6 +61,7 @@ def lib():
             "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
             "fscc_prepare_sector": ([vp, ip, vp, vp], ip),
             "fscc_heff": ([vp, vp, vp, vp], ip),
+            "fscc_heff2": ([vp, vp, vp], ip),
             "fscc_precondition": ([vp, ip, ip, ctypes.c_double], ip),
             "fscc_autotune": ([vp, ip], ip),
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
@@ -174,6 +175,8 @@ class Context:
         self.n1, self.n2 = self.layout(FSCC_S00)
         self.nact = len(self._act)
         self.m1, self.m2 = self.layout(FSCC_S01) if self.nact else (0, 0)
+        self.npair = self.nact * (self.nact - 1) // 2
+        self.p2 = self.layout(FSCC_S02)[1] if self.nact >= 2 else 0
 
     def _d(self, t, n=None):
         """Device pointer of an amplitude / residual / integral tensor of this
@@ -181,6 +184,8 @@ class Context:
         return _dev_ptr(t, n, self.dtype)
 
     def _sizes(self, sector):
+        if sector == FSCC_S02:
+            return (0, self.p2)
         return (self.n1, self.n2) if sector == FSCC_S00 else (self.m1, self.m2)
 
     @classmethod
@@ -249,7 +254,10 @@ class Context:
         return m.value
 
     def prepare_sector(self, t1, t2, sector=FSCC_S01):
-        self._check(lib().fscc_prepare_sector(self._h, sector, self._d(t1, self.n1), self._d(t2, self.n2)))
+        """FSCC_S01: t1, t2 = converged (0h,0p) amplitudes; FSCC_S02: the converged
+        (0h,1p) amplitudes s1, s2 (after the (0h,1p) preparation)."""
+        a, b = (self.m1, self.m2) if sector == FSCC_S02 else (self.n1, self.n2)
+        self._check(lib().fscc_prepare_sector(self._h, sector, self._d(t1, a), self._d(t2, b)))
 
     def precondition(self, mode=1, floor=0.1, sector=FSCC_S01):
         self._check(lib().fscc_precondition(self._h, sector, int(mode), float(floor)))
@@ -260,6 +268,14 @@ class Context:
         out = np.zeros((self.nact, self.nact), np.complex128)
         self._check(lib().fscc_heff(self._h, self._d(s1, self.m1), self._d(s2, self.m2),
                                     out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def heff2(self, s):
+        """(0h,2p) H_eff[pair(zw)][pair(xy)] (numpy complex, P x P over the pairs i < j of
+        positions in the active list, row-major upper triangle)."""
+        import numpy as np
+        out = np.zeros((self.npair, self.npair), np.complex128)
+        self._check(lib().fscc_heff2(self._h, self._d(s, self.p2), out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def energy(self, t1, t2):
@@ -354,6 +370,29 @@ def solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=6, log=None):
             converged = True
             break
     h = ctx.heff(s1, s2)
+    w = np.linalg.eigvals(h)
+    w = w[np.lexsort((w.imag, w.real))]
+    return dict(heff=h, eig=w, iters=k, converged=converged)
+
+
+def solve02(ctx, s, tol=1e-10, maxit=200, ndiis=6, log=None):
+    """(0h,2p) Jacobi + DIIS iterations on s_xy^ab (after ctx.prepare_sector(s1, s2,
+    FSCC_S02)).  Returns dict(heff, eig (sorted by real part), iters, converged)."""
+    import numpy as np
+    import torch
+    r = torch.empty_like(s)
+    ctx.diis_reset(ndiis, FSCC_S02)
+    converged = False
+    k = 0
+    for k in range(1, maxit + 1):
+        ctx.build_residual(None, s, None, r, FSCC_S02)
+        dmax = ctx.update_amplitudes(None, s, None, r, FSCC_S02)
+        if log:
+            log(f"(0h,2p) iter {k:3d}  max|step| = {dmax:.3e}")
+        if dmax < tol:
+            converged = True
+            break
+    h = ctx.heff2(s)
     w = np.linalg.eigvals(h)
     w = w[np.lexsort((w.imag, w.real))]
     return dict(heff=h, eig=w, iters=k, converged=converged)

@@ -341,6 +341,12 @@ void bind_io01(fscc_ctx* c, const fscc_c128* s1, const fscc_c128* s2, fscc_c128*
     c->dbuf[P.b_rs2] = (void*)r2;
 }
 
+void bind_io02(fscc_ctx* c, const fscc_c128* s, fscc_c128* r) {
+    Plan& P = c->plan;
+    c->dbuf[P.b_s02] = (void*)s;
+    c->dbuf[P.b_rs02] = (void*)r;
+}
+
 bool all_integrals(const fscc_ctx* c) {
     for (int k = 0; k < IC_N; ++k)
         if (!c->have_cls[k]) return false;
@@ -369,6 +375,8 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     up_real(P.b_D1x, P.D1x);
     up_real(P.b_D2x, P.D2x);
     up_real(P.b_mask1, P.mask1);
+    up_real(P.b_D02, P.D02);
+    up_real(P.b_mask02, P.mask02);
     for (auto& hc : P.const_host)
         if (!hc.data.empty())
             hip_check(hipMemcpy(c->dbuf[hc.buf], hc.data.data(), hc.data.size() * sizeof(double2),
@@ -387,12 +395,17 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     setup_list(c, c->L00, P.ops);
     setup_list(c, c->L01p, P.ops01_prep);
     setup_list(c, c->L01, P.ops01);
+    setup_list(c, c->L02p, P.ops02_prep);
+    setup_list(c, c->L02, P.ops02);
     c->L01.base = (int)P.ops.size();
+    c->L02.base = (int)(P.ops.size() + P.ops01.size());
     if (diis) setup_diis(c, c->diis[0], c->n1(), c->n2(), P.b_D1, P.b_D2);
     if (P.has01) {
         setup_diis(c, c->diis[1], P.L_S1.total, P.L_S2.total, P.b_D1x, P.b_D2x);
-        c->rs_tmp = (double2*)c->dalloc((size_t)(P.L_S1.total + P.L_S2.total) * sizeof(double2));
+        int64_t ntmp = std::max<int64_t>(P.L_S1.total + P.L_S2.total, P.has02 ? P.L_S02.total : 0);
+        c->rs_tmp = (double2*)c->dalloc((size_t)std::max<int64_t>(1, ntmp) * sizeof(double2));
     }
+    if (P.has02) setup_diis(c, c->diis[2], 0, P.L_S02.total, -1, P.b_D02);
     c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
     c->part_max = (double*)c->dalloc(2048 * sizeof(double));
     c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
@@ -524,6 +537,11 @@ fscc_status fscc_layout(const fscc_ctx* ctx, fscc_sector sector, size_t* n1, siz
         *n2 = (size_t)ctx->plan.L_S2.total;
         return FSCC_OK;
     }
+    if (sector == FSCC_S02 && ctx->plan.has02) {
+        *n1 = 0;
+        *n2 = (size_t)ctx->plan.L_S02.total;
+        return FSCC_OK;
+    }
     return FSCC_EINVAL;
 }
 
@@ -578,6 +596,10 @@ fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
         if (!ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
         n1 = ctx->plan.L_S1.total;
         n2 = ctx->plan.L_S2.total;
+    } else if (sector == FSCC_S02 && ctx->plan.has02) {
+        if (!ctx->ready02) return fail(ctx, FSCC_ESTATE, "(0h,2p) sector not prepared (fscc_prepare_sector)");
+        n1 = 0;
+        n2 = ctx->plan.L_S02.total;
     } else {
         return fail(ctx, FSCC_EINVAL, "sector not available for this system");
     }
@@ -588,9 +610,12 @@ fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
         if (sector == FSCC_S00) {
             bind_io(ctx, t1, t2, r1, r2);
             ctx->run_list(ctx->L00, ctx->prof);
-        } else {
+        } else if (sector == FSCC_S01) {
             bind_io01(ctx, t1, t2, r1, r2);
             ctx->run_list(ctx->L01, ctx->prof);
+        } else {
+            bind_io02(ctx, t2, r2);
+            ctx->run_list(ctx->L02, ctx->prof);
         }
         return FSCC_OK;
     });
@@ -598,6 +623,20 @@ fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
 
 fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2) {
     if (!ctx) return FSCC_EINVAL;
+    if (sector == FSCC_S02) {
+        Plan& P = ctx->plan;
+        if (!P.has02) return fail(ctx, FSCC_EINVAL, "no (0h,2p) sector for this system (needs two active spinors)");
+        if (!ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
+        if ((P.L_S1.total && !t1) || (P.L_S2.total && !t2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+        return guarded(ctx, [&]() -> fscc_status {
+            bind_io01(ctx, t1, t2, nullptr, nullptr);
+            ctx->run_list(ctx->L02p, false);
+            hip_check(hipStreamSynchronize(ctx->st), "prepare sync");
+            ctx->ready02 = true;
+            ctx->diis[2].order.clear();
+            return FSCC_OK;
+        });
+    }
     if (sector != FSCC_S01 || !ctx->plan.has01) return fail(ctx, FSCC_EINVAL, "no (0h,1p) sector for this system");
     if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
     if ((ctx->n1() && !t1) || (ctx->n2() && !t2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
@@ -606,6 +645,7 @@ fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
         ctx->run_list(ctx->L01p, false);
         hip_check(hipStreamSynchronize(ctx->st), "prepare sync");
         ctx->ready01 = true;
+        ctx->ready02 = false;   // the (0h,2p) fixed part depends on T through the (0h,1p) Hbar
         ctx->diis[1].order.clear();
         return FSCC_OK;
     });
@@ -638,6 +678,44 @@ fscc_status fscc_heff(fscc_ctx* ctx, const fscc_c128* s1, const fscc_c128* s2, f
                 }
             off += (int64_t)ng * ng;
         }
+        return FSCC_OK;
+    });
+}
+
+fscc_status fscc_heff2(fscc_ctx* ctx, const fscc_c128* s, fscc_c128* heff_host) {
+    if (!ctx || !heff_host) return FSCC_EINVAL;
+    Plan& P = ctx->plan;
+    if (!P.has02) return fail(ctx, FSCC_EINVAL, "no (0h,2p) sector for this system");
+    if (!ctx->ready02) return fail(ctx, FSCC_ESTATE, "(0h,2p) sector not prepared (fscc_prepare_sector)");
+    if (P.L_S02.total && !s) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        bind_io02(ctx, s, (fscc_c128*)ctx->rs_tmp);
+        ctx->run_list(ctx->L02, false);
+        std::vector<double2> h(P.L_Heff02.total);
+        if (!h.empty())
+            hip_check(hipMemcpyAsync(h.data(), ctx->B(P.b_heff02), h.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                                     ctx->st), "heff d2h");
+        hip_check(hipStreamSynchronize(ctx->st), "heff sync");
+        // [G][zw<][xy<] over irrep-sorted active pairs -> dense [pair(zw)][pair(xy)] over the pairs
+        // i < j of the caller's active list (row-major upper triangle); a pair whose irrep-sorted
+        // order is the reverse of the caller's order contributes with a minus sign
+        const int nact = P.X.n, np = nact * (nact - 1) / 2;
+        for (int k = 0; k < np * np; ++k) heff_host[k] = fscc_c128{0.0, 0.0};
+        auto pidx = [&](int p, int q, int* sg) {
+            int i = P.x_order[p], j = P.x_order[q];
+            *sg = 1;
+            if (i > j) {
+                std::swap(i, j);
+                *sg = -1;
+            }
+            return i * (2 * nact - i - 1) / 2 + (j - i - 1);
+        };
+        P.L_Heff02.for_each([&](int64_t k, const int* p) {
+            int s1, s2;
+            int r = pidx(p[0], p[1], &s1), c = pidx(p[2], p[3], &s2);
+            double2 v = h[(size_t)k];
+            heff_host[r * np + c] = fscc_c128{s1 * s2 * v.x, s1 * s2 * v.y};
+        });
         return FSCC_OK;
     });
 }
@@ -696,7 +774,7 @@ fscc_status fscc_ladder(fscc_ctx* ctx, const fscc_c128* tau, fscc_c128* out) {
 
 fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
     if (!ctx) return FSCC_EINVAL;
-    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01)))
+    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01) || (sector == FSCC_S02 && ctx->plan.has02)))
         return fail(ctx, FSCC_EINVAL, "sector not available for this system");
     if (ndiis < 0 || ndiis > kMaxDiis) return fail(ctx, FSCC_EINVAL, "DIIS depth out of range");
     ctx->diis[sector].ndiis = ndiis;
@@ -707,7 +785,7 @@ fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
 fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2,
                                    const fscc_c128* r1, const fscc_c128* r2, double* max_step) {
     if (!ctx || !max_step) return FSCC_EINVAL;
-    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01)))
+    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01) || (sector == FSCC_S02 && ctx->plan.has02)))
         return fail(ctx, FSCC_EINVAL, "sector not available for this system");
     Diis& D = ctx->diis[sector];
     if ((D.n1 && (!t1 || !r1)) || (D.n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
@@ -843,7 +921,7 @@ fscc_status fscc_profile(fscc_ctx* ctx, int enable) {
     if (!ctx) return FSCC_EINVAL;
     return guarded(ctx, [&]() -> fscc_status {
         ctx->prof = enable != 0;
-        for (OpList* L : {&ctx->L00, &ctx->L01}) {
+        for (OpList* L : {&ctx->L00, &ctx->L01, &ctx->L02}) {
             ctx->collect(*L);   // finish outstanding timings before clearing
             std::fill(L->ms.begin(), L->ms.end(), 0.0);
             std::fill(L->calls.begin(), L->calls.end(), 0);
@@ -860,23 +938,26 @@ fscc_status fscc_profile_select(fscc_ctx* ctx, int k) {
     return FSCC_OK;
 }
 
-// operations are numbered: (0h,0p) residual first, then the (0h,1p) residual
+// operations are numbered: (0h,0p) residual first, then the (0h,1p) and (0h,2p) residuals
 static bool op_ref(fscc_ctx* ctx, int k, OpList** L, int* j) {
-    int n0 = (int)ctx->plan.ops.size(), n1 = (int)ctx->plan.ops01.size();
-    if (k < 0 || k >= n0 + n1) return false;
+    int n0 = (int)ctx->plan.ops.size(), n1 = (int)ctx->plan.ops01.size(), n2 = (int)ctx->plan.ops02.size();
+    if (k < 0 || k >= n0 + n1 + n2) return false;
     if (k < n0) {
         *L = &ctx->L00;
         *j = k;
-    } else {
+    } else if (k < n0 + n1) {
         *L = &ctx->L01;
         *j = k - n0;
+    } else {
+        *L = &ctx->L02;
+        *j = k - n0 - n1;
     }
     return true;
 }
 
 fscc_status fscc_op_count(const fscc_ctx* ctx, int* count) {
     if (!ctx || !count) return FSCC_EINVAL;
-    *count = (int)(ctx->plan.ops.size() + ctx->plan.ops01.size());
+    *count = (int)(ctx->plan.ops.size() + ctx->plan.ops01.size() + ctx->plan.ops02.size());
     return FSCC_OK;
 }
 
@@ -905,7 +986,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
     if (level < 0 || level > 2) return fail(ctx, FSCC_EINVAL, "autotune level must be 0, 1 or 2");
     return guarded(ctx, [&]() -> fscc_status {
         Plan& P = ctx->plan;
-        std::vector<OpList*> lists = {&ctx->L00, &ctx->L01};
+        std::vector<OpList*> lists = {&ctx->L00, &ctx->L01, &ctx->L02};
         if (level == 0) {
             for (OpList* L : lists)
                 for (size_t k = 0; k < L->ops->size(); ++k) {
@@ -921,6 +1002,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         }
         int64_t nio = 2 * std::max<int64_t>(1, ctx->n1()) + 2 * std::max<int64_t>(1, ctx->n2());
         if (P.has01) nio += 2 * std::max<int64_t>(1, P.L_S1.total) + 2 * std::max<int64_t>(1, P.L_S2.total);
+        if (P.has02) nio += 2 * std::max<int64_t>(1, P.L_S02.total);
         double2* tmp = (double2*)ctx->dalloc((size_t)nio * sizeof(double2));   // large enough for either element type
         hip_check(hipMemsetAsync(tmp, 0, (size_t)nio * sizeof(double2), ctx->st), "memset");
         {
@@ -941,6 +1023,11 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 fscc_c128* g = take(P.L_S1.total);
                 fscc_c128* h = take(P.L_S2.total);
                 bind_io01(ctx, e, f, g, h);
+            }
+            if (P.has02) {
+                fscc_c128* e = take(P.L_S02.total);
+                fscc_c128* f = take(P.L_S02.total);
+                bind_io02(ctx, e, f);
             }
         }
         hipEvent_t e0, e1;
@@ -1028,8 +1115,9 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
 
 fscc_status fscc_dynamic_shift(fscc_ctx* ctx, fscc_sector sector, double S, int n) {
     if (!ctx) return FSCC_EINVAL;
-    if (sector != FSCC_S00 && sector != FSCC_S01) return fail(ctx, FSCC_EINVAL, "unknown sector");
+    if (sector != FSCC_S00 && sector != FSCC_S01 && sector != FSCC_S02) return fail(ctx, FSCC_EINVAL, "unknown sector");
     if (sector == FSCC_S01 && !ctx->plan.has01) return fail(ctx, FSCC_EINVAL, "context has no (0h,1p) sector");
+    if (sector == FSCC_S02 && !ctx->plan.has02) return fail(ctx, FSCC_EINVAL, "context has no (0h,2p) sector");
     if (!(S <= 0.0 && S > -1e6) || (S < 0.0 && (n < 1 || n > 16)))
         return fail(ctx, FSCC_EINVAL, "dynamic shift needs -1e6 < S <= 0 and 1 <= n <= 16");
     Diis& D = ctx->diis[sector];
@@ -1120,10 +1208,10 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
         if (ctx->sp.buf >= 0) return fail(ctx, FSCC_ESTATE, "VVVV is already out of device memory");
         if (ctx->prec != FSCC_FP64) return fail(ctx, FSCC_ESTATE, "out-of-core VVVV needs FP64 precision");
         // every reader of the buffer must be a GEMM taking it as a transposed B
-        for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01})
+        for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01, &ctx->L02p, &ctx->L02})
             for (auto& o : *L->ops) {
                 const bool reads = o.src == b || o.dst == b || o.src2 == b;
-                if (reads && !(o.kind == OP_GEMM && o.src2 == b && o.tB && L != &ctx->L01p))
+                if (reads && !(o.kind == OP_GEMM && o.src2 == b && o.tB && L != &ctx->L01p && L != &ctx->L02p))
                     return fail(ctx, FSCC_EINVAL, "operation " + o.name + " cannot stream VVVV");
             }
         StreamPlan& sp = ctx->sp;
@@ -1142,6 +1230,7 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
             hip_check(hipStreamCreateWithFlags(&sp.cs, hipStreamNonBlocking), "copy stream");
             sp.ch00 = stream_plan(ctx, ctx->L00, b, sp.half);
             sp.ch01 = stream_plan(ctx, ctx->L01, b, sp.half);
+            sp.ch02 = stream_plan(ctx, ctx->L02, b, sp.half);
             sp.buf = b;
         } catch (...) {
             ctx->free_stream();

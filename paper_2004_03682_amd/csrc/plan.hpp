@@ -20,11 +20,11 @@ namespace fscc {
 using cplx = std::complex<double>;
 
 enum BufKind { BUF_IN_T1, BUF_IN_T2, BUF_OUT_R1, BUF_OUT_R2, BUF_CONST, BUF_SCRATCH, BUF_REAL,
-               BUF_IN_S1, BUF_IN_S2, BUF_OUT_RS1, BUF_OUT_RS2 };
+               BUF_IN_S1, BUF_IN_S2, BUF_OUT_RS1, BUF_OUT_RS2, BUF_IN_P2, BUF_OUT_RP2 };
 
 inline bool caller_buffer(BufKind k) {
     return k == BUF_IN_T1 || k == BUF_IN_T2 || k == BUF_OUT_R1 || k == BUF_OUT_R2 || k == BUF_IN_S1 ||
-           k == BUF_IN_S2 || k == BUF_OUT_RS1 || k == BUF_OUT_RS2;
+           k == BUF_IN_S2 || k == BUF_OUT_RS1 || k == BUF_OUT_RS2 || k == BUF_IN_P2 || k == BUF_OUT_RP2;
 }
 
 struct BufDesc {
@@ -112,6 +112,14 @@ struct Plan {
     std::vector<int64_t> fvv_diag, foo_diag;   // offset of the diagonal element per V / O position
     std::vector<Op> ops01_prep;       // Hbar elements from the converged (0h,0p) amplitudes
     std::vector<Op> ops01;            // sigma + Bloch residual
+
+    // ---- (0h,2p) sector (present when there are at least two active virtuals)
+    bool has02 = false;
+    Layout L_S02, L_Heff02;           // s_xy^ab: [G][xy<][ab<];  H_eff: [G][zw<][xy<]
+    int b_s02 = -1, b_rs02 = -1, b_D02 = -1, b_mask02 = -1, b_heff02 = -1;
+    std::vector<double> D02, mask02;
+    std::vector<Op> ops02_prep;       // fixed part of sigma2 from the converged (0h,1p) amplitudes
+    std::vector<Op> ops02;            // S_xy terms + Bloch residual
     struct HostConst {
         int buf;
         std::vector<cplx> data;

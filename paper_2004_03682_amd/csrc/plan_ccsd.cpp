@@ -481,7 +481,7 @@ void build_plan_ccsd(const System& S, Plan& P) {
         P.b_rs1 = P.buf("rs1", L_S1.total, BUF_OUT_RS1);
         P.b_rs2 = P.buf("rs2", L_S2.total, BUF_OUT_RS2);
         // denominators D_x^a = e_x - e_a, D_xj^ab = e_x + e_j - e_a - e_b; model-space entries masked
-        P.D1x.assign(L_S1.total, 1.0);
+        P.D1x.assign(L_S1.total, -1.0);   // masked entries: any negative value keeps D + Delta away from 0
         P.mask1.assign(L_S1.total, 0.0);
         std::vector<cplx> eid(L_S1.total, 0.0);
         L_S1.for_each([&](int64_t k, const int* p) {
@@ -692,6 +692,156 @@ void build_plan_ccsd(const System& S, Plan& P) {
         B.mul("R1*=mask", P.b_rs1, P.b_mask1, L_S1.total);
         B.gemm("R2.Heff", P.b_heff, L_Heff, true, false, b_S12, L_S12, false, false, b_C9, L_S12, -1.0, 1);
         B.gather("rs2+=C9", P.b_rs2, L_S2, b_C9, L_S12, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 1);
+
+        // =================================================================
+        // (0h,2p) sector over the active pairs x < y, at fixed T and (0h,1p)
+        // amplitudes.  Omega|xy> = R_x R_y |Phi> + S_xy |Phi> (R_x the dressed
+        // one-particle attachment r(x) = e_x + s_x); projected on the 2p space:
+        //   sigma2 = K + sum_{e<f} Wbar_abef omega^ef + P(ab) sum_e Fbar_be s^ae
+        //   omega  = A_ab[r1(x)^a r1(y)^b] + s_xy^ab
+        //   K      = A_ab[sigma1(x)^a r1(y)^b + r1(x)^a sigma1(y)^b]
+        //            + sum_m [g(x)_m s_ym^ab - g(y)_m s_xm^ab]
+        //            + P(ab) { sum_me (Y - v)(x)_a,me s_ym^be + v(y)_a,me s_xm^be }
+        //   g(x)_m = sum_e Fbar_me r1(x)^e + sum_{n,e<f} <mn||ef> s_xn^ef
+        //   v(x)_a,me = sum_f Wbar_amef r1(x)^f,  Y(x)_a,me = sum_{m'e'} s_xm'^ae' <m'm||e'e>
+        //   H_eff[zw, xy] = sigma2(xy)^zw;  R = sigma2 - sum_{z<w} omega(zw) H_eff[zw, xy]
+        if (x->n >= 2) {
+            P.has02 = true;
+            P.L_S02 = make_layout("S02", G, {s(0, x, 1), s(1, x, 1)}, 0, {s(2, v, 1), s(3, v, 1)}, 0, 1);
+            P.L_Heff02 = make_layout("Heff02", G, {s(0, x, 1), s(1, x, 1)}, 0, {s(2, x, 1), s(3, x, 1)}, 0, 1);
+            const Layout& L_S02 = P.L_S02;
+            const Layout& L_H2 = P.L_Heff02;
+            P.b_s02 = P.buf("s02", L_S02.total, BUF_IN_P2);
+            P.b_rs02 = P.buf("rs02", L_S02.total, BUF_OUT_RP2);
+            // D_xy^ab = e_x + e_y - e_a - e_b; model pairs (a, b both active) are not amplitudes
+            std::vector<char> isact(v->n, 0);
+            for (int q = 0; q < x->n; ++q) isact[P.x_vpos[q]] = 1;
+            P.D02.assign(L_S02.total, -1.0);   // masked entries: negative, so D + Delta never vanishes
+            P.mask02.assign(L_S02.total, 0.0);
+            L_S02.for_each([&](int64_t k, const int* p) {
+                if (isact[p[2]] && isact[p[3]]) return;
+                P.D02[k] = S.eps[x->glob[p[0]]] + S.eps[x->glob[p[1]]] - S.eps[v->glob[p[2]]] - S.eps[v->glob[p[3]]];
+                P.mask02[k] = 1.0;
+            });
+            P.b_D02 = P.buf("D02", L_S02.total, BUF_REAL);
+            P.b_mask02 = P.buf("mask02", L_S02.total, BUF_REAL);
+
+            // ------------------------------------------ fixed part (prepare)
+            B.out = &P.ops02_prep;
+            B.axpby("r1=s1 (02)", b_r1x, P.b_s1, L_S1.total, 1.0, 0, false);
+            B.mul("r1*=mask (02)", b_r1x, P.b_mask1, L_S1.total);
+            B.axpby("r1+=e_x (02)", b_r1x, b_eid, L_S1.total, 1.0, 1, false);
+            B.gather("s2->ring (02)", b_S9, L_S9, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            B.gather("s2->(x|m,ef<) (02)", b_S12, L_S12, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            // sigma1(x) (the (0h,1p) sigma vector, 1p part)
+            int b_sg1 = P.buf("sigma1(02)", L_S1.total, BUF_SCRATCH);
+            B.gemm("P2.sigma1.Fvv", b_r1x, L_S1, false, false, b_Fvv, L_Fae_m, true, false, b_sg1, L_S1, 1.0, 0);
+            B.gemm("P2.sigma1.Fov", b_S9, L_S9, false, false, b_Fov, L_Fme_v, false, false, b_sg1, L_S1v, 1.0, 1);
+            B.gemm("P2.sigma1.Wamef", b_S12, L_S12, false, false, b_Wam, L_ovvv_14e, false, false, b_sg1, L_S1, 1.0, 1);
+            // g(x)_m
+            int b_g = P.buf("g(02)", L_q.total, BUF_SCRATCH);
+            B.gemm("P2.g.oovv", b_S12, L_S12, false, false, b_oovv_3b, L_oovv_3b, true, false, b_g, L_q, 1.0, 0);
+            B.gemm("P2.g.Fov", b_r1x, L_S1, false, false, b_Fov, L_Fme_m, true, false, b_g, L_q, 1.0, 1);
+            // omega_pp = A_ab[r1(x)^a r1(y)^b]
+            int b_wpp = P.buf("omega_pp", L_S02.total, BUF_SCRATCH);
+            B.gather("omega_pp", b_wpp, L_S02, b_r1x, L_S1, {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}}, 1.0, 0,
+                     false, b_r1x, &L_S1);
+            // K: legs on one line
+            int b_K = P.buf("K02", L_S02.total, BUF_SCRATCH);
+            B.gather("K=sigma1 r1", b_K, L_S02, b_sg1, L_S1, {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}}, 1.0, 0,
+                     false, b_r1x, &L_S1);
+            B.gather("K+=r1 sigma1", b_K, L_S02, b_r1x, L_S1, {T{{0, 2}, 1, {1, 3}}, T{{0, 3}, -1, {1, 2}}}, 1.0, 1,
+                     false, b_sg1, &L_S1);
+            // K += sum_m g(x)_m s_ym^ab - (x <-> y)
+            Layout L_S2m = make_layout("S2(m|y,ab<)", G, {s(1, o, 1)}, -1, {s(0, x, -1), s(2, v, 1), s(3, v, 1)}, 1, 1);
+            int b_S2m = P.buf("S2(m|y,ab<)", L_S2m.total, BUF_SCRATCH);
+            B.gather("s2->(m|y,ab<)", b_S2m, L_S2m, P.b_s2, L_S2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            Layout L_Hg = make_layout("Hg02", G, {s(0, x, 1)}, -1, {s(1, x, -1), s(2, v, 1), s(3, v, 1)}, 1, 1);
+            int b_Hg = P.buf("Hg02", L_Hg.total, BUF_SCRATCH);
+            B.gemm("P2.g.s2", b_g, L_q, false, false, b_S2m, L_S2m, false, false, b_Hg, L_Hg, 1.0, 0);
+            B.gather("K+=Hg", b_K, L_S02, b_Hg, L_Hg, {T{{0, 1, 2, 3}, 1, {}}, T{{1, 0, 2, 3}, -1, {}}}, 1.0, 1);
+            // v(x)_a,me = sum_f Wbar_amef r1(x)^f
+            Layout L_Wp = make_layout("Wbar(a,m,e|f)", G, {s(1, v, 1), s(0, o, 1), s(2, v, -1)}, -1, {s(3, v, 1)}, -1, 1);
+            int b_Wp = P.buf("Wbar(a,m,e|f)", L_Wp.total, BUF_SCRATCH);
+            B.gather("Wbar->(a,m,e|f)", b_Wp, L_Wp, b_Wam, L_ovvv_14e, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            Layout L_vt = make_layout("v(a,m,e|x)", G, {s(1, v, 1), s(0, o, 1), s(2, v, -1)}, -1, {s(3, x, 1)}, -1, 1);
+            int b_vt = P.buf("v(a,m,e|x)", L_vt.total, BUF_SCRATCH);
+            B.gemm("P2.v", b_Wp, L_Wp, false, false, b_r1x, L_S1, true, false, b_vt, L_vt, 1.0, 0);
+            Layout L_v3 = make_layout("v(x,a|m,e)", G, {s(0, x, -1), s(2, v, 1)}, -1, {s(1, o, -1), s(3, v, 1)}, -1, 1);
+            int b_v3 = P.buf("v(x,a|m,e)", L_v3.total, BUF_SCRATCH);
+            B.gather("v->(x,a|m,e)", b_v3, L_v3, b_vt, L_vt, {T{{1, 2, 3, 0}, 1, {}}}, 1.0, 0);
+            // Y(x)_a,me = sum_{m'e'} s_xm'^ae' <m'm||e'e>, then U = Y - v in the same layout
+            Layout L_Yr = make_layout("Y(x,a|n,f)", G, {s(0, x, -1), s(2, v, 1)}, -1, {s(1, o, 1), s(3, v, -1)}, -1, -1);
+            int b_Yr = P.buf("Y(x,a|n,f)", L_Yr.total, BUF_SCRATCH);
+            B.gemm("P2.Y", b_S9, L_S9, false, false, b_oovv_ph, L_oovv_ph, false, false, b_Yr, L_Yr, 1.0, 0);
+            int b_U3 = P.buf("U(x,a|m,e)", L_v3.total, BUF_SCRATCH);
+            B.gather("U=Y", b_U3, L_v3, b_Yr, L_Yr, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            B.axpby("U-=v", b_U3, b_v3, L_v3.total, -1.0, 1, false);
+            // C[(x,a),(y,b)] = sum_me U s_ym^be,  C'[(x,a),(y,b)] = sum_me v s_ym^be
+            Layout L_C3 = make_layout("C(x,a|y,b)", G, {s(0, x, -1), s(2, v, 1)}, -1, {s(1, x, -1), s(3, v, 1)}, -1, -1);
+            int b_C3 = P.buf("C(x,a|y,b)", L_C3.total, BUF_SCRATCH);
+            int b_C3p = P.buf("C'(x,a|y,b)", L_C3.total, BUF_SCRATCH);
+            B.gemm("P2.U.s2", b_U3, L_v3, false, false, b_S9, L_S9, true, false, b_C3, L_C3, 1.0, 0);
+            B.gemm("P2.v.s2", b_v3, L_v3, false, false, b_S9, L_S9, true, false, b_C3p, L_C3, 1.0, 0);
+            B.gather("K+=P(ab)C", b_K, L_S02, b_C3, L_C3, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}}, 1.0, 1);
+            B.gather("K+=P(ab)C'", b_K, L_S02, b_C3p, L_C3, {T{{1, 0, 2, 3}, 1, {}}, T{{1, 0, 3, 2}, -1, {}}}, 1.0, 1);
+
+            // ---------------------------------------- per iteration: sigma2 + residual
+            B.out = &P.ops02;
+            int b_om = P.buf("omega", L_S02.total, BUF_SCRATCH);
+            B.axpby("omega=omega_pp", b_om, b_wpp, L_S02.total, 1.0, 0, false);
+            B.axpby("omega+=s", b_om, P.b_s02, L_S02.total, 1.0, 1, false);
+            B.axpby("sigma2=K", P.b_rs02, b_K, L_S02.total, 1.0, 0, false);
+            // sum_{e<f} Wbar_abef omega^ef: bare ladder, T1 part, tau part
+            B.gemm("P2-ladder", b_om, L_S02, false, false, b_vvvv, L_VVVV, true, false, P.b_rs02, L_S02, 1.0, 1);
+            Layout L_Z02 = make_layout("Z02", G, {s(0, o, 1), s(1, v, 1)}, -1, {s(2, x, 1), s(3, x, 1)}, 0, 1);
+            int b_Z02 = P.buf("Z02", L_Z02.total, BUF_SCRATCH);
+            B.gemm("P2.Z", b_ovvv, L_OVVV, false, false, b_om, L_S02, true, false, b_Z02, L_Z02, -1.0, 0);
+            Layout L_Z2b = make_layout("Z02'", G, {s(2, x, 1), s(3, x, 1), s(1, v, -1)}, 0, {s(0, o, 1)}, -1, 1);
+            int b_Z2b = P.buf("Z02'", L_Z2b.total, BUF_SCRATCH);
+            B.gather("Z02->Z02'", b_Z2b, L_Z2b, b_Z02, L_Z02, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            Layout L_Y4b = make_layout("Y4(02)", G, {s(0, x, 1), s(1, x, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+            int b_Y4b = P.buf("Y4(02)", L_Y4b.total, BUF_SCRATCH);
+            B.gemm("P2.Z.t1", b_Z2b, L_Z2b, false, false, b_t1c, L_T1, false, false, b_Y4b, L_Y4b, 1.0, 0);
+            B.gather("sigma2+=-P(ab)Y4", P.b_rs02, L_S02, b_Y4b, L_Y4b,
+                     {T{{0, 1, 2, 3}, -1, {}}, T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
+            Layout L_X02 = make_layout("X02", G, {s(0, o, 1), s(1, o, 1)}, 0, {s(2, x, 1), s(3, x, 1)}, 0, 1);
+            int b_X02 = P.buf("X02", L_X02.total, BUF_SCRATCH);
+            B.gemm("P2.X", b_oovv, L_OOVV, false, false, b_om, L_S02, true, false, b_X02, L_X02, 1.0, 0);
+            B.gemm("P2.hh", b_X02, L_X02, true, false, b_tauc, L_T2, false, false, P.b_rs02, L_S02, 1.0, 1);
+            // P(ab) sum_e Fbar_be s^ae
+            Layout L_S7b = make_layout("S02(x,y,a|e)", G, {s(0, x, 1), s(1, x, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
+            int b_S7b = P.buf("S02(x,y,a|e)", L_S7b.total, BUF_SCRATCH);
+            B.gather("s02->(x,y,a|e)", b_S7b, L_S7b, P.b_s02, L_S02, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
+            int b_Y7b = P.buf("Y7(02)", L_S7b.total, BUF_SCRATCH);
+            B.gemm("P2.Fvv", b_S7b, L_S7b, false, false, b_Fvv, L_Fae_m, true, false, b_Y7b, L_S7b, 1.0, 0);
+            B.gather("sigma2+=P(ab)Y7", P.b_rs02, L_S02, b_Y7b, L_S7b, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}},
+                     1.0, 1);
+            // H_eff[zw, xy] = sigma2(xy)^zw
+            P.b_heff02 = P.buf("Heff02", L_H2.total, BUF_SCRATCH);
+            {
+                Op op;
+                op.kind = OP_GATHER;
+                op.name = "Heff02=sigma2";
+                op.dst = P.b_heff02;
+                op.src = P.b_rs02;
+                op.alpha = 1.0;
+                op.beta = 0;
+                op.n = L_H2.total;
+                std::vector<uint32_t> m((size_t)L_H2.total, MAP_ZERO);
+                L_H2.for_each([&](int64_t k, const int* p) {
+                    int pos[4] = {p[2], p[3], P.x_vpos[p[0]], P.x_vpos[p[1]]};   // sigma2(xy)^zw
+                    int sg = 1;
+                    int64_t so = L_S02.find(pos, &sg);
+                    if (so >= 0) m[(size_t)k] = (uint32_t)so | (sg < 0 ? MAP_NEG : 0u);
+                });
+                op.mapsA.push_back(P.map("Heff02/A0", std::move(m)));
+                B.out->push_back(std::move(op));
+            }
+            // Bloch residual R = sigma2 - sum_{z<w} omega(zw) H_eff[zw, xy], model pairs masked
+            B.gemm("P2.R.Heff", P.b_heff02, L_H2, true, false, b_om, L_S02, false, false, P.b_rs02, L_S02, -1.0, 1);
+            B.mul("R02*=mask", P.b_rs02, P.b_mask02, L_S02.total);
+        }
         B.out = &P.ops;
     }
 }

@@ -92,7 +92,7 @@ struct StreamPlan {
     hipStream_t cs = nullptr;
     hipEvent_t free_ev[2] = {nullptr, nullptr};
     int next = 0;         // staging buffer of the next chunk
-    std::vector<std::vector<StreamChunk>> ch00, ch01;
+    std::vector<std::vector<StreamChunk>> ch00, ch01, ch02;
 };
 
 struct OpList {
@@ -132,11 +132,12 @@ struct fscc_ctx {
     Plan plan;
     std::vector<void*> dbuf;
     std::vector<uint32_t*> dmap;
-    OpList L00, L01p, L01;
+    OpList L00, L01p, L01, L02p, L02;
     StreamPlan sp;   // out-of-core VVVV (fscc_vvvv_out_of_core)
     bool have_cls[IC_N] = {false, false, false, false, false, false};
     bool ready01 = false;
-    Diis diis[2];
+    bool ready02 = false;
+    Diis diis[3];
     double* part = nullptr;
     double* part_max = nullptr;
     double* coef = nullptr;
@@ -189,7 +190,7 @@ struct fscc_ctx {
     }
 
     void free_stream() {
-        for (auto* L : {&sp.ch00, &sp.ch01})
+        for (auto* L : {&sp.ch00, &sp.ch01, &sp.ch02})
             for (auto& v : *L)
                 for (auto& c : v) {
                     free_gemm_dev(c.g);
@@ -226,6 +227,8 @@ struct fscc_ctx {
         free_list(L00);
         free_list(L01p);
         free_list(L01);
+        free_list(L02p);
+        free_list(L02);
         for (auto& d : diis) {
             if (d.ht) (void)hipFree(d.ht);
             if (d.he) (void)hipFree(d.he);
@@ -365,6 +368,7 @@ struct fscc_ctx {
         if (sp.buf < 0) return nullptr;
         if (&L == &L00) return &sp.ch00;
         if (&L == &L01) return &sp.ch01;
+        if (&L == &L02) return &sp.ch02;
         return nullptr;
     }
 
@@ -508,6 +512,7 @@ void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops);
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2);
 void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2);
 void bind_io01(fscc_ctx* c, const fscc_c128* s1, const fscc_c128* s2, fscc_c128* r1, fscc_c128* r2);
+void bind_io02(fscc_ctx* c, const fscc_c128* s, fscc_c128* r);
 bool all_integrals(const fscc_ctx* c);
 void ctx_allocate(fscc_ctx* c, bool diis);
 

@@ -159,3 +159,71 @@ def unpack_s2(sysm, buf):
         s2[X[:, None], J[:, None], B[None, :], A[None, :]] = -x
     assert off == buf.size
     return s2
+
+
+# ---------------------------------------------------------------- (0h,2p) sector
+#   S02: [G][xy<][ab<]  (active pairs x < y in the irrep-sorted active order, grouped
+#   like the T2 pairs; the dense oracle tensor is s[pair(i, j)][a][b] over the
+#   pairs i < j of positions in the sorted active list, row-major upper triangle)
+
+def xy_pair_list(sysm, G):
+    n = sysm.nirrep
+    P, Q = [], []
+    for gp in range(n):
+        gq = (G - gp) % n
+        if gp > gq:
+            continue
+        mp, mq = active_members(sysm, gp), active_members(sysm, gq)
+        if gp < gq:
+            for p in mp:
+                for q in mq:
+                    P.append(p)
+                    Q.append(q)
+        else:
+            for a in range(len(mp)):
+                for b in range(a + 1, len(mp)):
+                    P.append(mp[a])
+                    Q.append(mp[b])
+    return np.array(P, dtype=np.int64), np.array(Q, dtype=np.int64)
+
+
+def pair_index(n, i, j):
+    return i * (2 * n - i - 1) // 2 + (j - i - 1)
+
+
+def _s02_full(sysm, s):
+    n = len(sysm.active)
+    full = np.zeros((n, n, sysm.nvirt, sysm.nvirt), np.complex128)
+    for i in range(n):
+        for j in range(i + 1, n):
+            full[i, j] = s[pair_index(n, i, j)]
+            full[j, i] = -s[pair_index(n, i, j)]
+    return full
+
+
+def pack_s02(sysm, s):
+    full = _s02_full(sysm, s)
+    out = []
+    for G in range(sysm.nirrep):
+        X, Y = xy_pair_list(sysm, G)
+        A, B = pair_list(sysm, "V", G)
+        out.append(full[X[:, None], Y[:, None], A[None, :], B[None, :]].ravel())
+    return np.concatenate(out)
+
+
+def unpack_s02(sysm, buf):
+    n = len(sysm.active)
+    full = np.zeros((n, n, sysm.nvirt, sysm.nvirt), np.complex128)
+    off = 0
+    for G in range(sysm.nirrep):
+        X, Y = xy_pair_list(sysm, G)
+        A, B = pair_list(sysm, "V", G)
+        sz = len(X) * len(A)
+        x = buf[off:off + sz].reshape(len(X), len(A))
+        off += sz
+        full[X[:, None], Y[:, None], A[None, :], B[None, :]] = x
+        full[X[:, None], Y[:, None], B[None, :], A[None, :]] = -x
+        full[Y[:, None], X[:, None], A[None, :], B[None, :]] = -x
+        full[Y[:, None], X[:, None], B[None, :], A[None, :]] = x
+    assert off == buf.size
+    return np.array([full[i, j] for i in range(n) for j in range(i + 1, n)]).reshape(-1, sysm.nvirt, sysm.nvirt)

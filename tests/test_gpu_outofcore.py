@@ -3,7 +3,7 @@ packed VVVV integrals live in pinned host memory and stream through two small
 device staging buffers while the ladder GEMMs run.  Staging buffers far
 smaller than one ladder block force problems to be cut along ab and many
 chunks per launch.  Results must equal the in-memory path (1e-12 of max|R|
-per call, 1e-10 Eh converged), in both sectors and in real arithmetic, and
+per call, 1e-10 Eh converged), in all three sectors and in real arithmetic, and
 moving VVVV back must restore the in-memory path."""
 import numpy as np
 import pytest
@@ -105,6 +105,26 @@ def test_out_of_core_second_sector():
     b1, b2 = _residual(ctx, s1, s2, 1)
     scale = float(max(a1.abs().max(), a2.abs().max()))
     assert float((a1 - b1).abs().max()) <= 1e-12 * scale and float((a2 - b2).abs().max()) <= 1e-12 * scale
+    ctx.destroy()
+
+
+def test_out_of_core_third_sector():
+    import torch
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(7, 19, 3, 0.05, 8, nact=6)
+    ctx = _ctx(s)
+    t1, t2 = _rand(ctx, ctx.n1, 3, 0.01), _rand(ctx, ctx.n2, 4, 0.01)
+    ctx.prepare_sector(t1, t2)
+    s1, s2 = _rand(ctx, ctx.m1, 5, 0.05), _rand(ctx, ctx.m2, 6, 0.05)
+    ctx.prepare_sector(s1, s2, sector=F.FSCC_S02)
+    sp = _rand(ctx, ctx.p2, 7, 0.05)
+    a = torch.empty_like(sp)
+    ctx.build_residual(None, sp, None, a, F.FSCC_S02)
+    ctx.vvvv_out_of_core(16 * 1024)
+    b = torch.empty_like(sp)
+    ctx.build_residual(None, sp, None, b, F.FSCC_S02)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max()) <= 1e-12 * float(a.abs().max())
     ctx.destroy()
 
 
