@@ -370,6 +370,78 @@ def learned_study(F, torch, b, mp2, t2_conv, log):
     return ev
 
 
+def fs02_study(ctx, F, torch, sysm, s1, s2, log, S=-3.0, n=3, scales=(1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4)):
+    """(0h,2p) sector over the active pairs, prepared from the (0h,1p) amplitudes in s1, s2:
+    dynamically shifted solves at decreasing scale, [2/1] Pade extrapolation of every
+    pair-state energy, time per iteration, and the pair ladder's streamed HBM rate."""
+    import numpy as np
+    out = {"npair": int(ctx.npair), "amplitudes": int(ctx.p2), "S": S, "n": n, "scales": list(scales)}
+    torch.cuda.synchronize()
+    st = time.perf_counter()
+    ctx.prepare_sector(s1, s2, F.FSCC_S02)
+    torch.cuda.synchronize()
+    out["prepare_ms"] = round((time.perf_counter() - st) * 1e3, 3)
+    sp = torch.zeros(ctx.p2, dtype=torch.complex128, device=s1.device)
+    eigs, iters, conv = [], [], []
+    st = time.perf_counter()
+    try:
+        for lam in scales:
+            ctx.dynamic_shift(lam * S, n, F.FSCC_S02)
+            r = F.solve02(ctx, sp, tol=1e-10, maxit=200, ndiis=8)
+            eigs.append(r["eig"])
+            iters.append(r["iters"])
+            conv.append(r["converged"])
+    except F.FsccError as e:
+        out["status"] = f"failed ({e})"
+        log(f"(0h,2p) failed: {e}")
+        return out
+    finally:
+        ctx.dynamic_shift(0.0, n, F.FSCC_S02)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - st
+    out.update(iterations=iters, converged=conv, seconds=round(el, 4),
+               ms_per_iteration=round(el / max(1, sum(iters)) * 1e3, 4))
+    if all(conv):
+        E = np.array(eigs)
+        ext = np.array([F.pade(list(scales), E[:, k], 2, 1) for k in range(E.shape[1])])
+        alt = np.array([F.pade(list(scales), E[:, k], 3, 0) for k in range(E.shape[1])])
+        out["extrapolated_re"] = [float(x.real) for x in ext]
+        out["max_abs_diff_pade_2_1_vs_3_0"] = float(np.abs(alt - ext).max())
+    # per-operation times of the residual; the pair ladder reads every VVVV block once
+    r = torch.empty_like(sp)
+    ctx.profile(True)
+    for _ in range(5):
+        ctx.build_residual(None, sp, None, r, F.FSCC_S02)
+    torch.cuda.synchronize()
+    ops = {o["name"]: o for o in ctx.op_times() if o["calls"]}
+    ctx.profile(False)
+    lad = ops.get("P2-ladder")
+    if lad:
+        # algorithmic bytes: every <ab||cd> block of a pair irrep that holds an active pair,
+        # read once, plus omega read and sigma2 read and written
+        G = sysm.nirrep
+        gv = [int(g) for g in sysm.irrep[sysm.nocc:]]
+        ga = [int(sysm.irrep[p]) for p in sysm.active]
+
+        def pairs(gl):
+            c = [0] * G
+            for i in range(len(gl)):
+                for j in range(i + 1, len(gl)):
+                    c[(gl[i] + gl[j]) % G] += 1
+            return c
+        nab, nxy = pairs(gv), pairs(ga)
+        vb = float(sum(16 * (nab[g] ** 2 + 3 * nxy[g] * nab[g]) for g in range(G) if nxy[g]))
+        ms = lad["ms"] / lad["calls"]
+        out["pair_ladder"] = {"ms": round(ms, 4), "bytes": vb, "GB_per_s": round(vb / (ms * 1e-3) / 1e9, 1),
+                              "frac_of_hbm_peak": round(vb / (ms * 1e-3) / 8.0e12, 3),
+                              "pair_irreps_with_pairs": sum(1 for g in range(G) if nxy[g])}
+    # only the (0h,2p) residual ran while profiling: every timed operation belongs to it
+    out["residual_ms"] = round(sum(o["ms"] / o["calls"] for o in ops.values()), 4)
+    log(f"(0h,2p): {ctx.npair} pairs, iterations {iters}, {out['ms_per_iteration']:.3f} ms/iteration, "
+        f"pair ladder {out.get('pair_ladder')}")
+    return out
+
+
 def batch_study(F, torch, fsgen, args, log):
     """64 independent systems (nocc U{10..30}, nvirt U{60..200}, 4-8 irreps,
     sigma 0.05, seeds 40000..40063): one batched solve (grouped launches, graph
@@ -478,7 +550,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) sector")
+    ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) and (0h,2p) sectors")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
     ap.add_argument("--no-real", action="store_true", help="skip the real-arithmetic (real double group) study")
@@ -691,6 +763,9 @@ def main():
             fs["dynamic_shift"] = {"S": S_dyn, "n": n_dyn, "status": f"failed ({e})"}
             log(f"(0h,1p) with dynamic shifts failed: {e}")
         result["fs01"] = fs
+        if s.nact >= 2:
+            # (0h,2p) from the last (0h,1p) amplitudes (the smallest-shift solve)
+            result["fs02"] = fs02_study(ctx, F, torch, s, s1, s2, log)
     if not args.no_ooc:
         result["out_of_core"] = out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log)
     ctx.destroy()
