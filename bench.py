@@ -432,9 +432,11 @@ def fs02_study(ctx, F, torch, sysm, s1, s2, log, S=-3.0, n=3, scales=(1.0, 0.9, 
         nab, nxy = pairs(gv), pairs(ga)
         vb = float(sum(16 * (nab[g] ** 2 + 3 * nxy[g] * nab[g]) for g in range(G) if nxy[g]))
         ms = lad["ms"] / lad["calls"]
+        cfg = next(((c, b, sp) for nm, c, b, sp in ctx.gemm_configs() if nm == "P2-ladder"), None)
         out["pair_ladder"] = {"ms": round(ms, 4), "bytes": vb, "GB_per_s": round(vb / (ms * 1e-3) / 1e9, 1),
                               "frac_of_hbm_peak": round(vb / (ms * 1e-3) / 8.0e12, 3),
-                              "pair_irreps_with_pairs": sum(1 for g in range(G) if nxy[g])}
+                              "pair_irreps_with_pairs": sum(1 for g in range(G) if nxy[g]),
+                              "tile": None if cfg is None else list(cfg)}
     # only the (0h,2p) residual ran while profiling: every timed operation belongs to it
     out["residual_ms"] = round(sum(o["ms"] / o["calls"] for o in ops.values()), 4)
     log(f"(0h,2p): {ctx.npair} pairs, iterations {iters}, {out['ms_per_iteration']:.3f} ms/iteration, "
@@ -607,7 +609,7 @@ def main():
 
     t0 = time.perf_counter()
     ctx.autotune(1)
-    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32"}
+    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot"}
     tuned = {n: f"{names[c]}/bk{b}{'/splitK' if sp else ''}" for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))

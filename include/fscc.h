@@ -251,7 +251,8 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
  * shapes 0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64,
  * 9: 32x64, 10: 64x32;
  * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
- * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256);
+ * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256),
+ * 11: dot (needs !tA, tB, M <= 8; every B row streamed once);
  * -1 = cost model.  FSCC_EINVAL if the shape does not fit the form.
  * bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.
  * Synchronises hip_stream. */

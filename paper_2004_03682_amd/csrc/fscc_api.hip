@@ -24,7 +24,7 @@ namespace rt {
 // take any shape).
 bool cfg_ok(const Op& o, int cfg, bool real) {
     if (cfg < 0 || cfg >= ZCFG_N) return false;
-    if (real && cfg == ZCFG_SKINNY) return false;   // no real form of the skinny kernel
+    if (real && (cfg == ZCFG_SKINNY || cfg == ZCFG_DOT)) return false;   // no real form of these kernels
     if (cfg == ZCFG_TALL) {
         if (o.tA) return false;
         for (auto& p : o.probs)
@@ -35,12 +35,17 @@ bool cfg_ok(const Op& o, int cfg, bool real) {
         for (auto& p : o.probs)
             if (p.M > ZRED_MAX_M || p.N > ZRED_MAX_N) return false;
     }
+    if (cfg == ZCFG_DOT) {
+        if (o.tA || !o.tB) return false;
+        for (auto& p : o.probs)
+            if (p.M > ZDOT_MAX_M) return false;
+    }
     return true;
 }
 
 double cfg_cost(const Op& o, int cfg) {
-    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0, 1.0, 1.0, 1.3, 1.3};
-    if (cfg == ZCFG_TALL || cfg == ZCFG_RED) {
+    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0, 1.0, 1.0, 1.3, 1.3, 1.0};
+    if (cfg == ZCFG_TALL || cfg == ZCFG_RED || cfg == ZCFG_DOT) {
         // streaming forms: every operand element read once, exact work on the
         // vector ALUs
         double fl = 0.0, by = 0.0;
@@ -245,7 +250,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
             const int need = (p.K + cap - 1) / cap;
             Sq[q] = std::max(1, std::max(need, allow_split ? std::min(S, (p.K + 127) / 128) : 1));
         }
-    } else if (cfg != ZCFG_TALL && allow_split && S > 1 && maxK >= 512)
+    } else if (cfg != ZCFG_TALL && cfg != ZCFG_DOT && allow_split && S > 1 && maxK >= 512)
         for (size_t q = 0; q < o.probs.size(); ++q) {
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
             split |= Sq[q] > 1;
@@ -1058,8 +1063,9 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (int cfg = 0; cfg < ZCFG_N; ++cfg)
                     for (int bk : {16, 32})
                         for (int sp = 1; sp >= 0; --sp) {
-                            if ((cfg == ZCFG_SKINNY || cfg == ZCFG_TALL || cfg == ZCFG_RED) && bk != 16) continue;
-                            if ((cfg == ZCFG_TALL && sp == 1) || (cfg == ZCFG_RED && sp == 0)) continue;
+                            if ((cfg == ZCFG_SKINNY || cfg == ZCFG_TALL || cfg == ZCFG_RED || cfg == ZCFG_DOT) && bk != 16)
+                                continue;
+                            if (((cfg == ZCFG_TALL || cfg == ZCFG_DOT) && sp == 1) || (cfg == ZCFG_RED && sp == 0)) continue;
                             if (!cfg_ok(o, cfg, ctx->real)) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);

@@ -610,11 +610,106 @@ __global__ __launch_bounds__(256) void k_zred(const double2* __restrict__ A, con
     }
 }
 
+// Dot-product-shaped products (M <= MAXM rows of A, B stored transposed so
+// that every output C(m, n) is the dot product of the contiguous K-vectors
+// A(m, :) and B(n, :)): one workgroup per ZDOT_ROWS rows of B, each of its
+// four waves streaming four rows.  A is staged in LDS in chunks of ZDOT_KC;
+// lane l takes k = l, l + 64, ... of the chunk, so every load instruction of
+// a wave reads 1 KB of one B row contiguously and the four rows x four
+// k-steps of a chunk (16 loads per lane) are issued before they are used.
+// Each B element is read once; the 64 lane partial sums of an output are
+// combined by a fixed butterfly.
+template <int MAXM>
+__global__ __launch_bounds__(256) void k_zdot(const double2* __restrict__ A, const double2* __restrict__ B,
+                                              double2* __restrict__ C, const ZProb* __restrict__ probs,
+                                              const ZTile* __restrict__ tiles, double ar, double ai, int beta,
+                                              int cA, int cB, const int* __restrict__ active) {
+    constexpr int RW = ZDOT_ROWS / 4, KS = ZDOT_KC / 64;
+    __shared__ double2 As[MAXM * ZDOT_KC];
+    const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;
+    const ZProb pr = probs[tl.prob];
+    const int M = pr.M, N = pr.N, K = pr.K;
+    if (M <= 0 || N <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = tl.n0 + wave * RW;
+    const double sA = cA ? -1.0 : 1.0, sB = cB ? -1.0 : 1.0;
+    const double2* Ap = A + pr.a_off;
+    const double2* Bp = B + pr.b_off;
+    double xr[RW][MAXM], xi[RW][MAXM];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) xr[r][i] = xi[r][i] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += ZDOT_KC) {
+        const int kc = min(ZDOT_KC, K - k0);
+        __syncthreads();
+        for (int e = tid; e < M * ZDOT_KC; e += kThreads) {
+            const int i = e / ZDOT_KC, k = e - i * ZDOT_KC;
+            double2 v = make_double2(0.0, 0.0);
+            if (k < kc) {
+                v = Ap[(long long)i * pr.lda + k0 + k];
+                v.y *= sA;
+            }
+            As[e] = v;
+        }
+        __syncthreads();
+        double2 b[KS][RW];
+#pragma unroll
+        for (int q = 0; q < KS; ++q)
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int k = q * 64 + lane, n = nb + r;
+                b[q][r] = (k < kc && n < N) ? Bp[(long long)n * pr.ldb + k0 + k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const int k = q * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i >= M) break;
+                const double2 a = As[i * ZDOT_KC + k];
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const double br = b[q][r].x, bi = sB * b[q][r].y;
+                    xr[r][i] += a.x * br - a.y * bi;
+                    xi[r][i] += a.x * bi + a.y * br;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) {
+            if (i >= M) break;
+            double sr = xr[r][i], si = xi[r][i];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                sr += __shfl_xor(sr, off, 64);
+                si += __shfl_xor(si, off, 64);
+            }
+            const int n = nb + r;
+            if (lane == 0 && n < N) {
+                double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+                double2* c = C + pr.c_off + (long long)i * pr.ldc + n;
+                if (beta) {
+                    const double2 old = *c;
+                    out.x += old.x;
+                    out.y += old.y;
+                }
+                *c = out;
+            }
+        }
+}
+
 void zcfg_tile(int cfg, int* bm, int* bn) {
     switch (cfg) {
         case ZCFG_SKINNY: *bm = ZSKINNY_BM; *bn = ZSKINNY_BN; break;
         case ZCFG_TALL: *bm = ZTALL_ROWS; *bn = ZTALL_MAX_KN; break;
         case ZCFG_RED: *bm = ZRED_MAX_M; *bn = ZRED_MAX_N; break;
+        case ZCFG_DOT: *bm = ZDOT_MAX_M; *bn = ZDOT_ROWS; break;
         case ZCFG_128x16: *bm = 128; *bn = 16; break;
         case ZCFG_16x128: *bm = 16; *bn = 128; break;
         case ZCFG_32x32: *bm = 32; *bn = 32; break;
@@ -686,6 +781,14 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
             if (tA) k_zred<true, 8, 4><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
             else k_zred<false, 8, 4><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
         }
+        return hipGetLastError();
+    }
+    if (cfg == ZCFG_DOT) {
+        if (tA || !tB || max_m < 1 || max_m > ZDOT_MAX_M) return hipErrorInvalidValue;
+        dim3 grid(ntiles), block(kThreads);
+        if (max_m <= 2) k_zdot<2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else if (max_m <= 4) k_zdot<4><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zdot<8><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
         return hipGetLastError();
     }
     if (cfg == ZCFG_SKINNY) {

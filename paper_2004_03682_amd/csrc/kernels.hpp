@@ -26,13 +26,17 @@ struct ZTile {
 // ZCFG_RED: one workgroup per K chunk of a problem with M <= ZRED_MAX_M and
 // 1 <= N <= ZRED_MAX_N, !tB, on the vector ALUs; always split along K into
 // chunks of at most ZRED_LDS / M.
+// ZCFG_DOT: one workgroup per ZDOT_ROWS rows of B of a problem with
+// M <= ZDOT_MAX_M, !tA, tB (every output a dot product of two contiguous
+// K-vectors), on the vector ALUs; each B row is streamed once; never split.
 enum ZCfg {
     ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_SKINNY, ZCFG_TALL, ZCFG_RED,
-    ZCFG_32x64, ZCFG_64x32, ZCFG_N
+    ZCFG_32x64, ZCFG_64x32, ZCFG_DOT, ZCFG_N
 };
 constexpr int ZSKINNY_BM = 64, ZSKINNY_BN = 32, ZSKINNY_MAX_MN = ZSKINNY_BM * ZSKINNY_BN;
 constexpr int ZTALL_ROWS = 256, ZTALL_MAX_K = 64, ZTALL_MAX_KN = 1024;
 constexpr int ZRED_MAX_M = 8, ZRED_MAX_N = 256, ZRED_LDS = 2048;   // LDS: A chunk of M * K <= ZRED_LDS
+constexpr int ZDOT_MAX_M = 8, ZDOT_ROWS = 16, ZDOT_KC = 256;       // LDS: A chunk of M * ZDOT_KC
 void zcfg_tile(int cfg, int* bm, int* bn);
 
 // C(m,n) = alpha * sum_k opA(m,k) opB(k,n) + beta*C(m,n)  for every tile in `tiles`
@@ -41,7 +45,7 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 //   cA/cB conjugate the operand; beta is 0 (overwrite) or 1 (accumulate).
 //   bk = 16 or 32 (K depth of one LDS stage); role only selects a distinct kernel symbol.
 //   active (may be null): tiles whose active[tile.sys] == 0 are skipped.
-//   max_m: largest M of the problems (used by ZCFG_RED only, 1..ZRED_MAX_M).
+//   max_m: largest M of the problems (used by ZCFG_RED and ZCFG_DOT only, 1..8).
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                         int cB, hipStream_t st, int role = 0, const int* active = nullptr, int max_m = 0);

@@ -1,6 +1,6 @@
 """Kernel-level parity of the grouped complex FP64 GEMM forms (through the C
 ABI) against numpy: every MFMA tile shape, K depth, transpose/conjugate flag
-and split-K choice, the vector-ALU skinny, tall and reduction forms, with
+and split-K choice, the vector-ALU skinny, tall, reduction and dot forms, with
 ragged sizes (not multiples of any tile), K = 0 and accumulation (beta = 1)."""
 import itertools
 
@@ -57,7 +57,7 @@ def test_zgemm_split_k_and_edges(cfg):
         assert err < 1e-13, (cfg, M, N, K, beta, err)
 
 
-TALL, RED = 7, 8
+TALL, RED, DOT = 7, 8, 11
 
 
 @pytest.mark.parametrize("tB,cA,cB", [(0, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1)])
@@ -82,8 +82,20 @@ def test_zgemm_reduction_form(tA, cA, cB):
                 assert err < 1e-13, (tA, cA, cB, M, N, K, split, beta, err)
 
 
+@pytest.mark.parametrize("cA,cB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_zgemm_dot_form(cA, cB):
+    # few rows of A against many contiguous rows of B (the ladder over active pairs);
+    # M <= 8 (register tiles 2, 4, 8), ragged N (16 rows per workgroup) and K (256 per LDS chunk)
+    for (M, N, K) in [(1, 1, 1), (1, 17, 255), (2, 33, 257), (3, 2801, 2800), (4, 100, 1000), (5, 16, 513),
+                      (8, 129, 64), (7, 5, 0)]:
+        for beta in (0, 1):
+            err = _run(M, N, K, 0, 1, cA, cB, DOT, 16, False, beta, seed=M + 3 * N + K)
+            assert err < 1e-13, (cA, cB, M, N, K, beta, err)
+
+
 def test_vector_forms_reject_shapes_they_do_not_fit():
     for (cfg, tA, tB, M, N, K) in [(TALL, 1, 0, 10, 3, 5), (TALL, 0, 0, 10, 3, 65), (TALL, 0, 1, 10, 40, 30),
-                                   (RED, 0, 1, 3, 3, 100), (RED, 0, 0, 9, 3, 100), (RED, 1, 0, 3, 257, 100)]:
+                                   (RED, 0, 1, 3, 3, 100), (RED, 0, 0, 9, 3, 100), (RED, 1, 0, 3, 257, 100),
+                                   (DOT, 0, 0, 3, 3, 100), (DOT, 1, 1, 3, 3, 100), (DOT, 0, 1, 9, 3, 100)]:
         with pytest.raises(Exception):
             _run(M, N, K, tA, tB, 0, 0, cfg, 16, True, 0)
