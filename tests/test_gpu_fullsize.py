@@ -1,8 +1,10 @@
 """GPU parity at the production size (nocc = 40, nvirt = 300, 16 irreps with
 uneven blocks), in the launch configuration the benchmark times (autotuned
 GEMM forms): the (0h,0p) residual at the MP2 amplitudes plus a small T1,
-every element against the block-list oracle (1e-12 of max|R|), and the
-first Jacobi step's energy against the closed-form MP2 energy.
+every element against the block-list oracle (1e-12 of max|R| in FP64; 2^-16
+of max|R| for the split-BF16 and split-FP32 forms of the mixed-precision
+workload), and the first Jacobi step's energy against the closed-form MP2
+energy.
 
 The oracle half of this test takes about a minute of host time."""
 import sys
@@ -56,6 +58,13 @@ def test_cfg2_residual_matches_blocked_oracle():
     ctx.build_residual(t1, t2, r1, r2)
     torch.cuda.synchronize()
     g1, g2 = LR.unpack_t1(s, r1.cpu().numpy()), LR.unpack_t2(s, r2.cpu().numpy())
+    split = {}
+    for prec in ("split_bf16", "split_fp32"):
+        ctx.set_precision(prec)
+        ctx.build_residual(t1, t2, r1, r2)
+        torch.cuda.synchronize()
+        split[prec] = (r1.cpu().numpy(), r2.cpu().numpy())
+    ctx.set_precision("fp64")
     h1, h2 = LR.unpack_t1(s, t1.cpu().numpy()), LR.unpack_t2(s, t2.cpu().numpy())
     ctx.destroy()
     bt1 = BlockTensor.from_dense(h1, [be.mem["O"], be.mem["V"]], list(be.D1.blocks.keys()))
@@ -66,8 +75,13 @@ def test_cfg2_residual_matches_blocked_oracle():
     R1 = be.dense(R1)
     scale = np.abs(g2).max()
     assert np.abs(g1 - R1).max() <= 1e-12 * scale
-    del g1, R1
     R2 = be.dense(R2)
     err = float(np.abs(g2 - R2).max())
     _log(f"cfg2 residual: max|dR| = {err:.2e}, max|R| = {scale:.2e}")
     assert err <= 1e-12 * scale
+    del g2
+    for prec, (q1, q2) in split.items():
+        e1 = float(np.abs(LR.unpack_t1(s, q1) - R1).max()) / scale
+        e2 = float(np.abs(LR.unpack_t2(s, q2) - R2).max()) / scale
+        _log(f"cfg2 residual {prec}: max|dR| / max|R| = {e1:.2e} (T1), {e2:.2e} (T2)")
+        assert e1 <= 2.0 ** -16 and e2 <= 2.0 ** -16
