@@ -125,3 +125,25 @@ def test_shifted_solves_extrapolate_to_plain_solution():
     for k in range(ys.shape[1]):
         e0 = shift.pade(lam, ys[:, k], 3, 0, 0.0)
         assert abs(e0 - plain["eig"][k]) < 0.1 * abs(ys[0, k] - plain["eig"][k])
+
+
+def test_s02_layout_round_trip():
+    """The packed (0h,2p) layout of the tests' layout helper: every active pair once per pair
+    irrep, antisymmetric amplitudes survive pack/unpack, forbidden elements are dropped."""
+    import layout_ref as LR
+    s = fsgen.make_system(3, 9, 3, 0.1, 4, nact=4)
+    n = len(s.active)
+    pairs = sum(len(LR.xy_pair_list(s, G)[0]) for G in range(s.nirrep))
+    assert pairs == n * (n - 1) // 2
+    rng = np.random.default_rng(0)
+    g = s.irrep[s.nocc:]
+    ga = s.irrep[np.sort(s.active)]
+    x = _rand(rng, (pairs, s.nvirt, s.nvirt))
+    x = x - x.transpose(0, 2, 1)
+    allowed = np.zeros_like(x, dtype=bool)
+    for i in range(n):
+        for j in range(i + 1, n):
+            p = LR.pair_index(n, i, j)
+            allowed[p] = ((ga[i] + ga[j] - g[:, None] - g[None, :]) % s.nirrep == 0)
+    y = LR.unpack_s02(s, LR.pack_s02(s, x))
+    assert np.array_equal(y, np.where(allowed, x, 0))
