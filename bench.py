@@ -158,7 +158,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
         lad = ops["pp-ladder"]
         lad_ms = lad["ms"] / max(1, lad["calls"])
         split_ops = {}
-        for n in ("pp-ladder", "W.U", "ring"):
+        for n in cfgs:                      # the operations that run split in this mode
             o = ops[n]
             ms = o["ms"] / max(1, o["calls"])
             split_ops[n] = {"ms_per_call": round(ms, 4),

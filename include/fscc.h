@@ -313,10 +313,11 @@ fscc_status fscc_dynamic_shift(fscc_ctx *ctx, fscc_sector sector, double S, int 
  * result. */
 fscc_status fscc_pade(int npts, const double *x, const fscc_c128 *y, int L, int M, double x0, fscc_c128 *out);
 
-/* Arithmetic of the three dominant (0h,0p) contractions: the particle-
- * particle ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets
- * (the T2 part of W_mbej and sum_me t_im^ae W_mbej), which together carry
- * most of the flops of an iteration.  Every other step -- the remaining contractions, the reorders,
+/* Arithmetic of the dominant (0h,0p) contractions: the particle-particle
+ * ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets (the T2
+ * part of W_mbej and sum_me t_im^ae W_mbej), which together carry most of
+ * the flops of an iteration, and in FSCC_SPLIT_BF16 also the ladder's T1 part
+ * Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef.  Every other step -- the remaining contractions, the reorders,
  * the denominator (Jacobi) update, the DIIS subspace solve and the energy --
  * stays FP64 in every mode.
  *   FSCC_FP64        complex FP64 on the FP64 matrix cores.

@@ -115,10 +115,14 @@ void free_gemm(GemmDev& g) {
     g = GemmDev();
 }
 
-// The contractions that may run in split precision: the particle-particle
-// ladder and the two ring GEMM sets (W_mbej's T2 part and the ring itself).
-bool mixed_eligible(const Op& o) {
-    return o.kind == OP_GEMM && (o.name == "pp-ladder" || o.name == "W.U" || o.name == "ring");
+// The contractions that run in split precision: the particle-particle ladder
+// and the two ring GEMM sets (W_mbej's T2 part and the ring itself); in the
+// bf16 form also the ladder's T1 part Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef
+// (its split-FP32 form is slower than FP64).
+bool mixed_eligible(const Op& o, int prec) {
+    if (o.kind != OP_GEMM) return false;
+    if (o.name == "Z") return prec == FSCC_SPLIT_BF16;
+    return o.name == "pp-ladder" || o.name == "W.U" || o.name == "ring";
 }
 
 long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
@@ -206,7 +210,7 @@ void apply_precision(fscc_ctx* c, int prec) {
     if (prec != FSCC_FP64) {
         std::vector<Op>& ops = *c->L00.ops;
         for (size_t k = 0; k < ops.size(); ++k) {
-            if (!mixed_eligible(ops[k])) continue;
+            if (!mixed_eligible(ops[k], prec)) continue;
             GemmDev& g = c->L00.g[k];
             if (g.mx && g.mx->prec == prec) continue;
             fscc_ctx::free_mixed(g.mx);
@@ -1095,7 +1099,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             for (size_t k = 0; k < ctx->L00.ops->size(); ++k) {
                 const Op& o = (*ctx->L00.ops)[k];
                 GemmDev& g = ctx->L00.g[k];
-                if (!mixed_eligible(o) || !g.mx) continue;
+                if (!mixed_eligible(o, ctx->prec) || !g.mx) continue;
                 float best_ms = time_op(o, &g);
                 for (int cfg = 0; cfg < MCFG_N; ++cfg) {
                     if (cfg == g.mx->cfg) continue;

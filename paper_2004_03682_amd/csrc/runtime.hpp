@@ -503,7 +503,7 @@ double cfg_cost(const Op& o, int cfg);
 int pick_cfg(const Op& o, bool real = false);
 std::vector<ZTile> xcd_order(const std::vector<ZTile>& logical);
 void free_gemm(GemmDev& g);
-bool mixed_eligible(const Op& o);
+bool mixed_eligible(const Op& o, int prec);
 MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg);
 int pick_mcfg(const Op& o);
 void apply_precision(fscc_ctx* c, int prec);
