@@ -256,11 +256,14 @@ def out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log, staging=512 << 
     return rec
 
 
-def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log):
+def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sectors=None):
     """The cfg2 shape as a real double group (the same seed's integrals made
     real): the real-arithmetic context's s/iteration, its GEMM rate and
-    iterations to convergence, against the complex iteration."""
-    s = fsgen.make_system(cfg["nocc"], cfg["nvirt"], cfg["nirrep"], cfg["sigma"], cfg["seed"], real=True)
+    iterations to convergence, against the complex iteration; then one
+    dynamically shifted (0h,1p) and (0h,2p) solve each (S = -3 Eh, n = 3) with
+    ms per iteration against the complex sectors' ms per iteration."""
+    s = fsgen.make_system(cfg["nocc"], cfg["nvirt"], cfg["nirrep"], cfg["sigma"], cfg["seed"], nact=cfg["nact"],
+                          real=True)
     ctx = F.Context.from_system(s, precision="real_fp64")
     for C in fsgen.CLASSES:
         buf, _ = fsgen.class_buffer(s, C)
@@ -313,6 +316,39 @@ def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log):
            "workload": "cfg2 shape, real integrals (sqrt(2) Re of seed 1002's), real-arithmetic context"}
     log(f"real: {per_it * 1e3:.3f} ms/iteration ({complex_s_per_iter / per_it:.2f}x the complex iteration), "
         f"ladder {lad_ms:.3f} ms, converged {g['converged']} in {g['iters']} iterations ({solve_s:.3f}s)")
+    if s.nact >= 2 and g["converged"]:
+        try:
+            ctx.prepare_sector(t1, t2)
+            s1 = torch.zeros(ctx.m1, dtype=torch.float64, device="cuda")
+            s2 = torch.zeros(ctx.m2, dtype=torch.float64, device="cuda")
+            ctx.dynamic_shift(-3.0, 3, F.FSCC_S01)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            o1 = F.solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=8)
+            torch.cuda.synchronize()
+            e1 = time.perf_counter() - ts
+            ctx.prepare_sector(s1, s2, F.FSCC_S02)
+            sp = torch.zeros(ctx.p2, dtype=torch.float64, device="cuda")
+            ctx.dynamic_shift(-3.0, 3, F.FSCC_S02)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            o2 = F.solve02(ctx, sp, tol=1e-10, maxit=200, ndiis=8)
+            torch.cuda.synchronize()
+            e2 = time.perf_counter() - ts
+            sec = {"shift": [-3.0, 3],
+                   "fs01": {"converged": o1["converged"], "iterations": o1["iters"],
+                            "ms_per_iteration": round(e1 / max(1, o1["iters"]) * 1e3, 4)},
+                   "fs02": {"converged": o2["converged"], "iterations": o2["iters"],
+                            "ms_per_iteration": round(e2 / max(1, o2["iters"]) * 1e3, 4)}}
+            for k in ("fs01", "fs02"):
+                c = (complex_sectors or {}).get(k)
+                if c:
+                    sec[k]["complex_ms_per_iteration"] = c
+                    sec[k]["speedup_vs_complex"] = round(c / sec[k]["ms_per_iteration"], 3)
+            rec["sectors"] = sec
+            log(f"real sectors: (0h,1p) {sec['fs01']}, (0h,2p) {sec['fs02']}")
+        except F.FsccError as e:
+            rec["sectors"] = {"status": f"failed ({e})"}
     ctx.destroy()
     torch.cuda.empty_cache()
     return rec
@@ -774,7 +810,12 @@ def main():
     del t1, t2, r1, r2
     torch.cuda.empty_cache()
     if not args.no_real:
-        result["real_arithmetic"] = real_study(F, torch, fsgen, cfg, s_per_iter, args, log)
+        cs = {}
+        if "fs01" in result and isinstance(result["fs01"].get("dynamic_shift"), dict):
+            cs["fs01"] = result["fs01"]["dynamic_shift"].get("ms_per_iteration")
+        if "fs02" in result:
+            cs["fs02"] = result["fs02"].get("ms_per_iteration")
+        result["real_arithmetic"] = real_study(F, torch, fsgen, cfg, s_per_iter, args, log, cs)
     if not args.no_batch:
         result["batch"] = batch_study(F, torch, fsgen, args, log)
     if not args.no_cpu:

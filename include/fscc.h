@@ -94,11 +94,12 @@ typedef enum {
 } fscc_status;
 
 /* Arithmetic of a context.  FSCC_REAL_FP64 (fscc_create only): real double
- * groups -- integrals, amplitudes and residuals are real, every buffer the
- * caller passes holds DOUBLES (8 bytes per element, the same layouts and
+ * groups -- integrals, amplitudes and residuals are real, every device buffer
+ * the caller passes holds DOUBLES (8 bytes per element, the same layouts and
  * element counts as the complex form), the fscc_c128 pointer types of the
- * calls are reinterpreted accordingly and fscc_energy returns e_im = 0; the
- * (0h,0p) sector only (nact must be 0), no split precision. */
+ * calls are reinterpreted accordingly, fscc_energy returns e_im = 0 and the
+ * host matrices of fscc_heff / fscc_heff2 stay complex with zero imaginary
+ * parts; all three sectors, no split precision. */
 typedef enum { FSCC_FP64 = 0, FSCC_SPLIT_FP32 = 1, FSCC_SPLIT_BF16 = 2, FSCC_REAL_FP64 = 3 } fscc_precision;
 
 typedef enum { FSCC_S00 = 0, FSCC_S01 = 1, FSCC_S02 = 2 } fscc_sector; /* (0h,0p), (0h,1p), (0h,2p) */

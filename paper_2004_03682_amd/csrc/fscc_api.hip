@@ -386,10 +386,18 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     up_real(P.b_mask1, P.mask1);
     up_real(P.b_D02, P.D02);
     up_real(P.b_mask02, P.mask02);
-    for (auto& hc : P.const_host)
-        if (!hc.data.empty())
+    for (auto& hc : P.const_host) {
+        if (hc.data.empty()) continue;
+        if (c->real) {   // these constants are real (unit entries, orbital energies)
+            std::vector<double> re(hc.data.size());
+            for (size_t k = 0; k < re.size(); ++k) re[k] = hc.data[k].real();
+            hip_check(hipMemcpy(c->dbuf[hc.buf], re.data(), re.size() * sizeof(double), hipMemcpyHostToDevice),
+                      "const upload");
+        } else {
             hip_check(hipMemcpy(c->dbuf[hc.buf], hc.data.data(), hc.data.size() * sizeof(double2),
                                 hipMemcpyHostToDevice), "const upload");
+        }
+    }
     // maps of the per-iteration gathers (setup maps are uploaded at set_integrals)
     c->dmap.assign(P.maps.size(), nullptr);
     std::vector<char> is_setup(P.maps.size(), 0);
@@ -495,7 +503,6 @@ fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_s
         return FSCC_EINVAL;
     if (sys->nocc < 0 || sys->nvirt < 0 || sys->nirrep < 1 || !sys->irrep || !sys->eps) return FSCC_EINVAL;
     if (sys->nact < 0 || (sys->nact > 0 && !sys->active)) return FSCC_EINVAL;
-    if (prec == FSCC_REAL_FP64 && sys->nact > 0) return FSCC_EINVAL;   // (0h,0p) only in real arithmetic
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
     if (!c) return FSCC_ENOMEM;
     fscc_status s = guarded(c, [&]() -> fscc_status {
@@ -660,6 +667,25 @@ fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
     });
 }
 
+// Copy n elements of device buffer b to the host as complex values (a real
+// context's buffers hold doubles: imaginary parts 0).  Synchronises.
+static std::vector<double2> read_elements(fscc_ctx* ctx, int b, int64_t n) {
+    std::vector<double2> h((size_t)n);
+    if (n == 0) return h;
+    if (ctx->real) {
+        std::vector<double> d((size_t)n);
+        hip_check(hipMemcpyAsync(d.data(), ctx->dbuf[b], d.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->st),
+                  "d2h");
+        hip_check(hipStreamSynchronize(ctx->st), "d2h sync");
+        for (size_t k = 0; k < d.size(); ++k) h[k] = make_double2(d[k], 0.0);
+    } else {
+        hip_check(hipMemcpyAsync(h.data(), ctx->dbuf[b], h.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->st),
+                  "d2h");
+        hip_check(hipStreamSynchronize(ctx->st), "d2h sync");
+    }
+    return h;
+}
+
 fscc_status fscc_heff(fscc_ctx* ctx, const fscc_c128* s1, const fscc_c128* s2, fscc_c128* heff_host) {
     if (!ctx || !heff_host) return FSCC_EINVAL;
     Plan& P = ctx->plan;
@@ -667,13 +693,13 @@ fscc_status fscc_heff(fscc_ctx* ctx, const fscc_c128* s1, const fscc_c128* s2, f
     if (!ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
     if ((P.L_S1.total && !s1) || (P.L_S2.total && !s2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
     return guarded(ctx, [&]() -> fscc_status {
-        bind_io01(ctx, s1, s2, (fscc_c128*)ctx->rs_tmp, (fscc_c128*)(ctx->rs_tmp + P.L_S1.total));
+        // residual scratch: complex elements, or doubles at the same offsets in a real context
+        fscc_c128* rs1 = (fscc_c128*)ctx->rs_tmp;
+        fscc_c128* rs2 = ctx->real ? (fscc_c128*)((double*)ctx->rs_tmp + P.L_S1.total)
+                                   : (fscc_c128*)(ctx->rs_tmp + P.L_S1.total);
+        bind_io01(ctx, s1, s2, rs1, rs2);
         ctx->run_list(ctx->L01, false);
-        std::vector<double2> h(P.L_Heff.total);
-        if (!h.empty())
-            hip_check(hipMemcpyAsync(h.data(), ctx->B(P.b_heff), h.size() * sizeof(double2), hipMemcpyDeviceToHost,
-                                     ctx->st), "heff d2h");
-        hip_check(hipStreamSynchronize(ctx->st), "heff sync");
+        std::vector<double2> h = read_elements(ctx, P.b_heff, P.L_Heff.total);
         const int nact = P.X.n;
         for (int k = 0; k < nact * nact; ++k) heff_host[k] = fscc_c128{0.0, 0.0};
         // block-diagonal [g][y_g][x_g] in irrep-sorted active order -> dense [y][x] in the caller's order
@@ -700,11 +726,7 @@ fscc_status fscc_heff2(fscc_ctx* ctx, const fscc_c128* s, fscc_c128* heff_host) 
     return guarded(ctx, [&]() -> fscc_status {
         bind_io02(ctx, s, (fscc_c128*)ctx->rs_tmp);
         ctx->run_list(ctx->L02, false);
-        std::vector<double2> h(P.L_Heff02.total);
-        if (!h.empty())
-            hip_check(hipMemcpyAsync(h.data(), ctx->B(P.b_heff02), h.size() * sizeof(double2), hipMemcpyDeviceToHost,
-                                     ctx->st), "heff d2h");
-        hip_check(hipStreamSynchronize(ctx->st), "heff sync");
+        std::vector<double2> h = read_elements(ctx, P.b_heff02, P.L_Heff02.total);
         // [G][zw<][xy<] over irrep-sorted active pairs -> dense [pair(zw)][pair(xy)] over the pairs
         // i < j of the caller's active list (row-major upper triangle); a pair whose irrep-sorted
         // order is the reverse of the caller's order contributes with a minus sign
@@ -738,14 +760,8 @@ fscc_status fscc_precondition(fscc_ctx* ctx, fscc_sector sector, int mode, doubl
     return guarded(ctx, [&]() -> fscc_status {
         std::vector<double> d1 = P.D1x, d2 = P.D2x;
         if (mode == 1) {
-            std::vector<double2> fv(P.bufs[P.b_Fvv01].n), fo(P.bufs[P.b_Foo01].n);
-            if (!fv.empty())
-                hip_check(hipMemcpyAsync(fv.data(), ctx->B(P.b_Fvv01), fv.size() * sizeof(double2),
-                                         hipMemcpyDeviceToHost, ctx->st), "Fbar d2h");
-            if (!fo.empty())
-                hip_check(hipMemcpyAsync(fo.data(), ctx->B(P.b_Foo01), fo.size() * sizeof(double2),
-                                         hipMemcpyDeviceToHost, ctx->st), "Fbar d2h");
-            hip_check(hipStreamSynchronize(ctx->st), "precondition sync");
+            std::vector<double2> fv = read_elements(ctx, P.b_Fvv01, P.bufs[P.b_Fvv01].n);
+            std::vector<double2> fo = read_elements(ctx, P.b_Foo01, P.bufs[P.b_Foo01].n);
             auto fvd = [&](int p) { return fv[(size_t)P.fvv_diag[p]].x; };
             auto fod = [&](int i) { return fo[(size_t)P.foo_diag[i]].x; };
             P.L_S1.for_each([&](int64_t k, const int* p) {

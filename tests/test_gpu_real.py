@@ -7,7 +7,10 @@ reduction), transposes, split-K, ragged sizes, K = 0, beta = 1, within 1e-13
 relative of numpy.  Residual per call within 1e-12 * max|R| of the oracle
 (whose imaginary parts are exactly zero on real inputs); converged energy
 within 1e-10 Eh of the oracle and of the complex context; first update =
-closed-form MP2; the ladder alone = the MP3 ladder closed form.
+closed-form MP2; the ladder alone = the MP3 ladder closed form.  The
+(0h,1p) and (0h,2p) sectors in real arithmetic: residuals and H_eff within
+1e-12 of the oracle, converged sector energies within 1e-10 Eh of the oracle
+and of the complex context.
 """
 import itertools
 
@@ -16,7 +19,7 @@ import pytest
 
 import fsgen
 import layout_ref as LR
-from oracle import ccsd, solver
+from oracle import ccsd, fs01, fs02, solver
 
 pytestmark = pytest.mark.gpu
 
@@ -161,12 +164,93 @@ def test_real_converged_energy_matches_oracle_and_complex_path():
     ctx.destroy()
 
 
+def _rdev(x):
+    import torch
+    assert not np.any(np.imag(x)), "real system amplitudes"
+    return torch.from_numpy(np.ascontiguousarray(np.real(x))).cuda()
+
+
+@pytest.mark.parametrize("spec", [(6, 14, 4, 0.1, 21, 4), (7, 19, 3, 0.05, 8, 5)])
+def test_real_sectors_residuals_match_oracle(spec):
+    import torch
+    import paper_2004_03682_amd as F
+    no, nv, ni, sg, seed, nact = spec
+    print("case real sectors", spec, flush=True)
+    s = fsgen.make_system(no, nv, ni, sg, seed, nact=nact, real=True)
+    be = ccsd.Dense(s)
+    r = solver.solve_ccsd(be, tol=1e-12)
+    ctx = _real_ctx(s)
+    ctx.prepare_sector(_rdev(LR.pack_t1(s, r["t1"])), _rdev(LR.pack_t2(s, r["t2"])))
+    F1 = fs01.FS01(be, r["t1"], r["t2"], s.active)
+    rng = np.random.default_rng(seed)
+    s1, s2 = F1.zeros()
+    s1 = np.where(F1.mask1, 0.05 * rng.normal(size=s1.shape), 0) + 0j
+    x2 = 0.05 * rng.normal(size=s2.shape)
+    s2 = np.where(F1.mask2, x2 - x2.transpose(0, 1, 3, 2), 0) + 0j
+    R1, R2, heff = F1.residual(s1, s2)
+    assert np.abs(R2.imag).max() == 0.0 and np.abs(heff.imag).max() == 0.0
+    d1, d2 = _rdev(LR.pack_s1(s, s1)), _rdev(LR.pack_s2(s, s2))
+    o1, o2 = torch.empty_like(d1), torch.empty_like(d2)
+    ctx.build_residual(d1, d2, o1, o2, sector=F.FSCC_S01)
+    scale = max(np.abs(R2).max(), np.abs(R1).max())
+    assert np.abs(LR.unpack_s1(s, o1.cpu().numpy() + 0j) - R1).max() <= 1e-12 * scale
+    assert np.abs(LR.unpack_s2(s, o2.cpu().numpy() + 0j) - R2).max() <= 1e-12 * scale
+    assert np.abs(ctx.heff(d1, d2) - heff).max() <= 1e-12 * max(1.0, np.abs(heff).max())
+    # (0h,2p) on top of these (0h,1p) amplitudes
+    ctx.prepare_sector(d1, d2, sector=F.FSCC_S02)
+    F2 = fs02.FS02(F1, s1, s2)
+    x = 0.05 * rng.normal(size=(F2.npair, nv, nv))
+    sp = np.where(F2.mask, x - x.transpose(0, 2, 1), 0) + 0j
+    R, h2 = F2.residual(sp)
+    d = _rdev(LR.pack_s02(s, sp))
+    o = torch.empty_like(d)
+    ctx.build_residual(None, d, None, o, sector=F.FSCC_S02)
+    scale = max(1.0, np.abs(R).max())
+    assert np.abs(LR.unpack_s02(s, o.cpu().numpy() + 0j) - R).max() <= 1e-12 * scale
+    assert np.abs(ctx.heff2(d) - h2).max() <= 1e-12 * max(1.0, np.abs(h2).max())
+    ctx.destroy()
+
+
+def test_real_sectors_converged_match_complex_context():
+    """(0h,0p) -> (0h,1p) -> (0h,2p) solved in a real context and in a complex context
+    on the same real integrals: the same sector energies (1e-10 Eh), and the oracle's."""
+    import torch
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(3, 6, 2, 0.1, 5, nact=3, real=True)
+    out = {}
+    for prec in ("real_fp64", "fp64"):
+        ctx = _real_ctx(s) if prec == "real_fp64" else F.Context.from_system(s)
+        if prec == "fp64":
+            for C in fsgen.CLASSES:
+                ctx.set_integrals(C, torch.from_numpy(fsgen.class_buffer(s, C)[0]).cuda())
+        dt = torch.float64 if prec == "real_fp64" else torch.complex128
+        t1 = torch.zeros(ctx.n1, dtype=dt, device="cuda")
+        t2 = torch.zeros(ctx.n2, dtype=dt, device="cuda")
+        assert F.solve(ctx, t1, t2, tol=1e-11)["converged"]
+        ctx.prepare_sector(t1, t2)
+        s1 = torch.zeros(ctx.m1, dtype=dt, device="cuda")
+        s2 = torch.zeros(ctx.m2, dtype=dt, device="cuda")
+        g1 = F.solve01(ctx, s1, s2, tol=1e-11)
+        ctx.prepare_sector(s1, s2, sector=F.FSCC_S02)
+        sp = torch.zeros(ctx.p2, dtype=dt, device="cuda")
+        g2 = F.solve02(ctx, sp, tol=1e-11)
+        assert g1["converged"] and g2["converged"]
+        out[prec] = (g1["eig"], g2["eig"])
+        ctx.destroy()
+    for k in range(2):
+        assert np.abs(out["real_fp64"][k] - out["fp64"][k]).max() <= 1e-10
+    be = ccsd.Dense(s)
+    r = solver.solve_ccsd(be, tol=1e-11)
+    F1 = fs01.FS01(be, r["t1"], r["t2"], s.active)
+    o1 = fs01.solve_fs01(F1, tol=1e-11)
+    o2 = fs02.solve_fs02(fs02.FS02(F1, o1["s1"], o1["s2"]), tol=1e-11)
+    assert np.abs(out["real_fp64"][0] - o1["eig"]).max() <= 1e-10
+    assert np.abs(out["real_fp64"][1] - o2["eig"]).max() <= 1e-10
+
+
 def test_real_context_rejects_what_it_does_not_do():
     import torch
     import paper_2004_03682_amd as F
-    s = fsgen.make_system(3, 8, 2, 0.05, 2, nact=2, real=True)
-    with pytest.raises(F.FsccError):
-        F.Context.from_system(s, precision="real_fp64")        # (0h,1p) sector: complex only
     s = fsgen.make_system(3, 8, 2, 0.05, 2, real=True)
     ctx = _real_ctx(s)
     assert ctx.precision() == "real_fp64"
