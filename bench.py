@@ -85,7 +85,7 @@ def cpu_baseline(sysm, buffers):
     del R1, R2, t1n, t2n
     return dict(value=round(dt, 3), unit="s/iteration", cores=int(cores), kind="oracle",
                 sample="one full oracle iteration (block-list residual + Jacobi step + energy) of the same "
-                       "cfg2 system at the MP2 amplitudes; DIIS bookkeeping excluded; setup %.1fs excluded" % setup,
+                       "nocc=40 nvirt=300 Z16 system at the MP2 amplitudes; DIIS bookkeeping excluded; setup %.1fs excluded" % setup,
                 energy_re=float(E.real))
 
 
@@ -203,7 +203,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
 
 
 def out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log, staging=512 << 20):
-    """The cfg2 iteration with the packed VVVV integrals in pinned host memory,
+    """The production-size iteration with the packed VVVV integrals in pinned host memory,
     streamed through 2 x 256 MB staging buffers: ladder time and whole
     iteration against the in-memory ones, and the host-to-device copy rate
     the ladder sustains against a plain pinned copy."""
@@ -257,7 +257,7 @@ def out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log, staging=512 << 
 
 
 def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sectors=None):
-    """The cfg2 shape as a real double group (the same seed's integrals made
+    """The production shape as a real double group (the same seed's integrals made
     real): the real-arithmetic context's s/iteration, its GEMM rate and
     iterations to convergence, against the complex iteration; then one
     dynamically shifted (0h,1p) and (0h,2p) solve each (S = -3 Eh, n = 3) with
@@ -313,7 +313,7 @@ def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sect
            "pp_ladder_tflops": round(lad["flops"] / 4.0 / (lad_ms * 1e-3) / 1e12, 3),
            "converged": g["converged"], "iterations": g["iters"], "iterations_to_1e-8": k8,
            "seconds_to_converged": round(solve_s, 4), "energy": E.real,
-           "workload": "cfg2 shape, real integrals (sqrt(2) Re of seed 1002's), real-arithmetic context"}
+           "workload": "nocc=40 nvirt=300 Z16 shape, real integrals (sqrt(2) Re of seed 1002's), real-arithmetic context"}
     log(f"real: {per_it * 1e3:.3f} ms/iteration ({complex_s_per_iter / per_it:.2f}x the complex iteration), "
         f"ladder {lad_ms:.3f} ms, converged {g['converged']} in {g['iters']} iterations ({solve_s:.3f}s)")
     if s.nact >= 2 and g["converged"]:
@@ -612,8 +612,8 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": 1 << 30, "copy_bytes_written_per_launch": 1 << 30}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the hot path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(no multi-GPU sharding is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -624,8 +624,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = fsgen.CONFIGS[2]
-    s = fsgen.config_system(2)
+    cfg = fsgen.WORKLOADS["o40v300z16"]
+    s = fsgen.workload_system("o40v300z16")
     t0 = time.perf_counter()
     buffers = {}
     for C in fsgen.CLASSES:

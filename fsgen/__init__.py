@@ -138,16 +138,18 @@ def make_system(nocc: int, nvirt: int, nirrep: int, sigma: float, seed: int, nac
     return System(nocc, nvirt, nirrep, float(sigma), int(seed), irrep, eps, nact, active, bool(real))
 
 
-# Workload configurations (sizes of the paper-shaped synthetic systems).
-CONFIGS = {
-    0: dict(nocc=8, nvirt=24, nirrep=1, sigma=0.05, seed=1000),
-    1: dict(nocc=20, nvirt=120, nirrep=8, sigma=0.05, seed=1001),
-    2: dict(nocc=40, nvirt=300, nirrep=16, sigma=0.03, seed=1002, nact=6),
+# The paper-shaped synthetic workloads, named by their sizes: a single-irrep
+# system, a symmetry-blocked one (Z8) and the production size (Z16, six active
+# virtual spinors for the (0h,1p) and (0h,2p) sectors).
+WORKLOADS = {
+    "o8v24": dict(nocc=8, nvirt=24, nirrep=1, sigma=0.05, seed=1000),
+    "o20v120z8": dict(nocc=20, nvirt=120, nirrep=8, sigma=0.05, seed=1001),
+    "o40v300z16": dict(nocc=40, nvirt=300, nirrep=16, sigma=0.03, seed=1002, nact=6),
 }
 
 
-def config_system(k: int) -> System:
-    return make_system(**CONFIGS[k])
+def workload_system(name: str) -> System:
+    return make_system(**WORKLOADS[name])
 
 
 def batch_systems(count: int, seed0: int) -> list:

@@ -26,11 +26,11 @@ def _log(msg):
 
 
 @pytest.mark.timeout(900)
-def test_cfg2_residual_matches_blocked_oracle():
+def test_production_size_residual_matches_blocked_oracle():
     import torch
     import paper_2004_03682_amd as F
     t0 = time.perf_counter()
-    s = fsgen.config_system(2)
+    s = fsgen.workload_system("o40v300z16")
     buffers = {C: fsgen.class_buffer(s, C)[0] for C in fsgen.CLASSES}
     ctx = F.Context.from_system(s)
     for C in fsgen.CLASSES:
@@ -38,7 +38,7 @@ def test_cfg2_residual_matches_blocked_oracle():
         ctx.set_integrals(C, d)
         del d
     ctx.autotune(1)
-    _log(f"cfg2 context ready at {time.perf_counter() - t0:.1f}s")
+    _log(f"production-size context ready at {time.perf_counter() - t0:.1f}s")
     # first Jacobi step from zero amplitudes: t2 = MP2 amplitudes, t1 = 0
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
@@ -77,11 +77,11 @@ def test_cfg2_residual_matches_blocked_oracle():
     assert np.abs(g1 - R1).max() <= 1e-12 * scale
     R2 = be.dense(R2)
     err = float(np.abs(g2 - R2).max())
-    _log(f"cfg2 residual: max|dR| = {err:.2e}, max|R| = {scale:.2e}")
+    _log(f"production-size residual: max|dR| = {err:.2e}, max|R| = {scale:.2e}")
     assert err <= 1e-12 * scale
     del g2
     for prec, (q1, q2) in split.items():
         e1 = float(np.abs(LR.unpack_t1(s, q1) - R1).max()) / scale
         e2 = float(np.abs(LR.unpack_t2(s, q2) - R2).max()) / scale
-        _log(f"cfg2 residual {prec}: max|dR| / max|R| = {e1:.2e} (T1), {e2:.2e} (T2)")
+        _log(f"production-size residual {prec}: max|dR| / max|R| = {e1:.2e} (T1), {e2:.2e} (T2)")
         assert e1 <= 2.0 ** -16 and e2 <= 2.0 ** -16

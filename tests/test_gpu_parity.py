@@ -61,7 +61,7 @@ def allowed_random_t(s, seed, scale=0.05):
 
 
 SYSTEMS = [
-    ("cfg0", None),
+    ("o8v24", None),
     ("z4-empty-irreps", (6, 14, 4, 0.1, 21)),
     ("z6-empty-irreps", (5, 12, 6, 0.1, 4)),
     ("one-occupied", (1, 5, 1, 0.1, 3)),
@@ -72,8 +72,8 @@ SYSTEMS = [
 
 def _system(spec):
     name, p = spec
-    if name == "cfg0":
-        return fsgen.config_system(0)
+    if name == "o8v24":
+        return fsgen.workload_system("o8v24")
     return fsgen.make_system(p[0], p[1], p[2], p[3], p[4])
 
 
@@ -98,9 +98,9 @@ def test_residual_matches_oracle(spec):
     ctx.destroy()
 
 
-def test_residual_matches_blocked_oracle_cfg1():
+def test_residual_matches_blocked_oracle_o20v120z8():
     torch = _torch()
-    s = fsgen.config_system(1)
+    s = fsgen.workload_system("o20v120z8")
     ctx = gpu_ctx(s)
     t1, t2 = allowed_random_t(s, 11, 0.02)
     d1, d2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
@@ -153,10 +153,10 @@ def test_ladder_mp3_closed_form():
     ctx.destroy()
 
 
-def test_converged_cfg0_matches_oracle():
+def test_converged_o8v24_matches_oracle():
     torch = _torch()
     import paper_2004_03682_amd as F
-    s = fsgen.config_system(0)
+    s = fsgen.workload_system("o8v24")
     ctx = gpu_ctx(s)
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
@@ -169,16 +169,16 @@ def test_converged_cfg0_matches_oracle():
     ctx.destroy()
 
 
-def test_converged_cfg1_matches_golden():
+def test_converged_o20v120z8_matches_golden():
     torch = _torch()
     import paper_2004_03682_amd as F
-    gold = json.load(open(os.path.join(HERE, "golden", "cfg1_ccsd.json")))
-    s = fsgen.config_system(1)
+    gold = json.load(open(os.path.join(HERE, "golden", "o20v120z8_ccsd.json")))
+    s = fsgen.workload_system("o20v120z8")
     ctx = gpu_ctx(s)
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
     g = F.solve(ctx, t1, t2, tol=1e-10)
-    print("cfg1 gpu", g["E"], g["iters"], "oracle", gold["E_re"], gold["E_im"], gold["iters"], flush=True)
+    print("o20v120z8 gpu", g["E"], g["iters"], "oracle", gold["E_re"], gold["E_im"], gold["iters"], flush=True)
     assert g["converged"]
     assert abs(g["E"].real - gold["E_re"]) <= 1e-10
     assert abs(g["E"].imag - gold["E_im"]) <= 1e-10

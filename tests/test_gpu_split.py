@@ -142,17 +142,17 @@ def test_split_residual_close_to_oracle(prec):
         ctx.destroy()
 
 
-def test_split_converge_then_fp64_polish_cfg1():
+def test_split_converge_then_fp64_polish_o20v120z8():
     torch = _torch()
     import paper_2004_03682_amd as F
-    gold = json.load(open(os.path.join(HERE, "golden", "cfg1_ccsd.json")))
-    s = fsgen.config_system(1)
+    gold = json.load(open(os.path.join(HERE, "golden", "o20v120z8_ccsd.json")))
+    s = fsgen.workload_system("o20v120z8")
     ctx = _ctx(s, "split_bf16")
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
     g = F.solve(ctx, t1, t2, tol=1e-6, maxit=200)
     dE_mixed = abs(complex(g["E"]) - complex(gold["E_re"], gold["E_im"]))
-    print("cfg1 split_bf16 to max|step| < 1e-6: E", g["E"], "iters", g["iters"],
+    print("o20v120z8 split_bf16 to max|step| < 1e-6: E", g["E"], "iters", g["iters"],
           "|dE| vs oracle %.2e" % dE_mixed, flush=True)
     assert g["converged"] and dE_mixed <= 1e-4
     ctx.set_precision("fp64")

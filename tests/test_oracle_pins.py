@@ -83,9 +83,9 @@ def test_class_buffer_layout(cls):
 
 # --------------------------------------------------------------------------- P2
 
-@pytest.mark.parametrize("cfg_or_sys", ["cfg0", (5, 11, 3, 8)])
-def test_first_iteration_is_mp2(cfg_or_sys):
-    s = fsgen.config_system(0) if cfg_or_sys == "cfg0" else fsgen.make_system(*cfg_or_sys[:3], 0.05, cfg_or_sys[3])
+@pytest.mark.parametrize("spec", ["o8v24", (5, 11, 3, 8)])
+def test_first_iteration_is_mp2(spec):
+    s = fsgen.workload_system("o8v24") if spec == "o8v24" else fsgen.make_system(*spec[:3], 0.05, spec[3])
     be = ccsd.Blocked(s) if s.nirrep > 1 else ccsd.Dense(s)
     t1, t2 = be.zeros_t1(), be.zeros_t2()
     R1, R2 = ccsd.residual(be, t1, t2)
@@ -212,7 +212,7 @@ def test_irrep_automorphism_invariance():
 
 
 def test_fixed_point_independent_of_diis():
-    s = fsgen.config_system(0)
+    s = fsgen.workload_system("o8v24")
     be = ccsd.Dense(s)
     a = solver.solve_ccsd(be, tol=1e-12, ndiis=6)
     b = solver.solve_ccsd(be, tol=1e-12, ndiis=0, maxit=400)
