@@ -233,7 +233,9 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
 /* Tile-shape autotuner for the grouped complex GEMMs (the block contractions
  * of Fig. 4 have very uneven shapes).  level 1: every candidate tile shape,
  * K depth (16/32) and split-K choice of each GEMM operation is timed on the
- * device (HIP events on the context's stream) and the fastest is kept;
+ * device (HIP events on the context's stream) and the fastest is kept, then
+ * for an MFMA winner its four-product complex form is timed against the
+ * default three-product form (FSCC_CFG_3M) and the faster kept;
  * in a split precision (fscc_set_precision) level 1 also times the split
  * kernel's tile shapes of the split operations; level 2 times only those;
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
@@ -241,8 +243,17 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
 
-/* Chosen configuration of operation k (cfg = tile shape id or -1 if k is not
- * a GEMM; bk = K depth; split = 1 if split along K); host outputs. */
+/* MFMA tile ids of fscc_zgemm / fscc_gemm_config may carry this bit: the
+ * complex product is formed from three real matrix products (Ar Br, Ai Bi,
+ * (Ar + Ai)(Br + Bi); Re = P1 - P2, Im = P3 - P1 - P2) instead of four.
+ * Contexts use it for every MFMA-tile GEMM unless the autotuner measured
+ * the four-product form faster.  Rounding: the imaginary part's error bound
+ * grows from ~u sum|Ar Bi| + |Ai Br| to ~u sum(|Ar| + |Ai|)(|Br| + |Bi|). */
+#define FSCC_CFG_3M 256
+
+/* Chosen configuration of operation k (cfg = tile shape id, with
+ * FSCC_CFG_3M set for a three-product MFMA tile, or -1 if k is not a GEMM;
+ * bk = K depth; split = 1 if split along K); host outputs. */
 fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int *split);
 
 /* One complex GEMM through the grouped MFMA kernel, for kernel-level tests:
@@ -254,7 +265,9 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
  * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
  * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256),
  * 11: dot (needs !tA, tB, M <= 8; every B row streamed once);
- * -1 = cost model.  FSCC_EINVAL if the shape does not fit the form.
+ * an MFMA tile id | FSCC_CFG_3M selects the three-product complex form;
+ * -1 = cost model (three-product form).  FSCC_EINVAL if the shape does not
+ * fit the form.
  * bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.
  * Synchronises hip_stream. */
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128 *A, int lda,

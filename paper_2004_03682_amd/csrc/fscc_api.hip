@@ -220,9 +220,10 @@ void apply_precision(fscc_ctx* c, int prec) {
     c->prec = prec;
 }
 
-void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split) {
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split, bool m3) {
     g.cfg = cfg;
     g.bk = bk;
+    g.m3 = m3 && !c->real && cfg != ZCFG_SKINNY && cfg != ZCFG_TALL && cfg != ZCFG_RED && cfg != ZCFG_DOT;
     g.role = o.name == "pp-ladder" ? 1 : (o.name == "ring" || o.name == "W.U") ? 2 : 0;
     int bm, bn;
     zcfg_tile(g.cfg, &bm, &bn);
@@ -484,7 +485,7 @@ static std::vector<std::vector<StreamChunk>> stream_plan(fscc_ctx* c, OpList& L,
             StreamChunk ch;
             ch.lo = span[j].first;
             ch.hi = span[j].second;
-            plan_gemm(c, sub, ch.g, g0.cfg, g0.bk, true);
+            plan_gemm(c, sub, ch.g, g0.cfg, g0.bk, true, g0.m3);
             hip_check(hipEventCreateWithFlags(&ch.copied, hipEventDisableTiming), "event");
             out[k].push_back(ch);
         }
@@ -1108,6 +1109,18 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                                 free_gemm(cand);
                             }
                         }
+                if (best.m3) {   // the winner's tile with the four-product complex form
+                    GemmDev alt;
+                    plan_gemm(ctx, o, alt, best.cfg, best.bk, best.split, false);
+                    float ms = time_op(o, &alt);
+                    if (ms < best_ms) {
+                        free_gemm(best);
+                        best = alt;
+                        best_ms = ms;
+                    } else {
+                        free_gemm(alt);
+                    }
+                }
                 L->g[k] = best;
                 L->g[k].mx = keep;
             }
@@ -1350,7 +1363,7 @@ fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int*
     int j;
     if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
     const GemmDev& g = L->g[j];
-    *cfg = (*L->ops)[j].kind == OP_GEMM ? g.cfg : -1;
+    *cfg = (*L->ops)[j].kind == OP_GEMM ? (g.cfg | (g.m3 ? FSCC_CFG_3M : 0)) : -1;
     *bk = g.bk;
     *split = g.split ? 1 : 0;
     return FSCC_OK;
@@ -1359,6 +1372,8 @@ fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int*
 fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K, const fscc_c128* A, int lda,
                        const fscc_c128* B, int ldb, fscc_c128* C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void* hip_stream) {
+    const bool m3 = cfg >= 0 && (cfg & FSCC_CFG_3M);
+    if (cfg >= 0) cfg &= ~FSCC_CFG_3M;
     if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
     if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
@@ -1378,14 +1393,14 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         if (M > 0 && N > 0) o.probs.push_back(GemmProblem{0, 0, 0, M, N, K, std::max(lda, 1), std::max(ldb, 1), ldc});
         if (cfg >= 0 && !cfg_ok(o, cfg)) return FSCC_EINVAL;
         GemmDev g;
-        plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0);
+        plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0, cfg < 0 || m3);
         hipError_t e;
         if (!g.split) {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
-                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM);
+                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3);
         } else {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM);
+                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3);
             if (e == hipSuccess)
                 e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, alpha_re, alpha_im, o.beta, c->st);
         }

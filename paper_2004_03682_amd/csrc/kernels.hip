@@ -23,7 +23,11 @@ static constexpr int kThreads = 256;
 // grouped complex GEMM
 
 // ROLE only distinguishes kernel symbols in profiles (0 generic, 1 pp-ladder, 2 ring).
-template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE>
+// M3: the complex product with three real matrix products, P1 = Ar Br,
+// P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Re = P1 - P2, Im = P3 - P1 - P2 (the
+// sums formed in registers from the LDS fragments); otherwise four products
+// (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br).
+template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE, bool M3>
 __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
@@ -54,13 +58,15 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
     const double sA = cA ? -1.0 : 1.0;
     const double sB = cB ? -1.0 : 1.0;
 
-    dbl4 accr[FM][FN], acci[FM][FN];
+    // 4M: accr = Re, acci = Im.  3M: accr = P1, acci = P2, accs = P3.
+    dbl4 accr[FM][FN], acci[FM][FN], accs[M3 ? FM : 1][M3 ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             accr[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
             acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (M3) accs[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
 
     // register staging of one BK slice: vectors of 4 consecutive complex along
@@ -249,28 +255,52 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
                 b_r[j] = Bs[0][ks * 4 + lk][wn0 + j * 16 + lr];
                 b_i[j] = Bs[1][ks * 4 + lk][wn0 + j * 16 + lr];
             }
-            // four passes over the fragment grid so that consecutive MFMAs
-            // update different accumulators
+            if constexpr (M3) {
+                double a_s[FM], b_s[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i) a_s[i] = a_r[i] + a_i[i];
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], accr[i][j], 0, 0, 0);
+                for (int j = 0; j < FN; ++j) b_s[j] = b_r[j] + b_i[j];
+                // three passes over the fragment grid, one per real product
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], acci[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j)
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], accr[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], accr[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j)
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_i[j], acci[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], acci[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j)
+                        accs[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[i], b_s[j], accs[i][j], 0, 0, 0);
+            } else {
+                // four passes over the fragment grid so that consecutive MFMAs
+                // update different accumulators
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], accr[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], acci[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], accr[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], acci[i][j], 0, 0, 0);
+            }
         }
     }
 
@@ -287,7 +317,14 @@ __global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A,
             for (int q = 0; q < 4; ++q) {
                 int row = m0 + wm0 + i * 16 + q * 4 + lk;
                 if (row >= M) continue;
-                double xr = accr[i][j][q], xi = acci[i][j][q];
+                double xr, xi;
+                if constexpr (M3) {
+                    xr = accr[i][j][q] - acci[i][j][q];
+                    xi = accs[i][j][q] - accr[i][j][q] - acci[i][j][q];
+                } else {
+                    xr = accr[i][j][q];
+                    xi = acci[i][j][q];
+                }
                 double2 out = make_double2(ar * xr - ai * xi, ar * xi + ai * xr);
                 double2* c = Cp + (long long)row * pr.ldc + col;
                 if (beta) {
@@ -721,45 +758,45 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
     }
 }
 
-template <int BM, int BN, int WM, int WN, int BK>
+template <int BM, int BN, int WM, int WN, int BK, bool M3>
 static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
                              const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
                              hipStream_t st, int role, const int* active) {
     dim3 grid(ntiles), block(kThreads);
     if (!tA && !tB) {
-        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
-        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (!tA && tB) {
-        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
-        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (tA && !tB) {
-        k_zgemm<BM, BN, WM, WN, BK, true, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        k_zgemm<BM, BN, WM, WN, BK, true, false, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else {
-        k_zgemm<BM, BN, WM, WN, BK, true, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        k_zgemm<BM, BN, WM, WN, BK, true, true, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     }
     return hipGetLastError();
 }
 
-template <int BK>
+template <int BK, bool M3>
 static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                             const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                             int cB, hipStream_t st, int role, const int* active) {
     switch (cfg) {
-        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role, const int* active, int max_m) {
+                        int cB, hipStream_t st, int role, const int* active, int max_m, bool m3) {
     if (ntiles <= 0) return hipSuccess;
     if (cfg == ZCFG_TALL) {
         if (tA) return hipErrorInvalidValue;
@@ -799,8 +836,13 @@ hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, con
         else k_zskinny<true, true><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
         return hipGetLastError();
     }
-    if (bk == 32) return launch_bk<32>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-    if (bk == 16) return launch_bk<16>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+    if (m3) {
+        if (bk == 32) return launch_bk<32, true>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        if (bk == 16) return launch_bk<16, true>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+    } else {
+        if (bk == 32) return launch_bk<32, false>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        if (bk == 16) return launch_bk<16, false>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+    }
     return hipErrorInvalidValue;
 }
 

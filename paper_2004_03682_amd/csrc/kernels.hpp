@@ -46,9 +46,12 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 //   bk = 16 or 32 (K depth of one LDS stage); role only selects a distinct kernel symbol.
 //   active (may be null): tiles whose active[tile.sys] == 0 are skipped.
 //   max_m: largest M of the problems (used by ZCFG_RED and ZCFG_DOT only, 1..8).
+//   m3: MFMA tiles form the complex product from three real products (3M)
+//   instead of four (4M); ignored by the vector-ALU forms.
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role = 0, const int* active = nullptr, int max_m = 0);
+                        int cB, hipStream_t st, int role = 0, const int* active = nullptr, int max_m = 0,
+                        bool m3 = false);
 
 // ---- compensated mixed-precision GEMM (kernels_split.hip)
 // element (r, k) of a rows x cols operand: src[src_off + r*ld + k] (trans = 0)

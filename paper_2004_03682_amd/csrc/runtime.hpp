@@ -57,6 +57,7 @@ struct GemmDev {
     int nred = 0;
     int maxMN = 0;
     int maxM = 0;   // largest M over the problems (ZCFG_RED picks its register tile by it)
+    bool m3 = false;   // MFMA tiles: complex product from three real products
     double2* work = nullptr;
     MixedDev* mx = nullptr;   // present for the ops that may run in split precision
 };
@@ -332,10 +333,10 @@ struct fscc_ctx {
                     e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
                 } else if (!g.split) {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM);
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3);
                 } else {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM);
+                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
                                                  beta, st, d_active);
@@ -412,9 +413,9 @@ struct fscc_ctx {
         double2* Cp = C_override ? C_override : B(o.dst);
         if (!g.split)
             return launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
-                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM);
+                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3);
         hipError_t e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
-                                    o.cA, o.cB, st, g.role, nullptr, g.maxM);
+                                    o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3);
         if (e == hipSuccess)
             e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(), beta, st);
         return e;
@@ -507,7 +508,7 @@ bool mixed_eligible(const Op& o, int prec);
 MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg);
 int pick_mcfg(const Op& o);
 void apply_precision(fscc_ctx* c, int prec);
-void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split);
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split, bool m3 = true);
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops);
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2);
 void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2);

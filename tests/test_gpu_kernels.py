@@ -1,5 +1,6 @@
 """Kernel-level parity of the grouped complex FP64 GEMM forms (through the C
-ABI) against numpy: every MFMA tile shape, K depth, transpose/conjugate flag
+ABI) against numpy: every MFMA tile shape in the four- and three-product
+complex forms, K depth, transpose/conjugate flag
 and split-K choice, the vector-ALU skinny, tall, reduction and dot forms, with
 ragged sizes (not multiples of any tile), K = 0 and accumulation (beta = 1)."""
 import itertools
@@ -9,7 +10,9 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-CFGS = (0, 1, 2, 3, 4, 5, 6, 9, 10)   # MFMA tiles 0-5, 9 (32x64), 10 (64x32); 6 = skinny (vector ALUs)
+M3 = 256   # FSCC_CFG_3M: three-product complex form of an MFMA tile
+MFMA_TILES = (0, 1, 2, 3, 4, 5, 9, 10)   # 0-5, 9 (32x64), 10 (64x32)
+CFGS = MFMA_TILES + tuple(c | M3 for c in MFMA_TILES) + (6,)   # 4M and 3M MFMA tiles; 6 = skinny (vector ALUs)
 
 
 def _rand(rng, *shape):
