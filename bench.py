@@ -45,7 +45,8 @@ def kernel_source_sha():
 
 def measured_traffic(kernel_name, tile=None):
     """HBM bytes per launch from committed rocprofv3 --pmc counters, if they were
-    taken on the current library sources and the same tile shape; else None."""
+    taken on the current library sources for the tile shape in use (the counter
+    run records every tile the autotuner dispatches for the op); else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -56,9 +57,8 @@ def measured_traffic(kernel_name, tile=None):
     ent = d.get(kernel_name)
     if not ent or ent.get("kernels_sha256") != kernel_source_sha():
         return None
-    if tile is not None and ent.get("tile") != tile:
-        return None
-    return ent.get("bytes_per_launch")
+    t = ent.get("tiles", {}).get(tile)
+    return None if t is None else t.get("bytes_per_launch")
 
 
 def cpu_baseline(sysm, buffers):
@@ -699,10 +699,15 @@ def main():
     per_launch_s = dom["ms"] / dom["calls"] * 1e-3
     achieved = dom["flops"] / per_launch_s / 1e12
     traffic = measured_traffic(dom["name"], tuned.get(dom["name"]))
+    dom_3m = "/3M" in tuned.get(dom["name"], "")
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64, 4), "traffic": traffic,
             "kernel": "k_zgemm (grouped complex FP64 MFMA GEMM), op '%s'" % dom["name"],
-            "flops_per_launch": dom["flops"], "avg_launch_ms": round(per_launch_s * 1e3, 4)}
+            "flops_per_launch": dom["flops"], "avg_launch_ms": round(per_launch_s * 1e3, 4),
+            # achieved counts the algorithmic 8 real flops per complex multiply-add; the
+            # three-product form issues 6 of them to the matrix cores
+            "complex_form": "3M" if dom_3m else "4M",
+            "issued_frac": round(achieved * (0.75 if dom_3m else 1.0) / PEAK_FP64, 4)}
     result = {
         "metric": METRIC, "value": round(s_per_iter, 6), "unit": "s/iteration", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(s_per_iter * 1e3, 4),
