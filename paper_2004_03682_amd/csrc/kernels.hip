@@ -27,8 +27,13 @@ static constexpr int kThreads = 256;
 // P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Re = P1 - P2, Im = P3 - P1 - P2 (the
 // sums formed in registers from the LDS fragments); otherwise four products
 // (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br).
+// Waves with a single 16x16 fragment on 16-deep slices fit in 96 registers:
+// they ask for five waves per SIMD (more global-load latency hidden); the
+// larger fragment grids keep three, which they reach without spills.
+constexpr int zgemm_min_waves(int BM, int BN, int BK) { return (BK == 16 && BM * BN == 1024) ? 5 : 3; }
+
 template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE, bool M3>
-__global__ __launch_bounds__(256, 3) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
+__global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
                                                int cA, int cB, const int* __restrict__ active) {
