@@ -645,7 +645,7 @@ def main():
 
     t0 = time.perf_counter()
     ctx.autotune(1)
-    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot"}
+    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot", 12: "64x64r", 13: "64x32r"}
     tuned = {n: f"{names[c & 255]}{'/3M' if c & 256 else ''}/bk{b}{'/splitK' if sp else ''}"
              for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +

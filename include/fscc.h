@@ -261,7 +261,8 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
  * conjugate (cA/cB); A is M x K (lda) or, if tA, K x M; B is K x N (ldb) or,
  * if tB, N x K; all row-major, device pointers.  cfg = kernel form: MFMA tile
  * shapes 0: 64x64, 1: 128x16, 2: 16x128, 3: 32x32, 4: 64x16, 5: 16x64,
- * 9: 32x64, 10: 64x32;
+ * 9: 32x64, 10: 64x32, and 12: 64x64, 13: 64x32 with the four waves
+ * stacked along M (a wave whose 16 rows lie past M issues no MFMA);
  * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
  * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256),
  * 11: dot (needs !tA, tB, M <= 8; every B row streamed once);

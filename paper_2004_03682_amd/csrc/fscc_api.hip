@@ -44,7 +44,7 @@ bool cfg_ok(const Op& o, int cfg, bool real) {
 }
 
 double cfg_cost(const Op& o, int cfg) {
-    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0, 1.0, 1.0, 1.3, 1.3, 1.0};
+    static const double eff[ZCFG_N] = {1.0, 1.4, 1.4, 1.6, 1.8, 1.8, 1.0, 1.0, 1.0, 1.3, 1.3, 1.0, 1.3, 1.3};
     if (cfg == ZCFG_TALL || cfg == ZCFG_RED || cfg == ZCFG_DOT) {
         // streaming forms: every operand element read once, exact work on the
         // vector ALUs

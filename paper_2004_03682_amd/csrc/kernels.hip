@@ -759,6 +759,8 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
         case ZCFG_16x64: *bm = 16; *bn = 64; break;
         case ZCFG_32x64: *bm = 32; *bn = 64; break;
         case ZCFG_64x32: *bm = 64; *bn = 32; break;
+        case ZCFG_64x64R: *bm = 64; *bn = 64; break;
+        case ZCFG_64x32R: *bm = 64; *bn = 32; break;
         default: *bm = 64; *bn = 64; break;
     }
 }
@@ -795,6 +797,8 @@ static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const d
         case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x64R: return launch_cfg<64, 64, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32R: return launch_cfg<64, 32, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }

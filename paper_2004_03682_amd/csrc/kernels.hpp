@@ -29,9 +29,13 @@ struct ZTile {
 // ZCFG_DOT: one workgroup per ZDOT_ROWS rows of B of a problem with
 // M <= ZDOT_MAX_M, !tA, tB (every output a dot product of two contiguous
 // K-vectors), on the vector ALUs; each B row is streamed once; never split.
+// ZCFG_64x64R / ZCFG_64x32R: 64-row MFMA tiles with the four waves stacked
+// along M (16 rows each): a problem of up to 64 rows reads each column panel
+// of B once, and a wave whose 16 rows lie past M issues no MFMA, so the
+// padding is that of 16-row tiles.
 enum ZCfg {
     ZCFG_64x64 = 0, ZCFG_128x16, ZCFG_16x128, ZCFG_32x32, ZCFG_64x16, ZCFG_16x64, ZCFG_SKINNY, ZCFG_TALL, ZCFG_RED,
-    ZCFG_32x64, ZCFG_64x32, ZCFG_DOT, ZCFG_N
+    ZCFG_32x64, ZCFG_64x32, ZCFG_DOT, ZCFG_64x64R, ZCFG_64x32R, ZCFG_N
 };
 constexpr int ZSKINNY_BM = 64, ZSKINNY_BN = 32, ZSKINNY_MAX_MN = ZSKINNY_BM * ZSKINNY_BN;
 constexpr int ZTALL_ROWS = 256, ZTALL_MAX_K = 64, ZTALL_MAX_KN = 1024;

@@ -358,6 +358,8 @@ hipError_t dlaunch_bk(int cfg, bool tA, bool tB, const double* A, const double* 
         case ZCFG_64x64: return dlaunch_cfg<64, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         case ZCFG_32x64: return dlaunch_cfg<32, 64, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         case ZCFG_64x32: return dlaunch_cfg<64, 32, 2, 2, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x64R: return dlaunch_cfg<64, 64, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x32R: return dlaunch_cfg<64, 32, 4, 1, BK>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }

@@ -11,7 +11,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 M3 = 256   # FSCC_CFG_3M: three-product complex form of an MFMA tile
-MFMA_TILES = (0, 1, 2, 3, 4, 5, 9, 10)   # 0-5, 9 (32x64), 10 (64x32)
+MFMA_TILES = (0, 1, 2, 3, 4, 5, 9, 10, 12, 13)   # 0-5, 9 (32x64), 10 (64x32), 12/13 (64x64, 64x32, waves along M)
 CFGS = MFMA_TILES + tuple(c | M3 for c in MFMA_TILES) + (6,)   # 4M and 3M MFMA tiles; 6 = skinny (vector ALUs)
 
 

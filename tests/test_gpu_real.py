@@ -23,7 +23,7 @@ from oracle import ccsd, fs01, fs02, solver
 
 pytestmark = pytest.mark.gpu
 
-MFMA = (0, 1, 2, 3, 4, 5, 9, 10)
+MFMA = (0, 1, 2, 3, 4, 5, 9, 10, 12, 13)
 TALL, RED, SKINNY = 7, 8, 6
 
 
