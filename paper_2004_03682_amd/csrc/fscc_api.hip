@@ -284,6 +284,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
                 if (p.K == 0) break;
             }
             rd.push_back(ZRed{p.c_off, woff, p.M, p.N, p.ldc, ns, p.sys, 0});
+            g.maxS = std::max(g.maxS, ns);
             woff += (long long)ns * p.M * p.N;
             maxMN = std::max(maxMN, p.M * p.N);
         }
@@ -1402,7 +1403,7 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
                              g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3);
             if (e == hipSuccess)
-                e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, alpha_re, alpha_im, o.beta, c->st);
+                e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha_re, alpha_im, o.beta, c->st);
         }
         hip_check(e, "zgemm");
         hip_check(hipStreamSynchronize(c->st), "zgemm sync");
@@ -1443,7 +1444,7 @@ fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, con
             e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, A, B, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0, 0, c->st,
                              0, nullptr, g.maxM);
             if (e == hipSuccess)
-                e = launch_dsplitk_reduce(C, (const double*)g.work, g.reds, g.nred, g.maxMN, alpha, o.beta, c->st);
+                e = launch_dsplitk_reduce(C, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha, o.beta, c->st);
         }
         hip_check(e, "dgemm");
         hip_check(hipStreamSynchronize(c->st), "dgemm sync");

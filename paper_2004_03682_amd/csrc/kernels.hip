@@ -910,11 +910,58 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(double2* __restrict__ C, 
     }
 }
 
-hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
-                                double ai, int beta, hipStream_t st, const int* active) {
+// The same pass for few K chunks (S <= ZRED_FEW_S, the MFMA tiles' split):
+// one output per thread, its S partial values read in chunk order (the
+// summation order of the kernel above), every load coalesced.
+__global__ __launch_bounds__(256) void k_splitk_reduce_few(double2* __restrict__ C, const double2* __restrict__ W,
+                                                           const ZRed* __restrict__ reds, double ar, double ai,
+                                                           int beta, const int* __restrict__ active) {
+    const ZRed r = reds[blockIdx.y];
+    if (active && !active[r.sys]) return;
+    const long long mn = (long long)r.M * r.N;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mn) return;
+    const double2* w = W + r.w_off + e;
+    double sr = 0.0, si = 0.0;
+    int s = 0;
+    for (; s + 4 <= r.S; s += 4) {
+        const double2 x0 = w[(long long)s * mn], x1 = w[(long long)(s + 1) * mn];
+        const double2 x2 = w[(long long)(s + 2) * mn], x3 = w[(long long)(s + 3) * mn];
+        sr += x0.x;
+        si += x0.y;
+        sr += x1.x;
+        si += x1.y;
+        sr += x2.x;
+        si += x2.y;
+        sr += x3.x;
+        si += x3.y;
+    }
+    for (; s < r.S; ++s) {
+        const double2 x = w[(long long)s * mn];
+        sr += x.x;
+        si += x.y;
+    }
+    const int m = (int)(e / r.N), n = (int)(e % r.N);
+    double2* c = C + r.c_off + (long long)m * r.ldc + n;
+    double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+    if (beta) {
+        const double2 old = *c;
+        out.x += old.x;
+        out.y += old.y;
+    }
+    *c = out;
+}
+
+hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, int maxS,
+                                double ar, double ai, int beta, hipStream_t st, const int* active) {
     if (nred <= 0 || maxMN <= 0) return hipSuccess;
-    dim3 grid((unsigned)((maxMN + 15) / 16), (unsigned)nred);
-    k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta, active);
+    if (maxS <= ZRED_FEW_S) {
+        dim3 grid((unsigned)((maxMN + kThreads - 1) / kThreads), (unsigned)nred);
+        k_splitk_reduce_few<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta, active);
+    } else {
+        dim3 grid((unsigned)((maxMN + 15) / 16), (unsigned)nred);
+        k_splitk_reduce<<<grid, kThreads, 0, st>>>(C, W, reds, ar, ai, beta, active);
+    }
     return hipGetLastError();
 }
 

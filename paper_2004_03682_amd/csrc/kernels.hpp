@@ -90,8 +90,10 @@ struct ZRed {
     long long c_off, w_off;
     int M, N, ldc, S, sys, pad;
 };
-hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, double ar,
-                                double ai, int beta, hipStream_t st, const int* active = nullptr);
+// maxS = the largest number of K chunks over the problems
+constexpr int ZRED_FEW_S = 8;
+hipError_t launch_splitk_reduce(double2* C, const double2* W, const ZRed* reds, int nred, int maxMN, int maxS,
+                                double ar, double ai, int beta, hipStream_t st, const int* active = nullptr);
 
 // Block table of a segmented elementwise launch over a batched buffer: block b
 // handles elements [start[b], min(start[b] + 256, end[b])) of system sys[b]
@@ -148,8 +150,8 @@ int reduce_blocks(long long n);
 hipError_t launch_dgemm(int cfg, int bk, bool tA, bool tB, const double* A, const double* B, double* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
                         int role = 0, const int* active = nullptr, int max_m = 0);
-hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, double alpha,
-                                 int beta, hipStream_t st);
+hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, int maxS,
+                                 double alpha, int beta, hipStream_t st);
 hipError_t launch_dgather(double* dst, const double* src, const double* src2, GatherMaps maps, int nt, long long n,
                           double alpha, int beta, hipStream_t st);
 hipError_t launch_daxpby(double* dst, const double* src, long long n, double alpha, int beta, hipStream_t st);

@@ -401,6 +401,32 @@ __global__ __launch_bounds__(256) void k_dsplitk_reduce(double* __restrict__ C, 
     }
 }
 
+// few K chunks: one output per thread, chunks summed in order
+__global__ __launch_bounds__(256) void k_dsplitk_reduce_few(double* __restrict__ C, const double* __restrict__ W,
+                                                            const ZRed* __restrict__ reds, double alpha, int beta) {
+    const ZRed r = reds[blockIdx.y];
+    const long long mn = (long long)r.M * r.N;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mn) return;
+    const double* w = W + r.w_off + e;
+    double s = 0.0;
+    int q = 0;
+    for (; q + 4 <= r.S; q += 4) {
+        const double x0 = w[(long long)q * mn], x1 = w[(long long)(q + 1) * mn];
+        const double x2 = w[(long long)(q + 2) * mn], x3 = w[(long long)(q + 3) * mn];
+        s += x0;
+        s += x1;
+        s += x2;
+        s += x3;
+    }
+    for (; q < r.S; ++q) s += w[(long long)q * mn];
+    const int m = (int)(e / r.N), n = (int)(e % r.N);
+    double* c = C + r.c_off + (long long)m * r.ldc + n;
+    double out = alpha * s;
+    if (beta) out += *c;
+    *c = out;
+}
+
 __device__ __forceinline__ double dmap_load(const double* __restrict__ s, uint32_t m) {
     if (m == 0xFFFFFFFFu) return 0.0;
     const double x = s[m & 0x7FFFFFFFu];
@@ -595,11 +621,16 @@ hipError_t launch_dgemm(int cfg, int bk, bool tA, bool tB, const double* A, cons
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, double alpha,
-                                 int beta, hipStream_t st) {
+hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, int maxS,
+                                 double alpha, int beta, hipStream_t st) {
     if (nred <= 0 || maxMN <= 0) return hipSuccess;
-    dim3 grid((unsigned)((maxMN + 15) / 16), (unsigned)nred);
-    k_dsplitk_reduce<<<grid, kT, 0, st>>>(C, W, reds, alpha, beta);
+    if (maxS <= ZRED_FEW_S) {
+        dim3 grid((unsigned)((maxMN + kT - 1) / kT), (unsigned)nred);
+        k_dsplitk_reduce_few<<<grid, kT, 0, st>>>(C, W, reds, alpha, beta);
+    } else {
+        dim3 grid((unsigned)((maxMN + 15) / 16), (unsigned)nred);
+        k_dsplitk_reduce<<<grid, kT, 0, st>>>(C, W, reds, alpha, beta);
+    }
     return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ struct GemmDev {
     ZRed* reds = nullptr;
     int nred = 0;
     int maxMN = 0;
+    int maxS = 0;    // largest number of K chunks of a problem (split)
     int maxM = 0;   // largest M over the problems (ZCFG_RED picks its register tile by it)
     bool m3 = false;   // MFMA tiles: complex product from three real products
     double2* work = nullptr;
@@ -286,7 +287,7 @@ struct fscc_ctx {
                 hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, D(o.src2), (double*)g.work, g.probs, g.tiles,
                                             g.ntiles, 1.0, 0, st, g.role, nullptr, g.maxM);
                 if (e == hipSuccess)
-                    e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), beta,
+                    e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), beta,
                                               st);
                 return e;
             }
@@ -338,7 +339,7 @@ struct fscc_ctx {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
                                      0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3);
                     if (e == hipSuccess)
-                        e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(),
+                        e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(),
                                                  beta, st, d_active);
                 }
                 break;
@@ -417,7 +418,7 @@ struct fscc_ctx {
         hipError_t e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
                                     o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3);
         if (e == hipSuccess)
-            e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), o.alpha.imag(), beta, st);
+            e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(), beta, st);
         return e;
     }
 
@@ -432,7 +433,7 @@ struct fscc_ctx {
         hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0,
                                     0, st, g.role, nullptr, g.maxM);
         if (e == hipSuccess)
-            e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, o.alpha.real(), beta, st);
+            e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), beta, st);
         return e;
     }
 

@@ -54,8 +54,11 @@ def test_zgemm_every_config(cfg, bk):
 
 @pytest.mark.parametrize("cfg", CFGS)
 def test_zgemm_split_k_and_edges(cfg):
-    # long K with few output tiles triggers the split-K path; K = 0 must give beta*C
-    for (M, N, K, beta) in [(7, 34, 3000, 0), (7, 7, 5000, 1), (20, 3, 700, 1), (9, 11, 0, 0), (9, 11, 0, 1)]:
+    # long K with few output tiles triggers the split-K path (more than 8 K
+    # chunks: the grouped reduction pass; at most 8, with several thousand
+    # outputs: the one-output-per-thread pass); K = 0 must give beta*C
+    for (M, N, K, beta) in [(7, 34, 3000, 0), (7, 7, 5000, 1), (20, 3, 700, 1), (300, 200, 1800, 1),
+                            (130, 70, 1200, 0), (9, 11, 0, 0), (9, 11, 0, 1)]:
         err = _run(M, N, K, 0, 1, 0, 0, cfg, 16, True, beta)
         assert err < 1e-13, (cfg, M, N, K, beta, err)
 

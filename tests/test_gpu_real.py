@@ -44,7 +44,9 @@ def _dg(M, N, K, tA, tB, cfg, bk, split, beta, seed=0, alpha=0.7):
 @pytest.mark.parametrize("cfg,bk", list(itertools.product(MFMA, (16, 32))))
 def test_dgemm_mfma_tiles(cfg, bk):
     for tA, tB in itertools.product((0, 1), (0, 1)):
-        for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 129), (130, 131, 40), (3, 48, 3000), (9, 11, 0)]:
+        # (3, 48, 3000): 12 K chunks when split; (130, 70, 1200) and (300, 200, 1800): 5 and 8 chunks
+        for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 129), (130, 131, 40), (3, 48, 3000), (130, 70, 1200),
+                          (300, 200, 1800), (9, 11, 0)]:
             for split in (False, True):
                 err = _dg(M, N, K, tA, tB, cfg, bk, split, beta=M % 2, seed=M + N + K)
                 assert err < 1e-13, (cfg, bk, tA, tB, M, N, K, split, err)
