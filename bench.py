@@ -707,7 +707,12 @@ def main():
             # achieved counts the algorithmic 8 real flops per complex multiply-add; the
             # three-product form issues 6 of them to the matrix cores
             "complex_form": "3M" if dom_3m else "4M",
-            "issued_frac": round(achieved * (0.75 if dom_3m else 1.0) / PEAK_FP64, 4)}
+            "issued_frac": round(achieved * (0.75 if dom_3m else 1.0) / PEAK_FP64, 4),
+            # the HIP events bracket the whole op: with a split-K tile, the GEMM
+            # kernel and the split-K reduction pass (rocprofv3 lists them apart);
+            # traffic is that of the GEMM kernel
+            "tile": tuned.get(dom["name"]),
+            "launch_includes_splitk_pass": tuned.get(dom["name"], "").endswith("/splitK")}
     result = {
         "metric": METRIC, "value": round(s_per_iter, 6), "unit": "s/iteration", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(s_per_iter * 1e3, 4),
