@@ -239,9 +239,18 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * in a split precision (fscc_set_precision) level 1 also times the split
  * kernel's tile shapes of the split operations; level 2 times only those;
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
- * shapes).  Results are numerically equivalent (summation order may
- * change). */
+ * shapes).  Level 1 also times each reorder (gather) of a complex context in
+ * destination order and by 16 x 16 destination tiles and keeps the faster.
+ * Results are numerically equivalent (summation order may change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
+
+/* Traversal of the reorders / antisymmetrisers (gathers) of every operation
+ * list: tiled = 0 walks each destination in storage order, tiled = 1 in
+ * 16 x 16 tiles of its blocks (complex contexts; a real context always uses
+ * storage order).  The results are bitwise identical; only the order of the
+ * source reads changes, and with it their cache-line locality.  Replaces the
+ * choice fscc_autotune(ctx, 1) made.  FSCC_EINVAL for another value. */
+fscc_status fscc_gather_order(fscc_ctx *ctx, int tiled);
 
 /* MFMA tile ids of fscc_zgemm / fscc_gemm_config may carry this bit: the
  * complex product is formed from three real matrix products (Ar Br, Ai Bi,

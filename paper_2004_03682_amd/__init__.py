@@ -69,6 +69,7 @@ def lib():
             "fscc_set_precision": ([vp, ip], ip),
             "fscc_profile_select": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
+            "fscc_gather_order": ([vp, ip], ip),
             "fscc_vvvv_out_of_core": ([vp, sz], ip),
             "fscc_dgemm": ([ip, ip, ip, ip, ip, ip, ip, vp, ip, vp, ip, vp, ip, ctypes.c_double, ip, ip, vp], ip),
             "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
@@ -328,6 +329,10 @@ class Context:
 
     def autotune(self, level=1):
         self._check(lib().fscc_autotune(self._h, int(level)))
+
+    def gather_order(self, tiled):
+        """Reorders in destination storage order (0) or by 16 x 16 destination tiles (1)."""
+        self._check(lib().fscc_gather_order(self._h, int(tiled)))
 
     def gemm_configs(self):
         """[(op name, tile cfg id, bk, split)] for every GEMM operation."""

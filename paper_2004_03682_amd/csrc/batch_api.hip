@@ -66,6 +66,9 @@ void merge_plans(const std::vector<std::unique_ptr<Plan>>& sub, Plan& M, std::ve
         const Op& o0 = P0.ops[k];
         Op o = o0;
         o.probs.clear();
+        o.gtiles.clear();   // batched gathers run over segments in destination order
+        o.d_gtiles = nullptr;
+        o.use_gtiles = false;
         o.mapsA.clear();
         o.mapsB.clear();
         o.flops = 0;

@@ -318,6 +318,12 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
 
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
     L.ops = &ops;
+    for (auto& o : ops)
+        if (o.kind == OP_GATHER && !o.gtiles.empty()) {
+            GTile* d = (GTile*)c->dalloc(o.gtiles.size() * sizeof(GTile));
+            hip_check(hipMemcpy(d, o.gtiles.data(), o.gtiles.size() * sizeof(GTile), hipMemcpyHostToDevice), "tiles");
+            o.d_gtiles = d;
+        }
     L.g.assign(ops.size(), GemmDev());
     L.ms.assign(ops.size(), 0.0);
     L.calls.assign(ops.size(), 0);
@@ -1018,6 +1024,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             for (OpList* L : lists)
                 for (size_t k = 0; k < L->ops->size(); ++k) {
                     const Op& o = (*L->ops)[k];
+                    (*L->ops)[k].use_gtiles = false;
                     if (o.kind != OP_GEMM) continue;
                     MixedDev* keep = L->g[k].mx;
                     L->g[k].mx = nullptr;
@@ -1077,6 +1084,16 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         for (OpList* L : lists)
             for (size_t k = 0; k < L->ops->size() && level == 1; ++k) {
                 const Op& o = (*L->ops)[k];
+                if (o.kind == OP_GATHER && o.d_gtiles && !ctx->real) {
+                    // destination order or 16 x 16 tiles, whichever is faster
+                    Op& m = (*L->ops)[k];
+                    m.use_gtiles = false;
+                    const float rows = time_op(m, nullptr);
+                    m.use_gtiles = true;
+                    const float tiles = time_op(m, nullptr);
+                    m.use_gtiles = tiles < rows;
+                    continue;
+                }
                 if (o.kind != OP_GEMM || o.flops < 1e5) continue;
                 MixedDev* keep = L->g[k].mx;   // the FP64 candidates are timed without it
                 L->g[k].mx = nullptr;
@@ -1280,6 +1297,15 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
         ctx->dbuf[b] = nullptr;
         return FSCC_OK;
     });
+}
+
+fscc_status fscc_gather_order(fscc_ctx* ctx, int tiled) {
+    if (!ctx) return FSCC_EINVAL;
+    if (tiled != 0 && tiled != 1) return fail(ctx, FSCC_EINVAL, "gather order must be 0 or 1");
+    for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01, &ctx->L02p, &ctx->L02})
+        if (L->ops)
+            for (auto& o : *L->ops) o.use_gtiles = tiled && o.d_gtiles != nullptr;
+    return FSCC_OK;
 }
 
 fscc_status fscc_level_shift(fscc_ctx* ctx, fscc_sector sector, double shift) {

@@ -994,12 +994,11 @@ __host__ inline unsigned elem_grid(const SegBlocks& sb, long long n) {
     return sb.sys ? (unsigned)sb.nblk : (unsigned)((n + kThreads - 1) / kThreads);
 }
 
+// one destination element: dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src[mA_t[k]]) (* src2[mB_t[k]])
 template <int NT, bool BIL>
-__global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const double2* __restrict__ src,
-                                                const double2* __restrict__ src2, GatherMaps maps, long long n,
-                                                double ar, double ai, int beta, int conj, SegBlocks sb) {
-    long long k;
-    if (!elem_index(sb, n, &k)) return;
+__device__ __forceinline__ void gather_elem(double2* __restrict__ dst, const double2* __restrict__ src,
+                                            const double2* __restrict__ src2, const GatherMaps& maps, long long k,
+                                            double ar, double ai, int beta, int conj) {
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -1021,6 +1020,51 @@ __global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const
         out.y += o.y;
     }
     dst[k] = out;
+}
+
+template <int NT, bool BIL>
+__global__ __launch_bounds__(256) void k_gather(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                const double2* __restrict__ src2, GatherMaps maps, long long n,
+                                                double ar, double ai, int beta, int conj, SegBlocks sb) {
+    long long k;
+    if (!elem_index(sb, n, &k)) return;
+    gather_elem<NT, BIL>(dst, src, src2, maps, k, ar, ai, beta, conj);
+}
+
+// The same gather traversing the destination in 16 x 16 tiles of its blocks
+// (one workgroup per tile, an 8 x 8 quarter per wave): where the maps follow
+// a transposition, the 64 source elements of a wave then lie in fewer cache
+// lines than along one destination row.
+template <int NT, bool BIL>
+__global__ __launch_bounds__(256) void k_gather_tiled(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                      const double2* __restrict__ src2, GatherMaps maps,
+                                                      const GTile* __restrict__ tiles, double ar, double ai, int beta,
+                                                      int conj) {
+    const GTile t = tiles[blockIdx.x];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = (w >> 1) * 8 + (l >> 3), c = (w & 1) * 8 + (l & 7);
+    if (r >= t.nr || c >= t.nc) return;
+    gather_elem<NT, BIL>(dst, src, src2, maps, t.k0 + (long long)r * t.ld + c, ar, ai, beta, conj);
+}
+
+hipError_t launch_gather_tiled(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
+                               const GTile* tiles, int ntiles, double ar, double ai, int beta, int conj,
+                               hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid((unsigned)ntiles), block(kThreads);
+    bool bil = src2 != nullptr;
+#define FSCC_GT(NT)                                                                                                \
+    if (bil) k_gather_tiled<NT, true><<<grid, block, 0, st>>>(dst, src, src2, maps, tiles, ar, ai, beta, conj);   \
+    else k_gather_tiled<NT, false><<<grid, block, 0, st>>>(dst, src, src2, maps, tiles, ar, ai, beta, conj);
+    switch (nt) {
+        case 1: FSCC_GT(1); break;
+        case 2: FSCC_GT(2); break;
+        case 3: FSCC_GT(3); break;
+        case 4: FSCC_GT(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FSCC_GT
+    return hipGetLastError();
 }
 
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,

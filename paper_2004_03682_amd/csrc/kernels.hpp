@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "gtile.hpp"
+
 namespace fscc {
 
 // one GEMM problem (offsets in complex elements)
@@ -115,6 +117,10 @@ struct GatherMaps {
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
                          long long n, double ar, double ai, int beta, int conj, hipStream_t st,
                          SegBlocks sb = SegBlocks());
+// the same gather over the 16 x 16 destination tiles of `tiles` (device array)
+hipError_t launch_gather_tiled(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
+                               const GTile* tiles, int ntiles, double ar, double ai, int beta, int conj,
+                               hipStream_t st);
 
 hipError_t launch_axpby(double2* dst, const double2* src, long long n, double ar, double ai, int beta, int conj,
                         hipStream_t st, SegBlocks sb = SegBlocks());

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "gtile.hpp"
 #include "layout.hpp"
 
 namespace fscc {
@@ -57,6 +58,9 @@ struct Op {
     int beta = 0;
     bool conj = false;
     int64_t n = 0;
+    std::vector<GTile> gtiles;       // gathers: 16 x 16 tiles covering the destination blocks
+    const GTile* d_gtiles = nullptr; // device copy (set up with the context)
+    bool use_gtiles = false;         // traverse the destination by tiles (chosen by timing)
     // GEMM
     bool tA = false, tB = false, cA = false, cB = false;
     std::vector<GemmProblem> probs;

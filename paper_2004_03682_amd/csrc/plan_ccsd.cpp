@@ -65,6 +65,15 @@ struct Builder {
         op.n = Ld.total;
         if (P.bufs[dst].n != Ld.total) throw std::logic_error("gather dst size mismatch: " + name);
         if (P.bufs[src].n != Ls.total) throw std::logic_error("gather src size mismatch: " + name);
+        if (Ld.total >= 256)
+            for (int k = 0; k < Ld.G; ++k) {
+                if (!Ld.kmask[k] || Ld.nrow[k] == 0 || Ld.ncol[k] == 0) continue;
+                for (int64_t r = 0; r < Ld.nrow[k]; r += 16)
+                    for (int64_t c = 0; c < Ld.ncol[k]; c += 16)
+                        op.gtiles.push_back(GTile{Ld.boff[k] + r * Ld.ncol[k] + c, (int32_t)Ld.ncol[k],
+                                                  (int16_t)std::min<int64_t>(16, Ld.nrow[k] - r),
+                                                  (int16_t)std::min<int64_t>(16, Ld.ncol[k] - c)});
+            }
         for (size_t t = 0; t < terms.size(); ++t) {
             op.mapsA.push_back(P.map(name + "/A" + std::to_string(t), build_map(Ld, Ls, terms[t].perm, terms[t].sign)));
             if (src2 >= 0)

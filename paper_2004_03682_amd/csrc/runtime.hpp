@@ -208,6 +208,12 @@ struct fscc_ctx {
     }
 
     static void free_list(OpList& L) {
+        if (L.ops)
+            for (auto& o : *L.ops)
+                if (o.d_gtiles) {
+                    (void)hipFree((void*)o.d_gtiles);
+                    o.d_gtiles = nullptr;
+                }
         for (auto& g : L.g) {
             if (g.probs) (void)hipFree(g.probs);
             if (g.tiles) (void)hipFree(g.tiles);
@@ -321,8 +327,13 @@ struct fscc_ctx {
                     gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
                     gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
                 }
-                e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(), o.n,
-                                  o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st, sb);
+                if (o.use_gtiles && o.d_gtiles && !sb.sys)
+                    e = launch_gather_tiled(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm,
+                                            (int)o.mapsA.size(), o.d_gtiles, (int)o.gtiles.size(), o.alpha.real(),
+                                            o.alpha.imag(), o.beta, o.conj, st);
+                else
+                    e = launch_gather(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm, (int)o.mapsA.size(),
+                                      o.n, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st, sb);
                 break;
             }
             case OP_GEMM: {

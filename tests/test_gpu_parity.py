@@ -77,12 +77,14 @@ def _system(spec):
     return fsgen.make_system(p[0], p[1], p[2], p[3], p[4])
 
 
+@pytest.mark.parametrize("tiled", [0, 1], ids=["storage-order", "tiled-gathers"])
 @pytest.mark.parametrize("spec", SYSTEMS, ids=[s[0] for s in SYSTEMS])
-def test_residual_matches_oracle(spec):
+def test_residual_matches_oracle(spec, tiled):
     torch = _torch()
     s = _system(spec)
-    print("case", spec, flush=True)
+    print("case", spec, tiled, flush=True)
     ctx = gpu_ctx(s)
+    ctx.gather_order(tiled)
     t1, t2 = allowed_random_t(s, 7)
     p1, p2 = LR.pack_t1(s, t1), LR.pack_t2(s, t2)
     assert (ctx.n1, ctx.n2) == (p1.size, p2.size)
@@ -106,6 +108,11 @@ def test_residual_matches_blocked_oracle_o20v120z8():
     d1, d2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
     r1, r2 = torch.empty_like(d1), torch.empty_like(d2)
     ctx.build_residual(d1, d2, r1, r2)
+    # the reorders by destination tiles give bitwise the same residual
+    ctx.gather_order(1)
+    q1, q2 = torch.empty_like(d1), torch.empty_like(d2)
+    ctx.build_residual(d1, d2, q1, q2)
+    assert torch.equal(q1, r1) and torch.equal(q2, r2)
     be = ccsd.Blocked(s)
     from oracle.blocks import BlockTensor
     bt1 = BlockTensor.from_dense(t1, [be.mem["O"], be.mem["V"]], list(be.D1.blocks.keys()))
@@ -198,4 +205,34 @@ def test_errors_are_reported():
     with pytest.raises(F.FsccError) as e:
         ctx.set_integrals("OOVV", torch.zeros(3, dtype=torch.complex128, device="cuda"))
     assert e.value.status == -1
+    ctx.destroy()
+
+
+def test_tiled_gathers_bitwise_equal_in_every_sector():
+    """(0h,0p), (0h,1p) and (0h,2p) residuals with every reorder walked by
+    destination tiles equal the storage-order ones bit for bit."""
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(8, 40, 4, 0.05, 9, nact=6)
+    ctx = gpu_ctx(s)
+    rng = np.random.default_rng(3)
+    def rnd(n):
+        return torch.from_numpy(0.05 * (rng.normal(size=n) + 1j * rng.normal(size=n))).cuda()
+    t1, t2 = allowed_random_t(s, 5, 0.02)
+    d1, d2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
+    ctx.prepare_sector(d1, d2)
+    s1, s2 = rnd(ctx.m1), rnd(ctx.m2)
+    ctx.prepare_sector(s1, s2, sector=F.FSCC_S02)
+    p2 = rnd(ctx.p2)
+    out = {}
+    for tiled in (0, 1):
+        ctx.gather_order(tiled)
+        r = [torch.empty_like(x) for x in (d1, d2, s1, s2, p2)]
+        ctx.build_residual(d1, d2, r[0], r[1])
+        ctx.build_residual(s1, s2, r[2], r[3], sector=F.FSCC_S01)
+        ctx.build_residual(None, p2, None, r[4], sector=F.FSCC_S02)
+        torch.cuda.synchronize()
+        out[tiled] = r
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
     ctx.destroy()
