@@ -286,6 +286,7 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
             rd.push_back(ZRed{p.c_off, woff, p.M, p.N, p.ldc, ns, p.sys, 0});
             g.maxS = std::max(g.maxS, ns);
             woff += (long long)ns * p.M * p.N;
+            if ((long long)p.M * p.N > 0x7FFFFFFFLL) throw std::length_error("split-K problem exceeds 2^31 outputs");
             maxMN = std::max(maxMN, p.M * p.N);
         }
     }

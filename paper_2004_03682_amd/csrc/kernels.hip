@@ -919,6 +919,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce_few(double2* __restrict__
     const ZRed r = reds[blockIdx.y];
     if (active && !active[r.sys]) return;
     const long long mn = (long long)r.M * r.N;
+    if ((long long)blockIdx.x * blockDim.x >= mn) return;   // whole workgroup past this problem
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mn) return;
     const double2* w = W + r.w_off + e;
@@ -941,8 +942,14 @@ __global__ __launch_bounds__(256) void k_splitk_reduce_few(double2* __restrict__
         sr += x.x;
         si += x.y;
     }
-    const int m = (int)(e / r.N), n = (int)(e % r.N);
-    double2* c = C + r.c_off + (long long)m * r.ldc + n;
+    // C rows contiguous (ldc == N): the output index is e itself; otherwise
+    // split it with 32-bit arithmetic (M*N < 2^31, checked by the planner)
+    long long ci = e;
+    if (r.ldc != r.N) {
+        const unsigned ue = (unsigned)e, un = (unsigned)r.N;
+        ci = (long long)(ue / un) * r.ldc + (ue % un);
+    }
+    double2* c = C + r.c_off + ci;
     double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
     if (beta) {
         const double2 old = *c;

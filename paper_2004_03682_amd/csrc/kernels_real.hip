@@ -420,8 +420,12 @@ __global__ __launch_bounds__(256) void k_dsplitk_reduce_few(double* __restrict__
         s += x3;
     }
     for (; q < r.S; ++q) s += w[(long long)q * mn];
-    const int m = (int)(e / r.N), n = (int)(e % r.N);
-    double* c = C + r.c_off + (long long)m * r.ldc + n;
+    long long ci = e;   // contiguous rows: the output index is e
+    if (r.ldc != r.N) {
+        const unsigned ue = (unsigned)e, un = (unsigned)r.N;
+        ci = (long long)(ue / un) * r.ldc + (ue % un);
+    }
+    double* c = C + r.c_off + ci;
     double out = alpha * s;
     if (beta) out += *c;
     *c = out;

@@ -63,6 +63,28 @@ def test_zgemm_split_k_and_edges(cfg):
         assert err < 1e-13, (cfg, M, N, K, beta, err)
 
 
+@pytest.mark.parametrize("cfg", (9 | M3, 0 | M3, 5, 6, 8))
+def test_split_k_pass_with_padded_c(cfg):
+    """Split-K into a C with row stride ldc > N: the reduction pass writes the
+    M x N block and leaves the padding columns untouched."""
+    import torch
+    import paper_2004_03682_amd as F
+    rng = np.random.default_rng(5)
+    for (M, N, K, ldc, beta) in [(7, 34, 3000, 41, 1), (130, 70, 1200, 77, 0), (5, 200, 1800, 203, 1)]:
+        if cfg == 8 and M > 8:   # the reduction form takes M <= 8
+            continue
+        A, B = _rand(rng, M, K), _rand(rng, K, N)
+        C0 = _rand(rng, M, ldc)
+        alpha = 0.6 + 0.2j
+        ref = C0.copy()
+        ref[:, :N] = alpha * (A @ B) + (C0[:, :N] if beta else 0)
+        dA, dB, dC = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (A, B, C0))
+        F.zgemm(dA, dB, dC, M, N, K, K, N, ldc, 0, 0, 0, 0, alpha, beta, cfg, 16, True)
+        out = dC.cpu().numpy()
+        assert np.array_equal(out[:, N:], C0[:, N:])
+        assert np.abs(out - ref).max() / max(1.0, np.abs(ref).max()) < 1e-13, (cfg, M, N, K, ldc)
+
+
 TALL, RED, DOT = 7, 8, 11
 
 
