@@ -102,7 +102,8 @@ void merge_plans(const std::vector<std::unique_ptr<Plan>>& sub, Plan& M, std::ve
                         for (size_t s = 0; s < nsys; ++s) {
                             const Op& os = sub[s]->ops[k];
                             const std::vector<uint32_t>& ms = sub[s]->maps[second ? os.mapsB[t] : os.mapsA[t]];
-                            const int64_t sh = base[s][second ? o0.src2 : o0.src];
+                            const int src_t = second ? o0.src2 : (t < o0.srcT.size() ? o0.srcT[t] : o0.src);
+                            const int64_t sh = base[s][src_t];
                             for (uint32_t e : ms) {
                                 if (e == MAP_ZERO) {
                                     m.push_back(e);

@@ -1268,7 +1268,8 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
         // every reader of the buffer must be a GEMM taking it as a transposed B
         for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01, &ctx->L02p, &ctx->L02})
             for (auto& o : *L->ops) {
-                const bool reads = o.src == b || o.dst == b || o.src2 == b;
+                const bool reads = o.src == b || o.dst == b || o.src2 == b ||
+                                   std::find(o.srcT.begin(), o.srcT.end(), b) != o.srcT.end();
                 if (reads && !(o.kind == OP_GEMM && o.src2 == b && o.tB && L != &ctx->L01p && L != &ctx->L02p))
                     return fail(ctx, FSCC_EINVAL, "operation " + o.name + " cannot stream VVVV");
             }

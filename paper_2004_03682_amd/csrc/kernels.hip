@@ -1009,7 +1009,7 @@ __device__ __forceinline__ void gather_elem(double2* __restrict__ dst, const dou
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        double2 x = map_load(src, maps.a[t][k]);
+        double2 x = map_load(maps.src[t] ? (const double2*)maps.src[t] : src, maps.a[t][k]);
         if (conj) x.y = -x.y;
         if (BIL) {
             double2 y = map_load(src2, maps.b[t][k]);

@@ -109,10 +109,13 @@ struct SegBlocks {
     int nblk = 0;
 };
 
-// dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
+// dst[k] = beta*dst[k] + alpha * sum_t s_t cj(src_t[mA_t[k]]) * (src2 ? src2[mB_t[k]] : 1)
+// src[t], when set, is term t's own source (a sum of reorders of different
+// buffers into one destination); otherwise term t reads the call's src
 struct GatherMaps {
     const uint32_t* a[4];
     const uint32_t* b[4];
+    const void* src[4];
 };
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
                          long long n, double ar, double ai, int beta, int conj, hipStream_t st,

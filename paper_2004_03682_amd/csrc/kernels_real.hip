@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void k_dgather(double* __restrict__ dst, const
     double s = 0.0;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        double x = dmap_load(src, maps.a[t][k]);
+        double x = dmap_load(maps.src[t] ? (const double*)maps.src[t] : src, maps.a[t][k]);
         if (BIL) x *= dmap_load(src2, maps.b[t][k]);
         s += x;
     }

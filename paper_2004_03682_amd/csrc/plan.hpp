@@ -54,6 +54,7 @@ struct Op {
     std::string name;
     int dst = -1, src = -1, src2 = -1;
     std::vector<int> mapsA, mapsB;   // gather maps (map ids)
+    std::vector<int> srcT;           // gathers summing reorders of several buffers: term t's source
     cplx alpha = 1.0;
     int beta = 0;
     bool conj = false;

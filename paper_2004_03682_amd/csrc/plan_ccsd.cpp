@@ -50,6 +50,21 @@ struct Builder {
         std::vector<int> perm2;   // for the second operand (bilinear); empty if none
     };
 
+    // 16 x 16 tiles of the destination blocks (row-major, leading dimension = columns)
+    static std::vector<GTile> dest_tiles(const Layout& Ld) {
+        std::vector<GTile> t;
+        if (Ld.total < 256) return t;
+        for (int k = 0; k < Ld.G; ++k) {
+            if (!Ld.kmask[k] || Ld.nrow[k] == 0 || Ld.ncol[k] == 0) continue;
+            for (int64_t r = 0; r < Ld.nrow[k]; r += 16)
+                for (int64_t c = 0; c < Ld.ncol[k]; c += 16)
+                    t.push_back(GTile{Ld.boff[k] + r * Ld.ncol[k] + c, (int32_t)Ld.ncol[k],
+                                      (int16_t)std::min<int64_t>(16, Ld.nrow[k] - r),
+                                      (int16_t)std::min<int64_t>(16, Ld.ncol[k] - c)});
+        }
+        return t;
+    }
+
     void gather(const std::string& name, int dst, const Layout& Ld, int src, const Layout& Ls,
                 const std::vector<Term>& terms, cplx alpha, int beta, bool conj = false, int src2 = -1,
                 const Layout* Ls2 = nullptr) {
@@ -65,19 +80,38 @@ struct Builder {
         op.n = Ld.total;
         if (P.bufs[dst].n != Ld.total) throw std::logic_error("gather dst size mismatch: " + name);
         if (P.bufs[src].n != Ls.total) throw std::logic_error("gather src size mismatch: " + name);
-        if (Ld.total >= 256)
-            for (int k = 0; k < Ld.G; ++k) {
-                if (!Ld.kmask[k] || Ld.nrow[k] == 0 || Ld.ncol[k] == 0) continue;
-                for (int64_t r = 0; r < Ld.nrow[k]; r += 16)
-                    for (int64_t c = 0; c < Ld.ncol[k]; c += 16)
-                        op.gtiles.push_back(GTile{Ld.boff[k] + r * Ld.ncol[k] + c, (int32_t)Ld.ncol[k],
-                                                  (int16_t)std::min<int64_t>(16, Ld.nrow[k] - r),
-                                                  (int16_t)std::min<int64_t>(16, Ld.ncol[k] - c)});
-            }
+        op.gtiles = dest_tiles(Ld);
         for (size_t t = 0; t < terms.size(); ++t) {
             op.mapsA.push_back(P.map(name + "/A" + std::to_string(t), build_map(Ld, Ls, terms[t].perm, terms[t].sign)));
             if (src2 >= 0)
                 op.mapsB.push_back(P.map(name + "/B" + std::to_string(t), build_map(Ld, *Ls2, terms[t].perm2, 1)));
+        }
+        out->push_back(std::move(op));
+    }
+
+    // dst = beta*dst + alpha * sum_t s_t src_t[perm_t]: reorders of several
+    // buffers summed into one destination in a single pass (term order kept)
+    void gather_sum(const std::string& name, int dst, const Layout& Ld,
+                    const std::vector<std::pair<int, const Layout*>>& srcs, const std::vector<Term>& terms,
+                    cplx alpha, int beta) {
+        if (srcs.size() != terms.size() || terms.empty() || terms.size() > 4)
+            throw std::logic_error("gather_sum: one source per term, 1..4 terms: " + name);
+        Op op;
+        op.kind = OP_GATHER;
+        op.name = name;
+        op.dst = dst;
+        op.src = srcs[0].first;
+        op.alpha = alpha;
+        op.beta = beta;
+        op.n = Ld.total;
+        if (P.bufs[dst].n != Ld.total) throw std::logic_error("gather dst size mismatch: " + name);
+        op.gtiles = dest_tiles(Ld);
+        for (size_t t = 0; t < terms.size(); ++t) {
+            if (P.bufs[srcs[t].first].n != srcs[t].second->total)
+                throw std::logic_error("gather src size mismatch: " + name);
+            op.srcT.push_back(srcs[t].first);
+            op.mapsA.push_back(P.map(name + "/A" + std::to_string(t),
+                                     build_map(Ld, *srcs[t].second, terms[t].perm, terms[t].sign)));
         }
         out->push_back(std::move(op));
     }
@@ -364,11 +398,12 @@ void build_plan_ccsd(const System& S, Plan& P) {
     Layout L_X9b = make_layout("X9b", G, {s(0, o, 1), s(1, v, -1), s(2, v, 1)}, -1, {s(3, o, 1)}, -1, 1);
     int b_X9b = P.buf("X9b", L_X9b.total, BUF_SCRATCH);
     B.gemm("W.t1.ovvv", b_ovvv_9b, L_ovvv_9b, false, false, P.b_t1, L_T1, true, false, b_X9b, L_X9b, 1.0, 0);
-    B.gather("W+=X9b", b_W, L_W, b_X9b, L_X9b, {T{{0, 2, 1, 3}, 1, {}}}, 1.0, 1);
     Layout L_X9c = make_layout("X9c", G, {s(0, o, -1), s(1, v, 1), s(2, o, 1)}, -1, {s(3, v, 1)}, -1, 1);
     int b_X9c = P.buf("X9c", L_X9c.total, BUF_SCRATCH);
     B.gemm("W.t1.ooov", b_oovo_9c, L_oovo_9c, false, false, P.b_t1, L_T1, false, false, b_X9c, L_X9c, -1.0, 0);
-    B.gather("W+=X9c", b_W, L_W, b_X9c, L_X9c, {T{{0, 2, 3, 1}, 1, {}}}, 1.0, 1);
+    // W += X9b + X9c in one pass over W
+    B.gather_sum("W+=X9b+X9c", b_W, L_W, {{b_X9b, &L_X9b}, {b_X9c, &L_X9c}},
+                 {T{{0, 2, 1, 3}, 1, {}}, T{{0, 2, 3, 1}, 1, {}}}, 1.0, 1);
     // U_(n,f),(j,b) = 1/2 t_jn^fb + t_j^f t_n^b  : logical (n,f,j,b)
     Layout L_U = make_layout("U", G, {s(0, o, 1), s(1, v, -1)}, -1, {s(2, o, -1), s(3, v, 1)}, -1, 1);
     int b_U = P.buf("U", L_U.total, BUF_SCRATCH);

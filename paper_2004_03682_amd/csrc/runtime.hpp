@@ -278,6 +278,7 @@ struct fscc_ctx {
                 for (int t = 0; t < 4; ++t) {
                     gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
                     gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
+                    gm.src[t] = t < (int)o.srcT.size() ? (const void*)D(o.srcT[t]) : nullptr;
                 }
                 return launch_dgather(D(o.dst), D(o.src), o.src2 >= 0 ? D(o.src2) : nullptr, gm, (int)o.mapsA.size(),
                                       o.n, o.alpha.real(), o.beta, st);
@@ -326,6 +327,7 @@ struct fscc_ctx {
                 for (int t = 0; t < 4; ++t) {
                     gm.a[t] = t < (int)o.mapsA.size() ? dmap[o.mapsA[t]] : nullptr;
                     gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
+                    gm.src[t] = t < (int)o.srcT.size() ? (const void*)B(o.srcT[t]) : nullptr;
                 }
                 if (o.use_gtiles && o.d_gtiles && !sb.sys)
                     e = launch_gather_tiled(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm,
