@@ -1,15 +1,27 @@
 """Writes tests/golden/*.json from the CPU oracle only (run by hand; committed output).
 
-  python tests/golden/make_golden.py
+  python tests/golden/make_golden.py                 # o20v120z8_ccsd.json
+  python tests/golden/make_golden.py o40v300z16      # o40v300z16_ccsd.json (about an hour on 8 cores)
 
 o20v120z8_ccsd.json: converged (0h,0p) CCSD correlation energy of the 20-occupied /
 120-virtual / Z8 synthetic system (seed 1001) from the block-list oracle, with
 Jacobi + DIIS(6) to max|step| < 1e-10.
+
+o40v300z16_ccsd.json: the production-size system (40 occupied / 300 virtual / Z16,
+seed 1002) converged by the block-list oracle with Jacobi + DIIS(6) (the fixed point
+of Eq. (3)) to max|step| < 1e-12, so that the stored values are the fixed point itself
+and not one more iterate.  Stored: E (re, im), the per-iteration energy and max|step|
+trajectory (iteration count to 1e-10 included), every T1 element, and a seeded sample of
+unique T2 elements (i<j, a<b, allowed by the Z16 selection rule) plus the 64 largest
+|t2|, each as (i, j, a, b, re, im) with spinor positions counted inside the occupied and
+virtual spaces.
 """
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -17,8 +29,10 @@ sys.path.insert(0, ROOT)
 import fsgen  # noqa: E402
 from oracle import ccsd, solver  # noqa: E402
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 
-def main():
+
+def small():
     s = fsgen.workload_system("o20v120z8")
     be = ccsd.Blocked(s)
     t0 = time.time()
@@ -26,11 +40,98 @@ def main():
     out = dict(config=fsgen.WORKLOADS["o20v120z8"], E_re=r["E"].real, E_im=r["E"].imag, iters=r["iters"],
                converged=r["converged"], tol=1e-10, mp2=float(ccsd.mp2_energy_closed_form(be).real),
                oracle="oracle.solver.solve_ccsd(oracle.ccsd.Blocked)", seconds=round(time.time() - t0, 1))
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "o20v120z8_ccsd.json")
-    with open(path, "w") as f:
+    with open(os.path.join(HERE, "o20v120z8_ccsd.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(out)
 
 
+def _element(be, t, idx):
+    """Element of a block-list amplitude at space positions idx = (i, a) or (i, j, a, b)."""
+    spaces = "OV" if len(idx) == 2 else "OOVV"
+    irr = be.sys.irrep
+    no = be.sys.nocc
+    key, loc = [], []
+    for X, p in zip(spaces, idx):
+        g = int(irr[p if X == "O" else no + p])
+        key.append(g)
+        loc.append(int(np.searchsorted(be.mem[X][g], p)))
+    blk = t.blocks.get(tuple(key))
+    return 0j if blk is None else complex(blk[tuple(loc)])
+
+
+def t2_sample(be, t2, count, seed, top):
+    """Seeded unique (i<j, a<b) elements allowed by the selection rule, plus the `top` largest."""
+    s = be.sys
+    no, nv, n = s.nocc, s.nvirt, s.nirrep
+    go, gv = s.irrep[:no], s.irrep[no:]
+    rng = np.random.default_rng(seed)
+    picked = set()
+    while len(picked) < count:
+        i, j = sorted(rng.choice(no, 2, replace=False))
+        a = int(rng.integers(nv))
+        # b must carry the irrep that conserves symmetry and differ from a
+        gb = (int(go[i]) + int(go[j]) - int(gv[a])) % n
+        cand = np.nonzero(gv == gb)[0]
+        cand = cand[cand != a]
+        if cand.size == 0:
+            continue
+        b = int(rng.choice(cand))
+        picked.add((int(i), int(j), min(a, b), max(a, b)))
+    big = []
+    for key, blk in t2.blocks.items():
+        mo = [be.mem["O"][key[0]], be.mem["O"][key[1]]]
+        mv = [be.mem["V"][key[2]], be.mem["V"][key[3]]]
+        flat = np.argsort(-np.abs(blk).ravel())[:top]
+        for f in flat:
+            ii, jj, aa, bb = np.unravel_index(f, blk.shape)
+            i, j, a, b = int(mo[0][ii]), int(mo[1][jj]), int(mv[0][aa]), int(mv[1][bb])
+            if i < j and a < b:
+                big.append((abs(blk[ii, jj, aa, bb]), (i, j, a, b)))
+    big.sort(key=lambda x: -x[0])
+    for _, e in big[:top]:
+        picked.add(e)
+    out = []
+    for e in sorted(picked):
+        v = _element(be, t2, e)
+        out.append([*e, v.real, v.imag])
+    return out
+
+
+def production():
+    name = "o40v300z16"
+    s = fsgen.workload_system(name)
+    t0 = time.time()
+    be = ccsd.Blocked(s)
+    setup = time.time() - t0
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    t0 = time.time()
+    r = solver.solve_ccsd(be, tol=1e-12, maxit=200, log=log)
+    solve = time.time() - t0
+    hist = r["history"]
+    it10 = next((h["iter"] for h in hist if h["dmax"] < 1e-10), None)
+    t1 = []
+    for i in range(s.nocc):
+        for a in range(s.nvirt):
+            if s.irrep[i] == s.irrep[s.nocc + a]:
+                v = _element(be, r["t1"], (i, a))
+                t1.append([i, a, v.real, v.imag])
+    t2 = t2_sample(be, r["t2"], 4096, 7, 64)
+    cfg = dict(fsgen.WORKLOADS[name])
+    out = dict(config=cfg, E_re=r["E"].real, E_im=r["E"].imag, iters=r["iters"], converged=r["converged"],
+               tol=1e-12, iters_to_1e10=it10,
+               E_at_1e10=[hist[it10 - 1]["E"].real, hist[it10 - 1]["E"].imag] if it10 else None,
+               history=[[h["iter"], h["E"].real, h["E"].imag, h["dmax"]] for h in hist],
+               mp2=float(ccsd.mp2_energy_closed_form(be).real),
+               t1=t1, t2_sample=t2, t2_sample_seed=7, t2_top=64,
+               oracle="oracle.solver.solve_ccsd(oracle.ccsd.Blocked, tol=1e-12)",
+               setup_seconds=round(setup, 1), seconds=round(solve, 1))
+    with open(os.path.join(HERE, name + "_ccsd.json"), "w") as f:
+        json.dump(out, f, indent=0)
+    print({k: v for k, v in out.items() if k not in ("t1", "t2_sample", "history")})
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "o40v300z16":
+        production()
+    else:
+        small()
