@@ -284,6 +284,24 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
                        const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void *hip_stream);
 
+/* Size of the static device array of fscc_zgemm_noalloc (bytes per GPU). */
+#define FSCC_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* fscc_zgemm for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and result,
+ * but the problem / tile / split-K tables and the split-K partial sums live in
+ * one static device array of FSCC_NOALLOC_SCRATCH_BYTES per GPU (held until
+ * the process ends) instead of buffers allocated per call; no hipMalloc or
+ * hipFree is called.  A K split whose partial sums do not fit the array runs
+ * unsplit; a plan whose tables alone do not fit returns FSCC_EINVAL.  Every
+ * call on one GPU uses that GPU's array: calls that overlap on one GPU (from
+ * two host threads at once) race.  Synchronises hip_stream.  The message of
+ * a failed call (of this one or fscc_zgemm) is fscc_last_error(NULL) on the
+ * calling thread. */
+fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, int M, int N, int K,
+                               const fscc_c128 *A, int lda, const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc,
+                               double alpha_re, double alpha_im, int beta, int allow_split, void *hip_stream);
+
 /* Real form of fscc_zgemm (kernel-level tests of the real-arithmetic path):
  * C = alpha * op(A) op(B) + beta*C on doubles, same layout conventions and
  * kernel forms except 6 (skinny), which has no real form (FSCC_EINVAL).
@@ -379,6 +397,8 @@ fscc_status fscc_zgemm_split(int prec, int cfg, int tA, int tB, int cA, int cB, 
                              double alpha_re, double alpha_im, int beta, void *hip_stream);
 
 void fscc_destroy(fscc_ctx *ctx);
+/* Message of the last failed call on ctx; with ctx = NULL, of the last failed
+ * context-free GEMM call (fscc_zgemm, fscc_zgemm_noalloc) on this thread. */
 const char *fscc_last_error(const fscc_ctx *ctx);
 
 /* ---- batches of independent systems (the block-loop structure of Fig. 4

@@ -66,6 +66,7 @@ def lib():
             "fscc_autotune": ([vp, ip], ip),
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
+            "fscc_zgemm_noalloc": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
             "fscc_set_precision": ([vp, ip], ip),
             "fscc_profile_select": ([vp, ip], ip),
             "fscc_level_shift": ([vp, ip, ctypes.c_double], ip),
@@ -499,7 +500,21 @@ def zgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=Fals
                          _dev_ptr(A), int(lda), _dev_ptr(B), int(ldb), _dev_ptr(C), int(ldc), alpha.real, alpha.imag,
                          int(beta), int(allow_split), ctypes.c_void_p(st.cuda_stream))
     if r != 0:
-        raise FsccError(r, "fscc_zgemm failed")
+        raise FsccError(r, "fscc_zgemm failed: " + lib().fscc_last_error(None).decode())
+
+
+def zgemm_noalloc(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, cA=False, cB=False, alpha=1.0, beta=0,
+                  cfg=-1, bk=16, allow_split=True, stream=None):
+    """fscc_zgemm_noalloc: zgemm() with its tables and split-K partial sums in the
+    library's static device array (no device allocation)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    alpha = complex(alpha)
+    r = lib().fscc_zgemm_noalloc(int(cfg), int(bk), int(tA), int(tB), int(cA), int(cB), int(M), int(N), int(K),
+                                 _dev_ptr(A), int(lda), _dev_ptr(B), int(ldb), _dev_ptr(C), int(ldc), alpha.real,
+                                 alpha.imag, int(beta), int(allow_split), ctypes.c_void_p(st.cuda_stream))
+    if r != 0:
+        raise FsccError(r, "fscc_zgemm_noalloc failed: " + lib().fscc_last_error(None).decode())
 
 
 def dgemm(A, B, C, M, N, K, lda, ldb, ldc, tA=False, tB=False, alpha=1.0, beta=0, cfg=-1, bk=16, allow_split=True,

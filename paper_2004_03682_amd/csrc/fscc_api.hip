@@ -220,10 +220,17 @@ void apply_precision(fscc_ctx* c, int prec) {
     c->prec = prec;
 }
 
-void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split, bool m3) {
+std::string& free_call_error() {
+    static thread_local std::string msg;
+    return msg;
+}
+
+void plan_gemm_host(bool real, const Op& o, int cfg, int bk, bool allow_split, bool m3, GemmHost& h) {
+    h = GemmHost();
+    GemmDev& g = h.g;
     g.cfg = cfg;
     g.bk = bk;
-    g.m3 = m3 && !c->real && cfg != ZCFG_SKINNY && cfg != ZCFG_TALL && cfg != ZCFG_RED && cfg != ZCFG_DOT;
+    g.m3 = m3 && !real && cfg != ZCFG_SKINNY && cfg != ZCFG_TALL && cfg != ZCFG_RED && cfg != ZCFG_DOT;
     g.role = o.name == "pp-ladder" ? 1 : (o.name == "ring" || o.name == "W.U") ? 2 : 0;
     int bm, bn;
     zcfg_tile(g.cfg, &bm, &bn);
@@ -260,10 +267,10 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
             Sq[q] = std::max(1, std::min(S, (o.probs[q].K + 255) / 256));
             split |= Sq[q] > 1;
         }
-    std::vector<ZProb> pr;
+    std::vector<ZProb>& pr = h.pr;
     std::vector<int> psys;
     std::vector<ZTile> tl;
-    std::vector<ZRed> rd;
+    std::vector<ZRed>& rd = h.rd;
     long long woff = 0;
     int maxMN = 0;
     for (size_t q = 0; q < o.probs.size(); ++q) {
@@ -300,19 +307,28 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
     }
     // longest-K tiles first (uneven symmetry blocks)
     std::stable_sort(tl.begin(), tl.end(), [&](const ZTile& a, const ZTile& b) { return pr[a.prob].K > pr[b.prob].K; });
-    tl = xcd_order(tl);
-    g.ntiles = (int)tl.size();
-    g.probs = (ZProb*)c->dalloc(std::max<size_t>(1, pr.size()) * sizeof(ZProb));
-    g.tiles = (ZTile*)c->dalloc(std::max<size_t>(1, tl.size()) * sizeof(ZTile));
-    if (!pr.empty()) hip_check(hipMemcpy(g.probs, pr.data(), pr.size() * sizeof(ZProb), hipMemcpyHostToDevice), "probs");
-    if (!tl.empty()) hip_check(hipMemcpy(g.tiles, tl.data(), tl.size() * sizeof(ZTile), hipMemcpyHostToDevice), "tiles");
+    h.tl = xcd_order(tl);
+    g.ntiles = (int)h.tl.size();
     g.split = split;
     if (split) {
         g.nred = (int)rd.size();
         g.maxMN = maxMN;
-        g.reds = (ZRed*)c->dalloc(rd.size() * sizeof(ZRed));
-        hip_check(hipMemcpy(g.reds, rd.data(), rd.size() * sizeof(ZRed), hipMemcpyHostToDevice), "reds");
-        g.work = (double2*)c->dalloc((size_t)std::max<long long>(1, woff) * c->esz());
+    }
+    h.work_elems = split ? std::max<long long>(1, woff) : 0;
+}
+
+void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split, bool m3) {
+    GemmHost h;
+    plan_gemm_host(c->real, o, cfg, bk, allow_split, m3, h);
+    g = h.g;
+    g.probs = (ZProb*)c->dalloc(std::max<size_t>(1, h.pr.size()) * sizeof(ZProb));
+    g.tiles = (ZTile*)c->dalloc(std::max<size_t>(1, h.tl.size()) * sizeof(ZTile));
+    if (!h.pr.empty()) hip_check(hipMemcpy(g.probs, h.pr.data(), h.pr.size() * sizeof(ZProb), hipMemcpyHostToDevice), "probs");
+    if (!h.tl.empty()) hip_check(hipMemcpy(g.tiles, h.tl.data(), h.tl.size() * sizeof(ZTile), hipMemcpyHostToDevice), "tiles");
+    if (g.split) {
+        g.reds = (ZRed*)c->dalloc(h.rd.size() * sizeof(ZRed));
+        hip_check(hipMemcpy(g.reds, h.rd.data(), h.rd.size() * sizeof(ZRed), hipMemcpyHostToDevice), "reds");
+        g.work = (double2*)c->dalloc((size_t)h.work_elems * c->esz());
     }
 }
 
@@ -503,7 +519,11 @@ static std::vector<std::vector<StreamChunk>> stream_plan(fscc_ctx* c, OpList& L,
 
 extern "C" {
 
-const char* fscc_last_error(const fscc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* fscc_last_error(const fscc_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    const std::string& e = free_call_error();
+    return e.empty() ? "null context" : e.c_str();
+}
 
 fscc_status fscc_create(const fscc_system* sys, fscc_precision prec, void* hip_stream, fscc_ctx** out) {
     if (!sys || !out) return FSCC_EINVAL;
@@ -1438,6 +1458,7 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         free_gemm(g);
         return FSCC_OK;
     });
+    if (s != FSCC_OK) free_call_error() = c->err;
     delete c;
     return s;
 }

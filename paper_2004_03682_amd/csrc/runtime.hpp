@@ -496,6 +496,14 @@ inline fscc_status fail(fscc_ctx* c, fscc_status s, const std::string& msg) {
     return s;
 }
 
+// Last error message of the context-free calls (fscc_zgemm, fscc_zgemm_noalloc)
+// on the calling thread; fscc_last_error(NULL) returns it.
+std::string& free_call_error();
+inline fscc_status free_call_fail(fscc_status s, const std::string& msg) {
+    free_call_error() = msg;
+    return s;
+}
+
 template <class F>
 fscc_status guarded(fscc_ctx* c, F f) {
     try {
@@ -523,6 +531,17 @@ MixedDev* plan_mixed(fscc_ctx* c, const Op& o, int prec, int cfg);
 int pick_mcfg(const Op& o);
 void apply_precision(fscc_ctx* c, int prec);
 void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow_split, bool m3 = true);
+// The host half of plan_gemm: problem, tile and split-K reduction tables of one
+// GEMM op, and the split-K workspace size (complex or real elements).  h.g
+// holds the launch parameters with null device pointers.
+struct GemmHost {
+    GemmDev g;
+    std::vector<ZProb> pr;
+    std::vector<ZTile> tl;
+    std::vector<ZRed> rd;
+    long long work_elems = 0;
+};
+void plan_gemm_host(bool real, const Op& o, int cfg, int bk, bool allow_split, bool m3, GemmHost& h);
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops);
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2);
 void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2);
