@@ -130,6 +130,11 @@ class Dense:
     def dense(self, x):
         return x
 
+    def fock_diag(self, X):
+        """The diagonal Fock matrix diag(eps) of space 'O' or 'V'."""
+        no = self.sys.nocc
+        return np.diag(self.sys.eps[:no] if X == "O" else self.sys.eps[no:])
+
 
 def _views(sysm, C, buf):
     """Block views of an already generated class buffer (boundary layout)."""
@@ -216,6 +221,12 @@ class Blocked:
             r = r + x * c
         return r
 
+    def fock_diag(self, X):
+        """diag(eps) of space 'O' or 'V' as one diagonal block per irrep."""
+        no = self.sys.nocc
+        e = self.sys.eps[:no] if X == "O" else self.sys.eps[no:]
+        return BlockTensor(2, {(g, g): np.diag(e[m]) for g, m in enumerate(self.mem[X]) if m.size})
+
     def dense(self, x):
         no, nv = self.sys.nocc, self.sys.nvirt
         spaces = "OV" if x.rank == 2 else "OOVV"
@@ -233,7 +244,9 @@ def _P(x, a, b):
     return x - x.transpose(ax)
 
 
-def intermediates(be, t1, t2, progress=None):
+def intermediates(be, t1, t2, progress=None, one_body_only=False):
+    """The intermediates listed in the module docstring; one_body_only=True stops
+    after tau, tau~ and the three F intermediates."""
     ein, V = be.ein, be.V
     say = progress or (lambda msg: None)
     t1t1 = ein("ia,jb->ijab", t1, t1)
@@ -243,6 +256,8 @@ def intermediates(be, t1, t2, progress=None):
     Fmi = ein("ne,mnie->mi", t1, V("ooov")) + 0.5 * ein("inef,mnef->mi", tau_t, V("oovv"))
     Fme = ein("nf,mnef->me", t1, V("oovv"))
     say("F intermediates")
+    if one_body_only:
+        return dict(tau=tau, tau_t=tau_t, Fae=Fae, Fmi=Fmi, Fme=Fme)
     Wmnij = (V("oooo") + _P(ein("je,mnie->mnij", t1, V("ooov")), 2, 3)
              + 0.25 * ein("ijef,mnef->mnij", tau, V("oovv")))
     Wabef = (V("vvvv") - _P(ein("mb,amef->abef", t1, V("vovv")), 0, 1)

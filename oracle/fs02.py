@@ -40,13 +40,17 @@ algebra above and are pinned against a brute-force construction of
 Omega |xy> and exp(-T) H exp(T) on the (N+2)-electron Fock space
 (oracle.fock.dea_state / hbar_apply).  Update: s += R / D with
 D_xy^ab = e_x + e_y - e_a - e_b; with dynamic shifts (oracle.shift)
-s += (R - Delta s) / (D + Delta).  Dense backend only.
+s += (R - Delta s) / (D + Delta).  FS02 runs on the dense backend; FS02Blocked
+evaluates the same terms with the four-index Hbar elements (Wbar_abef,
+Wbar_amef, <mn||ef>) as block lists and everything that carries the pair index
+(at most npair x nvirt x nvirt) dense.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import fs01
+from .blocks import BlockTensor, bein
 
 
 def _A(x):
@@ -120,6 +124,86 @@ class FS02:
         w = self.wpp + s
         R = sg - np.einsum("qab,qp->pab", w, heff)
         return np.where(self.mask, R, 0.0), heff
+
+
+class FS02Blocked(FS02):
+    """FS02 on top of an FS01Blocked sector.  The pair amplitudes s[p, a, b],
+    K, the denominators and the residual stay dense (p over the pairs x < y of
+    positions in the active list, as in FS02); the contractions with Wbar_abef,
+    Wbar_amef and <mn||ef> run over block lists, the pair index carrying the
+    pair irrep g_x + g_y."""
+
+    def __init__(self, f01: fs01.FS01Blocked, s1, s2, shift=None):
+        be, hb = f01.be, f01.hb
+        ein = be.ein
+        self.f01 = f01
+        self.no, self.nv, self.nact = f01.no, f01.nv, f01.nact
+        act = f01.act
+        n = be.sys.nirrep
+        mV = be.mem["V"]
+        self.pairs = [(x, y) for x in range(self.nact) for y in range(x + 1, self.nact)]
+        self.npair = len(self.pairs)
+        px = np.array([p[0] for p in self.pairs], int)
+        py = np.array([p[1] for p in self.pairs], int)
+        gA = be.sys.irrep[act + be.sys.nocc]
+        gp = (gA[px] + gA[py]) % n if self.npair else np.zeros(0, int)
+        self.memP = [np.nonzero(gp == G)[0] for G in range(n)]
+        self.keysP = [(G, ga, (G - ga) % n) for G in range(n) for ga in range(n)
+                      if self.memP[G].size and mV[ga].size and mV[(G - ga) % n].size]
+        r1b, r2b = f01.rvec(s1, s2)                     # block lists
+        sg1b, _ = fs01.sigma(be, hb, r1b, r2b)
+        r1, r2, sg1 = f01.to_dense(r1b), f01.to_dense(r2b), f01.to_dense(sg1b)
+        self.Wabef = hb["Wabef"]
+        self.Fvv = hb["Fae"].to_dense([mV, mV], (self.nv, self.nv))
+        r1x, r1y, r2x, r2y = r1[px], r1[py], r2[px], r2[py]
+        self.wpp = _A(r1x[:, :, None] * r1y[:, None, :])
+        K = _A(sg1[px][:, :, None] * r1y[:, None, :] + r1x[:, :, None] * sg1[py][:, None, :])
+        K = K + 0.5 * self._w_pairs(self.wpp)
+        g = be.ein("me,xe->xm", hb["Fme"], r1b) - 0.5 * bein("nmef,xnef->xm", be.V("oovv"), r2b)
+        g = g.to_dense([f01.memA, be.mem["O"]], (self.nact, self.no))
+        K = K + np.einsum("pm,pmab->pab", g[px], r2y) - np.einsum("pm,pmab->pab", g[py], r2x)
+        v = bein("amef,xf->xame", hb["Wamef"], r1b).to_dense([f01.memA, mV, be.mem["O"], mV],
+                                                            (self.nact, self.nv, self.no, self.nv))
+        # sum_me v(x)_ame s_ym^eb as one matrix product per pair ((m, e) contracted)
+        nme = self.no * self.nv
+        vx = v[px].reshape(self.npair, self.nv, nme)
+        vy = v[py].reshape(self.npair, self.nv, nme)
+        K = K + _A(np.matmul(vx, r2y.reshape(self.npair, nme, self.nv))
+                   - np.matmul(vy, r2x.reshape(self.npair, nme, self.nv)))
+        # sum_mnef <mn||ef> s_xm^ae s_yn^bf: Y_y[m, e, b] = sum_nf <mn||ef> s_yn^bf, then sum over (m, e)
+        Y = bein("mnef,ynbf->ymeb", be.V("oovv"), r2b).to_dense([f01.memA, be.mem["O"], mV, mV],
+                                                               (self.nact, self.no, self.nv, self.nv))
+        K = K + _A(np.matmul(r2x.transpose(0, 2, 1, 3).reshape(self.npair, self.nv, nme),
+                             Y[py].reshape(self.npair, nme, self.nv)))
+        self.K = K
+        self.ma = act[px]
+        self.mb = act[py]
+        ev = be.sys.eps[be.sys.nocc:]
+        exy = ev[self.ma] + ev[self.mb]
+        self.D = exy[:, None, None] - ev[None, :, None] - ev[None, None, :]
+        g_ = be.sys.irrep[be.sys.nocc:]
+        gxy = g_[self.ma] + g_[self.mb]
+        self.mask = ((gxy[:, None, None] - g_[None, :, None] - g_[None, None, :]) % n == 0)
+        ia = np.zeros(self.nv, bool)
+        ia[act] = True
+        self.mask &= ~(ia[:, None] & ia[None, :])[None]
+        self.mask &= ~np.eye(self.nv, dtype=bool)[None]
+        self.Delta = np.zeros_like(self.D)
+        if shift is not None:
+            from .shift import delta
+            self.Delta = delta(self.D, shift[0], shift[1])
+
+    def _w_pairs(self, w):
+        """sum_ef Wbar_abef w[p, e, f] over block lists (dense in and out)."""
+        mV = self.f01.be.mem["V"]
+        wb = BlockTensor.from_dense(w, [self.memP, mV, mV], self.keysP)
+        out = bein("abef,pef->pab", self.Wabef, wb)
+        return out.to_dense([self.memP, mV, mV], (self.npair, self.nv, self.nv))
+
+    def sigma2(self, s):
+        """sigma2(xy) for every model pair: the fixed part plus the S_xy terms."""
+        t = np.matmul(s, self.Fvv.T)                                 # sum_e Fbar_be s_xy^ae
+        return self.K + (t - np.swapaxes(t, 1, 2)) + 0.5 * self._w_pairs(s)
 
 
 def solve_fs02(fs, tol=1e-10, maxit=200, ndiis=6, log=None, start=None):
