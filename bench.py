@@ -776,9 +776,7 @@ def main():
         fs = {"nact": int(s.nact), "ms_per_iteration": round(el01 / max(1, n01) * 1e3, 4), "iterations": n01,
               "status": status, "last_max_step": d01, "preconditioner": "Hbar diagonal, floor 0.1 Eh"}
         if status == "converged":
-            h = ctx.heff(s1, s2)
-            w = np.linalg.eigvals(h)
-            w = w[np.lexsort((w.imag, w.real))]
+            w = F.heff_eig(ctx.heff(s1, s2))
             fs["heff_eigenvalues_re"] = [float(x.real) for x in w]
         log(f"(0h,1p): {status}; {n01} iterations, {fs['ms_per_iteration']:.3f} ms/iteration")
         # the intruder-state remedy: dynamic denominator shifts at decreasing

@@ -63,8 +63,10 @@
  *   fscc_create / fscc_set_integrals and released by fscc_destroy).
  *   All device work is ordered on the hip_stream given to fscc_create; a
  *   call with host outputs synchronises that stream before returning.
- *   No C++ exception crosses the ABI.  On error the outputs are untouched,
- *   the call returns a negative status and fscc_last_error() describes it.
+ *   No C++ exception crosses the ABI.  On error the outputs are untouched
+ *   (one exception: FSCC_ENOCONV from fscc_update_amplitudes after sustained
+ *   growth, where the amplitudes hold the last finite iterate), the call
+ *   returns a negative status and fscc_last_error() describes it.
  *   A context must not be used from two host threads at once.
  */
 #ifndef FSCC_H
@@ -90,7 +92,8 @@ typedef enum {
     FSCC_ENOMEM = -3,  /* device allocation failed                               */
     FSCC_EHIP = -4,    /* a HIP runtime call failed                              */
     FSCC_ESTATE = -5,  /* call out of order (e.g. integrals not all set)         */
-    FSCC_ENOCONV = -6  /* non-finite update (NaN / Inf in the step)              */
+    FSCC_ENOCONV = -6  /* the amplitude iteration diverges (fscc_update_amplitudes)
+                          or an eigenvalue iteration fails (fscc_heff_eig)          */
 } fscc_status;
 
 /* Arithmetic of a context.  FSCC_REAL_FP64 (fscc_create only): real double
@@ -114,7 +117,10 @@ typedef struct {
     const int32_t *active; /* host [nact], global indices of the active virtuals   */
 } fscc_system;
 
-/* Build the plan for one system: irrep-sorted index spaces, block layouts,
+/* Build the plan for one system (the second-quantised Hamiltonian of Eq. (1)
+ * given by its orbital energies and irrep labels; active virtual spinors
+ * select the model space of the (0h,1p) and (0h,2p) sectors of Eq. (5)):
+ * irrep-sorted index spaces, block layouts,
  * reorder maps and grouped-GEMM problem lists (the TTGT decomposition of
  * every contraction of the CCSD residual).  hip_stream may be NULL (the null
  * stream).  prec selects the arithmetic of the dominant contractions (see
@@ -124,11 +130,33 @@ fscc_status fscc_create(const fscc_system *sys, fscc_precision prec, void *hip_s
 /* Import one integral class (boundary layout above, n complex elements) and
  * pack it into the library's block layouts (integral sorting, step I of the
  * flowchart).  dev_blocks may be freed on return.  All six classes must be
- * set before fscc_build_residual / fscc_energy. */
+ * set before fscc_build_residual / fscc_energy.
+ * Input checks, before anything is packed (the class then stays unset, so a
+ * corrected buffer can be passed again):
+ *   - every value is finite (a full scan of the buffer), else FSCC_EINVAL;
+ *   - at a sample of elements (fscc_set_validation; 4096 per class by
+ *     default, seeded, so a call is reproducible) the symmetries of Eq. (1)'s
+ *     antisymmetrised integrals that relate two elements of the same class:
+ *     <pq||rs> = -<qp||rs> and <pq||rs> = -<pq||sr> where both indices of a
+ *     pair lie in one space, and Hermiticity <pq||rs> = conj <rs||pq> where
+ *     (pq) and (rs) span the same spaces (OOOO, OVOV, VVVV; plain symmetry in
+ *     a real context), each to 1e-10 of the largest sampled magnitude; a
+ *     violation returns FSCC_ESYMM naming the element.  Sampling can miss an
+ *     isolated bad element; systematic violations are caught. */
 fscc_status fscc_set_integrals(fscc_ctx *ctx, fscc_iclass cls, const fscc_c128 *dev_blocks, size_t n);
 
+/* Number of sampled elements per class for the symmetry checks of
+ * fscc_set_integrals (0 = no symmetry checks; the finiteness scan always
+ * runs).  0 <= nsample <= 2^20, else FSCC_EINVAL.  Applies to later
+ * fscc_set_integrals calls. */
+fscc_status fscc_set_validation(fscc_ctx *ctx, int nsample);
+
 /* Packed lengths (complex elements) of T1/R1 and T2/R2 for a sector (for
- * FSCC_S02: n1 = 0 and n2 = the length of S_xy^ab, see fscc_heff2). */
+ * FSCC_S02: n1 = 0 and n2 = the length of S_xy^ab, see fscc_heff2): the
+ * amplitudes of the wave operator of Eq. (2) restricted to the sector of
+ * Eq. (5), stored as the symmetry blocks of the block partition (Fig. 3) in
+ * the layouts given at the top of this file.  FSCC_EINVAL for a sector the
+ * system does not have (no active spinors, fewer than two for FSCC_S02). */
 fscc_status fscc_layout(const fscc_ctx *ctx, fscc_sector sector, size_t *n1, size_t *n2);
 
 /* R = RHS - D*t for the CCSD equations (Eq. (3)), D_i^a = e_i - e_a,
@@ -141,7 +169,15 @@ fscc_status fscc_build_residual(fscc_ctx *ctx, fscc_sector sector, const fscc_c1
  * ndiis (t', step) pairs (B_kl = Re <step_k, step_l> over the packed unique
  * amplitudes, bordered Pulay system solved on the device in FP64) writes the
  * extrapolated amplitudes into t1, t2.  *max_step (host) = max |step|.
- * Returns FSCC_ENOCONV if the step is not finite. */
+ * Divergence (the intruder-state failure of the iteration): the largest step
+ * of every iteration is watched per sector; a step more than 1e3 times the
+ * smallest one since the watch started (that smallest one taken as at least
+ * 1e-8) clears the DIIS subspace and restarts the watch from that step; a
+ * second such growth returns FSCC_ENOCONV with *max_step set and t1, t2
+ * holding the last (finite) iterate.  A step that is not finite returns
+ * FSCC_ENOCONV at once with t1, t2 left at their input values.  Either
+ * failure clears the DIIS subspace; fscc_diis_reset, fscc_prepare_sector,
+ * fscc_precondition and fscc_dynamic_shift restart the watch. */
 fscc_status fscc_update_amplitudes(fscc_ctx *ctx, fscc_sector sector, fscc_c128 *t1, fscc_c128 *t2,
                                    const fscc_c128 *r1, const fscc_c128 *r2, double *max_step);
 
@@ -190,6 +226,18 @@ fscc_status fscc_heff(fscc_ctx *ctx, const fscc_c128 *s1, const fscc_c128 *s2, f
  * energies relative to the (0h,0p) reference state.  Synchronises. */
 fscc_status fscc_heff2(fscc_ctx *ctx, const fscc_c128 *s, fscc_c128 *heff_host);
 
+/* Eigenvalues of an effective Hamiltonian (step V of the flowchart, Fig. 1:
+ * diagonalise H_eff = (H Omega)_Cl of a sector; its eigenvalues are the state
+ * energies relative to the (0h,0p) reference): heff_host is a dense row-major
+ * n x n complex matrix in host memory (e.g. the output of fscc_heff or
+ * fscc_heff2), eig_host receives its n eigenvalues sorted by real part (ties
+ * by imaginary part).  Host code only (no device work, no context): Householder
+ * reduction to Hessenberg form, then single-shift complex QR iterations with
+ * the Wilkinson shift and deflation.  FSCC_EINVAL for n outside 0..4096, null
+ * arrays or non-finite elements; FSCC_ENOCONV if the QR iteration does not
+ * converge in 60 n steps. */
+fscc_status fscc_heff_eig(int n, const fscc_c128 *heff_host, fscc_c128 *eig_host);
+
 /* Jacobi denominators of the (0h,1p) sector (sector = FSCC_S01).  mode 0:
  * D from the orbital energies (Eq. (3)-(4), the default).  mode 1 (after
  * fscc_prepare_sector): D from the diagonal of Hbar, D_x^a = Re(Fbar_xx -
@@ -198,11 +246,19 @@ fscc_status fscc_heff2(fscc_ctx *ctx, const fscc_c128 *s, fscc_c128 *heff_host);
  * Bloch equation; clears the sector's DIIS history. */
 fscc_status fscc_precondition(fscc_ctx *ctx, fscc_sector sector, int mode, double floor);
 
-/* Correlation energy E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a)
- * (f_ia = 0), complex in general; host outputs. */
+/* Correlation energy of the (0h,0p) sector, the expectation value of Eq. (1)'s
+ * normal-ordered Hamiltonian in the coupled-cluster state of Eq. (2):
+ * E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a) (the f_ia term
+ * vanishes for the diagonal Fock operator), complex in general (complex
+ * integrals without time-reversal symmetry; the real part is the correlation
+ * energy).  t1, t2: device, packed (0h,0p) layouts; e_re, e_im: host.
+ * FSCC_ESTATE before the OOVV class is set.  Synchronises the stream. */
 fscc_status fscc_energy(fscc_ctx *ctx, const fscc_c128 *t1, const fscc_c128 *t2, double *e_re, double *e_im);
 
-/* Clear the DIIS history of a sector and set its depth (0 or 1 = plain Jacobi, max 8). */
+/* Clear the DIIS history of a sector and set its depth (0 or 1 = plain Jacobi
+ * of Eq. (3), max 8); also restarts the sector's divergence watch (see
+ * fscc_update_amplitudes).  FSCC_EINVAL for a depth outside 0..8 or a sector
+ * the system does not have. */
 fscc_status fscc_diis_reset(fscc_ctx *ctx, fscc_sector sector, int ndiis);
 
 /* The particle-particle ladder alone: out_ij^ab = sum_{c<d} <ab||cd> tau_ij^cd

@@ -75,6 +75,8 @@ def lib():
             "fscc_dgemm": ([ip, ip, ip, ip, ip, ip, ip, vp, ip, vp, ip, vp, ip, ctypes.c_double, ip, ip, vp], ip),
             "fscc_dynamic_shift": ([vp, ip, ctypes.c_double, ip], ip),
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
+            "fscc_heff_eig": ([ip, vp, vp], ip),
+            "fscc_set_validation": ([vp, ip], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
             "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
@@ -234,6 +236,10 @@ class Context:
             msg = lib().fscc_last_error(self._h)
             raise FsccError(st, msg.decode() if msg else "")
 
+    def set_validation(self, nsample):
+        """Sampled symmetry checks per integral class at set_integrals (0 = off)."""
+        self._check(lib().fscc_set_validation(self._h, int(nsample)))
+
     def set_integrals(self, cls, dev_blocks):
         k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)
         self._check(lib().fscc_set_integrals(self._h, k, self._d(dev_blocks), dev_blocks.numel()))
@@ -376,9 +382,7 @@ def solve01(ctx, s1, s2, tol=1e-10, maxit=200, ndiis=6, log=None):
             converged = True
             break
     h = ctx.heff(s1, s2)
-    w = np.linalg.eigvals(h)
-    w = w[np.lexsort((w.imag, w.real))]
-    return dict(heff=h, eig=w, iters=k, converged=converged)
+    return dict(heff=h, eig=heff_eig(h), iters=k, converged=converged)
 
 
 def solve02(ctx, s, tol=1e-10, maxit=200, ndiis=6, log=None):
@@ -399,9 +403,22 @@ def solve02(ctx, s, tol=1e-10, maxit=200, ndiis=6, log=None):
             converged = True
             break
     h = ctx.heff2(s)
-    w = np.linalg.eigvals(h)
-    w = w[np.lexsort((w.imag, w.real))]
-    return dict(heff=h, eig=w, iters=k, converged=converged)
+    return dict(heff=h, eig=heff_eig(h), iters=k, converged=converged)
+
+
+def heff_eig(h):
+    """Eigenvalues of a square complex matrix (H_eff) sorted by real part, then
+    imaginary part (fscc_heff_eig, host code of the library)."""
+    import numpy as np
+    a = np.ascontiguousarray(h, dtype=np.complex128)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("heff_eig needs a square matrix")
+    n = a.shape[0]
+    out = np.zeros(n, dtype=np.complex128)
+    r = lib().fscc_heff_eig(int(n), a.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p))
+    if r != 0:
+        raise FsccError(r, "fscc_heff_eig failed")
+    return out
 
 
 def pade(x, y, L, M, x0=0.0):

@@ -450,7 +450,7 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     if (P.has02) setup_diis(c, c->diis[2], 0, P.L_S02.total, -1, P.b_D02);
     c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
     c->part_max = (double*)c->dalloc(2048 * sizeof(double));
-    c->coef = (double*)c->dalloc(kMaxDiis * sizeof(double));
+    c->coef = (double*)c->dalloc((kMaxDiis + 1) * sizeof(double));
     c->scal = (double*)c->dalloc(4 * sizeof(double));
     c->dorder = (int*)c->dalloc(kMaxDiis * sizeof(int));
     c->epart = (double*)c->dalloc(2048 * sizeof(double));
@@ -590,6 +590,114 @@ fscc_status fscc_layout(const fscc_ctx* ctx, fscc_sector sector, size_t* n1, siz
     return FSCC_EINVAL;
 }
 
+namespace {
+
+uint64_t splitmix64(uint64_t& x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Input checks of one boundary class buffer before it is packed: every value
+// finite (a full scan), and at `nsample` sampled elements the symmetries that
+// relate two elements of the same class -- antisymmetry <pq||rs> = -<qp||rs>
+// and <pq||rs> = -<pq||sr> where both indices of a pair lie in one space, and
+// Hermiticity <pq||rs> = conj <rs||pq> where (pq) and (rs) span the same
+// spaces (plain symmetry in a real context).  Returns FSCC_OK, FSCC_EINVAL
+// (non-finite values) or FSCC_ESYMM with a message naming the element.
+fscc_status check_class(fscc_ctx* ctx, int cls, const void* dev, int64_t n) {
+    const int64_t ndbl = ctx->real ? n : 2 * n;
+    unsigned long long* cnt = (unsigned long long*)ctx->dalloc(sizeof(unsigned long long));
+    unsigned long long bad = 0;
+    hipError_t e = launch_count_nonfinite((const double*)dev, ndbl, cnt, ctx->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    (void)hipFree(cnt);
+    hip_check(e, "non-finite scan");
+    static const char* names[IC_N] = {"OOOO", "OOOV", "OOVV", "OVOV", "OVVV", "VVVV"};
+    if (bad) return fail(ctx, FSCC_EINVAL, std::to_string(bad) + " non-finite values in integral class " + names[cls]);
+    const FullBlocks& F = ctx->plan.full[cls];
+    const bool swap12 = F.sp[0] == F.sp[1], swap34 = F.sp[2] == F.sp[3];
+    const bool herm = F.sp[0] == F.sp[2] && F.sp[1] == F.sp[3];
+    if (ctx->validate_n <= 0 || n == 0 || !(swap12 || swap34 || herm)) return FSCC_OK;
+    for (int k = 0; k < 4; ++k)
+        if (F.sp[k]->n == 0) return FSCC_OK;
+    // sampled elements: (offset, partner offset, kind) with kind 0: partner = -x, 1: partner = conj(x)
+    struct Pick {
+        int64_t self, other;
+        int kind;
+        int pos[4];
+    };
+    std::vector<Pick> picks;
+    uint64_t rng = 0x5EEDull + (uint64_t)cls;
+    const int G = F.G;
+    for (int tries = 0; (int)picks.size() < ctx->validate_n && tries < 8 * ctx->validate_n; ++tries) {
+        int pos[4];
+        for (int k = 0; k < 3; ++k) pos[k] = (int)(splitmix64(rng) % (uint64_t)F.sp[k]->n);
+        const int g3 = modG(F.sp[0]->irr[pos[0]] + F.sp[1]->irr[pos[1]] - F.sp[2]->irr[pos[2]], G);
+        const int c3 = F.sp[3]->cnt[g3];
+        if (c3 == 0) continue;
+        pos[3] = F.sp[3]->off[g3] + (int)(splitmix64(rng) % (uint64_t)c3);
+        int sg;
+        const int64_t self = F.find(pos, &sg);
+        if (self < 0) continue;
+        auto partner = [&](int a, int b, int c, int d, int kind) {
+            const int q[4] = {pos[a], pos[b], pos[c], pos[d]};
+            int s2;
+            const int64_t o = F.find(q, &s2);
+            if (o >= 0) picks.push_back(Pick{self, o, kind, {pos[0], pos[1], pos[2], pos[3]}});
+        };
+        if (swap12) partner(1, 0, 2, 3, 0);
+        if (swap34) partner(0, 1, 3, 2, 0);
+        if (herm) partner(2, 3, 0, 1, 1);
+    }
+    if (picks.empty()) return FSCC_OK;
+    std::vector<int64_t> idx;
+    for (auto& p : picks) {
+        idx.push_back(p.self);
+        idx.push_back(p.other);
+    }
+    const size_t es = ctx->esz();
+    int64_t* didx = (int64_t*)ctx->dalloc(idx.size() * sizeof(int64_t));
+    void* dval = ctx->dalloc(idx.size() * es);
+    std::vector<double2> val(idx.size());
+    e = hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->st);
+    if (e == hipSuccess && fscc_ws_gather(dev, es, didx, idx.size(), dval, ctx->st) != FSCC_OK) e = hipErrorLaunchFailure;
+    if (ctx->real) {
+        std::vector<double> rv(idx.size());
+        if (e == hipSuccess) e = hipMemcpyAsync(rv.data(), dval, idx.size() * es, hipMemcpyDeviceToHost, ctx->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+        for (size_t k = 0; k < rv.size(); ++k) val[k] = make_double2(rv[k], 0.0);
+    } else {
+        if (e == hipSuccess) e = hipMemcpyAsync(val.data(), dval, idx.size() * es, hipMemcpyDeviceToHost, ctx->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    }
+    (void)hipFree(didx);
+    (void)hipFree(dval);
+    hip_check(e, "symmetry sample");
+    double scale = 0.0;
+    for (auto& v : val) scale = std::max(scale, std::hypot(v.x, v.y));
+    const double tol = 1e-10 * scale;
+    for (size_t k = 0; k < picks.size(); ++k) {
+        const double2 x = val[2 * k], y = val[2 * k + 1];
+        const double dev_ = picks[k].kind == 0 ? std::hypot(x.x + y.x, x.y + y.y) : std::hypot(x.x - y.x, x.y + y.y);
+        if (dev_ > tol) {
+            const Pick& p = picks[k];
+            std::string at = "<" + std::to_string(F.sp[0]->glob[p.pos[0]]) + " " + std::to_string(F.sp[1]->glob[p.pos[1]]) +
+                             "||" + std::to_string(F.sp[2]->glob[p.pos[2]]) + " " +
+                             std::to_string(F.sp[3]->glob[p.pos[3]]) + ">";
+            return fail(ctx, FSCC_ESYMM,
+                        std::string("integral class ") + names[cls] + ": " + at +
+                            (p.kind == 0 ? " violates antisymmetry" : " violates Hermiticity") + " by " +
+                            std::to_string(dev_) + " (tolerance " + std::to_string(tol) + ")");
+        }
+    }
+    return FSCC_OK;
+}
+
+}  // namespace
+
 fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* dev_blocks, size_t n) {
     if (!ctx) return FSCC_EINVAL;
     if ((int)cls < 0 || (int)cls >= IC_N) return fail(ctx, FSCC_EINVAL, "bad integral class");
@@ -600,6 +708,8 @@ fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* 
     if (n > 0 && !dev_blocks) return fail(ctx, FSCC_EINVAL, "null integral buffer");
     if (ctx->have_cls[cls]) return fail(ctx, FSCC_ESTATE, "integral class already set");
     return guarded(ctx, [&]() -> fscc_status {
+        const fscc_status chk = check_class(ctx, (int)cls, dev_blocks, (int64_t)n);
+        if (chk != FSCC_OK) return chk;
         for (auto& sg : P.setup) {
             if (sg.cls != (int)cls) continue;
             std::vector<uint32_t>& m = P.maps[sg.map];
@@ -627,6 +737,13 @@ fscc_status fscc_set_integrals(fscc_ctx* ctx, fscc_iclass cls, const fscc_c128* 
         ctx->have_cls[cls] = true;
         return FSCC_OK;
     });
+}
+
+fscc_status fscc_set_validation(fscc_ctx* ctx, int nsample) {
+    if (!ctx) return FSCC_EINVAL;
+    if (nsample < 0 || nsample > (1 << 20)) return fail(ctx, FSCC_EINVAL, "validation sample count out of range");
+    ctx->validate_n = nsample;
+    return FSCC_OK;
 }
 
 fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2,
@@ -679,6 +796,7 @@ fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
             hip_check(hipStreamSynchronize(ctx->st), "prepare sync");
             ctx->ready02 = true;
             ctx->diis[2].order.clear();
+            ctx->diis[2].watch.restart();
             return FSCC_OK;
         });
     }
@@ -692,6 +810,7 @@ fscc_status fscc_prepare_sector(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
         ctx->ready01 = true;
         ctx->ready02 = false;   // the (0h,2p) fixed part depends on T through the (0h,1p) Hbar
         ctx->diis[1].order.clear();
+        ctx->diis[1].watch.restart();
         return FSCC_OK;
     });
 }
@@ -805,6 +924,7 @@ fscc_status fscc_precondition(fscc_ctx* ctx, fscc_sector sector, int mode, doubl
         if (!d2.empty())
             hip_check(hipMemcpy(ctx->dbuf[P.b_D2x], d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice), "D2x");
         ctx->diis[1].order.clear();
+        ctx->diis[1].watch.restart();
         return FSCC_OK;
     });
 }
@@ -833,6 +953,7 @@ fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
     if (ndiis < 0 || ndiis > kMaxDiis) return fail(ctx, FSCC_EINVAL, "DIIS depth out of range");
     ctx->diis[sector].ndiis = ndiis;
     ctx->diis[sector].order.clear();
+    ctx->diis[sector].watch.restart();
     return FSCC_OK;
 }
 
@@ -923,7 +1044,24 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
         if (dropped > 0) ord.erase(ord.begin(), ord.begin() + std::min(dropped, (int)ord.size() - 1));
         if (D.ndiis <= 1) ord.clear();
         double mx = ctx->hscal[0];
-        if (!std::isfinite(mx)) return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step");
+        switch (D.watch.observe(mx)) {
+            case DivergenceWatch::CONTINUE:
+                break;
+            case DivergenceWatch::RESET_DIIS:
+                ord.clear();   // the next step starts a fresh subspace
+                break;
+            case DivergenceWatch::GIVE_UP:
+                ord.clear();
+                D.watch.restart();
+                if (!std::isfinite(mx))
+                    return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step (amplitudes left at their input values)");
+                *max_step = mx;
+                return fail(ctx, FSCC_ENOCONV,
+                            "max|step| = " + std::to_string(mx) + " grew more than " +
+                                std::to_string(DivergenceWatch::kGrowth) +
+                                "x above its smallest value again after a DIIS reset: the iteration diverges "
+                                "(amplitudes hold the last, finite, iterate)");
+        }
         *max_step = mx;
         return FSCC_OK;
     });
@@ -1202,6 +1340,7 @@ fscc_status fscc_dynamic_shift(fscc_ctx* ctx, fscc_sector sector, double S, int 
     D.dyn_S = S;
     D.dyn_n = S < 0.0 ? n : 0;
     D.order.clear();   // iterates of other equations are no DIIS history
+    D.watch.restart();
     return FSCC_OK;
 }
 

@@ -11,6 +11,8 @@
 //  * elementwise / reduction kernels of the Jacobi + DIIS update and the energy.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace fscc {
@@ -1344,7 +1346,10 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
 // (oldest first) by Gaussian elimination with partial pivoting in FP64;
 // if a pivot is below 1e-14 * max|A| the oldest slot is dropped and the solve
 // repeated.  coef[slot] receives the coefficient (0 for unused slots);
-// scal[0] = max |step|, scal[1] = number of dropped slots.
+// scal[0] = max |step|, scal[1] = number of dropped slots.  A step that is
+// not finite sets coef[ldb] = 1 (the extrapolation then leaves the
+// amplitudes at their input values) and leaves B untouched; otherwise
+// coef[ldb] = 0.
 __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ part, int nblk, int m,
                                                      const double* __restrict__ part_max, int nblk_max,
                                                      double* __restrict__ B, int ldb, int newslot,
@@ -1367,6 +1372,13 @@ __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ 
     __syncthreads();
     if (threadIdx.x != 0) return;
     scal[0] = mx;
+    if (!isfinite(mx)) {
+        for (int j = 0; j < ldb; ++j) coef[j] = 0.0;
+        coef[ldb] = 1.0;
+        scal[1] = 0.0;
+        return;
+    }
+    coef[ldb] = 0.0;
     // row[j] pairs the new vector with the slot order[j]
     for (int j = 0; j < m; ++j) {
         B[newslot * ldb + order[j]] = row[j];
@@ -1382,10 +1394,35 @@ hipError_t launch_finish_diis(const double* part, int nblk, int m, const double*
     return hipGetLastError();
 }
 
+// *count += number of non-finite values among x[0..n) (the caller zeroes *count)
+__global__ __launch_bounds__(256) void k_count_nonfinite(const double* __restrict__ x, long long n,
+                                                         unsigned long long* __restrict__ count) {
+    __shared__ unsigned int sh[kThreads];
+    unsigned int c = 0;
+    for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads)
+        c += isfinite(x[k]) ? 0u : 1u;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sh[0]) atomicAdd(count, (unsigned long long)sh[0]);
+}
+
+hipError_t launch_count_nonfinite(const double* x, long long n, unsigned long long* count, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess || n <= 0) return e;
+    const long long blocks = std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+    k_count_nonfinite<<<(unsigned)blocks, kThreads, 0, st>>>(x, n, count);
+    return hipGetLastError();
+}
+
+// out = sum_j coef[j] xs[j]; coef[m] != 0 (a non-finite step) leaves out untouched
 __global__ __launch_bounds__(256) void k_lincomb(double2* __restrict__ out, PtrList xs, const double* __restrict__ coef,
                                                  int m, long long n) {
     long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k >= n || coef[m] != 0.0) return;
     double sr = 0.0, si = 0.0;
     for (int j = 0; j < m; ++j) {
         double c = coef[j];

@@ -141,8 +141,13 @@ hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, do
 // sum_b part[b*stride + j] -> out[j]  (j < cols), and max over part_max
 hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
                        hipStream_t st);
+// *count = number of non-finite doubles in x[0..n) (zeroes *count first; not
+// for code under graph capture: it records a memset)
+hipError_t launch_count_nonfinite(const double* x, long long n, unsigned long long* count, hipStream_t st);
+// coef holds ldb + 1 doubles: coef[ldb] = 1 marks a non-finite step
 hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
                               int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st);
+// out = sum_{j<m} coef[j] xs[j], unless coef[m] != 0 (out is then left untouched)
 hipError_t launch_lincomb(double2* out, const double2* const* xs, const double* coef, int m, long long n,
                           hipStream_t st);
 // complex dot sum_k x[k]*y[k] (no conjugation): per-block partials then final
@@ -171,6 +176,7 @@ hipError_t launch_djacobi(const double* t, const double* r, const double* D, dou
                           double dyn_S = 0.0, int dyn_n = 0);
 hipError_t launch_ddots(const double* const* e, int m, const double* enew, long long n, double* part, int nblk,
                         hipStream_t st);
+// real form of launch_lincomb (same coef[m] convention)
 hipError_t launch_dlincomb(double* out, const double* const* xs, const double* coef, int m, long long n,
                            hipStream_t st);
 // out[0] = sum x*y, out[1] = 0

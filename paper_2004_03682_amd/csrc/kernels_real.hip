@@ -556,10 +556,11 @@ __global__ __launch_bounds__(256) void k_ddots(DPtrList e, int m, const double* 
     }
 }
 
+// out = sum_j coef[j] xs[j]; coef[m] != 0 (a non-finite step) leaves out untouched
 __global__ __launch_bounds__(256) void k_dlincomb(double* __restrict__ out, DPtrList xs, const double* __restrict__ coef,
                                                   int m, long long n) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k >= n || coef[m] != 0.0) return;
     double s = 0.0;
     for (int j = 0; j < m; ++j) {
         const double c = coef[j];

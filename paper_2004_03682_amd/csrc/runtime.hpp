@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/fscc.h"
+#include "diverge.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -119,6 +120,7 @@ struct Diis {
     double shift = 0.0;   // level shift of the Jacobi denominators
     double dyn_S = 0.0;   // dynamic denominator shift (changes the solved equations)
     int dyn_n = 0;
+    DivergenceWatch watch;   // growth of max|step| (reset of the subspace, then give up)
 };
 
 
@@ -158,6 +160,7 @@ struct fscc_ctx {
     double* D(int id) const { return (double*)dbuf[id]; }
     int prec = FSCC_FP64;
     const int* d_active = nullptr;   // batched plans: per-system flags, GEMM tiles of 0-systems are skipped
+    int validate_n = 4096;           // sampled symmetry checks per integral class (fscc_set_validation)
     std::string err;
 
     int64_t n1() const { return plan.L_T1.total; }
