@@ -582,6 +582,28 @@ def batch_study(F, torch, fsgen, args, log):
     return out
 
 
+def reorder_table(ops, nwarm):
+    """HBM rate of the reorders / antisymmetrisers (TTGT steps 1, 2 and 4) from the
+    per-operation times of the warm-up iterations and the library's algorithmic
+    bytes per call (each destination element written once, read once when
+    accumulating; each distinct source element read once)."""
+    rows = []
+    for o in ops:
+        if o["kind"] != "reorder" or o["calls"] <= 0:
+            continue
+        per = o["ms"] / o["calls"]
+        gbs = o["bytes"] / (per * 1e-3) / 1e9 if per > 0 else 0.0
+        rows.append({"op": o["name"], "ms_per_call": round(per, 4), "bytes": o["bytes"],
+                     "GB_per_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM, 3)})
+    tot_ms = sum(o["ms"] for o in ops if o["kind"] == "reorder") / max(1, nwarm)
+    tot_b = sum(o["bytes"] * o["calls"] for o in ops if o["kind"] == "reorder") / max(1, nwarm)
+    rows.sort(key=lambda r: -r["ms_per_call"])
+    return {"ms_per_iteration": round(tot_ms, 4), "bytes_per_iteration": tot_b,
+            "GB_per_s": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms > 0 else None,
+            "frac_of_hbm_peak": round(tot_b / (tot_ms * 1e-3) / 1e9 / PEAK_HBM, 3) if tot_ms > 0 else None,
+            "ops": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -646,7 +668,7 @@ def main():
     t0 = time.perf_counter()
     ctx.autotune(1)
     names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot", 12: "64x64r", 13: "64x32r"}
-    tuned = {n: f"{names[c & 255]}{'/3M' if c & 256 else ''}/bk{b}{'/splitK' if sp else ''}"
+    tuned = {n: f"{names[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}/bk{b}{'/splitK' if sp else ''}"
              for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
@@ -729,6 +751,7 @@ def main():
                        "tflops": round(o["flops"] / (o["ms"] / max(1, o["calls"]) * 1e-3) / 1e12, 2)}
                       for o in sorted(gemms, key=lambda o: -o["ms"])[:4]],
         "residual_ms_per_iteration": round(resid_ms, 4),
+        "reorders": reorder_table(ops, nwarm),
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,
     }

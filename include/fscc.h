@@ -284,6 +284,15 @@ fscc_status fscc_profile(fscc_ctx *ctx, int enable);
  * others' launch sequence untouched.  FSCC_EINVAL if k is not an operation. */
 fscc_status fscc_profile_select(fscc_ctx *ctx, int k);
 fscc_status fscc_op_count(const fscc_ctx *ctx, int *count);
+/* Kind and algorithmic bytes of one call of operation k (host outputs):
+ * kind 0 = reorder / antisymmetriser (a gather: steps 1, 2 and 4 of the TTGT
+ * scheme of the algorithm-design section), 1 = grouped GEMM (step 3),
+ * 2 = elementwise.  Bytes: every destination element written once (and read
+ * once when accumulating), every distinct source element read once (the
+ * structural zeros of a reorder read nothing; index maps are not counted),
+ * every GEMM operand element read once.  With the measured time per call
+ * (fscc_op_info) this gives each operation's HBM rate. */
+fscc_status fscc_op_traffic(const fscc_ctx *ctx, int k, int *kind, double *bytes);
 fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, int *calls, double *flops);
 
 /* Tile-shape autotuner for the grouped complex GEMMs (the block contractions
@@ -295,7 +304,8 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * in a split precision (fscc_set_precision) level 1 also times the split
  * kernel's tile shapes of the split operations; level 2 times only those;
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
- * shapes).  Level 1 also times each reorder (gather) of a complex context in
+ * shapes).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) of
+ * every eligible tile.  Level 1 also times each reorder (gather) of a complex context in
  * destination order and by 16 x 16 destination tiles and keeps the faster.
  * Results are numerically equivalent (summation order may change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
@@ -316,8 +326,17 @@ fscc_status fscc_gather_order(fscc_ctx *ctx, int tiled);
  * grows from ~u sum|Ar Bi| + |Ai Br| to ~u sum(|Ar| + |Ai|)(|Br| + |Bi|). */
 #define FSCC_CFG_3M 256
 
+/* MFMA tile ids may also carry this bit: double-buffered LDS (two buffer
+ * pairs per operand, one barrier per K slice: the next slice is stored while
+ * the matrix cores work on the current one).  Needs bk = 16 and one of the
+ * tiles 3: 32x32, 4: 64x16, 5: 16x64, 9: 32x64, 10: 64x32, 13: 64x32 stacked
+ * (their two buffer pairs stay within 64 KB of LDS); FSCC_EINVAL otherwise.
+ * The result is the same (same summation order). */
+#define FSCC_CFG_DB 512
+
 /* Chosen configuration of operation k (cfg = tile shape id, with
- * FSCC_CFG_3M set for a three-product MFMA tile, or -1 if k is not a GEMM;
+ * FSCC_CFG_3M set for a three-product MFMA tile and FSCC_CFG_DB for a
+ * double-buffered one, or -1 if k is not a GEMM;
  * bk = K depth; split = 1 if split along K); host outputs. */
 fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int *split);
 

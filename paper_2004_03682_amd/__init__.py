@@ -59,6 +59,7 @@ def lib():
             "fscc_profile": ([vp, ip], ip),
             "fscc_op_count": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
+            "fscc_op_traffic": ([vp, ip, ctypes.POINTER(ip), dp], ip),
             "fscc_prepare_sector": ([vp, ip, vp, vp], ip),
             "fscc_heff": ([vp, vp, vp, vp], ip),
             "fscc_heff2": ([vp, vp, vp], ip),
@@ -331,7 +332,10 @@ class Context:
             nm, ms, calls, fl = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
             self._check(lib().fscc_op_info(self._h, k, ctypes.byref(nm), ctypes.byref(ms), ctypes.byref(calls),
                                            ctypes.byref(fl)))
-            out.append(dict(name=nm.value.decode(), ms=ms.value, calls=calls.value, flops=fl.value))
+            kind, by = ctypes.c_int(), ctypes.c_double()
+            self._check(lib().fscc_op_traffic(self._h, k, ctypes.byref(kind), ctypes.byref(by)))
+            out.append(dict(name=nm.value.decode(), ms=ms.value, calls=calls.value, flops=fl.value,
+                            kind=("reorder", "gemm", "elementwise")[kind.value], bytes=by.value))
         return out
 
     def autotune(self, level=1):

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -220,6 +222,40 @@ void apply_precision(fscc_ctx* c, int prec) {
     c->prec = prec;
 }
 
+// Algorithmic bytes of one call of an operation: every destination element
+// written once (and read once when accumulating), every distinct source
+// element read once, for the GEMMs each operand element read once.
+// Structural zeros of a gather map read nothing; index maps are not counted.
+double op_bytes(const Plan& P, const Op& o, const std::vector<int64_t>& nnz, size_t es) {
+    const double e = (double)es;
+    switch (o.kind) {
+        case OP_GEMM: {
+            double b = 0.0;
+            for (auto& q : o.probs)
+                b += e * ((double)q.M * q.K + (double)q.K * q.N + (1.0 + o.beta) * (double)q.M * q.N);
+            return b;
+        }
+        case OP_AXPBY: return e * (double)o.n * (2.0 + o.beta);
+        case OP_DIAG: return e * (double)o.n * 3.0 + 8.0 * (double)o.n;
+        case OP_MUL: return e * (double)o.n * 2.0 + 8.0 * (double)o.n;
+        case OP_GATHER: {
+            double b = e * (double)o.n * (1.0 + o.beta);
+            // distinct source buffers: at most their size, at most the entries that read them
+            std::vector<std::pair<int, int64_t>> reads;
+            for (size_t t = 0; t < o.mapsA.size(); ++t) {
+                const int src = o.srcT.empty() ? o.src : o.srcT[t];
+                auto it = std::find_if(reads.begin(), reads.end(), [&](const auto& r) { return r.first == src; });
+                if (it == reads.end()) reads.push_back({src, nnz[o.mapsA[t]]});
+                else it->second += nnz[o.mapsA[t]];
+            }
+            for (auto& r : reads) b += e * (double)std::min<int64_t>(r.second, P.bufs[r.first].n);
+            if (o.src2 >= 0) b += e * (double)P.bufs[o.src2].n;
+            return b;
+        }
+    }
+    return 0.0;
+}
+
 std::string& free_call_error() {
     static thread_local std::string msg;
     return msg;
@@ -427,6 +463,12 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     c->dmap.assign(P.maps.size(), nullptr);
     std::vector<char> is_setup(P.maps.size(), 0);
     for (auto& sg : P.setup) is_setup[sg.map] = 1;
+    std::vector<int64_t> nnz(P.maps.size(), 0);
+    for (size_t k = 0; k < P.maps.size(); ++k)
+        if (!is_setup[k])
+            for (uint32_t e : P.maps[k]) nnz[k] += e != MAP_ZERO;
+    for (auto* L : {&P.ops, &P.ops01_prep, &P.ops01, &P.ops02_prep, &P.ops02})
+        for (auto& o : *L) o.bytes = op_bytes(P, o, nnz, c->esz());
     for (size_t k = 0; k < P.maps.size(); ++k) {
         if (is_setup[k]) continue;
         c->dmap[k] = (uint32_t*)c->dalloc(P.maps[k].size() * sizeof(uint32_t));
@@ -1153,6 +1195,17 @@ fscc_status fscc_op_count(const fscc_ctx* ctx, int* count) {
     return FSCC_OK;
 }
 
+fscc_status fscc_op_traffic(const fscc_ctx* ctx, int k, int* kind, double* bytes) {
+    if (!ctx || !kind || !bytes) return FSCC_EINVAL;
+    OpList* L;
+    int j;
+    if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
+    const Op& o = (*L->ops)[j];
+    *kind = o.kind == OP_GATHER ? 0 : o.kind == OP_GEMM ? 1 : 2;
+    *bytes = o.bytes;
+    return FSCC_OK;
+}
+
 fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, int* calls, double* flops) {
     if (!ctx || !name || !ms || !calls || !flops) return FSCC_EINVAL;
     OpList* L;
@@ -1226,6 +1279,13 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
+        // FSCC_AUTOTUNE_LOG=1: every measured candidate on stderr
+        const bool tlog = std::getenv("FSCC_AUTOTUNE_LOG") != nullptr;
+        auto note = [&](const Op& o, const GemmDev& g, float ms) {
+            if (tlog)
+                std::fprintf(stderr, "autotune %-16s cfg %2d bk %d split %d m3 %d db %d: %.4f ms\n", o.name.c_str(), g.cfg,
+                             g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.db ? 1 : 0, ms);
+        };
         auto time_op = [&](const Op& o, const GemmDev* g) -> float {
             ctx->run_op(o, g);
             float best = 1e30f;
@@ -1277,19 +1337,26 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                                     continue;
                                 }
                             }
-                            float ms = time_op(o, &cand);
-                            if (ms < best_ms) {
-                                free_gemm(best);
-                                best = cand;
-                                best_ms = ms;
-                            } else {
-                                free_gemm(cand);
+                            // single- and double-buffered LDS forms of the same plan
+                            const bool try_db = !ctx->real && bk == 16 && zcfg_has_db(cfg);
+                            for (int db = 0; db <= (try_db ? 1 : 0); ++db) {
+                                cand.db = db == 1;
+                                float ms = time_op(o, &cand);
+                                note(o, cand, ms);
+                                if (ms < best_ms) {
+                                    if (best.probs != cand.probs) free_gemm(best);
+                                    best = cand;
+                                    best_ms = ms;
+                                }
                             }
+                            if (best.probs != cand.probs) free_gemm(cand);
                         }
                 if (best.m3) {   // the winner's tile with the four-product complex form
                     GemmDev alt;
                     plan_gemm(ctx, o, alt, best.cfg, best.bk, best.split, false);
+                    alt.db = best.db;
                     float ms = time_op(o, &alt);
+                    note(o, alt, ms);
                     if (ms < best_ms) {
                         free_gemm(best);
                         best = alt;
@@ -1551,7 +1618,7 @@ fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int*
     int j;
     if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
     const GemmDev& g = L->g[j];
-    *cfg = (*L->ops)[j].kind == OP_GEMM ? (g.cfg | (g.m3 ? FSCC_CFG_3M : 0)) : -1;
+    *cfg = (*L->ops)[j].kind == OP_GEMM ? (g.cfg | (g.m3 ? FSCC_CFG_3M : 0) | (g.db ? FSCC_CFG_DB : 0)) : -1;
     *bk = g.bk;
     *split = g.split ? 1 : 0;
     return FSCC_OK;
@@ -1561,8 +1628,10 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
                        const fscc_c128* B, int ldb, fscc_c128* C, int ldc, double alpha_re, double alpha_im, int beta,
                        int allow_split, void* hip_stream) {
     const bool m3 = cfg >= 0 && (cfg & FSCC_CFG_3M);
-    if (cfg >= 0) cfg &= ~FSCC_CFG_3M;
+    const bool db = cfg >= 0 && (cfg & FSCC_CFG_DB);
+    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB);
     if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
+    if (db && (bk != 16 || !zcfg_has_db(cfg))) return FSCC_EINVAL;
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
     if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
@@ -1582,13 +1651,14 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         if (cfg >= 0 && !cfg_ok(o, cfg)) return FSCC_EINVAL;
         GemmDev g;
         plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0, cfg < 0 || m3);
+        g.db = db;
         hipError_t e;
         if (!g.split) {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
-                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3);
+                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.db);
         } else {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3);
+                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.db);
             if (e == hipSuccess)
                 e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha_re, alpha_im, o.beta, c->st);
         }

@@ -34,7 +34,10 @@ static constexpr int kThreads = 256;
 // larger fragment grids keep three, which they reach without spills.
 constexpr int zgemm_min_waves(int BM, int BN, int BK) { return (BK == 16 && BM * BN == 1024) ? 5 : 3; }
 
-template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE, bool M3>
+// DB: two LDS buffers per operand (double buffering): slice k+1 is stored
+// into one buffer while the matrix cores work on slice k from the other, with
+// one barrier per slice (otherwise one buffer pair and two barriers).
+template <int BM, int BN, int WM, int WN, int BK, bool TA, bool TB, int ROLE, bool M3, bool DB>
 __global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(const double2* __restrict__ A, const double2* __restrict__ B,
                                                double2* __restrict__ C, const ZProb* __restrict__ probs,
                                                const ZTile* __restrict__ tiles, double ar, double ai, int beta,
@@ -48,8 +51,8 @@ __global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(cons
     constexpr int KS_UNROLL = FM * FN >= 4 ? 1 : BK / 4;   // 4-deep steps unrolled per slice
     static_assert(WM * WN == 4, "four waves");
     static_assert(FM >= 1 && FN >= 1, "tile too small");
-    __shared__ double As[2][BK][BM + PAD];
-    __shared__ double Bs[2][BK][BN + PAD];
+    __shared__ double As[DB ? 4 : 2][BK][BM + PAD];
+    __shared__ double Bs[DB ? 4 : 2][BK][BN + PAD];
 
     const ZTile tl = tiles[blockIdx.x];
     if (active && !active[tl.sys]) return;   // whole workgroup: a converged system of a batch
@@ -236,15 +239,9 @@ __global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(cons
     // issues no MFMA
     const bool wave_live = m0 + wm0 < M && n0 + wn0 < N;
 
-    // LDS buffer 0 holds the real planes, buffer 1 the imaginary planes; the
-    // global loads of slice k+1 are in flight while slice k is multiplied
-    if (K > 0) load_slice(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
-        store_slice(0);
-        store_slice_im(1);
-        __syncthreads();
-        if (k0 + BK < K) load_slice(k0 + BK);
+    // one K slice of matrix-core work on the LDS planes As/Bs[pb] (real) and
+    // [pb + 1] (imaginary)
+    auto compute = [&](int pb) {
         // large fragment grids: one 4-deep step at a time keeps the register
         // count (and so the occupancy) of the 64x64 tile in check
 #pragma unroll KS_UNROLL
@@ -253,14 +250,14 @@ __global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(cons
             double a_r[FM], a_i[FM], a_n[FM], b_r[FN], b_i[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
-                a_r[i] = As[0][ks * 4 + lk][wm0 + i * 16 + lr];
-                a_i[i] = As[1][ks * 4 + lk][wm0 + i * 16 + lr];
+                a_r[i] = As[pb][ks * 4 + lk][wm0 + i * 16 + lr];
+                a_i[i] = As[pb + 1][ks * 4 + lk][wm0 + i * 16 + lr];
                 a_n[i] = -a_i[i];
             }
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
-                b_r[j] = Bs[0][ks * 4 + lk][wn0 + j * 16 + lr];
-                b_i[j] = Bs[1][ks * 4 + lk][wn0 + j * 16 + lr];
+                b_r[j] = Bs[pb][ks * 4 + lk][wn0 + j * 16 + lr];
+                b_i[j] = Bs[pb + 1][ks * 4 + lk][wn0 + j * 16 + lr];
             }
             if constexpr (M3) {
                 double a_s[FM], b_s[FN];
@@ -308,6 +305,44 @@ __global__ __launch_bounds__(256, zgemm_min_waves(BM, BN, BK)) void k_zgemm(cons
                     for (int j = 0; j < FN; ++j)
                         acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], acci[i][j], 0, 0, 0);
             }
+        }
+    };
+
+    if constexpr (!DB) {
+        // LDS buffer 0 holds the real planes, buffer 1 the imaginary planes; the
+        // global loads of slice k+1 are in flight while slice k is multiplied
+        if (K > 0) load_slice(0);
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            __syncthreads();
+            store_slice(0);
+            store_slice_im(1);
+            __syncthreads();
+            if (k0 + BK < K) load_slice(k0 + BK);
+            compute(0);
+        }
+    } else {
+        // planes 0/1 and 2/3 alternate: slice k+1 is written into one pair
+        // (its global loads were issued one slice earlier) and the loads of
+        // slice k+2 are issued before the matrix cores start on slice k in the
+        // other pair; the barrier after the slice separates the reads of a
+        // pair from its next writes
+        if (K > 0) {
+            load_slice(0);
+            store_slice(0);
+            store_slice_im(1);
+            if (BK < K) load_slice(BK);
+        }
+        __syncthreads();
+        int cur = 0;
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            if (k0 + BK < K) {
+                store_slice(2 * (cur ^ 1));
+                store_slice_im(2 * (cur ^ 1) + 1);
+                if (k0 + 2 * BK < K) load_slice(k0 + 2 * BK);
+            }
+            compute(2 * cur);
+            __syncthreads();
+            cur ^= 1;
         }
     }
 
@@ -767,21 +802,21 @@ void zcfg_tile(int cfg, int* bm, int* bn) {
     }
 }
 
-template <int BM, int BN, int WM, int WN, int BK, bool M3>
+template <int BM, int BN, int WM, int WN, int BK, bool M3, bool DB>
 static hipError_t launch_cfg(bool tA, bool tB, const double2* A, const double2* B, double2* C, const ZProb* probs,
                              const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA, int cB,
                              hipStream_t st, int role, const int* active) {
     dim3 grid(ntiles), block(kThreads);
     if (!tA && !tB) {
-        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
-        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        if (role == 2) k_zgemm<BM, BN, WM, WN, BK, false, false, 2, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, false, 0, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (!tA && tB) {
-        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
-        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        if (role == 1) k_zgemm<BM, BN, WM, WN, BK, false, true, 1, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        else k_zgemm<BM, BN, WM, WN, BK, false, true, 0, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else if (tA && !tB) {
-        k_zgemm<BM, BN, WM, WN, BK, true, false, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        k_zgemm<BM, BN, WM, WN, BK, true, false, 0, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     } else {
-        k_zgemm<BM, BN, WM, WN, BK, true, true, 0, M3><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
+        k_zgemm<BM, BN, WM, WN, BK, true, true, 0, M3, DB><<<grid, block, 0, st>>>(A, B, C, probs, tiles, ar, ai, beta, cA, cB, active);
     }
     return hipGetLastError();
 }
@@ -791,24 +826,51 @@ static hipError_t launch_bk(int cfg, bool tA, bool tB, const double2* A, const d
                             const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                             int cB, hipStream_t st, int role, const int* active) {
     switch (cfg) {
-        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x64R: return launch_cfg<64, 64, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
-        case ZCFG_64x32R: return launch_cfg<64, 32, 4, 1, BK, M3>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_128x16: return launch_cfg<128, 16, 4, 1, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x128: return launch_cfg<16, 128, 1, 4, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x64: return launch_cfg<64, 64, 2, 2, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x64R: return launch_cfg<64, 64, 4, 1, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32R: return launch_cfg<64, 32, 4, 1, BK, M3, false>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
         default: return hipErrorInvalidValue;
     }
 }
 
+// double-buffered forms: 16-deep slices, tiles whose two LDS buffer pairs
+// stay within 64 KB per workgroup
+template <bool M3>
+static hipError_t launch_db(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C,
+                            const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
+                            int cB, hipStream_t st, int role, const int* active) {
+    switch (cfg) {
+        case ZCFG_32x32: return launch_cfg<32, 32, 2, 2, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x16: return launch_cfg<64, 16, 4, 1, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_16x64: return launch_cfg<16, 64, 1, 4, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_32x64: return launch_cfg<32, 64, 2, 2, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32: return launch_cfg<64, 32, 2, 2, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        case ZCFG_64x32R: return launch_cfg<64, 32, 4, 1, 16, M3, true>(tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool zcfg_has_db(int cfg) {
+    return cfg == ZCFG_32x32 || cfg == ZCFG_64x16 || cfg == ZCFG_16x64 || cfg == ZCFG_32x64 || cfg == ZCFG_64x32 ||
+           cfg == ZCFG_64x32R;
+}
+
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role, const int* active, int max_m, bool m3) {
+                        int cB, hipStream_t st, int role, const int* active, int max_m, bool m3, bool db) {
     if (ntiles <= 0) return hipSuccess;
+    if (db) {
+        if (bk != 16 || !zcfg_has_db(cfg)) return hipErrorInvalidValue;
+        return m3 ? launch_db<true>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active)
+                  : launch_db<false>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+    }
     if (cfg == ZCFG_TALL) {
         if (tA) return hipErrorInvalidValue;
         dim3 grid(ntiles), block(kThreads);

@@ -61,8 +61,9 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
                                const fscc_c128* A, int lda, const fscc_c128* B, int ldb, fscc_c128* C, int ldc,
                                double alpha_re, double alpha_im, int beta, int allow_split, void* hip_stream) {
     const bool m3 = cfg >= 0 && (cfg & FSCC_CFG_3M);
-    if (cfg >= 0) cfg &= ~FSCC_CFG_3M;
-    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32))
+    const bool db = cfg >= 0 && (cfg & FSCC_CFG_DB);
+    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB);
+    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32) || (db && (bk != 16 || !zcfg_has_db(cfg))))
         return free_call_fail(FSCC_EINVAL, "fscc_zgemm_noalloc: bad size, tile id or K depth");
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B))))
         return free_call_fail(FSCC_EINVAL, "fscc_zgemm_noalloc: null operand");
@@ -100,6 +101,7 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
         hip_check(scratch_address(dev, &base), "hipGetSymbolAddress(scratch)");
         unsigned char* p = (unsigned char*)base;
         GemmDev g = h.g;
+        g.db = db;
         g.probs = (ZProb*)p;
         p += align256(h.pr.size() * sizeof(ZProb));
         g.tiles = (ZTile*)p;
@@ -119,10 +121,10 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
         if (g.ntiles > 0) {
             if (!g.split) {
                 e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs,
-                                 g.tiles, g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3);
+                                 g.tiles, g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.db);
             } else {
                 e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                                 g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3);
+                                 g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.db);
                 if (e == hipSuccess)
                     e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha_re, alpha_im,
                                              o.beta, st);

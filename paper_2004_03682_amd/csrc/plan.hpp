@@ -66,6 +66,7 @@ struct Op {
     bool tA = false, tB = false, cA = false, cB = false;
     std::vector<GemmProblem> probs;
     double flops = 0;                // real flops (8 per complex MAC)
+    double bytes = 0;                // algorithmic bytes per call (set when the context is built)
 };
 
 // integral classes

@@ -65,6 +65,25 @@ struct Builder {
         return t;
     }
 
+    // An accumulating gather (beta = 1) leaves a destination tile unchanged
+    // when every term's map is a structural zero on it: such tiles are
+    // dropped from the tiled traversal (e.g. the t1 x t1 part of tau and U
+    // touches a few irrep blocks only).
+    void prune_zero_tiles(Op& op) const {
+        if (op.beta != 1) return;
+        std::vector<GTile> keep;
+        for (const GTile& t : op.gtiles) {
+            bool any = false;
+            for (size_t q = 0; q < op.mapsA.size() && !any; ++q) {
+                const std::vector<uint32_t>& m = P.maps[op.mapsA[q]];
+                for (int r = 0; r < t.nr && !any; ++r)
+                    for (int c = 0; c < t.nc && !any; ++c) any = m[(size_t)(t.k0 + (int64_t)r * t.ld + c)] != MAP_ZERO;
+            }
+            if (any) keep.push_back(t);
+        }
+        op.gtiles.swap(keep);
+    }
+
     void gather(const std::string& name, int dst, const Layout& Ld, int src, const Layout& Ls,
                 const std::vector<Term>& terms, cplx alpha, int beta, bool conj = false, int src2 = -1,
                 const Layout* Ls2 = nullptr) {
@@ -86,6 +105,7 @@ struct Builder {
             if (src2 >= 0)
                 op.mapsB.push_back(P.map(name + "/B" + std::to_string(t), build_map(Ld, *Ls2, terms[t].perm2, 1)));
         }
+        prune_zero_tiles(op);
         out->push_back(std::move(op));
     }
 
@@ -113,6 +133,7 @@ struct Builder {
             op.mapsA.push_back(P.map(name + "/A" + std::to_string(t),
                                      build_map(Ld, *srcs[t].second, terms[t].perm, terms[t].sign)));
         }
+        prune_zero_tiles(op);
         out->push_back(std::move(op));
     }
 
@@ -390,20 +411,21 @@ void build_plan_ccsd(const System& S, Plan& P) {
     Layout L_Y8 = make_layout("Y8", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
     int b_Y8 = P.buf("Y8", L_Y8.total, BUF_SCRATCH);
     B.gemm("Z.t1", b_Z2, L_Z2, false, false, P.b_t1, L_T1, false, false, b_Y8, L_Y8, 1.0, 0);
-    B.gather("r2+=-P(ab)Y8", P.b_r2, L_T2, b_Y8, L_Y8, {T{{0, 1, 2, 3}, -1, {}}, T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
+    // Y8 also collects -Y10a and -Y12 below (the same layout; their
+    // antisymmetrisers are the negative of Y8's), then one pass adds
+    // -P(ab) Y8 to r2
 
     // ---------------------------------------------------------------- ring
     int b_W = P.buf("W", L_W.total, BUF_SCRATCH);
-    B.axpby("W=<mb||ej>", b_W, b_ring0, L_W.total, 1.0, 0, false);
     Layout L_X9b = make_layout("X9b", G, {s(0, o, 1), s(1, v, -1), s(2, v, 1)}, -1, {s(3, o, 1)}, -1, 1);
     int b_X9b = P.buf("X9b", L_X9b.total, BUF_SCRATCH);
     B.gemm("W.t1.ovvv", b_ovvv_9b, L_ovvv_9b, false, false, P.b_t1, L_T1, true, false, b_X9b, L_X9b, 1.0, 0);
     Layout L_X9c = make_layout("X9c", G, {s(0, o, -1), s(1, v, 1), s(2, o, 1)}, -1, {s(3, v, 1)}, -1, 1);
     int b_X9c = P.buf("X9c", L_X9c.total, BUF_SCRATCH);
     B.gemm("W.t1.ooov", b_oovo_9c, L_oovo_9c, false, false, P.b_t1, L_T1, false, false, b_X9c, L_X9c, -1.0, 0);
-    // W += X9b + X9c in one pass over W
-    B.gather_sum("W+=X9b+X9c", b_W, L_W, {{b_X9b, &L_X9b}, {b_X9c, &L_X9c}},
-                 {T{{0, 2, 1, 3}, 1, {}}, T{{0, 2, 3, 1}, 1, {}}}, 1.0, 1);
+    // W = <mb||ej> + X9b + X9c in one pass
+    B.gather_sum("W=V+X9b+X9c", b_W, L_W, {{b_ring0, &L_W}, {b_X9b, &L_X9b}, {b_X9c, &L_X9c}},
+                 {T{{0, 1, 2, 3}, 1, {}}, T{{0, 2, 1, 3}, 1, {}}, T{{0, 2, 3, 1}, 1, {}}}, 1.0, 0);
     // U_(n,f),(j,b) = 1/2 t_jn^fb + t_j^f t_n^b  : logical (n,f,j,b)
     Layout L_U = make_layout("U", G, {s(0, o, 1), s(1, v, -1)}, -1, {s(2, o, -1), s(3, v, 1)}, -1, 1);
     int b_U = P.buf("U", L_U.total, BUF_SCRATCH);
@@ -441,10 +463,8 @@ void build_plan_ccsd(const System& S, Plan& P) {
     Layout L_T10a = make_layout("T10a", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
     int b_T10a = P.buf("T10a", L_T10a.total, BUF_SCRATCH);
     B.gather("t2->10a", b_T10a, L_T10a, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);
-    Layout L_Y10a = make_layout("Y10a", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
-    int b_Y10a = P.buf("Y10a", L_Y10a.total, BUF_SCRATCH);
-    B.gemm("t2.Fbe", b_T10a, L_T10a, false, false, b_Fbe, L_Fbe, true, false, b_Y10a, L_Y10a, 1.0, 0);
-    B.gather("r2+=P(ab)Y10a", P.b_r2, L_T2, b_Y10a, L_Y10a, {T{{0, 1, 2, 3}, 1, {}}, T{{0, 1, 3, 2}, -1, {}}}, 1.0, 1);
+    // Y10a = sum_e t_ij^ae F'_be enters r2 as P(ab) Y10a: collected into Y8 as -Y10a
+    B.gemm("t2.Fbe", b_T10a, L_T10a, false, false, b_Fbe, L_Fbe, true, false, b_Y8, L_Y8, -1.0, 1);
     // F'_mj = F_mj + 1/2 sum_e t_j^e F_me
     Layout L_Fmj = make_layout("Fmj", G, {s(0, o, 1)}, -1, {s(1, o, 1)}, -1, 1);
     int b_Fmj = P.buf("Fmj", L_Fmj.total, BUF_SCRATCH);
@@ -456,17 +476,13 @@ void build_plan_ccsd(const System& S, Plan& P) {
     Layout L_Y10b = make_layout("Y10b", G, {s(0, v, 1), s(1, v, 1), s(2, o, -1)}, 0, {s(3, o, 1)}, -1, 1);
     int b_Y10b = P.buf("Y10b", L_Y10b.total, BUF_SCRATCH);
     B.gemm("t2.Fmj", b_T10b, L_T10b, false, false, b_Fmj, L_Fmj, false, false, b_Y10b, L_Y10b, 1.0, 0);
+    // P(ij) sum_e t_i^e <ab||ej> (Y11): the same layout and antisymmetriser as
+    // -P(ij) Y10b, so it accumulates into Y10b and one pass adds both to r2
+    B.gemm("t1.vvvo", b_vvvo_11, L_vvvo_11, false, false, P.b_t1, L_T1, true, false, b_Y10b, L_Y10b, 1.0, 1);
     B.gather("r2+=-P(ij)Y10b", P.b_r2, L_T2, b_Y10b, L_Y10b, {T{{2, 3, 0, 1}, -1, {}}, T{{2, 3, 1, 0}, 1, {}}}, 1.0, 1);
-    // P(ij) sum_e t_i^e <ab||ej>
-    Layout L_Y11 = make_layout("Y11", G, {s(0, v, 1), s(1, v, 1), s(2, o, -1)}, 0, {s(3, o, 1)}, -1, 1);
-    int b_Y11 = P.buf("Y11", L_Y11.total, BUF_SCRATCH);
-    B.gemm("t1.vvvo", b_vvvo_11, L_vvvo_11, false, false, P.b_t1, L_T1, true, false, b_Y11, L_Y11, 1.0, 0);
-    B.gather("r2+=P(ij)Y11", P.b_r2, L_T2, b_Y11, L_Y11, {T{{2, 3, 1, 0}, 1, {}}, T{{2, 3, 0, 1}, -1, {}}}, 1.0, 1);
-    // -P(ab) sum_m t_m^a <mb||ij>
-    Layout L_Y12 = make_layout("Y12", G, {s(0, o, 1), s(1, o, 1), s(2, v, -1)}, 0, {s(3, v, 1)}, -1, 1);
-    int b_Y12 = P.buf("Y12", L_Y12.total, BUF_SCRATCH);
-    B.gemm("t1.ovoo", b_ovoo_12, L_ovoo_12, false, false, P.b_t1, L_T1, false, false, b_Y12, L_Y12, 1.0, 0);
-    B.gather("r2+=-P(ab)Y12", P.b_r2, L_T2, b_Y12, L_Y12, {T{{0, 1, 3, 2}, -1, {}}, T{{0, 1, 2, 3}, 1, {}}}, 1.0, 1);
+    // -P(ab) sum_m t_m^a <mb||ij> (Y12): collected into Y8 as -Y12
+    B.gemm("t1.ovoo", b_ovoo_12, L_ovoo_12, false, false, P.b_t1, L_T1, false, false, b_Y8, L_Y8, -1.0, 1);
+    B.gather("r2+=-P(ab)Y8", P.b_r2, L_T2, b_Y8, L_Y8, {T{{0, 1, 2, 3}, -1, {}}, T{{0, 1, 3, 2}, 1, {}}}, 1.0, 1);
     B.diag("r2-=D2*t2", P.b_r2, P.b_D2, P.b_t2, L_T2.total);
 
     // --------------------------------------------------------- T1 residual

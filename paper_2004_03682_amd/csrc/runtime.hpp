@@ -60,6 +60,7 @@ struct GemmDev {
     int maxS = 0;    // largest number of K chunks of a problem (split)
     int maxM = 0;   // largest M over the problems (ZCFG_RED picks its register tile by it)
     bool m3 = false;   // MFMA tiles: complex product from three real products
+    bool db = false;   // MFMA tiles: double-buffered LDS (16-deep slices)
     double2* work = nullptr;
     MixedDev* mx = nullptr;   // present for the ops that may run in split precision
 };
@@ -350,10 +351,10 @@ struct fscc_ctx {
                     e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
                 } else if (!g.split) {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3);
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.db);
                 } else {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3);
+                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.db);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(),
                                                  beta, st, d_active);
@@ -430,9 +431,9 @@ struct fscc_ctx {
         double2* Cp = C_override ? C_override : B(o.dst);
         if (!g.split)
             return launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
-                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3);
+                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.db);
         hipError_t e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
-                                    o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3);
+                                    o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.db);
         if (e == hipSuccess)
             e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(), beta, st);
         return e;
@@ -545,6 +546,7 @@ struct GemmHost {
     long long work_elems = 0;
 };
 void plan_gemm_host(bool real, const Op& o, int cfg, int bk, bool allow_split, bool m3, GemmHost& h);
+double op_bytes(const Plan& P, const Op& o, const std::vector<int64_t>& nnz, size_t es);
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops);
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2);
 void bind_io(fscc_ctx* c, const fscc_c128* t1, const fscc_c128* t2, fscc_c128* r1, fscc_c128* r2);

@@ -1,7 +1,9 @@
 """Writes tests/golden/*.json from the CPU oracle only (run by hand; committed output).
 
   python tests/golden/make_golden.py                 # o20v120z8_ccsd.json
-  python tests/golden/make_golden.py o40v300z16      # o40v300z16_ccsd.json (about an hour on 8 cores)
+  python tests/golden/make_golden.py o40v300z16 [--save-amplitudes PATH.npz]
+                                                     # o40v300z16_ccsd.json (about an hour on 8 cores);
+                                                     # optionally also every converged block of t1, t2
 
 o20v120z8_ccsd.json: converged (0h,0p) CCSD correlation energy of the 20-occupied /
 120-virtual / Z8 synthetic system (seed 1001) from the block-list oracle, with
@@ -97,7 +99,7 @@ def t2_sample(be, t2, count, seed, top):
     return out
 
 
-def production():
+def production(save=None):
     name = "o40v300z16"
     s = fsgen.workload_system(name)
     t0 = time.time()
@@ -128,10 +130,14 @@ def production():
     with open(os.path.join(HERE, name + "_ccsd.json"), "w") as f:
         json.dump(out, f, indent=0)
     print({k: v for k, v in out.items() if k not in ("t1", "t2_sample", "history")})
+    if save:
+        arrays = {"t1_" + "_".join(map(str, k)): v for k, v in r["t1"].blocks.items()}
+        arrays.update({"t2_" + "_".join(map(str, k)): v for k, v in r["t2"].blocks.items()})
+        np.savez(save, **arrays)
 
 
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "o40v300z16":
-        production()
+        production(sys.argv[3] if len(sys.argv) > 3 and sys.argv[2] == "--save-amplitudes" else None)
     else:
         small()

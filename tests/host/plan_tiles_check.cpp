@@ -1,6 +1,7 @@
 // Host-side check of the planner's gather tile tables (no GPU): for every
-// gather of every operation list, the 16 x 16 destination tiles must cover
-// each destination element exactly once and stay inside the destination.
+// gather of every operation list, the 16 x 16 destination tiles must stay
+// inside the destination, cover no element twice, and cover every element
+// except those an accumulating gather leaves unchanged (all maps zero).
 #include <cstdio>
 #include <vector>
 
@@ -40,10 +41,16 @@ extern "C" int plan_tiles_check(int nocc, int nvirt, int G, const int* irrep, co
                         if (seen[(size_t)k]++) ++bad;
                     }
             }
+            // an element no tile covers must be one an accumulating gather leaves
+            // unchanged: every term's map a structural zero there
             for (long long k = 0; k < o.n; ++k)
                 if (!seen[(size_t)k]) {
-                    ++bad;
-                    break;
+                    bool zero = o.beta == 1;
+                    for (size_t q = 0; q < o.mapsA.size() && zero; ++q) zero = P.maps[o.mapsA[q]][(size_t)k] == MAP_ZERO;
+                    if (!zero) {
+                        ++bad;
+                        break;
+                    }
                 }
         }
     *ops_checked = nops;

@@ -11,8 +11,11 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 M3 = 256   # FSCC_CFG_3M: three-product complex form of an MFMA tile
+DB = 512   # FSCC_CFG_DB: double-buffered LDS form (16-deep slices)
 MFMA_TILES = (0, 1, 2, 3, 4, 5, 9, 10, 12, 13)   # 0-5, 9 (32x64), 10 (64x32), 12/13 (64x64, 64x32, waves along M)
+DB_TILES = (3, 4, 5, 9, 10, 13)
 CFGS = MFMA_TILES + tuple(c | M3 for c in MFMA_TILES) + (6,)   # 4M and 3M MFMA tiles; 6 = skinny (vector ALUs)
+DB_CFGS = tuple(c | DB for c in DB_TILES) + tuple(c | DB | M3 for c in DB_TILES)
 
 
 def _rand(rng, *shape):
@@ -50,6 +53,29 @@ def test_zgemm_every_config(cfg, bk):
         for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 129), (130, 131, 40), (1017, 1, 300), (3, 48, 700)]:
             err = _run(M, N, K, tA, tB, cA, cB, cfg, bk, False, beta=(M % 2))
             assert err < 1e-13, (cfg, bk, tA, tB, cA, cB, M, N, K, err)
+
+
+@pytest.mark.parametrize("cfg", DB_CFGS)
+def test_zgemm_double_buffered_forms(cfg):
+    """The double-buffered LDS forms: ragged sizes, every transpose/conjugate
+    flag, K below, at and above one and two 16-deep slices, split-K, K = 0."""
+    for (tA, tB, cA, cB) in [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 0, 1), (1, 1, 1, 1)]:
+        for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 16), (33, 65, 17), (130, 131, 32), (40, 50, 33),
+                          (1017, 1, 300), (3, 48, 700)]:
+            err = _run(M, N, K, tA, tB, cA, cB, cfg, 16, False, beta=(M % 2))
+            assert err < 1e-13, (cfg, tA, tB, cA, cB, M, N, K, err)
+    for (M, N, K, beta) in [(7, 34, 3000, 0), (300, 200, 1800, 1), (9, 11, 0, 1)]:
+        err = _run(M, N, K, 0, 1, 0, 0, cfg, 16, True, beta)
+        assert err < 1e-13, (cfg, M, N, K, beta, err)
+
+
+def test_double_buffered_form_needs_an_eligible_tile():
+    import torch
+    import paper_2004_03682_amd as F
+    a = torch.zeros((4, 4), dtype=torch.complex128, device="cuda")
+    for cfg, bk in ((0 | DB, 16), (12 | DB, 16), (9 | DB, 32)):
+        with pytest.raises(F.FsccError):
+            F.zgemm(a, a, a, 4, 4, 4, 4, 4, 4, cfg=cfg, bk=bk)
 
 
 @pytest.mark.parametrize("cfg", CFGS)

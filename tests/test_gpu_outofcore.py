@@ -4,12 +4,17 @@ device staging buffers while the ladder GEMMs run.  Staging buffers far
 smaller than one ladder block force problems to be cut along ab and many
 chunks per launch.  Results must equal the in-memory path (1e-12 of max|R|
 per call, 1e-10 Eh converged), in all three sectors and in real arithmetic, and
-moving VVVV back must restore the in-memory path."""
+moving VVVV back must restore the in-memory path.  The streamed path is also
+checked against the CPU oracle directly (a defect shared by both GPU paths
+would pass the first kind of test): the streamed (0h,0p) residual in complex
+and real arithmetic, the streamed converged energy, and the streamed (0h,1p)
+and (0h,2p) residuals and H_eff, each at 1e-12 of max|R| (1e-10 Eh)."""
 import numpy as np
 import pytest
 
 import fsgen
 import layout_ref as LR
+from oracle import ccsd, fs01, fs02, solver
 
 pytestmark = pytest.mark.gpu
 
@@ -138,4 +143,71 @@ def test_out_of_core_rejects_tiny_staging_and_repeats():
     with pytest.raises(F.FsccError):
         ctx.vvvv_out_of_core(1 << 16)          # already out of device memory
     ctx.vvvv_out_of_core(0)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "real_fp64"])
+def test_out_of_core_residual_matches_oracle(precision):
+    import torch
+    s = fsgen.make_system(12, 70, 4, 0.05, 77, real=precision == "real_fp64")
+    print("case out-of-core vs oracle", precision, flush=True)
+    ctx = _ctx(s, precision)
+    ctx.vvvv_out_of_core(64 * 1024)
+    t1, t2 = _rand(ctx, ctx.n1, 1, 0.02), _rand(ctx, ctx.n2, 2, 0.02)
+    g1, g2 = _residual(ctx, t1, t2)
+    cplx = lambda x: x.cpu().numpy().astype(np.complex128)  # noqa: E731
+    h1, h2 = LR.unpack_t1(s, cplx(t1)), LR.unpack_t2(s, cplx(t2))
+    R1, R2 = ccsd.residual(ccsd.Dense(s), h1, h2)
+    scale = max(np.abs(R1).max(), np.abs(R2).max())
+    assert np.abs(LR.unpack_t1(s, cplx(g1)) - R1).max() <= 1e-12 * scale
+    assert np.abs(LR.unpack_t2(s, cplx(g2)) - R2).max() <= 1e-12 * scale
+    ctx.destroy()
+
+
+def test_out_of_core_converged_energy_matches_oracle():
+    import torch
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(10, 50, 4, 0.05, 61)
+    ctx = _ctx(s)
+    ctx.vvvv_out_of_core(1 << 20)
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    g = F.solve(ctx, t1, t2, tol=1e-11)
+    ctx.destroy()
+    o = solver.solve_ccsd(ccsd.Dense(s), tol=1e-11)
+    assert g["converged"] and o["converged"]
+    assert abs(g["E"].real - o["E"].real) <= 1e-10 and abs(g["E"].imag - o["E"].imag) <= 1e-10
+    assert np.abs(LR.unpack_t2(s, t2.cpu().numpy()) - o["t2"]).max() <= 1e-9
+
+
+def test_out_of_core_sectors_match_oracle():
+    import torch
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(7, 19, 3, 0.05, 8, nact=6)
+    ctx = _ctx(s)
+    ctx.vvvv_out_of_core(16 * 1024)
+    t1, t2 = _rand(ctx, ctx.n1, 3, 0.01), _rand(ctx, ctx.n2, 4, 0.01)
+    ctx.prepare_sector(t1, t2)
+    be = ccsd.Dense(s)
+    F1 = fs01.FS01(be, LR.unpack_t1(s, t1.cpu().numpy()), LR.unpack_t2(s, t2.cpu().numpy()), s.active)
+    s1 = LR.unpack_s1(s, _rand(ctx, ctx.m1, 5, 0.05).cpu().numpy())
+    s1 = np.where(F1.mask1, s1, 0)
+    s2 = LR.unpack_s2(s, _rand(ctx, ctx.m2, 6, 0.05).cpu().numpy())
+    d1, d2 = torch.from_numpy(LR.pack_s1(s, s1)).cuda(), torch.from_numpy(LR.pack_s2(s, s2)).cuda()
+    g1, g2 = _residual(ctx, d1, d2, 1)
+    R1, R2, heff = F1.residual(s1, s2)
+    scale = max(np.abs(R1).max(), np.abs(R2).max())
+    assert np.abs(LR.unpack_s1(s, g1.cpu().numpy()) - R1).max() <= 1e-12 * scale
+    assert np.abs(LR.unpack_s2(s, g2.cpu().numpy()) - R2).max() <= 1e-12 * scale
+    assert np.abs(ctx.heff(d1, d2) - heff).max() <= 1e-12 * np.abs(heff).max()
+    ctx.prepare_sector(d1, d2, sector=F.FSCC_S02)
+    F2 = fs02.FS02(F1, s1, s2)
+    x = LR.unpack_s02(s, _rand(ctx, ctx.p2, 7, 0.05).cpu().numpy())
+    sp = np.where(F2.mask, x, 0)
+    d = torch.from_numpy(LR.pack_s02(s, sp)).cuda()
+    o = torch.empty_like(d)
+    ctx.build_residual(None, d, None, o, F.FSCC_S02)
+    R, h2 = F2.residual(sp)
+    assert np.abs(LR.unpack_s02(s, o.cpu().numpy()) - R).max() <= 1e-12 * np.abs(R).max()
+    assert np.abs(ctx.heff2(d) - h2).max() <= 1e-12 * np.abs(h2).max()
     ctx.destroy()

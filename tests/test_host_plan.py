@@ -1,7 +1,8 @@
 """Host logic of the planner, on the CPU: the destination tile tables of the
-reorders (gathers) partition every destination exactly once, in every
-operation list ((0h,0p), (0h,1p), (0h,2p)), for systems with empty irreps,
-ragged blocks and active spaces.  The planner source is compiled with g++
+reorders (gathers) of every operation list ((0h,0p), (0h,1p), (0h,2p)) stay
+inside the destination, cover no element twice and cover every element except
+those an accumulating gather leaves unchanged (all maps zero), for systems
+with empty irreps, ragged blocks and active spaces.  The planner source is compiled with g++
 (it uses no HIP)."""
 import ctypes
 import os
