@@ -306,16 +306,24 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
  * shapes).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) of
  * every eligible tile.  Level 1 also times each reorder (gather) of a complex context in
- * destination order and by 16 x 16 destination tiles and keeps the faster.
+ * destination order, by 16 x 16 destination tiles and by affine tiles (see
+ * fscc_gather_order) and keeps the fastest.
  * Results are numerically equivalent (summation order may change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
 
 /* Traversal of the reorders / antisymmetrisers (gathers) of every operation
- * list: tiled = 0 walks each destination in storage order, tiled = 1 in
- * 16 x 16 tiles of its blocks (complex contexts; a real context always uses
- * storage order).  The results are bitwise identical; only the order of the
- * source reads changes, and with it their cache-line locality.  Replaces the
- * choice fscc_autotune(ctx, 1) made.  FSCC_EINVAL for another value. */
+ * list (steps 1, 2 and 4 of the TTGT scheme of the algorithm-design section):
+ * tiled = 0 walks each destination in storage order through per-element
+ * index maps, tiled = 1 in 16 x 16 tiles of its blocks, tiled = 2 in affine
+ * tiles (at most 16 x 16) on which each term's source index is an affine
+ * function of the destination row and column: no index map is read there,
+ * the source is read with consecutive lanes on consecutive elements and a
+ * transposed term is staged through LDS so that the destination is written
+ * along its rows; a term without an affine form on a tile uses its map
+ * (gathers with a second operand fall back to tiled = 1).  Complex contexts;
+ * a real context always uses storage order.  The results are bitwise
+ * identical.  Replaces the choice fscc_autotune(ctx, 1) made.  FSCC_EINVAL for
+ * another value. */
 fscc_status fscc_gather_order(fscc_ctx *ctx, int tiled);
 
 /* MFMA tile ids of fscc_zgemm / fscc_gemm_config may carry this bit: the

@@ -69,6 +69,13 @@ void merge_plans(const std::vector<std::unique_ptr<Plan>>& sub, Plan& M, std::ve
         o.gtiles.clear();   // batched gathers run over segments in destination order
         o.d_gtiles = nullptr;
         o.use_gtiles = false;
+        o.rtiles.clear();
+        o.rterms.clear();
+        o.runits.clear();
+        o.d_rtiles = nullptr;
+        o.d_rterms = nullptr;
+        o.d_runits = nullptr;
+        o.use_rtiles = false;
         o.mapsA.clear();
         o.mapsB.clear();
         o.flops = 0;

@@ -371,12 +371,24 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
 
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
     L.ops = &ops;
-    for (auto& o : ops)
+    for (auto& o : ops) {
         if (o.kind == OP_GATHER && !o.gtiles.empty()) {
             GTile* d = (GTile*)c->dalloc(o.gtiles.size() * sizeof(GTile));
             hip_check(hipMemcpy(d, o.gtiles.data(), o.gtiles.size() * sizeof(GTile), hipMemcpyHostToDevice), "tiles");
             o.d_gtiles = d;
         }
+        if (o.kind == OP_GATHER && !o.rtiles.empty() && !c->real) {
+            GTile* d = (GTile*)c->dalloc(o.rtiles.size() * sizeof(GTile));
+            hip_check(hipMemcpy(d, o.rtiles.data(), o.rtiles.size() * sizeof(GTile), hipMemcpyHostToDevice), "rtiles");
+            o.d_rtiles = d;
+            RTerm* q = (RTerm*)c->dalloc(o.rterms.size() * sizeof(RTerm));
+            hip_check(hipMemcpy(q, o.rterms.data(), o.rterms.size() * sizeof(RTerm), hipMemcpyHostToDevice), "rterms");
+            o.d_rterms = q;
+            RUnit* un = (RUnit*)c->dalloc(o.runits.size() * sizeof(RUnit));
+            hip_check(hipMemcpy(un, o.runits.data(), o.runits.size() * sizeof(RUnit), hipMemcpyHostToDevice), "runits");
+            o.d_runits = un;
+        }
+    }
     L.g.assign(ops.size(), GemmDev());
     L.ms.assign(ops.size(), 0.0);
     L.calls.assign(ops.size(), 0);
@@ -1237,6 +1249,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 for (size_t k = 0; k < L->ops->size(); ++k) {
                     const Op& o = (*L->ops)[k];
                     (*L->ops)[k].use_gtiles = false;
+                    (*L->ops)[k].use_rtiles = false;
                     if (o.kind != OP_GEMM) continue;
                     MixedDev* keep = L->g[k].mx;
                     L->g[k].mx = nullptr;
@@ -1304,13 +1317,23 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
             for (size_t k = 0; k < L->ops->size() && level == 1; ++k) {
                 const Op& o = (*L->ops)[k];
                 if (o.kind == OP_GATHER && o.d_gtiles && !ctx->real) {
-                    // destination order or 16 x 16 tiles, whichever is faster
+                    // destination order, 16 x 16 tiles or affine tiles, whichever is fastest
                     Op& m = (*L->ops)[k];
                     m.use_gtiles = false;
+                    m.use_rtiles = false;
                     const float rows = time_op(m, nullptr);
                     m.use_gtiles = true;
                     const float tiles = time_op(m, nullptr);
-                    m.use_gtiles = tiles < rows;
+                    float aff = 1e30f;
+                    if (m.d_rtiles) {
+                        m.use_rtiles = true;
+                        aff = time_op(m, nullptr);
+                    }
+                    m.use_rtiles = aff < std::min(rows, tiles);
+                    m.use_gtiles = !m.use_rtiles && tiles < rows;
+                    if (tlog)
+                        std::fprintf(stderr, "autotune %-16s reorder rows %.4f tiles %.4f affine %.4f ms\n", m.name.c_str(),
+                                     rows, tiles, aff);
                     continue;
                 }
                 if (o.kind != OP_GEMM || o.flops < 1e5) continue;
@@ -1529,10 +1552,14 @@ fscc_status fscc_vvvv_out_of_core(fscc_ctx* ctx, size_t staging_bytes) {
 
 fscc_status fscc_gather_order(fscc_ctx* ctx, int tiled) {
     if (!ctx) return FSCC_EINVAL;
-    if (tiled != 0 && tiled != 1) return fail(ctx, FSCC_EINVAL, "gather order must be 0 or 1");
+    if (tiled < 0 || tiled > 2) return fail(ctx, FSCC_EINVAL, "gather order must be 0, 1 or 2");
     for (OpList* L : {&ctx->L00, &ctx->L01p, &ctx->L01, &ctx->L02p, &ctx->L02})
         if (L->ops)
-            for (auto& o : *L->ops) o.use_gtiles = tiled && o.d_gtiles != nullptr;
+            for (auto& o : *L->ops) {
+                // affine tiles where the gather has them, 16 x 16 tiles otherwise
+                o.use_rtiles = tiled == 2 && o.d_rtiles != nullptr;
+                o.use_gtiles = !o.use_rtiles && tiled >= 1 && o.d_gtiles != nullptr;
+            }
     return FSCC_OK;
 }
 

@@ -1138,6 +1138,126 @@ hipError_t launch_gather_tiled(double2* dst, const double2* src, const double2* 
     return hipGetLastError();
 }
 
+// The same gather traversing its affine tiles (at most 16 x 16 destination
+// elements each), grouped into work units of at most 256 elements and 8 tiles:
+// one single-wave workgroup per unit, element e of the unit (tiles
+// concatenated, row-major inside each) on lane e % 64, so a lane handles up
+// to four elements and keeps up to 4 x NT independent loads in flight (every
+// term's loads are issued before any is used).  A term is read with
+// consecutive lanes on consecutive source elements: along the destination
+// rows when its column stride is 1 (or it has no affine form), down the
+// columns when its row stride is 1 -- a transposition, staged through LDS so
+// that the destination is written along its rows.  Affine terms read no map;
+// the others use their maps.
+template <int NT>
+__global__ __launch_bounds__(64) void k_reorder(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                GatherMaps maps, const RUnit* __restrict__ units,
+                                                const GTile* __restrict__ tiles, const RTerm* __restrict__ terms,
+                                                double ar, double ai, int beta, int conj) {
+    __shared__ double2 tr[NT][RUNIT_MAX_ELEMS];
+    const int lane = threadIdx.x;
+    const RUnit u = units[blockIdx.x];
+    // tile of each of the lane's elements: element offsets of the unit's tiles
+    int start[RUNIT_MAX_RECTS + 1];
+    GTile tl[RUNIT_MAX_RECTS];
+    start[0] = 0;
+#pragma unroll
+    for (int j = 0; j < RUNIT_MAX_RECTS; ++j) {
+        tl[j] = j < u.count ? tiles[u.first + j] : GTile{0, 0, 0, 0};
+        start[j + 1] = start[j] + (int)tl[j].nr * tl[j].nc;
+    }
+    const int n = start[RUNIT_MAX_RECTS];
+    // per element: its tile (selected without dynamic register indexing)
+    int jt[4], st[4];
+    GTile te[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;
+        jt[k] = 0;
+        st[k] = 0;
+        te[k] = tl[0];
+#pragma unroll
+        for (int i = 1; i < RUNIT_MAX_RECTS; ++i)
+            if (i < u.count && e >= start[i]) {
+                jt[k] = i;
+                st[k] = start[i];
+                te[k] = tl[i];
+            }
+    }
+    double2 x[NT][4];
+    bool cmk[NT][4];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const double2* __restrict__ s = maps.src[q] ? (const double2*)maps.src[q] : src;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = lane + 64 * k;
+            x[q][k] = make_double2(0.0, 0.0);
+            cmk[q][k] = false;
+            if (e >= n) continue;
+            const GTile t = te[k];
+            const RTerm rt = terms[(long long)(u.first + jt[k]) * NT + q];
+            const int nr = t.nr, nc = t.nc, el = e - st[k];
+            const bool cm = rt.s0 >= 0 && rt.sa == 1 && rt.sb != 1 && nr > 1;
+            const int r = cm ? el % nr : el / nc, c = cm ? el / nr : el % nc;
+            if (rt.s0 == RTERM_MAPPED) {
+                x[q][k] = map_load(s, maps.a[q][t.k0 + (long long)r * t.ld + c]);
+            } else if (rt.s0 != RTERM_ZERO) {
+                x[q][k] = s[(rt.s0 & ~RTERM_NEG) + (long long)r * rt.sa + (long long)c * rt.sb];
+                if (rt.s0 & RTERM_NEG) {
+                    x[q][k].x = -x[q][k].x;
+                    x[q][k].y = -x[q][k].y;
+                }
+            }
+            if (conj) x[q][k].y = -x[q][k].y;
+            cmk[q][k] = cm;
+            // a transposed read: element (r, c) of the tile is unit element st + r * nc + c
+            if (cm) tr[q][st[k] + r * nc + c] = x[q][k];
+        }
+    }
+    // a single wave: the barrier orders the LDS writes before the reads
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;
+        if (e >= n) continue;
+        const GTile t = te[k];
+        const int el = e - st[k], r = el / t.nc, c = el % t.nc;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            // the term's orientation is that of the tile, the same for all its elements: the
+            // row-major read of element e, or the LDS copy of a transposed read
+            const double2 y = cmk[q][k] ? tr[q][e] : x[q][k];
+            sr += y.x;
+            si += y.y;
+        }
+        double2* d = dst + t.k0 + (long long)r * t.ld + c;
+        double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
+        if (beta) {
+            const double2 o = *d;
+            out.x += o.x;
+            out.y += o.y;
+        }
+        *d = out;
+    }
+}
+
+hipError_t launch_reorder(double2* dst, const double2* src, GatherMaps maps, int nt, const RUnit* units, int nunits,
+                          const GTile* tiles, const RTerm* terms, double ar, double ai, int beta, int conj,
+                          hipStream_t st) {
+    if (nunits <= 0) return hipSuccess;
+    dim3 grid((unsigned)nunits), block(64);
+    switch (nt) {
+        case 1: k_reorder<1><<<grid, block, 0, st>>>(dst, src, maps, units, tiles, terms, ar, ai, beta, conj); break;
+        case 2: k_reorder<2><<<grid, block, 0, st>>>(dst, src, maps, units, tiles, terms, ar, ai, beta, conj); break;
+        case 3: k_reorder<3><<<grid, block, 0, st>>>(dst, src, maps, units, tiles, terms, ar, ai, beta, conj); break;
+        case 4: k_reorder<4><<<grid, block, 0, st>>>(dst, src, maps, units, tiles, terms, ar, ai, beta, conj); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
                          long long n, double ar, double ai, int beta, int conj, hipStream_t st, SegBlocks sb) {
     if (n <= 0 || (sb.sys && sb.nblk <= 0)) return hipSuccess;

@@ -120,6 +120,12 @@ struct GatherMaps {
     const uint32_t* b[4];
     const void* src[4];
 };
+// the same gather over its affine tiles (no second operand): work units
+// units[nunits] over tiles[], terms[tile * nt + t] (see RTerm); mapped terms
+// read maps.a[t]
+hipError_t launch_reorder(double2* dst, const double2* src, GatherMaps maps, int nt, const RUnit* units, int nunits,
+                          const GTile* tiles, const RTerm* terms, double ar, double ai, int beta, int conj,
+                          hipStream_t st);
 hipError_t launch_gather(double2* dst, const double2* src, const double2* src2, GatherMaps maps, int nt,
                          long long n, double ar, double ai, int beta, int conj, hipStream_t st,
                          SegBlocks sb = SegBlocks());

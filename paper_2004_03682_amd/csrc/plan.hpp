@@ -62,6 +62,16 @@ struct Op {
     std::vector<GTile> gtiles;       // gathers: 16 x 16 tiles covering the destination blocks
     const GTile* d_gtiles = nullptr; // device copy (set up with the context)
     bool use_gtiles = false;         // traverse the destination by tiles (chosen by timing)
+    // affine traversal: destination tiles (at most 16 x 16, inside one of the
+    // 16 x 16 tiles above) on which each term's source index is affine in
+    // (row, column) -- rterms[tile * nterms + t] -- so no map is read there
+    std::vector<GTile> rtiles;
+    std::vector<RTerm> rterms;
+    std::vector<RUnit> runits;       // consecutive affine tiles grouped into work units
+    const GTile* d_rtiles = nullptr;
+    const RTerm* d_rterms = nullptr;
+    const RUnit* d_runits = nullptr;
+    bool use_rtiles = false;         // chosen by timing
     // GEMM
     bool tA = false, tB = false, cA = false, cB = false;
     std::vector<GemmProblem> probs;

@@ -84,6 +84,91 @@ struct Builder {
         op.gtiles.swap(keep);
     }
 
+    // Affine traversal of a reorder without a second operand.  Each 16 x 16
+    // destination tile is cut into rectangles on which every term's map is
+    // affine: rows are cut where the first column of some term stops
+    // continuing the step of the strip's first two rows (or changes sign or
+    // zero status), columns likewise along the strip's first row.  Each
+    // rectangle is then checked element by element; a term that is not
+    // affine on it keeps its map there (RTERM_MAPPED).  Rectangles of an
+    // accumulating gather on which every term is zero are dropped.
+    void affine_tiles(Op& op) const {
+        op.rtiles.clear();
+        op.rterms.clear();
+        op.runits.clear();
+        if (op.src2 >= 0 || op.gtiles.empty()) return;
+        const int NT = (int)op.mapsA.size();
+        std::vector<const std::vector<uint32_t>*> M;
+        for (int m : op.mapsA) M.push_back(&P.maps[m]);
+        auto at = [&](int t, const GTile& g, int r, int c) { return (*M[t])[(size_t)(g.k0 + (int64_t)r * g.ld + c)]; };
+        auto kind = [](uint32_t v) { return v == MAP_ZERO ? 0 : (v & MAP_NEG) ? 2 : 1; };
+        auto off = [](uint32_t v) { return (int64_t)(v & ~MAP_NEG); };
+        // does element (r1 | c1) continue the affine run started at (r0, c0) along rows (dr) or columns?
+        auto continues = [&](const GTile& g, int r0, int c0, int r1, int c1) {
+            for (int t = 0; t < NT; ++t) {
+                const uint32_t a = at(t, g, r0, c0), b = at(t, g, r1, c1);
+                if (kind(a) != kind(b)) return false;
+                const int d = (r1 - r0) + (c1 - c0);
+                if (kind(a) && d >= 2) {
+                    const uint32_t n1 = r1 > r0 ? at(t, g, r0 + 1, c0) : at(t, g, r0, c0 + 1);
+                    if (off(b) != off(a) + (int64_t)d * (off(n1) - off(a))) return false;
+                }
+            }
+            return true;
+        };
+        for (const GTile& g : op.gtiles) {
+            for (int r0 = 0; r0 < g.nr;) {
+                int r1 = r0 + 1;
+                while (r1 < g.nr && continues(g, r0, 0, r1, 0)) ++r1;
+                for (int c0 = 0; c0 < g.nc;) {
+                    int c1 = c0 + 1;
+                    while (c1 < g.nc && continues(g, r0, c0, r0, c1)) ++c1;
+                    GTile rt{g.k0 + (int64_t)r0 * g.ld + c0, g.ld, (int16_t)(r1 - r0), (int16_t)(c1 - c0)};
+                    std::vector<RTerm> tt(NT);
+                    bool any = false;
+                    for (int t = 0; t < NT; ++t) {
+                        const uint32_t a = at(t, g, r0, c0);
+                        const int64_t sa = r1 - r0 > 1 ? off(at(t, g, r0 + 1, c0)) - off(a) : 0;
+                        const int64_t sb = c1 - c0 > 1 ? off(at(t, g, r0, c0 + 1)) - off(a) : 0;
+                        bool ok = sa >= INT32_MIN && sa <= INT32_MAX && sb >= INT32_MIN && sb <= INT32_MAX;
+                        for (int r = r0; r < r1 && ok; ++r)
+                            for (int c = c0; c < c1 && ok; ++c) {
+                                const uint32_t v = at(t, g, r, c);
+                                ok = kind(v) == kind(a) &&
+                                     (kind(v) == 0 || off(v) == off(a) + (r - r0) * sa + (c - c0) * sb);
+                            }
+                        if (!ok)
+                            tt[t] = RTerm{RTERM_MAPPED, 0, 0};
+                        else if (kind(a) == 0)
+                            tt[t] = RTerm{RTERM_ZERO, 0, 0};
+                        else
+                            tt[t] = RTerm{off(a) | (kind(a) == 2 ? RTERM_NEG : 0), (int32_t)sa, (int32_t)sb};
+                        any |= tt[t].s0 != RTERM_ZERO;
+                    }
+                    if (any || op.beta != 1) {
+                        op.rtiles.push_back(rt);
+                        op.rterms.insert(op.rterms.end(), tt.begin(), tt.end());
+                    }
+                    c0 = c1;
+                }
+                r0 = r1;
+            }
+        }
+        // work units: consecutive tiles up to RUNIT_MAX_ELEMS elements / RUNIT_MAX_RECTS tiles
+        op.runits.clear();
+        for (size_t i = 0; i < op.rtiles.size();) {
+            RUnit u{(int32_t)i, 0};
+            int el = 0;
+            while (i < op.rtiles.size() && u.count < RUNIT_MAX_RECTS &&
+                   el + op.rtiles[i].nr * op.rtiles[i].nc <= RUNIT_MAX_ELEMS) {
+                el += op.rtiles[i].nr * op.rtiles[i].nc;
+                ++u.count;
+                ++i;
+            }
+            op.runits.push_back(u);
+        }
+    }
+
     void gather(const std::string& name, int dst, const Layout& Ld, int src, const Layout& Ls,
                 const std::vector<Term>& terms, cplx alpha, int beta, bool conj = false, int src2 = -1,
                 const Layout* Ls2 = nullptr) {
@@ -105,6 +190,7 @@ struct Builder {
             if (src2 >= 0)
                 op.mapsB.push_back(P.map(name + "/B" + std::to_string(t), build_map(Ld, *Ls2, terms[t].perm2, 1)));
         }
+        affine_tiles(op);
         prune_zero_tiles(op);
         out->push_back(std::move(op));
     }
@@ -133,6 +219,7 @@ struct Builder {
             op.mapsA.push_back(P.map(name + "/A" + std::to_string(t),
                                      build_map(Ld, *srcs[t].second, terms[t].perm, terms[t].sign)));
         }
+        affine_tiles(op);
         prune_zero_tiles(op);
         out->push_back(std::move(op));
     }

@@ -333,7 +333,10 @@ struct fscc_ctx {
                     gm.b[t] = t < (int)o.mapsB.size() ? dmap[o.mapsB[t]] : nullptr;
                     gm.src[t] = t < (int)o.srcT.size() ? (const void*)B(o.srcT[t]) : nullptr;
                 }
-                if (o.use_gtiles && o.d_gtiles && !sb.sys)
+                if (o.use_rtiles && o.d_rtiles && !sb.sys)
+                    e = launch_reorder(B(o.dst), B(o.src), gm, (int)o.mapsA.size(), o.d_runits, (int)o.runits.size(),
+                                       o.d_rtiles, o.d_rterms, o.alpha.real(), o.alpha.imag(), o.beta, o.conj, st);
+                else if (o.use_gtiles && o.d_gtiles && !sb.sys)
                     e = launch_gather_tiled(B(o.dst), B(o.src), o.src2 >= 0 ? B(o.src2) : nullptr, gm,
                                             (int)o.mapsA.size(), o.d_gtiles, (int)o.gtiles.size(), o.alpha.real(),
                                             o.alpha.imag(), o.beta, o.conj, st);

@@ -77,7 +77,7 @@ def _system(spec):
     return fsgen.make_system(p[0], p[1], p[2], p[3], p[4])
 
 
-@pytest.mark.parametrize("tiled", [0, 1], ids=["storage-order", "tiled-gathers"])
+@pytest.mark.parametrize("tiled", [0, 1, 2], ids=["storage-order", "tiled-gathers", "affine-tiles"])
 @pytest.mark.parametrize("spec", SYSTEMS, ids=[s[0] for s in SYSTEMS])
 def test_residual_matches_oracle(spec, tiled):
     torch = _torch()
@@ -108,11 +108,12 @@ def test_residual_matches_blocked_oracle_o20v120z8():
     d1, d2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
     r1, r2 = torch.empty_like(d1), torch.empty_like(d2)
     ctx.build_residual(d1, d2, r1, r2)
-    # the reorders by destination tiles give bitwise the same residual
-    ctx.gather_order(1)
-    q1, q2 = torch.empty_like(d1), torch.empty_like(d2)
-    ctx.build_residual(d1, d2, q1, q2)
-    assert torch.equal(q1, r1) and torch.equal(q2, r2)
+    # the reorders by destination tiles and by affine tiles give bitwise the same residual
+    for order in (0, 1, 2):
+        ctx.gather_order(order)
+        q1, q2 = torch.empty_like(d1), torch.empty_like(d2)
+        ctx.build_residual(d1, d2, q1, q2)
+        assert torch.equal(q1, r1) and torch.equal(q2, r2), order
     be = ccsd.Blocked(s)
     from oracle.blocks import BlockTensor
     bt1 = BlockTensor.from_dense(t1, [be.mem["O"], be.mem["V"]], list(be.D1.blocks.keys()))
@@ -225,7 +226,7 @@ def test_tiled_gathers_bitwise_equal_in_every_sector():
     ctx.prepare_sector(s1, s2, sector=F.FSCC_S02)
     p2 = rnd(ctx.p2)
     out = {}
-    for tiled in (0, 1):
+    for tiled in (0, 1, 2):
         ctx.gather_order(tiled)
         r = [torch.empty_like(x) for x in (d1, d2, s1, s2, p2)]
         ctx.build_residual(d1, d2, r[0], r[1])
@@ -233,6 +234,7 @@ def test_tiled_gathers_bitwise_equal_in_every_sector():
         ctx.build_residual(None, p2, None, r[4], sector=F.FSCC_S02)
         torch.cuda.synchronize()
         out[tiled] = r
-    for a, b in zip(out[0], out[1]):
-        assert torch.equal(a, b)
+    for tiled in (1, 2):
+        for a, b in zip(out[0], out[tiled]):
+            assert torch.equal(a, b), tiled
     ctx.destroy()

@@ -2,7 +2,9 @@
 reorders (gathers) of every operation list ((0h,0p), (0h,1p), (0h,2p)) stay
 inside the destination, cover no element twice and cover every element except
 those an accumulating gather leaves unchanged (all maps zero), for systems
-with empty irreps, ragged blocks and active spaces.  The planner source is compiled with g++
+with empty irreps, ragged blocks and active spaces; and the same holds for
+the affine tiles, whose every affine term reproduces the term's index map
+(offset, row and column stride, sign) element by element.  The planner source is compiled with g++
 (it uses no HIP)."""
 import ctypes
 import os
