@@ -648,14 +648,17 @@ def main():
     dev = torch.device("cuda:0")
     cfg = fsgen.WORKLOADS["o40v300z16"]
     s = fsgen.workload_system("o40v300z16")
+    setup = {}
     t0 = time.perf_counter()
     buffers = {}
     for C in fsgen.CLASSES:
         buffers[C], _ = fsgen.class_buffer(s, C)
-    log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
+    setup["inputs_s"] = round(time.perf_counter() - t0, 2)
+    log(f"inputs generated in {setup['inputs_s']:.1f}s")
     t0 = time.perf_counter()
     ctx = F.Context.from_system(s)
-    log(f"plan + device buffers in {time.perf_counter() - t0:.1f}s; n1={ctx.n1} n2={ctx.n2}")
+    setup["plan_s"] = round(time.perf_counter() - t0, 2)
+    log(f"plan + device buffers in {setup['plan_s']:.1f}s; n1={ctx.n1} n2={ctx.n2}")
     t0 = time.perf_counter()
     for C in fsgen.CLASSES:
         d = torch.from_numpy(buffers[C]).to(dev)
@@ -663,14 +666,26 @@ def main():
         del d
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"integral import + pack in {time.perf_counter() - t0:.1f}s")
+    setup["integrals_s"] = round(time.perf_counter() - t0, 2)
+    log(f"integral import + pack in {setup['integrals_s']:.1f}s")
 
+    # autotuning: measured once (the cache file starts empty), then read back
+    # from the autotune result cache, as a second run on this GPU would
+    import tempfile
+    tune_file = os.path.join(tempfile.mkdtemp(prefix="fscc_tune_"), "tune.json")
+    ctx.tune_cache(tune_file)
     t0 = time.perf_counter()
     ctx.autotune(1)
+    setup["autotune_s"] = round(time.perf_counter() - t0, 2)
+    t1_ = time.perf_counter()
+    ctx.autotune(1)
+    setup["autotune_cached_s"] = round(time.perf_counter() - t1_, 3)
+    setup["autotune_cache_hit"] = ctx.autotune_cached()
+    ctx.tune_cache(None)
     names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot", 12: "64x64r", 13: "64x32r"}
     tuned = {n: f"{names[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}/bk{b}{'/splitK' if sp else ''}"
              for n, c, b, sp in ctx.gemm_configs()}
-    log(f"autotuned GEMM tiles in {time.perf_counter() - t0:.1f}s: " +
+    log(f"autotuned GEMM tiles in {setup['autotune_s']:.1f}s (from the cache: {setup['autotune_cached_s']:.3f}s): " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
 
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device=dev)
@@ -751,6 +766,7 @@ def main():
                        "tflops": round(o["flops"] / (o["ms"] / max(1, o["calls"]) * 1e-3) / 1e12, 2)}
                       for o in sorted(gemms, key=lambda o: -o["ms"])[:4]],
         "residual_ms_per_iteration": round(resid_ms, 4),
+        "setup": setup,
         "reorders": reorder_table(ops, nwarm),
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,

@@ -311,6 +311,21 @@ fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, in
  * Results are numerically equivalent (summation order may change). */
 fscc_status fscc_autotune(fscc_ctx *ctx, int level);
 
+/* Autotune result cache (the paper's proposal to choose each block
+ * operation's parallelism from a first-iteration profile, kept across runs):
+ * with a path set, fscc_autotune(ctx, 1 or 2) first looks in that JSON file
+ * for an entry keyed by the GPU architecture, the precision, the level, the
+ * library's kernel-set version and a hash of every operation of the
+ * context's plans (kinds, sizes, GEMM problem shapes); if one fits it is
+ * applied without timing anything, otherwise every candidate is timed as
+ * usual and the choices are written to the file (entries of other keys are
+ * kept; the file is replaced through a rename).  path NULL or "" switches the
+ * cache off (the default).  An unreadable or unwritable file only costs the
+ * timing.  fscc_autotune_cached reports whether the last fscc_autotune call
+ * applied cached choices (1) or measured (0). */
+fscc_status fscc_tune_cache(fscc_ctx *ctx, const char *path);
+fscc_status fscc_autotune_cached(const fscc_ctx *ctx, int *from_cache);
+
 /* Traversal of the reorders / antisymmetrisers (gathers) of every operation
  * list (steps 1, 2 and 4 of the TTGT scheme of the algorithm-design section):
  * tiled = 0 walks each destination in storage order through per-element

@@ -78,6 +78,8 @@ def lib():
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
             "fscc_heff_eig": ([ip, vp, vp], ip),
             "fscc_set_validation": ([vp, ip], ip),
+            "fscc_tune_cache": ([vp, ctypes.c_char_p], ip),
+            "fscc_autotune_cached": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_mixed_config": ([vp, ip, ctypes.POINTER(ip)], ip),
             "fscc_zgemm_split": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, vp], ip),
@@ -337,6 +339,16 @@ class Context:
             out.append(dict(name=nm.value.decode(), ms=ms.value, calls=calls.value, flops=fl.value,
                             kind=("reorder", "gemm", "elementwise")[kind.value], bytes=by.value))
         return out
+
+    def tune_cache(self, path):
+        """Autotune result cache file (None: off)."""
+        self._check(lib().fscc_tune_cache(self._h, None if path is None else str(path).encode()))
+
+    def autotune_cached(self):
+        """True if the last autotune applied cached choices instead of timing."""
+        v = ctypes.c_int()
+        self._check(lib().fscc_autotune_cached(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def autotune(self, level=1):
         self._check(lib().fscc_autotune(self._h, int(level)))

@@ -272,11 +272,13 @@ fscc_status fscc_batch_create(const fscc_system* sys, int nsys, fscc_precision p
         std::vector<std::thread> pool;
         for (int w = 0; w < nw; ++w)
             pool.emplace_back([&, w]() {
+                plan_thread_depth()++;   // no nested threads inside one system's plan
                 try {
                     for (int s = w; s < nsys; s += nw) build_plan_ccsd(S[s], *b->sub[s]);
                 } catch (...) {
                     errs[w] = std::current_exception();
                 }
+                plan_thread_depth()--;
             });
         for (auto& t : pool) t.join();
         for (auto& e : errs)

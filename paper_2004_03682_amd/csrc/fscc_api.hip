@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -13,6 +14,8 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "runtime.hpp"
 
@@ -1237,6 +1240,217 @@ fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, in
 // Measure every candidate (tile shape x K depth x split) of each GEMM op on
 // the device and keep the fastest.  Timing is data independent, so the
 // context's own buffers and zeroed temporary amplitude buffers are used.
+namespace {
+
+// ---- autotune result cache ------------------------------------------------
+// One JSON file holds entries keyed by the GPU architecture, the precision,
+// the tuning level, a version of the kernel set and a hash of every operation
+// of the context's plans (kind, name, sizes, GEMM problem shapes); an entry
+// lists per operation the chosen form: GEMM [1, tile, bk, split, 3M, DB,
+// split-precision tile or -1], reorder [0, traversal], other [2].
+constexpr int kTuneVersion = 3;
+
+std::vector<OpList*> tune_lists(fscc_ctx* c) { return {&c->L00, &c->L01, &c->L02}; }
+
+std::string tune_key(fscc_ctx* c, int level) {
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xFF;
+            h *= 1099511628211ull;
+        }
+    };
+    for (OpList* L : tune_lists(c)) {
+        if (!L->ops) continue;
+        mix(L->ops->size());
+        for (const Op& o : *L->ops) {
+            mix((uint64_t)o.kind);
+            for (char ch : o.name) mix((uint64_t)(unsigned char)ch);
+            mix((uint64_t)o.n);
+            mix(o.mapsA.size());
+            mix(o.gtiles.size());
+            mix(o.rtiles.size());
+            mix((uint64_t)o.tA | ((uint64_t)o.tB << 1));
+            for (const GemmProblem& q : o.probs) {
+                mix((uint64_t)q.M);
+                mix((uint64_t)q.N);
+                mix((uint64_t)q.K);
+                mix(((uint64_t)q.lda << 40) ^ ((uint64_t)q.ldb << 20) ^ (uint64_t)q.ldc);
+            }
+        }
+    }
+    char hex[32];
+    std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
+    std::string arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == '"' || ch == '\\') ch = '_';
+    return arch + "|p" + std::to_string(c->prec) + "|L" + std::to_string(level) + "|v" + std::to_string(kTuneVersion) +
+           (c->real ? "|real" : "|complex") + "|" + hex;
+}
+
+std::vector<std::array<int, 7>> tune_collect(fscc_ctx* c) {
+    std::vector<std::array<int, 7>> out;
+    for (OpList* L : tune_lists(c)) {
+        if (!L->ops) continue;
+        for (size_t k = 0; k < L->ops->size(); ++k) {
+            const Op& o = (*L->ops)[k];
+            if (o.kind == OP_GEMM) {
+                const GemmDev& g = L->g[k];
+                out.push_back({1, g.cfg, g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.db ? 1 : 0, g.mx ? g.mx->cfg : -1});
+            } else if (o.kind == OP_GATHER) {
+                out.push_back({0, o.use_rtiles ? 2 : o.use_gtiles ? 1 : 0, 0, 0, 0, 0, -1});
+            } else {
+                out.push_back({2, 0, 0, 0, 0, 0, -1});
+            }
+        }
+    }
+    return out;
+}
+
+// Read the entry for key; false if the file or the entry is absent or malformed.
+bool tune_load(const std::string& path, const std::string& key, std::vector<std::array<int, 7>>& ops) {
+    std::FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    std::string text;
+    char buf[65536];
+    for (size_t r; (r = std::fread(buf, 1, sizeof buf, f)) > 0;) text.append(buf, r);
+    std::fclose(f);
+    const std::string tag = "{\"key\": \"" + key + "\", \"ops\": [";
+    size_t p = text.find(tag);
+    if (p == std::string::npos) return false;
+    p += tag.size();
+    ops.clear();
+    while (p < text.size()) {
+        while (p < text.size() && (text[p] == ' ' || text[p] == ',')) ++p;
+        if (p < text.size() && text[p] == ']') return true;
+        if (p >= text.size() || text[p] != '[') return false;
+        ++p;
+        std::array<int, 7> a;
+        for (int j = 0; j < 7; ++j) {
+            while (p < text.size() && (text[p] == ' ' || text[p] == ',')) ++p;
+            char* end = nullptr;
+            const long v = std::strtol(text.c_str() + p, &end, 10);
+            if (end == text.c_str() + p) return false;
+            a[j] = (int)v;
+            p = (size_t)(end - text.c_str());
+        }
+        while (p < text.size() && text[p] == ' ') ++p;
+        if (p >= text.size() || text[p] != ']') return false;
+        ++p;
+        ops.push_back(a);
+    }
+    return false;
+}
+
+// Add (or replace) the entry for key; the file is rewritten through a
+// temporary file and a rename, so a reader never sees half an entry.
+void tune_store(const std::string& path, const std::string& key, const std::vector<std::array<int, 7>>& ops) {
+    const std::string head = "{\"key\": \"";
+    std::vector<std::string> keep;
+    if (std::FILE* f = std::fopen(path.c_str(), "r")) {
+        std::string text;
+        char buf[65536];
+        for (size_t r; (r = std::fread(buf, 1, sizeof buf, f)) > 0;) text.append(buf, r);
+        std::fclose(f);
+        // one entry per line; keep the other keys' entries
+        for (size_t a = 0; a < text.size();) {
+            size_t b = text.find('\n', a);
+            if (b == std::string::npos) b = text.size();
+            std::string line = text.substr(a, b - a);
+            while (!line.empty() && (line.back() == ',' || line.back() == '\r')) line.pop_back();
+            if (line.rfind(head, 0) == 0 && line.rfind(head + key + "\"", 0) != 0) keep.push_back(line);
+            a = b + 1;
+        }
+    }
+    std::string e = head + key + "\", \"ops\": [";
+    for (size_t i = 0; i < ops.size(); ++i) {
+        e += i ? ", [" : "[";
+        for (int j = 0; j < 7; ++j) e += (j ? ", " : "") + std::to_string(ops[i][j]);
+        e += "]";
+    }
+    e += "]}";
+    keep.push_back(e);
+    const std::string tmp = path + ".tmp." + std::to_string((long long)getpid());
+    std::FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;   // an unwritable cache only costs the next run its tuning
+    std::fputs("{\"fscc_autotune_cache\": 1, \"entries\": [\n", f);
+    for (size_t i = 0; i < keep.size(); ++i) {
+        std::fputs(keep[i].c_str(), f);
+        std::fputs(i + 1 < keep.size() ? ",\n" : "\n", f);
+    }
+    std::fputs("]}\n", f);
+    if (std::fclose(f) == 0) {
+        if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+    } else {
+        std::remove(tmp.c_str());
+    }
+}
+
+// Apply cached choices; false (nothing changed) if they do not fit this plan.
+bool tune_apply(fscc_ctx* c, const std::vector<std::array<int, 7>>& ops) {
+    size_t i = 0;
+    for (OpList* L : tune_lists(c)) {
+        if (!L->ops) continue;
+        for (size_t k = 0; k < L->ops->size(); ++k, ++i) {
+            if (i >= ops.size()) return false;
+            const Op& o = (*L->ops)[k];
+            const auto& a = ops[i];
+            const int kind = o.kind == OP_GEMM ? 1 : o.kind == OP_GATHER ? 0 : 2;
+            if (a[0] != kind) return false;
+            if (kind == 1) {
+                if (!cfg_ok(o, a[1], c->real) || (a[2] != 16 && a[2] != 32)) return false;
+                if (a[5] && (c->real || a[2] != 16 || !zcfg_has_db(a[1]))) return false;
+                if (a[6] >= MCFG_N) return false;
+            } else if (kind == 0) {
+                if (a[1] < 0 || a[1] > 2 || (a[1] == 2 && !o.d_rtiles) || (a[1] == 1 && !o.d_gtiles)) return false;
+            }
+        }
+    }
+    if (i != ops.size()) return false;
+    i = 0;
+    for (OpList* L : tune_lists(c)) {
+        if (!L->ops) continue;
+        for (size_t k = 0; k < L->ops->size(); ++k, ++i) {
+            Op& o = (*L->ops)[k];
+            const auto& a = ops[i];
+            if (a[0] == 0) {
+                o.use_rtiles = a[1] == 2;
+                o.use_gtiles = a[1] == 1;
+            } else if (a[0] == 1) {
+                GemmDev& g = L->g[k];
+                MixedDev* keep = g.mx;
+                g.mx = nullptr;
+                free_gemm(g);
+                plan_gemm(c, o, g, a[1], a[2], a[3] != 0, a[4] != 0);
+                g.db = a[5] != 0;
+                g.mx = keep;
+                if (a[6] >= 0 && g.mx && g.mx->cfg != a[6]) {
+                    const int prec = g.mx->prec;
+                    fscc_ctx::free_mixed(g.mx);
+                    g.mx = plan_mixed(c, o, prec, a[6]);
+                }
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+fscc_status fscc_tune_cache(fscc_ctx* ctx, const char* path) {
+    if (!ctx) return FSCC_EINVAL;
+    ctx->tune_path = path ? path : "";
+    return FSCC_OK;
+}
+
+fscc_status fscc_autotune_cached(const fscc_ctx* ctx, int* from_cache) {
+    if (!ctx || !from_cache) return FSCC_EINVAL;
+    *from_cache = ctx->tune_from_cache ? 1 : 0;
+    return FSCC_OK;
+}
+
 fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
     if (!ctx) return FSCC_EINVAL;
     if (ctx->sp.buf >= 0) return fail(ctx, FSCC_ESTATE, "autotune before moving VVVV out of device memory");
@@ -1258,6 +1472,16 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                     L->g[k].mx = keep;
                 }
             return FSCC_OK;
+        }
+        ctx->tune_from_cache = false;
+        std::string key;
+        if (!ctx->tune_path.empty()) {
+            key = tune_key(ctx, level);
+            std::vector<std::array<int, 7>> cached;
+            if (tune_load(ctx->tune_path, key, cached) && tune_apply(ctx, cached)) {
+                ctx->tune_from_cache = true;
+                return FSCC_OK;
+            }
         }
         int64_t nio = 2 * std::max<int64_t>(1, ctx->n1()) + 2 * std::max<int64_t>(1, ctx->n2());
         if (P.has01) nio += 2 * std::max<int64_t>(1, P.L_S1.total) + 2 * std::max<int64_t>(1, P.L_S2.total);
@@ -1415,6 +1639,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         (void)hipEventDestroy(e1);
         hip_check(hipStreamSynchronize(ctx->st), "autotune sync");
         (void)hipFree(tmp);
+        if (!key.empty()) tune_store(ctx->tune_path, key, tune_collect(ctx));
         return FSCC_OK;
     });
 }

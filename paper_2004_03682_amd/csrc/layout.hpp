@@ -24,9 +24,13 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdint>
+#include <cstdlib>
+#include <exception>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace fscc {
@@ -227,6 +231,50 @@ struct Group {
     }
 };
 
+// Host threads for building one plan's maps: at most 16 (and at most
+// OMP_NUM_THREADS when that is set); 1 inside a worker thread (plans of a
+// batch are themselves built in parallel).
+inline int& plan_thread_depth() {
+    static thread_local int depth = 0;
+    return depth;
+}
+inline int plan_threads() {
+    if (plan_thread_depth() > 0) return 1;
+    int n = (int)std::max(1u, std::thread::hardware_concurrency());
+    if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+        const int m = std::atoi(e);
+        if (m > 0) n = std::min(n, m);
+    }
+    return std::min(n, 16);
+}
+
+// Run body(i) for i in [0, n) on up to plan_threads() threads (the first
+// exception is rethrown after all threads have finished).
+template <class F>
+void parallel_for(size_t n, F body) {
+    const int nt = (int)std::min<size_t>(n, (size_t)plan_threads());
+    if (nt <= 1) {
+        for (size_t i = 0; i < n; ++i) body(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> errs(nt);
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nt; ++w)
+        pool.emplace_back([&, w]() {
+            plan_thread_depth()++;
+            try {
+                for (size_t i; (i = next.fetch_add(1)) < n;) body(i);
+            } catch (...) {
+                errs[w] = std::current_exception();
+            }
+            plan_thread_depth()--;
+        });
+    for (auto& t : pool) t.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
 struct Layout {
     int G = 1;
     int rank = 0;              // number of logical slots
@@ -254,6 +302,43 @@ struct Layout {
         if (!kmask[kr]) throw std::logic_error("lookup into a non-materialised block of " + name);
         *sign = s1 * s2;
         return boff[kr] + lr * ncol[kr] + lc;
+    }
+
+    // visit every stored element, in chunks of rows on several host threads:
+    // f(offset, pos[logical]) must only write state owned by `offset`
+    template <class F>
+    void for_each_par(F f) const {
+        if (total < (int64_t)1 << 20 || plan_threads() <= 1) {
+            for_each(f);
+            return;
+        }
+        std::vector<std::vector<int>> rt(G), ct(G);
+        struct Chunk {
+            int k;
+            int64_t r0, r1;
+        };
+        std::vector<Chunk> work;
+        for (int k = 0; k < G; ++k) {
+            if (!kmask[k] || nrow[k] == 0 || ncol[k] == 0) continue;
+            rt[k] = R.tuples(k);
+            ct[k] = C.tuples(col_kappa(k));
+            const int64_t step = std::max<int64_t>(1, ((int64_t)1 << 16) / ncol[k]);
+            for (int64_t r = 0; r < nrow[k]; r += step) work.push_back(Chunk{k, r, std::min(nrow[k], r + step)});
+        }
+        const int rs = std::max(R.ns, 1), cs = std::max(C.ns, 1);
+        parallel_for(work.size(), [&](size_t i) {
+            const Chunk& w = work[i];
+            int pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int64_t o = boff[w.k] + w.r0 * ncol[w.k];
+            for (int64_t r = w.r0; r < w.r1; ++r) {
+                for (int q = 0; q < R.ns; ++q) pos[R.s[q].logical] = rt[w.k][r * rs + q];
+                for (int64_t c = 0; c < ncol[w.k]; ++c) {
+                    for (int q = 0; q < C.ns; ++q) pos[C.s[q].logical] = ct[w.k][c * cs + q];
+                    f(o, pos);
+                    ++o;
+                }
+            }
+        });
     }
 
     // visit every stored element in storage order: f(offset, pos[logical])
@@ -361,7 +446,7 @@ struct FullBlocks {
 template <class Src>
 std::vector<uint32_t> build_map(const Layout& dst, const Src& src, const std::vector<int>& perm, int sign) {
     std::vector<uint32_t> m((size_t)dst.total, MAP_ZERO);
-    dst.for_each([&](int64_t o, const int* x) {
+    dst.for_each_par([&](int64_t o, const int* x) {
         int y[8];
         for (size_t j = 0; j < perm.size(); ++j) y[j] = x[perm[j]];
         int s = 1;

@@ -71,16 +71,20 @@ struct Builder {
     // touches a few irrep blocks only).
     void prune_zero_tiles(Op& op) const {
         if (op.beta != 1) return;
-        std::vector<GTile> keep;
-        for (const GTile& t : op.gtiles) {
-            bool any = false;
-            for (size_t q = 0; q < op.mapsA.size() && !any; ++q) {
+        std::vector<char> any(op.gtiles.size(), 0);
+        parallel_for(op.gtiles.size(), [&](size_t i) {
+            const GTile& t = op.gtiles[i];
+            bool a = false;
+            for (size_t q = 0; q < op.mapsA.size() && !a; ++q) {
                 const std::vector<uint32_t>& m = P.maps[op.mapsA[q]];
-                for (int r = 0; r < t.nr && !any; ++r)
-                    for (int c = 0; c < t.nc && !any; ++c) any = m[(size_t)(t.k0 + (int64_t)r * t.ld + c)] != MAP_ZERO;
+                for (int r = 0; r < t.nr && !a; ++r)
+                    for (int c = 0; c < t.nc && !a; ++c) a = m[(size_t)(t.k0 + (int64_t)r * t.ld + c)] != MAP_ZERO;
             }
-            if (any) keep.push_back(t);
-        }
+            any[i] = a;
+        });
+        std::vector<GTile> keep;
+        for (size_t i = 0; i < op.gtiles.size(); ++i)
+            if (any[i]) keep.push_back(op.gtiles[i]);
         op.gtiles.swap(keep);
     }
 
@@ -116,7 +120,11 @@ struct Builder {
             }
             return true;
         };
-        for (const GTile& g : op.gtiles) {
+        // each 16 x 16 tile on its own (host threads), then concatenated in order
+        std::vector<std::vector<GTile>> part_t(op.gtiles.size());
+        std::vector<std::vector<RTerm>> part_q(op.gtiles.size());
+        parallel_for(op.gtiles.size(), [&](size_t gi) {
+            const GTile& g = op.gtiles[gi];
             for (int r0 = 0; r0 < g.nr;) {
                 int r1 = r0 + 1;
                 while (r1 < g.nr && continues(g, r0, 0, r1, 0)) ++r1;
@@ -146,13 +154,17 @@ struct Builder {
                         any |= tt[t].s0 != RTERM_ZERO;
                     }
                     if (any || op.beta != 1) {
-                        op.rtiles.push_back(rt);
-                        op.rterms.insert(op.rterms.end(), tt.begin(), tt.end());
+                        part_t[gi].push_back(rt);
+                        part_q[gi].insert(part_q[gi].end(), tt.begin(), tt.end());
                     }
                     c0 = c1;
                 }
                 r0 = r1;
             }
+        });
+        for (size_t gi = 0; gi < op.gtiles.size(); ++gi) {
+            op.rtiles.insert(op.rtiles.end(), part_t[gi].begin(), part_t[gi].end());
+            op.rterms.insert(op.rterms.end(), part_q[gi].begin(), part_q[gi].end());
         }
         // work units: consecutive tiles up to RUNIT_MAX_ELEMS elements / RUNIT_MAX_RECTS tiles
         op.runits.clear();

@@ -162,6 +162,8 @@ struct fscc_ctx {
     int prec = FSCC_FP64;
     const int* d_active = nullptr;   // batched plans: per-system flags, GEMM tiles of 0-systems are skipped
     int validate_n = 4096;           // sampled symmetry checks per integral class (fscc_set_validation)
+    std::string tune_path;           // autotune result cache (fscc_tune_cache); empty = none
+    bool tune_from_cache = false;    // the last fscc_autotune applied cached choices
     std::string err;
 
     int64_t n1() const { return plan.L_T1.total; }
