@@ -582,6 +582,32 @@ def batch_study(F, torch, fsgen, args, log):
     return out
 
 
+def sector_op_table(ctx, run, nrep=5, top=16):
+    """Per-operation times of one sector's residual (HIP events around each
+    operation over nrep evaluations): ms per call, TFLOP/s of the GEMMs, GB/s of
+    the algorithmic bytes, and the residual's total."""
+    ctx.profile(True)
+    for _ in range(nrep):
+        run()
+    ops = [o for o in ctx.op_times() if o["calls"] > 0]
+    ctx.profile(False)
+    rows = []
+    for o in ops:
+        per = o["ms"] / o["calls"]
+        row = {"op": o["name"], "kind": o["kind"], "ms_per_call": round(per, 4), "bytes": o["bytes"],
+               "GB_per_s": round(o["bytes"] / (per * 1e-3) / 1e9, 1) if per > 0 else None}
+        if o["flops"] > 0:
+            row["tflops"] = round(o["flops"] / (per * 1e-3) / 1e12, 2)
+        rows.append(row)
+    rows.sort(key=lambda r: -r["ms_per_call"])
+    total = sum(o["ms"] for o in ops) / nrep
+    by_kind = {}
+    for o in ops:
+        by_kind[o["kind"]] = by_kind.get(o["kind"], 0.0) + o["ms"] / nrep
+    return {"residual_ms": round(total, 4), "ms_by_kind": {k: round(v, 4) for k, v in by_kind.items()},
+            "bytes_per_residual": sum(o["bytes"] * o["calls"] for o in ops) / nrep, "ops": rows[:top]}
+
+
 def reorder_table(ops, nwarm):
     """HBM rate of the reorders / antisymmetrisers (TTGT steps 1, 2 and 4) from the
     per-operation times of the warm-up iterations and the library's algorithmic
@@ -604,6 +630,121 @@ def reorder_table(ops, nwarm):
             "ops": rows}
 
 
+PROFILE_REPS = 5
+
+
+def profile_reorders(args):
+    """Each reorder of one (0h,0p) residual run alone, PROFILE_REPS times in a
+    row, at the end of the run (so that the last PROFILE_REPS x n dispatches of
+    a counter run are exactly these, in this order).  Times them with HIP events
+    on the library's stream and writes the op list to args.profile_reorders."""
+    import torch
+
+    import fsgen
+    import paper_2004_03682_amd as F
+    s = fsgen.workload_system("o40v300z16")
+    ctx = F.Context.from_system(s)
+    for C in fsgen.CLASSES:
+        ctx.set_integrals(C, torch.from_numpy(fsgen.class_buffer(s, C)[0]).cuda())
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.tune_file:
+        ctx.tune_cache(args.tune_file)
+    ctx.autotune(1)
+    cached = ctx.autotune_cached()
+    t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+    r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+    # two iterations give the amplitudes (and so every reorder's input) their
+    # values of the second iteration; the residual binds the buffers
+    ctx.diis_reset(6)
+    for _ in range(2):
+        ctx.build_residual(t1, t2, r1, r2)
+        ctx.update_amplitudes(t1, t2, r1, r2)
+    ctx.profile(True)
+    ctx.build_residual(t1, t2, r1, r2)
+    ops = ctx.op_times()
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    sel = [k for k, o in enumerate(ops) if o["kind"] == "reorder" and o["calls"] > 0 and o["bytes"] > 0]
+    rows = []
+    for k in sel:
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(ctx.stream)
+        ctx.op_run(k, PROFILE_REPS)
+        b.record(ctx.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / PROFILE_REPS
+        rows.append({"k": k, "op": ops[k]["name"], "bytes": ops[k]["bytes"], "reps": PROFILE_REPS,
+                     "ms_per_call": ms, "GB_per_s": ops[k]["bytes"] / (ms * 1e-3) / 1e9})
+        log(f"  {ops[k]['name']:24s} {ms * 1e3:8.1f} us  {rows[-1]['GB_per_s']:7.1f} GB/s")
+    torch.cuda.synchronize()
+    with open(args.profile_reorders, "w") as f:
+        json.dump({"autotune_cached": cached, "ops": rows}, f, indent=1)
+    ctx.destroy()
+
+
+def _read_counters(path, counter):
+    """(dispatch id, kernel name, workgroups, value) per dispatch of a rocprofv3
+    --pmc csv, in dispatch order."""
+    import csv
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])),
+                        float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def summarize_reorders(args):
+    """Markdown table of the reorders' HBM traffic from the counter runs of
+    --profile-reorders (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration."""
+    times, fetch, write, cfetch, cwrite = args.summarize_reorders
+    prof = json.load(open(times))
+    rows = prof["ops"]
+    f = _read_counters(fetch, "FETCH_SIZE")
+    w = _read_counters(write, "WRITE_SIZE")
+    cf = [d for d in _read_counters(cfetch, "FETCH_SIZE") if "copyBuffer" in d[1]]
+    cw = [d for d in _read_counters(cwrite, "WRITE_SIZE") if "copyBuffer" in d[1]]
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / (sum(d[3] for d in cf) / len(cf))
+    wscale = gib_kib / (sum(d[3] for d in cw) / len(cw))
+    n = sum(r["reps"] for r in rows)
+    f, w = f[-n:], w[-n:]
+    lines = ["| op | kernel | workgroups | ms per call | algorithmic bytes | HBM read | HBM written "
+             "| counter / algorithmic | GB/s (algorithmic) | of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|---|"]
+    i = 0
+    tot_alg = tot_hbm = tot_ms = tot_rd = 0.0
+    for r in rows:
+        fs, ws = f[i:i + r["reps"]], w[i:i + r["reps"]]
+        i += r["reps"]
+        names = {d[1] for d in fs} | {d[1] for d in ws}
+        assert len(names) == 1, (r["op"], names)
+        kern = names.pop().split("(")[0].replace("void ", "")
+        grid = fs[0][2]
+        rd = sum(d[3] for d in fs) / len(fs) * fscale * 1024.0
+        wr = sum(d[3] for d in ws) / len(ws) * wscale * 1024.0
+        hbm = rd + wr
+        gbs = r["bytes"] / (r["ms_per_call"] * 1e-3) / 1e9
+        tot_alg += r["bytes"]
+        tot_hbm += hbm
+        tot_rd += rd
+        tot_ms += r["ms_per_call"]
+        lines.append(f"| {r['op']} | `{kern}` | {grid} | "
+                     f"{r['ms_per_call']:.4f} | {r['bytes'] / 1e6:.1f} MB | {rd / 1e6:.1f} MB | {wr / 1e6:.1f} MB | "
+                     f"{hbm / r['bytes']:.2f} | {gbs:.0f} | {gbs / PEAK_HBM:.2f} |")
+    lines.append(f"| all | | | {tot_ms:.4f} | {tot_alg / 1e6:.1f} MB | {tot_rd / 1e6:.1f} MB | "
+                 f"{(tot_hbm - tot_rd) / 1e6:.1f} MB | "
+                 f"{tot_hbm / tot_alg:.2f} | {tot_alg / (tot_ms * 1e-3) / 1e9:.0f} | "
+                 f"{tot_alg / (tot_ms * 1e-3) / 1e9 / PEAK_HBM:.2f} |")
+    print(f"calibration: fetch x {fscale:.4f}, write x {wscale:.4f} (1 GiB device copy)")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -621,7 +762,19 @@ def main():
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 device copies of 1 GiB (calibrates HBM byte counters)")
+    ap.add_argument("--profile-reorders", metavar="OUT_JSON",
+                    help="only run each reorder of one residual alone (for counter runs); write the op list")
+    ap.add_argument("--tune-file", help="autotune result cache file for --profile-reorders")
+    ap.add_argument("--summarize-reorders", nargs=5,
+                    metavar=("OPS_JSON", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="print the reorder traffic table from the counter runs")
     args = ap.parse_args()
+    if args.summarize_reorders:
+        summarize_reorders(args)
+        return
+    if args.profile_reorders:
+        profile_reorders(args)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
@@ -848,6 +1001,11 @@ def main():
         except F.FsccError as e:
             fs["dynamic_shift"] = {"S": S_dyn, "n": n_dyn, "status": f"failed ({e})"}
             log(f"(0h,1p) with dynamic shifts failed: {e}")
+        # per-operation table of the (0h,1p) residual at the last amplitudes
+        q1, q2 = torch.empty_like(s1), torch.empty_like(s2)
+        fs["residual_ops"] = sector_op_table(ctx, lambda: ctx.build_residual(s1, s2, q1, q2, F.FSCC_S01))
+        log(f"(0h,1p) residual {fs['residual_ops']['residual_ms']:.3f} ms: " +
+            ", ".join(f"{r['op']} {r['ms_per_call']:.3f}" for r in fs["residual_ops"]["ops"][:8]))
         result["fs01"] = fs
         if s.nact >= 2:
             # (0h,2p) from the last (0h,1p) amplitudes (the smallest-shift solve)

@@ -294,6 +294,13 @@ fscc_status fscc_op_count(const fscc_ctx *ctx, int *count);
  * (fscc_op_info) this gives each operation's HBM rate. */
 fscc_status fscc_op_traffic(const fscc_ctx *ctx, int k, int *kind, double *bytes);
 fscc_status fscc_op_info(fscc_ctx *ctx, int k, const char **name, double *ms, int *calls, double *flops);
+/* Run operation k alone, reps times (1..1000), on the buffers bound by the
+ * last residual evaluation of its sector (FSCC_ESTATE before one): a single
+ * reorder or GEMM of the TTGT scheme in isolation, for profiling its kernel
+ * (e.g. its HBM counters per dispatch).  Accumulating operations keep
+ * accumulating, so the sector's residual buffers hold no result afterwards.
+ * Asynchronous on the stream. */
+fscc_status fscc_op_run(fscc_ctx *ctx, int k, int reps);
 
 /* Tile-shape autotuner for the grouped complex GEMMs (the block contractions
  * of Fig. 4 have very uneven shapes).  level 1: every candidate tile shape,

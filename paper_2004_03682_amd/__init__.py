@@ -60,6 +60,7 @@ def lib():
             "fscc_op_count": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_op_info": ([vp, ip, ctypes.POINTER(ctypes.c_char_p), dp, ctypes.POINTER(ip), dp], ip),
             "fscc_op_traffic": ([vp, ip, ctypes.POINTER(ip), dp], ip),
+            "fscc_op_run": ([vp, ip, ip], ip),
             "fscc_prepare_sector": ([vp, ip, vp, vp], ip),
             "fscc_heff": ([vp, vp, vp, vp], ip),
             "fscc_heff2": ([vp, vp, vp], ip),
@@ -349,6 +350,10 @@ class Context:
         v = ctypes.c_int()
         self._check(lib().fscc_autotune_cached(self._h, ctypes.byref(v)))
         return bool(v.value)
+
+    def op_run(self, k, reps=1):
+        """Run operation k alone reps times (after one residual evaluation of its sector)."""
+        self._check(lib().fscc_op_run(self._h, int(k), int(reps)))
 
     def autotune(self, level=1):
         self._check(lib().fscc_autotune(self._h, int(level)))

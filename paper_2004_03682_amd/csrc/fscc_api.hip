@@ -228,7 +228,9 @@ void apply_precision(fscc_ctx* c, int prec) {
 // Algorithmic bytes of one call of an operation: every destination element
 // written once (and read once when accumulating), every distinct source
 // element read once, for the GEMMs each operand element read once.
-// Structural zeros of a gather map read nothing; index maps are not counted.
+// Structural zeros of a gather map read nothing, an accumulating gather
+// leaves the elements whose terms are all structural zeros untouched, and
+// index maps are not counted.
 double op_bytes(const Plan& P, const Op& o, const std::vector<int64_t>& nnz, size_t es) {
     const double e = (double)es;
     switch (o.kind) {
@@ -242,7 +244,23 @@ double op_bytes(const Plan& P, const Op& o, const std::vector<int64_t>& nnz, siz
         case OP_DIAG: return e * (double)o.n * 3.0 + 8.0 * (double)o.n;
         case OP_MUL: return e * (double)o.n * 2.0 + 8.0 * (double)o.n;
         case OP_GATHER: {
-            double b = e * (double)o.n * (1.0 + o.beta);
+            int64_t written = o.n;
+            if (o.beta) {
+                bool host_maps = true;
+                for (int m : o.mapsA) host_maps = host_maps && (int64_t)P.maps[m].size() == o.n;
+                for (int m : o.mapsB) host_maps = host_maps && (int64_t)P.maps[m].size() == o.n;
+                if (host_maps) {
+                    written = 0;
+                    for (int64_t k = 0; k < o.n; ++k) {
+                        bool any = false;
+                        for (size_t t = 0; t < o.mapsA.size() && !any; ++t)
+                            any = P.maps[o.mapsA[t]][k] != MAP_ZERO &&
+                                  (t >= o.mapsB.size() || P.maps[o.mapsB[t]][k] != MAP_ZERO);
+                        written += any;
+                    }
+                }
+            }
+            double b = e * (double)written * (1.0 + o.beta);
             // distinct source buffers: at most their size, at most the entries that read them
             std::vector<std::pair<int, int64_t>> reads;
             for (size_t t = 0; t < o.mapsA.size(); ++t) {
@@ -1219,6 +1237,28 @@ fscc_status fscc_op_traffic(const fscc_ctx* ctx, int k, int* kind, double* bytes
     *kind = o.kind == OP_GATHER ? 0 : o.kind == OP_GEMM ? 1 : 2;
     *bytes = o.bytes;
     return FSCC_OK;
+}
+
+fscc_status fscc_op_run(fscc_ctx* ctx, int k, int reps) {
+    if (!ctx || reps < 1 || reps > 1000) return FSCC_EINVAL;
+    OpList* L;
+    int j;
+    if (!op_ref(ctx, k, &L, &j)) return fail(ctx, FSCC_EINVAL, "op index out of range");
+    const Plan& P = ctx->plan;
+    auto bound = [&](std::initializer_list<int> ids) {
+        for (int b : ids)
+            if (b >= 0 && P.bufs[b].n > 0 && !ctx->dbuf[b]) return false;
+        return true;
+    };
+    const bool ok = L == &ctx->L00   ? bound({P.b_t1, P.b_t2, P.b_r1, P.b_r2}) && all_integrals(ctx)
+                    : L == &ctx->L01 ? ctx->ready01 && bound({P.b_s1, P.b_s2, P.b_rs1, P.b_rs2})
+                                     : ctx->ready02 && bound({P.b_s02, P.b_rs02});
+    if (!ok) return fail(ctx, FSCC_ESTATE, "evaluate the operation's residual once first");
+    return guarded(ctx, [&]() -> fscc_status {
+        const Op& o = (*L->ops)[j];
+        for (int r = 0; r < reps; ++r) ctx->run_op(o, o.kind == OP_GEMM ? &L->g[j] : nullptr);
+        return FSCC_OK;
+    });
 }
 
 fscc_status fscc_op_info(fscc_ctx* ctx, int k, const char** name, double* ms, int* calls, double* flops) {

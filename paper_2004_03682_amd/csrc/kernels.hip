@@ -1049,6 +1049,17 @@ __device__ __forceinline__ double2 map_load(const double2* __restrict__ s, uint3
     return x;
 }
 
+// Workgroup b of a launch of G runs on XCD b % 8, and each XCD has its own L2.
+// The reorders number their work so that XCD x takes one contiguous run of
+// about G / 8 logical blocks (x < G % 8 take one more): neighbouring
+// destination blocks, which read neighbouring source elements (the same cache
+// lines, for a transposition), then share one L2 instead of fetching those
+// lines once per XCD.  A bijection of [0, G).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned G) {
+    const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+    return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + i;
+}
+
 // element of this thread in a plain or segmented launch; false if none
 __device__ __forceinline__ bool elem_index(const SegBlocks& sb, long long n, long long* k) {
     if (sb.sys) {
@@ -1057,7 +1068,7 @@ __device__ __forceinline__ bool elem_index(const SegBlocks& sb, long long n, lon
         *k = sb.start[b] + threadIdx.x;
         return *k < sb.end[b];
     }
-    *k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    *k = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     return *k < n;
 }
 
@@ -1071,12 +1082,17 @@ __device__ __forceinline__ void gather_elem(double2* __restrict__ dst, const dou
                                             const double2* __restrict__ src2, const GatherMaps& maps, long long k,
                                             double ar, double ai, int beta, int conj) {
     double sr = 0.0, si = 0.0;
+    bool any = false;   // some term is not a structural zero
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        double2 x = map_load(maps.src[t] ? (const double2*)maps.src[t] : src, maps.a[t][k]);
+        const uint32_t ma = maps.a[t][k];
+        double2 x = map_load(maps.src[t] ? (const double2*)maps.src[t] : src, ma);
         if (conj) x.y = -x.y;
+        if (!BIL) any = any || ma != 0xFFFFFFFFu;
         if (BIL) {
-            double2 y = map_load(src2, maps.b[t][k]);
+            const uint32_t mb = maps.b[t][k];
+            any = any || (ma != 0xFFFFFFFFu && mb != 0xFFFFFFFFu);
+            double2 y = map_load(src2, mb);
             double xr = x.x * y.x - x.y * y.y, xi = x.x * y.y + x.y * y.x;
             x.x = xr;
             x.y = xi;
@@ -1084,6 +1100,9 @@ __device__ __forceinline__ void gather_elem(double2* __restrict__ dst, const dou
         sr += x.x;
         si += x.y;
     }
+    // an accumulating gather leaves an element whose terms are all structural
+    // zeros as it is (no read, no write)
+    if (beta && !any) return;
     double2 out = make_double2(ar * sr - ai * si, ar * si + ai * sr);
     if (beta) {
         double2 o = dst[k];
@@ -1111,7 +1130,7 @@ __global__ __launch_bounds__(256) void k_gather_tiled(double2* __restrict__ dst,
                                                       const double2* __restrict__ src2, GatherMaps maps,
                                                       const GTile* __restrict__ tiles, double ar, double ai, int beta,
                                                       int conj) {
-    const GTile t = tiles[blockIdx.x];
+    const GTile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int r = (w >> 1) * 8 + (l >> 3), c = (w & 1) * 8 + (l & 7);
     if (r >= t.nr || c >= t.nc) return;
@@ -1156,7 +1175,7 @@ __global__ __launch_bounds__(64) void k_reorder(double2* __restrict__ dst, const
                                                 double ar, double ai, int beta, int conj) {
     __shared__ double2 tr[NT][RUNIT_MAX_ELEMS];
     const int lane = threadIdx.x;
-    const RUnit u = units[blockIdx.x];
+    const RUnit u = units[xcd_block(blockIdx.x, gridDim.x)];
     // tile of each of the lane's elements: element offsets of the unit's tiles
     int start[RUNIT_MAX_RECTS + 1];
     GTile tl[RUNIT_MAX_RECTS];

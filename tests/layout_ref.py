@@ -227,3 +227,41 @@ def unpack_s02(sysm, buf):
         full[Y[:, None], X[:, None], B[None, :], A[None, :]] = x
     assert off == buf.size
     return np.array([full[i, j] for i in range(n) for j in range(i + 1, n)]).reshape(-1, sysm.nvirt, sysm.nvirt)
+
+
+def t2_positions(sysm, idx):
+    """Packed T2 offsets of elements (i, j, a, b) with i < j, a < b (positions in
+    the occupied and virtual spaces), for sampled comparisons without unpacking."""
+    n = sysm.nirrep
+    go, gv = sysm.irrep[:sysm.nocc], sysm.irrep[sysm.nocc:]
+    off, rows, cols = {}, {}, {}
+    o = 0
+    for G in range(n):
+        I, J = pair_list(sysm, "O", G)
+        A, B = pair_list(sysm, "V", G)
+        off[G] = o
+        rows[G] = {(int(p), int(q)): k for k, (p, q) in enumerate(zip(I, J))}
+        cols[G] = {(int(p), int(q)): k for k, (p, q) in enumerate(zip(A, B))}
+        o += len(I) * len(A)
+    out = []
+    for i, j, a, b in idx:
+        G = (int(go[i]) + int(go[j])) % n
+        assert (int(gv[a]) + int(gv[b])) % n == G
+        out.append(off[G] + rows[G][(i, j)] * len(cols[G]) + cols[G][(a, b)])
+    return np.array(out, dtype=np.int64)
+
+
+def t1_positions(sysm, idx):
+    """Packed T1 offsets of elements (i, a)."""
+    out = []
+    base = 0
+    offs = {}
+    for g in range(sysm.nirrep):
+        mo, mv = members(sysm, "O", g), members(sysm, "V", g)
+        offs[g] = (base, {int(p): k for k, p in enumerate(mo)}, {int(p): k for k, p in enumerate(mv)}, len(mv))
+        base += len(mo) * len(mv)
+    for i, a in idx:
+        g = int(sysm.irrep[i])
+        b0, ro, co, nv = offs[g]
+        out.append(b0 + ro[i] * nv + co[a])
+    return np.array(out, dtype=np.int64)
