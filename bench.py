@@ -97,10 +97,44 @@ def time_to(hist, E_ref, t_start, thr=1e-8):
     return k + 1, round(hist[k]["time"] - t_start, 5)
 
 
-def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
+GOLDEN = os.path.join(ROOT, "tests", "golden", "o40v300z16_ccsd.json")
+
+
+def oracle_fixed_point(sysm):
+    """The block-list oracle's converged fixed point of the production system
+    (stored by tests/golden/make_golden.py): E, and a comparator giving the
+    largest |t - t_oracle| of packed device amplitudes over every T1 element
+    and the stored T2 sample; None if the file is absent."""
+    if not os.path.exists(GOLDEN):
+        return None
+    g = json.load(open(GOLDEN))
+    if g["config"]["seed"] != sysm.seed or not g["converged"]:
+        return None
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import layout_ref as LR
+    T1 = np.array(g["t1"])
+    T2 = np.array(g["t2_sample"])
+    p1 = LR.t1_positions(sysm, [(int(i), int(a)) for i, a in T1[:, :2]])
+    p2, sg2 = LR.t2_positions(sysm, [tuple(int(x) for x in r[:4]) for r in T2])
+    v1 = T1[:, 2] + 1j * T1[:, 3]
+    v2 = T2[:, 4] + 1j * T2[:, 5]
+
+    def dt(t1, t2):
+        a = t1.cpu().numpy()[p1]
+        b = sg2 * t2.cpu().numpy()[p2]
+        return float(np.abs(a - v1).max()), float(np.abs(b - v2).max())
+    return {"E": complex(g["E_re"], g["E_im"]), "iters_to_1e10": g["iters_to_1e10"], "tol": g["tol"], "dt": dt,
+            "t2_sample": len(T2)}
+
+
+def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
     """FP64 against split-BF16 / split-FP32 ladder + ring contractions:
     per-iteration time, per-result error and time to |E - E_inf| < 1e-8 Eh
-    (E_inf = the FP64 converged energy), all from the same zero start."""
+    (E_inf = the oracle's converged energy when stored, else the FP64 one),
+    all from the same zero start; amplitude errors against the oracle's
+    fixed point (every T1 element and the stored T2 sample) when stored, and
+    against the FP64 GPU fixed point."""
     u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device=dev)
     u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device=dev)
     q1, q2 = torch.empty_like(u1), torch.empty_like(u2)
@@ -192,9 +226,13 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log):
         k8, s8 = time_to(c["history"], E_inf, ts)
         rec["split_only"] = {"iterations": c["iters"], "last_max_step": c["history"][-1]["dmax"],
                              "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
-                             "dE_vs_fp64": abs(c["E"] - E_inf),
+                             "dE_vs_reference": abs(c["E"] - E_inf),
                              "max_abs_dt1_vs_fp64": float((u1 - tconv[0]).abs().max()),
                              "max_abs_dt2_vs_fp64": float((u2 - tconv[1]).abs().max())}
+        if ora is not None:
+            d1, d2 = ora["dt"](u1, u2)
+            rec["split_only"]["max_abs_dt1_vs_oracle"] = d1
+            rec["split_only"]["max_abs_dt2_sample_vs_oracle"] = d2
         log(f"{prec}: split-only after {c['iters']} iterations: max|step| {c['history'][-1]['dmax']:.2e}, "
             f"|dE| = {abs(c['E'] - E_inf):.2e}; {per_it * 1e3:.3f} ms/iteration, residual rel. error {err:.2e}")
         out[prec] = rec
@@ -633,11 +671,14 @@ def reorder_table(ops, nwarm):
 PROFILE_REPS = 5
 
 
-def profile_reorders(args):
-    """Each reorder of one (0h,0p) residual run alone, PROFILE_REPS times in a
-    row, at the end of the run (so that the last PROFILE_REPS x n dispatches of
-    a counter run are exactly these, in this order).  Times them with HIP events
-    on the library's stream and writes the op list to args.profile_reorders."""
+def profile_ops(args):
+    """Operations of one residual run alone, PROFILE_REPS times in a row each,
+    at the end of the program, every batch preceded by one small torch fill
+    kernel as a marker (so that the dispatches of operation i in a counter
+    run are those between the i-th of the last n markers and the next).
+    Times them with HIP events on the library's stream and writes the list to
+    args.profile_ops.  --ops: "reorders" (every reorder), "gemms", or names;
+    --sector 0 or 1 ((0h,0p) or (0h,1p), 6 active virtuals); --precision."""
     import torch
 
     import fsgen
@@ -652,95 +693,132 @@ def profile_reorders(args):
         ctx.tune_cache(args.tune_file)
     ctx.autotune(1)
     cached = ctx.autotune_cached()
+    if args.precision != "fp64":
+        ctx.set_precision(args.precision)
+        ctx.autotune(2)
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
-    # two iterations give the amplitudes (and so every reorder's input) their
-    # values of the second iteration; the residual binds the buffers
+    # two iterations give the amplitudes (and so every operation's input) the
+    # values of the second iteration; the last residual binds the buffers
     ctx.diis_reset(6)
     for _ in range(2):
         ctx.build_residual(t1, t2, r1, r2)
         ctx.update_amplitudes(t1, t2, r1, r2)
+    run = lambda: ctx.build_residual(t1, t2, r1, r2)
+    if args.sector == 1:
+        ctx.prepare_sector(t1, t2)
+        ctx.precondition(1, 0.1)
+        s1 = torch.zeros(ctx.m1, dtype=torch.complex128, device="cuda")
+        s2 = torch.zeros(ctx.m2, dtype=torch.complex128, device="cuda")
+        q1, q2 = torch.empty_like(s1), torch.empty_like(s2)
+        ctx.diis_reset(6, F.FSCC_S01)
+        ctx.build_residual(s1, s2, q1, q2, F.FSCC_S01)
+        ctx.update_amplitudes(s1, s2, q1, q2, F.FSCC_S01)
+        run = lambda: ctx.build_residual(s1, s2, q1, q2, F.FSCC_S01)
     ctx.profile(True)
-    ctx.build_residual(t1, t2, r1, r2)
+    run()
     ops = ctx.op_times()
     ctx.profile(False)
     torch.cuda.synchronize()
-    sel = [k for k, o in enumerate(ops) if o["kind"] == "reorder" and o["calls"] > 0 and o["bytes"] > 0]
+    if args.ops == "reorders":
+        sel = [k for k, o in enumerate(ops) if o["kind"] == "reorder" and o["calls"] > 0 and o["bytes"] > 0]
+    elif args.ops == "all":
+        sel = [k for k, o in enumerate(ops) if o["calls"] > 0]
+    elif args.ops == "gemms":
+        sel = [k for k, o in enumerate(ops) if o["kind"] == "gemm" and o["calls"] > 0]
+    else:
+        names = args.ops.split(",")
+        sel = [k for k, o in enumerate(ops) if o["name"] in names and o["calls"] > 0]
+    marker = torch.zeros(64, dtype=torch.float32, device="cuda")
     rows = []
-    for k in sel:
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(ctx.stream)
-        ctx.op_run(k, PROFILE_REPS)
-        b.record(ctx.stream)
-        b.synchronize()
-        ms = a.elapsed_time(b) / PROFILE_REPS
-        rows.append({"k": k, "op": ops[k]["name"], "bytes": ops[k]["bytes"], "reps": PROFILE_REPS,
-                     "ms_per_call": ms, "GB_per_s": ops[k]["bytes"] / (ms * 1e-3) / 1e9})
-        log(f"  {ops[k]['name']:24s} {ms * 1e3:8.1f} us  {rows[-1]['GB_per_s']:7.1f} GB/s")
+    with torch.cuda.stream(ctx.stream):
+        for k in sel:
+            marker.fill_(float(k))
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(ctx.stream)
+            ctx.op_run(k, PROFILE_REPS)
+            b.record(ctx.stream)
+            b.synchronize()
+            ms = a.elapsed_time(b) / PROFILE_REPS
+            o = ops[k]
+            rows.append({"k": k, "op": o["name"], "kind": o["kind"], "bytes": o["bytes"], "flops": o["flops"],
+                         "reps": PROFILE_REPS, "ms_per_call": ms, "GB_per_s": o["bytes"] / (ms * 1e-3) / 1e9})
+            log(f"  {o['name']:24s} {ms * 1e3:8.1f} us  {rows[-1]['GB_per_s']:7.1f} GB/s"
+                + (f"  {o['flops'] / (ms * 1e-3) / 1e12:6.2f} TFLOP/s" if o["flops"] else ""))
     torch.cuda.synchronize()
-    with open(args.profile_reorders, "w") as f:
-        json.dump({"autotune_cached": cached, "ops": rows}, f, indent=1)
+    with open(args.profile_ops, "w") as f:
+        json.dump({"autotune_cached": cached, "precision": args.precision, "sector": args.sector, "ops": rows},
+                  f, indent=1)
     ctx.destroy()
 
 
-def _read_counters(path, counter):
-    """(dispatch id, kernel name, workgroups, value) per dispatch of a rocprofv3
-    --pmc csv, in dispatch order."""
+def _read_counters(path, counters):
+    """Per dispatch of a rocprofv3 --pmc csv, in dispatch order: (id, kernel
+    name, workgroups, {counter: value})."""
     import csv
-    out = []
+    by = {}
     with open(path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] != counter:
-                continue
-            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])),
-                        float(r["Counter_Value"])))
-    out.sort()
-    return out
+            d = int(r["Dispatch_Id"])
+            e = by.setdefault(d, [d, r["Kernel_Name"], int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), {}])
+            if r["Counter_Name"] in counters:
+                e[3][r["Counter_Name"]] = e[3].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [by[d] for d in sorted(by)]
 
 
-def summarize_reorders(args):
-    """Markdown table of the reorders' HBM traffic from the counter runs of
-    --profile-reorders (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration."""
-    times, fetch, write, cfetch, cwrite = args.summarize_reorders
+def _windows(disp, nops):
+    """Dispatches of each profiled operation: between the last nops markers."""
+    marks = [i for i, d in enumerate(disp) if "FillFunctor" in d[1]][-nops:]
+    assert len(marks) == nops, "marker kernels not found"
+    return [disp[m + 1:(marks[j + 1] if j + 1 < nops else len(disp))] for j, m in enumerate(marks)]
+
+
+def _short(kernel):
+    k = kernel.split("(")[0].replace("void ", "").replace("fscc::", "")
+    return k
+
+
+def summarize_ops(args):
+    """Markdown table of HBM traffic per operation from the counter runs of
+    --profile-ops (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration: per
+    operation and kernel, counter bytes per call against the operation's
+    algorithmic bytes and its time."""
+    times, fetch, write, cfetch, cwrite = args.summarize_ops
     prof = json.load(open(times))
     rows = prof["ops"]
-    f = _read_counters(fetch, "FETCH_SIZE")
-    w = _read_counters(write, "WRITE_SIZE")
-    cf = [d for d in _read_counters(cfetch, "FETCH_SIZE") if "copyBuffer" in d[1]]
-    cw = [d for d in _read_counters(cwrite, "WRITE_SIZE") if "copyBuffer" in d[1]]
+    cf = [d for d in _read_counters(cfetch, {"FETCH_SIZE"}) if "copyBuffer" in d[1]]
+    cw = [d for d in _read_counters(cwrite, {"WRITE_SIZE"}) if "copyBuffer" in d[1]]
     gib_kib = float(1 << 20)
-    fscale = gib_kib / (sum(d[3] for d in cf) / len(cf))
-    wscale = gib_kib / (sum(d[3] for d in cw) / len(cw))
-    n = sum(r["reps"] for r in rows)
-    f, w = f[-n:], w[-n:]
-    lines = ["| op | kernel | workgroups | ms per call | algorithmic bytes | HBM read | HBM written "
-             "| counter / algorithmic | GB/s (algorithmic) | of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|---|"]
-    i = 0
-    tot_alg = tot_hbm = tot_ms = tot_rd = 0.0
-    for r in rows:
-        fs, ws = f[i:i + r["reps"]], w[i:i + r["reps"]]
-        i += r["reps"]
-        names = {d[1] for d in fs} | {d[1] for d in ws}
-        assert len(names) == 1, (r["op"], names)
-        kern = names.pop().split("(")[0].replace("void ", "")
-        grid = fs[0][2]
-        rd = sum(d[3] for d in fs) / len(fs) * fscale * 1024.0
-        wr = sum(d[3] for d in ws) / len(ws) * wscale * 1024.0
-        hbm = rd + wr
+    fscale = gib_kib / (sum(d[3]["FETCH_SIZE"] for d in cf) / len(cf))
+    wscale = gib_kib / (sum(d[3]["WRITE_SIZE"] for d in cw) / len(cw))
+    fw = _windows(_read_counters(fetch, {"FETCH_SIZE"}), len(rows))
+    ww = _windows(_read_counters(write, {"WRITE_SIZE"}), len(rows))
+    lines = ["| op | kernels (dispatches per call) | workgroups | ms per call | algorithmic bytes | HBM read "
+             "| HBM written | counter / algorithmic | GB/s (algorithmic) | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    tot_alg = tot_rd = tot_wr = tot_ms = 0.0
+    for r, fs, ws in zip(rows, fw, ww):
+        reps = r["reps"]
+        kern = {}
+        for d in fs:
+            kern.setdefault(_short(d[1]), [0, d[2]])[0] += 1
+        rd = sum(d[3].get("FETCH_SIZE", 0.0) for d in fs) / reps * fscale * 1024.0
+        wr = sum(d[3].get("WRITE_SIZE", 0.0) for d in ws) / reps * wscale * 1024.0
         gbs = r["bytes"] / (r["ms_per_call"] * 1e-3) / 1e9
         tot_alg += r["bytes"]
-        tot_hbm += hbm
         tot_rd += rd
+        tot_wr += wr
         tot_ms += r["ms_per_call"]
-        lines.append(f"| {r['op']} | `{kern}` | {grid} | "
-                     f"{r['ms_per_call']:.4f} | {r['bytes'] / 1e6:.1f} MB | {rd / 1e6:.1f} MB | {wr / 1e6:.1f} MB | "
-                     f"{hbm / r['bytes']:.2f} | {gbs:.0f} | {gbs / PEAK_HBM:.2f} |")
+        ks = ", ".join(f"`{k}` ({n // reps})" for k, (n, g) in kern.items())
+        grids = "/".join(str(g) for k, (n, g) in kern.items())
+        lines.append(f"| {r['op']} | {ks} | {grids} | {r['ms_per_call']:.4f} | {r['bytes'] / 1e6:.1f} MB | "
+                     f"{rd / 1e6:.1f} MB | {wr / 1e6:.1f} MB | {(rd + wr) / r['bytes']:.2f} | {gbs:.0f} | "
+                     f"{gbs / PEAK_HBM:.2f} |")
     lines.append(f"| all | | | {tot_ms:.4f} | {tot_alg / 1e6:.1f} MB | {tot_rd / 1e6:.1f} MB | "
-                 f"{(tot_hbm - tot_rd) / 1e6:.1f} MB | "
-                 f"{tot_hbm / tot_alg:.2f} | {tot_alg / (tot_ms * 1e-3) / 1e9:.0f} | "
-                 f"{tot_alg / (tot_ms * 1e-3) / 1e9 / PEAK_HBM:.2f} |")
+                 f"{tot_wr / 1e6:.1f} MB | {(tot_rd + tot_wr) / tot_alg:.2f} | "
+                 f"{tot_alg / (tot_ms * 1e-3) / 1e9:.0f} | {tot_alg / (tot_ms * 1e-3) / 1e9 / PEAK_HBM:.2f} |")
     print(f"calibration: fetch x {fscale:.4f}, write x {wscale:.4f} (1 GiB device copy)")
     print("\n".join(lines))
 
@@ -762,18 +840,22 @@ def main():
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 device copies of 1 GiB (calibrates HBM byte counters)")
-    ap.add_argument("--profile-reorders", metavar="OUT_JSON",
-                    help="only run each reorder of one residual alone (for counter runs); write the op list")
-    ap.add_argument("--tune-file", help="autotune result cache file for --profile-reorders")
-    ap.add_argument("--summarize-reorders", nargs=5,
+    ap.add_argument("--profile-ops", metavar="OUT_JSON",
+                    help="only run operations of one residual alone (for counter runs); write the op list")
+    ap.add_argument("--ops", default="reorders", help="--profile-ops: reorders, gemms, all or op names (a,b,...)")
+    ap.add_argument("--sector", type=int, default=0, choices=(0, 1), help="--profile-ops: (0h,0p) or (0h,1p)")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "split_bf16", "split_fp32"),
+                    help="--profile-ops: precision of the split-eligible GEMMs")
+    ap.add_argument("--tune-file", help="autotune result cache file for --profile-ops")
+    ap.add_argument("--summarize-ops", nargs=5,
                     metavar=("OPS_JSON", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="print the reorder traffic table from the counter runs")
+                    help="print the per-operation traffic table from the counter runs")
     args = ap.parse_args()
-    if args.summarize_reorders:
-        summarize_reorders(args)
+    if args.summarize_ops:
+        summarize_ops(args)
         return
-    if args.profile_reorders:
-        profile_reorders(args)
+    if args.profile_ops:
+        profile_ops(args)
         return
     if args.copy_calibration:
         import torch
@@ -924,21 +1006,35 @@ def main():
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,
     }
+    ora = oracle_fixed_point(s)
+    E_ref = E
     if args.converge or not args.no_fs01 or not args.no_mixed:
-        # continue to convergence, record |E_k - E_inf| < 1e-8 Eh
+        # continue to convergence, record |E_k - E_inf| < 1e-8 Eh, E_inf the
+        # oracle's converged energy (tests/golden) when stored
         it = args.warmup + args.steps
         es = [h[1] for h in hist]
         while dmax >= 1e-10 and it < 300:
             dmax, E = step()
             it += 1
             es.append(E)
+        E_ref = ora["E"] if ora else E
         first = args.warmup + 1
-        k8 = next((first + k for k, e in enumerate(es) if all(abs(x - E) < 1e-8 for x in es[k:])), None)
+        k8 = next((first + k for k, e in enumerate(es) if all(abs(x - E_ref) < 1e-8 for x in es[k:])), None)
         result["converged_iterations"] = it
         result["iterations_to_1e-8"] = k8
         result["converged_energy"] = [E.real, E.imag]
+        if ora:
+            d1, d2 = ora["dt"](t1, t2)
+            result["vs_oracle"] = {
+                "oracle_energy": [ora["E"].real, ora["E"].imag], "oracle_tol": ora["tol"],
+                "dE_re": E.real - ora["E"].real, "dE_im": E.imag - ora["E"].imag,
+                "max_abs_dt1": d1, "max_abs_dt2_sample": d2, "t2_sample": ora["t2_sample"],
+                "iterations_to_1e-10": it, "oracle_iterations_to_1e-10": ora["iters_to_1e10"],
+                "iterations_to_1e-8_measured_against": "oracle E"}
+            log(f"vs oracle: dE = {E.real - ora['E'].real:.2e} {E.imag - ora['E'].imag:+.2e}i, "
+                f"max|dT1| {d1:.2e}, max|dT2| (sample) {d2:.2e}")
     if not args.no_mixed:
-        result["precision"] = precision_study(ctx, F, torch, dev, E, (t1, t2), args, log)
+        result["precision"] = precision_study(ctx, F, torch, dev, E_ref, (t1, t2), args, log, ora)
     if not args.no_fs01:
         # (0h,1p) sector with the 6 lowest virtual spinors active, on the converged T
         ctx.prepare_sector(t1, t2)

@@ -230,8 +230,11 @@ def unpack_s02(sysm, buf):
 
 
 def t2_positions(sysm, idx):
-    """Packed T2 offsets of elements (i, j, a, b) with i < j, a < b (positions in
-    the occupied and virtual spaces), for sampled comparisons without unpacking."""
+    """Packed T2 offsets and signs of elements (i, j, a, b) (positions in the
+    occupied and virtual spaces): t2[i, j, a, b] = sign * packed[offset].  A
+    pair is stored once, in the order of pair_list (lower irrep first, then
+    ascending position), so a swapped pair reads its stored partner with a
+    minus sign."""
     n = sysm.nirrep
     go, gv = sysm.irrep[:sysm.nocc], sysm.irrep[sysm.nocc:]
     off, rows, cols = {}, {}, {}
@@ -243,12 +246,20 @@ def t2_positions(sysm, idx):
         rows[G] = {(int(p), int(q)): k for k, (p, q) in enumerate(zip(I, J))}
         cols[G] = {(int(p), int(q)): k for k, (p, q) in enumerate(zip(A, B))}
         o += len(I) * len(A)
-    out = []
+
+    def find(table, p, q):
+        if (p, q) in table:
+            return table[(p, q)], 1.0
+        return table[(q, p)], -1.0
+    pos, sign = [], []
     for i, j, a, b in idx:
         G = (int(go[i]) + int(go[j])) % n
         assert (int(gv[a]) + int(gv[b])) % n == G
-        out.append(off[G] + rows[G][(i, j)] * len(cols[G]) + cols[G][(a, b)])
-    return np.array(out, dtype=np.int64)
+        r, sr = find(rows[G], int(i), int(j))
+        c, sc = find(cols[G], int(a), int(b))
+        pos.append(off[G] + r * len(cols[G]) + c)
+        sign.append(sr * sc)
+    return np.array(pos, dtype=np.int64), np.array(sign)
 
 
 def t1_positions(sysm, idx):
