@@ -238,12 +238,18 @@ fscc_status fscc_heff2(fscc_ctx *ctx, const fscc_c128 *s, fscc_c128 *heff_host);
  * converge in 60 n steps. */
 fscc_status fscc_heff_eig(int n, const fscc_c128 *heff_host, fscc_c128 *eig_host);
 
-/* Jacobi denominators of the (0h,1p) sector (sector = FSCC_S01).  mode 0:
- * D from the orbital energies (Eq. (3)-(4), the default).  mode 1 (after
+/* Jacobi denominators of a sector.  mode 0: D from the orbital energies
+ * (Eq. (3)-(4), the default).  mode 1, dressed: sector FSCC_S01 (after
  * fscc_prepare_sector): D from the diagonal of Hbar, D_x^a = Re(Fbar_xx -
- * Fbar_aa), D_xj^ab = Re(Fbar_xx + Fbar_jj - Fbar_aa - Fbar_bb), clamped to
- * <= -floor (floor > 0, Eh).  Only the step changes, not the solution of the
- * Bloch equation; clears the sector's DIIS history. */
+ * Fbar_aa), D_xj^ab = Re(Fbar_xx + Fbar_jj - Fbar_aa - Fbar_bb); sector
+ * FSCC_S00 (after a (0h,0p) residual evaluation, FSCC_ESTATE before one): the
+ * diagonal of the amplitude equations at the amplitudes of that residual,
+ * f_p = e_p + Re F'_pp with the one-body intermediates F'_be (virtual) and
+ * F'_mj (occupied) that multiply t2 in Eq. (3), D_i^a = f_i - f_a and
+ * D_ij^ab = f_i + f_j - f_a - f_b; clamped to <= -floor (floor > 0, Eh).  The
+ * dressed denominators are computed once per call (call again to refresh
+ * them).  Only the step changes, not the solution of the amplitude or Bloch
+ * equations; clears the sector's DIIS history. */
 fscc_status fscc_precondition(fscc_ctx *ctx, fscc_sector sector, int mode, double floor);
 
 /* Correlation energy of the (0h,0p) sector, the expectation value of Eq. (1)'s
@@ -562,6 +568,16 @@ fscc_status fscc_batch_step(fscc_batch *b, fscc_c128 *t1, fscc_c128 *t2, fscc_c1
  * amplitudes their segments then hold; iteration counts keep running.
  * Synchronous. */
 fscc_status fscc_batch_restart(fscc_batch *b, const int *mask);
+
+/* Jacobi denominators of every system of the batch, as fscc_precondition for
+ * the (0h,0p) sector: mode 0 the bare orbital-energy differences (default),
+ * mode 1 the dressed ones, f_i + f_j - f_a - f_b with f_p = e_p + Re F'_pp
+ * from each system's F'_be, F'_mj of the last residual evaluation (FSCC_ESTATE
+ * before the first step or residual), clamped to <= -floor (floor > 0, Eh);
+ * the step is R / (D - shift).  The solution R = 0 is unchanged.  Every
+ * system's DIIS subspace restarts (active flags and iteration counts are
+ * kept); switching between modes drops a captured graph.  Synchronous. */
+fscc_status fscc_batch_precondition(fscc_batch *b, int mode, double floor);
 
 /* Device copies of the batch's Jacobi denominators D (concatenated T1 / T2
  * layouts, e_i - e_a and e_i + e_j - e_a - e_b, without level shift). */

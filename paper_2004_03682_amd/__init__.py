@@ -96,6 +96,7 @@ def lib():
             "fscc_batch_context": ([vp], vp),
             "fscc_batch_denominators": ([vp, vp, vp], ip),
             "fscc_batch_restart": ([vp, vp], ip),
+            "fscc_batch_precondition": ([vp, ip, ctypes.c_double], ip),
             "fscc_batch_maxnorm": ([vp, vp, vp, dp], ip),
             "fscc_mlp_num_params": ([ctypes.POINTER(sz)], ip),
             "fscc_mlp_create": ([ctypes.c_uint64, vp, ctypes.POINTER(vp)], ip),
@@ -482,24 +483,30 @@ def solve01_extrapolated(ctx, s1, s2, S, n=3, scales=(1.0, 0.8, 0.6, 0.4), L=1, 
     return dict(scales=list(scales), eig=eigs, iters=iters, converged=conv, extrapolated=ext)
 
 
-def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True):
+def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True, dressed=0, floor=0.1):
     """Jacobi + DIIS iterations on the device until max|step| < tol.
 
     Each iteration: fscc_build_residual -> fscc_update_amplitudes ->
     fscc_energy.  Returns dict(E, iters, converged, history); history entries
     carry the host time after the iteration's energy (which synchronises).
-    reset_diis=False continues with the context's current DIIS subspace."""
+    reset_diis=False continues with the context's current DIIS subspace (and
+    denominators).  dressed=m > 0: dressed Jacobi denominators
+    (fscc_precondition, mode 1) from iteration 3 on, taken from the residual of
+    the iteration before and refreshed every m iterations; 0: the bare ones."""
     import time
     import torch
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
     if reset_diis:
+        ctx.precondition(0, floor, FSCC_S00)
         ctx.diis_reset(ndiis)
     hist = []
     E = 0j
     converged = False
     k = 0
     for k in range(1, maxit + 1):
+        if dressed and k >= 3 and (k - 3) % dressed == 0:
+            ctx.precondition(1, floor, FSCC_S00)     # from the residual of iteration k - 1
         ctx.build_residual(t1, t2, r1, r2)
         dmax = ctx.update_amplitudes(t1, t2, r1, r2)
         E = ctx.energy(t1, t2)
@@ -664,6 +671,10 @@ class Batch:
     def context(self):
         return _ContextView(ctypes.c_void_p(lib().fscc_batch_context(self._h)))
 
+    def precondition(self, mode=1, floor=0.1):
+        """Jacobi denominators of every system: 0 bare, 1 dressed (after a step)."""
+        self._check(lib().fscc_batch_precondition(self._h, int(mode), float(floor)))
+
     def restart(self, mask):
         """Fresh DIIS subspace for the systems where mask is true."""
         import numpy as np
@@ -704,8 +715,11 @@ class Batch:
 
 
 def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None, shift=0.0, reset=True,
-                first=None):
+                first=None, dressed=0, floor=0.1):
     """Iterate every system of a batch until each one's max|step| < tol.
+    dressed=m > 0: dressed Jacobi denominators (fscc_batch_precondition) from
+    iteration 3 on, taken from the residual of the iteration before and
+    refreshed every m iterations (the rule of solve()).
     Returns dict(E [complex per system], iters, converged, failed, history
     (list of reports), times (host time after each iteration))."""
     import time
@@ -714,6 +728,7 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
     if reset:
+        batch.precondition(0, floor)
         batch.reset(ndiis, tol, shift)
     hist, times = [], []
     rep = None
@@ -724,6 +739,8 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
     for k in range(len(hist) + 1, maxit + 1):
         if rep is not None and not rep[:, 3].any():
             break
+        if dressed and k >= 3 and (k - 3) % dressed == 0:
+            batch.precondition(1, floor)             # from the residual of iteration k - 1
         rep = batch.step(t1, t2, r1, r2, use_graph)
         hist.append(rep)
         times.append(time.perf_counter())

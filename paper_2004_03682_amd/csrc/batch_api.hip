@@ -165,6 +165,12 @@ struct fscc_batch {
     double *Bm = nullptr, *coef = nullptr, *maxstep = nullptr, *part = nullptr, *part_max = nullptr, *epart = nullptr,
            *report = nullptr;
     double* hreport = nullptr;   // pinned host copy of the report rows
+    double *pre1 = nullptr, *pre2 = nullptr;   // dressed Jacobi denominators (fscc_batch_precondition)
+    bool dressed = false;
+    bool iterated = false;   // a residual has been evaluated (the F' intermediates are current)
+
+    const double* jD1() { return dressed ? pre1 : (const double*)c.dbuf[c.plan.b_D1]; }
+    const double* jD2() { return dressed ? pre2 : (const double*)c.dbuf[c.plan.b_D2]; }
     hipStream_t gst = nullptr;   // stream used for graph capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -183,7 +189,7 @@ struct fscc_batch {
         else (void)hipDeviceSynchronize();
         drop_graph();
         if (gst) (void)hipStreamDestroy(gst);
-        void* ps[] = {dseg, dstate, dactive, dupd, ht, he, Bm, coef, maxstep, part, part_max, epart, report};
+        void* ps[] = {dseg, dstate, dactive, dupd, ht, he, Bm, coef, maxstep, part, part_max, epart, report, pre1, pre2};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hreport) (void)hipHostFree(hreport);
@@ -212,8 +218,8 @@ void enqueue_iteration(fscc_batch* b, hipStream_t st, const fscc_c128* t1, const
         bind_io(&c, t1, t2, r1, r2);
         c.run_list(c.L00, false);
         hip_check(launch_batch_update((const double2*)t1, (const double2*)t2, (const double2*)r1, (const double2*)r2,
-                                      (double2*)t1, (double2*)t2, (const double*)c.dbuf[P.b_D1],
-                                      (const double*)c.dbuf[P.b_D2], b->dseg, b->dstate, b->ht, b->he, b->part_max,
+                                      (double2*)t1, (double2*)t2, b->jD1(), b->jD2(), b->dseg, b->dstate, b->ht,
+                                      b->he, b->part_max,
                                       b->part, b->Bm, b->coef, b->maxstep, b->tol, b->shift, b->dactive, b->dupd, b->nsys, b->nblk, st),
                   "batch update");
         // tau of the updated amplitudes (the systems updated in this iteration)
@@ -458,6 +464,7 @@ fscc_status fscc_batch_build_residual(fscc_batch* b, const fscc_c128* t1, const 
     return guarded(&b->c, [&]() -> fscc_status {
         bind_io(&b->c, t1, t2, r1, r2);
         b->c.run_list(b->c.L00, b->c.prof);
+        b->iterated = true;
         return FSCC_OK;
     });
 }
@@ -477,8 +484,7 @@ fscc_status fscc_batch_step(fscc_batch* b, fscc_c128* t1, fscc_c128* t2, fscc_c1
                 bind_io(&c, t1, t2, r1, r2);
                 c.run_list(c.L00, true);
                 hip_check(launch_batch_update((const double2*)t1, (const double2*)t2, (const double2*)r1,
-                                              (const double2*)r2, (double2*)t1, (double2*)t2,
-                                              (const double*)c.dbuf[c.plan.b_D1], (const double*)c.dbuf[c.plan.b_D2],
+                                              (const double2*)r2, (double2*)t1, (double2*)t2, b->jD1(), b->jD2(),
                                               b->dseg, b->dstate, b->ht, b->he, b->part_max, b->part, b->Bm, b->coef,
                                               b->maxstep, b->tol, b->shift, b->dactive, b->dupd, b->nsys, b->nblk, c.st),
                           "batch update");
@@ -513,6 +519,7 @@ fscc_status fscc_batch_step(fscc_batch* b, fscc_c128* t1, fscc_c128* t2, fscc_c1
             hip_check(hipGraphLaunch(b->gexec, c.st), "graph launch");
         }
         hip_check(hipStreamSynchronize(c.st), "step sync");
+        b->iterated = true;
         std::memcpy(report, b->hreport, sizeof(double) * 6 * b->nsys);
         return FSCC_OK;
     });
@@ -568,6 +575,64 @@ fscc_status fscc_batch_restart(fscc_batch* b, const int* mask) {
         }
         hip_check(hipMemcpy(b->dstate, h.data(), sizeof(BState) * b->nsys, hipMemcpyHostToDevice), "state h2d");
         hip_check(hipMemcpy(b->dactive, a.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice), "active h2d");
+        return FSCC_OK;
+    });
+}
+
+// Dressed Jacobi denominators per system (the single-system rule of
+// fscc_precondition, sector (0h,0p)): f_p = e_p + Re F'_pp from each system's
+// F'_be, F'_mj segments of the last residual, written at the system's T1/T2
+// segment offsets; the DIIS subspaces restart (iteration counts and the
+// active flags are kept).
+fscc_status fscc_batch_precondition(fscc_batch* b, int mode, double floor) {
+    if (!b) return FSCC_EINVAL;
+    if (mode < 0 || mode > 1 || !(floor > 0.0)) return bfail(b, FSCC_EINVAL, "bad preconditioner mode or floor");
+    if (mode == 1 && !b->iterated)
+        return bfail(b, FSCC_ESTATE, "evaluate a residual (or step) before the dressed preconditioner");
+    return guarded(&b->c, [&]() -> fscc_status {
+        fscc_ctx& c = b->c;
+        Plan& M = c.plan;
+        hip_check(hipStreamSynchronize(c.st), "precondition sync");
+        if (mode == 0) {
+            if (b->dressed) b->drop_graph();
+            b->dressed = false;
+        } else {
+            const int bf = b->sub[0]->b_Fbe, bm = b->sub[0]->b_Fmj;
+            std::vector<double2> fbe((size_t)M.bufs[bf].n), fmj((size_t)M.bufs[bm].n);
+            hip_check(hipMemcpy(fbe.data(), c.dbuf[bf], fbe.size() * sizeof(double2), hipMemcpyDeviceToHost), "F'be d2h");
+            hip_check(hipMemcpy(fmj.data(), c.dbuf[bm], fmj.size() * sizeof(double2), hipMemcpyDeviceToHost), "F'mj d2h");
+            std::vector<double> d1((size_t)c.n1()), d2((size_t)c.n2());
+            parallel_for((size_t)b->nsys, [&](size_t s) {
+                const Plan& P = *b->sub[s];
+                std::vector<double> fo(P.eps_o), fv(P.eps_v);
+                for (size_t i = 0; i < fo.size(); ++i)
+                    if (P.fmj_diag[i] >= 0) fo[i] += fmj[(size_t)(b->base[s][bm] + P.fmj_diag[i])].x;
+                for (size_t a = 0; a < fv.size(); ++a)
+                    if (P.fbe_diag[a] >= 0) fv[a] += fbe[(size_t)(b->base[s][bf] + P.fbe_diag[a])].x;
+                const int64_t o1 = b->seg[s].off1, o2 = b->seg[s].off2;
+                P.L_T1.for_each([&](int64_t k, const int* x) { d1[o1 + k] = std::min(fo[x[0]] - fv[x[1]], -floor); });
+                P.L_T2.for_each([&](int64_t k, const int* x) {
+                    d2[o2 + k] = std::min(fo[x[0]] + fo[x[1]] - fv[x[2]] - fv[x[3]], -floor);
+                });
+            });
+            if (!b->pre1) {
+                b->pre1 = (double*)c.dalloc(std::max<size_t>(d1.size(), 1) * sizeof(double));
+                b->pre2 = (double*)c.dalloc(std::max<size_t>(d2.size(), 1) * sizeof(double));
+            }
+            if (!d1.empty())
+                hip_check(hipMemcpy(b->pre1, d1.data(), d1.size() * sizeof(double), hipMemcpyHostToDevice), "D1 dressed");
+            if (!d2.empty())
+                hip_check(hipMemcpy(b->pre2, d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice), "D2 dressed");
+            if (!b->dressed) b->drop_graph();   // the captured update reads the bare denominators
+            b->dressed = true;
+        }
+        std::vector<BState> h(b->nsys);
+        hip_check(hipMemcpy(h.data(), b->dstate, sizeof(BState) * b->nsys, hipMemcpyDeviceToHost), "state d2h");
+        for (auto& x : h) {
+            x.count = 0;
+            x.newest = x.nd - 1;
+        }
+        hip_check(hipMemcpy(b->dstate, h.data(), sizeof(BState) * b->nsys, hipMemcpyHostToDevice), "state h2d");
         return FSCC_OK;
     });
 }

@@ -847,6 +847,7 @@ fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c1
         if (sector == FSCC_S00) {
             bind_io(ctx, t1, t2, r1, r2);
             ctx->run_list(ctx->L00, ctx->prof);
+            ctx->resid00 = true;
         } else if (sector == FSCC_S01) {
             bind_io01(ctx, t1, t2, r1, r2);
             ctx->run_list(ctx->L01, ctx->prof);
@@ -974,10 +975,63 @@ fscc_status fscc_heff2(fscc_ctx* ctx, const fscc_c128* s, fscc_c128* heff_host) 
     });
 }
 
+// Dressed (0h,0p) Jacobi denominators: the part of the T2 residual that is
+// diagonal in the amplitude is -(f_i + f_j - f_a - f_b) t_ij^ab with
+// f_p = eps_p + F'_pp (F'_be, F'_mj of the last residual evaluation: the
+// one-body intermediates that multiply t2), and likewise f_i - f_a for T1;
+// dividing the residual by these instead of the bare orbital-energy
+// differences leaves the solution (R = 0) unchanged.  Capped at -floor.
+static fscc_status precondition00(fscc_ctx* ctx, int mode, double floor) {
+    Plan& P = ctx->plan;
+    Diis& D = ctx->diis[FSCC_S00];
+    if (mode == 0) {
+        D.b_D1 = P.b_D1;
+        D.b_D2 = P.b_D2;
+    } else {
+        std::vector<double2> fbe = read_elements(ctx, P.b_Fbe, P.bufs[P.b_Fbe].n);
+        std::vector<double2> fmj = read_elements(ctx, P.b_Fmj, P.bufs[P.b_Fmj].n);
+        std::vector<double> fo(P.eps_o), fv(P.eps_v);
+        for (size_t i = 0; i < fo.size(); ++i)
+            if (P.fmj_diag[i] >= 0) fo[i] += fmj[(size_t)P.fmj_diag[i]].x;
+        for (size_t a = 0; a < fv.size(); ++a)
+            if (P.fbe_diag[a] >= 0) fv[a] += fbe[(size_t)P.fbe_diag[a]].x;
+        std::vector<double> d1((size_t)P.L_T1.total), d2((size_t)P.L_T2.total);
+        P.L_T1.for_each([&](int64_t k, const int* x) { d1[k] = std::min(fo[x[0]] - fv[x[1]], -floor); });
+        P.L_T2.for_each([&](int64_t k, const int* x) {
+            d2[k] = std::min(fo[x[0]] + fo[x[1]] - fv[x[2]] - fv[x[3]], -floor);
+        });
+        if (ctx->b_pre1 < 0) {
+            ctx->b_pre1 = (int)P.bufs.size();
+            P.bufs.push_back(BufDesc{"D1 dressed", P.L_T1.total, BUF_REAL});
+            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>(d1.size(), 1) * sizeof(double)));
+            ctx->b_pre2 = (int)P.bufs.size();
+            P.bufs.push_back(BufDesc{"D2 dressed", P.L_T2.total, BUF_REAL});
+            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>(d2.size(), 1) * sizeof(double)));
+        }
+        if (!d1.empty())
+            hip_check(hipMemcpy(ctx->dbuf[ctx->b_pre1], d1.data(), d1.size() * sizeof(double), hipMemcpyHostToDevice),
+                      "D1 dressed");
+        if (!d2.empty())
+            hip_check(hipMemcpy(ctx->dbuf[ctx->b_pre2], d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice),
+                      "D2 dressed");
+        D.b_D1 = ctx->b_pre1;
+        D.b_D2 = ctx->b_pre2;
+    }
+    D.order.clear();
+    D.watch.restart();
+    return FSCC_OK;
+}
+
 fscc_status fscc_precondition(fscc_ctx* ctx, fscc_sector sector, int mode, double floor) {
     if (!ctx) return FSCC_EINVAL;
     Plan& P = ctx->plan;
-    if (sector != FSCC_S01 || !P.has01) return fail(ctx, FSCC_EINVAL, "only the (0h,1p) sector has preconditioner modes");
+    if (sector == FSCC_S00) {
+        if (mode < 0 || mode > 1 || !(floor > 0.0)) return fail(ctx, FSCC_EINVAL, "bad preconditioner mode or floor");
+        if (mode == 1 && !ctx->resid00)
+            return fail(ctx, FSCC_ESTATE, "evaluate a (0h,0p) residual before the dressed preconditioner");
+        return guarded(ctx, [&]() -> fscc_status { return precondition00(ctx, mode, floor); });
+    }
+    if (sector != FSCC_S01 || !P.has01) return fail(ctx, FSCC_EINVAL, "no preconditioner modes for this sector");
     if (mode < 0 || mode > 1 || !(floor > 0.0)) return fail(ctx, FSCC_EINVAL, "bad preconditioner mode or floor");
     if (mode == 1 && !ctx->ready01) return fail(ctx, FSCC_ESTATE, "(0h,1p) sector not prepared (fscc_prepare_sector)");
     return guarded(ctx, [&]() -> fscc_status {

@@ -126,6 +126,11 @@ struct Plan {
     std::vector<double> D1x, D2x, mask1;
     int b_Fvv01 = -1, b_Foo01 = -1;   // Fbar_vv, Fbar_oo ([g][n_g][n_g] blocks)
     std::vector<int64_t> fvv_diag, foo_diag;   // offset of the diagonal element per V / O position
+    // (0h,0p) dressed preconditioner: F'_be / F'_mj of the last residual and
+    // the offsets of their diagonal elements; orbital energies by position
+    int b_Fbe = -1, b_Fmj = -1;
+    std::vector<int64_t> fbe_diag, fmj_diag;
+    std::vector<double> eps_o, eps_v;
     std::vector<Op> ops01_prep;       // Hbar elements from the converged (0h,0p) amplitudes
     std::vector<Op> ops01;            // sigma + Bloch residual
 

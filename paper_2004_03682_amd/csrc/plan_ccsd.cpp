@@ -385,6 +385,10 @@ void build_plan_ccsd(const System& S, Plan& P) {
         });
         P.b_D1 = P.buf("D1", L_T1.total, BUF_REAL);
         P.b_D2 = P.buf("D2", L_T2.total, BUF_REAL);
+        P.eps_o.assign(o->n, 0.0);
+        P.eps_v.assign(v->n, 0.0);
+        for (int i = 0; i < o->n; ++i) P.eps_o[i] = S.eps[o->glob[i]];
+        for (int a = 0; a < v->n; ++a) P.eps_v[a] = S.eps[v->glob[a]];
     }
 
     // ------------------------------------------------------- stored integrals
@@ -569,6 +573,12 @@ void build_plan_ccsd(const System& S, Plan& P) {
     int b_Fmj = P.buf("Fmj", L_Fmj.total, BUF_SCRATCH);
     B.axpby("Fmj=Fmi", b_Fmj, b_Fmi, L_Fmj.total, 1.0, 0, false);
     B.gemm("Fmj.t1", b_Fme, L_Fme_m, false, false, P.b_t1, L_T1, true, false, b_Fmj, L_Fmj, 0.5, 1);
+    P.b_Fbe = b_Fbe;
+    P.b_Fmj = b_Fmj;
+    P.fbe_diag.assign(v->n, -1);
+    P.fmj_diag.assign(o->n, -1);
+    L_Fbe.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) P.fbe_diag[p[0]] = k; });
+    L_Fmj.for_each([&](int64_t k, const int* p) { if (p[0] == p[1]) P.fmj_diag[p[0]] = k; });
     Layout L_T10b = make_layout("T10b", G, {s(2, v, 1), s(3, v, 1), s(0, o, -1)}, 0, {s(1, o, 1)}, -1, 1);
     int b_T10b = P.buf("T10b", L_T10b.total, BUF_SCRATCH);
     B.gather("t2->10b", b_T10b, L_T10b, P.b_t2, L_T2, {T{{0, 1, 2, 3}, 1, {}}}, 1.0, 0);

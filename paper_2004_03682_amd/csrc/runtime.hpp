@@ -142,6 +142,8 @@ struct fscc_ctx {
     bool have_cls[IC_N] = {false, false, false, false, false, false};
     bool ready01 = false;
     bool ready02 = false;
+    bool resid00 = false;   // a (0h,0p) residual has been evaluated (its F'_be, F'_mj are current)
+    int b_pre1 = -1, b_pre2 = -1;   // dressed (0h,0p) denominators (fscc_precondition)
     Diis diis[3];
     double* part = nullptr;
     double* part_max = nullptr;

@@ -4,6 +4,9 @@
   python tests/golden/make_golden.py o40v300z16 [--save-amplitudes PATH.npz]
                                                      # o40v300z16_ccsd.json (about an hour on 8 cores);
                                                      # optionally also every converged block of t1, t2
+  python tests/golden/make_golden.py fs01-plain PATH.npz
+                                                     # o40v300z16_fs01_plain.json from the saved
+                                                     # converged amplitudes (a few minutes)
 
 o20v120z8_ccsd.json: converged (0h,0p) CCSD correlation energy of the 20-occupied /
 120-virtual / Z8 synthetic system (seed 1001) from the block-list oracle, with
@@ -17,6 +20,13 @@ trajectory (iteration count to 1e-10 included), every T1 element, and a seeded s
 unique T2 elements (i<j, a<b, allowed by the Z16 selection rule) plus the 64 largest
 |t2|, each as (i, j, a, b, re, im) with spinor positions counted inside the occupied and
 virtual spaces.
+
+o40v300z16_fs01_plain.json: the (0h,1p) sector of the same system (the six lowest
+virtual spinors active) iterated from zero on the oracle's converged T: Jacobi steps
+with the Hbar-diagonal denominators (floor 0.1 Eh), DIIS(6), 40 iterations; stored:
+max|step| of every iteration.  At this size the plain iteration diverges (an intruder
+state: Section 2.1); the trajectory pins the divergence to the method rather than to
+any one implementation of it.
 """
 import json
 import os
@@ -136,7 +146,32 @@ def production(save=None):
         np.savez(save, **arrays)
 
 
+def fs01_plain(npz, n=40):
+    from oracle import fs01
+    from oracle.blocks import BlockTensor
+    name = "o40v300z16"
+    s = fsgen.workload_system(name)
+    z = np.load(npz)
+    key = lambda k: tuple(int(x) for x in k.split("_")[1:])  # noqa: E731
+    t1 = BlockTensor(2, {key(k): z[k] for k in z.files if k.startswith("t1_")})
+    t2 = BlockTensor(4, {key(k): z[k] for k in z.files if k.startswith("t2_")})
+    t0 = time.time()
+    be = ccsd.Blocked(s)
+    fs = fs01.FS01Blocked(be, t1, t2, s.active, precond="dressed", floor=0.1)
+    r = fs01.solve_fs01_blocked(fs, tol=1e-10, maxit=n, ndiis=6, log=lambda m: print(m, flush=True))
+    out = dict(config=dict(fsgen.WORKLOADS[name]), precond="dressed", floor=0.1, ndiis=6,
+               max_step=[float(x) for x in r["history"]],
+               oracle="oracle.fs01.solve_fs01_blocked(FS01Blocked(precond='dressed', floor=0.1), ndiis=6)",
+               seconds=round(time.time() - t0, 1))
+    with open(os.path.join(HERE, name + "_fs01_plain.json"), "w") as f:
+        json.dump(out, f, indent=0)
+    print({k: v for k, v in out.items() if k != "max_step"})
+
+
 if __name__ == "__main__":
+    if len(sys.argv) > 2 and sys.argv[1] == "fs01-plain":
+        fs01_plain(sys.argv[2])
+        sys.exit(0)
     if len(sys.argv) > 1 and sys.argv[1] == "o40v300z16":
         production(sys.argv[3] if len(sys.argv) > 3 and sys.argv[2] == "--save-amplitudes" else None)
     else:

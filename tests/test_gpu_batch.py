@@ -87,15 +87,19 @@ def test_batch_layout_and_residual_match_single_systems():
     b.destroy()
 
 
-@pytest.mark.parametrize("use_graph,shift,ndiis", [(False, 0.0, 6), (True, 0.0, 6), (True, 0.7, 8)])
-def test_batch_converges_like_single_systems(use_graph, shift, ndiis):
+@pytest.mark.parametrize("use_graph,shift,ndiis,dressed", [(False, 0.0, 6, 0), (True, 0.0, 6, 0), (True, 0.7, 8, 0),
+                                                           (True, 0.0, 8, 10), (False, 0.0, 6, 4)])
+def test_batch_converges_like_single_systems(use_graph, shift, ndiis, dressed):
+    """Also with dressed Jacobi denominators (fscc_batch_precondition against
+    fscc_precondition per system): the same iterations and fixed point."""
     torch = _torch()
     import paper_2004_03682_amd as F
     systems = [fsgen.make_system(*p) for p in SPECS[:4]] + [fsgen.make_system(7, 30, 4, 0.05, 8)]
     b = make_batch(systems)
     t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
-    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=use_graph, shift=shift, ndiis=ndiis)
+    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=use_graph, shift=shift, ndiis=ndiis,
+                        dressed=dressed)
     assert res["converged"].all(), res["iters"]
     T1, T2 = t1.cpu().numpy(), t2.cpu().numpy()
     for k, s in enumerate(systems):
@@ -103,7 +107,7 @@ def test_batch_converges_like_single_systems(use_graph, shift, ndiis):
         u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
         u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
         ctx.level_shift(shift)
-        g = F.solve(ctx, u1, u2, tol=1e-10, maxit=150, ndiis=ndiis)
+        g = F.solve(ctx, u1, u2, tol=1e-10, maxit=150, ndiis=ndiis, dressed=dressed)
         print("system", k, "batch", res["E"][k], res["iters"][k], "single", g["E"], g["iters"], flush=True)
         assert g["converged"]
         assert abs(res["E"][k] - g["E"]) <= 1e-10

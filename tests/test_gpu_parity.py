@@ -161,14 +161,18 @@ def test_ladder_mp3_closed_form():
     ctx.destroy()
 
 
-def test_converged_o8v24_matches_oracle():
+@pytest.mark.parametrize("dressed", [0, 1, 10])
+def test_converged_o8v24_matches_oracle(dressed):
+    """Bare and dressed Jacobi denominators (fscc_precondition, (0h,0p)) reach
+    the oracle's fixed point."""
     torch = _torch()
     import paper_2004_03682_amd as F
     s = fsgen.workload_system("o8v24")
     ctx = gpu_ctx(s)
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
-    g = F.solve(ctx, t1, t2, tol=1e-10)
+    g = F.solve(ctx, t1, t2, tol=1e-10, dressed=dressed)
+    print("o8v24 dressed", dressed, "iterations", g["iters"], flush=True)
     o = solver.solve_ccsd(ccsd.Dense(s), tol=1e-10)
     assert g["converged"] and o["converged"]
     assert abs(g["E"].real - o["E"].real) <= 1e-10 and abs(g["E"].imag - o["E"].imag) <= 1e-10
@@ -177,7 +181,8 @@ def test_converged_o8v24_matches_oracle():
     ctx.destroy()
 
 
-def test_converged_o20v120z8_matches_golden():
+@pytest.mark.parametrize("dressed", [0, 10])
+def test_converged_o20v120z8_matches_golden(dressed):
     torch = _torch()
     import paper_2004_03682_amd as F
     gold = json.load(open(os.path.join(HERE, "golden", "o20v120z8_ccsd.json")))
@@ -185,7 +190,7 @@ def test_converged_o20v120z8_matches_golden():
     ctx = gpu_ctx(s)
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
-    g = F.solve(ctx, t1, t2, tol=1e-10)
+    g = F.solve(ctx, t1, t2, tol=1e-10, dressed=dressed)
     print("o20v120z8 gpu", g["E"], g["iters"], "oracle", gold["E_re"], gold["E_im"], gold["iters"], flush=True)
     assert g["converged"]
     assert abs(g["E"].real - gold["E_re"]) <= 1e-10
@@ -206,6 +211,14 @@ def test_errors_are_reported():
     with pytest.raises(F.FsccError) as e:
         ctx.set_integrals("OOVV", torch.zeros(3, dtype=torch.complex128, device="cuda"))
     assert e.value.status == -1
+    # dressed (0h,0p) denominators need a residual first; bad mode / floor
+    with pytest.raises(F.FsccError) as e:
+        ctx.precondition(1, 0.1, F.FSCC_S00)
+    assert e.value.status == -5
+    for mode, floor in ((2, 0.1), (1, 0.0), (0, -1.0)):
+        with pytest.raises(F.FsccError) as e:
+            ctx.precondition(mode, floor, F.FSCC_S00)
+        assert e.value.status == -1
     ctx.destroy()
 
 
