@@ -715,11 +715,13 @@ class Batch:
 
 
 def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, log=None, shift=0.0, reset=True,
-                first=None, dressed=0, floor=0.1):
+                first=None, dressed=0, floor=0.1, stop_active=0):
     """Iterate every system of a batch until each one's max|step| < tol.
     dressed=m > 0: dressed Jacobi denominators (fscc_batch_precondition) from
     iteration 3 on, taken from the residual of the iteration before and
-    refreshed every m iterations (the rule of solve()).
+    refreshed every m iterations (the rule of solve()).  stop_active=n > 0:
+    return as soon as at most n systems are still iterating (their converged
+    flag is then False; see finish_batch_in_contexts).
     Returns dict(E [complex per system], iters, converged, failed, history
     (list of reports), times (host time after each iteration))."""
     import time
@@ -746,11 +748,43 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
         times.append(time.perf_counter())
         if log:
             log(f"batch iter {k:3d}: active {int(rep[:, 3].sum())}/{batch.nsys}, max|step| {rep[:, 2].max():.3e}")
-        if not rep[:, 3].any():
+        if not rep[:, 3].any() or (stop_active and rep[:, 3].sum() <= stop_active):
             break
     E = rep[:, 0] + 1j * rep[:, 1]
     return dict(E=E, iters=rep[:, 4].astype(int), converged=(rep[:, 3] == 0) & (rep[:, 5] == 0),
                 failed=rep[:, 5] != 0, history=hist, times=times)
+
+
+def finish_batch_in_contexts(batch, res, t1, t2, make_ctx, tol=1e-10, maxit=200, ndiis=6, dressed=0, floor=0.1):
+    """Systems still iterating when solve_batch stopped (stop_active) continue
+    alone, each in its own context (make_ctx(s) -> Context with integrals
+    set), from the amplitudes their batch segments hold, with a fresh DIIS
+    subspace, until max|step| < tol or maxit iterations in all; the converged
+    amplitudes are copied back into the segments and res (E, iters,
+    converged) is updated in place.  A batch's launches are tuned for all of
+    its systems; a lone straggler runs faster with its own tiles.  Returns the
+    per-system results of the continued systems."""
+    import numpy as np
+    import torch
+    rep = res["history"][-1]
+    out = {}
+    for s in np.nonzero(rep[:, 3] != 0)[0]:
+        s = int(s)
+        off1, n1, off2, n2 = batch.segments[s]
+        ctx = make_ctx(s)
+        u1 = t1[off1:off1 + n1].clone()
+        u2 = t2[off2:off2 + n2].clone()
+        done = int(rep[s, 4])
+        g = solve(ctx, u1, u2, tol=tol, maxit=max(1, maxit - done), ndiis=ndiis, dressed=dressed, floor=floor)
+        t1[off1:off1 + n1].copy_(u1)
+        t2[off2:off2 + n2].copy_(u2)
+        res["E"][s] = g["E"]
+        res["iters"][s] = done + g["iters"]
+        res["converged"][s] = g["converged"]
+        out[s] = g
+        ctx.destroy()
+    torch.cuda.synchronize()
+    return out
 
 
 # ---------------------------------------------------------------- learned warm start

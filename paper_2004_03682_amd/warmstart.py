@@ -33,7 +33,9 @@ from . import (MLP, Batch, FsccError, mlp_num_params, solve_batch, ws_apply, ws_
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "warmstart_mlp.npz")
-SOLVER = dict(ndiis=8, shift=1.0)      # DIIS(8) + 1 Eh level shift (same fixed point)
+# the solver the network was trained and is evaluated under: DIIS(8) with a
+# 1 Eh level shift on the bare denominators (same fixed point)
+SOLVER = dict(ndiis=8, shift=1.0)
 TRAIN_SEED0, EVAL_SEED0 = 50000, 40000
 
 
@@ -177,7 +179,15 @@ def solve_from(b, t1, t2, tol=1e-10, maxit=300):
     torch.cuda.synchronize()
     ts = time.perf_counter()
     res = solve_batch(b, t1, t2, tol=tol, maxit=maxit, use_graph=True, **SOLVER)
+    res["start_time"] = ts
     return res, time.perf_counter() - ts
+
+
+def seconds_to(res, thr=1e-8):
+    """Per system: seconds from the solve's start (res["start_time"]) to the
+    iteration after which |E_k - E_final| < thr holds."""
+    k = iterations_to(res, thr)
+    return np.array([res["times"][max(0, min(len(res["times"]), int(i)) - 1)] - res["start_time"] for i in k])
 
 
 def iterations_to(res, thr=1e-8):
@@ -207,11 +217,16 @@ def evaluate(net, b, tol=1e-10, maxit=300, log=None, mp2=None):
     torch.cuda.synchronize()
     ts = time.perf_counter()
     lrn, info = solve_learned(b, net, D1, D2, tol, maxit)
+    lrn["start_time"] = ts
     t_lrn = time.perf_counter() - ts
     both = mp2["converged"] & lrn["converged"]
     extra = info["start_evaluations"]
     it_mp2, it_lrn = mp2["iters"][both], lrn["iters"][both] + extra
     e8_mp2, e8_lrn = iterations_to(mp2)[both], iterations_to(lrn)[both] + extra
+    # wall time to 1e-8 per system, from each solve's start (the learned side
+    # includes its start-up residuals and the network's inference)
+    s8_mp2 = seconds_to(mp2)[both] if "start_time" in mp2 else None
+    s8_lrn = seconds_to(lrn)[both]
     ok = bool(both.any())
     dE = float(np.abs(mp2["E"][both] - lrn["E"][both]).max()) if ok else None
     out = {"systems": b.nsys, "both_converged": int(both.sum()), "mp2_converged": int(mp2["converged"].sum()),
@@ -223,11 +238,16 @@ def evaluate(net, b, tol=1e-10, maxit=300, log=None, mp2=None):
            "systems_faster_to_1e-8": int((e8_lrn < e8_mp2).sum()), "systems_slower_to_1e-8": int((e8_lrn > e8_mp2).sum()),
            "fallback_systems": int(info["fallback"].sum()),
            "seconds_mp2": round(t_mp2, 4), "seconds_learned": round(t_lrn, 4),
+           "seconds_to_1e-8_mp2_mean": float(s8_mp2.mean()) if ok and s8_mp2 is not None else None,
+           "seconds_to_1e-8_learned_mean": float(s8_lrn.mean()) if ok else None,
+           "seconds_to_1e-8_mp2": [round(float(x), 4) for x in s8_mp2] if ok and s8_mp2 is not None else None,
+           "seconds_to_1e-8_learned": [round(float(x), 4) for x in s8_lrn] if ok else None,
            "max_abs_dE_mp2_vs_learned": dE, "start_residual_evaluations": extra}
     if log:
         log(f"warm start: iterations to 1e-8 Eh {out['iterations_to_1e-8_mp2_mean']} (MP2) -> "
             f"{out['iterations_to_1e-8_learned_mean']} (learned, incl. {extra} start evaluations); to convergence "
             f"{out['iterations_mp2_mean']} -> {out['iterations_learned_mean']}; time {t_mp2:.2f}s -> {t_lrn:.2f}s; "
+            f"mean seconds to 1e-8 {out['seconds_to_1e-8_mp2_mean']} -> {out['seconds_to_1e-8_learned_mean']}; "
             f"fallback {out['fallback_systems']}; max |dE| {dE}")
     return out
 
