@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CCSD s/iteration + MFMA TFLOP/s, FP64 vs mixed at dE<1e-8 Eh"
+DRESSED = 25       # refresh period of the dressed Jacobi denominators (fscc_precondition)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0  # GB/s
 
@@ -142,14 +143,15 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
     ctx.set_precision("fp64")
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    a = F.solve(ctx, u1, u2, tol=1e-10, maxit=300)
+    a = F.solve(ctx, u1, u2, tol=1e-10, maxit=300, dressed=DRESSED)
     k8, s8 = time_to(a["history"], E_inf, ts)
     out["fp64"] = {"iterations": a["iters"], "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
                    "seconds_to_converged": round(a["history"][-1]["time"] - ts, 5)}
     log(f"fp64 from zero: {a['iters']} iterations, |dE|<1e-8 after {k8} ({s8}s)")
-    # reference residual at the MP2 amplitudes (first Jacobi step from zero)
+    # reference residual at the MP2 amplitudes (first Jacobi step from zero, bare denominators)
     u1.zero_()
     u2.zero_()
+    ctx.precondition(0, 0.1, F.FSCC_S00)
     ctx.diis_reset(1)
     ctx.build_residual(u1, u2, q1, q2)
     ctx.update_amplitudes(u1, u2, q1, q2)
@@ -161,7 +163,8 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
         ctx.set_precision(prec)
         t0 = time.perf_counter()
         ctx.autotune(2)
-        cfgs = {n: {0: "64x64", 1: "64x32", 2: "32x64", 3: "32x32"}[c] for n, c in ctx.mixed_configs()}
+        tiles = {0: "64x64", 1: "64x32", 2: "32x64", 3: "32x32"}
+        cfgs = {n: tiles[c % 4] + ("/Bdirect" if c >= 4 else "") for n, c in ctx.mixed_configs()}
         log(f"{prec}: split tiles {cfgs} (tuned in {time.perf_counter() - t0:.1f}s)")
         u1.copy_(mp2[0])
         u2.copy_(mp2[1])
@@ -208,7 +211,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
             u2.zero_()
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            b = F.solve_mixed(ctx, u1, u2, switch_tol=sw, tol=1e-10, maxit=300)
+            b = F.solve_mixed(ctx, u1, u2, switch_tol=sw, tol=1e-10, maxit=300, dressed=DRESSED)
             k8, s8 = time_to(b["history"], E_inf, ts)
             rec[f"two_stage_switch_{sw:g}"] = {
                 "split_iterations": b["split_iters"], "fp64_iterations": b["fp64_iters"],
@@ -222,7 +225,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
         u2.zero_()
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        c = F.solve(ctx, u1, u2, tol=1e-12, maxit=120)
+        c = F.solve(ctx, u1, u2, tol=1e-12, maxit=120, dressed=DRESSED)
         k8, s8 = time_to(c["history"], E_inf, ts)
         rec["split_only"] = {"iterations": c["iters"], "last_max_step": c["history"][-1]["dmax"],
                              "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
@@ -953,7 +956,14 @@ def main():
     ctx.diis_reset(6)
     E = 0j
 
+    # the solver: Jacobi + DIIS(6) with dressed denominators (refreshed from the
+    # previous residual at iteration 3 and every DRESSED iterations after it)
+    nit = [0]
+
     def step():
+        nit[0] += 1
+        if nit[0] >= 3 and (nit[0] - 3) % DRESSED == 0:
+            ctx.precondition(1, 0.1, F.FSCC_S00)
         ctx.build_residual(t1, t2, r1, r2)
         d = ctx.update_amplitudes(t1, t2, r1, r2)
         return d, ctx.energy(t1, t2)

@@ -495,13 +495,15 @@ fscc_status fscc_get_precision(const fscc_ctx *ctx, int *prec);
 
 /* Split-kernel tile shape of operation k in the current precision (host
  * output; -1 if k does not run in split precision now).  Shapes: 0: 64x64,
- * 1: 64x32, 2: 32x64, 3: 32x32.  fscc_autotune(ctx, 1) in a split mode also
- * measures these shapes. */
+ * 1: 64x32, 2: 32x64, 3: 32x32; 4..7: the same tiles with the B operand's
+ * fragments loaded from device memory straight into registers (only A staged
+ * in LDS).  fscc_autotune(ctx, 1) in a split mode also measures these
+ * shapes. */
 fscc_status fscc_mixed_config(const fscc_ctx *ctx, int k, int *cfg);
 
 /* One complex GEMM through the split-precision kernel (kernel-level tests):
  * same operand conventions as fscc_zgemm; prec = FSCC_SPLIT_BF16 or
- * FSCC_SPLIT_FP32; cfg = split tile shape (0..3).  Allocates and frees its
+ * FSCC_SPLIT_FP32; cfg = split tile shape (0..7).  Allocates and frees its
  * piece buffers; synchronises hip_stream. */
 fscc_status fscc_zgemm_split(int prec, int cfg, int tA, int tB, int cA, int cB, int M, int N, int K,
                              const fscc_c128 *A, int lda, const fscc_c128 *B, int ldb, fscc_c128 *C, int ldc,

@@ -519,16 +519,19 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True,
     return dict(E=E, iters=k, converged=converged, history=hist)
 
 
-def solve_mixed(ctx, t1, t2, switch_tol=1e-6, tol=1e-10, maxit=200, ndiis=6, log=None, keep_diis=True):
+def solve_mixed(ctx, t1, t2, switch_tol=1e-6, tol=1e-10, maxit=200, ndiis=6, log=None, keep_diis=True, dressed=0,
+                floor=0.1):
     """Two-stage solve: iterate with the context's split precision until
     max|step| < switch_tol, then continue in FP64 to tol (keeping the DIIS
-    subspace unless keep_diis=False).  The context's precision is restored on
-    return.  Returns dict(E, iters, split_iters, fp64_iters, converged, history)."""
+    subspace and denominators unless keep_diis=False).  dressed as in solve().
+    The context's precision is restored on return.  Returns dict(E, iters,
+    split_iters, fp64_iters, converged, history)."""
     prec = ctx.precision()
     try:
-        a = solve(ctx, t1, t2, tol=switch_tol, maxit=maxit, ndiis=ndiis, log=log)
+        a = solve(ctx, t1, t2, tol=switch_tol, maxit=maxit, ndiis=ndiis, log=log, dressed=dressed, floor=floor)
         ctx.set_precision("fp64")
-        b = solve(ctx, t1, t2, tol=tol, maxit=maxit, ndiis=ndiis, log=log, reset_diis=not keep_diis)
+        b = solve(ctx, t1, t2, tol=tol, maxit=maxit, ndiis=ndiis, log=log, reset_diis=not keep_diis, dressed=dressed,
+                  floor=floor)
     finally:
         ctx.set_precision(prec)
     return dict(E=b["E"], iters=a["iters"] + b["iters"], split_iters=a["iters"], fp64_iters=b["iters"],

@@ -990,30 +990,47 @@ static fscc_status precondition00(fscc_ctx* ctx, int mode, double floor) {
     } else {
         std::vector<double2> fbe = read_elements(ctx, P.b_Fbe, P.bufs[P.b_Fbe].n);
         std::vector<double2> fmj = read_elements(ctx, P.b_Fmj, P.bufs[P.b_Fmj].n);
-        std::vector<double> fo(P.eps_o), fv(P.eps_v);
-        for (size_t i = 0; i < fo.size(); ++i)
-            if (P.fmj_diag[i] >= 0) fo[i] += fmj[(size_t)P.fmj_diag[i]].x;
-        for (size_t a = 0; a < fv.size(); ++a)
-            if (P.fbe_diag[a] >= 0) fv[a] += fbe[(size_t)P.fbe_diag[a]].x;
-        std::vector<double> d1((size_t)P.L_T1.total), d2((size_t)P.L_T2.total);
-        P.L_T1.for_each([&](int64_t k, const int* x) { d1[k] = std::min(fo[x[0]] - fv[x[1]], -floor); });
-        P.L_T2.for_each([&](int64_t k, const int* x) {
-            d2[k] = std::min(fo[x[0]] + fo[x[1]] - fv[x[2]] - fv[x[3]], -floor);
-        });
+        const size_t no = P.eps_o.size(), nv = P.eps_v.size();
+        if (no > 65535 || nv > 65535) throw std::invalid_argument("dressed denominators support up to 65535 spinors per space");
+        std::vector<double> f(no + nv);
+        for (size_t i = 0; i < no; ++i)
+            f[i] = P.eps_o[i] + (P.fmj_diag[i] >= 0 ? fmj[(size_t)P.fmj_diag[i]].x : 0.0);
+        for (size_t a = 0; a < nv; ++a)
+            f[no + a] = P.eps_v[a] + (P.fbe_diag[a] >= 0 ? fbe[(size_t)P.fbe_diag[a]].x : 0.0);
+        const int64_t n1 = P.L_T1.total, n2 = P.L_T2.total;
         if (ctx->b_pre1 < 0) {
+            // first use: the orbital positions of every amplitude, kept on the device
+            std::vector<uint16_t> i1((size_t)n1 * 2), i2((size_t)n2 * 4);
+            P.L_T1.for_each([&](int64_t k, const int* x) {
+                i1[2 * k] = (uint16_t)x[0];
+                i1[2 * k + 1] = (uint16_t)x[1];
+            });
+            P.L_T2.for_each_par([&](int64_t k, const int* x) {
+                for (int q = 0; q < 4; ++q) i2[4 * k + q] = (uint16_t)x[q];
+            });
+            ctx->d_idx1 = (uint16_t*)ctx->dalloc(std::max<size_t>(i1.size(), 1) * sizeof(uint16_t));
+            ctx->d_idx2 = (uint16_t*)ctx->dalloc(std::max<size_t>(i2.size(), 1) * sizeof(uint16_t));
+            ctx->d_fov = (double*)ctx->dalloc(std::max<size_t>(f.size(), 1) * sizeof(double));
+            if (!i1.empty())
+                hip_check(hipMemcpy(ctx->d_idx1, i1.data(), i1.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "idx1");
+            if (!i2.empty())
+                hip_check(hipMemcpy(ctx->d_idx2, i2.data(), i2.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "idx2");
             ctx->b_pre1 = (int)P.bufs.size();
-            P.bufs.push_back(BufDesc{"D1 dressed", P.L_T1.total, BUF_REAL});
-            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>(d1.size(), 1) * sizeof(double)));
+            P.bufs.push_back(BufDesc{"D1 dressed", n1, BUF_REAL});
+            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>((size_t)n1, 1) * sizeof(double)));
             ctx->b_pre2 = (int)P.bufs.size();
-            P.bufs.push_back(BufDesc{"D2 dressed", P.L_T2.total, BUF_REAL});
-            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>(d2.size(), 1) * sizeof(double)));
+            P.bufs.push_back(BufDesc{"D2 dressed", n2, BUF_REAL});
+            ctx->dbuf.push_back(ctx->dalloc(std::max<size_t>((size_t)n2, 1) * sizeof(double)));
         }
-        if (!d1.empty())
-            hip_check(hipMemcpy(ctx->dbuf[ctx->b_pre1], d1.data(), d1.size() * sizeof(double), hipMemcpyHostToDevice),
-                      "D1 dressed");
-        if (!d2.empty())
-            hip_check(hipMemcpy(ctx->dbuf[ctx->b_pre2], d2.data(), d2.size() * sizeof(double), hipMemcpyHostToDevice),
-                      "D2 dressed");
+        if (!f.empty())
+            hip_check(hipMemcpyAsync(ctx->d_fov, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st),
+                      "f upload");
+        hip_check(launch_dressed_denoms(ctx->d_idx1, 2, ctx->d_fov, (int)no, floor, ctx->D(ctx->b_pre1), n1, ctx->st),
+                  "D1 dressed");
+        hip_check(launch_dressed_denoms(ctx->d_idx2, 4, ctx->d_fov, (int)no, floor, ctx->D(ctx->b_pre2), n2, ctx->st),
+                  "D2 dressed");
+        // the host vector f is read by the copy above before it goes out of scope
+        hip_check(hipStreamSynchronize(ctx->st), "dressed sync");
         D.b_D1 = ctx->b_pre1;
         D.b_D2 = ctx->b_pre2;
     }
@@ -1342,7 +1359,7 @@ namespace {
 // of the context's plans (kind, name, sizes, GEMM problem shapes); an entry
 // lists per operation the chosen form: GEMM [1, tile, bk, split, 3M, DB,
 // split-precision tile or -1], reorder [0, traversal], other [2].
-constexpr int kTuneVersion = 3;
+constexpr int kTuneVersion = 4;
 
 std::vector<OpList*> tune_lists(fscc_ctx* c) { return {&c->L00, &c->L01, &c->L02}; }
 

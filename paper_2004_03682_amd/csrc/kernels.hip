@@ -1611,6 +1611,32 @@ __global__ __launch_bounds__(256) void k_count_nonfinite(const double* __restric
     if (threadIdx.x == 0 && sh[0]) atomicAdd(count, (unsigned long long)sh[0]);
 }
 
+template <int ORDER>
+__global__ __launch_bounds__(256) void k_dressed_denoms(const uint16_t* __restrict__ idx, const double* __restrict__ f,
+                                                        int no, double floor, double* __restrict__ D, long long n) {
+    const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    double d;
+    if (ORDER == 2) {
+        const ushort2 x = *(const ushort2*)(idx + 2 * k);
+        d = f[x.x] - f[no + x.y];
+    } else {
+        const ushort4 x = *(const ushort4*)(idx + 4 * k);
+        d = f[x.x] + f[x.y] - f[no + x.z] - f[no + x.w];
+    }
+    D[k] = fmin(d, -floor);
+}
+
+hipError_t launch_dressed_denoms(const uint16_t* idx, int order, const double* f, int no, double floor, double* D,
+                                 long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    if (order == 2) k_dressed_denoms<2><<<grid, kThreads, 0, st>>>(idx, f, no, floor, D, n);
+    else if (order == 4) k_dressed_denoms<4><<<grid, kThreads, 0, st>>>(idx, f, no, floor, D, n);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_count_nonfinite(const double* x, long long n, unsigned long long* count, hipStream_t st) {
     hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess || n <= 0) return e;

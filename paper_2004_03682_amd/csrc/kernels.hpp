@@ -83,7 +83,9 @@ struct MProb {
     long long a_off, b_off, c_off;
     int M, N, Kp, ldc, rows_a, rows_b;
 };
-enum MCfg { MCFG_64x64 = 0, MCFG_64x32, MCFG_32x64, MCFG_32x32, MCFG_N };
+// split-kernel tiles; MCFG_TILES + t: tile t with the B fragments read from
+// global memory straight into registers (only A staged in LDS)
+enum MCfg { MCFG_64x64 = 0, MCFG_64x32, MCFG_32x64, MCFG_32x32, MCFG_TILES, MCFG_N = 2 * MCFG_TILES };
 void mcfg_tile(int cfg, int* bm, int* bn);
 hipError_t launch_zgemm_split(bool bf16, int cfg, const void* A, long long sA, const void* B, long long sB, double2* C,
                               const MProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta,
@@ -153,6 +155,11 @@ hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long
 // *count = number of non-finite doubles in x[0..n) (zeroes *count first; not
 // for code under graph capture: it records a memset)
 hipError_t launch_count_nonfinite(const double* x, long long n, unsigned long long* count, hipStream_t st);
+// dressed Jacobi denominators: D[k] = min(f[i] - f[no + a], -floor) (order 2,
+// idx = (i, a) per element) or min(f[i] + f[j] - f[no + a] - f[no + b], -floor)
+// (order 4, idx = (i, j, a, b)); f = occupied then virtual one-particle energies
+hipError_t launch_dressed_denoms(const uint16_t* idx, int order, const double* f, int no, double floor, double* D,
+                                 long long n, hipStream_t st);
 // coef holds ldb + 1 doubles: coef[ldb] = 1 marks a non-finite step
 hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
                               int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st);

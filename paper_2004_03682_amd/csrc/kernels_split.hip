@@ -113,7 +113,13 @@ __global__ __launch_bounds__(256) void k_split(const double2* __restrict__ src, 
 // Planes: piece-major, re/im minor (plane 2*piece + ri).  Accumulator terms per
 // fragment: 0 = sum Ar*Br, 1 = sum Ai*Bi, 2 = sum Ar*Bi, 3 = sum Ai*Br.
 // ROLE only distinguishes kernel symbols in profiles (1 pp-ladder, 2 ring).
-template <bool BF, int BM, int BN, int WM, int WN, int ROLE>
+// BD: the B fragments are read by each wave straight from global memory into
+// registers (the panel layout makes the 16 x 32 slice of one fragment 1 KB
+// (bf16) or 2 KB (fp32) contiguous, lane l at offset 16 l or 32 l: the MFMA
+// operand layout itself), one k block ahead; only A goes through LDS.  This
+// takes the B stores and B fragment reads off the LDS, which otherwise
+// carries more bytes per MFMA than it can serve.
+template <bool BF, int BM, int BN, int WM, int WN, int ROLE, bool BD>
 __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av, long long sA,
                                                      const void* __restrict__ Bv, long long sB,
                                                      double2* __restrict__ C, const MProb* __restrict__ probs,
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
     constexpr int FM = BM / (16 * WM), FN = BN / (16 * WN);
     constexpr int FV = BF ? 1 : 2;             // 16-byte vectors per fragment and plane
     static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "tile");
-    __shared__ __attribute__((aligned(16))) unsigned char lds[NPL * (BM + BN) * PITCH];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[NPL * (BM + (BD ? 0 : BN)) * PITCH];
     unsigned char* ldsA = lds;
     unsigned char* ldsB = lds + NPL * BM * PITCH;
 
@@ -143,7 +149,9 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
     const unsigned char* Bb = (const unsigned char*)Bv + (pr.b_off + (long long)n0 * KB) * ES;
     const long long stepA = (long long)pr.rows_a * KB * ES, stepB = (long long)pr.rows_b * KB * ES;
 
-    u4v ra[AVT], rb[BVT];
+    const int lr = lane & 15, kq = lane >> 4;
+    u4v ra[AVT], rb[BD ? 1 : BVT];
+    u4v gb[NPC][2][FN][FV];   // BD: the next k block's B fragments
     auto load = [&](int kb) {
 #pragma unroll
         for (int u = 0; u < AVT; ++u) {
@@ -153,12 +161,26 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
                 ra[u] = *(const u4v*)(Ab + (long long)p * sA * ES + kb * stepA + (long long)w * 16);
             }
         }
+        if constexpr (BD) {
 #pragma unroll
-        for (int u = 0; u < BVT; ++u) {
-            const int v = tid + u * kT;
-            if (v < BVEC) {
-                const int p = v / (BN * VPR), w = v % (BN * VPR);
-                rb[u] = *(const u4v*)(Bb + (long long)p * sB * ES + kb * stepB + (long long)w * 16);
+            for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int h = 0; h < FV; ++h)
+                            gb[pc][ri][j][h] = *(const u4v*)(Bb + (long long)(2 * pc + ri) * sB * ES + kb * stepB +
+                                                             (long long)(wn0 + j * 16 + lr) * ROWB + kq * 16 * FV +
+                                                             h * 16);
+        } else {
+#pragma unroll
+            for (int u = 0; u < BVT; ++u) {
+                const int v = tid + u * kT;
+                if (v < BVEC) {
+                    const int p = v / (BN * VPR), w = v % (BN * VPR);
+                    rb[u] = *(const u4v*)(Bb + (long long)p * sB * ES + kb * stepB + (long long)w * 16);
+                }
             }
         }
     };
@@ -171,17 +193,18 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
                 *(u4v*)(ldsA + (p * BM + w / VPR) * PITCH + (w % VPR) * 16) = ra[u];
             }
         }
+        if constexpr (!BD) {
 #pragma unroll
-        for (int u = 0; u < BVT; ++u) {
-            const int v = tid + u * kT;
-            if (v < BVEC) {
-                const int p = v / (BN * VPR), w = v % (BN * VPR);
-                *(u4v*)(ldsB + (p * BN + w / VPR) * PITCH + (w % VPR) * 16) = rb[u];
+            for (int u = 0; u < BVT; ++u) {
+                const int v = tid + u * kT;
+                if (v < BVEC) {
+                    const int p = v / (BN * VPR), w = v % (BN * VPR);
+                    *(u4v*)(ldsB + (p * BN + w / VPR) * PITCH + (w % VPR) * 16) = rb[u];
+                }
             }
         }
     };
 
-    const int lr = lane & 15, kq = lane >> 4;
     double dr[FM][FN][4], di[FM][FN][4];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -195,20 +218,31 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
         __syncthreads();
         store();
         __syncthreads();
-        if (kb + 1 < nkb) load(kb + 1);
-
         // fragments: lane (lr, kq) holds k = 8*kq .. 8*kq+7 of row/column lr
         u4v fb[NPC][2][FN][FV];
+        if constexpr (BD) {
 #pragma unroll
-        for (int pc = 0; pc < NPC; ++pc)
+            for (int pc = 0; pc < NPC; ++pc)
 #pragma unroll
-            for (int ri = 0; ri < 2; ++ri)
+                for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
+                    for (int j = 0; j < FN; ++j)
 #pragma unroll
-                    for (int h = 0; h < FV; ++h)
-                        fb[pc][ri][j][h] = *(const u4v*)(ldsB + ((2 * pc + ri) * BN + wn0 + j * 16 + lr) * PITCH +
-                                                         kq * 16 * FV + h * 16);
+                        for (int h = 0; h < FV; ++h) fb[pc][ri][j][h] = gb[pc][ri][j][h];
+        }
+        if (kb + 1 < nkb) load(kb + 1);
+        if constexpr (!BD) {
+#pragma unroll
+            for (int pc = 0; pc < NPC; ++pc)
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int h = 0; h < FV; ++h)
+                            fb[pc][ri][j][h] = *(const u4v*)(ldsB + ((2 * pc + ri) * BN + wn0 + j * 16 + lr) * PITCH +
+                                                             kq * 16 * FV + h * 16);
+        }
         f4v acc[FM][FN][4];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -295,7 +329,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
 }
 
 void mcfg_tile(int cfg, int* bm, int* bn) {
-    switch (cfg) {
+    switch (cfg % MCFG_TILES) {
         case MCFG_64x32: *bm = 64; *bn = 32; break;
         case MCFG_32x64: *bm = 32; *bn = 64; break;
         case MCFG_32x32: *bm = 32; *bn = 32; break;
@@ -313,31 +347,41 @@ hipError_t launch_split(bool bf16, const double2* src, void* dst, long long plan
     return hipGetLastError();
 }
 
-template <bool BF, int BM, int BN, int WM, int WN>
+template <bool BF, int BM, int BN, int WM, int WN, bool BD>
 static hipError_t launch_split_cfg(const void* A, long long sA, const void* B, long long sB, double2* C,
                                    const MProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta,
                                    hipStream_t st, int role) {
     dim3 grid(ntiles), block(kT);
     if (role == 1)
-        k_zgemm_split<BF, BM, BN, WM, WN, 1><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
+        k_zgemm_split<BF, BM, BN, WM, WN, 1, BD><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
     else if (role == 2)
-        k_zgemm_split<BF, BM, BN, WM, WN, 2><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
+        k_zgemm_split<BF, BM, BN, WM, WN, 2, BD><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
     else
-        k_zgemm_split<BF, BM, BN, WM, WN, 0><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
+        k_zgemm_split<BF, BM, BN, WM, WN, 0, BD><<<grid, block, 0, st>>>(A, sA, B, sB, C, probs, tiles, ar, ai, beta);
     return hipGetLastError();
+}
+
+template <bool BF, bool BD>
+static hipError_t launch_split_tile(int tile, const void* A, long long sA, const void* B, long long sB, double2* C,
+                                    const MProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta,
+                                    hipStream_t st, int role) {
+    switch (tile) {
+        case MCFG_64x64: return launch_split_cfg<BF, 64, 64, 2, 2, BD>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
+        case MCFG_64x32: return launch_split_cfg<BF, 64, 32, 2, 2, BD>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
+        case MCFG_32x64: return launch_split_cfg<BF, 32, 64, 2, 2, BD>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
+        case MCFG_32x32: return launch_split_cfg<BF, 32, 32, 2, 2, BD>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <bool BF>
 static hipError_t launch_split_bf(int cfg, const void* A, long long sA, const void* B, long long sB, double2* C,
                                   const MProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta,
                                   hipStream_t st, int role) {
-    switch (cfg) {
-        case MCFG_64x64: return launch_split_cfg<BF, 64, 64, 2, 2>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
-        case MCFG_64x32: return launch_split_cfg<BF, 64, 32, 2, 2>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
-        case MCFG_32x64: return launch_split_cfg<BF, 32, 64, 2, 2>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
-        case MCFG_32x32: return launch_split_cfg<BF, 32, 32, 2, 2>(A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
-        default: return hipErrorInvalidValue;
-    }
+    if (cfg < 0 || cfg >= MCFG_N) return hipErrorInvalidValue;
+    if (cfg >= MCFG_TILES)
+        return launch_split_tile<BF, true>(cfg - MCFG_TILES, A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
+    return launch_split_tile<BF, false>(cfg, A, sA, B, sB, C, probs, tiles, ntiles, ar, ai, beta, st, role);
 }
 
 hipError_t launch_zgemm_split(bool bf16, int cfg, const void* A, long long sA, const void* B, long long sB, double2* C,

@@ -144,6 +144,8 @@ struct fscc_ctx {
     bool ready02 = false;
     bool resid00 = false;   // a (0h,0p) residual has been evaluated (its F'_be, F'_mj are current)
     int b_pre1 = -1, b_pre2 = -1;   // dressed (0h,0p) denominators (fscc_precondition)
+    uint16_t *d_idx1 = nullptr, *d_idx2 = nullptr;   // per amplitude: its (i, a) / (i, j, a, b) positions
+    double* d_fov = nullptr;                          // f_p of the occupied, then the virtual positions
     Diis diis[3];
     double* part = nullptr;
     double* part_max = nullptr;
@@ -252,7 +254,7 @@ struct fscc_ctx {
         }
         for (void* p : seg_mem)
             if (p) (void)hipFree(p);
-        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp};
+        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp, d_idx1, d_idx2, d_fov};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hscal) (void)hipHostFree(hscal);

@@ -4,6 +4,9 @@
   python tests/golden/make_golden.py o40v300z16 [--save-amplitudes PATH.npz]
                                                      # o40v300z16_ccsd.json (about an hour on 8 cores);
                                                      # optionally also every converged block of t1, t2
+  python tests/golden/make_golden.py batch40000 K [K ...]
+                                                     # batch40000_ccsd.json: systems K of the
+                                                     # 64-system batched workload (seeds 40000 + K)
   python tests/golden/make_golden.py fs01-plain PATH.npz
                                                      # o40v300z16_fs01_plain.json from the saved
                                                      # converged amplitudes (a few minutes)
@@ -20,6 +23,10 @@ trajectory (iteration count to 1e-10 included), every T1 element, and a seeded s
 unique T2 elements (i<j, a<b, allowed by the Z16 selection rule) plus the 64 largest
 |t2|, each as (i, j, a, b, re, im) with spinor positions counted inside the occupied and
 virtual spaces.
+
+batch40000_ccsd.json: converged (0h,0p) energies of systems of the batched workload
+(fsgen.batch_systems(64, 40000): nocc 10-30, nvirt 60-200, 4-8 irreps, sigma 0.05),
+block-list oracle, Jacobi + DIIS(6) to max|step| < 1e-11; keyed by the system's index.
 
 o40v300z16_fs01_plain.json: the (0h,1p) sector of the same system (the six lowest
 virtual spinors active) iterated from zero on the oracle's converged T: Jacobi steps
@@ -146,6 +153,23 @@ def production(save=None):
         np.savez(save, **arrays)
 
 
+def batch_systems(indices):
+    path = os.path.join(HERE, "batch40000_ccsd.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    ss = fsgen.batch_systems(64, 40000)
+    for k in indices:
+        s = ss[k]
+        t0 = time.time()
+        r = solver.solve_ccsd(ccsd.Blocked(s), tol=1e-11, maxit=300, log=lambda m: print(m, flush=True))
+        out[str(k)] = dict(nocc=s.nocc, nvirt=s.nvirt, nirrep=s.nirrep, seed=s.seed, E_re=r["E"].real,
+                           E_im=r["E"].imag, iters=r["iters"], converged=r["converged"], tol=1e-11,
+                           oracle="oracle.solver.solve_ccsd(oracle.ccsd.Blocked, tol=1e-11)",
+                           seconds=round(time.time() - t0, 1))
+        print(k, out[str(k)], flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
+
 def fs01_plain(npz, n=40):
     from oracle import fs01
     from oracle.blocks import BlockTensor
@@ -169,6 +193,9 @@ def fs01_plain(npz, n=40):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) > 2 and sys.argv[1] == "batch40000":
+        batch_systems([int(x) for x in sys.argv[2:]])
+        sys.exit(0)
     if len(sys.argv) > 2 and sys.argv[1] == "fs01-plain":
         fs01_plain(sys.argv[2])
         sys.exit(0)

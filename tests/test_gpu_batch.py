@@ -201,3 +201,32 @@ def test_device_generator_matches_host_generator():
             # same counters and definition; device transcendental functions may differ in the last bits
             assert np.abs(got - ref).max(initial=0.0) <= 1e-15 * max(1.0, s.sigma), (p, C)
             assert np.array_equal(got == 0, ref == 0), (p, C)
+
+
+def test_batched_workload_systems_converge_to_the_oracle():
+    """Systems of the 64-system batched workload (nocc 10-30, nvirt 60-200,
+    4-8 irreps) solved as a batch with the workload's solver (DIIS(8),
+    dressed denominators refreshed every 25 iterations) reach the block-list
+    oracle's converged energies (tests/golden/batch40000_ccsd.json)."""
+    import json
+    import os
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch40000_ccsd.json")))
+    idx = sorted(int(k) for k in gold)
+    ss = fsgen.batch_systems(64, 40000)
+    systems = [ss[k] for k in idx]
+    for k, s in zip(idx, systems):
+        assert (s.nocc, s.nvirt, s.nirrep, s.seed) == (gold[str(k)]["nocc"], gold[str(k)]["nvirt"],
+                                                       gold[str(k)]["nirrep"], gold[str(k)]["seed"])
+        assert gold[str(k)]["converged"]
+    b = make_batch(systems)
+    t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
+    res = F.solve_batch(b, t1, t2, tol=1e-11, maxit=600, use_graph=True, ndiis=8, dressed=25)
+    for j, k in enumerate(idx):
+        g = gold[str(k)]
+        print("system", k, "batch", res["E"][j], res["iters"][j], "oracle", g["E_re"], g["E_im"], g["iters"], flush=True)
+        assert res["converged"][j]
+        assert abs(res["E"][j].real - g["E_re"]) <= 1e-10 and abs(res["E"][j].imag - g["E_im"]) <= 1e-10
+    b.destroy()

@@ -63,7 +63,7 @@ def _run(prec, cfg, M, N, K, tA, tB, cA, cB, beta, seed=0, alpha=0.7 - 0.3j):
     return err, bound, ref
 
 
-@pytest.mark.parametrize("prec,cfg", list(itertools.product(PRECS, range(4))))
+@pytest.mark.parametrize("prec,cfg", list(itertools.product(PRECS, range(8))))
 def test_split_gemm_every_config(prec, cfg):
     for (tA, tB, cA, cB) in [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 0, 1), (1, 1, 1, 1)]:
         for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 129), (130, 131, 40), (64, 64, 64)]:
