@@ -252,6 +252,13 @@ fscc_status fscc_heff_eig(int n, const fscc_c128 *heff_host, fscc_c128 *eig_host
  * equations; clears the sector's DIIS history. */
 fscc_status fscc_precondition(fscc_ctx *ctx, fscc_sector sector, int mode, double floor);
 
+/* Device copies of the Jacobi denominators the (0h,0p) update uses now
+ * (sector = FSCC_S00: the bare e_i - e_a, e_i + e_j - e_a - e_b, or the
+ * dressed ones after fscc_precondition mode 1), in the packed T1 / T2
+ * layouts, without level shift.  D1, D2: device arrays of n1, n2 doubles
+ * (fscc_layout), owned by the caller.  Asynchronous on the stream. */
+fscc_status fscc_denominators(fscc_ctx *ctx, fscc_sector sector, double *D1, double *D2);
+
 /* Correlation energy of the (0h,0p) sector, the expectation value of Eq. (1)'s
  * normal-ordered Hamiltonian in the coupled-cluster state of Eq. (2):
  * E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a) (the f_ia term

@@ -65,6 +65,7 @@ def lib():
             "fscc_heff": ([vp, vp, vp, vp], ip),
             "fscc_heff2": ([vp, vp, vp], ip),
             "fscc_precondition": ([vp, ip, ip, ctypes.c_double], ip),
+            "fscc_denominators": ([vp, ip, vp, vp], ip),
             "fscc_autotune": ([vp, ip], ip),
             "fscc_gemm_config": ([vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)], ip),
             "fscc_zgemm": ([ip] * 9 + [vp, ip, vp, ip, vp, ip, ctypes.c_double, ctypes.c_double, ip, ip, vp], ip),
@@ -274,6 +275,14 @@ class Context:
 
     def precondition(self, mode=1, floor=0.1, sector=FSCC_S01):
         self._check(lib().fscc_precondition(self._h, sector, int(mode), float(floor)))
+
+    def denominators(self):
+        """(D1, D2): the (0h,0p) Jacobi denominators in use (float64 device tensors)."""
+        import torch
+        D1 = torch.empty(max(self.n1, 1), dtype=torch.float64, device="cuda")[:self.n1]
+        D2 = torch.empty(max(self.n2, 1), dtype=torch.float64, device="cuda")[:self.n2]
+        self._check(lib().fscc_denominators(self._h, FSCC_S00, _ptr(D1), _ptr(D2)))
+        return D1, D2
 
     def heff(self, s1, s2):
         """H_eff[y][x] (numpy complex, nact x nact, rows/columns in the order of the active list)."""

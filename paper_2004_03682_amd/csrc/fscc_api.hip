@@ -1039,6 +1039,22 @@ static fscc_status precondition00(fscc_ctx* ctx, int mode, double floor) {
     return FSCC_OK;
 }
 
+fscc_status fscc_denominators(fscc_ctx* ctx, fscc_sector sector, double* D1, double* D2) {
+    if (!ctx) return FSCC_EINVAL;
+    if (sector != FSCC_S00) return fail(ctx, FSCC_EINVAL, "denominators of the (0h,0p) sector only");
+    if ((ctx->n1() && !D1) || (ctx->n2() && !D2)) return fail(ctx, FSCC_EINVAL, "null denominator buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        const Diis& D = ctx->diis[FSCC_S00];
+        if (ctx->n1())
+            hip_check(hipMemcpyAsync(D1, ctx->dbuf[D.b_D1], sizeof(double) * ctx->n1(), hipMemcpyDeviceToDevice, ctx->st),
+                      "D1 copy");
+        if (ctx->n2())
+            hip_check(hipMemcpyAsync(D2, ctx->dbuf[D.b_D2], sizeof(double) * ctx->n2(), hipMemcpyDeviceToDevice, ctx->st),
+                      "D2 copy");
+        return FSCC_OK;
+    });
+}
+
 fscc_status fscc_precondition(fscc_ctx* ctx, fscc_sector sector, int mode, double floor) {
     if (!ctx) return FSCC_EINVAL;
     Plan& P = ctx->plan;

@@ -251,3 +251,48 @@ def test_tiled_gathers_bitwise_equal_in_every_sector():
         for a, b in zip(out[0], out[tiled]):
             assert torch.equal(a, b), tiled
     ctx.destroy()
+
+
+@pytest.mark.parametrize("spec", [(6, 14, 4, 0.1, 21), (9, 37, 5, 0.05, 17), (8, 24, 1, 0.05, 1000)],
+                         ids=["z4", "ragged-z5", "o8v24"])
+def test_dressed_denominators_match_oracle_intermediates(spec):
+    """fscc_precondition (0h,0p) mode 1: D_i^a = f_i - f_a and D_ij^ab = f_i + f_j
+    - f_a - f_b with f_p = e_p + Re F'_pp, F'_be = F_be - 1/2 sum_m t_m^b F_me and
+    F'_mj = F_mj + 1/2 sum_e t_j^e F_me from the oracle's one-body intermediates
+    at the amplitudes of the last residual, capped at -floor; mode 0 restores
+    the bare e_i - e_a, e_i + e_j - e_a - e_b."""
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    s = fsgen.make_system(*spec)
+    ctx = gpu_ctx(s)
+    t1, t2 = allowed_random_t(s, 5, scale=0.1)
+    a1, a2 = dev(LR.pack_t1(s, t1)), dev(LR.pack_t2(s, t2))
+    r1, r2 = torch.empty_like(a1), torch.empty_like(a2)
+    ctx.build_residual(a1, a2, r1, r2)
+    floor = 0.3
+    ctx.precondition(1, floor, F.FSCC_S00)
+    G1, G2 = (host(x) for x in ctx.denominators())
+    be = ccsd.Dense(s)
+    I = ccsd.intermediates(be, t1, t2, one_body_only=True)
+    Fbe = I["Fae"] - 0.5 * np.einsum("mb,me->be", t1, I["Fme"])
+    Fmj = I["Fmi"] + 0.5 * np.einsum("je,me->mj", t1, I["Fme"])
+    no = s.nocc
+    fo = s.eps[:no] + np.real(np.diag(Fmj))
+    fv = s.eps[no:] + np.real(np.diag(Fbe))
+    D1 = np.minimum(fo[:, None] - fv[None, :], -floor)
+    D2 = np.minimum(fo[:, None, None, None] + fo[None, :, None, None] - fv[None, None, :, None]
+                    - fv[None, None, None, :], -floor)
+    W1 = LR.pack_t1(s, D1.astype(np.complex128)).real
+    W2 = LR.pack_t2(s, D2.astype(np.complex128)).real
+    print("max |D'| diff", np.abs(G1 - W1).max(initial=0.0), np.abs(G2 - W2).max(initial=0.0), flush=True)
+    assert np.abs(G1 - W1).max(initial=0.0) <= 1e-12 * max(1.0, np.abs(W1).max(initial=0.0))
+    assert np.abs(G2 - W2).max(initial=0.0) <= 1e-12 * max(1.0, np.abs(W2).max(initial=0.0))
+    assert (W2 != LR.pack_t2(s, (s.eps[:no, None, None, None] + s.eps[None, :no, None, None]
+                                 - s.eps[None, None, no:, None] - s.eps[None, None, None, no:]).astype(complex)).real).any()
+    ctx.precondition(0, floor, F.FSCC_S00)
+    B1, B2 = (host(x) for x in ctx.denominators())
+    e = s.eps
+    assert np.array_equal(B1, LR.pack_t1(s, (e[:no, None] - e[None, no:]).astype(complex)).real)
+    d2 = e[:no, None, None, None] + e[None, :no, None, None] - e[None, None, no:, None] - e[None, None, None, no:]
+    assert np.abs(B2 - LR.pack_t2(s, d2.astype(complex)).real).max(initial=0.0) <= 1e-14
+    ctx.destroy()
