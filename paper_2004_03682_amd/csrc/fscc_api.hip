@@ -1375,7 +1375,7 @@ namespace {
 // of the context's plans (kind, name, sizes, GEMM problem shapes); an entry
 // lists per operation the chosen form: GEMM [1, tile, bk, split, 3M, DB,
 // split-precision tile or -1], reorder [0, traversal], other [2].
-constexpr int kTuneVersion = 4;
+constexpr int kTuneVersion = 5;
 
 std::vector<OpList*> tune_lists(fscc_ctx* c) { return {&c->L00, &c->L01, &c->L02}; }
 
@@ -1701,7 +1701,9 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                             if (!cfg_ok(o, cfg, ctx->real)) continue;
                             GemmDev cand;
                             plan_gemm(ctx, o, cand, cfg, bk, sp == 1);
-                            if (sp == 0 && !cand.split) {
+                            // a plan without a split that the sp = 1 pass already timed
+                            const bool timed_split_pass = !(cfg == ZCFG_TALL || cfg == ZCFG_DOT);
+                            if (sp == 0 && !cand.split && timed_split_pass) {
                                 GemmDev probe;
                                 plan_gemm(ctx, o, probe, cfg, bk, true);
                                 bool same = !probe.split;
