@@ -2,10 +2,11 @@
 synthetic workload (nocc=40, nvirt=300 spinors, 16 Abelian irreps with
 Dirichlet(1) block sizes, sigma=0.03, complex128).
 
-One step = one CCSD iteration of the whole hot path: fscc_build_residual
-(every contraction of the residual) + fscc_update_amplitudes (Jacobi step,
-DIIS(6) on the device) + fscc_energy.  Inputs (packed integrals, amplitudes)
-are resident in HBM when the timed region starts.
+One step = one CCSD iteration of the whole hot path (fscc_iterate): the
+residual (every contraction), the Jacobi step with dressed denominators
+(refreshed every 25 iterations) and DIIS(6) on the device, and the energy,
+with one host synchronisation.  Inputs (packed integrals, amplitudes) are
+resident in HBM when the timed region starts.
 
 Prints ONE JSON line.  The roofline object is for the dominant kernel (the
 grouped complex GEMM with the largest time per step), timed with HIP events
@@ -964,9 +965,7 @@ def main():
         nit[0] += 1
         if nit[0] >= 3 and (nit[0] - 3) % DRESSED == 0:
             ctx.precondition(1, 0.1, F.FSCC_S00)
-        ctx.build_residual(t1, t2, r1, r2)
-        d = ctx.update_amplitudes(t1, t2, r1, r2)
-        return d, ctx.energy(t1, t2)
+        return ctx.iterate(t1, t2, r1, r2)
 
     # warm-up iterations time every operation (HIP events around each one):
     # the per-operation table and the choice of the dominant GEMM

@@ -259,6 +259,15 @@ fscc_status fscc_precondition(fscc_ctx *ctx, fscc_sector sector, int mode, doubl
  * (fscc_layout), owned by the caller.  Asynchronous on the stream. */
 fscc_status fscc_denominators(fscc_ctx *ctx, fscc_sector sector, double *D1, double *D2);
 
+/* One whole (0h,0p) iteration with a single synchronisation: the residual
+ * of t1, t2 into r1, r2 (as fscc_build_residual), the Jacobi + DIIS update of
+ * t1, t2 (as fscc_update_amplitudes) and the energy of the updated amplitudes
+ * (as fscc_energy), all enqueued before the host waits once for the step size
+ * and the energy.  Same arguments, layouts and errors as those three calls;
+ * on FSCC_ENOCONV *e_re, *e_im hold the energy of whatever t1, t2 then hold. */
+fscc_status fscc_iterate(fscc_ctx *ctx, fscc_c128 *t1, fscc_c128 *t2, fscc_c128 *r1, fscc_c128 *r2, double *max_step,
+                         double *e_re, double *e_im);
+
 /* Correlation energy of the (0h,0p) sector, the expectation value of Eq. (1)'s
  * normal-ordered Hamiltonian in the coupled-cluster state of Eq. (2):
  * E = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_i^b t_j^a) (the f_ia term

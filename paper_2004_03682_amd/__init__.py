@@ -53,6 +53,7 @@ def lib():
             "fscc_build_residual": ([vp, ip, vp, vp, vp, vp], ip),
             "fscc_update_amplitudes": ([vp, ip, vp, vp, vp, vp, dp], ip),
             "fscc_energy": ([vp, vp, vp, dp, dp], ip),
+            "fscc_iterate": ([vp, vp, vp, vp, vp, dp, dp, dp], ip),
             "fscc_diis_reset": ([vp, ip, ip], ip),
             "fscc_ladder": ([vp, vp, vp], ip),
             "fscc_work": ([vp, dp, dp, dp], ip),
@@ -300,6 +301,14 @@ class Context:
         self._check(lib().fscc_heff2(self._h, self._d(s, self.p2), out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def iterate(self, t1, t2, r1, r2):
+        """One (0h,0p) iteration (residual, update, energy) with one synchronisation:
+        returns (max|step|, E)."""
+        d, er, ei = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().fscc_iterate(self._h, self._d(t1, self.n1), self._d(t2, self.n2), self._d(r1, self.n1),
+                                       self._d(r2, self.n2), ctypes.byref(d), ctypes.byref(er), ctypes.byref(ei)))
+        return d.value, complex(er.value, ei.value)
+
     def energy(self, t1, t2):
         er, ei = ctypes.c_double(), ctypes.c_double()
         self._check(lib().fscc_energy(self._h, self._d(t1, self.n1), self._d(t2, self.n2),
@@ -516,9 +525,7 @@ def solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=6, log=None, reset_diis=True,
     for k in range(1, maxit + 1):
         if dressed and k >= 3 and (k - 3) % dressed == 0:
             ctx.precondition(1, floor, FSCC_S00)     # from the residual of iteration k - 1
-        ctx.build_residual(t1, t2, r1, r2)
-        dmax = ctx.update_amplitudes(t1, t2, r1, r2)
-        E = ctx.energy(t1, t2)
+        dmax, E = ctx.iterate(t1, t2, r1, r2)
         hist.append(dict(iter=k, E=E, dmax=dmax, time=time.perf_counter()))
         if log:
             log(f"iter {k:3d}  E = {E.real:+.14f} {E.imag:+.3e}i  max|step| = {dmax:.3e}")

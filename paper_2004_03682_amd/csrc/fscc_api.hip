@@ -1119,62 +1119,61 @@ fscc_status fscc_diis_reset(fscc_ctx* ctx, fscc_sector sector, int ndiis) {
     return FSCC_OK;
 }
 
-fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2,
-                                   const fscc_c128* r1, const fscc_c128* r2, double* max_step) {
-    if (!ctx || !max_step) return FSCC_EINVAL;
-    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01) || (sector == FSCC_S02 && ctx->plan.has02)))
-        return fail(ctx, FSCC_EINVAL, "sector not available for this system");
+namespace {
+
+// The update of one sector up to the device work: Jacobi step, DIIS dots,
+// bordered solve and extrapolation enqueued on the stream, the subspace's
+// slot bookkeeping done, and max|step| / dropped vectors copied to pinned
+// host memory (hscal[0..1]); update_finish reads them after a sync.
+void update_enqueue(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2, const fscc_c128* r1,
+                    const fscc_c128* r2) {
     Diis& D = ctx->diis[sector];
-    if ((D.n1 && (!t1 || !r1)) || (D.n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
-    return guarded(ctx, [&]() -> fscc_status {
-        const int64_t n1 = D.n1, n2 = D.n2, n = n1 + n2;
-        const int depth = std::max(1, D.ndiis);
-        std::vector<int>& ord = D.order;
-        int slot;
-        if ((int)ord.size() < depth) {
-            std::vector<char> used(kMaxDiis, 0);
-            for (int s : ord) used[s] = 1;
-            slot = 0;
-            while (used[slot]) ++slot;
-        } else {
-            slot = ord.front();
-            ord.erase(ord.begin());
+    const int64_t n1 = D.n1, n2 = D.n2, n = n1 + n2;
+    const int depth = std::max(1, D.ndiis);
+    std::vector<int>& ord = D.order;
+    int slot;
+    if ((int)ord.size() < depth) {
+        std::vector<char> used(kMaxDiis, 0);
+        for (int s : ord) used[s] = 1;
+        slot = 0;
+        while (used[slot]) ++slot;
+    } else {
+        slot = ord.front();
+        ord.erase(ord.begin());
+    }
+    ord.push_back(slot);
+    double2* ht = D.ht + (size_t)slot * n;
+    double2* he = D.he + (size_t)slot * n;
+    int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
+    if (ctx->real) {
+        // the same sequence on doubles (history slots hold n doubles)
+        double* dht = (double*)D.ht + (size_t)slot * n;
+        double* dhe = (double*)D.he + (size_t)slot * n;
+        if (n1 > 0)
+            hip_check(launch_djacobi((const double*)t1, (const double*)r1, (const double*)ctx->dbuf[D.b_D1], dht, dhe, n1,
+                                     ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
+                      "jacobi 1");
+        if (n2 > 0)
+            hip_check(launch_djacobi((const double*)t2, (const double*)r2, (const double*)ctx->dbuf[D.b_D2], dht + n1,
+                                     dhe + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift, D.dyn_S, D.dyn_n),
+                      "jacobi 2");
+        int m = (int)ord.size();
+        std::vector<const double*> ev(m);
+        for (int j = 0; j < m; ++j) ev[j] = (const double*)D.he + (size_t)ord[j] * n;
+        int nbd = reduce_blocks(n);
+        hip_check(launch_ddots(ev.data(), m, dhe, n, ctx->part, nbd, ctx->st), "diis dots");
+        hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st), "order");
+        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, ctx->dorder,
+                                     ctx->coef, ctx->scal, ctx->st),
+                  "diis solve");
+        std::vector<const double*> xs(kMaxDiis);
+        for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n;
+        if (n1 > 0) hip_check(launch_dlincomb((double*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb 1");
+        if (n2 > 0) {
+            for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n + n1;
+            hip_check(launch_dlincomb((double*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
         }
-        ord.push_back(slot);
-        double2* ht = D.ht + (size_t)slot * n;
-        double2* he = D.he + (size_t)slot * n;
-        int nb1 = n1 > 0 ? reduce_blocks(n1) : 0, nb2 = n2 > 0 ? reduce_blocks(n2) : 0;
-        if (ctx->real) {
-            // the same sequence on doubles (history slots hold n doubles)
-            double* dht = (double*)D.ht + (size_t)slot * n;
-            double* dhe = (double*)D.he + (size_t)slot * n;
-            if (n1 > 0)
-                hip_check(launch_djacobi((const double*)t1, (const double*)r1, (const double*)ctx->dbuf[D.b_D1], dht,
-                                         dhe, n1, ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
-                          "jacobi 1");
-            if (n2 > 0)
-                hip_check(launch_djacobi((const double*)t2, (const double*)r2, (const double*)ctx->dbuf[D.b_D2],
-                                         dht + n1, dhe + n1, n2, ctx->part_max + nb1, nb2, ctx->st, D.shift, D.dyn_S,
-                                         D.dyn_n),
-                          "jacobi 2");
-            int m = (int)ord.size();
-            std::vector<const double*> ev(m);
-            for (int j = 0; j < m; ++j) ev[j] = (const double*)D.he + (size_t)ord[j] * n;
-            int nbd = reduce_blocks(n);
-            hip_check(launch_ddots(ev.data(), m, dhe, n, ctx->part, nbd, ctx->st), "diis dots");
-            hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st),
-                      "order");
-            hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot,
-                                         ctx->dorder, ctx->coef, ctx->scal, ctx->st),
-                      "diis solve");
-            std::vector<const double*> xs(kMaxDiis);
-            for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n;
-            if (n1 > 0) hip_check(launch_dlincomb((double*)t1, xs.data(), ctx->coef, kMaxDiis, n1, ctx->st), "lincomb 1");
-            if (n2 > 0) {
-                for (int q = 0; q < kMaxDiis; ++q) xs[q] = (const double*)D.ht + (size_t)q * n + n1;
-                hip_check(launch_dlincomb((double*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
-            }
-        } else {
+    } else {
         if (n1 > 0)
             hip_check(launch_jacobi((const double2*)t1, (const double2*)r1, (const double*)ctx->dbuf[D.b_D1], ht, he, n1,
                                     ctx->part_max, nb1, ctx->st, D.shift, D.dyn_S, D.dyn_n),
@@ -1199,33 +1198,89 @@ fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128*
             for (int s = 0; s < kMaxDiis; ++s) xs[s] = D.ht + (size_t)s * n + n1;
             hip_check(launch_lincomb((double2*)t2, xs.data(), ctx->coef, kMaxDiis, n2, ctx->st), "lincomb 2");
         }
-        }
-        hip_check(hipMemcpyAsync(ctx->hscal, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "scal");
+    }
+    hip_check(hipMemcpyAsync(ctx->hscal, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "scal");
+}
+
+// After the stream has synchronised: subspace bookkeeping from the device's
+// solve and the divergence watch.
+fscc_status update_finish(fscc_ctx* ctx, fscc_sector sector, double* max_step) {
+    Diis& D = ctx->diis[sector];
+    std::vector<int>& ord = D.order;
+    int dropped = (int)ctx->hscal[1];
+    if (dropped > 0) ord.erase(ord.begin(), ord.begin() + std::min(dropped, (int)ord.size() - 1));
+    if (D.ndiis <= 1) ord.clear();
+    double mx = ctx->hscal[0];
+    switch (D.watch.observe(mx)) {
+        case DivergenceWatch::CONTINUE:
+            break;
+        case DivergenceWatch::RESET_DIIS:
+            ord.clear();   // the next step starts a fresh subspace
+            break;
+        case DivergenceWatch::GIVE_UP:
+            ord.clear();
+            D.watch.restart();
+            if (!std::isfinite(mx))
+                return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step (amplitudes left at their input values)");
+            *max_step = mx;
+            return fail(ctx, FSCC_ENOCONV,
+                        "max|step| = " + std::to_string(mx) + " grew more than " +
+                            std::to_string(DivergenceWatch::kGrowth) +
+                            "x above its smallest value again after a DIIS reset: the iteration diverges "
+                            "(amplitudes hold the last, finite, iterate)");
+    }
+    *max_step = mx;
+    return FSCC_OK;
+}
+
+// (0h,0p) energy of t1, t2: tau = t2 + t1 t1 (the first two operations of
+// the plan), sum <ij||ab> tau, result copied to hscal[4..5].
+void energy_enqueue(fscc_ctx* ctx, const fscc_c128* t1, const fscc_c128* t2) {
+    Plan& P = ctx->plan;
+    bind_io(ctx, t1, t2, nullptr, nullptr);
+    for (size_t k = 0; k < 2; ++k) ctx->run_op(P.ops[k], &ctx->L00.g[k]);
+    int nb = reduce_blocks(ctx->n2());
+    if (ctx->real)
+        hip_check(launch_ddot(ctx->D(P.b_oovv), ctx->D(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st), "energy");
+    else
+        hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st), "energy");
+    hip_check(hipMemcpyAsync(ctx->hscal + 4, ctx->eout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "e d2h");
+}
+
+}  // namespace
+
+fscc_status fscc_update_amplitudes(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128* t2,
+                                   const fscc_c128* r1, const fscc_c128* r2, double* max_step) {
+    if (!ctx || !max_step) return FSCC_EINVAL;
+    if (!(sector == FSCC_S00 || (sector == FSCC_S01 && ctx->plan.has01) || (sector == FSCC_S02 && ctx->plan.has02)))
+        return fail(ctx, FSCC_EINVAL, "sector not available for this system");
+    Diis& D = ctx->diis[sector];
+    if ((D.n1 && (!t1 || !r1)) || (D.n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    return guarded(ctx, [&]() -> fscc_status {
+        update_enqueue(ctx, sector, t1, t2, r1, r2);
         hip_check(hipStreamSynchronize(ctx->st), "update sync");
-        int dropped = (int)ctx->hscal[1];
-        if (dropped > 0) ord.erase(ord.begin(), ord.begin() + std::min(dropped, (int)ord.size() - 1));
-        if (D.ndiis <= 1) ord.clear();
-        double mx = ctx->hscal[0];
-        switch (D.watch.observe(mx)) {
-            case DivergenceWatch::CONTINUE:
-                break;
-            case DivergenceWatch::RESET_DIIS:
-                ord.clear();   // the next step starts a fresh subspace
-                break;
-            case DivergenceWatch::GIVE_UP:
-                ord.clear();
-                D.watch.restart();
-                if (!std::isfinite(mx))
-                    return fail(ctx, FSCC_ENOCONV, "non-finite amplitude step (amplitudes left at their input values)");
-                *max_step = mx;
-                return fail(ctx, FSCC_ENOCONV,
-                            "max|step| = " + std::to_string(mx) + " grew more than " +
-                                std::to_string(DivergenceWatch::kGrowth) +
-                                "x above its smallest value again after a DIIS reset: the iteration diverges "
-                                "(amplitudes hold the last, finite, iterate)");
-        }
-        *max_step = mx;
-        return FSCC_OK;
+        return update_finish(ctx, sector, max_step);
+    });
+}
+
+fscc_status fscc_iterate(fscc_ctx* ctx, fscc_c128* t1, fscc_c128* t2, fscc_c128* r1, fscc_c128* r2, double* max_step,
+                         double* e_re, double* e_im) {
+    if (!ctx || !max_step || !e_re || !e_im) return FSCC_EINVAL;
+    if (!all_integrals(ctx)) return fail(ctx, FSCC_ESTATE, "integrals not set");
+    const int64_t n1 = ctx->n1(), n2 = ctx->n2();
+    if ((n1 && (!t1 || !r1)) || (n2 && (!t2 || !r2))) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
+    if ((n1 && (const void*)r1 == (const void*)t1) || (n2 && (const void*)r2 == (const void*)t2))
+        return fail(ctx, FSCC_EINVAL, "residual aliases amplitudes");
+    return guarded(ctx, [&]() -> fscc_status {
+        bind_io(ctx, t1, t2, r1, r2);
+        ctx->run_list(ctx->L00, ctx->prof);
+        ctx->resid00 = true;
+        update_enqueue(ctx, FSCC_S00, t1, t2, r1, r2);
+        energy_enqueue(ctx, t1, t2);
+        hip_check(hipStreamSynchronize(ctx->st), "iteration sync");
+        *e_re = ctx->hscal[4];
+        *e_im = ctx->hscal[5];
+        return update_finish(ctx, FSCC_S00, max_step);
     });
 }
 
@@ -1234,18 +1289,7 @@ fscc_status fscc_energy(fscc_ctx* ctx, const fscc_c128* t1, const fscc_c128* t2,
     if (!ctx->have_cls[IC_OOVV]) return fail(ctx, FSCC_ESTATE, "OOVV integrals not set");
     if ((ctx->n1() && !t1) || (ctx->n2() && !t2)) return fail(ctx, FSCC_EINVAL, "null amplitude buffer");
     return guarded(ctx, [&]() -> fscc_status {
-        Plan& P = ctx->plan;
-        bind_io(ctx, t1, t2, nullptr, nullptr);
-        // tau = t2 + t1 t1 (the first two operations of the plan)
-        for (size_t k = 0; k < 2; ++k) ctx->run_op(P.ops[k], &ctx->L00.g[k]);
-        int nb = reduce_blocks(ctx->n2());
-        if (ctx->real)
-            hip_check(launch_ddot(ctx->D(P.b_oovv), ctx->D(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st),
-                      "energy");
-        else
-            hip_check(launch_zdotu(ctx->B(P.b_oovv), ctx->B(P.b_tau), ctx->n2(), ctx->epart, nb, ctx->eout, ctx->st),
-                      "energy");
-        hip_check(hipMemcpyAsync(ctx->hscal + 4, ctx->eout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->st), "e d2h");
+        energy_enqueue(ctx, t1, t2);
         hip_check(hipStreamSynchronize(ctx->st), "energy sync");
         *e_re = ctx->hscal[4];
         *e_im = ctx->hscal[5];

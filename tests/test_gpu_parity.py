@@ -296,3 +296,31 @@ def test_dressed_denominators_match_oracle_intermediates(spec):
     d2 = e[:no, None, None, None] + e[None, :no, None, None] - e[None, None, no:, None] - e[None, None, None, no:]
     assert np.abs(B2 - LR.pack_t2(s, d2.astype(complex)).real).max(initial=0.0) <= 1e-14
     ctx.destroy()
+
+
+def test_iterate_equals_residual_update_energy():
+    """fscc_iterate (one synchronisation per iteration) gives bit for bit the
+    amplitudes, steps and energies of fscc_build_residual + fscc_update_amplitudes
+    + fscc_energy, over several DIIS iterations."""
+    torch = _torch()
+    s = fsgen.make_system(9, 37, 5, 0.05, 17)
+    ctx = gpu_ctx(s)
+    runs = []
+    for fused in (False, True):
+        t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+        t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+        r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+        ctx.diis_reset(6)
+        hist = []
+        for _ in range(8):
+            if fused:
+                d, E = ctx.iterate(t1, t2, r1, r2)
+            else:
+                ctx.build_residual(t1, t2, r1, r2)
+                d = ctx.update_amplitudes(t1, t2, r1, r2)
+                E = ctx.energy(t1, t2)
+            hist.append((d, E))
+        runs.append((hist, host(t1), host(t2)))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    ctx.destroy()
