@@ -1130,6 +1130,39 @@ def main():
         except F.FsccError as e:
             fs["dynamic_shift"] = {"S": S_dyn, "n": n_dyn, "status": f"failed ({e})"}
             log(f"(0h,1p) with dynamic shifts failed: {e}")
+        # split-BF16 (0h,1p): the ladder over all virtual pairs on the bf16
+        # matrix cores; one shifted solve (S = -3 Eh, n = 3, the largest shift)
+        # from zero in each precision, H_eff eigenvalue differences per state
+        try:
+            sh01 = {}
+            ctx.dynamic_shift(S_dyn, n_dyn)
+            for prec in ("fp64", "split_bf16"):
+                ctx.set_precision(prec)
+                if prec != "fp64":
+                    ctx.autotune(2)
+                u1, u2 = torch.zeros_like(s1), torch.zeros_like(s2)
+                torch.cuda.synchronize()
+                st = time.perf_counter()
+                g01 = F.solve01(ctx, u1, u2, tol=1e-10, maxit=200, ndiis=8)
+                torch.cuda.synchronize()
+                sh01[prec] = (g01, time.perf_counter() - st)
+            ctx.set_precision("fp64")
+            ctx.dynamic_shift(0.0, n_dyn)
+            g64, t64 = sh01["fp64"]
+            gbf, tbf = sh01["split_bf16"]
+            deig = np.abs(np.array(gbf["eig"]) - np.array(g64["eig"]))
+            fs["split_bf16_sector"] = {
+                "shift": [S_dyn, n_dyn], "converged": [bool(g64["converged"]), bool(gbf["converged"])],
+                "iterations": [g64["iters"], gbf["iters"]],
+                "ms_per_iteration": [round(t64 / g64["iters"] * 1e3, 4), round(tbf / gbf["iters"] * 1e3, 4)],
+                "max_abs_delta_eig_heff": float(deig.max()), "delta_eig_heff": [float(x) for x in deig]}
+            log(f"(0h,1p) split-BF16 ladder (shifted solve): {gbf['iters']} iterations at "
+                f"{tbf / gbf['iters'] * 1e3:.3f} ms vs FP64 {g64['iters']} at {t64 / g64['iters'] * 1e3:.3f} ms; "
+                f"max |d eig(H_eff)| = {deig.max():.2e} Eh")
+        except F.FsccError as e:
+            ctx.set_precision("fp64")
+            ctx.dynamic_shift(0.0, n_dyn)
+            fs["split_bf16_sector"] = {"status": f"failed ({e})"}
         # per-operation table of the (0h,1p) residual at the last amplitudes
         q1, q2 = torch.empty_like(s1), torch.empty_like(s2)
         fs["residual_ops"] = sector_op_table(ctx, lambda: ctx.build_residual(s1, s2, q1, q2, F.FSCC_S01))

@@ -486,7 +486,8 @@ fscc_status fscc_pade(int npts, const double *x, const fscc_c128 *y, int L, int 
  * ladder sum_{c<d} <ab||cd> tau_ij^cd and the two ring GEMM sets (the T2
  * part of W_mbej and sum_me t_im^ae W_mbej), which together carry most of
  * the flops of an iteration, and in FSCC_SPLIT_BF16 also the ladder's T1 part
- * Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef.  Every other step -- the remaining contractions, the reorders,
+ * Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef and the (0h,1p) sector's ladder
+ * sum_{e<f} <ab||ef> s_xj^ef (Eq. (6)).  Every other step -- the remaining contractions, the reorders,
  * the denominator (Jacobi) update, the DIIS subspace solve and the energy --
  * stays FP64 in every mode.
  *   FSCC_FP64        complex FP64 on the FP64 matrix cores.

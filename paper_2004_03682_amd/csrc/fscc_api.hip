@@ -123,10 +123,11 @@ void free_gemm(GemmDev& g) {
 // The contractions that run in split precision: the particle-particle ladder
 // and the two ring GEMM sets (W_mbej's T2 part and the ring itself); in the
 // bf16 form also the ladder's T1 part Z_ij^am = sum_{e<f} <am||ef> tau_ij^ef
-// (its split-FP32 form is slower than FP64).
+// (its split-FP32 form is slower than FP64) and the (0h,1p) sector's ladder
+// over all virtual pairs (HBM-bound: 12 instead of 16 bytes per <ab||cd>).
 bool mixed_eligible(const Op& o, int prec) {
     if (o.kind != OP_GEMM) return false;
-    if (o.name == "Z") return prec == FSCC_SPLIT_BF16;
+    if (o.name == "Z" || o.name == "S2-ladder") return prec == FSCC_SPLIT_BF16;
     return o.name == "pp-ladder" || o.name == "W.U" || o.name == "ring";
 }
 
@@ -209,19 +210,22 @@ int pick_mcfg(const Op& o) {
     return MCFG_32x32;
 }
 
-// Switch the eligible GEMM ops of the (0h,0p) residual to precision `prec`
-// (planning their split form on first use); FP64 keeps the plans.
+// Switch the eligible GEMM ops of the (0h,0p) and (0h,1p) residuals to
+// precision `prec` (planning their split form on first use); FP64 keeps the
+// plans.
 void apply_precision(fscc_ctx* c, int prec) {
-    if (prec != FSCC_FP64) {
-        std::vector<Op>& ops = *c->L00.ops;
-        for (size_t k = 0; k < ops.size(); ++k) {
-            if (!mixed_eligible(ops[k], prec)) continue;
-            GemmDev& g = c->L00.g[k];
-            if (g.mx && g.mx->prec == prec) continue;
-            fscc_ctx::free_mixed(g.mx);
-            g.mx = plan_mixed(c, ops[k], prec, pick_mcfg(ops[k]));
+    if (prec != FSCC_FP64)
+        for (OpList* L : {&c->L00, &c->L01}) {
+            if (!L->ops) continue;
+            std::vector<Op>& ops = *L->ops;
+            for (size_t k = 0; k < ops.size(); ++k) {
+                if (!mixed_eligible(ops[k], prec)) continue;
+                GemmDev& g = L->g[k];
+                if (g.mx && g.mx->prec == prec) continue;
+                fscc_ctx::free_mixed(g.mx);
+                g.mx = plan_mixed(c, ops[k], prec, pick_mcfg(ops[k]));
+            }
         }
-    }
     c->prec = prec;
 }
 
@@ -1789,9 +1793,10 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 L->g[k].mx = keep;
             }
         if (ctx->prec != FSCC_FP64)
-            for (size_t k = 0; k < ctx->L00.ops->size(); ++k) {
-                const Op& o = (*ctx->L00.ops)[k];
-                GemmDev& g = ctx->L00.g[k];
+            for (OpList* ML : {&ctx->L00, &ctx->L01})
+            for (size_t k = 0; ML->ops && k < ML->ops->size(); ++k) {
+                const Op& o = (*ML->ops)[k];
+                GemmDev& g = ML->g[k];
                 if (!mixed_eligible(o, ctx->prec) || !g.mx) continue;
                 float best_ms = time_op(o, &g);
                 for (int cfg = 0; cfg < MCFG_N; ++cfg) {
@@ -1812,6 +1817,9 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         (void)hipEventDestroy(e1);
         hip_check(hipStreamSynchronize(ctx->st), "autotune sync");
         (void)hipFree(tmp);
+        // the caller-buffer slots pointed into tmp: unbound until the next residual
+        for (size_t b = 0; b < P.bufs.size(); ++b)
+            if (caller_buffer(P.bufs[b].kind)) ctx->dbuf[b] = nullptr;
         if (!key.empty()) tune_store(ctx->tune_path, key, tune_collect(ctx));
         return FSCC_OK;
     });

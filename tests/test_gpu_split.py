@@ -169,3 +169,39 @@ def test_split_converge_then_fp64_polish_o20v120z8():
     assert q["converged"] and abs(q["E"].real - gold["E_re"]) <= 1e-10 and abs(q["E"].imag - gold["E_im"]) <= 1e-10
     assert ctx.precision() == "split_bf16"
     ctx.destroy()
+
+
+@pytest.mark.parametrize("spec", [(6, 14, 4, 0.1, 21, 5), (7, 19, 3, 0.05, 8, 6)])
+def test_split_bf16_sector01_residual_close_to_oracle(spec):
+    """In split-BF16 the (0h,1p) ladder over all virtual pairs runs on the bf16
+    matrix cores: the sector's residual stays within 2^-16 of max|R| of the
+    oracle's, and FP64 gives it back to 1e-12."""
+    torch = _torch()
+    from oracle import fs01, solver
+    no, nv, ni, sg, seed, nact = spec
+    s = fsgen.make_system(no, nv, ni, sg, seed, nact=nact)
+    be = ccsd.Dense(s)
+    r = solver.solve_ccsd(be, tol=1e-12)
+    ctx = _ctx(s, "fp64")
+    ctx.prepare_sector(dev(LR.pack_t1(s, r["t1"])), dev(LR.pack_t2(s, r["t2"])))
+    Fo = fs01.FS01(be, r["t1"], r["t2"], s.active)
+    rng = np.random.default_rng(seed)
+    s1, s2 = Fo.zeros()
+    s1 = np.where(Fo.mask1, 0.05 * (rng.normal(size=s1.shape) + 1j * rng.normal(size=s1.shape)), 0)
+    x2 = 0.05 * (rng.normal(size=s2.shape) + 1j * rng.normal(size=s2.shape))
+    s2 = np.where(Fo.mask2, x2 - x2.transpose(0, 1, 3, 2), 0)
+    R1, R2, heff = Fo.residual(s1, s2)
+    d1, d2 = dev(LR.pack_s1(s, s1)), dev(LR.pack_s2(s, s2))
+    o1, o2 = torch.empty_like(d1), torch.empty_like(d2)
+    scale = max(np.abs(R2).max(), np.abs(R1).max())
+    ctx.set_precision("split_bf16")
+    ctx.build_residual(d1, d2, o1, o2, sector=1)
+    e1 = np.abs(LR.unpack_s1(s, o1.cpu().numpy()) - R1).max() / scale
+    e2 = np.abs(LR.unpack_s2(s, o2.cpu().numpy()) - R2).max() / scale
+    print(spec, "split_bf16 (0h,1p) relative residual error %.2e %.2e" % (e1, e2), flush=True)
+    assert e1 <= 2.0 ** -16 and e2 <= 2.0 ** -16
+    assert e2 > 0.0       # the ladder did run in split precision
+    ctx.set_precision("fp64")
+    ctx.build_residual(d1, d2, o1, o2, sector=1)
+    assert np.abs(LR.unpack_s2(s, o2.cpu().numpy()) - R2).max() <= 1e-12 * scale
+    ctx.destroy()
