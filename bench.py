@@ -697,6 +697,13 @@ def reorder_table(ops, nwarm):
 
 
 PROFILE_REPS = 5
+TILE_NAMES = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall",
+              8: "reduction", 9: "32x64", 10: "64x32", 11: "dot", 12: "64x64r", 13: "64x32r"}
+
+
+def tile_str(c, b, sp):
+    """Name of a GEMM configuration (fscc_gemm_config): tile, 3M/DB flags, K depth, split-K."""
+    return f"{TILE_NAMES[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}/bk{b}{'/splitK' if sp else ''}"
 
 
 def profile_ops(args):
@@ -773,6 +780,8 @@ def profile_ops(args):
             o = ops[k]
             rows.append({"k": k, "op": o["name"], "kind": o["kind"], "bytes": o["bytes"], "flops": o["flops"],
                          "reps": PROFILE_REPS, "ms_per_call": ms, "GB_per_s": o["bytes"] / (ms * 1e-3) / 1e9})
+            if o["kind"] == "gemm":
+                rows[-1]["tile"] = tile_str(*ctx.gemm_config(k))
             log(f"  {o['name']:24s} {ms * 1e3:8.1f} us  {rows[-1]['GB_per_s']:7.1f} GB/s"
                 + (f"  {o['flops'] / (ms * 1e-3) / 1e12:6.2f} TFLOP/s" if o["flops"] else ""))
     torch.cuda.synchronize()
@@ -849,6 +858,30 @@ def summarize_ops(args):
                  f"{tot_alg / (tot_ms * 1e-3) / 1e9:.0f} | {tot_alg / (tot_ms * 1e-3) / 1e9 / PEAK_HBM:.2f} |")
     print(f"calibration: fetch x {fscale:.4f}, write x {wscale:.4f} (1 GiB device copy)")
     print("\n".join(lines))
+    if args.traffic_out and prof.get("precision", "fp64") == "fp64":
+        # HBM bytes per launch of each GEMM's grouped kernel (not its split-K
+        # pass), for the roofline object of the bench line
+        d = json.load(open(args.traffic_out)) if os.path.exists(args.traffic_out) else {}
+        for r, fs, ws in zip(rows, fw, ww):
+            if r["kind"] != "gemm" or "tile" not in r:
+                continue
+            mf = [x for x in fs if _short(x[1]).startswith("k_z") and "splitk" not in x[1]]
+            mw = [x for x in ws if _short(x[1]).startswith("k_z") and "splitk" not in x[1]]
+            if not mf or not mw:
+                continue
+            fk = sum(x[3].get("FETCH_SIZE", 0.0) for x in mf) / len(mf)
+            wk = sum(x[3].get("WRITE_SIZE", 0.0) for x in mw) / len(mw)
+            ent = d.setdefault(r["op"], {})
+            if ent.get("kernels_sha256") != kernel_source_sha():
+                ent["tiles"] = {}          # counters of other library sources do not carry over
+            ent.update({"kernel": _short(mf[0][1]), "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+                        "algorithmic_bytes_per_launch": r["bytes"], "kernels_sha256": kernel_source_sha()})
+            ent.setdefault("tiles", {})
+            ent["tiles"][r["tile"]] = {"workgroups": mf[0][2], "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
+                                       "dispatches": len(mf),
+                                       "bytes_per_launch": int((fk * fscale + wk * wscale) * 1024)}
+        with open(args.traffic_out, "w") as f:
+            json.dump(d, f, indent=1)
 
 
 def main():
@@ -875,6 +908,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "split_bf16", "split_fp32"),
                     help="--profile-ops: precision of the split-eligible GEMMs")
     ap.add_argument("--tune-file", help="autotune result cache file for --profile-ops")
+    ap.add_argument("--traffic-out", help="--summarize-ops: also store the GEMM kernels' HBM bytes per launch here")
     ap.add_argument("--summarize-ops", nargs=5,
                     metavar=("OPS_JSON", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="print the per-operation traffic table from the counter runs")
@@ -945,9 +979,7 @@ def main():
     setup["autotune_cached_s"] = round(time.perf_counter() - t1_, 3)
     setup["autotune_cache_hit"] = ctx.autotune_cached()
     ctx.tune_cache(None)
-    names = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "16x64", 6: "skinny64x32", 7: "tall", 8: "reduction", 9: "32x64", 10: "64x32", 11: "dot", 12: "64x64r", 13: "64x32r"}
-    tuned = {n: f"{names[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}/bk{b}{'/splitK' if sp else ''}"
-             for n, c, b, sp in ctx.gemm_configs()}
+    tuned = {n: tile_str(c, b, sp) for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {setup['autotune_s']:.1f}s (from the cache: {setup['autotune_cached_s']:.3f}s): " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))
 

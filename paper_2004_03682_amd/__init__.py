@@ -381,6 +381,12 @@ class Context:
         """Reorders in destination storage order (0) or by 16 x 16 destination tiles (1)."""
         self._check(lib().fscc_gather_order(self._h, int(tiled)))
 
+    def gemm_config(self, k):
+        """(tile cfg id with the 3M / DB flags, bk, split) of operation k (cfg -1: not a GEMM)."""
+        c, b, sp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(lib().fscc_gemm_config(self._h, int(k), ctypes.byref(c), ctypes.byref(b), ctypes.byref(sp)))
+        return c.value, b.value, sp.value
+
     def gemm_configs(self):
         """[(op name, tile cfg id, bk, split)] for every GEMM operation."""
         out = []
