@@ -884,6 +884,59 @@ def summarize_ops(args):
             json.dump(d, f, indent=1)
 
 
+_TILE_OF = {(64, 64, 2, 2): 0, (128, 16, 4, 1): 1, (16, 128, 1, 4): 2, (32, 32, 2, 2): 3, (64, 16, 4, 1): 4,
+            (16, 64, 1, 4): 5, (32, 64, 2, 2): 9, (64, 32, 2, 2): 10, (64, 64, 4, 1): 12, (64, 32, 4, 1): 13}
+
+
+def summarize_ladder_candidates(args):
+    """HBM bytes per launch of every pp-ladder tile the autotuner dispatches
+    (the grouped GEMM with ROLE = 1 is the ladder's alone), from counter runs
+    of an autotuning program: per template instance and grid, the smaller grid
+    being the unsplit and the larger the split-K launch.  Stored under
+    'pp-ladder' in --traffic-out, beside the tile the profile run chose."""
+    fetch, write, cfetch, cwrite = args.summarize_ladder_candidates
+    cf = [d for d in _read_counters(cfetch, {"FETCH_SIZE"}) if "copyBuffer" in d[1]]
+    cw = [d for d in _read_counters(cwrite, {"WRITE_SIZE"}) if "copyBuffer" in d[1]]
+    fscale = float(1 << 20) / (sum(d[3]["FETCH_SIZE"] for d in cf) / len(cf))
+    wscale = float(1 << 20) / (sum(d[3]["WRITE_SIZE"] for d in cw) / len(cw))
+    groups = {}
+    for path, cnt in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
+        for d in _read_counters(path, {cnt}):
+            k = _short(d[1])
+            if not k.startswith("k_zgemm<"):
+                continue
+            t = [x.strip() for x in k[len("k_zgemm<"):-1].split(",")]
+            if len(t) < 10 or t[7] != "1":
+                continue
+            key = (int(t[0]), int(t[1]), int(t[2]), int(t[3]), int(t[4]), t[8] == "true", t[9] == "true")
+            g = groups.setdefault(key, {}).setdefault(d[2], {"FETCH_SIZE": [], "WRITE_SIZE": []})
+            g[cnt].append(d[3].get(cnt, 0.0))
+    d = json.load(open(args.traffic_out)) if os.path.exists(args.traffic_out) else {}
+    ent = d.setdefault("pp-ladder", {})
+    if ent.get("kernels_sha256") != kernel_source_sha():
+        ent.clear()
+    ent.update({"kernels_sha256": kernel_source_sha(), "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4)})
+    tiles = ent.setdefault("tiles", {})
+    rows = []
+    for (bm, bn, wm, wn, bk, m3, db), by_grid in groups.items():
+        grids = sorted(by_grid)
+        for gi, grid in enumerate(grids):
+            f, w = by_grid[grid]["FETCH_SIZE"], by_grid[grid]["WRITE_SIZE"]
+            if not f or not w:
+                continue
+            c = _TILE_OF[(bm, bn, wm, wn)] | (256 if m3 else 0) | (512 if db else 0)
+            name = tile_str(c, bk, gi > 0)
+            fk, wk = sum(f) / len(f), sum(w) / len(w)
+            tiles.setdefault(name, {"workgroups": grid, "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
+                                    "dispatches": len(f), "bytes_per_launch": int((fk * fscale + wk * wscale) * 1024)})
+            rows.append((tiles[name]["bytes_per_launch"], name, grid, len(f)))
+    with open(args.traffic_out, "w") as fo:
+        json.dump(d, fo, indent=1)
+    print("| tile | workgroups | dispatches | HBM bytes per launch |\n|---|---|---|---|")
+    for b, name, grid, n in sorted(rows):
+        print(f"| {name} | {grid} | {n} | {b / 1e9:.2f} GB |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -912,7 +965,13 @@ def main():
     ap.add_argument("--summarize-ops", nargs=5,
                     metavar=("OPS_JSON", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="print the per-operation traffic table from the counter runs")
+    ap.add_argument("--summarize-ladder-candidates", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="store the HBM bytes per launch of every autotuned pp-ladder tile in --traffic-out")
     args = ap.parse_args()
+    if args.summarize_ladder_candidates:
+        summarize_ladder_candidates(args)
+        return
     if args.summarize_ops:
         summarize_ops(args)
         return
