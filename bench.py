@@ -196,8 +196,10 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
         lad = ops["pp-ladder"]
         lad_ms = lad["ms"] / max(1, lad["calls"])
         split_ops = {}
-        for n in cfgs:                      # the operations that run split in this mode
-            o = ops[n]
+        for n in cfgs:                      # the (0h,0p) operations that run split in this mode
+            o = ops.get(n)
+            if o is None or o["calls"] == 0:
+                continue                    # an operation of another sector
             ms = o["ms"] / max(1, o["calls"])
             split_ops[n] = {"ms_per_call": round(ms, 4),
                             "fp64_equivalent_tflops": round(o["flops"] / (ms * 1e-3) / 1e12, 2),
