@@ -704,8 +704,9 @@ TILE_NAMES = {0: "64x64", 1: "128x16", 2: "16x128", 3: "32x32", 4: "64x16", 5: "
 
 
 def tile_str(c, b, sp):
-    """Name of a GEMM configuration (fscc_gemm_config): tile, 3M/DB flags, K depth, split-K."""
-    return f"{TILE_NAMES[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}/bk{b}{'/splitK' if sp else ''}"
+    """Name of a GEMM configuration (fscc_gemm_config): tile, 3M/DB/DL flags, K depth, split-K."""
+    return (f"{TILE_NAMES[c & 255]}{'/3M' if c & 256 else ''}{'/DB' if c & 512 else ''}{'/DL' if c & 1024 else ''}"
+            f"/bk{b}{'/splitK' if sp else ''}")
 
 
 def profile_ops(args):
@@ -815,7 +816,7 @@ def _windows(disp, nops):
 
 
 def _short(kernel):
-    k = kernel.split("(")[0].replace("void ", "").replace("fscc::", "")
+    k = kernel.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("fscc::", "")
     return k
 
 
@@ -905,12 +906,18 @@ def summarize_ladder_candidates(args):
     for path, cnt in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
         for d in _read_counters(path, {cnt}):
             k = _short(d[1])
-            if not k.startswith("k_zgemm<"):
+            if k.startswith("k_zgemm<"):         # BM, BN, WM, WN, BK, TA, TB, ROLE, M3, DB
+                t = [x.strip() for x in k[len("k_zgemm<"):-1].split(",")]
+                if len(t) < 10 or t[7] != "1":
+                    continue
+                key = (int(t[0]), int(t[1]), int(t[2]), int(t[3]), int(t[4]), t[8] == "true", 512 if t[9] == "true" else 0)
+            elif k.startswith("k_zgemm_dl<"):    # BM, BN, WM, WN, S, TA, TB, ROLE, M3 (16-deep slices)
+                t = [x.strip() for x in k[len("k_zgemm_dl<"):-1].split(",")]
+                if len(t) < 9 or t[7] != "1":
+                    continue
+                key = (int(t[0]), int(t[1]), int(t[2]), int(t[3]), 16, t[8] == "true", 1024)
+            else:
                 continue
-            t = [x.strip() for x in k[len("k_zgemm<"):-1].split(",")]
-            if len(t) < 10 or t[7] != "1":
-                continue
-            key = (int(t[0]), int(t[1]), int(t[2]), int(t[3]), int(t[4]), t[8] == "true", t[9] == "true")
             g = groups.setdefault(key, {}).setdefault(d[2], {"FETCH_SIZE": [], "WRITE_SIZE": []})
             g[cnt].append(d[3].get(cnt, 0.0))
     d = json.load(open(args.traffic_out)) if os.path.exists(args.traffic_out) else {}
@@ -920,13 +927,13 @@ def summarize_ladder_candidates(args):
     ent.update({"kernels_sha256": kernel_source_sha(), "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4)})
     tiles = ent.setdefault("tiles", {})
     rows = []
-    for (bm, bn, wm, wn, bk, m3, db), by_grid in groups.items():
+    for (bm, bn, wm, wn, bk, m3, form), by_grid in groups.items():
         grids = sorted(by_grid)
         for gi, grid in enumerate(grids):
             f, w = by_grid[grid]["FETCH_SIZE"], by_grid[grid]["WRITE_SIZE"]
             if not f or not w:
                 continue
-            c = _TILE_OF[(bm, bn, wm, wn)] | (256 if m3 else 0) | (512 if db else 0)
+            c = _TILE_OF[(bm, bn, wm, wn)] | (256 if m3 else 0) | form
             name = tile_str(c, bk, gi > 0)
             fk, wk = sum(f) / len(f), sum(w) / len(w)
             tiles.setdefault(name, {"workgroups": grid, "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
@@ -1100,7 +1107,8 @@ def main():
     dom_3m = "/3M" in tuned.get(dom["name"], "")
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64, 4), "traffic": traffic,
-            "kernel": "k_zgemm (grouped complex FP64 MFMA GEMM), op '%s'" % dom["name"],
+            "kernel": "%s (grouped complex FP64 MFMA GEMM), op '%s'" % (
+                "k_zgemm_dl" if "/DL" in tuned.get(dom["name"], "") else "k_zgemm", dom["name"]),
             "flops_per_launch": dom["flops"], "avg_launch_ms": round(per_launch_s * 1e3, 4),
             # achieved counts the algorithmic 8 real flops per complex multiply-add; the
             # three-product form issues 6 of them to the matrix cores

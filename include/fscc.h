@@ -333,8 +333,8 @@ fscc_status fscc_op_run(fscc_ctx *ctx, int k, int reps);
  * in a split precision (fscc_set_precision) level 1 also times the split
  * kernel's tile shapes of the split operations; level 2 times only those;
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
- * shapes).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) of
- * every eligible tile.  Level 1 also times each reorder (gather) of a complex context in
+ * shapes).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) and
+ * the direct-to-LDS form (FSCC_CFG_DL) of every eligible tile.  Level 1 also times each reorder (gather) of a complex context in
  * destination order, by 16 x 16 destination tiles and by affine tiles (see
  * fscc_gather_order) and keeps the fastest.
  * Results are numerically equivalent (summation order may change). */
@@ -386,9 +386,21 @@ fscc_status fscc_gather_order(fscc_ctx *ctx, int tiled);
  * The result is the same (same summation order). */
 #define FSCC_CFG_DB 512
 
+/* MFMA tile ids may instead carry this bit: the K slices are loaded from
+ * device memory straight into LDS (one complex element per lane and load,
+ * no register staging) into two LDS stages: the next slice arrives while the
+ * matrix cores work on the current one, and the smaller register and LDS
+ * footprint lets more workgroups share a CU.
+ * Needs bk = 16 and one of the tiles 0: 64x64, 3: 32x32, 4: 64x16,
+ * 5: 16x64, 9: 32x64, 10: 64x32, 12: 64x64 stacked, 13: 64x32 stacked;
+ * FSCC_EINVAL otherwise or together with FSCC_CFG_DB.  The result is the
+ * same (same summation order). */
+#define FSCC_CFG_DL 1024
+
 /* Chosen configuration of operation k (cfg = tile shape id, with
- * FSCC_CFG_3M set for a three-product MFMA tile and FSCC_CFG_DB for a
- * double-buffered one, or -1 if k is not a GEMM;
+ * FSCC_CFG_3M set for a three-product MFMA tile, FSCC_CFG_DB for a
+ * double-buffered one and FSCC_CFG_DL for a direct-to-LDS one, or -1 if k
+ * is not a GEMM;
  * bk = K depth; split = 1 if split along K); host outputs. */
 fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int *split);
 
@@ -402,7 +414,8 @@ fscc_status fscc_gemm_config(const fscc_ctx *ctx, int k, int *cfg, int *bk, int 
  * vector-ALU forms 6: skinny (64x32 output blocks), 7: tall (needs !tA,
  * K <= 64, K*N <= 1024), 8: reduction (needs !tB, M <= 8, N <= 256),
  * 11: dot (needs !tA, tB, M <= 8; every B row streamed once);
- * an MFMA tile id | FSCC_CFG_3M selects the three-product complex form;
+ * an MFMA tile id | FSCC_CFG_3M selects the three-product complex form,
+ * | FSCC_CFG_DB or | FSCC_CFG_DL the LDS staging form (see above);
  * -1 = cost model (three-product form).  FSCC_EINVAL if the shape does not
  * fit the form.
  * bk = 16 or 32, allow_split = 1 permits split-K.  beta is 0 or 1.

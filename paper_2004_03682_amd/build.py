@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfscc.so")
 SOURCES = ["fscc_api.hip", "batch_api.hip", "noalloc_api.hip", "kernels.hip", "kernels_real.hip", "kernels_split.hip",
-           "mlp.hip", "plan_ccsd.cpp", "host_linalg.cpp"]
+           "kernels_dl.hip", "mlp.hip", "plan_ccsd.cpp", "host_linalg.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1423,7 +1423,7 @@ namespace {
 // of the context's plans (kind, name, sizes, GEMM problem shapes); an entry
 // lists per operation the chosen form: GEMM [1, tile, bk, split, 3M, DB,
 // split-precision tile or -1], reorder [0, traversal], other [2].
-constexpr int kTuneVersion = 5;
+constexpr int kTuneVersion = 6;
 
 std::vector<OpList*> tune_lists(fscc_ctx* c) { return {&c->L00, &c->L01, &c->L02}; }
 
@@ -1473,7 +1473,7 @@ std::vector<std::array<int, 7>> tune_collect(fscc_ctx* c) {
             const Op& o = (*L->ops)[k];
             if (o.kind == OP_GEMM) {
                 const GemmDev& g = L->g[k];
-                out.push_back({1, g.cfg, g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.db ? 1 : 0, g.mx ? g.mx->cfg : -1});
+                out.push_back({1, g.cfg, g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.lds, g.mx ? g.mx->cfg : -1});
             } else if (o.kind == OP_GATHER) {
                 out.push_back({0, o.use_rtiles ? 2 : o.use_gtiles ? 1 : 0, 0, 0, 0, 0, -1});
             } else {
@@ -1576,7 +1576,9 @@ bool tune_apply(fscc_ctx* c, const std::vector<std::array<int, 7>>& ops) {
             if (a[0] != kind) return false;
             if (kind == 1) {
                 if (!cfg_ok(o, a[1], c->real) || (a[2] != 16 && a[2] != 32)) return false;
-                if (a[5] && (c->real || a[2] != 16 || !zcfg_has_db(a[1]))) return false;
+                if (a[5] < LDS_STAGED || a[5] > LDS_DIRECT) return false;
+                if (a[5] != LDS_STAGED && (c->real || a[2] != 16)) return false;
+                if ((a[5] == LDS_DOUBLE && !zcfg_has_db(a[1])) || (a[5] == LDS_DIRECT && !zcfg_has_dl(a[1]))) return false;
                 if (a[6] >= MCFG_N) return false;
             } else if (kind == 0) {
                 if (a[1] < 0 || a[1] > 2 || (a[1] == 2 && !o.d_rtiles) || (a[1] == 1 && !o.d_gtiles)) return false;
@@ -1599,7 +1601,7 @@ bool tune_apply(fscc_ctx* c, const std::vector<std::array<int, 7>>& ops) {
                 g.mx = nullptr;
                 free_gemm(g);
                 plan_gemm(c, o, g, a[1], a[2], a[3] != 0, a[4] != 0);
-                g.db = a[5] != 0;
+                g.lds = a[5];
                 g.mx = keep;
                 if (a[6] >= 0 && g.mx && g.mx->cfg != a[6]) {
                     const int prec = g.mx->prec;
@@ -1695,8 +1697,8 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
         const bool tlog = std::getenv("FSCC_AUTOTUNE_LOG") != nullptr;
         auto note = [&](const Op& o, const GemmDev& g, float ms) {
             if (tlog)
-                std::fprintf(stderr, "autotune %-16s cfg %2d bk %d split %d m3 %d db %d: %.4f ms\n", o.name.c_str(), g.cfg,
-                             g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.db ? 1 : 0, ms);
+                std::fprintf(stderr, "autotune %-16s cfg %2d bk %d split %d m3 %d lds %d: %.4f ms\n", o.name.c_str(), g.cfg,
+                             g.bk, g.split ? 1 : 0, g.m3 ? 1 : 0, g.lds, ms);
         };
         auto time_op = [&](const Op& o, const GemmDev* g) -> float {
             ctx->run_op(o, g);
@@ -1761,10 +1763,14 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                                     continue;
                                 }
                             }
-                            // single- and double-buffered LDS forms of the same plan
-                            const bool try_db = !ctx->real && bk == 16 && zcfg_has_db(cfg);
-                            for (int db = 0; db <= (try_db ? 1 : 0); ++db) {
-                                cand.db = db == 1;
+                            // the LDS staging forms of the same plan: through registers,
+                            // double-buffered, direct-to-LDS ring
+                            for (int lds = LDS_STAGED; lds <= LDS_DIRECT; ++lds) {
+                                if (lds != LDS_STAGED &&
+                                    (ctx->real || bk != 16 ||
+                                     (lds == LDS_DOUBLE && !zcfg_has_db(cfg)) || (lds == LDS_DIRECT && !zcfg_has_dl(cfg))))
+                                    continue;
+                                cand.lds = lds;
                                 float ms = time_op(o, &cand);
                                 note(o, cand, ms);
                                 if (ms < best_ms) {
@@ -1778,7 +1784,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                 if (best.m3) {   // the winner's tile with the four-product complex form
                     GemmDev alt;
                     plan_gemm(ctx, o, alt, best.cfg, best.bk, best.split, false);
-                    alt.db = best.db;
+                    alt.lds = best.lds;
                     float ms = time_op(o, &alt);
                     note(o, alt, ms);
                     if (ms < best_ms) {
@@ -2051,7 +2057,9 @@ fscc_status fscc_gemm_config(const fscc_ctx* ctx, int k, int* cfg, int* bk, int*
     int j;
     if (!op_ref(const_cast<fscc_ctx*>(ctx), k, &L, &j)) return FSCC_EINVAL;
     const GemmDev& g = L->g[j];
-    *cfg = (*L->ops)[j].kind == OP_GEMM ? (g.cfg | (g.m3 ? FSCC_CFG_3M : 0) | (g.db ? FSCC_CFG_DB : 0)) : -1;
+    *cfg = (*L->ops)[j].kind == OP_GEMM ? (g.cfg | (g.m3 ? FSCC_CFG_3M : 0) | (g.lds == LDS_DOUBLE ? FSCC_CFG_DB : 0) |
+                                           (g.lds == LDS_DIRECT ? FSCC_CFG_DL : 0))
+                                        : -1;
     *bk = g.bk;
     *split = g.split ? 1 : 0;
     return FSCC_OK;
@@ -2062,9 +2070,11 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
                        int allow_split, void* hip_stream) {
     const bool m3 = cfg >= 0 && (cfg & FSCC_CFG_3M);
     const bool db = cfg >= 0 && (cfg & FSCC_CFG_DB);
-    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB);
+    const bool dl = cfg >= 0 && (cfg & FSCC_CFG_DL);
+    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB | FSCC_CFG_DL);
     if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
-    if (db && (bk != 16 || !zcfg_has_db(cfg))) return FSCC_EINVAL;
+    if (db && (dl || bk != 16 || !zcfg_has_db(cfg))) return FSCC_EINVAL;
+    if (dl && (bk != 16 || !zcfg_has_dl(cfg))) return FSCC_EINVAL;
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
     if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
@@ -2084,14 +2094,14 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
         if (cfg >= 0 && !cfg_ok(o, cfg)) return FSCC_EINVAL;
         GemmDev g;
         plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o) : cfg, bk, allow_split != 0, cfg < 0 || m3);
-        g.db = db;
+        g.lds = dl ? LDS_DIRECT : db ? LDS_DOUBLE : LDS_STAGED;
         hipError_t e;
         if (!g.split) {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs, g.tiles,
-                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.db);
+                             g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.lds);
         } else {
             e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.db);
+                             g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, c->st, 0, nullptr, g.maxM, g.m3, g.lds);
             if (e == hipSuccess)
                 e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha_re, alpha_im, o.beta, c->st);
         }

@@ -864,9 +864,13 @@ bool zcfg_has_db(int cfg) {
 
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
-                        int cB, hipStream_t st, int role, const int* active, int max_m, bool m3, bool db) {
+                        int cB, hipStream_t st, int role, const int* active, int max_m, bool m3, int lds) {
     if (ntiles <= 0) return hipSuccess;
-    if (db) {
+    if (lds == LDS_DIRECT) {
+        if (bk != 16 || !zcfg_has_dl(cfg)) return hipErrorInvalidValue;
+        return launch_zgemm_dl(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active, m3);
+    }
+    if (lds == LDS_DOUBLE) {
         if (bk != 16 || !zcfg_has_db(cfg)) return hipErrorInvalidValue;
         return m3 ? launch_db<true>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active)
                   : launch_db<false>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);

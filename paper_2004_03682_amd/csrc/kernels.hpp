@@ -54,13 +54,23 @@ void zcfg_tile(int cfg, int* bm, int* bn);
 //   max_m: largest M of the problems (used by ZCFG_RED and ZCFG_DOT only, 1..8).
 //   m3: MFMA tiles form the complex product from three real products (3M)
 //   instead of four (4M); ignored by the vector-ALU forms.
-//   db: double-buffered LDS (two buffer pairs, one barrier per slice); only
-//   bk = 16 and the tiles for which zcfg_has_db() holds.
+//   lds: how an MFMA tile stages its K slices in LDS: LDS_STAGED (through
+//   registers, one buffer pair), LDS_DOUBLE (two buffer pairs, one barrier per
+//   slice; bk = 16 and the tiles for which zcfg_has_db() holds) or
+//   LDS_DIRECT (direct-to-LDS loads through a ring of stages; bk = 16 and the
+//   tiles for which zcfg_has_dl() holds).
+enum { LDS_STAGED = 0, LDS_DOUBLE = 1, LDS_DIRECT = 2 };
 hipError_t launch_zgemm(int cfg, int bk, bool tA, bool tB, const double2* A, const double2* B, double2* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
                         int cB, hipStream_t st, int role = 0, const int* active = nullptr, int max_m = 0,
-                        bool m3 = false, bool db = false);
+                        bool m3 = false, int lds = LDS_STAGED);
 bool zcfg_has_db(int cfg);
+// The same GEMM with direct-to-LDS loads through a ring of LDS stages
+// (kernels_dl.hip); 16-deep slices, the tiles for which zcfg_has_dl() holds.
+hipError_t launch_zgemm_dl(int cfg, bool tA, bool tB, const double2* A, const double2* B, double2* C,
+                           const ZProb* probs, const ZTile* tiles, int ntiles, double ar, double ai, int beta, int cA,
+                           int cB, hipStream_t st, int role, const int* active, bool m3);
+bool zcfg_has_dl(int cfg);
 
 // ---- compensated mixed-precision GEMM (kernels_split.hip)
 // element (r, k) of a rows x cols operand: src[src_off + r*ld + k] (trans = 0)

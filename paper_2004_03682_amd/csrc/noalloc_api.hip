@@ -62,8 +62,10 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
                                double alpha_re, double alpha_im, int beta, int allow_split, void* hip_stream) {
     const bool m3 = cfg >= 0 && (cfg & FSCC_CFG_3M);
     const bool db = cfg >= 0 && (cfg & FSCC_CFG_DB);
-    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB);
-    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32) || (db && (bk != 16 || !zcfg_has_db(cfg))))
+    const bool dl = cfg >= 0 && (cfg & FSCC_CFG_DL);
+    if (cfg >= 0) cfg &= ~(FSCC_CFG_3M | FSCC_CFG_DB | FSCC_CFG_DL);
+    if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32) ||
+        (db && (dl || bk != 16 || !zcfg_has_db(cfg))) || (dl && (bk != 16 || !zcfg_has_dl(cfg))))
         return free_call_fail(FSCC_EINVAL, "fscc_zgemm_noalloc: bad size, tile id or K depth");
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B))))
         return free_call_fail(FSCC_EINVAL, "fscc_zgemm_noalloc: null operand");
@@ -101,7 +103,7 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
         hip_check(scratch_address(dev, &base), "hipGetSymbolAddress(scratch)");
         unsigned char* p = (unsigned char*)base;
         GemmDev g = h.g;
-        g.db = db;
+        g.lds = dl ? LDS_DIRECT : db ? LDS_DOUBLE : LDS_STAGED;
         g.probs = (ZProb*)p;
         p += align256(h.pr.size() * sizeof(ZProb));
         g.tiles = (ZTile*)p;
@@ -121,10 +123,10 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
         if (g.ntiles > 0) {
             if (!g.split) {
                 e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, (double2*)C, g.probs,
-                                 g.tiles, g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.db);
+                                 g.tiles, g.ntiles, alpha_re, alpha_im, o.beta, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.lds);
             } else {
                 e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, (const double2*)A, (const double2*)B, g.work, g.probs, g.tiles,
-                                 g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.db);
+                                 g.ntiles, 1.0, 0.0, 0, o.cA, o.cB, st, 0, nullptr, g.maxM, g.m3, g.lds);
                 if (e == hipSuccess)
                     e = launch_splitk_reduce((double2*)C, g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha_re, alpha_im,
                                              o.beta, st);

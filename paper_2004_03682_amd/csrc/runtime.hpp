@@ -60,7 +60,7 @@ struct GemmDev {
     int maxS = 0;    // largest number of K chunks of a problem (split)
     int maxM = 0;   // largest M over the problems (ZCFG_RED picks its register tile by it)
     bool m3 = false;   // MFMA tiles: complex product from three real products
-    bool db = false;   // MFMA tiles: double-buffered LDS (16-deep slices)
+    int lds = LDS_STAGED;   // MFMA tiles: how K slices are staged in LDS (launch_zgemm)
     double2* work = nullptr;
     MixedDev* mx = nullptr;   // present for the ops that may run in split precision
 };
@@ -360,10 +360,10 @@ struct fscc_ctx {
                     e = run_mixed(o, *g.mx, Ap, B(o.src2), Cp, beta);
                 } else if (!g.split) {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.db);
+                                     o.alpha.real(), o.alpha.imag(), beta, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.lds);
                 } else {
                     e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, B(o.src2), g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.db);
+                                     0.0, 0, o.cA, o.cB, st, g.role, d_active, g.maxM, g.m3, g.lds);
                     if (e == hipSuccess)
                         e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(),
                                                  beta, st, d_active);
@@ -440,9 +440,9 @@ struct fscc_ctx {
         double2* Cp = C_override ? C_override : B(o.dst);
         if (!g.split)
             return launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(),
-                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.db);
+                                o.alpha.imag(), beta, o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.lds);
         hipError_t e = launch_zgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, g.work, g.probs, g.tiles, g.ntiles, 1.0, 0.0, 0,
-                                    o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.db);
+                                    o.cA, o.cB, st, g.role, nullptr, g.maxM, g.m3, g.lds);
         if (e == hipSuccess)
             e = launch_splitk_reduce(Cp, g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), o.alpha.imag(), beta, st);
         return e;

@@ -1,7 +1,7 @@
 """Kernel-level parity of the grouped complex FP64 GEMM forms (through the C
 ABI) against numpy: every MFMA tile shape in the four- and three-product
-complex forms, K depth, transpose/conjugate flag
-and split-K choice, the vector-ALU skinny, tall, reduction and dot forms, with
+complex forms, K depth, transpose/conjugate flag, LDS staging form (through
+registers, double-buffered, direct-to-LDS ring) and split-K choice, the vector-ALU skinny, tall, reduction and dot forms, with
 ragged sizes (not multiples of any tile), K = 0 and accumulation (beta = 1)."""
 import itertools
 
@@ -16,6 +16,9 @@ MFMA_TILES = (0, 1, 2, 3, 4, 5, 9, 10, 12, 13)   # 0-5, 9 (32x64), 10 (64x32), 1
 DB_TILES = (3, 4, 5, 9, 10, 13)
 CFGS = MFMA_TILES + tuple(c | M3 for c in MFMA_TILES) + (6,)   # 4M and 3M MFMA tiles; 6 = skinny (vector ALUs)
 DB_CFGS = tuple(c | DB for c in DB_TILES) + tuple(c | DB | M3 for c in DB_TILES)
+DL = 1024   # FSCC_CFG_DL: direct-to-LDS loads through a ring of LDS stages (16-deep slices)
+DL_TILES = (0, 3, 4, 5, 9, 10, 12, 13)
+DL_CFGS = tuple(c | DL for c in DL_TILES) + tuple(c | DL | M3 for c in DL_TILES)
 
 
 def _rand(rng, *shape):
@@ -67,6 +70,31 @@ def test_zgemm_double_buffered_forms(cfg):
     for (M, N, K, beta) in [(7, 34, 3000, 0), (300, 200, 1800, 1), (9, 11, 0, 1)]:
         err = _run(M, N, K, 0, 1, 0, 0, cfg, 16, True, beta)
         assert err < 1e-13, (cfg, M, N, K, beta, err)
+
+
+@pytest.mark.parametrize("cfg", DL_CFGS)
+def test_zgemm_direct_to_lds_forms(cfg):
+    """The direct-to-LDS forms: ragged sizes, every transpose/conjugate flag,
+    K from below one 16-deep slice to many turns of the stage ring (its
+    prologue, wrap-around and the clamped loads past the last slice), the
+    zeroed k past K of a last partial slice, split-K and K = 0."""
+    for (tA, tB, cA, cB) in [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 0, 1), (1, 1, 1, 1)]:
+        for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 16), (33, 65, 17), (130, 131, 32), (40, 50, 33),
+                          (19, 77, 48), (65, 20, 49), (31, 129, 64), (50, 50, 95), (1017, 1, 300), (3, 48, 700)]:
+            err = _run(M, N, K, tA, tB, cA, cB, cfg, 16, False, beta=(M % 2))
+            assert err < 1e-13, (cfg, tA, tB, cA, cB, M, N, K, err)
+    for (M, N, K, beta) in [(7, 34, 3000, 0), (300, 200, 1800, 1), (9, 11, 0, 1), (9, 11, 0, 0)]:
+        err = _run(M, N, K, 0, 1, 0, 0, cfg, 16, True, beta)
+        assert err < 1e-13, (cfg, M, N, K, beta, err)
+
+
+def test_direct_to_lds_form_needs_an_eligible_tile():
+    import torch
+    import paper_2004_03682_amd as F
+    a = torch.zeros((4, 4), dtype=torch.complex128, device="cuda")
+    for cfg, bk in ((1 | DL, 16), (6 | DL, 16), (9 | DL, 32), (9 | DL | DB, 16)):
+        with pytest.raises(F.FsccError):
+            F.zgemm(a, a, a, 4, 4, 4, 4, 4, 4, cfg=cfg, bk=bk)
 
 
 def test_double_buffered_form_needs_an_eligible_tile():
