@@ -951,6 +951,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=1, choices=(1, 2),
+                    help="residual operations on one stream or two overlapping streams (fscc_set_streams)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fs01", action="store_true", help="skip the (0h,1p) and (0h,2p) sectors")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision study")
@@ -1047,6 +1049,7 @@ def main():
     setup["autotune_cached_s"] = round(time.perf_counter() - t1_, 3)
     setup["autotune_cache_hit"] = ctx.autotune_cached()
     ctx.tune_cache(None)
+    ctx.set_streams(args.streams)
     tuned = {n: tile_str(c, b, sp) for n, c, b, sp in ctx.gemm_configs()}
     log(f"autotuned GEMM tiles in {setup['autotune_s']:.1f}s (from the cache: {setup['autotune_cached_s']:.3f}s): " +
         ", ".join(f"{k}={tuned[k]}" for k in ("pp-ladder", "ring", "W.U", "Z") if k in tuned))

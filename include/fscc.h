@@ -151,6 +151,22 @@ fscc_status fscc_set_integrals(fscc_ctx *ctx, fscc_iclass cls, const fscc_c128 *
  * fscc_set_integrals calls. */
 fscc_status fscc_set_validation(fscc_ctx *ctx, int nsample);
 
+/* Streams of the residual evaluations (the block operations of the
+ * algorithm-design section, executed as a dependency graph): n = 1 runs every
+ * operation in order on the context's stream; n = 2 puts the GEMMs bound by
+ * the matrix cores on the context's stream and the reorders, elementwise
+ * operations and memory-bound GEMMs on a second stream of the library's
+ * (default priority), with an event wait for every dependency between the
+ * two (read after write, write after read and write after write on each
+ * buffer), so that independent operations of the two kinds overlap.  Work
+ * enqueued on the context's stream before a residual is seen by both
+ * streams, and the context's stream waits for the second before the call
+ * returns, so callers still see one stream.  Results are bitwise the same
+ * (each operation's arithmetic is unchanged and the dependencies fix every
+ * buffer's order of writes).  Out-of-core VVVV and batched contexts always
+ * run on one stream.  n other than 1 or 2: FSCC_EINVAL. */
+fscc_status fscc_set_streams(fscc_ctx *ctx, int n);
+
 /* Packed lengths (complex elements) of T1/R1 and T2/R2 for a sector (for
  * FSCC_S02: n1 = 0 and n2 = the length of S_xy^ab, see fscc_heff2): the
  * amplitudes of the wave operator of Eq. (2) restricted to the sector of

@@ -81,6 +81,7 @@ def lib():
             "fscc_pade": ([ip, vp, vp, ip, ip, ctypes.c_double, vp], ip),
             "fscc_heff_eig": ([ip, vp, vp], ip),
             "fscc_set_validation": ([vp, ip], ip),
+            "fscc_set_streams": ([vp, ip], ip),
             "fscc_tune_cache": ([vp, ctypes.c_char_p], ip),
             "fscc_autotune_cached": ([vp, ctypes.POINTER(ip)], ip),
             "fscc_get_precision": ([vp, ctypes.POINTER(ip)], ip),
@@ -246,6 +247,10 @@ class Context:
     def set_validation(self, nsample):
         """Sampled symmetry checks per integral class at set_integrals (0 = off)."""
         self._check(lib().fscc_set_validation(self._h, int(nsample)))
+
+    def set_streams(self, n):
+        """Residual operations on one stream (1) or on two overlapping streams (2)."""
+        self._check(lib().fscc_set_streams(self._h, int(n)))
 
     def set_integrals(self, cls, dev_blocks):
         k = CLASSES.index(cls) if isinstance(cls, str) else int(cls)

@@ -825,6 +825,16 @@ fscc_status fscc_set_validation(fscc_ctx* ctx, int nsample) {
     return FSCC_OK;
 }
 
+fscc_status fscc_set_streams(fscc_ctx* ctx, int n) {
+    if (!ctx) return FSCC_EINVAL;
+    if (n != 1 && n != 2) return fail(ctx, FSCC_EINVAL, "stream count must be 1 or 2");
+    return guarded(ctx, [&]() -> fscc_status {
+        hip_check(hipStreamSynchronize(ctx->st), "sync");
+        ctx->streams = n;
+        return FSCC_OK;
+    });
+}
+
 fscc_status fscc_build_residual(fscc_ctx* ctx, fscc_sector sector, const fscc_c128* t1, const fscc_c128* t2,
                                 fscc_c128* r1, fscc_c128* r2) {
     if (!ctx) return FSCC_EINVAL;

@@ -107,7 +107,87 @@ struct OpList {
     std::vector<double> ms;
     std::vector<int> calls;
     int base = 0;             // number of the first operation (fscc_op_info numbering)
+    // Two-stream schedule (fscc_ctx::streams == 2): operations that are bound
+    // by the matrix cores run on the context's stream, the others (reorders,
+    // elementwise and memory-bound GEMMs) on a second stream, so that the two
+    // kinds overlap where the operations' buffers allow.  on2[k]: operation k
+    // runs on the second stream; wait[k]: the latest operation of the other
+    // stream that k depends on (-1: none); rec[k]: an event is recorded after
+    // k for such a wait.
+    std::vector<char> on2, rec;
+    std::vector<int> wait;
+    std::vector<hipEvent_t> xev;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
+
+// Dependencies of an operation list through its buffers: operation k reads
+// src, src2, every term source and, when it accumulates (beta = 1, diagonal
+// and multiply forms), dst; it writes dst.  k depends on the last writer of
+// every buffer it reads or writes (read after write, write after write) and
+// on every reader of dst since that writer (write after read).  Buffers are
+// separate allocations, so distinct ids never overlap.
+inline std::vector<std::vector<int>> op_dependencies(const std::vector<Op>& ops) {
+    std::vector<std::vector<int>> deps(ops.size());
+    std::vector<int> last_w;
+    std::vector<std::vector<int>> readers;
+    auto grow = [&](int b) {
+        if (b >= (int)last_w.size()) {
+            last_w.resize(b + 1, -1);
+            readers.resize(b + 1);
+        }
+    };
+    for (size_t k = 0; k < ops.size(); ++k) {
+        const Op& o = ops[k];
+        std::vector<int> rd;
+        for (int b : {o.src, o.src2})
+            if (b >= 0) rd.push_back(b);
+        for (int b : o.srcT)
+            if (b >= 0) rd.push_back(b);
+        if (o.beta || o.kind == OP_DIAG || o.kind == OP_MUL) rd.push_back(o.dst);
+        std::vector<int>& d = deps[k];
+        for (int b : rd) {
+            grow(b);
+            if (last_w[b] >= 0) d.push_back(last_w[b]);
+        }
+        if (o.dst >= 0) {
+            grow(o.dst);
+            if (last_w[o.dst] >= 0) d.push_back(last_w[o.dst]);
+            for (int r : readers[o.dst]) d.push_back(r);
+        }
+        std::sort(d.begin(), d.end());
+        d.erase(std::unique(d.begin(), d.end()), d.end());
+        d.erase(std::remove(d.begin(), d.end(), (int)k), d.end());
+        for (int b : rd) readers[b].push_back((int)k);
+        if (o.dst >= 0) {
+            last_w[o.dst] = (int)k;
+            readers[o.dst].clear();
+        }
+    }
+    return deps;
+}
+
+// The two-stream schedule of a list (see OpList): GEMMs with more than
+// 8 flops per algorithmic byte on the first stream, everything else on the
+// second.
+inline void build_two_stream(OpList& L) {
+    const std::vector<Op>& ops = *L.ops;
+    const size_t n = ops.size();
+    L.on2.assign(n, 0);
+    L.rec.assign(n, 0);
+    L.wait.assign(n, -1);
+    for (size_t k = 0; k < n; ++k) {
+        const Op& o = ops[k];
+        L.on2[k] = !(o.kind == OP_GEMM && o.flops > 8.0 * std::max(o.bytes, 1.0));
+    }
+    const std::vector<std::vector<int>> deps = op_dependencies(ops);
+    for (size_t k = 0; k < n; ++k) {
+        int w = -1;
+        for (int j : deps[k])
+            if (L.on2[j] != L.on2[k]) w = std::max(w, j);
+        L.wait[k] = w;
+        if (w >= 0) L.rec[w] = 1;
+    }
+}
 
 // DIIS state of one sector
 struct Diis {
@@ -158,6 +238,10 @@ struct fscc_ctx {
     double2* rs_tmp = nullptr; // residual scratch for fscc_heff
     bool prof = false;
     int prof_sel = -1;   // with prof: time only this operation (-1: all)
+    // operation lists on one stream or two (see OpList); the second stream is
+    // created on first use, with the default priority
+    int streams = 1;
+    hipStream_t st2 = nullptr;
     // real arithmetic (real double groups): every amplitude, integral and
     // intermediate buffer holds doubles instead of complex doubles
     bool real = false;
@@ -233,6 +317,10 @@ struct fscc_ctx {
         }
         for (auto& e : L.ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& e : L.xev)
+            if (e) (void)hipEventDestroy(e);
+        if (L.fork) (void)hipEventDestroy(L.fork);
+        if (L.join) (void)hipEventDestroy(L.join);
     }
 
     ~fscc_ctx() {
@@ -258,6 +346,10 @@ struct fscc_ctx {
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hscal) (void)hipHostFree(hscal);
+        if (st2) {
+            (void)hipStreamSynchronize(st2);
+            (void)hipStreamDestroy(st2);
+        }
     }
 
     double2* B(int id) const { return (double2*)dbuf[id]; }
@@ -487,6 +579,10 @@ struct fscc_ctx {
         }
         if (timed) collect(L);
         std::vector<std::vector<StreamChunk>>* sc = stream_chunks(L);
+        if (streams == 2 && !sc && !d_active) {
+            run_list_two(L, timed);
+            return;
+        }
         for (size_t k = 0; k < ops.size(); ++k) {
             const bool tk = timed && (prof_sel < 0 || prof_sel == L.base + (int)k);
             if (tk) hip_check(hipEventRecord(L.ev[2 * k], st), "event");
@@ -497,6 +593,48 @@ struct fscc_ctx {
                 L.pend[k] = 1;
             }
         }
+    }
+
+    // run_list on two streams: the second stream first waits for the work
+    // already on the context's stream, every cross-stream dependency is an
+    // event wait, and the context's stream finally waits for the second, so
+    // that callers see one stream.  Operations launch on the member stream st,
+    // which is switched per operation (and restored on every exit).
+    void run_list_two(OpList& L, bool timed) {
+        std::vector<Op>& ops = *L.ops;
+        if (!st2) hip_check(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking), "second stream");
+        if (L.on2.size() != ops.size()) {
+            build_two_stream(L);
+            L.xev.assign(ops.size(), nullptr);
+            for (size_t k = 0; k < ops.size(); ++k)
+                if (L.rec[k]) hip_check(hipEventCreateWithFlags(&L.xev[k], hipEventDisableTiming), "event");
+            hip_check(hipEventCreateWithFlags(&L.fork, hipEventDisableTiming), "event");
+            hip_check(hipEventCreateWithFlags(&L.join, hipEventDisableTiming), "event");
+        }
+        const hipStream_t s0 = st;
+        struct Restore {
+            hipStream_t& s;
+            hipStream_t v;
+            ~Restore() { s = v; }
+        } restore{st, s0};
+        hip_check(hipEventRecord(L.fork, s0), "event");
+        hip_check(hipStreamWaitEvent(st2, L.fork, 0), "stream wait");
+        for (size_t k = 0; k < ops.size(); ++k) {
+            const hipStream_t s = L.on2[k] ? st2 : s0;
+            if (L.wait[k] >= 0) hip_check(hipStreamWaitEvent(s, L.xev[L.wait[k]], 0), "stream wait");
+            const bool tk = timed && (prof_sel < 0 || prof_sel == L.base + (int)k);
+            if (tk) hip_check(hipEventRecord(L.ev[2 * k], s), "event");
+            st = s;
+            run_op(ops[k], &L.g[k]);
+            st = s0;
+            if (tk) {
+                hip_check(hipEventRecord(L.ev[2 * k + 1], s), "event");
+                L.pend[k] = 1;
+            }
+            if (L.rec[k]) hip_check(hipEventRecord(L.xev[k], s), "event");
+        }
+        hip_check(hipEventRecord(L.join, st2), "event");
+        hip_check(hipStreamWaitEvent(s0, L.join, 0), "stream wait");
     }
 };
 
