@@ -58,8 +58,10 @@ __device__ __forceinline__ uint32_t lds_addr(const double2* p) {
 
 // The fragment reads of one 4-deep step: NF 16-byte LDS reads and the wait
 // for them in one asm block.  Written out because the compiler, which cannot
-// tell the ring's stages apart, would otherwise make every LDS read wait for
-// all direct-to-LDS loads in flight (the pipeline would drain each slice).
+// tell the stages apart, would otherwise make every LDS read wait for all
+// direct-to-LDS loads in flight, including those of the next slice (the
+// pipeline would drain every slice).  Their order against the loads and
+// barriers is kept by the explicit waits and the memory clobbers.
 template <int NF>
 __device__ __forceinline__ void lds_frags(dbl2 (&v)[NF], const uint32_t (&a)[NF]) {
     static_assert(NF >= 2 && NF <= 5, "fragment count");
@@ -88,10 +90,9 @@ __device__ __forceinline__ void lds_frags(dbl2 (&v)[NF], const uint32_t (&a)[NF]
     }
 }
 
-// Stage I of the ring as an LDS variable of its own: with every access tied
-// to one variable at compile time, the compiler's wait for the in-flight
-// loads into a stage covers only that stage's loads (one array indexed by a
-// run-time stage would make every LDS read wait for all of them).
+// Stage I of the ring as an LDS variable of its own; the ring is unrolled so
+// that every stage is named at compile time (no run-time stage arithmetic in
+// the load and fragment addresses).
 template <int SE, int I>
 __device__ __forceinline__ double2* lds_stage() {
     __shared__ double2 buf[SE];
