@@ -46,8 +46,8 @@ def _case(F, torch, rng, M, N, K, tA, tB, cfg, allow_split, beta):
     return np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("cfg,allow_split", [(-1, 1), (3 | 256, 1), (0, 0), (6, 1)],
-                         ids=["cost-model", "32x32-3M-split", "64x64-unsplit", "skinny"])
+@pytest.mark.parametrize("cfg,allow_split", [(-1, 1), (3 | 256, 1), (0, 0), (6, 1), (9 | 256 | 1024, 1)],
+                         ids=["cost-model", "32x32-3M-split", "64x64-unsplit", "skinny", "32x64-3M-direct-LDS-split"])
 def test_noalloc_matches_allocating_entry_point(cfg, allow_split):
     torch = _torch()
     import paper_2004_03682_amd as F
