@@ -4,7 +4,7 @@ Dirichlet(1) block sizes, sigma=0.03, complex128).
 
 One step = one CCSD iteration of the whole hot path (fscc_iterate): the
 residual (every contraction), the Jacobi step with dressed denominators
-(refreshed every 25 iterations) and DIIS(6) on the device, and the energy,
+(refreshed every 25 iterations) and DIIS(8) on the device, and the energy,
 with one host synchronisation.  Inputs (packed integrals, amplitudes) are
 resident in HBM when the timed region starts.
 
@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CCSD s/iteration + MFMA TFLOP/s, FP64 vs mixed at dE<1e-8 Eh"
 DRESSED = 25       # refresh period of the dressed Jacobi denominators (fscc_precondition)
+NDIIS = 8          # DIIS depth of the production context's solves
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0  # GB/s
 
@@ -144,7 +145,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
     ctx.set_precision("fp64")
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    a = F.solve(ctx, u1, u2, tol=1e-10, maxit=300, dressed=DRESSED)
+    a = F.solve(ctx, u1, u2, tol=1e-10, maxit=300, ndiis=NDIIS, dressed=DRESSED)
     k8, s8 = time_to(a["history"], E_inf, ts)
     out["fp64"] = {"iterations": a["iters"], "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
                    "seconds_to_converged": round(a["history"][-1]["time"] - ts, 5)}
@@ -175,7 +176,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
         # per-iteration time of unprofiled steps
         u1.zero_()
         u2.zero_()
-        ctx.diis_reset(6)
+        ctx.diis_reset(NDIIS)
         ctx.profile(True)
         for _ in range(max(1, args.warmup)):
             ctx.build_residual(u1, u2, q1, q2)
@@ -214,7 +215,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
             u2.zero_()
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            b = F.solve_mixed(ctx, u1, u2, switch_tol=sw, tol=1e-10, maxit=300, dressed=DRESSED)
+            b = F.solve_mixed(ctx, u1, u2, switch_tol=sw, tol=1e-10, maxit=300, ndiis=NDIIS, dressed=DRESSED)
             k8, s8 = time_to(b["history"], E_inf, ts)
             rec[f"two_stage_switch_{sw:g}"] = {
                 "split_iterations": b["split_iters"], "fp64_iterations": b["fp64_iters"],
@@ -228,7 +229,7 @@ def precision_study(ctx, F, torch, dev, E_inf, tconv, args, log, ora=None):
         u2.zero_()
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        c = F.solve(ctx, u1, u2, tol=1e-12, maxit=120, dressed=DRESSED)
+        c = F.solve(ctx, u1, u2, tol=1e-12, maxit=120, ndiis=NDIIS, dressed=DRESSED)
         k8, s8 = time_to(c["history"], E_inf, ts)
         rec["split_only"] = {"iterations": c["iters"], "last_max_step": c["history"][-1]["dmax"],
                              "iterations_to_1e-8": k8, "seconds_to_1e-8": s8,
@@ -270,7 +271,7 @@ def out_of_core_study(ctx, F, torch, s_per_iter, dom, args, log, staging=512 << 
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
-    ctx.diis_reset(6)
+    ctx.diis_reset(NDIIS)
     for _ in range(max(1, args.warmup)):
         ctx.build_residual(t1, t2, r1, r2)
         ctx.update_amplitudes(t1, t2, r1, r2)
@@ -318,7 +319,7 @@ def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sect
     t1 = torch.zeros(ctx.n1, dtype=torch.float64, device="cuda")
     t2 = torch.zeros(ctx.n2, dtype=torch.float64, device="cuda")
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
-    ctx.diis_reset(6)
+    ctx.diis_reset(NDIIS)
     ctx.profile(True)
     for _ in range(max(1, args.warmup)):
         ctx.build_residual(t1, t2, r1, r2)
@@ -344,7 +345,7 @@ def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sect
     t2.zero_()
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    g = F.solve(ctx, t1, t2, tol=1e-10, maxit=200)
+    g = F.solve(ctx, t1, t2, tol=1e-10, maxit=200, ndiis=NDIIS)
     solve_s = time.perf_counter() - ts
     E = g["E"]
     k8 = next((h["iter"] for k, h in enumerate(g["history"]) if all(abs(x["E"] - E) < 1e-8 for x in g["history"][k:])),
@@ -401,6 +402,9 @@ def real_study(F, torch, fsgen, cfg, complex_s_per_iter, args, log, complex_sect
 # the batched workload's solver: DIIS(8), dressed Jacobi denominators refreshed
 # every 25 iterations (same fixed point); at most 600 iterations per system
 BATCH_SOLVER = dict(ndiis=8, shift=0.0, dressed=25)
+# DIIS depth of a system in a context of its own (the batch keeps 8): the
+# stragglers the batch hands off and the one-after-another baseline
+ALONE_NDIIS = 12
 BATCH_MAXIT = 600
 BATCH_STOP_ACTIVE = 2      # stragglers continue in their own contexts
 
@@ -581,7 +585,7 @@ def batch_study(F, torch, fsgen, args, log):
     t_batch = time.perf_counter() - ts
     n_batch_its = len(res["history"])
     alone = F.finish_batch_in_contexts(b, res, t1, t2, make_ctx, tol=1e-10, maxit=BATCH_MAXIT,
-                                       ndiis=BATCH_SOLVER["ndiis"], dressed=BATCH_SOLVER["dressed"])
+                                       ndiis=ALONE_NDIIS, dressed=BATCH_SOLVER["dressed"])
     el = time.perf_counter() - ts
     conv = res["converged"]
     E = res["E"]
@@ -604,7 +608,8 @@ def batch_study(F, torch, fsgen, args, log):
            "solve_seconds": round(el, 4), "seconds_to_1e-8_all_converged": round(t8, 4) if t8 else None,
            "converged": int(conv.sum()), "iterations_mean": float(res["iters"].mean()),
            "iterations_max": int(res["iters"].max()),
-           "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True, maxit=BATCH_MAXIT, stop_active=BATCH_STOP_ACTIVE),
+           "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True, maxit=BATCH_MAXIT, stop_active=BATCH_STOP_ACTIVE,
+                          alone_ndiis=ALONE_NDIIS),
            "batched_iterations": n_batch_its, "batched_seconds": round(t_batch, 4),
            "continued_alone": {int(k): {"iterations": int(res["iters"][k]), "converged": bool(conv[k])} for k in alone},
            "plan_seconds": round(t_plan, 2), "integral_seconds": round(t_int, 2), "autotune_seconds": round(t_tune, 2)}
@@ -630,7 +635,7 @@ def batch_study(F, torch, fsgen, args, log):
         torch.cuda.synchronize()
         ts = time.perf_counter()
         try:
-            g = F.solve(ctx, u1, u2, tol=1e-10, maxit=BATCH_MAXIT, ndiis=BATCH_SOLVER["ndiis"],
+            g = F.solve(ctx, u1, u2, tol=1e-10, maxit=BATCH_MAXIT, ndiis=ALONE_NDIIS,
                         dressed=BATCH_SOLVER["dressed"])
             iters += g["iters"]
             if conv[k] and g["converged"]:
@@ -739,7 +744,7 @@ def profile_ops(args):
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
     # two iterations give the amplitudes (and so every operation's input) the
     # values of the second iteration; the last residual binds the buffers
-    ctx.diis_reset(6)
+    ctx.diis_reset(NDIIS)
     for _ in range(2):
         ctx.build_residual(t1, t2, r1, r2)
         ctx.update_amplitudes(t1, t2, r1, r2)
@@ -1057,10 +1062,10 @@ def main():
     t1 = torch.zeros(ctx.n1, dtype=torch.complex128, device=dev)
     t2 = torch.zeros(ctx.n2, dtype=torch.complex128, device=dev)
     r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
-    ctx.diis_reset(6)
+    ctx.diis_reset(NDIIS)
     E = 0j
 
-    # the solver: Jacobi + DIIS(6) with dressed denominators (refreshed from the
+    # the solver: Jacobi + DIIS(NDIIS) with dressed denominators (refreshed from the
     # previous residual at iteration 3 and every DRESSED iterations after it)
     nit = [0]
 

@@ -294,8 +294,9 @@ fscc_status fscc_iterate(fscc_ctx *ctx, fscc_c128 *t1, fscc_c128 *t2, fscc_c128 
 fscc_status fscc_energy(fscc_ctx *ctx, const fscc_c128 *t1, const fscc_c128 *t2, double *e_re, double *e_im);
 
 /* Clear the DIIS history of a sector and set its depth (0 or 1 = plain Jacobi
- * of Eq. (3), max 8); also restarts the sector's divergence watch (see
- * fscc_update_amplitudes).  FSCC_EINVAL for a depth outside 0..8 or a sector
+ * of Eq. (3), max 16; the context keeps 16 vector pairs per sector on the
+ * device); also restarts the sector's divergence watch (see
+ * fscc_update_amplitudes).  FSCC_EINVAL for a depth outside 0..16 or a sector
  * the system does not have. */
 fscc_status fscc_diis_reset(fscc_ctx *ctx, fscc_sector sector, int ndiis);
 

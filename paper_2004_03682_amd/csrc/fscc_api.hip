@@ -527,7 +527,7 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
         c->rs_tmp = (double2*)c->dalloc((size_t)std::max<int64_t>(1, ntmp) * sizeof(double2));
     }
     if (P.has02) setup_diis(c, c->diis[2], 0, P.L_S02.total, -1, P.b_D02);
-    c->part = (double*)c->dalloc(1024 * 8 * sizeof(double));
+    c->part = (double*)c->dalloc(1024 * kDiisMax * sizeof(double));
     c->part_max = (double*)c->dalloc(2048 * sizeof(double));
     c->coef = (double*)c->dalloc((kMaxDiis + 1) * sizeof(double));
     c->scal = (double*)c->dalloc(4 * sizeof(double));

@@ -1449,32 +1449,39 @@ hipError_t launch_jacobi(const double2* t, const double2* r, const double* D, do
     return hipGetLastError();
 }
 
-// part[b*8 + j] = Re sum conj(e_j) enew over block b's share
+// part[b*kDiisMax + j] = Re sum conj(e_j) enew over block b's share
 struct PtrList {
-    const double2* p[8];
+    const double2* p[kDiisMax];
 };
 
 __global__ __launch_bounds__(256) void k_dots(PtrList e, int m, const double2* __restrict__ enew, long long n,
                                               double* part) {
     __shared__ double sh[kThreads];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kDiisMax];
+#pragma unroll
+    for (int j = 0; j < kDiisMax; ++j) acc[j] = 0.0;
     for (long long k = (long long)blockIdx.x * kThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kThreads) {
         double2 y = enew[k];
-        for (int j = 0; j < m; ++j) {
-            double2 x = e.p[j][k];
-            acc[j] += x.x * y.x + x.y * y.y;
+#pragma unroll
+        for (int j = 0; j < kDiisMax; ++j)
+            if (j < m) {
+                double2 x = e.p[j][k];
+                acc[j] += x.x * y.x + x.y * y.y;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < kDiisMax; ++j)
+        if (j < m) {
+            double b = block_sum(acc[j], sh);
+            if (threadIdx.x == 0) part[blockIdx.x * kDiisMax + j] = b;
         }
-    }
-    for (int j = 0; j < m; ++j) {
-        double b = block_sum(acc[j], sh);
-        if (threadIdx.x == 0) part[blockIdx.x * 8 + j] = b;
-    }
 }
 
 hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long long n, double* part, int nblk,
                        hipStream_t st) {
+    if (m < 0 || m > kDiisMax) return hipErrorInvalidValue;
     PtrList pl;
-    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? e[j] : nullptr;
+    for (int j = 0; j < kDiisMax; ++j) pl.p[j] = j < m ? e[j] : nullptr;
     k_dots<<<nblk, kThreads, 0, st>>>(pl, m, enew, n, part);
     return hipGetLastError();
 }
@@ -1493,7 +1500,7 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
             coef[order[m - 1]] = 1.0;
             break;
         }
-        double a[9][10];
+        double a[kDiisMax + 1][kDiisMax + 2];
         double scale = 0.0;
         for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(B[order[first + i] * ldb + order[first + i]]));
         if (!(scale > 0.0)) scale = 1.0;
@@ -1534,7 +1541,7 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
             ++dropped;
             continue;
         }
-        double x[9];
+        double x[kDiisMax + 1];
         for (int i = nn - 1; i >= 0; --i) {
             double s = a[i][nn];
             for (int j = i + 1; j < nn; ++j) s -= a[i][j] * x[j];
@@ -1561,10 +1568,10 @@ __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ 
                                                      const int* __restrict__ order, double* __restrict__ coef,
                                                      double* __restrict__ scal) {
     __shared__ double sh[kThreads];
-    __shared__ double row[8];
+    __shared__ double row[kDiisMax];
     for (int j = 0; j < m; ++j) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * 8 + j];
+        for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * kDiisMax + j];
         double s = block_sum(v, sh);
         if (threadIdx.x == 0) row[j] = s;
     }
@@ -1669,8 +1676,9 @@ __global__ __launch_bounds__(256) void k_lincomb(double2* __restrict__ out, PtrL
 hipError_t launch_lincomb(double2* out, const double2* const* xs, const double* coef, int m, long long n,
                           hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (m < 0 || m > kDiisMax) return hipErrorInvalidValue;
     PtrList pl;
-    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? xs[j] : nullptr;
+    for (int j = 0; j < kDiisMax; ++j) pl.p[j] = j < m ? xs[j] : nullptr;
     k_lincomb<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, st>>>(out, pl, coef, m, n);
     return hipGetLastError();
 }

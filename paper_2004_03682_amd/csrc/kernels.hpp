@@ -40,6 +40,9 @@ enum ZCfg {
     ZCFG_32x64, ZCFG_64x32, ZCFG_DOT, ZCFG_64x64R, ZCFG_64x32R, ZCFG_N
 };
 constexpr int ZSKINNY_BM = 64, ZSKINNY_BN = 32, ZSKINNY_MAX_MN = ZSKINNY_BM * ZSKINNY_BN;
+// deepest DIIS subspace of a single-system context (vectors kept; the dot
+// partials of the DIIS kernels have this stride)
+constexpr int kDiisMax = 16;
 constexpr int ZTALL_ROWS = 256, ZTALL_MAX_K = 64, ZTALL_MAX_KN = 1024;
 constexpr int ZRED_MAX_M = 8, ZRED_MAX_N = 256, ZRED_LDS = 2048;   // LDS: A chunk of M * K <= ZRED_LDS
 constexpr int ZDOT_MAX_M = 8, ZDOT_ROWS = 16, ZDOT_KC = 256;       // LDS: A chunk of M * ZDOT_KC

@@ -539,21 +539,27 @@ __global__ __launch_bounds__(256) void k_djacobi(const double* __restrict__ t, c
 }
 
 struct DPtrList {
-    const double* p[8];
+    const double* p[kDiisMax];
 };
 
 __global__ __launch_bounds__(256) void k_ddots(DPtrList e, int m, const double* __restrict__ enew, long long n,
                                                double* part) {
     __shared__ double sh[kT];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kDiisMax];
+#pragma unroll
+    for (int j = 0; j < kDiisMax; ++j) acc[j] = 0.0;
     for (long long k = (long long)blockIdx.x * kT + threadIdx.x; k < n; k += (long long)gridDim.x * kT) {
         const double y = enew[k];
-        for (int j = 0; j < m; ++j) acc[j] += e.p[j][k] * y;
+#pragma unroll
+        for (int j = 0; j < kDiisMax; ++j)
+            if (j < m) acc[j] += e.p[j][k] * y;
     }
-    for (int j = 0; j < m; ++j) {
-        double b = dblock_sum(acc[j], sh);
-        if (threadIdx.x == 0) part[blockIdx.x * 8 + j] = b;
-    }
+#pragma unroll
+    for (int j = 0; j < kDiisMax; ++j)
+        if (j < m) {
+            double b = dblock_sum(acc[j], sh);
+            if (threadIdx.x == 0) part[blockIdx.x * kDiisMax + j] = b;
+        }
 }
 
 // out = sum_j coef[j] xs[j]; coef[m] != 0 (a non-finite step) leaves out untouched
@@ -685,8 +691,9 @@ hipError_t launch_djacobi(const double* t, const double* r, const double* D, dou
 
 hipError_t launch_ddots(const double* const* e, int m, const double* enew, long long n, double* part, int nblk,
                         hipStream_t st) {
+    if (m < 0 || m > kDiisMax) return hipErrorInvalidValue;
     DPtrList pl;
-    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? e[j] : nullptr;
+    for (int j = 0; j < kDiisMax; ++j) pl.p[j] = j < m ? e[j] : nullptr;
     k_ddots<<<nblk, kT, 0, st>>>(pl, m, enew, n, part);
     return hipGetLastError();
 }
@@ -694,8 +701,9 @@ hipError_t launch_ddots(const double* const* e, int m, const double* enew, long 
 hipError_t launch_dlincomb(double* out, const double* const* xs, const double* coef, int m, long long n,
                            hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (m < 0 || m > kDiisMax) return hipErrorInvalidValue;
     DPtrList pl;
-    for (int j = 0; j < 8; ++j) pl.p[j] = j < m ? xs[j] : nullptr;
+    for (int j = 0; j < kDiisMax; ++j) pl.p[j] = j < m ? xs[j] : nullptr;
     k_dlincomb<<<grid_of(n), kT, 0, st>>>(out, pl, coef, m, n);
     return hipGetLastError();
 }

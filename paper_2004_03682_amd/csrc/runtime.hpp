@@ -73,7 +73,7 @@ inline void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr int kMaxDiis = 8;
+constexpr int kMaxDiis = kDiisMax;
 
 // one executable op list with its device GEMM lists and timing slots
 // One chunk of a GEMM whose B operand streams from pinned host memory: the
