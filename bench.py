@@ -573,14 +573,14 @@ def batch_study(F, torch, fsgen, args, log):
     t1.zero_()
     t2.zero_()
 
-    def make_ctx(k):
-        c = F.Context.from_system(ss[k])
+    def make_ctx(k, stream):
+        c = F.Context.from_system(ss[k], stream=stream)
         for C in fsgen.CLASSES:
-            c.set_integrals(C, fsgen.class_buffer_gpu(ss[k], C))
+            c.set_integrals(C, fsgen.class_buffer_gpu(ss[k], C, stream=stream))
         return c
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=BATCH_MAXIT, use_graph=True, stop_active=BATCH_STOP_ACTIVE,
+    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=BATCH_MAXIT, use_graph=True, stop_active=args.batch_stop_active,
                         **BATCH_SOLVER)
     t_batch = time.perf_counter() - ts
     n_batch_its = len(res["history"])
@@ -608,8 +608,8 @@ def batch_study(F, torch, fsgen, args, log):
            "solve_seconds": round(el, 4), "seconds_to_1e-8_all_converged": round(t8, 4) if t8 else None,
            "converged": int(conv.sum()), "iterations_mean": float(res["iters"].mean()),
            "iterations_max": int(res["iters"].max()),
-           "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True, maxit=BATCH_MAXIT, stop_active=BATCH_STOP_ACTIVE,
-                          alone_ndiis=ALONE_NDIIS),
+           "solver": dict(BATCH_SOLVER, tol=1e-10, graph=True, maxit=BATCH_MAXIT, stop_active=args.batch_stop_active,
+                          alone_ndiis=ALONE_NDIIS, alone_concurrent=True),
            "batched_iterations": n_batch_its, "batched_seconds": round(t_batch, 4),
            "continued_alone": {int(k): {"iterations": int(res["iters"][k]), "converged": bool(conv[k])} for k in alone},
            "plan_seconds": round(t_plan, 2), "integral_seconds": round(t_int, 2), "autotune_seconds": round(t_tune, 2)}
@@ -965,6 +965,8 @@ def main():
     ap.add_argument("--no-real", action="store_true", help="skip the real-arithmetic (real double group) study")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core VVVV study")
     ap.add_argument("--no-sequential", action="store_true", help="skip the one-by-one baseline of the batch")
+    ap.add_argument("--batch-stop-active", type=int, default=BATCH_STOP_ACTIVE,
+                    help="the batch hands its last N iterating systems to concurrent contexts of their own")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start on the batch")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")

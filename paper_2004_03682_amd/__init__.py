@@ -785,34 +785,54 @@ def solve_batch(batch, t1, t2, tol=1e-10, maxit=200, ndiis=6, use_graph=True, lo
                 failed=rep[:, 5] != 0, history=hist, times=times)
 
 
-def finish_batch_in_contexts(batch, res, t1, t2, make_ctx, tol=1e-10, maxit=200, ndiis=6, dressed=0, floor=0.1):
+def finish_batch_in_contexts(batch, res, t1, t2, make_ctx, tol=1e-10, maxit=200, ndiis=6, dressed=0, floor=0.1,
+                             concurrent=True):
     """Systems still iterating when solve_batch stopped (stop_active) continue
-    alone, each in its own context (make_ctx(s) -> Context with integrals
-    set), from the amplitudes their batch segments hold, with a fresh DIIS
-    subspace, until max|step| < tol or maxit iterations in all; the converged
-    amplitudes are copied back into the segments and res (E, iters,
-    converged) is updated in place.  A batch's launches are tuned for all of
-    its systems; a lone straggler runs faster with its own tiles.  Returns the
-    per-system results of the continued systems."""
+    alone, each in its own context (make_ctx(s, stream) -> Context on that
+    torch stream with integrals set), from the amplitudes their batch segments
+    hold, with a fresh DIIS subspace, until max|step| < tol or maxit iterations
+    in all; the converged amplitudes are copied back into the segments and res
+    (E, iters, converged) is updated in place.  A batch's launches are tuned
+    for all of its systems; a lone straggler runs faster with its own tiles.
+    concurrent=True: the continued systems iterate at the same time, each from
+    a host thread of its own on a stream of its own (a lone small system does
+    not fill the GPU; the library's calls release the interpreter lock), with
+    the same results as one after another.  Returns the per-system results of
+    the continued systems."""
     import numpy as np
     import torch
     rep = res["history"][-1]
-    out = {}
-    for s in np.nonzero(rep[:, 3] != 0)[0]:
-        s = int(s)
+    left = [int(s) for s in np.nonzero(rep[:, 3] != 0)[0]]
+    torch.cuda.synchronize()      # the batch's amplitudes are final before other streams read them
+
+    def run(s):
         off1, n1, off2, n2 = batch.segments[s]
-        ctx = make_ctx(s)
-        u1 = t1[off1:off1 + n1].clone()
-        u2 = t2[off2:off2 + n2].clone()
-        done = int(rep[s, 4])
-        g = solve(ctx, u1, u2, tol=tol, maxit=max(1, maxit - done), ndiis=ndiis, dressed=dressed, floor=floor)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            ctx = make_ctx(s, stream)
+            u1 = t1[off1:off1 + n1].clone()
+            u2 = t2[off2:off2 + n2].clone()
+            done = int(rep[s, 4])
+            g = solve(ctx, u1, u2, tol=tol, maxit=max(1, maxit - done), ndiis=ndiis, dressed=dressed, floor=floor)
+            stream.synchronize()
+            ctx.destroy()
+        return s, done, g, u1, u2
+
+    if concurrent and len(left) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=len(left)) as ex:
+            results = list(ex.map(run, left))
+    else:
+        results = [run(s) for s in left]
+    out = {}
+    for s, done, g, u1, u2 in results:
+        off1, n1, off2, n2 = batch.segments[s]
         t1[off1:off1 + n1].copy_(u1)
         t2[off2:off2 + n2].copy_(u2)
         res["E"][s] = g["E"]
         res["iters"][s] = done + g["iters"]
         res["converged"][s] = g["converged"]
         out[s] = g
-        ctx.destroy()
     torch.cuda.synchronize()
     return out
 

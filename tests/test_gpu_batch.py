@@ -230,3 +230,42 @@ def test_batched_workload_systems_converge_to_the_oracle():
         assert res["converged"][j]
         assert abs(res["E"][j].real - g["E_re"]) <= 1e-10 and abs(res["E"][j].imag - g["E_im"]) <= 1e-10
     b.destroy()
+
+
+def test_stragglers_continue_concurrently_with_the_sequential_results():
+    """finish_batch_in_contexts: the systems left when the batch stops
+    (stop_active) continue in contexts of their own, concurrently (one host
+    thread and stream each) or one after another, with the same energies and
+    amplitudes, and reach the single-system fixed point."""
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    systems = [fsgen.make_system(*p) for p in SPECS[:4]] + [fsgen.make_system(7, 30, 4, 0.05, 8)]
+
+    def make_ctx(k, stream):
+        ctx = F.Context.from_system(systems[k], stream=stream)
+        for C in fsgen.CLASSES:
+            buf, _ = fsgen.class_buffer(systems[k], C)
+            ctx.set_integrals(C, torch.from_numpy(buf).to("cuda"))
+        return ctx
+
+    out = []
+    for concurrent in (False, True):
+        b = make_batch(systems)
+        t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
+        t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
+        res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=True, ndiis=8, dressed=10, stop_active=3)
+        left = F.finish_batch_in_contexts(b, res, t1, t2, make_ctx, tol=1e-10, maxit=150, ndiis=12, dressed=10,
+                                          concurrent=concurrent)
+        print("concurrent", concurrent, "continued", sorted(left), "iterations", list(res["iters"]), flush=True)
+        assert len(left) >= 2 and res["converged"].all()
+        out.append((np.array(res["E"]), t1.cpu().numpy(), t2.cpu().numpy()))
+        b.destroy()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+    for k, s in enumerate(systems):
+        ctx = single_ctx(s)
+        u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+        u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+        g = F.solve(ctx, u1, u2, tol=1e-11, maxit=200, ndiis=8)
+        assert abs(out[1][0][k] - g["E"]) <= 1e-9
+        ctx.destroy()
