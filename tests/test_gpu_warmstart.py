@@ -33,6 +33,13 @@ def test_trained_network_saves_iterations():
     assert out["fallback_systems"] == 0
     # fewer iterations to |E - E_final| < 1e-8 Eh on average, start-up evaluations included
     assert out["iterations_to_1e-8_learned_mean"] < out["iterations_to_1e-8_mp2_mean"]
+    # The time to 1e-8 Eh is reported, not asserted: on these eight smallest
+    # systems the network's start evaluations cost about what the saved
+    # fraction of an iteration saves (measured 0.027 s MP2 start, 0.028 s
+    # learned); on the 64-system batch of the benchmark the learned start
+    # reaches 1e-8 Eh 2 % sooner on average.
+    print("seconds to 1e-8 Eh (mean): MP2", out["seconds_to_1e-8_mp2_mean"], "learned",
+          out["seconds_to_1e-8_learned_mean"], flush=True)
     b.destroy()
 
 
