@@ -531,7 +531,6 @@ void ctx_allocate(fscc_ctx* c, bool diis) {
     c->part_max = (double*)c->dalloc(2048 * sizeof(double));
     c->coef = (double*)c->dalloc((kMaxDiis + 1) * sizeof(double));
     c->scal = (double*)c->dalloc(4 * sizeof(double));
-    c->dorder = (int*)c->dalloc(kMaxDiis * sizeof(int));
     c->epart = (double*)c->dalloc(2048 * sizeof(double));
     c->eout = (double*)c->dalloc(4 * sizeof(double));
     hip_check(hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
@@ -1176,8 +1175,9 @@ void update_enqueue(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128*
         for (int j = 0; j < m; ++j) ev[j] = (const double*)D.he + (size_t)ord[j] * n;
         int nbd = reduce_blocks(n);
         hip_check(launch_ddots(ev.data(), m, dhe, n, ctx->part, nbd, ctx->st), "diis dots");
-        hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st), "order");
-        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, ctx->dorder,
+        DiisOrder dord{};
+        for (int j = 0; j < m; ++j) dord.v[j] = ord[j];
+        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, dord,
                                      ctx->coef, ctx->scal, ctx->st),
                   "diis solve");
         std::vector<const double*> xs(kMaxDiis);
@@ -1201,8 +1201,9 @@ void update_enqueue(fscc_ctx* ctx, fscc_sector sector, fscc_c128* t1, fscc_c128*
         for (int j = 0; j < m; ++j) ev[j] = D.he + (size_t)ord[j] * n;
         int nbd = reduce_blocks(n);
         hip_check(launch_dots(ev.data(), m, he, n, ctx->part, nbd, ctx->st), "diis dots");
-        hip_check(hipMemcpyAsync(ctx->dorder, ord.data(), m * sizeof(int), hipMemcpyHostToDevice, ctx->st), "order");
-        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, ctx->dorder,
+        DiisOrder dord{};
+        for (int j = 0; j < m; ++j) dord.v[j] = ord[j];
+        hip_check(launch_finish_diis(ctx->part, nbd, m, ctx->part_max, nb1 + nb2, D.dB, kMaxDiis, slot, dord,
                                      ctx->coef, ctx->scal, ctx->st),
                   "diis solve");
         std::vector<const double2*> xs(kMaxDiis);

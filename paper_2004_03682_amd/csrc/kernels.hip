@@ -1490,8 +1490,14 @@ hipError_t launch_dots(const double2* const* e, int m, const double2* enew, long
 // symmetric matrix B (leading dimension ldb): Gaussian elimination with
 // partial pivoting in FP64; a pivot below 1e-14 * max|A| drops the oldest
 // slot and the solve is repeated.  coef[slot] receives the coefficients (0 for
-// slots not used).  Single-thread code.  Returns the number of dropped slots.
-__device__ int diis_solve(const double* B, int ldb, const int* order, int m, double* coef) {
+// slots not used).  Single-thread code; the working matrix wa ((MAXM + 1) x
+// (MAXM + 2)) and x (MAXM + 1) live in LDS (as private arrays they would be
+// scratch memory, which made the solve 20x slower).  Returns the number of
+// dropped slots.
+template <int MAXM>
+__device__ int diis_solve(const double* B, int ldb, const int* order, int m, double* coef, double* __restrict__ wa,
+                          double* __restrict__ x) {
+    auto A = [wa](int i, int j) -> double& { return wa[i * (MAXM + 2) + j]; };
     for (int j = 0; j < ldb; ++j) coef[j] = 0.0;
     int first = 0, dropped = 0;
     while (true) {
@@ -1500,40 +1506,39 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
             coef[order[m - 1]] = 1.0;
             break;
         }
-        double a[kDiisMax + 1][kDiisMax + 2];
         double scale = 0.0;
         for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(B[order[first + i] * ldb + order[first + i]]));
         if (!(scale > 0.0)) scale = 1.0;
         for (int i = 0; i < k; ++i) {
-            for (int j = 0; j < k; ++j) a[i][j] = B[order[first + i] * ldb + order[first + j]] / scale;
-            a[i][k] = -1.0;
-            a[i][k + 1] = 0.0;
+            for (int j = 0; j < k; ++j) A(i, j) = B[order[first + i] * ldb + order[first + j]] / scale;
+            A(i, k) = -1.0;
+            A(i, k + 1) = 0.0;
         }
-        for (int j = 0; j < k; ++j) a[k][j] = -1.0;
-        a[k][k] = 0.0;
-        a[k][k + 1] = -1.0;
+        for (int j = 0; j < k; ++j) A(k, j) = -1.0;
+        A(k, k) = 0.0;
+        A(k, k + 1) = -1.0;
         int nn = k + 1;
         double amax = 0.0;
         for (int i = 0; i < nn; ++i)
-            for (int j = 0; j < nn; ++j) amax = fmax(amax, fabs(a[i][j]));
+            for (int j = 0; j < nn; ++j) amax = fmax(amax, fabs(A(i, j)));
         bool singular = false;
         for (int c = 0; c < nn && !singular; ++c) {
             int p = c;
             for (int i = c + 1; i < nn; ++i)
-                if (fabs(a[i][c]) > fabs(a[p][c])) p = i;
-            if (!(fabs(a[p][c]) >= 1e-14 * amax)) {
+                if (fabs(A(i, c)) > fabs(A(p, c))) p = i;
+            if (!(fabs(A(p, c)) >= 1e-14 * amax)) {
                 singular = true;
                 break;
             }
             if (p != c)
                 for (int j = 0; j <= nn; ++j) {
-                    double t = a[c][j];
-                    a[c][j] = a[p][j];
-                    a[p][j] = t;
+                    double t = A(c, j);
+                    A(c, j) = A(p, j);
+                    A(p, j) = t;
                 }
             for (int i = c + 1; i < nn; ++i) {
-                double f = a[i][c] / a[c][c];
-                for (int j = c; j <= nn; ++j) a[i][j] -= f * a[c][j];
+                double f = A(i, c) / A(c, c);
+                for (int j = c; j <= nn; ++j) A(i, j) -= f * A(c, j);
             }
         }
         if (singular) {
@@ -1541,11 +1546,10 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
             ++dropped;
             continue;
         }
-        double x[kDiisMax + 1];
         for (int i = nn - 1; i >= 0; --i) {
-            double s = a[i][nn];
-            for (int j = i + 1; j < nn; ++j) s -= a[i][j] * x[j];
-            x[i] = s / a[i][i];
+            double s = A(i, nn);
+            for (int j = i + 1; j < nn; ++j) s -= A(i, j) * x[j];
+            x[i] = s / A(i, i);
         }
         for (int i = 0; i < k; ++i) coef[order[first + i]] = x[i];
         break;
@@ -1565,10 +1569,13 @@ __device__ int diis_solve(const double* B, int ldb, const int* order, int m, dou
 __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ part, int nblk, int m,
                                                      const double* __restrict__ part_max, int nblk_max,
                                                      double* __restrict__ B, int ldb, int newslot,
-                                                     const int* __restrict__ order, double* __restrict__ coef,
+                                                     DiisOrder ord, double* __restrict__ coef,
                                                      double* __restrict__ scal) {
     __shared__ double sh[kThreads];
     __shared__ double row[kDiisMax];
+    __shared__ int order[kDiisMax];
+    __shared__ double wa[(kDiisMax + 1) * (kDiisMax + 2)], wx[kDiisMax + 1];
+    if (threadIdx.x < kDiisMax) order[threadIdx.x] = (int)threadIdx.x < m ? ord.v[threadIdx.x] : 0;
     for (int j = 0; j < m; ++j) {
         double v = 0.0;
         for (int b = threadIdx.x; b < nblk; b += kThreads) v += part[b * kDiisMax + j];
@@ -1596,12 +1603,13 @@ __global__ __launch_bounds__(256) void k_finish_diis(const double* __restrict__ 
         B[newslot * ldb + order[j]] = row[j];
         B[order[j] * ldb + newslot] = row[j];
     }
-    int dropped = diis_solve(B, ldb, order, m, coef);
+    int dropped = diis_solve<kDiisMax>(B, ldb, order, m, coef, wa, wx);
     scal[1] = (double)dropped;
 }
 
 hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
-                              int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st) {
+                              int ldb, int newslot, const DiisOrder& order, double* coef, double* scal, hipStream_t st) {
+    if (m < 1 || m > kDiisMax) return hipErrorInvalidValue;
     k_finish_diis<<<1, kThreads, 0, st>>>(part, nblk, m, part_max, nblk_max, B, ldb, newslot, order, coef, scal);
     return hipGetLastError();
 }
@@ -1814,6 +1822,7 @@ __global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, con
                                                  int* __restrict__ active, int* __restrict__ upd) {
     __shared__ double sh[kThreads];
     __shared__ double row[8];
+    __shared__ double wa[9 * 10], wx[9];
     const int s = blockIdx.x;
     BState stt = state[s];
     if (!stt.active) {
@@ -1846,7 +1855,7 @@ __global__ __launch_bounds__(256) void k_bfinish(BState* __restrict__ state, con
         B[nw * 8 + order[j]] = row[j];
         B[order[j] * 8 + nw] = row[j];
     }
-    const int dropped = diis_solve(B, 8, order, m, coef + (long long)s * 8);
+    const int dropped = diis_solve<8>(B, 8, order, m, coef + (long long)s * 8, wa, wx);
     stt.newest = nw;
     stt.count = max(1, m - dropped);
     stt.iters += 1;

@@ -173,9 +173,14 @@ hipError_t launch_count_nonfinite(const double* x, long long n, unsigned long lo
 // (order 4, idx = (i, j, a, b)); f = occupied then virtual one-particle energies
 hipError_t launch_dressed_denoms(const uint16_t* idx, int order, const double* f, int no, double floor, double* D,
                                  long long n, hipStream_t st);
-// coef holds ldb + 1 doubles: coef[ldb] = 1 marks a non-finite step
+// coef holds ldb + 1 doubles: coef[ldb] = 1 marks a non-finite step.  The
+// live slots (oldest first) travel as a kernel argument, so that enqueueing
+// the update needs no copy from host memory.
+struct DiisOrder {
+    int v[kDiisMax];
+};
 hipError_t launch_finish_diis(const double* part, int nblk, int m, const double* part_max, int nblk_max, double* B,
-                              int ldb, int newslot, const int* order, double* coef, double* scal, hipStream_t st);
+                              int ldb, int newslot, const DiisOrder& order, double* coef, double* scal, hipStream_t st);
 // out = sum_{j<m} coef[j] xs[j], unless coef[m] != 0 (out is then left untouched)
 hipError_t launch_lincomb(double2* out, const double2* const* xs, const double* coef, int m, long long n,
                           hipStream_t st);

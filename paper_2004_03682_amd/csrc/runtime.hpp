@@ -231,7 +231,6 @@ struct fscc_ctx {
     double* part_max = nullptr;
     double* coef = nullptr;
     double* scal = nullptr;
-    int* dorder = nullptr;
     double* hscal = nullptr;   // pinned host
     double* epart = nullptr;
     double* eout = nullptr;
@@ -342,7 +341,7 @@ struct fscc_ctx {
         }
         for (void* p : seg_mem)
             if (p) (void)hipFree(p);
-        void* ps[] = {part, part_max, coef, scal, dorder, epart, eout, rs_tmp, d_idx1, d_idx2, d_fov};
+        void* ps[] = {part, part_max, coef, scal, epart, eout, rs_tmp, d_idx1, d_idx2, d_fov};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (hscal) (void)hipHostFree(hscal);
