@@ -269,3 +269,29 @@ def test_stragglers_continue_concurrently_with_the_sequential_results():
         g = F.solve(ctx, u1, u2, tol=1e-11, maxit=200, ndiis=8)
         assert abs(out[1][0][k] - g["E"]) <= 1e-9
         ctx.destroy()
+
+
+def test_autotuned_batch_converges_like_single_systems():
+    """The batch in the autotuner's launch forms (direct-to-LDS MFMA tiles
+    among the candidates, workgroups of converged systems skipped through the
+    active flags): the same energies as single-system contexts."""
+    torch = _torch()
+    import paper_2004_03682_amd as F
+    systems = [fsgen.make_system(*p) for p in SPECS[:4]] + [fsgen.make_system(7, 30, 4, 0.05, 8)]
+    b = make_batch(systems)
+    b.context().autotune(1)
+    tiles = {n: c for n, c, _, _ in b.context().gemm_configs()}
+    print("batch tiles", tiles, flush=True)
+    t1 = torch.zeros(b.n1, dtype=torch.complex128, device="cuda")
+    t2 = torch.zeros(b.n2, dtype=torch.complex128, device="cuda")
+    res = F.solve_batch(b, t1, t2, tol=1e-10, maxit=150, use_graph=True, ndiis=8, dressed=10)
+    assert res["converged"].all(), res["iters"]
+    for k, s in enumerate(systems):
+        ctx = single_ctx(s)
+        u1 = torch.zeros(ctx.n1, dtype=torch.complex128, device="cuda")
+        u2 = torch.zeros(ctx.n2, dtype=torch.complex128, device="cuda")
+        g = F.solve(ctx, u1, u2, tol=1e-10, maxit=150, ndiis=8, dressed=10)
+        assert g["converged"]
+        assert abs(res["E"][k] - g["E"]) <= 1e-9
+        ctx.destroy()
+    b.destroy()
