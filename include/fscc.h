@@ -461,8 +461,10 @@ fscc_status fscc_zgemm_noalloc(int cfg, int bk, int tA, int tB, int cA, int cB, 
 
 /* Real form of fscc_zgemm (kernel-level tests of the real-arithmetic path):
  * C = alpha * op(A) op(B) + beta*C on doubles, same layout conventions and
- * kernel forms except 6 (skinny), which has no real form (FSCC_EINVAL).
- * Synchronises hip_stream. */
+ * kernel forms except 6 (skinny), which has no real form (FSCC_EINVAL); an
+ * MFMA tile id may carry FSCC_CFG_DL (the direct-to-LDS form: each double
+ * moves as two 4-byte direct-to-LDS loads; bk = 16 and the tiles listed at
+ * FSCC_CFG_DL), not FSCC_CFG_3M or FSCC_CFG_DB.  Synchronises hip_stream. */
 fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, const double *A, int lda, const double *B,
                        int ldb, double *C, int ldc, double alpha, int beta, int allow_split, void *hip_stream);
 

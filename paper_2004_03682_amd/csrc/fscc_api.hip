@@ -1588,7 +1588,8 @@ bool tune_apply(fscc_ctx* c, const std::vector<std::array<int, 7>>& ops) {
             if (kind == 1) {
                 if (!cfg_ok(o, a[1], c->real) || (a[2] != 16 && a[2] != 32)) return false;
                 if (a[5] < LDS_STAGED || a[5] > LDS_DIRECT) return false;
-                if (a[5] != LDS_STAGED && (c->real || a[2] != 16)) return false;
+                if (a[5] != LDS_STAGED && a[2] != 16) return false;
+                if (a[5] == LDS_DOUBLE && c->real) return false;
                 if ((a[5] == LDS_DOUBLE && !zcfg_has_db(a[1])) || (a[5] == LDS_DIRECT && !zcfg_has_dl(a[1]))) return false;
                 if (a[6] >= MCFG_N) return false;
             } else if (kind == 0) {
@@ -1778,8 +1779,8 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                             // double-buffered, direct-to-LDS ring
                             for (int lds = LDS_STAGED; lds <= LDS_DIRECT; ++lds) {
                                 if (lds != LDS_STAGED &&
-                                    (ctx->real || bk != 16 ||
-                                     (lds == LDS_DOUBLE && !zcfg_has_db(cfg)) || (lds == LDS_DIRECT && !zcfg_has_dl(cfg))))
+                                    (bk != 16 || (lds == LDS_DOUBLE && (ctx->real || !zcfg_has_db(cfg))) ||
+                                     (lds == LDS_DIRECT && !zcfg_has_dl(cfg))))
                                     continue;
                                 cand.lds = lds;
                                 float ms = time_op(o, &cand);
@@ -2129,7 +2130,10 @@ fscc_status fscc_zgemm(int cfg, int bk, int tA, int tB, int cA, int cB, int M, i
 
 fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, const double* A, int lda, const double* B,
                        int ldb, double* C, int ldc, double alpha, int beta, int allow_split, void* hip_stream) {
+    const bool dl = cfg >= 0 && (cfg & FSCC_CFG_DL);
+    if (cfg >= 0) cfg &= ~FSCC_CFG_DL;
     if (M < 0 || N < 0 || K < 0 || cfg >= ZCFG_N || (bk != 16 && bk != 32)) return FSCC_EINVAL;
+    if (dl && (bk != 16 || !zcfg_has_dl(cfg))) return FSCC_EINVAL;
     if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return FSCC_EINVAL;
     if (ldc < N || lda < (tA ? M : K) || ldb < (tB ? K : N)) return FSCC_EINVAL;
     fscc_ctx* c = new (std::nothrow) fscc_ctx();
@@ -2148,13 +2152,14 @@ fscc_status fscc_dgemm(int cfg, int bk, int tA, int tB, int M, int N, int K, con
         if (cfg >= 0 && !cfg_ok(o, cfg, true)) return FSCC_EINVAL;
         GemmDev g;
         plan_gemm(c, o, g, cfg < 0 ? pick_cfg(o, true) : cfg, bk, allow_split != 0);
+        g.lds = dl ? LDS_DIRECT : LDS_STAGED;
         hipError_t e;
         if (!g.split) {
             e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, A, B, C, g.probs, g.tiles, g.ntiles, alpha, o.beta, c->st, 0,
-                             nullptr, g.maxM);
+                             nullptr, g.maxM, g.lds);
         } else {
             e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, A, B, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0, 0, c->st,
-                             0, nullptr, g.maxM);
+                             0, nullptr, g.maxM, g.lds);
             if (e == hipSuccess)
                 e = launch_dsplitk_reduce(C, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, alpha, o.beta, c->st);
         }

@@ -197,7 +197,11 @@ int reduce_blocks(long long n);
 // tile shapes and ZCFG_TALL / ZCFG_RED (not ZCFG_SKINNY).
 hipError_t launch_dgemm(int cfg, int bk, bool tA, bool tB, const double* A, const double* B, double* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
-                        int role = 0, const int* active = nullptr, int max_m = 0);
+                        int role = 0, const int* active = nullptr, int max_m = 0, int lds = LDS_STAGED);
+// the real direct-to-LDS form (kernels_dl.hip); the tiles of zcfg_has_dl(), bk = 16
+hipError_t launch_dgemm_dl(int cfg, bool tA, bool tB, const double* A, const double* B, double* C,
+                           const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
+                           int role, const int* active);
 hipError_t launch_dsplitk_reduce(double* C, const double* W, const ZRed* reds, int nred, int maxMN, int maxS,
                                  double alpha, int beta, hipStream_t st);
 hipError_t launch_dgather(double* dst, const double* src, const double* src2, GatherMaps maps, int nt, long long n,

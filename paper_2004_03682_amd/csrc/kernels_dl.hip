@@ -386,6 +386,227 @@ hipError_t launch_dl_m3(int cfg, bool tA, bool tB, const double2* A, const doubl
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Real form (real-arithmetic contexts): the same ring with one double per LDS
+// slot.  A double travels as two 4-byte direct-to-LDS loads of neighbouring
+// lanes (global_load_lds_dword; 4-byte alignment is all a real operand
+// guarantees), so one wave instruction moves 32 elements.  Rows of an operand
+// whose K index is contiguous are XOR-swizzled as in the complex form (the 16
+// lanes of an 8-byte fragment column read 16 different bank pairs); one real
+// MFMA chain per fragment.
+
+__device__ __forceinline__ void dma4(const void* g, double* l) {
+    __builtin_amdgcn_global_load_lds(g, (lds_void*)l, 4, 0, 0);
+}
+
+template <int SE, int I>
+__device__ __forceinline__ double* lds_stage_d() {
+    __shared__ double buf[SE];
+    return buf;
+}
+
+__device__ __forceinline__ uint32_t lds_addr_d(const double* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// NF 8-byte LDS reads and their wait in one asm block (see lds_frags)
+#define DSR64(o, i) "ds_read_b64 %" #o ", %" #i "\n\t"
+template <int NF>
+__device__ __forceinline__ void lds_frags64(double (&v)[NF], const uint32_t (&a)[NF]) {
+    static_assert(NF >= 2 && NF <= 5, "fragment count");
+    if constexpr (NF == 2) {
+        asm volatile(DSR64(0, 2) DSR64(1, 3) "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(v[0]), "=&v"(v[1])
+                     : "v"(a[0]), "v"(a[1])
+                     : "memory");
+    } else if constexpr (NF == 3) {
+        asm volatile(DSR64(0, 3) DSR64(1, 4) DSR64(2, 5) "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2])
+                     : "v"(a[0]), "v"(a[1]), "v"(a[2])
+                     : "memory");
+    } else if constexpr (NF == 4) {
+        asm volatile(DSR64(0, 4) DSR64(1, 5) DSR64(2, 6) DSR64(3, 7) "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])
+                     : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])
+                     : "memory");
+    } else {
+        asm volatile(DSR64(0, 5) DSR64(1, 6) DSR64(2, 7) DSR64(3, 8) DSR64(4, 9) "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4])
+                     : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4])
+                     : "memory");
+    }
+}
+#undef DSR64
+
+template <int BM, int BN, int WM, int WN, int S, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(256) void k_dgemm_dl(const double* __restrict__ A, const double* __restrict__ B,
+                                                  double* __restrict__ C, const ZProb* __restrict__ probs,
+                                                  const ZTile* __restrict__ tiles, double alpha, int beta,
+                                                  const int* __restrict__ active) {
+    constexpr int BK = kBK;
+    constexpr int FM = BM / (16 * WM);
+    constexpr int FN = BN / (16 * WN);
+    constexpr int AE = BM * BK, BE = BN * BK, SE = AE + BE;   // doubles per stage
+    constexpr int AI = AE / (4 * 32), BI = BE / (4 * 32);     // loads per thread per slice (4 waves x 32 doubles)
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(FM >= 1 && FN >= 1, "tile too small");
+    static_assert(AE % 128 == 0 && BE % 128 == 0, "whole load instructions");
+    static_assert((S - 2) * (AI + BI) <= 63, "vmcnt range");
+    static_assert(S >= 2 && S <= 4, "ring depth");
+
+    const ZTile tl = tiles[blockIdx.x];
+    if (active && !active[tl.sys]) return;
+    const ZProb pr = probs[tl.prob];
+    const int M = pr.M, N = pr.N, K = pr.K;
+    const double* Ap = A + pr.a_off;
+    const double* Bp = B + pr.b_off;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int m0 = tl.m0, n0 = tl.n0;
+
+    dbl4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    // load instruction u of this thread: element slot q = (4u + wave)*32 +
+    // lane/2 of the stage, word lane&1 of that double
+    const int word = lane & 1;
+    const double* abase[AI];
+    const double* bbase[BI];
+    int akq[AI], bkq[BI];
+    const long long askk = TA ? pr.lda : 1, bskk = TB ? 1 : pr.ldb;
+#pragma unroll
+    for (int u = 0; u < AI; ++u) {
+        const int q = (4 * u + wave) * 32 + (lane >> 1);
+        if (!TA) {
+            const int r = q / BK, c = q % BK;
+            abase[u] = Ap + (long long)min(m0 + r, M - 1) * pr.lda;
+            akq[u] = c ^ (r & 15);
+        } else {
+            const int kr = q / BM, c = q % BM;
+            abase[u] = Ap + min(m0 + c, M - 1);
+            akq[u] = kr;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < BI; ++u) {
+        const int q = (4 * u + wave) * 32 + (lane >> 1);
+        if (TB) {
+            const int r = q / BK, c = q % BK;
+            bbase[u] = Bp + (long long)min(n0 + r, N - 1) * pr.ldb;
+            bkq[u] = c ^ (r & 15);
+        } else {
+            const int kr = q / BN, c = q % BN;
+            bbase[u] = Bp + min(n0 + c, N - 1);
+            bkq[u] = kr;
+        }
+    }
+
+    auto issue = [&](auto stage, int kt) {
+        const int k0 = kt * BK;
+        double* st = lds_stage_d<SE, decltype(stage)::value>();
+#pragma unroll
+        for (int u = 0; u < AI; ++u)
+            dma4((const char*)(abase[u] + (long long)min(k0 + akq[u], K - 1) * askk) + 4 * word,
+                 st + (4 * u + wave) * 32);
+#pragma unroll
+        for (int u = 0; u < BI; ++u)
+            dma4((const char*)(bbase[u] + (long long)min(k0 + bkq[u], K - 1) * bskk) + 4 * word,
+                 st + AE + (4 * u + wave) * 32);
+    };
+
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    const int wm0 = wm * FM * 16, wn0 = wn * FN * 16;
+    const bool wave_live = m0 + wm0 < M && n0 + wn0 < N;
+
+    constexpr int NF = FM + FN;
+    auto compute = [&](auto stage, int krem) {
+        const double* As = lds_stage_d<SE, decltype(stage)::value>();
+        const double* Bs = As + AE;
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            uint32_t addr[NF];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm0 + i * 16 + lr;
+                addr[i] = lds_addr_d(TA ? As + k * BM + r : As + r * BK + (k ^ (r & 15)));
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int c = wn0 + j * 16 + lr;
+                addr[FM + j] = lds_addr_d(TB ? Bs + c * BK + (k ^ (c & 15)) : Bs + k * BN + c);
+            }
+            double v[NF];
+            lds_frags64<NF>(v, addr);
+            const double kf = k < krem ? 1.0 : 0.0;   // zero for k past K (clamped, finite elements)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(kf * v[i], v[FM + j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    const int nk = K > 0 ? (K + BK - 1) / BK : 0;
+    auto prologue = [&](auto stage, int) {
+        if constexpr (decltype(stage)::value < S - 1) issue(stage, min((int)decltype(stage)::value, nk - 1));
+    };
+    if (nk > 0) unroll_ring<0, S>(prologue, 0, S);
+    auto step = [&](auto stage, int kt) {
+        constexpr int I = decltype(stage)::value;
+        wait_vmem<(S - 2) * (AI + BI)>();
+        lds_barrier();
+        issue(std::integral_constant<int, (I + S - 1) % S>{}, min(kt + S - 1, nk - 1));
+        if (wave_live) compute(stage, K - kt * BK);
+    };
+    for (int kb = 0; kb < nk; kb += S) unroll_ring<0, S>(step, kb, nk);
+    wait_vmem<0>();
+
+    double* Cp = C + pr.c_off;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn0 + j * 16 + lr;
+            if (col >= N) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wm0 + i * 16 + q * 4 + lk;
+                if (row >= M) continue;
+                double out = alpha * acc[i][j][q];
+                double* c = Cp + (long long)row * pr.ldc + col;
+                if (beta) out += *c;
+                *c = out;
+            }
+        }
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+hipError_t launch_ddl_cfg(bool tA, bool tB, const double* A, const double* B, double* C, const ZProb* probs,
+                          const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st, int role,
+                          const int* active) {
+    dim3 grid(ntiles), block(kThreads);
+    if (!tA && !tB) {
+        if (role == 2) k_dgemm_dl<BM, BN, WM, WN, S, false, false, 2><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+        else k_dgemm_dl<BM, BN, WM, WN, S, false, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+    } else if (!tA && tB) {
+        if (role == 1) k_dgemm_dl<BM, BN, WM, WN, S, false, true, 1><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+        else k_dgemm_dl<BM, BN, WM, WN, S, false, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+    } else if (tA && !tB) {
+        k_dgemm_dl<BM, BN, WM, WN, S, true, false, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+    } else {
+        k_dgemm_dl<BM, BN, WM, WN, S, true, true, 0><<<grid, block, 0, st>>>(A, B, C, probs, tiles, alpha, beta, active);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool zcfg_has_dl(int cfg) {
@@ -399,6 +620,27 @@ hipError_t launch_zgemm_dl(int cfg, bool tA, bool tB, const double2* A, const do
     if (ntiles <= 0) return hipSuccess;
     return m3 ? launch_dl_m3<true>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active)
               : launch_dl_m3<false>(cfg, tA, tB, A, B, C, probs, tiles, ntiles, ar, ai, beta, cA, cB, st, role, active);
+}
+
+}  // namespace fscc
+
+namespace fscc {
+
+hipError_t launch_dgemm_dl(int cfg, bool tA, bool tB, const double* A, const double* B, double* C,
+                           const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
+                           int role, const int* active) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (cfg) {
+        case ZCFG_32x32: return launch_ddl_cfg<32, 32, 2, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x16: return launch_ddl_cfg<64, 16, 4, 1, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_16x64: return launch_ddl_cfg<16, 64, 1, 4, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_32x64: return launch_ddl_cfg<32, 64, 2, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x32: return launch_ddl_cfg<64, 32, 2, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x32R: return launch_ddl_cfg<64, 32, 4, 1, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x64: return launch_ddl_cfg<64, 64, 2, 2, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        case ZCFG_64x64R: return launch_ddl_cfg<64, 64, 4, 1, 2>(tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fscc

@@ -604,8 +604,13 @@ inline unsigned grid_of(long long n) { return (unsigned)((n + kT - 1) / kT); }
 
 hipError_t launch_dgemm(int cfg, int bk, bool tA, bool tB, const double* A, const double* B, double* C,
                         const ZProb* probs, const ZTile* tiles, int ntiles, double alpha, int beta, hipStream_t st,
-                        int role, const int* active, int max_m) {
+                        int role, const int* active, int max_m, int lds) {
     if (ntiles <= 0) return hipSuccess;
+    if (lds == LDS_DIRECT) {
+        if (bk != 16 || !zcfg_has_dl(cfg)) return hipErrorInvalidValue;
+        return launch_dgemm_dl(cfg, tA, tB, A, B, C, probs, tiles, ntiles, alpha, beta, st, role, active);
+    }
+    if (lds != LDS_STAGED) return hipErrorInvalidValue;
     dim3 grid(ntiles), block(kT);
     if (cfg == ZCFG_TALL) {
         if (tA) return hipErrorInvalidValue;

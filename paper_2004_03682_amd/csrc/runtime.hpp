@@ -391,9 +391,9 @@ struct fscc_ctx {
                 double* Cp = C_override ? C_override : D(o.dst);
                 if (!g.split)
                     return launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, D(o.src2), Cp, g.probs, g.tiles, g.ntiles,
-                                        o.alpha.real(), beta, st, g.role, nullptr, g.maxM);
+                                        o.alpha.real(), beta, st, g.role, nullptr, g.maxM, g.lds);
                 hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, D(o.src2), (double*)g.work, g.probs, g.tiles,
-                                            g.ntiles, 1.0, 0, st, g.role, nullptr, g.maxM);
+                                            g.ntiles, 1.0, 0, st, g.role, nullptr, g.maxM, g.lds);
                 if (e == hipSuccess)
                     e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), beta,
                                               st);
@@ -546,9 +546,9 @@ struct fscc_ctx {
         double* Cp = C_override ? C_override : D(o.dst);
         if (!g.split)
             return launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, Cp, g.probs, g.tiles, g.ntiles, o.alpha.real(), beta,
-                                st, g.role, nullptr, g.maxM);
+                                st, g.role, nullptr, g.maxM, g.lds);
         hipError_t e = launch_dgemm(g.cfg, g.bk, o.tA, o.tB, Ap, Bp, (double*)g.work, g.probs, g.tiles, g.ntiles, 1.0,
-                                    0, st, g.role, nullptr, g.maxM);
+                                    0, st, g.role, nullptr, g.maxM, g.lds);
         if (e == hipSuccess)
             e = launch_dsplitk_reduce(Cp, (const double*)g.work, g.reds, g.nred, g.maxMN, g.maxS, o.alpha.real(), beta, st);
         return e;

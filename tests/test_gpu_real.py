@@ -67,6 +67,23 @@ def test_dgemm_vector_forms():
         _dg(10, 10, 10, 0, 0, SKINNY, 16, True, 0)
 
 
+@pytest.mark.parametrize("cfg", (0, 3, 4, 5, 9, 10, 12, 13))
+def test_dgemm_direct_to_lds_tiles(cfg):
+    """The real direct-to-LDS form (each double moved as two 4-byte
+    direct-to-LDS loads): every transpose, ragged M, N and K (below, at and
+    past one 16-deep slice, several ring turns), split-K, K = 0, beta = 1,
+    odd leading dimensions (8-byte aligned operands)."""
+    DL = 1024
+    for tA, tB in itertools.product((0, 1), (0, 1)):
+        for (M, N, K) in [(1, 1, 1), (17, 33, 15), (70, 23, 16), (33, 65, 17), (130, 131, 40), (31, 129, 64),
+                          (3, 48, 3000), (300, 200, 1800), (9, 11, 0)]:
+            for split in (False, True):
+                err = _dg(M, N, K, tA, tB, cfg | DL, 16, split, M % 2, seed=M + N + K)
+                assert err < 1e-13, ("direct-to-LDS", cfg, tA, tB, M, N, K, split, err)
+    with pytest.raises(Exception):
+        _dg(10, 10, 10, 0, 0, cfg | DL, 32, False, 0)
+
+
 def _real_ctx(s):
     import torch
     import paper_2004_03682_amd as F
