@@ -128,28 +128,39 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
     constexpr int NPC = BF ? 3 : 2;            // pieces
     constexpr int NPL = 2 * NPC;               // planes
     constexpr int ROWB = KB * ES;              // bytes of one row of a k block
-    constexpr int PITCH = ROWB + 16;           // LDS row pitch (bytes)
+    // LDS rows: bf16 rows are 64 bytes, unpadded, with 16-byte chunk c of row r
+    // at chunk c ^ swz(r): the stores (4 lanes per row, consecutive rows) and
+    // the fragment reads (16 rows, one chunk each) then touch distinct banks
+    // whether the LDS serves 8 or 16 lanes of a 16-byte access per cycle;
+    // fp32 rows are padded by 16 bytes instead.
+    constexpr int PITCH = BF ? ROWB : ROWB + 16;   // LDS row pitch (bytes)
     constexpr int VPR = ROWB / 16;             // 16-byte vectors per row
     constexpr int AVEC = NPL * BM * VPR, BVEC = NPL * BN * VPR;
     constexpr int AVT = (AVEC + kT - 1) / kT, BVT = (BVEC + kT - 1) / kT;
     constexpr int FM = BM / (16 * WM), FN = BN / (16 * WN);
     constexpr int FV = BF ? 1 : 2;             // 16-byte vectors per fragment and plane
     static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "tile");
+    static_assert(BM % 16 == 0 && BN % 16 == 0, "row swizzle: rows mod 16 = fragment lane rows");
     __shared__ __attribute__((aligned(16))) unsigned char lds[NPL * (BM + (BD ? 0 : BN)) * PITCH];
     unsigned char* ldsA = lds;
     unsigned char* ldsB = lds + NPL * BM * PITCH;
 
     const ZTile tl = tiles[blockIdx.x];
     const MProb pr = probs[tl.prob];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm0 = (wave / WN) * FM * 16, wn0 = (wave % WN) * FN * 16;
     const int m0 = tl.m0, n0 = tl.n0;
+    // a wave whose rows (or columns) all lie past the edge only helps load
+    // the tile: the 64-row tiles over short pair-row blocks do no padded MFMAs
+    const bool wave_live = m0 + wm0 < pr.M && n0 + wn0 < pr.N;
     const int nkb = pr.Kp / KB;
     const unsigned char* Ab = (const unsigned char*)Av + (pr.a_off + (long long)m0 * KB) * ES;
     const unsigned char* Bb = (const unsigned char*)Bv + (pr.b_off + (long long)n0 * KB) * ES;
     const long long stepA = (long long)pr.rows_a * KB * ES, stepB = (long long)pr.rows_b * KB * ES;
 
     const int lr = lane & 15, kq = lane >> 4;
+    auto swz = [](int r) { return BF ? (((r >> 1) + (r >> 3)) & 3) : 0; };   // r: row mod 16
+    const int sl = swz(lr);
     u4v ra[AVT], rb[BD ? 1 : BVT];
     u4v gb[NPC][2][FN][FV];   // BD: the next k block's B fragments
     auto load = [&](int kb) {
@@ -190,7 +201,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
             const int v = tid + u * kT;
             if (v < AVEC) {
                 const int p = v / (BM * VPR), w = v % (BM * VPR);
-                *(u4v*)(ldsA + (p * BM + w / VPR) * PITCH + (w % VPR) * 16) = ra[u];
+                *(u4v*)(ldsA + (p * BM + w / VPR) * PITCH + ((w % VPR) ^ swz((w / VPR) & 15)) * 16) = ra[u];
             }
         }
         if constexpr (!BD) {
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
                 const int v = tid + u * kT;
                 if (v < BVEC) {
                     const int p = v / (BN * VPR), w = v % (BN * VPR);
-                    *(u4v*)(ldsB + (p * BN + w / VPR) * PITCH + (w % VPR) * 16) = rb[u];
+                    *(u4v*)(ldsB + (p * BN + w / VPR) * PITCH + ((w % VPR) ^ swz((w / VPR) & 15)) * 16) = rb[u];
                 }
             }
         }
@@ -231,6 +242,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
                         for (int h = 0; h < FV; ++h) fb[pc][ri][j][h] = gb[pc][ri][j][h];
         }
         if (kb + 1 < nkb) load(kb + 1);
+        if (!wave_live) continue;
         if constexpr (!BD) {
 #pragma unroll
             for (int pc = 0; pc < NPC; ++pc)
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
 #pragma unroll
                         for (int h = 0; h < FV; ++h)
                             fb[pc][ri][j][h] = *(const u4v*)(ldsB + ((2 * pc + ri) * BN + wn0 + j * 16 + lr) * PITCH +
-                                                             kq * 16 * FV + h * 16);
+                                                             ((kq * FV + h) ^ sl) * 16);
         }
         f4v acc[FM][FN][4];
 #pragma unroll
@@ -263,7 +275,7 @@ __global__ __launch_bounds__(256) void k_zgemm_split(const void* __restrict__ Av
 #pragma unroll
                     for (int h = 0; h < FV; ++h)
                         fa[ri][i][h] = *(const u4v*)(ldsA + ((2 * pa + ri) * BM + wm0 + i * 16 + lr) * PITCH +
-                                                     kq * 16 * FV + h * 16);
+                                                     ((kq * FV + h) ^ sl) * 16);
 #pragma unroll
             for (int pb = NPC - 1 - pa; pb >= 0; --pb) {
 #pragma unroll
