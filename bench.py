@@ -64,6 +64,34 @@ def measured_traffic(kernel_name, tile=None):
     return None if t is None else t.get("bytes_per_launch")
 
 
+def measured_peaks(F, torch):
+    """This GPU's rates at the clock it runs under load: matrix-core
+    throughput of the three MFMA instructions the GEMMs issue
+    (fscc_probe_mfma: register operands only, every SIMD busy) and a 1 GiB
+    device-to-device copy (HIP events; bytes read + written)."""
+    out = {}
+    for k in ("fp64", "bf16", "fp32"):
+        tf, _ = F.probe_mfma(k, 4096)
+        out[k + "_mfma_tflops"] = round(tf, 2)
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    out["hbm_copy_gbs"] = round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    out["spec"] = {"fp64_mfma_tflops": PEAK_FP64, "bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3,
+                   "hbm_gbs": 8000.0}
+    return out
+
+
 def cpu_baseline(sysm, buffers):
     import numpy as np
     from oracle import ccsd
@@ -1129,6 +1157,10 @@ def main():
             # traffic is that of the GEMM kernel
             "tile": tuned.get(dom["name"]),
             "launch_includes_splitk_pass": tuned.get(dom["name"], "").endswith("/splitK")}
+    peaks = measured_peaks(F, torch)
+    roof["measured_peak"] = peaks["fp64_mfma_tflops"]
+    roof["frac_of_measured_peak"] = round(achieved / peaks["fp64_mfma_tflops"], 4)
+    log(f"measured peaks: {peaks}; pp-ladder at {roof['frac_of_measured_peak']:.3f} of the probed FP64 rate")
     result = {
         "metric": METRIC, "value": round(s_per_iter, 6), "unit": "s/iteration", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(s_per_iter * 1e3, 4),
@@ -1149,6 +1181,7 @@ def main():
         "reorders": reorder_table(ops, nwarm),
         "energy_re": E.real, "energy_im": E.imag, "last_max_step": hist[-1][0],
         "roofline": roof,
+        "measured_peaks": peaks,
     }
     ora = oracle_fixed_point(s)
     E_ref = E

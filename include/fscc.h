@@ -643,6 +643,22 @@ fscc_status fscc_batch_maxnorm(fscc_batch *b, const fscc_c128 *r1, const fscc_c1
  * operations are the merged grouped launches.  Owned by the batch. */
 fscc_ctx *fscc_batch_context(fscc_batch *b);
 
+/* ---- matrix-core throughput probe -------------------------------------
+ * The roofline of the GEMMs (the contractions of Eq. (3) and of the sector
+ * equations run as block matrix products on the matrix cores) measured on
+ * this GPU at the clock it runs: kind 0 = FP64 v_mfma_f64_16x16x4f64,
+ * 1 = BF16 v_mfma_f32_16x16x32_bf16 (fp32 accumulation), 2 = FP32
+ * v_mfma_f32_16x16x4f32.  Every wave runs 8 independent accumulator chains of
+ * iters instructions each from register operands (no memory traffic), four
+ * waves per workgroup, as many workgroups per compute unit as are resident
+ * at once (hipOccupancyMaxActiveBlocksPerMultiprocessor); one untimed launch
+ * first, then one launch timed with HIP events on hip_stream (NULL: the
+ * default stream).  *tflops = issued flops (2*16*16*k per instruction) / time;
+ * *ms (may be NULL) = the timed launch.  Allocates and frees a small device
+ * buffer; synchronous.  FSCC_EINVAL for another kind, iters outside
+ * 1..2^20 or tflops NULL; FSCC_ENOMEM / FSCC_EHIP on runtime failures. */
+fscc_status fscc_probe_mfma(int kind, int iters, void *hip_stream, double *tflops, double *ms);
+
 /* ---- learned warm start ----------------------------------------------
  * A small network predicts the converged T2 amplitudes from quantities of
  * the first two Jacobi iterates, to start the iteration of Eq. (3) closer to

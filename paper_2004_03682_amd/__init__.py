@@ -99,6 +99,7 @@ def lib():
             "fscc_batch_context": ([vp], vp),
             "fscc_batch_denominators": ([vp, vp, vp], ip),
             "fscc_batch_restart": ([vp, vp], ip),
+            "fscc_probe_mfma": ([ip, ip, vp, vp, vp], ip),
             "fscc_batch_precondition": ([vp, ip, ctypes.c_double], ip),
             "fscc_batch_maxnorm": ([vp, vp, vp, dp], ip),
             "fscc_mlp_num_params": ([ctypes.POINTER(sz)], ip),
@@ -470,6 +471,20 @@ def heff_eig(h):
     if r != 0:
         raise FsccError(r, "fscc_heff_eig failed")
     return out
+
+
+PROBE_KINDS = {"fp64": 0, "bf16": 1, "fp32": 2}
+
+
+def probe_mfma(kind="fp64", iters=4096, stream=None):
+    """Measured matrix-core throughput of this GPU (fscc_probe_mfma): kind
+    'fp64', 'bf16' or 'fp32'; returns (TFLOP/s, ms of the timed launch)."""
+    tf, ms = ctypes.c_double(), ctypes.c_double()
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    r = lib().fscc_probe_mfma(PROBE_KINDS[kind], int(iters), st, ctypes.byref(tf), ctypes.byref(ms))
+    if r != 0:
+        raise FsccError(r, "fscc_probe_mfma failed")
+    return tf.value, ms.value
 
 
 def pade(x, y, L, M, x0=0.0):

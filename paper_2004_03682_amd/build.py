@@ -15,7 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfscc.so")
 SOURCES = ["fscc_api.hip", "batch_api.hip", "noalloc_api.hip", "kernels.hip", "kernels_real.hip", "kernels_split.hip",
-           "kernels_dl.hip", "mlp.hip", "plan_ccsd.cpp", "host_linalg.cpp"]
+           "kernels_dl.hip", "mlp.hip", "probe.hip", "plan_ccsd.cpp", "host_linalg.cpp"]
+# per-source extra flags: the throughput probe's accumulators stay in VGPRs
+# (no accumulator copies around its loop)
+EXTRA = {"probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,7 +39,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for s in SOURCES:
         obj = os.path.join(OBJ, os.path.splitext(s)[0] + "." + tag + ".o")
         objs.append(obj)
-        cmds.append([HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, s)])
+        cmds.append([HIPCC] + FLAGS + EXTRA.get(s, []) + ["-c", "-o", obj, os.path.join(CSRC, s)])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_run, cmds))
     bad = [(c, out) for c, (rc, out) in zip(cmds, results) if rc != 0]

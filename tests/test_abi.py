@@ -37,3 +37,12 @@ def test_null_arguments_are_rejected():
     assert L.fscc_layout(None, 0, None, None) == -1
     assert L.fscc_build_residual(None, 0, None, None, None, None) == -1
     L.fscc_destroy(None)
+
+
+def test_probe_arguments_are_checked_before_any_device_call():
+    import paper_2004_03682_amd as F
+    L = F.lib()
+    tf = ctypes.c_double()
+    for kind, iters in ((3, 16), (-1, 16), (0, 0), (0, (1 << 20) + 1)):
+        assert L.fscc_probe_mfma(kind, iters, None, ctypes.byref(tf), None) == -1
+    assert L.fscc_probe_mfma(0, 16, None, None, None) == -1
