@@ -998,6 +998,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start on the batch")
     ap.add_argument("--converge", action="store_true",
                     help="after timing, iterate to convergence and report iterations to |E-E_inf|<1e-8")
+    ap.add_argument("--probe-peaks", action="store_true",
+                    help="only measure this GPU's MFMA rates (fscc_probe_mfma) and device copy rate; print them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 device copies of 1 GiB (calibrates HBM byte counters)")
     ap.add_argument("--profile-ops", metavar="OUT_JSON",
@@ -1023,6 +1025,11 @@ def main():
         return
     if args.profile_ops:
         profile_ops(args)
+        return
+    if args.probe_peaks:
+        import torch
+        import paper_2004_03682_amd as F
+        print(json.dumps(measured_peaks(F, torch)))
         return
     if args.copy_calibration:
         import torch
