@@ -350,7 +350,8 @@ fscc_status fscc_op_run(fscc_ctx *ctx, int k, int reps);
  * in a split precision (fscc_set_precision) level 1 also times the split
  * kernel's tile shapes of the split operations; level 2 times only those;
  * level 0: restore the cost-model defaults chosen at fscc_create (FP64
- * shapes).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) and
+ * shapes; 16-deep K slices, split-K allowed, the direct-to-LDS form
+ * FSCC_CFG_DL wherever the tile has one).  Level 1 also times the double-buffered LDS form (FSCC_CFG_DB) and
  * the direct-to-LDS form (FSCC_CFG_DL) of every eligible tile.  Level 1 also times each reorder (gather) of a complex context in
  * destination order, by 16 x 16 destination tiles and by affine tiles (see
  * fscc_gather_order) and keeps the fastest.

@@ -394,6 +394,16 @@ void plan_gemm(fscc_ctx* c, const Op& o, GemmDev& g, int cfg, int bk, bool allow
 }
 
 
+// Cost-model default of a GEMM operation before (or without) autotuning:
+// pick_cfg's tile with 16-deep K slices and split-K allowed, in the
+// direct-to-LDS form wherever that tile has one (the form the autotuner
+// keeps for the large contractions).
+void plan_gemm_default(fscc_ctx* c, const Op& o, GemmDev& g) {
+    const int cfg = pick_cfg(o, c->real);
+    plan_gemm(c, o, g, cfg, 16, true);
+    if (zcfg_has_dl(cfg)) g.lds = LDS_DIRECT;
+}
+
 void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
     L.ops = &ops;
     for (auto& o : ops) {
@@ -418,7 +428,7 @@ void setup_list(fscc_ctx* c, OpList& L, std::vector<Op>& ops) {
     L.ms.assign(ops.size(), 0.0);
     L.calls.assign(ops.size(), 0);
     for (size_t k = 0; k < ops.size(); ++k)
-        if (ops[k].kind == OP_GEMM) plan_gemm(c, ops[k], L.g[k], pick_cfg(ops[k], c->real), 16, true);
+        if (ops[k].kind == OP_GEMM) plan_gemm_default(c, ops[k], L.g[k]);
 }
 
 void setup_diis(fscc_ctx* c, Diis& d, int64_t n1, int64_t n2, int bD1, int bD2) {
@@ -1657,7 +1667,7 @@ fscc_status fscc_autotune(fscc_ctx* ctx, int level) {
                     MixedDev* keep = L->g[k].mx;
                     L->g[k].mx = nullptr;
                     free_gemm(L->g[k]);
-                    plan_gemm(ctx, o, L->g[k], pick_cfg(o, ctx->real), 16, true);
+                    plan_gemm_default(ctx, o, L->g[k]);
                     L->g[k].mx = keep;
                 }
             return FSCC_OK;
